@@ -1,0 +1,880 @@
+"""Plain FP64 CPU oracle of the self-learning AMG method for extremal singular triplets and
+eigenpairs (H. De Sterck, "A Self-learning Algebraic Multigrid Method for Extremal Singular
+Triplets and Eigenpairs", arXiv:1102.0919).
+
+TEST INFRASTRUCTURE ONLY.  This module is the slow, obviously-correct reference that the HIP
+library is checked against.  Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline``
+leg of ``bench.py`` may import it; the library never calls it and shares no code with it.
+
+Everything is float64 and uses NumPy / SciPy primitives (sparse products, dense SVD, eigh,
+Cholesky) as single steps; the method's steps are taken in the paper's order.  Where the paper is
+silent or ambiguous, the reading taken is stated at the function (the same readings are listed in
+the design notes of the repository):
+
+  R1  initial test vectors: uniform[-1,1) SplitMix64 stream, column-major over [U_t; V_t].
+  R2  empty rows / columns of A are removed before solving and re-inserted as zeros.
+  R3  strength rule: row-sum rule of §3.7 with the sum over all k (diagonal included);
+      alternatives: max-based rule of §3.7, and a top-s rule (s largest off-diagonal magnitudes)
+      on the strength operator built from A with high-document-frequency rows ignored.
+  R4  C/F split and interpolation patterns are built in the first multiplicative cycle only;
+      later cycles refit the weights and rebuild the Galerkin operators on fixed patterns.
+  R5  Alg. 1 tie-break: lowest index among maximal lambda; lambda only increases.
+  R6  Kaczmarz-relaxed test vectors are normalised in the B/C norm after each outer sweep.
+  R7  minimal boot relaxation: v from the rows of (3.27) A v = s B u + kappa, then u from the
+      rows of (3.28) A^t u = s C v + tau, each by one Kaczmarz sweep.
+  R8  Kaczmarz order: greedy first-fit multicolouring of the row-conflict graph (rows sharing a
+      column) in index order; colours ascending, rows ascending in a colour; weight 1.
+      (lexicographic order is available as the literal variant).
+  R9  additive V-cycle: mu_b pre- and mu_b post-relaxations on every level but the coarsest.
+  R10 coarsest generalized SVD: Theorem 3.1's change of variables with Cholesky factors of B, C.
+  R11 coarsest vectors scaled so that u^t B u = v^t C v = 1.
+  R12 LS normal equations: (G^t W G + eps I) p = G^t W b with eps = 1e-13 trace / n_ci.
+  R13 interpolatory sets larger than n_t - 1 are capped to the n_t - 1 strongest connections.
+  R14 parameters per problem follow the nearest experiment of §6.
+  R15 coarsening stops when the level size (n for eigenproblems, m+n for SVD) is at most
+      ``coarse_max``, when the coarse level would keep more than ``stall_ratio`` of the points,
+      when it would have fewer than n_b + n_t points on a side, or at ``max_levels``.
+  R16 no test-vector relaxation on the coarsest level.
+  R17 additive coarsest solve: pseudo-inverse from the SVD of X - sigma Y without its smallest
+      singular component (§4.2).  Variant 1 drops the component of the pencil (X, Y)
+      eigenvector whose eigenvalue is nearest sigma instead.
+  R18 convergence: rho_j = max(||A v - s u||, ||A^t u - s v||) / ||A||_est with unit vectors;
+      ||A||_est from 30 power steps on A^t A started from a SplitMix64 vector.
+  R19 the LS weight of pair k is |RQ_k| (dominant) or 1 / max(|RQ_k|, 1e-12 ||A||_est) (minimal).
+  R20 all n_b triplets iterate until all have converged (no locking).
+  R21 after a boot relaxation in the multiplicative phase, a negative Rayleigh quotient flips the
+      sign of u and of sigma (§5.3), for both targets.
+  R23 minimal SVD targets: after each Ritz step, u_j <- A v_j / ||A v_j|| for sigma_j > 1e-8 ||A||_est.
+  R22 the extra F-point Jacobi step of the minimal LS fit (§3.8) uses weight omega_J on the
+      strength operator N (A for eigenproblems, A A^t and A^t A for SVD).
+"""
+from __future__ import annotations
+
+import heapq
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+SPD = "spd"
+SVD = "svd"
+DOMINANT = "dominant"
+MINIMAL = "minimal"
+
+
+# ----------------------------------------------------------------------------------------------
+# parameters
+# ----------------------------------------------------------------------------------------------
+@dataclass
+class Params:
+    theta: float = 0.06
+    strength_rule: int = 0        # 0 row-sum, 1 max-based, 2 top-s
+    top_s: int = 4
+    df_filter: float = 0.0        # rule 2: ignore rows with more than df_filter * n nonzeros
+    n_t: int = 8
+    mu_t: int = 4
+    mu_b: int = 4
+    omega: float = 0.7            # omega_J, §3.4
+    n_mult: int = 10
+    max_add: int = 200
+    coarse_max: int = 128
+    max_levels: int = 25
+    stall_ratio: float = 0.9
+    tol: float = 1e-8
+    seed: int = 1102
+    kaczmarz_order: int = 0       # 0 multicolour, 1 lexicographic
+    coarse_pinv: int = 0          # 0 Euclidean SVD pseudo-inverse (literal), 1 pencil variant
+    ritz_in_mult: int = 1
+    u_from_v: int = 0             # R23: minimal SVD, u_j <- A v_j / ||A v_j|| after each Ritz step
+
+
+NORM_SEED_XOR = 0xA5A5A5A5A5A5A5A5
+
+
+# ----------------------------------------------------------------------------------------------
+# SplitMix64 (Steele, Lea & Flood 2014), written out independently of any other module
+# ----------------------------------------------------------------------------------------------
+def _splitmix_uniform(seed: int, count: int) -> np.ndarray:
+    with np.errstate(over="ignore"):
+        k = np.arange(1, count + 1, dtype=np.uint64)
+        z = np.uint64(seed & 0xFFFFFFFFFFFFFFFF) + k * np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return (z >> np.uint64(11)).astype(np.float64) * 2.0 ** -53 * 2.0 - 1.0
+
+
+def initial_test_vectors(kind, m, n, n_t, seed):
+    """R1: uniform[-1,1) values, column-major over [U_t; V_t] (SVD) or X_t (eigenproblem)."""
+    rows = n if kind == SPD else m + n
+    blk = _splitmix_uniform(seed, rows * n_t).reshape(n_t, rows).T
+    if kind == SPD:
+        return blk.copy(), None
+    return blk[:m].copy(), blk[m:].copy()
+
+
+# ----------------------------------------------------------------------------------------------
+# sparse helpers (structural patterns: Galerkin products keep every structurally present entry)
+# ----------------------------------------------------------------------------------------------
+def _ones(M):
+    M = sp.csr_matrix(M)
+    return sp.csr_matrix((np.ones(M.nnz), M.indices.copy(), M.indptr.copy()), shape=M.shape)
+
+
+def structural_product(*mats):
+    """Product of sparse matrices on the structural pattern of the product (no cancellation
+    pruning): values of the numeric product placed on the pattern of the all-ones product."""
+    pat = _ones(mats[0])
+    val = sp.csr_matrix(mats[0])
+    for M in mats[1:]:
+        pat = (pat @ _ones(M)).tocsr()
+        val = (val @ sp.csr_matrix(M)).tocsr()
+    pat.sort_indices(); val.sort_indices()
+    nr, nc = pat.shape
+    kp = np.repeat(np.arange(nr, dtype=np.int64), np.diff(pat.indptr)) * nc + pat.indices
+    kv = np.repeat(np.arange(nr, dtype=np.int64), np.diff(val.indptr)) * nc + val.indices
+    data = np.zeros(pat.nnz)
+    data[np.searchsorted(kp, kv)] = val.data
+    return sp.csr_matrix((data, pat.indices.copy(), pat.indptr.copy()), shape=pat.shape)
+
+
+def _diag(M):
+    return np.asarray(M.diagonal()).ravel()
+
+
+# ----------------------------------------------------------------------------------------------
+# §3.7: strength of connection and Algorithm 1 (one-pass Ruge-Stueben coarsening)
+# ----------------------------------------------------------------------------------------------
+def strength_sets(N, theta, rule=0, top_s=4):
+    """S_i = set of j (j != i) that strongly influence i, as CSR (indptr, indices).
+
+    rule 0: |n_ij| >= theta * sum_k |n_ik| (the row-sum condition of §3.7, sum over all k).
+    rule 1: |n_ij| >= theta * max_{k != i} |n_ik| (the max-based condition mentioned in §3.7).
+    rule 2: the top_s largest off-diagonal |n_ij| of row i (ties to the lower j).
+    Entries with n_ij = 0 are never strong.
+    """
+    N = sp.csr_matrix(N)
+    nr = N.shape[0]
+    ind, data = N.indices, np.abs(N.data)
+    rows = np.repeat(np.arange(nr), np.diff(N.indptr))
+    off = (ind != rows) & (data > 0)
+    if rule == 0:
+        rowsum = np.add.reduceat(data, N.indptr[:-1]) if N.nnz else np.zeros(nr)
+        rowsum[np.diff(N.indptr) == 0] = 0.0
+        strong = off & (data >= theta * rowsum[rows])
+    elif rule == 1:
+        offv = np.where(off, data, 0.0)
+        mx = np.zeros(nr)
+        np.maximum.at(mx, rows, offv)
+        strong = off & (data >= theta * mx[rows])
+    else:
+        strong = np.zeros(N.nnz, dtype=bool)
+        for i in range(nr):
+            a, b = N.indptr[i], N.indptr[i + 1]
+            cand = np.nonzero(off[a:b])[0]
+            if cand.size == 0:
+                continue
+            order = np.lexsort((ind[a:b][cand], -data[a:b][cand]))
+            strong[a + cand[order[:top_s]]] = True
+    counts = np.bincount(rows[strong], minlength=nr)
+    indptr = np.zeros(nr + 1, dtype=np.int64)
+    np.cumsum(counts, out=indptr[1:])
+    return indptr, ind[strong].astype(np.int64)
+
+
+def rs_coarsen(S_indptr, S_indices, npts):
+    """Algorithm 1 (one-pass Ruge-Stueben).  Returns a bool array, True for C-points.
+
+    "i strongly influences j" means i is in S_j.  lambda_i starts as the number of points that i
+    strongly influences; the undecided point with maximal lambda (lowest index on ties, R5) becomes
+    C; the undecided points it strongly influences become F; every undecided point that strongly
+    influences one of the new F-points has its lambda incremented.
+    """
+    # influence lists: T_i = { j : i in S_j }
+    cnt = np.bincount(S_indices, minlength=npts)
+    T_ptr = np.zeros(npts + 1, dtype=np.int64)
+    np.cumsum(cnt, out=T_ptr[1:])
+    rows = np.repeat(np.arange(npts), np.diff(S_indptr))
+    order = np.argsort(S_indices, kind="stable")
+    T_idx = rows[order]
+    lam = cnt.astype(np.int64).copy()
+    state = np.zeros(npts, dtype=np.int8)       # 0 undecided, 1 C, 2 F
+    heap = [(-int(lam[i]), i) for i in range(npts)]
+    heapq.heapify(heap)
+    while heap:
+        negl, i = heapq.heappop(heap)
+        if state[i] != 0 or -negl != lam[i]:
+            continue
+        state[i] = 1
+        for j in T_idx[T_ptr[i]:T_ptr[i + 1]]:
+            if state[j] == 0:
+                state[j] = 2
+                for k in S_indices[S_indptr[j]:S_indptr[j + 1]]:
+                    if state[k] == 0:
+                        lam[k] += 1
+                        heapq.heappush(heap, (-int(lam[k]), int(k)))
+    return state == 1
+
+
+def interp_pattern(S_indptr, S_indices, N, is_c, cap):
+    """Coarse interpolatory sets C^i = S_i intersected with C (§3.7), capped (R13).
+
+    Returns (ptr, fine_cols, n_capped): for every fine point i, the fine ids of the C-points that
+    interpolate to it (for a C-point: itself), sorted ascending.
+    """
+    N = sp.csr_matrix(N)
+    npts = is_c.size
+    ptr = np.zeros(npts + 1, dtype=np.int64)
+    cols = []
+    capped = 0
+    for i in range(npts):
+        if is_c[i]:
+            sel = np.array([i], dtype=np.int64)
+        else:
+            s = S_indices[S_indptr[i]:S_indptr[i + 1]]
+            sel = s[is_c[s]]
+            if sel.size > cap:
+                capped += 1
+                a, b = N.indptr[i], N.indptr[i + 1]
+                rowc, rowv = N.indices[a:b], np.abs(N.data[a:b])
+                mag = rowv[np.searchsorted(rowc, sel)]
+                keep = np.lexsort((sel, -mag))[:cap]
+                sel = np.sort(sel[keep])
+        cols.append(sel)
+        ptr[i + 1] = ptr[i] + sel.size
+    return ptr, (np.concatenate(cols) if cols else np.zeros(0, np.int64)), capped
+
+
+# ----------------------------------------------------------------------------------------------
+# §3.8: least-squares interpolation weights
+# ----------------------------------------------------------------------------------------------
+def ls_interpolation(ptr, fine_cols, is_c, Uf, Ub_values, w):
+    """Interpolation matrix P (npts x n_c) with unit rows at C-points and LS weights at F-points.
+
+    For each F-point i:  minimise sum_k w_k (b_k^i - sum_{j in C^i} p_ij u_k^j)^2  over p_i
+    (eq. (LS) of §3.8, rows weighted by w_k, R19), where u_k^j are the values of the fitted vectors
+    at the interpolating C-points (their injected coarse values) and b_k^i the values at i
+    (``Ub_values``: the vectors themselves, or their Jacobi-smoothed values for minimal targets).
+    Normal equations with the R12 regularisation, solved per F-point.
+    """
+    npts = is_c.size
+    cidx = np.cumsum(is_c) - 1                     # alpha(i): coarse index of a C-point
+    n_c = int(is_c.sum())
+    sizes = np.diff(ptr)
+    data = np.zeros(fine_cols.size)
+    data[ptr[:-1][is_c]] = 1.0
+    F = np.nonzero(~is_c)[0]
+    for q in np.unique(sizes[F]):
+        if q == 0:
+            continue
+        Fi = F[sizes[F] == q]
+        idx = ptr[Fi][:, None] + np.arange(q)[None, :]
+        J = fine_cols[idx]                         # (nF, q) fine ids of interpolating C-points
+        G = Uf[J]                                  # (nF, q, nf)
+        G = np.transpose(G, (0, 2, 1))             # (nF, nf, q)
+        b = Ub_values[Fi]                          # (nF, nf)
+        GtW = np.transpose(G, (0, 2, 1)) * w[None, None, :]
+        Nm = GtW @ G                               # (nF, q, q)
+        rhs = np.einsum("fqk,fk->fq", GtW, b)
+        eps = 1e-13 * np.trace(Nm, axis1=1, axis2=2) / q
+        Nm = Nm + eps[:, None, None] * np.eye(q)[None]
+        p = np.linalg.solve(Nm, rhs[..., None])[..., 0]
+        data[idx] = p
+    P = sp.csr_matrix((data, cidx[fine_cols], ptr), shape=(npts, n_c))
+    return P
+
+
+# ----------------------------------------------------------------------------------------------
+# Multicolour ordering for Kaczmarz (R8)
+# ----------------------------------------------------------------------------------------------
+def greedy_row_colouring(M):
+    """Greedy first-fit colouring in row order of the graph 'rows sharing a column'."""
+    M = sp.csr_matrix(M)
+    MT = M.T.tocsr()
+    nr = M.shape[0]
+    colour = np.full(nr, -1, dtype=np.int64)
+    for i in range(nr):
+        cols = M.indices[M.indptr[i]:M.indptr[i + 1]]
+        used = set()
+        for k in cols:
+            for r in MT.indices[MT.indptr[k]:MT.indptr[k + 1]]:
+                if r < i:
+                    used.add(int(colour[r]))
+        c = 0
+        while c in used:
+            c += 1
+        colour[i] = c
+    return colour
+
+
+def colour_groups(colour):
+    """Rows of each colour, colours ascending, rows ascending."""
+    if colour.size == 0:
+        return []
+    return [np.nonzero(colour == c)[0] for c in range(int(colour.max()) + 1)]
+
+
+def kaczmarz_sweep(M, x, rhs, groups, rownorm2=None):
+    """One Kaczmarz sweep on M x = rhs (weight 1), row by row in the order of ``groups``.
+
+    Rows of one group share no column, so processing a group at once equals processing its rows
+    one after another.  Rows with zero norm are skipped.  x is (n, k), rhs is (nrows, k) or None;
+    ``rownorm2`` (nrows,) or (nrows, k) defaults to the squared row norms of M.
+    """
+    M = sp.csr_matrix(M)
+    if rownorm2 is None:
+        rownorm2 = np.asarray(M.multiply(M).sum(axis=1)).ravel()
+    x = x.copy()
+    for rows in groups:
+        Mr = M[rows]
+        r = (rhs[rows] if rhs is not None else 0.0) - Mr @ x
+        rn = rownorm2[rows]
+        rn = rn[:, None] if rn.ndim == 1 else rn
+        coef = np.where(rn > 0, r / np.where(rn > 0, rn, 1.0), 0.0)
+        x += Mr.T @ coef
+    return x
+
+
+# ----------------------------------------------------------------------------------------------
+# Level data
+# ----------------------------------------------------------------------------------------------
+@dataclass
+class Side:
+    """Coarsening data of one set of variables (u or v; x for eigenproblems)."""
+    is_c: np.ndarray
+    cpts: np.ndarray
+    ptr: np.ndarray
+    fine_cols: np.ndarray
+    capped: int
+    P: sp.csr_matrix | None = None
+
+
+@dataclass
+class Level:
+    A: sp.csr_matrix
+    B: sp.csr_matrix
+    C: sp.csr_matrix | None
+    groups_A: list = field(default_factory=list)     # Kaczmarz order over rows of A
+    groups_At: list = field(default_factory=list)    # over rows of A^t (SVD only)
+    su: Side | None = None
+    sv: Side | None = None
+
+    @property
+    def At(self):
+        return self.A.T.tocsr()
+
+
+def _colourings(lev, kind, params):
+    order = (lambda M: [np.array([i]) for i in range(M.shape[0])]) if params.kaczmarz_order == 1 \
+        else (lambda M: colour_groups(greedy_row_colouring(M)))
+    if kind == SPD:
+        lev.groups_A = order(_ones(lev.A) + _ones(lev.B))
+    else:
+        lev.groups_A = order(lev.A)
+        lev.groups_At = order(lev.At)
+
+
+# ----------------------------------------------------------------------------------------------
+# Relaxation (§3.4, §3.5, §5.3)
+# ----------------------------------------------------------------------------------------------
+def _bnorm(M, X):
+    return np.sqrt(np.maximum(np.sum(X * (M @ X), axis=0), 0.0))
+
+
+def relax_test_dominant(lev, kind, U, V, omega):
+    """One outer power-method step with one weighted-Jacobi inner step (§3.4).
+
+    SVD: v_bar = v - omega D_C^-1 (C v - A^t u), v = v_bar / ||v_bar||_C, then
+         u_bar = u - omega D_B^-1 (B u - A v),   u = u_bar / ||u_bar||_B.
+    Eigenproblem: x_bar = x - omega D_B^-1 (B x - A x), x = x_bar / ||x_bar||_B.
+    """
+    A, B, C = lev.A, lev.B, lev.C
+    if kind == SPD:
+        Xb = U - omega * (B @ U - A @ U) / _diag(B)[:, None]
+        return Xb / _bnorm(B, Xb), None
+    Vb = V - omega * (C @ V - A.T @ U) / _diag(C)[:, None]
+    V = Vb / _bnorm(C, Vb)
+    Ub = U - omega * (B @ U - A @ V) / _diag(B)[:, None]
+    U = Ub / _bnorm(B, Ub)
+    return U, V
+
+
+def relax_test_minimal(lev, kind, U, V):
+    """One Kaczmarz sweep on A v = 0 then on A^t u = 0 (SVD) or on A x = 0, then B/C-normalise
+    (§5.3, R6, R8)."""
+    if kind == SPD:
+        X = kaczmarz_sweep(lev.A, U, None, lev.groups_A)
+        return X / _bnorm(lev.B, X), None
+    V = kaczmarz_sweep(lev.A, V, None, lev.groups_A)
+    V = V / _bnorm(lev.C, V)
+    U = kaczmarz_sweep(lev.At, U, None, lev.groups_At)
+    U = U / _bnorm(lev.B, U)
+    return U, V
+
+
+def relax_boot_dominant(lev, kind, U, V, sig, kap, tau, omega):
+    """Block Gauss-Seidel with one weighted-Jacobi inner step per block (§3.5):
+    u <- u - omega D_B^-1 (B u - (A v - kappa)/sigma), then v <- v - omega D_C^-1 (C v - (A^t u - tau)/sigma).
+    Eigenproblem: x <- x - omega D_B^-1 (B x - (A x - kappa)/lambda)."""
+    A, B, C = lev.A, lev.B, lev.C
+    if kind == SPD:
+        return U - omega * (B @ U - (A @ U - kap) / sig[None, :]) / _diag(B)[:, None], None
+    U = U - omega * (B @ U - (A @ V - kap) / sig[None, :]) / _diag(B)[:, None]
+    V = V - omega * (C @ V - (A.T @ U - tau) / sig[None, :]) / _diag(C)[:, None]
+    return U, V
+
+
+def relax_boot_minimal(lev, kind, U, V, sig, kap, tau):
+    """Block Gauss-Seidel with Kaczmarz blocks (§5.3, R7): v from A v = sigma B u + kappa, then u
+    from A^t u = sigma C v + tau.  Eigenproblem: Kaczmarz on (A - lambda_j B) x = kappa."""
+    A, B, C = lev.A, lev.B, lev.C
+    if kind == SPD:
+        X = U.copy()
+        for j in range(X.shape[1]):
+            Mj = sp.csr_matrix(A - sig[j] * B)
+            X[:, j:j + 1] = kaczmarz_sweep(Mj, X[:, j:j + 1], kap[:, j:j + 1], lev.groups_A)
+        return X, None
+    V = kaczmarz_sweep(A, V, sig[None, :] * (B @ U) + kap, lev.groups_A)
+    U = kaczmarz_sweep(A.T.tocsr(), U, sig[None, :] * (C @ V) + tau, lev.groups_At)
+    return U, V
+
+
+def rayleigh(lev, kind, U, V):
+    """Rayleigh quotient (3.31) per column: u^t A v / (||u||_B ||v||_C), or x^t A x / x^t B x."""
+    if kind == SPD:
+        return np.sum(U * (lev.A @ U), axis=0) / np.sum(U * (lev.B @ U), axis=0)
+    return np.sum(U * (lev.A @ V), axis=0) / (_bnorm(lev.B, U) * _bnorm(lev.C, V))
+
+
+def relax_boot_with_rq(lev, kind, target, U, V, sig, params):
+    """Multiplicative-phase boot relaxation: mu_b outer steps, each followed by a Rayleigh-quotient
+    update of sigma_b (§3.5) and the sign check of §5.3 (R21)."""
+    z_u = np.zeros_like(U)
+    z_v = None if V is None else np.zeros_like(V)
+    for _ in range(params.mu_b):
+        if target == DOMINANT:
+            U, V = relax_boot_dominant(lev, kind, U, V, sig, z_u, z_v, params.omega)
+        else:
+            U, V = relax_boot_minimal(lev, kind, U, V, sig, z_u, z_v)
+        sig = rayleigh(lev, kind, U, V)
+        neg = sig < 0
+        if np.any(neg):
+            U = U.copy(); U[:, neg] *= -1.0
+            sig = np.abs(sig)
+    return U, V, sig
+
+
+# ----------------------------------------------------------------------------------------------
+# Coarsest level (§3.6, Theorem 3.1 / 3.2) and additive coarsest solve (§4.2)
+# ----------------------------------------------------------------------------------------------
+def coarsest_gsvd(lev, kind, target, n_b):
+    """n_b extremal generalized singular triplets of (A, B, C), or eigenpairs of (A, B) (R10, R11)."""
+    A = lev.A.toarray(); B = lev.B.toarray()
+    if kind == SPD:
+        lam, X = sla.eigh(A, B)                          # ascending, B-orthonormal
+        idx = np.arange(n_b) if target == MINIMAL else np.arange(lam.size - 1, lam.size - 1 - n_b, -1)
+        return lam[idx].copy(), X[:, idx].copy(), None
+    C = lev.C.toarray()
+    LB = np.linalg.cholesky(B); LC = np.linalg.cholesky(C)
+    D = sla.solve_triangular(LB, sla.solve_triangular(LC, A.T, lower=True).T, lower=True)
+    T, s, Wt = np.linalg.svd(D, full_matrices=True)      # descending
+    l = s.size
+    idx = np.arange(n_b) if target == DOMINANT else np.arange(l - 1, l - 1 - n_b, -1)
+    U = sla.solve_triangular(LB.T, T[:, idx], lower=False)
+    V = sla.solve_triangular(LC.T, Wt.T[:, idx], lower=False)
+    return s[idx].copy(), U, V
+
+
+def pencil_matrices(lev, kind):
+    """Dense X and Y of (3.10)-(3.11) (SVD) or A and B (eigenproblem) on the coarsest level."""
+    if kind == SPD:
+        return lev.A.toarray(), lev.B.toarray()
+    m, n = lev.A.shape
+    X = np.zeros((m + n, m + n)); Y = np.zeros((m + n, m + n))
+    Ad = lev.A.toarray()
+    X[:m, m:] = Ad; X[m:, :m] = Ad.T
+    Y[:m, :m] = lev.B.toarray(); Y[m:, m:] = lev.C.toarray()
+    return X, Y
+
+
+def coarse_pinv_solve(X, Y, sig, rhs):
+    """Per column j: pseudo-inverse of X - sigma_j Y from its SVD with the smallest singular
+    component left out, applied to rhs[:, j] (§4.2, R17 literal)."""
+    out = np.zeros_like(rhs)
+    for j in range(rhs.shape[1]):
+        W, s, Zt = np.linalg.svd(X - sig[j] * Y)
+        k = s.size - 1
+        out[:, j] = Zt[:k].T @ ((W[:, :k].T @ rhs[:, j]) / s[:k])
+    return out
+
+
+def coarse_pencil_solve(X, Y, sig, rhs):
+    """R17 variant 1: with the Y-orthonormal pencil eigenbasis X z = mu Y z, apply
+    sum_{i != i*} z_i z_i^t / (mu_i - sigma_j), i* = argmin |mu_i - sigma_j|."""
+    mu, Z = sla.eigh(X, Y)
+    out = np.zeros_like(rhs)
+    for j in range(rhs.shape[1]):
+        d = mu - sig[j]
+        keep = np.ones(mu.size, dtype=bool); keep[np.argmin(np.abs(d))] = False
+        out[:, j] = Z[:, keep] @ ((Z[:, keep].T @ rhs[:, j]) / d[keep])
+    return out
+
+
+# ----------------------------------------------------------------------------------------------
+# §4.3: Ritz projection on the finest level (B = I, C = I)
+# ----------------------------------------------------------------------------------------------
+def ritz(A, kind, target, U, V, u_from_v=False, anorm=1.0):
+    if kind == SPD:
+        Xh, _ = np.linalg.qr(U)
+        M = Xh.T @ (A @ Xh)
+        M = 0.5 * (M + M.T)
+        lam, Yv = np.linalg.eigh(M)
+        order = np.argsort(lam) if target == MINIMAL else np.argsort(-lam)
+        return lam[order], Xh @ Yv[:, order], None
+    Uh, _ = np.linalg.qr(U)
+    Vh, _ = np.linalg.qr(V)
+    M = Uh.T @ (A @ Vh)
+    Y, s, Zt = np.linalg.svd(M)
+    order = np.argsort(s) if target == MINIMAL else np.argsort(-s)
+    s, U, V = s[order], Uh @ Y[:, order], Vh @ Zt.T[:, order]
+    if u_from_v:
+        # R23: left vectors of non-zero Ritz values taken from A v_j, which removes the components
+        # in the null space of A^t that relaxation never changes.
+        AV = A @ V
+        nrm = np.linalg.norm(AV, axis=0)
+        ok = s > 1e-8 * anorm
+        U[:, ok] = AV[:, ok] / nrm[ok]
+    return s, U, V
+
+
+def residuals(A, kind, U, V, sig, anorm):
+    """R18: rho_j (unit vectors assumed)."""
+    if kind == SPD:
+        return np.linalg.norm(A @ U - U * sig[None, :], axis=0) / anorm
+    r1 = np.linalg.norm(A @ V - U * sig[None, :], axis=0)
+    r2 = np.linalg.norm(A.T @ U - V * sig[None, :], axis=0)
+    return np.maximum(r1, r2) / anorm
+
+
+def norm_estimate(A, seed, steps=30):
+    """R18: ||A||_2 estimate from power steps on A^t A started from a SplitMix64 vector."""
+    x = _splitmix_uniform(seed ^ NORM_SEED_XOR, A.shape[1])
+    x /= np.linalg.norm(x)
+    for _ in range(steps):
+        y = A.T @ (A @ x)
+        ny = np.linalg.norm(y)
+        if ny == 0:
+            return 0.0
+        x = y / ny
+    return float(np.linalg.norm(A @ x))
+
+
+# ----------------------------------------------------------------------------------------------
+# Hierarchy construction pieces
+# ----------------------------------------------------------------------------------------------
+def strength_operators(lev, kind, params, finest=True):
+    """Operators strength is measured on (§3.7, §5.1-5.2): A (eigenproblem), A A^t and A^t A (SVD).
+    The document-frequency filter of rule 2 applies on the finest level only (R3)."""
+    if kind == SPD:
+        return lev.A, None
+    A = lev.A
+    if finest and params.strength_rule == 2 and params.df_filter > 0:
+        df = np.diff(A.indptr)
+        keep = (df <= params.df_filter * A.shape[1]).astype(np.float64)
+        A = sp.diags(keep) @ A
+        A = sp.csr_matrix(A)
+    At = A.T.tocsr()
+    return structural_product(A, At), structural_product(At, A)
+
+
+def build_side(N, params, n_t):
+    Sp, Si = strength_sets(N, params.theta, params.strength_rule, params.top_s)
+    is_c = rs_coarsen(Sp, Si, N.shape[0])
+    ptr, cols, capped = interp_pattern(Sp, Si, N, is_c, n_t - 1)
+    return Side(is_c, np.nonzero(is_c)[0], ptr, cols, capped)
+
+
+def minimal_presmooth(lev, kind, side_is_u, Vals, omega):
+    """Extra Jacobi step on N z = 0 applied to the F-point values before the LS fit (§3.8, R22)."""
+    A = lev.A
+    if kind == SPD:
+        NZ = A @ Vals; d = _diag(A)
+    elif side_is_u:
+        NZ = A @ (A.T @ Vals); d = np.asarray(A.multiply(A).sum(axis=1)).ravel()
+    else:
+        NZ = A.T @ (A @ Vals); d = np.asarray(A.multiply(A).sum(axis=0)).ravel()
+    d = np.where(d > 0, d, 1.0)
+    return Vals - omega * NZ / d[:, None]
+
+
+def ls_weights(lev, kind, target, U, V, anorm):
+    rq = rayleigh(lev, kind, U, V)
+    if target == DOMINANT:
+        return np.abs(rq)
+    return 1.0 / np.maximum(np.abs(rq), 1e-12 * anorm)
+
+
+def galerkin(lev, kind):
+    """(3.4): A_c = P^t A Q, B_c = P^t B P, C_c = Q^t C Q (eigenproblem: P^t A P, P^t B P)."""
+    P = lev.su.P
+    if kind == SPD:
+        return Level(structural_product(P.T.tocsr(), lev.A, P), structural_product(P.T.tocsr(), lev.B, P), None)
+    Q = lev.sv.P
+    return Level(structural_product(P.T.tocsr(), lev.A, Q), structural_product(P.T.tocsr(), lev.B, P),
+                 structural_product(Q.T.tocsr(), lev.C, Q))
+
+
+def level_size(lev, kind):
+    return lev.A.shape[0] if kind == SPD else lev.A.shape[0] + lev.A.shape[1]
+
+
+# ----------------------------------------------------------------------------------------------
+# The solver
+# ----------------------------------------------------------------------------------------------
+@dataclass
+class Result:
+    sigma: np.ndarray
+    U: np.ndarray
+    V: np.ndarray | None
+    report: dict
+
+
+class Solver:
+    """Hybrid multiplicative-additive solver (§3, §4, §5) on a prepared (m >= n, no empty rows or
+    columns) matrix."""
+
+    def __init__(self, A, kind, target, n_b, params: Params, init=None):
+        self.kind, self.target, self.n_b, self.p = kind, target, n_b, params
+        A = sp.csr_matrix(A, dtype=np.float64)
+        A.sort_indices()
+        m, n = A.shape
+        I_m = sp.identity(m, format="csr"); I_n = sp.identity(n, format="csr")
+        self.levels = [Level(A, I_m, None if kind == SPD else I_n)]
+        _colourings(self.levels[0], kind, params)
+        if init is None:
+            self.Ut, self.Vt = initial_test_vectors(kind, m, n, params.n_t, params.seed)
+        else:
+            self.Ut, self.Vt = init
+        self.anorm = norm_estimate(A, params.seed)
+        self.sig = None; self.Ub = None; self.Vb = None
+        self.report = dict(levels=0, sizes=[], mult_sigma=[], add_sigma=[], rho=[], capped=[],
+                           colours=[], mult_cycles=0, add_iters=0, anorm=self.anorm)
+
+    # -------------------------------------------------------------- multiplicative cycle (§3.3)
+    def mult_cycle(self, c):
+        kind, target, p = self.kind, self.target, self.p
+        Ut, Vt = self.Ut, self.Vt
+        Ub, Vb, sig = self.Ub, self.Vb, self.sig
+        tests_u, tests_v = [Ut], [Vt]
+        l = 0
+        while True:
+            lev = self.levels[l]
+            if c == 1:
+                if self._is_coarsest_size(l):
+                    break
+                Nu, Nv = strength_operators(lev, kind, p, l == 0)
+                su = build_side(Nu, p, p.n_t)
+                sv = None if kind == SPD else build_side(Nv, p, p.n_t)
+                if not self._coarsening_ok(lev, su, sv):
+                    break
+                lev.su, lev.sv = su, sv
+                self.report["capped"].append(su.capped + (0 if sv is None else sv.capped))
+            elif l == len(self.levels) - 1:
+                break
+            # relax test vectors (§3.4 / §5.3)
+            for _ in range(p.mu_t):
+                if target == DOMINANT:
+                    Ut, Vt = relax_test_dominant(lev, kind, Ut, Vt, p.omega)
+                else:
+                    Ut, Vt = relax_test_minimal(lev, kind, Ut, Vt)
+            tests_u[l], tests_v[l] = Ut, Vt
+            if c >= 2:
+                Ub, Vb, sig = relax_boot_with_rq(lev, kind, target, Ub, Vb, sig, p)
+            # LS fit of P (and Q) (§3.8)
+            if c == 1:
+                Uf, Vf = Ut, Vt
+            else:
+                Uf = np.hstack([Ut, Ub]); Vf = None if kind == SPD else np.hstack([Vt, Vb])
+            w = ls_weights(lev, kind, target, Uf, Vf, self.anorm)
+            self._fit(lev, lev.su, Uf, w, True)
+            if kind == SVD:
+                self._fit(lev, lev.sv, Vf, w, False)
+            # Galerkin coarse operators (3.4)
+            coarse = galerkin(lev, kind)
+            if c == 1:
+                _colourings(coarse, kind, p)
+                self.levels.append(coarse)
+            else:
+                old = self.levels[l + 1]
+                old.A, old.B, old.C = coarse.A, coarse.B, coarse.C
+            # injection (§3.3)
+            Ut = Ut[lev.su.cpts]
+            Vt = None if kind == SPD else Vt[lev.sv.cpts]
+            tests_u.append(Ut); tests_v.append(Vt)
+            if c >= 2:
+                Ub = Ub[lev.su.cpts]
+                Vb = None if kind == SPD else Vb[lev.sv.cpts]
+            l += 1
+        L = l
+        if c == 1:
+            self.report["levels"] = L + 1
+            self.report["sizes"] = [lv.A.shape for lv in self.levels]
+        # coarsest generalized SVD (§3.6)
+        sig, Ub, Vb = coarsest_gsvd(self.levels[L], kind, target, self.n_b)
+        # upward sweep: multiplicative interpolation, boot relaxation with RQ updates (§3.3)
+        for l in range(L - 1, -1, -1):
+            lev = self.levels[l]
+            Ub = lev.su.P @ Ub
+            Vb = None if kind == SPD else lev.sv.P @ Vb
+            Ub, Vb, sig = relax_boot_with_rq(lev, kind, target, Ub, Vb, sig, p)
+        self.Ut, self.Vt = tests_u[0], tests_v[0]
+        if p.ritz_in_mult:
+            sig, Ub, Vb = self._ritz(Ub, Vb)
+        self.sig, self.Ub, self.Vb = sig, Ub, Vb
+        self.report["mult_sigma"].append(sig.copy())
+
+    def _ritz(self, U, V):
+        ufv = bool(self.p.u_from_v) and self.kind == SVD and self.target == MINIMAL
+        return ritz(self.levels[0].A, self.kind, self.target, U, V, ufv, self.anorm)
+
+    def _is_coarsest_size(self, l):
+        return level_size(self.levels[l], self.kind) <= self.p.coarse_max or l + 1 >= self.p.max_levels
+
+    def _coarsening_ok(self, lev, su, sv):
+        kind, p = self.kind, self.p
+        nc_u = int(su.is_c.sum())
+        nc = nc_u if kind == SPD else nc_u + int(sv.is_c.sum())
+        if nc > p.stall_ratio * level_size(lev, kind):
+            return False
+        need = self.n_b + p.n_t
+        if nc_u < need or (kind == SVD and int(sv.is_c.sum()) < need):
+            return False
+        return True
+
+    def _fit(self, lev, side, Vals, w, is_u):
+        bvals = Vals
+        if self.target == MINIMAL:
+            bvals = minimal_presmooth(lev, self.kind, is_u, Vals, self.p.omega)
+        side.P = ls_interpolation(side.ptr, side.fine_cols, side.is_c, Vals, bvals, w)
+
+    # -------------------------------------------------------------- additive V-cycle (§4.1-4.2)
+    def additive_vcycle(self):
+        kind, target, p, sig = self.kind, self.target, self.p, self.sig
+        L = len(self.levels) - 1
+        us, vs = [self.Ub], [self.Vb]
+        kaps = [np.zeros_like(self.Ub)]
+        taus = [None if kind == SPD else np.zeros_like(self.Vb)]
+
+        def relax(l, U, V, kap, tau):
+            lev = self.levels[l]
+            for _ in range(p.mu_b):
+                if target == DOMINANT:
+                    U, V = relax_boot_dominant(lev, kind, U, V, sig, kap, tau, p.omega)
+                else:
+                    U, V = relax_boot_minimal(lev, kind, U, V, sig, kap, tau)
+            return U, V
+
+        for l in range(L):
+            lev = self.levels[l]
+            U, V = relax(l, us[l], vs[l], kaps[l], taus[l])
+            us[l], vs[l] = U, V
+            if kind == SPD:
+                r = kaps[l] - (lev.A @ U - (lev.B @ U) * sig[None, :])
+                kaps.append(lev.su.P.T @ r); taus.append(None)
+                us.append(np.zeros((lev.su.cpts.size, self.n_b))); vs.append(None)
+            else:
+                r = kaps[l] - (lev.A @ V - (lev.B @ U) * sig[None, :])
+                s = taus[l] - (lev.A.T @ U - (lev.C @ V) * sig[None, :])
+                kaps.append(lev.su.P.T @ r); taus.append(lev.sv.P.T @ s)
+                us.append(np.zeros((lev.su.cpts.size, self.n_b)))
+                vs.append(np.zeros((lev.sv.cpts.size, self.n_b)))
+        X, Y = pencil_matrices(self.levels[L], kind)
+        rhs = kaps[L] if kind == SPD else np.vstack([kaps[L], taus[L]])
+        z = (coarse_pinv_solve if p.coarse_pinv == 0 else coarse_pencil_solve)(X, Y, sig, rhs)
+        if kind == SPD:
+            us[L] = z
+        else:
+            mL = self.levels[L].A.shape[0]
+            us[L], vs[L] = z[:mL], z[mL:]
+        for l in range(L - 1, -1, -1):
+            lev = self.levels[l]
+            U = us[l] + lev.su.P @ us[l + 1]
+            V = None if kind == SPD else vs[l] + lev.sv.P @ vs[l + 1]
+            us[l], vs[l] = relax(l, U, V, kaps[l], taus[l])
+        self.Ub, self.Vb = us[0], vs[0]
+
+    # -------------------------------------------------------------- driver (§3.3, §4)
+    def run(self):
+        p, A0 = self.p, self.levels[0].A
+        for c in range(1, p.n_mult + 1):
+            self.mult_cycle(c)
+            self.report["mult_cycles"] = c
+        if not p.ritz_in_mult:
+            self.sig, self.Ub, self.Vb = self._ritz(self.Ub, self.Vb)
+        rho = residuals(A0, self.kind, self.Ub, self.Vb, self.sig, self.anorm)
+        self.report["rho"].append(rho)
+        it = 0
+        while rho.max() > p.tol and it < p.max_add:
+            self.additive_vcycle()
+            self.sig, self.Ub, self.Vb = self._ritz(self.Ub, self.Vb)
+            rho = residuals(A0, self.kind, self.Ub, self.Vb, self.sig, self.anorm)
+            it += 1
+            self.report["rho"].append(rho)
+            self.report["add_sigma"].append(self.sig.copy())
+        self.report["add_iters"] = it
+        self.report["converged"] = bool(rho.max() <= p.tol)
+        return self.sig, self.Ub, self.Vb
+
+
+def _sign_normalise(U, V):
+    """Output convention: the entry of largest magnitude of v_j (x_j) is positive (lowest index on
+    ties)."""
+    ref = V if V is not None else U
+    for j in range(ref.shape[1]):
+        k = int(np.argmax(np.abs(ref[:, j])))
+        if ref[k, j] < 0:
+            U[:, j] *= -1.0
+            if V is not None:
+                V[:, j] *= -1.0
+    return U, V
+
+
+def solve(A, kind, target, n_b, params: Params | None = None, init=None) -> Result:
+    """Entry point: n_b dominant or minimal singular triplets (kind 'svd') or eigenpairs (kind
+    'spd') of the sparse matrix A, following §3-§5.
+
+    The matrix is transposed when m < n (§1 assumes m >= n) and empty rows and columns are removed
+    (R2).  ``init`` optionally gives the initial test vectors (U_t, V_t) for the prepared matrix.
+    Returns sigma (sorted descending for dominant, ascending for minimal), unit-norm U (m x n_b)
+    and V (n x n_b; None for eigenproblems), and a report.
+    """
+    params = params or Params()
+    A = sp.csr_matrix(A, dtype=np.float64)
+    A.sort_indices()
+    m0, n0 = A.shape
+    transposed = False
+    if kind == SVD and m0 < n0:
+        A = A.T.tocsr(); transposed = True
+    m, n = A.shape
+    rows_keep = np.nonzero(np.diff(A.indptr) > 0)[0]
+    cols_keep = np.nonzero(np.bincount(A.indices, minlength=n) > 0)[0]
+    if kind == SPD:
+        keep = np.union1d(rows_keep, cols_keep)
+        Ar = A[keep][:, keep]
+        rows_keep = cols_keep = keep
+    else:
+        Ar = A[rows_keep][:, cols_keep]
+    Ar = sp.csr_matrix(Ar); Ar.sort_indices()
+    s = Solver(Ar, kind, target, n_b, params, init)
+    sig, U, V = s.run()
+    Ufull = np.zeros((m, n_b)); Ufull[rows_keep] = U
+    Vfull = None
+    if kind == SVD:
+        Vfull = np.zeros((n, n_b)); Vfull[cols_keep] = V
+    Ufull, Vfull = _sign_normalise(Ufull, Vfull)
+    if transposed:
+        Ufull, Vfull = Vfull, Ufull
+    s.report["solver"] = s
+    return Result(sig, Ufull, Vfull, s.report)
