@@ -1,0 +1,172 @@
+#!/usr/bin/env python
+"""Benchmark of the self-learning AMG solver on one MI355X.
+
+One step = one complete solve (multiplicative set-up phase + additive phase with Ritz steps down
+to relative residual 1e-8) of the named workload, with the matrix resident in device memory when
+the timed region starts.  Prints ONE JSON line (see the design doc for the definitions):
+
+  value      triplets/s = n_b / (seconds per solve)
+  roofline   the dominant kernel class, timed live with HIP events on the library's stream over the
+             timed steps: algorithmic bytes per launch / average launch duration, against 8 TB/s
+  cpu_baseline  the FP64 oracle on the host cores, on a bounded sample of the same workload
+             (the multiplicative phase plus a few additive iterations, scaled to the iteration
+             count of the GPU solve)
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+CLASS_NAMES = {0: "finest-level operator row kernels (k_spmm / k_rowop / k_dots)",
+               1: "finest-level Kaczmarz sweeps (k_kacz)", 2: "MFMA FP64 Gram (k_gram)",
+               3: "Galerkin SpGEMM (k_spgemm_dot)", 4: "coarsest dense solves"}
+DEFAULT_WORKLOAD = "gradient2d_256_dom8"
+
+
+def _closed_form(name, n_b, target):
+    from paper_1102_0919_amd import workloads as W
+    if name.startswith("gradient2d_256"):
+        s = W.gradient2d_singular_values(256)
+        return s[::-1][:n_b] if target == "dominant" else s[:n_b]
+    if name.startswith("laplace2d_31"):
+        e = W.laplace2d_eigs(31)
+        return e[:n_b] if target == "minimal" else e[::-1][:n_b]
+    if name.startswith("aniso3d_128"):
+        return W.aniso3d_eigs_smallest(128, 0.01, n_b)
+    return None
+
+
+def cpu_baseline(name, A, wl, gpu_add_iters, budget_s=30.0):
+    """Oracle timing on a bounded sample: multiplicative phase + up to 5 additive iterations,
+    extrapolated to the GPU solve's additive iteration count."""
+    import numpy as np
+    from oracle import slamg_oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = 1
+    p = O.Params(**wl["params"])
+    t0 = time.perf_counter()
+    s = O.Solver(A, wl["kind"], wl["target"], wl["n_b"], p)
+    for c in range(1, p.n_mult + 1):
+        s.mult_cycle(c)
+    t_setup = time.perf_counter() - t0
+    k = 0
+    t1 = time.perf_counter()
+    while k < 5 and time.perf_counter() - t0 < budget_s:
+        s.additive_vcycle()
+        s.sig, s.Ub, s.Vb = s._ritz(s.Ub, s.Vb)
+        O.residuals(s.levels[0].A, s.kind, s.Ub, s.Vb, s.sig, s.anorm)
+        k += 1
+    t_iter = (time.perf_counter() - t1) / max(k, 1)
+    t_total = t_setup + t_iter * gpu_add_iters
+    return {"value": wl["n_b"] / t_total, "unit": "triplets/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"oracle multiplicative phase ({p.n_mult} cycles, {t_setup:.1f} s) + {k} additive "
+                      f"iterations ({t_iter:.3f} s each) on the same matrix, extrapolated to the GPU's "
+                      f"{gpu_add_iters} additive iterations; scipy sparse kernels are single-threaded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed_fp32"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the single-GPU "
+              "figure is the whole measurement", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1102_0919_amd import api, workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    name = args.workload
+    wl = W.WORKLOADS[name]
+    A = W.build_workload_matrix(name).to_scipy()
+    kind, target, n_b = wl["kind"], wl["target"], wl["n_b"]
+    stream = torch.cuda.current_stream()
+    prm = dict(wl["params"])
+    prm["precision"] = args.precision
+    prm["profile_mask"] = 0 if args.no_profile else (0b11111)
+    p = api.params_init(kind, target, **prm)
+    ctx = api.Context(0, stream=stream.cuda_stream)
+    mat = api.Matrix(ctx, A, kind)          # validated, prepared and resident in device memory
+    # the singular vectors are written to device arrays (column-major m x n_b, n x n_b)
+    U_dev = torch.empty((n_b, A.shape[0]), dtype=torch.float64, device="cuda")
+    V_dev = torch.empty((n_b, A.shape[1]), dtype=torch.float64, device="cuda") if kind == "svd" else None
+    print(f"[bench] workload {name}: {A.shape[0]}x{A.shape[1]} nnz={A.nnz} n_b={n_b} {args.precision}",
+          file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        api.solve_matrix(ctx, mat, target, n_b, p, U_dev=U_dev, V_dev=V_dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = []
+    for k in range(args.steps):
+        r = api.solve_matrix(ctx, mat, target, n_b, p, U_dev=U_dev, V_dev=V_dev)
+        reps.append(r)
+        print(f"[bench] step {k}: add_iters={r.report.add_iters} converged={r.converged}", file=sys.stderr,
+              flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    value = n_b / (ms / 1e3)
+    last = reps[-1]
+    # roofline of the dominant kernel class over the timed steps
+    tot_ms = np.zeros(8); tot_n = np.zeros(8); tot_b = np.zeros(8)
+    for r in reps:
+        for c in range(8):
+            tot_ms[c] += r.report.prof_ms[c]; tot_n[c] += r.report.prof_launches[c]
+            tot_b[c] += r.report.prof_bytes[c]
+    roof = None
+    if tot_ms.sum() > 0:
+        c = int(np.argmax(np.where(tot_b > 0, tot_ms, 0)))
+        avg_ms = tot_ms[c] / tot_n[c]
+        per_launch = tot_b[c] / tot_n[c]
+        ach = per_launch / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": CLASS_NAMES[c],
+                "launches_per_step": int(tot_n[c] / args.steps), "avg_launch_us": round(avg_ms * 1e3, 3),
+                "algorithmic_bytes_per_launch": int(per_launch),
+                "share_of_step": round(tot_ms[c] / args.steps / ms, 4),
+                "class_ms_per_step": {CLASS_NAMES[i]: round(tot_ms[i] / args.steps, 3) for i in range(5)}}
+    ref = _closed_form(name, n_b, target)
+    acc = {"max_rel_residual": float(max(last.report.resid[j] for j in range(n_b))),
+           "levels": int(last.report.levels), "add_iters": int(last.report.add_iters),
+           "mult_cycles": int(last.report.mult_cycles)}
+    if ref is not None:
+        err = np.abs(last.sigma - ref) / np.maximum(np.abs(ref), 1e-8 * last.report.anorm)
+        acc["max_rel_sigma_err_vs_closed_form"] = float(err.max())
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(name, A, wl, int(last.report.add_iters))
+    line = {"metric": "triplets/s at resid 1e-8", "value": round(value, 4), "unit": "triplets/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+            "data": "synthetic",
+            "config": {"workload": name, "description": wl["desc"], "rows": int(A.shape[0]),
+                       "cols": int(A.shape[1]), "nnz": int(A.nnz), "n_b": n_b, "kind": kind, "target": target,
+                       "precision": args.precision, "tol": 1e-8},
+            "roofline": roof, "cpu_baseline": cpu, "accuracy": acc,
+            "setup_ms": round(last.report.t_setup_ms, 3), "solve_ms": round(last.report.t_solve_ms, 3)}
+    mat.close()
+    ctx.close()
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

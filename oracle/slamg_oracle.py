@@ -873,8 +873,8 @@ def solve(A, kind, target, n_b, params: Params | None = None, init=None) -> Resu
     Vfull = None
     if kind == SVD:
         Vfull = np.zeros((n, n_b)); Vfull[cols_keep] = V
-    Ufull, Vfull = _sign_normalise(Ufull, Vfull)
     if transposed:
         Ufull, Vfull = Vfull, Ufull
+    Ufull, Vfull = _sign_normalise(Ufull, Vfull)
     s.report["solver"] = s
     return Result(sig, Ufull, Vfull, s.report)

@@ -1,0 +1,166 @@
+// Internal declarations shared by the HIP kernels, the host-side graph code and the solver.
+// Nothing here crosses the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace slamg {
+
+// ------------------------------------------------------------------------------------------------
+// Device CSR (int32 row pointers and column indices; all supported problems have nnz < 2^31).
+// Values are kept in FP64 and, in the mixed-precision mode, also in FP32.
+// ------------------------------------------------------------------------------------------------
+struct DCsr {
+  int m = 0, n = 0;
+  int nnz = 0;
+  int* rp = nullptr;      // m + 1
+  int* ci = nullptr;      // nnz, sorted within a row
+  double* v = nullptr;    // nnz
+  float* vf = nullptr;    // nnz, FP32 copy (mixed precision only)
+};
+
+// Host CSR pattern (+ optional values)
+struct HCsr {
+  int m = 0, n = 0;
+  std::vector<int> rp, ci;
+  std::vector<double> v;
+  int nnz() const { return rp.empty() ? 0 : rp.back(); }
+};
+
+// Launch configuration helpers ------------------------------------------------------------------
+struct ErrorState {
+  std::string msg;
+  int code = 0;
+};
+
+// status codes (mirrors slamg.h)
+enum {
+  ST_OK = 0,
+  ST_NOT_CONVERGED = 1,
+  ST_E_INVALID = -1,
+  ST_E_OOM = -2,
+  ST_E_BUDGET = -3,
+  ST_E_DEVICE = -4,
+  ST_E_NUMERIC = -5,
+  ST_E_BUSY = -6
+};
+
+// ------------------------------------------------------------------------------------------------
+// Kernel launchers (kernels.hip).  All take a stream; none synchronises.
+// Blocks are row-major rows x w, w <= 16 unless stated.
+// ------------------------------------------------------------------------------------------------
+enum MMode { M_NONE = 0, M_IDENT = 1, M_CSR = 2, M_SHARED = 3 };
+enum CMode {
+  C_JAC_TEST = 0,   // out = x + D*( w*(Kz) - w*(My) )
+  C_JAC_BOOT = 1,   // out = x + D*( (w/s)*(Kz) - w*(My) - (w/s)*kap )
+  C_RESID = 2,      // out = -(Kz) + s*(My) + kap
+  C_SMOOTH = 3,     // out = x + D*( -w*(Kz) )
+  C_COPYK = 4       // out = Kz (+ x if given)
+};
+
+template <typename T>
+struct RowOpArgs {
+  int nrows = 0, w = 0;
+  const int* Krp = nullptr; const int* Kci = nullptr; const T* Kv = nullptr; const T* z = nullptr;
+  int mmode = M_NONE;
+  const int* Mrp = nullptr; const int* Mci = nullptr; const T* Mv = nullptr; const T* y = nullptr;
+  const T* x = nullptr;      // nullable
+  const T* D = nullptr;      // nullable per-row scale
+  const T* kap = nullptr;    // nullable
+  const double* sig = nullptr;
+  int cmode = C_JAC_TEST;
+  double omega = 0.7;
+  T* out = nullptr;
+};
+
+template <typename T> void launch_rowop(const RowOpArgs<T>& a, hipStream_t s);
+
+template <typename T>
+void launch_spmm(int m, int w, const int* rp, const int* ci, const T* v, const T* x, T* y,
+                 double beta, hipStream_t s);
+
+template <typename T>
+struct KaczArgs {
+  int nrows = 0;             // rows in this colour
+  const int* rows = nullptr; // row ids of this colour
+  int w = 0;
+  const int* rp = nullptr; const int* ci = nullptr; const T* av = nullptr;
+  const T* bv = nullptr;     // shared-pattern B values (eigenproblem boot relaxation) or null
+  const double* lam = nullptr;
+  const T* rn_aa = nullptr; const T* rn_ab = nullptr; const T* rn_bb = nullptr;
+  int rmode = M_NONE;        // right-hand side operator on y: none / identity / CSR
+  const int* Mrp = nullptr; const int* Mci = nullptr; const T* Mv = nullptr; const T* y = nullptr;
+  const double* rsig = nullptr;
+  const T* kap = nullptr;
+  T* x = nullptr;
+};
+template <typename T> void launch_kacz(const KaczArgs<T>& a, hipStream_t s);
+
+// Column reductions: partial sums over a fixed grid, then a fixed-order finalisation.
+// value_ic = (K ? (K z)_ic : z_ic) - (y ? s_c y_ic : 0);  acc_c += a ? a_ic * value_ic : value_ic^2
+template <typename T>
+struct DotArgs {
+  int nrows = 0, w = 0;
+  const T* a = nullptr;
+  const int* Krp = nullptr; const int* Kci = nullptr; const T* Kv = nullptr;
+  const T* z = nullptr;
+  const T* y = nullptr; const double* sig = nullptr;
+};
+template <typename T> void launch_dots(const DotArgs<T>& a, double* partial, double* out, hipStream_t s);
+int dots_grid(int nrows, int w);
+
+void launch_gram(int rows, int w, const double* X, const double* Y, double* partial, double* G,
+                 hipStream_t s);
+int gram_grid(int rows);
+
+template <typename T>
+void launch_rotate(int rows, int win, int wout, const T* X, const double* S, T* out, hipStream_t s);
+template <typename T>
+void launch_gather_rows(int nout, int w, const int* idx, const T* X, T* out, hipStream_t s);
+template <typename T>
+void launch_scale_cols(int rows, int w, T* X, const double* d, int mode, hipStream_t s);
+void launch_rq_update(int w, const double* num, const double* nu, const double* nv, double* sig,
+                      double* flip, hipStream_t s);
+void launch_fill(double* p, size_t n, double val, hipStream_t s);
+void launch_fillf(float* p, size_t n, float val, hipStream_t s);
+void launch_copy_cast_df(const double* in, float* out, size_t n, hipStream_t s);
+void launch_copy_cast_fd(const float* in, double* out, size_t n, hipStream_t s);
+void launch_axpy_fd(const float* in, double* out, size_t n, hipStream_t s);   // out += in
+void launch_splitmix_block(long ru, long rv, int w, unsigned long long seed, double* U, double* V, hipStream_t s);
+void launch_sign_argmax(int rows, int w, const double* X, double* sgn, hipStream_t s);
+void launch_scatter_out(int rows, int w, const double* X, const int* keep, const double* sgn, double* out, long ld,
+                        hipStream_t s);
+void launch_recip(int n, const double* in, double* out, hipStream_t s);
+void launch_perm_gather(int n, const int* perm, const double* in, double* out, hipStream_t s);
+void launch_spgemm_dot(int nnz, const int* rowC, const int* colC, const int* rpL, const int* ciL,
+                       const double* vL, const int* rpR, const int* ciR, const double* vR, double* out,
+                       hipStream_t s);
+void launch_diag_inv(int m, const int* rp, const int* ci, const double* v, double* dinv, hipStream_t s);
+void launch_row_sq(int m, const int* rp, const double* v, const double* bv, double* aa, double* ab,
+                   double* bb, const int* ci, hipStream_t s);
+void launch_csr_to_dense(int m, const int* rp, const int* ci, const double* v, double* D, int ld,
+                         int roff, int coff, bool transpose, hipStream_t s);
+void launch_ls_fit(int nF, const int* Fpts, const int* prp, const int* fine_cols, int w1,
+                   const double* U1, int w2, const double* U2, const double* B1, const double* B2,
+                   const double* wts, double* pval, int qmax, hipStream_t s);
+void launch_rq_weights(int nf, const double* num, const double* nu, const double* nv, int minimal,
+                       double floor_abs, double* w, hipStream_t s);
+
+// dense.hip (single-workgroup dense FP64 procedures)
+void launch_chol_inv_upper(int w, const double* G, double* T, int* status, hipStream_t s);
+void launch_small_ritz(int w, int spd, int minimal, const double* M, double* Y, double* Z, double* sig,
+                       double* work, int* status, hipStream_t s);
+void launch_coarse_gsvd(int spd, int minimal, int mL, int nL, int nb, double* A, double* B, double* C,
+                        double* work, double* sig, double* U, double* V, int* status, hipStream_t s);
+void launch_pinv_solve(int N, int nb, const double* X, const double* Y, const double* sig,
+                       const double* rhs, double* out, double* work, int* status, hipStream_t s);
+void launch_pencil_setup(int N, double* X, double* Y, double* mu, double* Z, double* work,
+                         int* status, hipStream_t s);
+void launch_pencil_solve(int N, int nb, const double* mu, const double* Z, const double* sig,
+                         const double* rhs, double* out, hipStream_t s);
+void launch_dense_sym_eig(int n, double* A, double* V, double* lam, int* status, hipStream_t s);
+
+}  // namespace slamg

@@ -1,0 +1,582 @@
+// Small dense FP64 procedures run by one workgroup each: Cholesky factorisation, triangular
+// solves, a parallel-order two-sided Jacobi eigensolver, the coarsest-level generalized SVD /
+// eigenproblem (§3.6 with Theorem 3.1's change of variables), the additive coarsest solves
+// (§4.2: pseudo-inverse of X - sigma Y without its smallest singular component, and the pencil
+// variant), and the n_b x n_b Ritz problems (§4.3).  Matrices are row-major in global memory
+// (they are small and stay in L2); rotation parameters live in LDS.
+#include "common.h"
+
+namespace slamg {
+
+static constexpr int DBLK = 256;
+static constexpr int MAXPAIR = 512;   // matrices up to 1024 x 1024
+
+__device__ static void wg_sync() { __syncthreads(); }
+
+// A (n x n, ld) <- L (lower), A = L L^t.  Returns (in *info) 0 or the first failing pivot + 1;
+// a failing pivot is replaced by a tiny positive value so the factor stays finite.
+__device__ static void wg_chol(double* A, int n, int ld, int* info) {
+  __shared__ double dk_s;
+  for (int k = 0; k < n; ++k) {
+    wg_sync();
+    if (threadIdx.x == 0) {
+      double d = A[(long)k * ld + k];
+      if (!(d > 0.0)) {
+        if (*info == 0) *info = k + 1;
+        d = 1e-300;
+      }
+      d = sqrt(d);
+      A[(long)k * ld + k] = d;
+      dk_s = d;
+    }
+    wg_sync();
+    const double dk = dk_s;
+    for (int i = k + 1 + threadIdx.x; i < n; i += DBLK) A[(long)i * ld + k] /= dk;
+    wg_sync();
+    const int nt = n - k - 1;
+    for (long t = threadIdx.x; t < (long)nt * nt; t += DBLK) {
+      int i = k + 1 + (int)(t / nt), j = k + 1 + (int)(t % nt);
+      if (j <= i) A[(long)i * ld + j] -= A[(long)i * ld + k] * A[(long)j * ld + k];
+    }
+  }
+  wg_sync();
+  for (long t = threadIdx.x; t < (long)n * n; t += DBLK) {
+    int i = (int)(t / n), j = (int)(t % n);
+    if (j > i) A[(long)i * ld + j] = 0.0;
+  }
+  wg_sync();
+}
+
+// Solve L X = B in place (B: n x nc, ldb), L lower; one thread per right-hand side column.
+__device__ static void wg_trsm_lower(const double* L, int n, int ld, double* B, int nc, int ldb) {
+  wg_sync();
+  for (int c = threadIdx.x; c < nc; c += DBLK) {
+    for (int i = 0; i < n; ++i) {
+      double s = B[(long)i * ldb + c];
+      for (int k = 0; k < i; ++k) s -= L[(long)i * ld + k] * B[(long)k * ldb + c];
+      B[(long)i * ldb + c] = s / L[(long)i * ld + i];
+    }
+  }
+  wg_sync();
+}
+
+// Solve L^t X = B in place (B: n x nc), L lower.
+__device__ static void wg_trsm_lower_t(const double* L, int n, int ld, double* B, int nc, int ldb) {
+  wg_sync();
+  for (int c = threadIdx.x; c < nc; c += DBLK) {
+    for (int i = n - 1; i >= 0; --i) {
+      double s = B[(long)i * ldb + c];
+      for (int k = i + 1; k < n; ++k) s -= L[(long)k * ld + i] * B[(long)k * ldb + c];
+      B[(long)i * ldb + c] = s / L[(long)i * ld + i];
+    }
+  }
+  wg_sync();
+}
+
+__device__ static void wg_transpose(const double* A, int r, int c, int lda, double* B, int ldb) {
+  wg_sync();
+  for (long t = threadIdx.x; t < (long)r * c; t += DBLK) {
+    int i = (int)(t / c), j = (int)(t % c);
+    B[(long)j * ldb + i] = A[(long)i * lda + j];
+  }
+  wg_sync();
+}
+
+// Two-sided cyclic Jacobi with the round-robin parallel ordering: A (n x n symmetric) is reduced to
+// diagonal form in place; V accumulates the rotations (A_in = V diag V^t).
+__device__ static void wg_jacobi(double* A, int n, int ld, double* V, int ldv, int maxsweep) {
+  __shared__ int P[MAXPAIR], Q[MAXPAIR];
+  __shared__ double Cs[MAXPAIR], Sn[MAXPAIR];
+  __shared__ double red[DBLK], red2[DBLK];
+  for (long t = threadIdx.x; t < (long)n * n; t += DBLK) {
+    int i = (int)(t / n), j = (int)(t % n);
+    V[(long)i * ldv + j] = i == j ? 1.0 : 0.0;
+  }
+  const int N = n + (n & 1);
+  const int npair = N / 2;
+  if (n <= 1) { wg_sync(); return; }
+  for (int sweep = 0; sweep < maxsweep; ++sweep) {
+    wg_sync();
+    double off = 0.0, tot = 0.0;
+    for (long t = threadIdx.x; t < (long)n * n; t += DBLK) {
+      int i = (int)(t / n), j = (int)(t % n);
+      double a = A[(long)i * ld + j];
+      tot += a * a;
+      if (i != j) off += a * a;
+    }
+    red[threadIdx.x] = off; red2[threadIdx.x] = tot;
+    wg_sync();
+    for (int s = DBLK / 2; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s) { red[threadIdx.x] += red[threadIdx.x + s]; red2[threadIdx.x] += red2[threadIdx.x + s]; }
+      wg_sync();
+    }
+    const double offs = red[0], tots = red2[0];
+    wg_sync();
+    if (!(offs > 1e-32 * tots)) break;
+    for (int r = 0; r < N - 1; ++r) {
+      for (int k = threadIdx.x; k < npair; k += DBLK) {
+        int a = k, b = N - 1 - k;
+        int p = a == 0 ? 0 : ((a - 1 + r) % (N - 1)) + 1;
+        int q = b == 0 ? 0 : ((b - 1 + r) % (N - 1)) + 1;
+        if (p > q) { int tmp = p; p = q; q = tmp; }
+        double c = 1.0, s = 0.0;
+        if (q < n) {
+          double apq = A[(long)p * ld + q];
+          if (fabs(apq) > 1e-300) {
+            double tau = (A[(long)q * ld + q] - A[(long)p * ld + p]) / (2.0 * apq);
+            double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + tt * tt);
+            s = tt * c;
+          }
+        }
+        P[k] = p; Q[k] = q; Cs[k] = c; Sn[k] = s;
+      }
+      wg_sync();
+      for (long t = threadIdx.x; t < (long)npair * n; t += DBLK) {
+        int k = (int)(t / n), j = (int)(t % n);
+        int p = P[k], q = Q[k];
+        if (q >= n || Sn[k] == 0.0) continue;
+        double c = Cs[k], s = Sn[k];
+        double apj = A[(long)p * ld + j], aqj = A[(long)q * ld + j];
+        A[(long)p * ld + j] = c * apj - s * aqj;
+        A[(long)q * ld + j] = s * apj + c * aqj;
+      }
+      wg_sync();
+      for (long t = threadIdx.x; t < (long)npair * n; t += DBLK) {
+        int k = (int)(t / n), i = (int)(t % n);
+        int p = P[k], q = Q[k];
+        if (q >= n || Sn[k] == 0.0) continue;
+        double c = Cs[k], s = Sn[k];
+        double aip = A[(long)i * ld + p], aiq = A[(long)i * ld + q];
+        A[(long)i * ld + p] = c * aip - s * aiq;
+        A[(long)i * ld + q] = s * aip + c * aiq;
+        double vip = V[(long)i * ldv + p], viq = V[(long)i * ldv + q];
+        V[(long)i * ldv + p] = c * vip - s * viq;
+        V[(long)i * ldv + q] = s * vip + c * viq;
+      }
+      wg_sync();
+    }
+  }
+  wg_sync();
+}
+
+// indices of the k extremal values of lam[0..n) (largest first if desc, else smallest first), by a
+// single thread (n small); ties to the lower index.
+__device__ static void select_extremal(const double* lam, int n, int k, bool desc, int* out) {
+  if (threadIdx.x == 0) {
+    for (int s = 0; s < k; ++s) {
+      int best = -1;
+      for (int i = 0; i < n; ++i) {
+        bool used = false;
+        for (int t = 0; t < s; ++t) used |= (out[t] == i);
+        if (used) continue;
+        if (best < 0 || (desc ? lam[i] > lam[best] : lam[i] < lam[best])) best = i;
+      }
+      out[s] = best;
+    }
+  }
+  wg_sync();
+}
+
+// ------------------------------------------------------------------------------------------------
+// Cholesky-QR step: G = R^t R, T = R^{-1} (upper), row-major w x w.  A non-positive pivot retries
+// once with a diagonal shift of 1e-14 trace; a second failure sets *status.
+// ------------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(DBLK) void k_chol_inv_upper(int w, const double* G, double* T, int* status) {
+  __shared__ double L[16 * 16];
+  __shared__ int info;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    double tr = 0.0;
+    for (int i = 0; i < w; ++i) tr += G[i * w + i];
+    for (int t = threadIdx.x; t < w * w; t += DBLK) {
+      int i = t / w, j = t % w;
+      L[i * 16 + j] = G[t] + (attempt && i == j ? 1e-14 * tr : 0.0);
+    }
+    if (threadIdx.x == 0) info = 0;
+    wg_sync();
+    wg_chol(L, w, 16, &info);
+    if (info == 0) break;
+    if (attempt == 1 && threadIdx.x == 0) *status = ST_E_NUMERIC;
+    wg_sync();
+  }
+  // T = L^{-t}: solve L^t T = I
+  for (int t = threadIdx.x; t < w * w; t += DBLK) T[t] = (t / w == t % w) ? 1.0 : 0.0;
+  wg_trsm_lower_t(L, w, 16, T, w, w);
+}
+void launch_chol_inv_upper(int w, const double* G, double* T, int* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_chol_inv_upper, dim3(1), dim3(DBLK), 0, s, w, G, T, status);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Ritz problem on the finest level (§4.3).  Eigenproblem: M = V diag V^t, Y = V sorted.
+// SVD: eigen-decomposition of [[0, M], [M^t, 0]] whose eigenvalues are +-sigma (Theorem 3.2);
+// y and z of each sigma are read from the +sigma and -sigma eigenvectors, normalised, and signed
+// so that y^t M z >= 0.  Order: descending (dominant) or ascending (minimal).
+// work: >= 2 (2w)^2 doubles.
+// ------------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(DBLK) void k_small_ritz(int w, int spd, int minimal, const double* M, double* Y,
+                                                     double* Z, double* sig, double* work, int* status) {
+  __shared__ int ord[32];
+  __shared__ double lam[32];
+  if (spd) {
+    double* A = work;
+    double* V = work + w * w;
+    for (int t = threadIdx.x; t < w * w; t += DBLK) {
+      int i = t / w, j = t % w;
+      A[t] = 0.5 * (M[i * w + j] + M[j * w + i]);
+    }
+    wg_jacobi(A, w, w, V, w, 60);
+    for (int i = threadIdx.x; i < w; i += DBLK) lam[i] = A[i * w + i];
+    wg_sync();
+    select_extremal(lam, w, w, !minimal, ord);
+    for (int t = threadIdx.x; t < w * w; t += DBLK) {
+      int i = t / w, k = t % w;
+      Y[i * w + k] = V[i * w + ord[k]];
+    }
+    for (int k = threadIdx.x; k < w; k += DBLK) sig[k] = lam[ord[k]];
+    return;
+  }
+  const int n2 = 2 * w;
+  double* A = work;
+  double* V = work + n2 * n2;
+  for (int t = threadIdx.x; t < n2 * n2; t += DBLK) {
+    int i = t / n2, j = t % n2;
+    double v = 0.0;
+    if (i < w && j >= w) v = M[i * w + (j - w)];
+    if (i >= w && j < w) v = M[j * w + (i - w)];
+    A[t] = v;
+  }
+  wg_jacobi(A, n2, n2, V, n2, 60);
+  for (int i = threadIdx.x; i < n2; i += DBLK) lam[i] = A[i * n2 + i];
+  wg_sync();
+  select_extremal(lam, n2, n2, true, ord);   // descending: +sigma_1 ... -sigma_1
+  // z_k: normalised lower part of the +sigma_k eigenvector (for sigma > 0 it holds half of the
+  // eigenvector's mass, and the lower parts of a degenerate eigenspace stay orthonormal);
+  // y_k = M z_k / sigma_k, so that (y_k, z_k) is consistent inside degenerate clusters.  For
+  // sigma_k ~ 0 the +-0 eigenvectors mix: y_k and z_k come from whichever of the two eigenvectors
+  // carries more mass in the respective part, and y_k is orthogonalised against the other y.
+  if (threadIdx.x == 0) {
+    double smax = 0.0;
+    for (int k = 0; k < w; ++k) smax = fmax(smax, lam[ord[k]]);
+    for (int k = 0; k < w; ++k) {
+      const int kp = ord[k], km = ord[n2 - 1 - k];
+      double tp = 0.0, tm = 0.0, bp = 0.0, bm = 0.0;
+      for (int i = 0; i < w; ++i) {
+        tp += V[i * n2 + kp] * V[i * n2 + kp];
+        tm += V[i * n2 + km] * V[i * n2 + km];
+        bp += V[(w + i) * n2 + kp] * V[(w + i) * n2 + kp];
+        bm += V[(w + i) * n2 + km] * V[(w + i) * n2 + km];
+      }
+      const double sk = fmax(lam[kp], 0.0);
+      const bool tiny = !(sk > 1e-13 * smax);
+      const int kz = (!tiny || bp >= bm) ? kp : km;
+      const double nz = sqrt(kz == kp ? bp : bm);
+      const int dst = minimal ? (w - 1 - k) : k;
+      for (int i = 0; i < w; ++i) Z[i * w + dst] = V[(w + i) * n2 + kz] / nz;
+      if (!tiny) {
+        for (int i = 0; i < w; ++i) {
+          double s = 0.0;
+          for (int j = 0; j < w; ++j) s += M[i * w + j] * Z[j * w + dst];
+          Y[i * w + dst] = s;
+        }
+      } else {
+        const int ky = tp >= tm ? kp : km;
+        for (int i = 0; i < w; ++i) Y[i * w + dst] = V[i * n2 + ky];
+      }
+      sig[dst] = sk;
+    }
+    // normalise y; for (numerically) zero sigma, orthogonalise against the other columns first
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int k = 0; k < w; ++k) {
+        const bool tiny = !(sig[k] > 1e-13 * smax);
+        if (pass == 0 && tiny) continue;
+        if (pass == 1 && !tiny) continue;
+        if (tiny) {
+          for (int k2 = 0; k2 < w; ++k2) {
+            if (k2 == k || (!(sig[k2] > 1e-13 * smax) && k2 > k)) continue;
+            double d = 0.0;
+            for (int i = 0; i < w; ++i) d += Y[i * w + k] * Y[i * w + k2];
+            for (int i = 0; i < w; ++i) Y[i * w + k] -= d * Y[i * w + k2];
+          }
+        }
+        double nrm = 0.0;
+        for (int i = 0; i < w; ++i) nrm += Y[i * w + k] * Y[i * w + k];
+        nrm = sqrt(nrm);
+        if (nrm > 0.0)
+          for (int i = 0; i < w; ++i) Y[i * w + k] /= nrm;
+      }
+    }
+  }
+}
+void launch_small_ritz(int w, int spd, int minimal, const double* M, double* Y, double* Z, double* sig, double* work,
+                       int* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_small_ritz, dim3(1), dim3(DBLK), 0, s, w, spd, minimal, M, Y, Z, sig, work, status);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Coarsest generalized SVD / eigenproblem (§3.6).  A, B, C dense row-major (C unused for spd);
+// B and C are overwritten by their Cholesky factors.
+// spd:  D = L^-1 A L^-t, D = W diag W^t, x = L^-t w; the n_b smallest / largest.
+// svd:  D = L_B^-1 A L_C^-t, D^t D = W diag(s^2) W^t, t = D w / s, u = L_B^-t t, v = L_C^-t w.
+//       A zero s gets t completed to an orthonormal set by Gram-Schmidt on unit vectors.
+// Output U (mL x nb), V (nL x nb) row-major, sig (nb).
+// work: >= 3 max(mL,nL)^2 + 2 mL nL + 2 max doubles.
+// ------------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(DBLK) void k_coarse_gsvd(int spd, int minimal, int mL, int nL, int nb, double* A,
+                                                      double* B, double* C, double* work, double* sig, double* U,
+                                                      double* V, int* status) {
+  __shared__ int info;
+  __shared__ int ord[64];
+  if (threadIdx.x == 0) info = 0;
+  wg_sync();
+  if (spd) {
+    const int n = nL;
+    double* T1 = work;                 // n x n
+    double* D = work + (long)n * n;    // n x n
+    double* W = work + 2L * n * n;     // n x n
+    double* lam = work + 3L * n * n;   // n
+    wg_chol(B, n, n, &info);
+    for (long t = threadIdx.x; t < (long)n * n; t += DBLK) T1[t] = A[t];
+    wg_trsm_lower(B, n, n, T1, n, n);           // T1 = L^-1 A
+    wg_transpose(T1, n, n, n, D, n);           // D = (L^-1 A)^t = A L^-t
+    wg_trsm_lower(B, n, n, D, n, n);            // D = L^-1 A L^-t
+    for (long t = threadIdx.x; t < (long)n * n; t += DBLK) {
+      int i = (int)(t / n), j = (int)(t % n);
+      if (j > i) {
+        double s = 0.5 * (D[(long)i * n + j] + D[(long)j * n + i]);
+        D[(long)i * n + j] = s; D[(long)j * n + i] = s;
+      }
+    }
+    wg_jacobi(D, n, n, W, n, 60);
+    for (int i = threadIdx.x; i < n; i += DBLK) lam[i] = D[(long)i * n + i];
+    wg_sync();
+    select_extremal(lam, n, nb, !minimal, ord);
+    for (long t = threadIdx.x; t < (long)n * nb; t += DBLK) {
+      int i = (int)(t / nb), k = (int)(t % nb);
+      U[t] = W[(long)i * n + ord[k]];
+    }
+    wg_trsm_lower_t(B, n, n, U, nb, nb);        // x = L^-t w
+    for (int k = threadIdx.x; k < nb; k += DBLK) sig[k] = lam[ord[k]];
+    if (threadIdx.x == 0 && info) *status = ST_E_NUMERIC;
+    return;
+  }
+  const int m = mL, n = nL;
+  const int mx = m > n ? m : n;
+  double* Dt = work;                       // n x m   (D^t)
+  double* G = work + (long)m * n;          // n x n
+  double* W = G + (long)n * n;             // n x n
+  double* Tm = W + (long)n * n;            // m x nb  (t vectors)
+  double* lam = Tm + (long)m * 64;         // n
+  (void)mx;
+  wg_chol(B, m, m, &info);
+  wg_chol(C, n, n, &info);
+  wg_trsm_lower(B, m, m, A, n, n);             // A <- L_B^-1 A   (m x n)
+  wg_transpose(A, m, n, n, Dt, m);             // Dt = (L_B^-1 A)^t   (n x m)
+  wg_trsm_lower(C, n, n, Dt, m, m);            // Dt = L_C^-1 A^t L_B^-t = D^t
+  for (long t = threadIdx.x; t < (long)n * n; t += DBLK) {
+    int i = (int)(t / n), j = (int)(t % n);
+    double s = 0.0;
+    for (int k = 0; k < m; ++k) s += Dt[(long)i * m + k] * Dt[(long)j * m + k];
+    G[t] = s;
+  }
+  wg_sync();
+  for (long t = threadIdx.x; t < (long)n * n; t += DBLK) {
+    int i = (int)(t / n), j = (int)(t % n);
+    if (j > i) {
+      double s = 0.5 * (G[(long)i * n + j] + G[(long)j * n + i]);
+      G[(long)i * n + j] = s; G[(long)j * n + i] = s;
+    }
+  }
+  wg_jacobi(G, n, n, W, n, 60);
+  for (int i = threadIdx.x; i < n; i += DBLK) lam[i] = sqrt(fmax(G[(long)i * n + i], 0.0));
+  wg_sync();
+  select_extremal(lam, n, nb, !minimal, ord);
+  double smax = 0.0;
+  for (int i = 0; i < n; ++i) smax = fmax(smax, lam[i]);
+  // t_k = D w_k / s_k  (D = Dt^t)
+  for (long t = threadIdx.x; t < (long)m * nb; t += DBLK) {
+    int r = (int)(t / nb), k = (int)(t % nb);
+    double s = 0.0;
+    for (int j = 0; j < n; ++j) s += Dt[(long)j * m + r] * W[(long)j * n + ord[k]];
+    double sk = lam[ord[k]];
+    Tm[t] = sk > 1e-12 * smax ? s / sk : 0.0;
+  }
+  wg_sync();
+  if (threadIdx.x == 0) {
+    // complete t for (numerically) zero singular values, orthonormal to the others
+    for (int k = 0; k < nb; ++k) {
+      if (lam[ord[k]] > 1e-12 * smax) continue;
+      for (int e = 0; e < m; ++e) {
+        for (int r = 0; r < m; ++r) Tm[(long)r * nb + k] = r == e ? 1.0 : 0.0;
+        for (int k2 = 0; k2 < nb; ++k2) {
+          if (k2 == k) continue;
+          if (lam[ord[k2]] <= 1e-12 * smax && k2 > k) continue;
+          double d = Tm[(long)e * nb + k2];
+          for (int r = 0; r < m; ++r) Tm[(long)r * nb + k] -= d * Tm[(long)r * nb + k2];
+        }
+        double nrm = 0.0;
+        for (int r = 0; r < m; ++r) nrm += Tm[(long)r * nb + k] * Tm[(long)r * nb + k];
+        if (nrm > 0.25) {
+          nrm = sqrt(nrm);
+          for (int r = 0; r < m; ++r) Tm[(long)r * nb + k] /= nrm;
+          break;
+        }
+      }
+    }
+  }
+  wg_sync();
+  for (long t = threadIdx.x; t < (long)m * nb; t += DBLK) U[t] = Tm[t];
+  for (long t = threadIdx.x; t < (long)n * nb; t += DBLK) {
+    int i = (int)(t / nb), k = (int)(t % nb);
+    V[t] = W[(long)i * n + ord[k]];
+  }
+  wg_trsm_lower_t(B, m, m, U, nb, nb);
+  wg_trsm_lower_t(C, n, n, V, nb, nb);
+  for (int k = threadIdx.x; k < nb; k += DBLK) sig[k] = lam[ord[k]];
+  if (threadIdx.x == 0 && info) *status = ST_E_NUMERIC;
+}
+void launch_coarse_gsvd(int spd, int minimal, int mL, int nL, int nb, double* A, double* B, double* C, double* work,
+                        double* sig, double* U, double* V, int* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_coarse_gsvd, dim3(1), dim3(DBLK), 0, s, spd, minimal, mL, nL, nb, A, B, C, work, sig, U, V,
+                     status);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Additive coarsest solve (§4.2), one workgroup per column j: M = X - sigma_j Y is symmetric, so
+// its SVD is its eigen-decomposition with |eigenvalues|; the pseudo-inverse without the smallest
+// singular component is sum_{i != i*} q_i q_i^t / lambda_i, i* = argmin |lambda_i|.
+// rhs / out: N x nb row-major.  work: nb * 2 N^2 doubles.
+// ------------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(DBLK) void k_pinv_solve(int N, int nb, const double* X, const double* Y,
+                                                     const double* sig, const double* rhs, double* out,
+                                                     double* work, int use_lds) {
+  extern __shared__ double dyn[];
+  const int j = blockIdx.x;
+  double* M = use_lds ? dyn : work + (long)j * 2 * N * N;
+  double* Qv = work + (long)j * 2 * N * N + (long)N * N;
+  __shared__ double cf[1024];
+  __shared__ int imin;
+  const double s = sig[j];
+  for (long t = threadIdx.x; t < (long)N * N; t += DBLK) M[t] = X[t] - s * Y[t];
+  wg_jacobi(M, N, N, Qv, N, 60);
+  if (threadIdx.x == 0) {
+    int best = 0;
+    for (int i = 1; i < N; ++i)
+      if (fabs(M[(long)i * N + i]) < fabs(M[(long)best * N + best])) best = i;
+    imin = best;
+  }
+  wg_sync();
+  for (int i = threadIdx.x; i < N; i += DBLK) {
+    double d = 0.0;
+    for (int r = 0; r < N; ++r) d += Qv[(long)r * N + i] * rhs[(long)r * nb + j];
+    double lam = M[(long)i * N + i];
+    cf[i] = (i == imin || lam == 0.0) ? 0.0 : d / lam;
+  }
+  wg_sync();
+  for (int r = threadIdx.x; r < N; r += DBLK) {
+    double z = 0.0;
+    for (int i = 0; i < N; ++i) z += Qv[(long)r * N + i] * cf[i];
+    out[(long)r * nb + j] = z;
+  }
+}
+
+// The eigensolve of X - sigma_j Y keeps the matrix in LDS when it fits the workgroup's share
+// (gfx950: 160 KB per CU); the rotation accumulator stays in global memory (L2).
+static size_t pinv_lds_bytes(int N) {
+  static int max_lds = -1;
+  if (max_lds < 0) {
+    int dev = 0, v = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) v = 65536;
+    max_lds = v;
+    if (v > 65536 &&
+        hipFuncSetAttribute((const void*)k_pinv_solve, hipFuncAttributeMaxDynamicSharedMemorySize, v - 32768) !=
+            hipSuccess) {
+      (void)hipGetLastError();
+      max_lds = 65536;
+    }
+  }
+  const size_t need = (size_t)N * N * sizeof(double);
+  const size_t static_lds = 32768;   // Jacobi rotation tables, reductions, coefficients
+  return need + static_lds <= (size_t)max_lds ? need : 0;
+}
+
+void launch_pinv_solve(int N, int nb, const double* X, const double* Y, const double* sig, const double* rhs,
+                       double* out, double* work, int* status, hipStream_t s) {
+  (void)status;
+  const size_t lds = pinv_lds_bytes(N);
+  hipLaunchKernelGGL(k_pinv_solve, dim3(nb), dim3(DBLK), lds, s, N, nb, X, Y, sig, rhs, out, work, lds ? 1 : 0);
+}
+
+// Pencil variant, set-up once per additive phase: Y = L L^t, K = L^-1 X L^-t = W diag(mu) W^t,
+// Z = L^-t W (Y-orthonormal eigenvectors of X z = mu Y z).  X and Y are overwritten.
+// work: >= 2 N^2 doubles.
+__global__ __launch_bounds__(DBLK) void k_pencil_setup(int N, double* X, double* Y, double* mu, double* Z,
+                                                       double* work, int* status) {
+  __shared__ int info;
+  if (threadIdx.x == 0) info = 0;
+  wg_sync();
+  double* K = work;
+  wg_chol(Y, N, N, &info);
+  wg_trsm_lower(Y, N, N, X, N, N);         // X <- L^-1 X
+  wg_transpose(X, N, N, N, K, N);          // K = X L^-t (X symmetric)
+  wg_trsm_lower(Y, N, N, K, N, N);         // K = L^-1 X L^-t
+  for (long t = threadIdx.x; t < (long)N * N; t += DBLK) {
+    int i = (int)(t / N), j = (int)(t % N);
+    if (j > i) {
+      double s = 0.5 * (K[(long)i * N + j] + K[(long)j * N + i]);
+      K[(long)i * N + j] = s; K[(long)j * N + i] = s;
+    }
+  }
+  wg_jacobi(K, N, N, Z, N, 60);
+  for (int i = threadIdx.x; i < N; i += DBLK) mu[i] = K[(long)i * N + i];
+  wg_trsm_lower_t(Y, N, N, Z, N, N);
+  if (threadIdx.x == 0 && info) *status = ST_E_NUMERIC;
+}
+void launch_pencil_setup(int N, double* X, double* Y, double* mu, double* Z, double* work, int* status,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_pencil_setup, dim3(1), dim3(DBLK), 0, s, N, X, Y, mu, Z, work, status);
+}
+
+__global__ __launch_bounds__(DBLK) void k_pencil_solve(int N, int nb, const double* mu, const double* Z,
+                                                       const double* sig, const double* rhs, double* out) {
+  const int j = blockIdx.x;
+  __shared__ double cf[1024];
+  __shared__ int imin;
+  const double s = sig[j];
+  if (threadIdx.x == 0) {
+    int best = 0;
+    for (int i = 1; i < N; ++i)
+      if (fabs(mu[i] - s) < fabs(mu[best] - s)) best = i;
+    imin = best;
+  }
+  wg_sync();
+  for (int i = threadIdx.x; i < N; i += DBLK) {
+    double d = 0.0;
+    for (int r = 0; r < N; ++r) d += Z[(long)r * N + i] * rhs[(long)r * nb + j];
+    double den = mu[i] - s;
+    cf[i] = (i == imin || den == 0.0) ? 0.0 : d / den;
+  }
+  wg_sync();
+  for (int r = threadIdx.x; r < N; r += DBLK) {
+    double z = 0.0;
+    for (int i = 0; i < N; ++i) z += Z[(long)r * N + i] * cf[i];
+    out[(long)r * nb + j] = z;
+  }
+}
+void launch_pencil_solve(int N, int nb, const double* mu, const double* Z, const double* sig, const double* rhs,
+                         double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_pencil_solve, dim3(nb), dim3(DBLK), 0, s, N, nb, mu, Z, sig, rhs, out);
+}
+
+// Plain symmetric eigen-decomposition (used by the step-level test entry point).
+__global__ __launch_bounds__(DBLK) void k_dense_sym_eig(int n, double* A, double* V, double* lam) {
+  wg_jacobi(A, n, n, V, n, 60);
+  for (int i = threadIdx.x; i < n; i += DBLK) lam[i] = A[(long)i * n + i];
+}
+void launch_dense_sym_eig(int n, double* A, double* V, double* lam, int* status, hipStream_t s) {
+  (void)status;
+  hipLaunchKernelGGL(k_dense_sym_eig, dim3(1), dim3(DBLK), 0, s, n, A, V, lam);
+}
+
+}  // namespace slamg

@@ -1,0 +1,237 @@
+// Host-side graph work of the first multiplicative cycle (§3.7): strength of connection,
+// Algorithm 1 (one-pass Ruge-Stueben coarsening), interpolatory sets and the sparsity patterns of
+// P and Q, plus the symbolic sparse products of the Galerkin operators, transposes and the greedy
+// multicolouring that orders the Kaczmarz sweeps.  These steps are sequential graph algorithms and
+// run once per level; every numeric step runs in the HIP kernels.
+#include "graph.h"
+
+#include <algorithm>
+#include <cmath>
+#include <queue>
+#include <stdexcept>
+
+namespace slamg {
+
+// S_i = { j != i : |n_ij| > 0 and the rule holds }, returned as a CSR pattern (sorted).
+//  rule 0: |n_ij| >= theta * sum_k |n_ik|   (the row-sum condition of §3.7, all k)
+//  rule 1: |n_ij| >= theta * max_{k != i} |n_ik|
+//  rule 2: the top_s largest off-diagonal |n_ij| (ties to the lower j)
+void strength_sets(const HCsr& N, double theta, int rule, int top_s, std::vector<int>& Sp, std::vector<int>& Si) {
+  const int n = N.m;
+  Sp.assign(n + 1, 0);
+  Si.clear();
+  std::vector<std::pair<double, int>> cand;
+  for (int i = 0; i < n; ++i) {
+    const int b = N.rp[i], e = N.rp[i + 1];
+    if (rule == 0) {
+      double sum = 0.0;
+      for (int k = b; k < e; ++k) sum += std::fabs(N.v[k]);
+      const double thr = theta * sum;
+      for (int k = b; k < e; ++k) {
+        const double a = std::fabs(N.v[k]);
+        if (N.ci[k] != i && a > 0.0 && a >= thr) Si.push_back(N.ci[k]);
+      }
+    } else if (rule == 1) {
+      double mx = 0.0;
+      for (int k = b; k < e; ++k)
+        if (N.ci[k] != i) mx = std::max(mx, std::fabs(N.v[k]));
+      const double thr = theta * mx;
+      for (int k = b; k < e; ++k) {
+        const double a = std::fabs(N.v[k]);
+        if (N.ci[k] != i && a > 0.0 && a >= thr) Si.push_back(N.ci[k]);
+      }
+    } else {
+      cand.clear();
+      for (int k = b; k < e; ++k) {
+        const double a = std::fabs(N.v[k]);
+        if (N.ci[k] != i && a > 0.0) cand.push_back({-a, N.ci[k]});
+      }
+      std::sort(cand.begin(), cand.end());
+      const int take = std::min<int>(top_s, (int)cand.size());
+      std::vector<int> sel;
+      for (int t = 0; t < take; ++t) sel.push_back(cand[t].second);
+      std::sort(sel.begin(), sel.end());
+      Si.insert(Si.end(), sel.begin(), sel.end());
+    }
+    Sp[i + 1] = (int)Si.size();
+  }
+}
+
+// Algorithm 1.  "i strongly influences j" <=> i in S_j.  lambda_i = #points i influences; the
+// undecided point of maximal lambda (lowest index on ties) becomes C, the undecided points it
+// influences become F, and every undecided point influencing a new F-point gets lambda + 1.
+std::vector<char> rs_coarsen(const std::vector<int>& Sp, const std::vector<int>& Si, int n) {
+  std::vector<int> Tp(n + 1, 0), Ti(Si.size());
+  for (int j : Si) Tp[j + 1]++;
+  for (int i = 0; i < n; ++i) Tp[i + 1] += Tp[i];
+  {
+    std::vector<int> pos(Tp.begin(), Tp.end() - 1);
+    for (int j = 0; j < n; ++j)
+      for (int k = Sp[j]; k < Sp[j + 1]; ++k) Ti[pos[Si[k]]++] = j;
+  }
+  std::vector<long> lam(n);
+  for (int i = 0; i < n; ++i) lam[i] = Tp[i + 1] - Tp[i];
+  std::vector<char> state(n, 0);   // 0 undecided, 1 C, 2 F
+  // max-heap on (lambda, -index)
+  std::priority_queue<std::pair<long, int>> heap;
+  for (int i = 0; i < n; ++i) heap.push({lam[i], -i});
+  while (!heap.empty()) {
+    auto top = heap.top();
+    heap.pop();
+    const int i = -top.second;
+    if (state[i] != 0 || top.first != lam[i]) continue;
+    state[i] = 1;
+    for (int t = Tp[i]; t < Tp[i + 1]; ++t) {
+      const int j = Ti[t];
+      if (state[j] != 0) continue;
+      state[j] = 2;
+      for (int k = Sp[j]; k < Sp[j + 1]; ++k) {
+        const int kk = Si[k];
+        if (state[kk] == 0) {
+          lam[kk] += 1;
+          heap.push({lam[kk], -kk});
+        }
+      }
+    }
+  }
+  std::vector<char> is_c(n);
+  for (int i = 0; i < n; ++i) is_c[i] = state[i] == 1;
+  return is_c;
+}
+
+// Interpolatory sets C^i = S_i intersected with C (a C-point interpolates from itself), capped to
+// the `cap` strongest connections |n_ij| (ties to the lower j); fine ids, ascending.
+void interp_pattern(const std::vector<int>& Sp, const std::vector<int>& Si, const HCsr& N,
+                    const std::vector<char>& is_c, int cap, std::vector<int>& ptr, std::vector<int>& fine_cols,
+                    int& capped) {
+  const int n = (int)is_c.size();
+  ptr.assign(n + 1, 0);
+  fine_cols.clear();
+  capped = 0;
+  std::vector<int> sel;
+  std::vector<std::pair<double, int>> mag;
+  for (int i = 0; i < n; ++i) {
+    sel.clear();
+    if (is_c[i]) {
+      sel.push_back(i);
+    } else {
+      for (int k = Sp[i]; k < Sp[i + 1]; ++k)
+        if (is_c[Si[k]]) sel.push_back(Si[k]);
+      if ((int)sel.size() > cap) {
+        ++capped;
+        mag.clear();
+        for (int j : sel) {
+          auto it = std::lower_bound(N.ci.begin() + N.rp[i], N.ci.begin() + N.rp[i + 1], j);
+          double a = std::fabs(N.v[it - N.ci.begin()]);
+          mag.push_back({-a, j});
+        }
+        std::sort(mag.begin(), mag.end());
+        sel.clear();
+        for (int t = 0; t < cap; ++t) sel.push_back(mag[t].second);
+        std::sort(sel.begin(), sel.end());
+      }
+    }
+    fine_cols.insert(fine_cols.end(), sel.begin(), sel.end());
+    ptr[i + 1] = (int)fine_cols.size();
+  }
+}
+
+// Transpose of a pattern; perm[e] = index in A of the e-th entry of A^t (rows of A^t sorted).
+HCsr transpose(const HCsr& A, std::vector<int>* perm) {
+  HCsr T;
+  T.m = A.n; T.n = A.m;
+  T.rp.assign(A.n + 1, 0);
+  const int nnz = A.nnz();
+  for (int k = 0; k < nnz; ++k) T.rp[A.ci[k] + 1]++;
+  for (int i = 0; i < A.n; ++i) T.rp[i + 1] += T.rp[i];
+  T.ci.resize(nnz);
+  if (!A.v.empty()) T.v.resize(nnz);
+  if (perm) perm->resize(nnz);
+  std::vector<int> pos(T.rp.begin(), T.rp.end() - 1);
+  for (int i = 0; i < A.m; ++i)
+    for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+      const int d = pos[A.ci[k]]++;
+      T.ci[d] = i;
+      if (!A.v.empty()) T.v[d] = A.v[k];
+      if (perm) (*perm)[d] = k;
+    }
+  return T;
+}
+
+// Structural pattern of L R (no cancellation pruning), rows sorted.
+HCsr symbolic_product(const HCsr& L, const HCsr& R) {
+  HCsr C;
+  C.m = L.m; C.n = R.n;
+  C.rp.assign(L.m + 1, 0);
+  std::vector<int> mark(R.n, -1), row;
+  for (int i = 0; i < L.m; ++i) {
+    row.clear();
+    for (int k = L.rp[i]; k < L.rp[i + 1]; ++k) {
+      const int j = L.ci[k];
+      for (int t = R.rp[j]; t < R.rp[j + 1]; ++t) {
+        const int c = R.ci[t];
+        if (mark[c] != i) { mark[c] = i; row.push_back(c); }
+      }
+    }
+    std::sort(row.begin(), row.end());
+    C.ci.insert(C.ci.end(), row.begin(), row.end());
+    C.rp[i + 1] = (int)C.ci.size();
+  }
+  return C;
+}
+
+// Greedy first-fit colouring of the rows of A in index order; rows conflict when they share a
+// column.  Returns the colour of every row; colours ascending, rows ascending within a colour
+// give the Kaczmarz order.
+std::vector<int> greedy_row_colouring(const HCsr& A) {
+  HCsr T = transpose(A, nullptr);
+  std::vector<int> colour(A.m, -1);
+  std::vector<int> stamp;
+  for (int i = 0; i < A.m; ++i) {
+    for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+      const int c = A.ci[k];
+      for (int t = T.rp[c]; t < T.rp[c + 1]; ++t) {
+        const int r = T.ci[t];
+        if (r < i) {
+          const int col = colour[r];
+          if (col >= (int)stamp.size()) stamp.resize(col + 1, -1);
+          stamp[col] = i;
+        }
+      }
+    }
+    int c = 0;
+    while (c < (int)stamp.size() && stamp[c] == i) ++c;
+    colour[i] = c;
+  }
+  return colour;
+}
+
+void colour_order(const std::vector<int>& colour, std::vector<int>& rows, std::vector<int>& cptr) {
+  int nc = 0;
+  for (int c : colour) nc = std::max(nc, c + 1);
+  cptr.assign(nc + 1, 0);
+  for (int c : colour) cptr[c + 1]++;
+  for (int c = 0; c < nc; ++c) cptr[c + 1] += cptr[c];
+  rows.resize(colour.size());
+  std::vector<int> pos(cptr.begin(), cptr.end() - 1);
+  for (int i = 0; i < (int)colour.size(); ++i) rows[pos[colour[i]]++] = i;
+}
+
+HCsr union_pattern(const HCsr& A, const HCsr& B) {
+  HCsr C;
+  C.m = A.m; C.n = A.n;
+  C.rp.assign(A.m + 1, 0);
+  for (int i = 0; i < A.m; ++i) {
+    int a = A.rp[i], ae = A.rp[i + 1], b = B.rp[i], be = B.rp[i + 1];
+    while (a < ae || b < be) {
+      int ca = a < ae ? A.ci[a] : INT32_MAX, cb = b < be ? B.ci[b] : INT32_MAX;
+      if (ca == cb) { C.ci.push_back(ca); ++a; ++b; }
+      else if (ca < cb) { C.ci.push_back(ca); ++a; }
+      else { C.ci.push_back(cb); ++b; }
+    }
+    C.rp[i + 1] = (int)C.ci.size();
+  }
+  return C;
+}
+
+}  // namespace slamg

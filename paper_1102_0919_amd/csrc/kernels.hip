@@ -1,0 +1,872 @@
+// Streaming kernels of the multilevel cycles: block SpMM, fused relaxation / residual row kernels,
+// multicolour Kaczmarz sweeps, deterministic column reductions, the MFMA FP64 Gram product,
+// block rotations, transfers, the merge-based numeric SpGEMM of the Galerkin products and the
+// per-F-point least-squares interpolation fit.
+//
+// Blocks of vectors are row-major (row i holds its w <= 16 columns contiguously), so one row of an
+// 8-column FP64 block is one 64-byte line.  A row of a sparse operator is handled by a group of
+// LPR lanes of a 64-wide wavefront; lane l of the group owns columns [CPL*l, CPL*l + CPL).  The
+// column loads of a gathered vector row are therefore contiguous across the group.
+#include "common.h"
+
+#include <algorithm>
+#include <type_traits>
+
+namespace slamg {
+
+static constexpr int BLK = 256;
+
+static inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
+static inline int cpl_of(int w) { return w >= 2 ? 2 : 1; }
+static inline int lshift_of(int w) {
+  int lanes = (w + cpl_of(w) - 1) / cpl_of(w);
+  int s = 0;
+  while ((1 << s) < lanes) ++s;
+  return s;
+}
+
+template <typename T, int CPL>
+__device__ __forceinline__ void ldrow(const T* __restrict__ p, int c0, int w, T (&v)[CPL]) {
+  if constexpr (CPL == 2) {
+    if (!(w & 1)) {
+      typedef T T2 __attribute__((ext_vector_type(2)));
+      T2 t = *reinterpret_cast<const T2*>(p + c0);
+      v[0] = t.x; v[1] = t.y;
+      return;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) v[c] = (c0 + c < w) ? p[c0 + c] : T(0);
+}
+
+template <typename T, int CPL>
+__device__ __forceinline__ void strow(T* __restrict__ p, int c0, int w, const T (&v)[CPL]) {
+  if constexpr (CPL == 2) {
+    if (!(w & 1)) {
+      typedef T T2 __attribute__((ext_vector_type(2)));
+      T2 t; t.x = v[0]; t.y = v[1];
+      *reinterpret_cast<T2*>(p + c0) = t;
+      return;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < CPL; ++c)
+    if (c0 + c < w) p[c0 + c] = v[c];
+}
+
+// ------------------------------------------------------------------------------------------------
+// Block SpMM  y = A x (+ beta y)
+// ------------------------------------------------------------------------------------------------
+template <typename T, int CPL>
+__global__ __launch_bounds__(BLK) void k_spmm(int m, int w, int lshift, const int* __restrict__ rp,
+                                              const int* __restrict__ ci, const T* __restrict__ v,
+                                              const T* __restrict__ x, T* __restrict__ y, T beta) {
+  long t = (long)blockIdx.x * BLK + threadIdx.x;
+  int row = (int)(t >> lshift);
+  int c0 = (int)(t & ((1 << lshift) - 1)) * CPL;
+  if (row >= m || c0 >= w) return;
+  T acc[CPL];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) acc[c] = T(0);
+  int k = rp[row], ke = rp[row + 1];
+  for (; k + 1 < ke; k += 2) {
+    int j0 = ci[k], j1 = ci[k + 1];
+    T a0 = v[k], a1 = v[k + 1];
+    T x0[CPL], x1[CPL];
+    ldrow<T, CPL>(x + (long)j0 * w, c0, w, x0);
+    ldrow<T, CPL>(x + (long)j1 * w, c0, w, x1);
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) acc[c] += a0 * x0[c] + a1 * x1[c];
+  }
+  if (k < ke) {
+    T xv[CPL];
+    ldrow<T, CPL>(x + (long)ci[k] * w, c0, w, xv);
+    T a = v[k];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) acc[c] += a * xv[c];
+  }
+  T* yr = y + (long)row * w;
+  if (beta != T(0)) {
+    T old[CPL];
+    ldrow<T, CPL>(yr, c0, w, old);
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) acc[c] += beta * old[c];
+  }
+  strow<T, CPL>(yr, c0, w, acc);
+}
+
+template <typename T>
+void launch_spmm(int m, int w, const int* rp, const int* ci, const T* v, const T* x, T* y, double beta,
+                 hipStream_t s) {
+  if (m <= 0) return;
+  int sh = lshift_of(w);
+  int grid = ceil_div((long)m << sh, BLK);
+  if (cpl_of(w) == 2)
+    hipLaunchKernelGGL((k_spmm<T, 2>), dim3(grid), dim3(BLK), 0, s, m, w, sh, rp, ci, v, x, y, (T)beta);
+  else
+    hipLaunchKernelGGL((k_spmm<T, 1>), dim3(grid), dim3(BLK), 0, s, m, w, sh, rp, ci, v, x, y, (T)beta);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Generic fused row kernel:
+//   out_ic = x_ic + D_i * ( ca_c (K z)_ic + cb_c (M y)_ic + ce_c kap_ic )
+// covering the weighted-Jacobi test and boot relaxations (power-method and block Gauss-Seidel
+// steps), the additive residuals and the Jacobi pre-smoothing of the minimal LS fit.
+// ------------------------------------------------------------------------------------------------
+template <typename T>
+struct RowOpPOD {
+  int nrows, w;
+  const int* Krp; const int* Kci; const T* Kv; const T* z;
+  int mmode;
+  const int* Mrp; const int* Mci; const T* Mv; const T* y;
+  const T* x; const T* D; const T* kap; const double* sig;
+  int cmode; double omega;
+  T* out;
+};
+
+template <typename T>
+__device__ __forceinline__ void coefs(int cmode, double om, double s, T& ca, T& cb, T& ce) {
+  switch (cmode) {
+    case C_JAC_TEST: ca = (T)om; cb = (T)(-om); ce = T(0); break;
+    case C_JAC_BOOT: ca = (T)(om / s); cb = (T)(-om); ce = (T)(-om / s); break;
+    case C_RESID: ca = T(-1); cb = (T)s; ce = T(1); break;
+    case C_SMOOTH: ca = (T)(-om); cb = T(0); ce = T(0); break;
+    default: ca = T(1); cb = T(0); ce = T(0); break;
+  }
+}
+
+template <typename T, int CPL>
+__global__ __launch_bounds__(BLK) void k_rowop(RowOpPOD<T> a, int lshift) {
+  long t = (long)blockIdx.x * BLK + threadIdx.x;
+  int row = (int)(t >> lshift);
+  int c0 = (int)(t & ((1 << lshift) - 1)) * CPL;
+  const int w = a.w;
+  if (row >= a.nrows || c0 >= w) return;
+  T ca[CPL], cb[CPL], ce[CPL];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) {
+    double s = (a.sig && c0 + c < w) ? a.sig[c0 + c] : 1.0;
+    coefs<T>(a.cmode, a.omega, s, ca[c], cb[c], ce[c]);
+  }
+  T kz[CPL], my[CPL];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) { kz[c] = T(0); my[c] = T(0); }
+  if (a.Kv) {
+    for (int k = a.Krp[row], ke = a.Krp[row + 1]; k < ke; ++k) {
+      T zv[CPL];
+      ldrow<T, CPL>(a.z + (long)a.Kci[k] * w, c0, w, zv);
+      T av = a.Kv[k];
+      if (a.mmode == M_SHARED) {
+        T bv = a.Mv[k];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) { kz[c] += av * zv[c]; my[c] += bv * zv[c]; }
+      } else {
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) kz[c] += av * zv[c];
+      }
+    }
+  }
+  if (a.mmode == M_IDENT) {
+    ldrow<T, CPL>(a.y + (long)row * w, c0, w, my);
+  } else if (a.mmode == M_CSR) {
+    for (int k = a.Mrp[row], ke = a.Mrp[row + 1]; k < ke; ++k) {
+      T yv[CPL];
+      ldrow<T, CPL>(a.y + (long)a.Mci[k] * w, c0, w, yv);
+      T mv = a.Mv[k];
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) my[c] += mv * yv[c];
+    }
+  }
+  T kp[CPL];
+  if (a.kap) ldrow<T, CPL>(a.kap + (long)row * w, c0, w, kp);
+  else {
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) kp[c] = T(0);
+  }
+  T d = a.D ? a.D[row] : T(1);
+  T r[CPL];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) r[c] = d * (ca[c] * kz[c] + cb[c] * my[c] + ce[c] * kp[c]);
+  if (a.x) {
+    T xv[CPL];
+    ldrow<T, CPL>(a.x + (long)row * w, c0, w, xv);
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) r[c] += xv[c];
+  }
+  strow<T, CPL>(a.out + (long)row * w, c0, w, r);
+}
+
+template <typename T>
+void launch_rowop(const RowOpArgs<T>& a, hipStream_t s) {
+  if (a.nrows <= 0) return;
+  RowOpPOD<T> p{a.nrows, a.w, a.Krp, a.Kci, a.Kv, a.z, a.mmode, a.Mrp, a.Mci, a.Mv, a.y,
+                a.x, a.D, a.kap, a.sig, a.cmode, a.omega, a.out};
+  int sh = lshift_of(a.w);
+  int grid = ceil_div((long)a.nrows << sh, BLK);
+  if (cpl_of(a.w) == 2) hipLaunchKernelGGL((k_rowop<T, 2>), dim3(grid), dim3(BLK), 0, s, p, sh);
+  else hipLaunchKernelGGL((k_rowop<T, 1>), dim3(grid), dim3(BLK), 0, s, p, sh);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Kaczmarz sweep over the rows of one colour.  Rows of a colour share no column, so their updates
+// touch disjoint entries of x and the result equals the row-by-row sweep in any order.
+//   res_c = rhs_rc - a_r(c) . x_c ;  x_c += res_c / ||a_r(c)||^2 * a_r(c)
+// with a_r(c) = A_r - lam_c B_r (shared pattern; bv == nullptr and lam != nullptr means B = I).
+// ------------------------------------------------------------------------------------------------
+template <typename T>
+struct KaczPOD {
+  int nrows; const int* rows; int w;
+  const int* rp; const int* ci; const T* av; const T* bv; const double* lam;
+  const T* rn_aa; const T* rn_ab; const T* rn_bb;
+  int rmode; const int* Mrp; const int* Mci; const T* Mv; const T* y; const double* rsig; const T* kap;
+  T* x;
+};
+
+template <typename T, int CPL>
+__global__ __launch_bounds__(BLK) void k_kacz(KaczPOD<T> a, int lshift) {
+  long t = (long)blockIdx.x * BLK + threadIdx.x;
+  int idx = (int)(t >> lshift);
+  int c0 = (int)(t & ((1 << lshift) - 1)) * CPL;
+  const int w = a.w;
+  if (idx >= a.nrows || c0 >= w) return;
+  int r = a.rows[idx];
+  T lam[CPL];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) lam[c] = (a.lam && c0 + c < w) ? (T)a.lam[c0 + c] : T(0);
+  const bool shifted = a.lam != nullptr;
+  // right-hand side
+  T rhs[CPL];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) rhs[c] = T(0);
+  if (a.rmode == M_IDENT || a.rmode == M_CSR) {
+    T my[CPL];
+    if (a.rmode == M_IDENT) ldrow<T, CPL>(a.y + (long)r * w, c0, w, my);
+    else {
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) my[c] = T(0);
+      for (int k = a.Mrp[r], ke = a.Mrp[r + 1]; k < ke; ++k) {
+        T yv[CPL];
+        ldrow<T, CPL>(a.y + (long)a.Mci[k] * w, c0, w, yv);
+        T mv = a.Mv[k];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) my[c] += mv * yv[c];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) rhs[c] = (c0 + c < w ? (T)a.rsig[c0 + c] : T(0)) * my[c];
+  }
+  if (a.kap) {
+    T kp[CPL];
+    ldrow<T, CPL>(a.kap + (long)r * w, c0, w, kp);
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) rhs[c] += kp[c];
+  }
+  const int kb = a.rp[r], ke = a.rp[r + 1];
+  T res[CPL];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) res[c] = rhs[c];
+  for (int k = kb; k < ke; ++k) {
+    int j = a.ci[k];
+    T xv[CPL];
+    ldrow<T, CPL>(a.x + (long)j * w, c0, w, xv);
+    T av = a.av[k];
+    if (shifted) {
+      T bv = a.bv ? a.bv[k] : (j == r ? T(1) : T(0));
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) res[c] -= (av - lam[c] * bv) * xv[c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) res[c] -= av * xv[c];
+    }
+  }
+  T coef[CPL];
+  T aa = a.rn_aa[r];
+  T ab = shifted ? a.rn_ab[r] : T(0), bb = shifted ? a.rn_bb[r] : T(0);
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) {
+    T nr = shifted ? aa - T(2) * lam[c] * ab + lam[c] * lam[c] * bb : aa;
+    coef[c] = nr > T(0) ? res[c] / nr : T(0);
+  }
+  for (int k = kb; k < ke; ++k) {
+    int j = a.ci[k];
+    T* xp = a.x + (long)j * w;
+    T xv[CPL];
+    ldrow<T, CPL>(xp, c0, w, xv);
+    T av = a.av[k];
+    if (shifted) {
+      T bv = a.bv ? a.bv[k] : (j == r ? T(1) : T(0));
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) xv[c] += coef[c] * (av - lam[c] * bv);
+    } else {
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) xv[c] += coef[c] * av;
+    }
+    strow<T, CPL>(xp, c0, w, xv);
+  }
+}
+
+template <typename T>
+void launch_kacz(const KaczArgs<T>& a, hipStream_t s) {
+  if (a.nrows <= 0) return;
+  KaczPOD<T> p{a.nrows, a.rows, a.w, a.rp, a.ci, a.av, a.bv, a.lam, a.rn_aa, a.rn_ab, a.rn_bb,
+               a.rmode, a.Mrp, a.Mci, a.Mv, a.y, a.rsig, a.kap, a.x};
+  int sh = lshift_of(a.w);
+  int grid = ceil_div((long)a.nrows << sh, BLK);
+  if (cpl_of(a.w) == 2) hipLaunchKernelGGL((k_kacz<T, 2>), dim3(grid), dim3(BLK), 0, s, p, sh);
+  else hipLaunchKernelGGL((k_kacz<T, 1>), dim3(grid), dim3(BLK), 0, s, p, sh);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Column reductions (fixed grid + fixed-order finalisation: bitwise reproducible)
+// ------------------------------------------------------------------------------------------------
+template <typename T>
+struct DotPOD {
+  int nrows, w;
+  const T* a; const int* Krp; const int* Kci; const T* Kv; const T* z; const T* y; const double* sig;
+};
+
+int dots_grid(int nrows, int w) {
+  int sh = lshift_of(w);
+  return std::max(1, std::min(1024, ceil_div((long)nrows << sh, BLK)));
+}
+
+template <typename T, int CPL>
+__global__ __launch_bounds__(BLK) void k_dots(DotPOD<T> a, int lshift, double* partial) {
+  __shared__ double red[BLK * 2];
+  const int w = a.w;
+  int lane = threadIdx.x & ((1 << lshift) - 1);
+  int c0 = lane * CPL;
+  double acc[CPL];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) acc[c] = 0.0;
+  int stride = (gridDim.x * BLK) >> lshift;
+  if (c0 < w) {
+    double sc[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) sc[c] = (a.sig && c0 + c < w) ? a.sig[c0 + c] : 0.0;
+    for (int row = (int)(((long)blockIdx.x * BLK + threadIdx.x) >> lshift); row < a.nrows; row += stride) {
+      T val[CPL];
+      if (a.Kv) {
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) val[c] = T(0);
+        for (int k = a.Krp[row], ke = a.Krp[row + 1]; k < ke; ++k) {
+          T zv[CPL];
+          ldrow<T, CPL>(a.z + (long)a.Kci[k] * w, c0, w, zv);
+          T av = a.Kv[k];
+#pragma unroll
+          for (int c = 0; c < CPL; ++c) val[c] += av * zv[c];
+        }
+      } else {
+        ldrow<T, CPL>(a.z + (long)row * w, c0, w, val);
+      }
+      if (a.y) {
+        T yv[CPL];
+        ldrow<T, CPL>(a.y + (long)row * w, c0, w, yv);
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) val[c] -= (T)sc[c] * yv[c];
+      }
+      if (a.a) {
+        T av[CPL];
+        ldrow<T, CPL>(a.a + (long)row * w, c0, w, av);
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) acc[c] += (double)av[c] * (double)val[c];
+      } else {
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) acc[c] += (double)val[c] * (double)val[c];
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) red[threadIdx.x * CPL + c] = acc[c];
+  __syncthreads();
+  if ((int)threadIdx.x < w) {
+    int col = threadIdx.x;
+    int ln = col / CPL, sub = col % CPL;
+    double s = 0.0;
+    for (int tt = ln; tt < BLK; tt += (1 << lshift)) s += red[tt * CPL + sub];
+    partial[(long)blockIdx.x * w + col] = s;
+  }
+}
+
+__global__ void k_finalize(int nparts, int w, const double* __restrict__ partial, double* __restrict__ out) {
+  int c = threadIdx.x;
+  if (c >= w) return;
+  double s = 0.0;
+  for (int b = 0; b < nparts; ++b) s += partial[(long)b * w + c];
+  out[c] = s;
+}
+
+template <typename T>
+void launch_dots(const DotArgs<T>& a, double* partial, double* out, hipStream_t s) {
+  int grid = dots_grid(a.nrows, a.w);
+  if (a.nrows <= 0) {
+    launch_fill(out, a.w, 0.0, s);
+    return;
+  }
+  DotPOD<T> p{a.nrows, a.w, a.a, a.Krp, a.Kci, a.Kv, a.z, a.y, a.sig};
+  int sh = lshift_of(a.w);
+  if (cpl_of(a.w) == 2) hipLaunchKernelGGL((k_dots<T, 2>), dim3(grid), dim3(BLK), 0, s, p, sh, partial);
+  else hipLaunchKernelGGL((k_dots<T, 1>), dim3(grid), dim3(BLK), 0, s, p, sh, partial);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, grid, a.w, partial, out);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Tall-skinny Gram G = X^t Y (rows x w, w <= 16) on the FP64 matrix cores.
+// v_mfma_f64_16x16x4f64: lane l supplies A[l%16][l/16] and B[l/16][l%16]; the 16x16 result has
+// D[l/16 + 4v][l%16] in register v of lane l.  Four rows of X and Y feed one instruction.
+// ------------------------------------------------------------------------------------------------
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+int gram_grid(int rows) { return std::max(1, std::min(512, ceil_div(rows, 4 * 4 * 16))); }
+
+__global__ __launch_bounds__(BLK) void k_gram(int rows, int w, const double* __restrict__ X,
+                                              const double* __restrict__ Y, double* __restrict__ partial) {
+  __shared__ double red[4][256];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int gw = blockIdx.x * 4 + wv, nw = gridDim.x * 4;
+  const int i = lane & 15, kk = lane >> 4;
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  for (long r0 = (long)gw * 16; r0 < rows; r0 += (long)nw * 16) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      long r = r0 + u * 4 + kk;
+      double av = 0.0, bv = 0.0;
+      if (r < rows && i < w) { av = X[r * w + i]; bv = Y[r * w + i]; }
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) red[wv][(kk + 4 * v) * 16 + i] = acc[v];
+  __syncthreads();
+  int tt = threadIdx.x;
+  partial[(long)blockIdx.x * 256 + tt] = ((red[0][tt] + red[1][tt]) + red[2][tt]) + red[3][tt];
+}
+
+__global__ void k_gram_finalize(int nparts, int w, const double* __restrict__ partial, double* __restrict__ G) {
+  int t = threadIdx.x;       // 256 threads
+  int i = t >> 4, j = t & 15;
+  if (i >= w || j >= w) return;
+  double s = 0.0;
+  for (int b = 0; b < nparts; ++b) s += partial[(long)b * 256 + t];
+  G[i * w + j] = s;
+}
+
+void launch_gram(int rows, int w, const double* X, const double* Y, double* partial, double* G, hipStream_t s) {
+  int grid = gram_grid(rows);
+  hipLaunchKernelGGL(k_gram, dim3(grid), dim3(BLK), 0, s, rows, w, X, Y, partial);
+  hipLaunchKernelGGL(k_gram_finalize, dim3(1), dim3(256), 0, s, grid, w, partial, G);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Rotation out = X S (S: win x wout, row-major), gather, column scaling
+// ------------------------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_rotate(int rows, int win, int wout, const T* __restrict__ X,
+                                                const double* __restrict__ S, T* __restrict__ out) {
+  __shared__ double Ss[16 * 16];
+  for (int t = threadIdx.x; t < win * wout; t += BLK) Ss[t] = S[t];
+  __syncthreads();
+  long t = (long)blockIdx.x * BLK + threadIdx.x;
+  long row = t / wout;
+  int c = (int)(t % wout);
+  if (row >= rows) return;
+  const T* xr = X + row * win;
+  double acc = 0.0;
+  for (int k = 0; k < win; ++k) acc += (double)xr[k] * Ss[k * wout + c];
+  out[row * wout + c] = (T)acc;
+}
+
+template <typename T>
+void launch_rotate(int rows, int win, int wout, const T* X, const double* S, T* out, hipStream_t s) {
+  if (rows <= 0) return;
+  hipLaunchKernelGGL((k_rotate<T>), dim3(ceil_div((long)rows * wout, BLK)), dim3(BLK), 0, s, rows, win,
+                     wout, X, S, out);
+}
+
+template <typename T>
+__global__ void k_gather_rows(int nout, int w, const int* __restrict__ idx, const T* __restrict__ X,
+                              T* __restrict__ out) {
+  long t = (long)blockIdx.x * BLK + threadIdx.x;
+  long r = t / w;
+  int c = (int)(t % w);
+  if (r >= nout) return;
+  out[r * w + c] = X[(long)idx[r] * w + c];
+}
+template <typename T>
+void launch_gather_rows(int nout, int w, const int* idx, const T* X, T* out, hipStream_t s) {
+  if (nout <= 0) return;
+  hipLaunchKernelGGL((k_gather_rows<T>), dim3(ceil_div((long)nout * w, BLK)), dim3(BLK), 0, s, nout, w,
+                     idx, X, out);
+}
+
+// mode 0: X[:,c] /= sqrt(d[c]) (d > 0);  mode 1: X[:,c] *= d[c]
+template <typename T>
+__global__ void k_scale_cols(int rows, int w, T* X, const double* __restrict__ d, int mode) {
+  long t = (long)blockIdx.x * BLK + threadIdx.x;
+  long r = t / w;
+  int c = (int)(t % w);
+  if (r >= rows) return;
+  double f = mode == 0 ? (d[c] > 0.0 ? 1.0 / sqrt(d[c]) : 1.0) : d[c];
+  X[r * w + c] = (T)((double)X[r * w + c] * f);
+}
+template <typename T>
+void launch_scale_cols(int rows, int w, T* X, const double* d, int mode, hipStream_t s) {
+  if (rows <= 0) return;
+  hipLaunchKernelGGL((k_scale_cols<T>), dim3(ceil_div((long)rows * w, BLK)), dim3(BLK), 0, s, rows, w, X,
+                     d, mode);
+}
+
+// Rayleigh quotient update with the sign check: sig = num / sqrt(nu * nv) (nv == null: num / nu);
+// a negative quotient flips u (flip = -1) and keeps |sig|.
+__global__ void k_rq_update(int w, const double* num, const double* nu, const double* nv, double* sig,
+                            double* flip) {
+  int c = threadIdx.x;
+  if (c >= w) return;
+  double q = nv ? num[c] / sqrt(nu[c] * nv[c]) : num[c] / nu[c];
+  flip[c] = q < 0.0 ? -1.0 : 1.0;
+  sig[c] = fabs(q);
+}
+void launch_rq_update(int w, const double* num, const double* nu, const double* nv, double* sig, double* flip,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_rq_update, dim3(1), dim3(64), 0, s, w, num, nu, nv, sig, flip);
+}
+
+// LS weights from Rayleigh quotients: |rq| (dominant) or 1 / max(|rq|, floor) (minimal)
+__global__ void k_rq_weights(int nf, const double* num, const double* nu, const double* nv, int minimal,
+                             double floor_abs, double* w) {
+  int c = threadIdx.x;
+  if (c >= nf) return;
+  double q = nv ? num[c] / sqrt(nu[c] * nv[c]) : num[c] / nu[c];
+  q = fabs(q);
+  w[c] = minimal ? 1.0 / fmax(q, floor_abs) : q;
+}
+void launch_rq_weights(int nf, const double* num, const double* nu, const double* nv, int minimal,
+                       double floor_abs, double* w, hipStream_t s) {
+  hipLaunchKernelGGL(k_rq_weights, dim3(1), dim3(64), 0, s, nf, num, nu, nv, minimal, floor_abs, w);
+}
+
+template <typename T>
+__global__ void k_fill(T* p, size_t n, T v) {
+  size_t t = (size_t)blockIdx.x * BLK + threadIdx.x;
+  if (t < n) p[t] = v;
+}
+void launch_fill(double* p, size_t n, double val, hipStream_t s) {
+  if (n) hipLaunchKernelGGL((k_fill<double>), dim3(ceil_div((long)n, BLK)), dim3(BLK), 0, s, p, n, val);
+}
+void launch_fillf(float* p, size_t n, float val, hipStream_t s) {
+  if (n) hipLaunchKernelGGL((k_fill<float>), dim3(ceil_div((long)n, BLK)), dim3(BLK), 0, s, p, n, val);
+}
+
+template <typename A, typename B>
+__global__ void k_cast(const A* in, B* out, size_t n) {
+  size_t t = (size_t)blockIdx.x * BLK + threadIdx.x;
+  if (t < n) out[t] = (B)in[t];
+}
+void launch_copy_cast_df(const double* in, float* out, size_t n, hipStream_t s) {
+  if (n) hipLaunchKernelGGL((k_cast<double, float>), dim3(ceil_div((long)n, BLK)), dim3(BLK), 0, s, in, out, n);
+}
+void launch_copy_cast_fd(const float* in, double* out, size_t n, hipStream_t s) {
+  if (n) hipLaunchKernelGGL((k_cast<float, double>), dim3(ceil_div((long)n, BLK)), dim3(BLK), 0, s, in, out, n);
+}
+__global__ void k_axpy_fd(const float* in, double* out, size_t n) {
+  size_t t = (size_t)blockIdx.x * BLK + threadIdx.x;
+  if (t < n) out[t] += (double)in[t];
+}
+void launch_axpy_fd(const float* in, double* out, size_t n, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_axpy_fd, dim3(ceil_div((long)n, BLK)), dim3(BLK), 0, s, in, out, n);
+}
+
+template <typename A, typename B>
+__global__ void k_recip(int n, const A* in, B* out) {
+  int t = blockIdx.x * BLK + threadIdx.x;
+  if (t < n) out[t] = in[t] != A(0) ? (B)(1.0 / (double)in[t]) : B(0);
+}
+void launch_recip(int n, const double* in, double* out, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL((k_recip<double, double>), dim3(ceil_div(n, BLK)), dim3(BLK), 0, s, n, in, out);
+}
+
+__global__ void k_perm_gather(int n, const int* __restrict__ perm, const double* __restrict__ in,
+                              double* __restrict__ out) {
+  int t = blockIdx.x * BLK + threadIdx.x;
+  if (t < n) out[t] = in[perm[t]];
+}
+void launch_perm_gather(int n, const int* perm, const double* in, double* out, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_perm_gather, dim3(ceil_div(n, BLK)), dim3(BLK), 0, s, n, perm, in, out);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Numeric SpGEMM on a known pattern: entry (i, j) of L R is the merge of row i of L with row j of
+// R^t (both sorted), summed in increasing inner index.  One thread per output entry.
+// ------------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(BLK) void k_spgemm_dot(int nnz, const int* __restrict__ rowC,
+                                                    const int* __restrict__ colC, const int* __restrict__ rpL,
+                                                    const int* __restrict__ ciL, const double* __restrict__ vL,
+                                                    const int* __restrict__ rpR, const int* __restrict__ ciR,
+                                                    const double* __restrict__ vR, double* __restrict__ out) {
+  int e = blockIdx.x * BLK + threadIdx.x;
+  if (e >= nnz) return;
+  int i = rowC[e], j = colC[e];
+  int a = rpL[i], ae = rpL[i + 1], b = rpR[j], be = rpR[j + 1];
+  double s = 0.0;
+  while (a < ae && b < be) {
+    int ca = ciL[a], cb = ciR[b];
+    if (ca == cb) {
+      s += vL[a] * vR[b];
+      ++a; ++b;
+    } else if (ca < cb) {
+      ++a;
+    } else {
+      ++b;
+    }
+  }
+  out[e] = s;
+}
+void launch_spgemm_dot(int nnz, const int* rowC, const int* colC, const int* rpL, const int* ciL, const double* vL,
+                       const int* rpR, const int* ciR, const double* vR, double* out, hipStream_t s) {
+  if (nnz > 0)
+    hipLaunchKernelGGL(k_spgemm_dot, dim3(ceil_div(nnz, BLK)), dim3(BLK), 0, s, nnz, rowC, colC, rpL, ciL, vL, rpR,
+                       ciR, vR, out);
+}
+
+__global__ void k_diag_inv(int m, const int* rp, const int* ci, const double* v, double* dinv) {
+  int r = blockIdx.x * BLK + threadIdx.x;
+  if (r >= m) return;
+  double d = 0.0;
+  for (int k = rp[r]; k < rp[r + 1]; ++k)
+    if (ci[k] == r) d = v[k];
+  dinv[r] = d != 0.0 ? 1.0 / d : 0.0;
+}
+void launch_diag_inv(int m, const int* rp, const int* ci, const double* v, double* dinv, hipStream_t s) {
+  if (m > 0) hipLaunchKernelGGL(k_diag_inv, dim3(ceil_div(m, BLK)), dim3(BLK), 0, s, m, rp, ci, v, dinv);
+}
+
+// Per-row sums for Kaczmarz norms: aa = sum a^2, ab = sum a b, bb = sum b^2 (b on the same pattern;
+// bv == nullptr means B = I).  ab and bb may be null.
+__global__ void k_row_sq(int m, const int* rp, const int* ci, const double* v, const double* bv, double* aa,
+                         double* ab, double* bb) {
+  int r = blockIdx.x * BLK + threadIdx.x;
+  if (r >= m) return;
+  double s_aa = 0.0, s_ab = 0.0, s_bb = 0.0;
+  for (int k = rp[r]; k < rp[r + 1]; ++k) {
+    double a = v[k];
+    double b = bv ? bv[k] : (ci[k] == r ? 1.0 : 0.0);
+    s_aa += a * a; s_ab += a * b; s_bb += b * b;
+  }
+  aa[r] = s_aa;
+  if (ab) ab[r] = s_ab;
+  if (bb) bb[r] = s_bb;
+}
+void launch_row_sq(int m, const int* rp, const double* v, const double* bv, double* aa, double* ab, double* bb,
+                   const int* ci, hipStream_t s) {
+  if (m > 0) hipLaunchKernelGGL(k_row_sq, dim3(ceil_div(m, BLK)), dim3(BLK), 0, s, m, rp, ci, v, bv, aa, ab, bb);
+}
+
+__global__ void k_csr_to_dense(int m, const int* rp, const int* ci, const double* v, double* D, int ld, int roff,
+                               int coff, int transpose) {
+  int r = blockIdx.x * BLK + threadIdx.x;
+  if (r >= m) return;
+  for (int k = rp[r]; k < rp[r + 1]; ++k) {
+    int c = ci[k];
+    if (transpose) D[(long)(roff + c) * ld + coff + r] = v[k];
+    else D[(long)(roff + r) * ld + coff + c] = v[k];
+  }
+}
+void launch_csr_to_dense(int m, const int* rp, const int* ci, const double* v, double* D, int ld, int roff, int coff,
+                         bool transpose, hipStream_t s) {
+  if (m > 0)
+    hipLaunchKernelGGL(k_csr_to_dense, dim3(ceil_div(m, BLK)), dim3(BLK), 0, s, m, rp, ci, v, D, ld, roff, coff,
+                       transpose ? 1 : 0);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Least-squares interpolation weights, one thread per F-point:
+//   (G^t W G + eps I) p = G^t W b,  eps = 1e-13 trace / q,  Cholesky in registers.
+// G_{k,a} = value of fitted vector k at the a-th interpolating C-point, b_k = (smoothed) value at
+// the F-point.  The fitted vectors are the columns of U1 (w1) followed by those of U2 (w2).
+// ------------------------------------------------------------------------------------------------
+template <int QM>
+__global__ __launch_bounds__(BLK) void k_ls_fit(int nF, const int* __restrict__ Fpts, const int* __restrict__ prp,
+                                                const int* __restrict__ fine_cols, int w1,
+                                                const double* __restrict__ U1, int w2,
+                                                const double* __restrict__ U2, const double* __restrict__ B1,
+                                                const double* __restrict__ B2, const double* __restrict__ wts,
+                                                double* __restrict__ pval) {
+  int f = blockIdx.x * BLK + threadIdx.x;
+  if (f >= nF) return;
+  const int i = Fpts[f];
+  const int p0 = prp[i];
+  const int q = prp[i + 1] - p0;
+  int J[QM];
+  double Nm[QM * (QM + 1) / 2];
+  double rhs[QM];
+#pragma unroll
+  for (int a = 0; a < QM; ++a) {
+    J[a] = a < q ? fine_cols[p0 + a] : 0;
+    rhs[a] = 0.0;
+  }
+#pragma unroll
+  for (int t = 0; t < QM * (QM + 1) / 2; ++t) Nm[t] = 0.0;
+  for (int blk = 0; blk < 2; ++blk) {
+    const int wb = blk == 0 ? w1 : w2;
+    const double* U = blk == 0 ? U1 : U2;
+    const double* Bv = blk == 0 ? B1 : B2;
+    const int woff = blk == 0 ? 0 : w1;
+    for (int k = 0; k < wb; ++k) {
+      const double wk = wts[woff + k];
+      const double bk = Bv[(long)i * wb + k];
+      double g[QM];
+#pragma unroll
+      for (int a = 0; a < QM; ++a) g[a] = a < q ? U[(long)J[a] * wb + k] : 0.0;
+#pragma unroll
+      for (int a = 0; a < QM; ++a) {
+        rhs[a] += wk * g[a] * bk;
+#pragma unroll
+        for (int b = 0; b <= a; ++b) Nm[a * (a + 1) / 2 + b] += wk * g[a] * g[b];
+      }
+    }
+  }
+  double tr = 0.0;
+#pragma unroll
+  for (int a = 0; a < QM; ++a) tr += a < q ? Nm[a * (a + 1) / 2 + a] : 0.0;
+  const double eps = q > 0 ? 1e-13 * tr / q : 0.0;
+#pragma unroll
+  for (int a = 0; a < QM; ++a) Nm[a * (a + 1) / 2 + a] += a < q ? eps : 1.0;
+  // Cholesky (lower, packed), padding rows are identity
+#pragma unroll
+  for (int a = 0; a < QM; ++a) {
+#pragma unroll
+    for (int b = 0; b <= a; ++b) {
+      double s = Nm[a * (a + 1) / 2 + b];
+#pragma unroll
+      for (int k = 0; k < b; ++k) s -= Nm[a * (a + 1) / 2 + k] * Nm[b * (b + 1) / 2 + k];
+      if (a == b) Nm[a * (a + 1) / 2 + a] = sqrt(fmax(s, 1e-300));
+      else Nm[a * (a + 1) / 2 + b] = s / Nm[b * (b + 1) / 2 + b];
+    }
+  }
+  // forward / backward substitution
+#pragma unroll
+  for (int a = 0; a < QM; ++a) {
+    double s = rhs[a];
+#pragma unroll
+    for (int k = 0; k < a; ++k) s -= Nm[a * (a + 1) / 2 + k] * rhs[k];
+    rhs[a] = s / Nm[a * (a + 1) / 2 + a];
+  }
+#pragma unroll
+  for (int a = QM - 1; a >= 0; --a) {
+    double s = rhs[a];
+#pragma unroll
+    for (int k = a + 1; k < QM; ++k) s -= Nm[k * (k + 1) / 2 + a] * rhs[k];
+    rhs[a] = s / Nm[a * (a + 1) / 2 + a];
+  }
+#pragma unroll
+  for (int a = 0; a < QM; ++a)
+    if (a < q) pval[p0 + a] = rhs[a];
+}
+
+void launch_ls_fit(int nF, const int* Fpts, const int* prp, const int* fine_cols, int w1, const double* U1, int w2,
+                   const double* U2, const double* B1, const double* B2, const double* wts, double* pval, int qmax,
+                   hipStream_t s) {
+  if (nF <= 0) return;
+  int grid = ceil_div(nF, BLK);
+  if (qmax <= 4)
+    hipLaunchKernelGGL(k_ls_fit<4>, dim3(grid), dim3(BLK), 0, s, nF, Fpts, prp, fine_cols, w1, U1, w2, U2, B1, B2,
+                       wts, pval);
+  else if (qmax <= 8)
+    hipLaunchKernelGGL(k_ls_fit<8>, dim3(grid), dim3(BLK), 0, s, nF, Fpts, prp, fine_cols, w1, U1, w2, U2, B1, B2,
+                       wts, pval);
+  else
+    hipLaunchKernelGGL(k_ls_fit<16>, dim3(grid), dim3(BLK), 0, s, nF, Fpts, prp, fine_cols, w1, U1, w2, U2, B1,
+                       B2, wts, pval);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Seeded initial vectors on the device: SplitMix64 (Steele, Lea & Flood 2014) output k+1 of the
+// stream started at `seed`, mapped to [-1, 1) as 2 (z >> 11) 2^-53 - 1.  Value k (column-major over
+// the stacked [U; V] of `rows = ru + rv` rows) goes to row-major U (ru x w) or V (rv x w).
+// ------------------------------------------------------------------------------------------------
+__device__ __forceinline__ double splitmix_uniform(unsigned long long seed, unsigned long long k) {
+  unsigned long long z = seed + k * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z = z ^ (z >> 31);
+  return (double)(z >> 11) * 0x1.0p-53 * 2.0 - 1.0;
+}
+__global__ void k_splitmix_block(long ru, long rv, int w, unsigned long long seed, double* U, double* V) {
+  long t = (long)blockIdx.x * BLK + threadIdx.x;
+  long rows = ru + rv;
+  if (t >= rows * w) return;
+  long c = t / rows, r = t % rows;
+  double x = splitmix_uniform(seed, (unsigned long long)t + 1ull);
+  if (r < ru) U[r * w + c] = x;
+  else V[(r - ru) * w + c] = x;
+}
+void launch_splitmix_block(long ru, long rv, int w, unsigned long long seed, double* U, double* V, hipStream_t s) {
+  long n = (ru + rv) * w;
+  if (n > 0) hipLaunchKernelGGL(k_splitmix_block, dim3(ceil_div(n, BLK)), dim3(BLK), 0, s, ru, rv, w, seed, U, V);
+}
+
+// Output convention: sgn_j = -1 when the entry of largest magnitude of column j (lowest index on
+// ties) is negative.  One workgroup per column.
+__global__ __launch_bounds__(BLK) void k_sign_argmax(int rows, int w, const double* __restrict__ X, double* sgn) {
+  __shared__ double bv[BLK];
+  __shared__ int bi[BLK];
+  const int j = blockIdx.x;
+  double best = -1.0;
+  int bidx = 0x7fffffff;
+  for (int r = threadIdx.x; r < rows; r += BLK) {
+    double a = fabs(X[(long)r * w + j]);
+    if (a > best) { best = a; bidx = r; }
+  }
+  bv[threadIdx.x] = best; bi[threadIdx.x] = bidx;
+  __syncthreads();
+  for (int s2 = BLK / 2; s2 > 0; s2 >>= 1) {
+    if ((int)threadIdx.x < s2) {
+      double a = bv[threadIdx.x + s2];
+      int ia = bi[threadIdx.x + s2];
+      if (a > bv[threadIdx.x] || (a == bv[threadIdx.x] && ia < bi[threadIdx.x])) {
+        bv[threadIdx.x] = a; bi[threadIdx.x] = ia;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sgn[j] = (bi[0] < rows && X[(long)bi[0] * w + j] < 0.0) ? -1.0 : 1.0;
+}
+void launch_sign_argmax(int rows, int w, const double* X, double* sgn, hipStream_t s) {
+  hipLaunchKernelGGL(k_sign_argmax, dim3(w), dim3(BLK), 0, s, rows, w, X, sgn);
+}
+
+// out[keep[r] + j ld] = sgn_j X[r][j] (column-major output with leading dimension ld)
+__global__ void k_scatter_out(int rows, int w, const double* __restrict__ X, const int* __restrict__ keep,
+                              const double* __restrict__ sgn, double* __restrict__ out, long ld) {
+  long t = (long)blockIdx.x * BLK + threadIdx.x;
+  long r = t / w;
+  int j = (int)(t % w);
+  if (r >= rows) return;
+  out[(long)keep[r] + (long)j * ld] = sgn[j] * X[r * w + j];
+}
+void launch_scatter_out(int rows, int w, const double* X, const int* keep, const double* sgn, double* out, long ld,
+                        hipStream_t s) {
+  if (rows > 0)
+    hipLaunchKernelGGL(k_scatter_out, dim3(ceil_div((long)rows * w, BLK)), dim3(BLK), 0, s, rows, w, X, keep, sgn,
+                       out, ld);
+}
+
+// explicit instantiations
+template void launch_spmm<double>(int, int, const int*, const int*, const double*, const double*, double*, double,
+                                  hipStream_t);
+template void launch_spmm<float>(int, int, const int*, const int*, const float*, const float*, float*, double,
+                                 hipStream_t);
+template void launch_rowop<double>(const RowOpArgs<double>&, hipStream_t);
+template void launch_rowop<float>(const RowOpArgs<float>&, hipStream_t);
+template void launch_kacz<double>(const KaczArgs<double>&, hipStream_t);
+template void launch_kacz<float>(const KaczArgs<float>&, hipStream_t);
+template void launch_dots<double>(const DotArgs<double>&, double*, double*, hipStream_t);
+template void launch_dots<float>(const DotArgs<float>&, double*, double*, hipStream_t);
+template void launch_rotate<double>(int, int, int, const double*, const double*, double*, hipStream_t);
+template void launch_rotate<float>(int, int, int, const float*, const double*, float*, hipStream_t);
+template void launch_gather_rows<double>(int, int, const int*, const double*, double*, hipStream_t);
+template void launch_gather_rows<float>(int, int, const int*, const float*, float*, hipStream_t);
+template void launch_scale_cols<double>(int, int, double*, const double*, int, hipStream_t);
+template void launch_scale_cols<float>(int, int, float*, const double*, int, hipStream_t);
+
+}  // namespace slamg

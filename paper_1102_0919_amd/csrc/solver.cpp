@@ -1,0 +1,1448 @@
+// Device orchestration of the self-learning AMG method: the multiplicative (setup) phase of §3,
+// the additive (solve) phase of §4 with the Ritz projection of §4.3, for SVD and SPD-eigen kinds and
+// dominant / minimal targets (§5).  Every numeric step is a HIP kernel launched on one stream; the
+// host only builds the hierarchy structure in the first cycle (graph.cpp) and reads the residual
+// norms once per additive iteration.
+#include "solver.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+
+#include "graph.h"
+
+namespace slamg {
+
+#define HIPCHK(x)                                                                                   \
+  do {                                                                                              \
+    hipError_t e_ = (x);                                                                            \
+    if (e_ != hipSuccess) throw SolverError{ST_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+// ------------------------------------------------------------------------------------------------
+// SplitMix64 (Steele, Lea & Flood 2014)
+// ------------------------------------------------------------------------------------------------
+uint64_t splitmix64_next(uint64_t& state) {
+  state += 0x9E3779B97F4A7C15ull;
+  uint64_t z = state;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+double splitmix64_uniform(uint64_t seed, uint64_t k) {
+  uint64_t st = seed + (k - 1) * 0x9E3779B97F4A7C15ull;
+  uint64_t z = splitmix64_next(st);
+  return (double)(z >> 11) * 0x1.0p-53 * 2.0 - 1.0;
+}
+static const uint64_t NORM_SEED_XOR = 0xA5A5A5A5A5A5A5A5ull;
+
+// ------------------------------------------------------------------------------------------------
+// Device memory arena (freed when the solve ends); enforces the context's HBM budget
+// ------------------------------------------------------------------------------------------------
+class Arena {
+ public:
+  explicit Arena(size_t budget) : budget_(budget) {}
+  ~Arena() {
+    for (void* p : ptrs_) (void)hipFree(p);
+  }
+  template <class T>
+  T* alloc(size_t n) {
+    size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+    bytes = (bytes + 255) & ~size_t(255);
+    if (budget_ && used_ + bytes > budget_)
+      throw SolverError{ST_E_BUDGET, "device footprint exceeds the HBM budget of the context"};
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      throw SolverError{ST_E_OOM, "hipMalloc failed"};
+    }
+    ptrs_.push_back(p);
+    used_ += bytes;
+    return static_cast<T*>(p);
+  }
+  size_t used() const { return used_; }
+
+ private:
+  size_t budget_, used_ = 0;
+  std::vector<void*> ptrs_;
+};
+
+template <class T>
+static void h2d(T* d, const std::vector<T>& h, hipStream_t s) {
+  if (!h.empty()) HIPCHK(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+template <class T>
+static void d2h(std::vector<T>& h, const T* d, size_t n, hipStream_t s) {
+  h.resize(n);
+  if (n) HIPCHK(hipMemcpyAsync(h.data(), d, n * sizeof(T), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+// ------------------------------------------------------------------------------------------------
+// Hierarchy data
+// ------------------------------------------------------------------------------------------------
+struct Plan {   // numeric C = L R on a fixed pattern: entry (i, j) = row i of L . row j of Rt
+  int nnz = 0;
+  int* rowC = nullptr;
+  const int* colC = nullptr;
+  const DCsr* L = nullptr;
+  const DCsr* Rt = nullptr;
+  double* out = nullptr;
+  void run(hipStream_t s) const {
+    launch_spgemm_dot(nnz, rowC, colC, L->rp, L->ci, L->v, Rt->rp, Rt->ci, Rt->v, out, s);
+  }
+};
+
+struct Side {
+  int npts = 0, nc = 0;
+  std::vector<char> is_c;
+  std::vector<int> cpts;
+  int* d_cpts = nullptr;
+  HCsr Ppat, Ptpat;
+  std::vector<int> perm;   // Pt entry -> P entry
+  DCsr P, Pt;
+  int* d_perm = nullptr;
+  int nF = 0, qmax = 0, capped = 0;
+  int* d_F = nullptr;
+  int* d_prp = nullptr;
+  int* d_fc = nullptr;
+};
+
+template <class T>
+struct Blocks {
+  T *Ut = nullptr, *Vt = nullptr;          // test vectors (mult phase, FP64 only)
+  T *Ub = nullptr, *Vb = nullptr;          // boot vectors / additive iterates (contiguous)
+  T *kap = nullptr, *tau = nullptr;        // restricted residuals (contiguous)
+  T *tU = nullptr, *tV = nullptr, *tU2 = nullptr, *tV2 = nullptr;
+};
+template <class T>
+struct Aux {
+  T *dinvB = nullptr, *dinvC = nullptr;    // 1 / diag(B), 1 / diag(C)
+  T *rnA = nullptr, *rnAab = nullptr, *rnAbb = nullptr, *rnAt = nullptr;   // Kaczmarz row sums
+};
+
+struct Level {
+  int m = 0, n = 0;
+  HCsr hA, hAt, hB, hC;     // host patterns (hB/hC: SVD only)
+  std::vector<int> permAt;
+  DCsr A, At, B, C;         // SPD: At aliases A, B lives on A's pattern, C unused
+  int* d_permAt = nullptr;
+  bool finest = false;
+  // Kaczmarz orders (minimal targets)
+  int* kA_rows = nullptr;  std::vector<int> kA_cptr;  std::vector<long> kA_cnnz;
+  int* kAt_rows = nullptr; std::vector<int> kAt_cptr; std::vector<long> kAt_cnnz;
+  // minimal LS pre-smoothing scales
+  double* smU = nullptr;    // 1 / diag(N_u)
+  double* smV = nullptr;    // 1 / diag(N_v)
+  Blocks<double> bd;
+  Blocks<float> bf;
+  Aux<double> ad;
+  Aux<float> af;
+  Side su, sv;
+  DCsr S1, S2, S3;
+  std::vector<Plan> plans;  // Galerkin numeric products producing level + 1
+  Plan pAc, pBc, pCc;
+};
+
+template <class T> static const T* vals(const DCsr& a);
+template <> const double* vals<double>(const DCsr& a) { return a.v; }
+template <> const float* vals<float>(const DCsr& a) { return a.vf; }
+template <class T> static Blocks<T>& blocks(Level& L);
+template <> Blocks<double>& blocks<double>(Level& L) { return L.bd; }
+template <> Blocks<float>& blocks<float>(Level& L) { return L.bf; }
+template <class T> static Aux<T>& aux(Level& L);
+template <> Aux<double>& aux<double>(Level& L) { return L.ad; }
+template <> Aux<float>& aux<float>(Level& L) { return L.af; }
+
+// ------------------------------------------------------------------------------------------------
+class Solver {
+ public:
+  Solver(hipStream_t s, size_t budget, const Problem& pb, const slamg_params& p)
+      : st_(s), ar_(budget), p_(p), spd_(pb.kind == SLAMG_SPD_EIG), minimal_(pb.target == SLAMG_MINIMAL),
+        nb_(pb.nb), nt_(p.n_t), mixed_(p.precision == SLAMG_MIXED_FP32), A0_(pb.A), pb_(pb) {}
+
+  void run(const double* init_tests, SolveOutput& out);
+
+ private:
+  // set-up helpers
+  DCsr upload(const HCsr& h, bool with_values);
+  void alloc_level_buffers(Level& L);
+  void finest_level(const double* init_tests);
+  void norm_estimate();
+  bool build_structure(int l);
+  void build_side(Level& L, Side& S, const HCsr& N, int npts);
+  void make_coarse_level(int l);
+  void refresh_level_aux(Level& L);
+  void colour(Level& L);
+  HCsr strength_operator(Level& L, bool u_side, bool finest);
+  // cycle pieces
+  void relax_tests(int l);
+  void boot_relax_rq(int l);
+  void fit_interpolation(int l, int cycle);
+  void galerkin(int l);
+  void inject(int l, int cycle);
+  void coarsest_mult();
+  void mult_cycle(int c);
+  template <class T> void boot_relax(int l, const T* kap, const T* tau, const double* sig);
+  template <class T> void additive_vcycle(const double* sig, T* rhsU, T* rhsV);
+  void additive_iteration();
+  void ritz();
+  void cholqr2(double* X, int rows, double* tmp, double* out);
+  void residuals(std::vector<double>& rho);
+  void check_status();
+  void dense_coarsest(double* X, double* Y);
+  void sync() { HIPCHK(hipStreamSynchronize(st_)); }
+  void lastcheck() { HIPCHK(hipGetLastError()); }
+
+  int rows_u(const Level& L) const { return L.m; }
+  int rows_v(const Level& L) const { return spd_ ? L.m : L.n; }
+  int size_of(const Level& L) const { return spd_ ? L.m : L.m + L.n; }
+
+  hipStream_t st_;
+  Arena ar_;
+  slamg_params p_;
+  bool spd_, minimal_;
+  int nb_, nt_;
+  bool mixed_;
+  const HCsr& A0_;
+  const Problem& pb_;
+  std::vector<std::unique_ptr<Level>> lv_;
+  double anorm_ = 0.0;
+  double* sig_ = nullptr;       // device sigma_b (nb)
+  double* flip_ = nullptr;
+  double* partial_ = nullptr;   // reduction partials
+  double* r1_ = nullptr;        // small device vectors (>= 64)
+  double* r2_ = nullptr;
+  double* r3_ = nullptr;
+  double* wts_ = nullptr;
+  double* gram_ = nullptr;      // 16 x 16
+  double* small1_ = nullptr;    // 16 x 16
+  double* small2_ = nullptr;
+  double* small_work_ = nullptr;
+  int* status_ = nullptr;
+  // coarsest dense data
+  int NL_ = 0;
+  double *dX_ = nullptr, *dY_ = nullptr, *dwork_ = nullptr, *dA_ = nullptr, *dB_ = nullptr, *dC_ = nullptr;
+  double *mu_ = nullptr, *Zp_ = nullptr;
+  bool pencil_ready_ = false;
+  slamg_report rep_{};
+  // profiling (HIP events around the launches of selected kernel classes)
+  struct ProfEv { hipEvent_t a, b; int cls; };
+  std::vector<ProfEv> pev_;
+  double pbytes_[8] = {};
+  long pn_[8] = {};
+  int pmask_ = 0;
+  template <class F> void prof(int cls, double bytes, F&& f) {
+    if (!((pmask_ >> cls) & 1)) { f(); return; }
+    ProfEv e{nullptr, nullptr, cls};
+    HIPCHK(hipEventCreate(&e.a));
+    HIPCHK(hipEventCreate(&e.b));
+    HIPCHK(hipEventRecord(e.a, st_));
+    f();
+    HIPCHK(hipEventRecord(e.b, st_));
+    pev_.push_back(e);
+    pbytes_[cls] += bytes;
+    pn_[cls] += 1;
+  }
+  void prof_finish();
+  template <class T> void rowop(int l, const RowOpArgs<T>& a, const DCsr* K);
+  template <class T> void spmm(int l, const DCsr& K, const T* Kv, int w, const T* x, T* y, double beta);
+  template <class T> void dots(int l, const DotArgs<T>& a, const DCsr* K, double* out);
+  template <class T> void kacz(int l, const KaczArgs<T>& a, long nnz_colour);
+};
+
+// Algorithmic bytes of one launch: every array the launch touches, counted once.
+template <class T>
+static double rowop_bytes(const RowOpArgs<T>& a, const DCsr* K) {
+  const double sz = sizeof(T), w = a.w, r = a.nrows;
+  double b = 0.0;
+  if (a.Kv && K) b += 4.0 * (r + 1) + (4.0 + sz) * K->nnz + sz * w * K->n;
+  if (a.mmode == M_SHARED && K) b += sz * K->nnz;
+  const bool own = a.x || a.mmode == M_IDENT;
+  const bool same = a.Kv && (a.z == a.x || a.z == a.y);
+  if (own && !same) b += sz * w * r;
+  if (a.D) b += sz * r;
+  if (a.kap) b += sz * w * r;
+  b += sz * w * r;
+  return b;
+}
+
+template <class T>
+void Solver::rowop(int l, const RowOpArgs<T>& a, const DCsr* K) {
+  if (l == 0) prof(0, rowop_bytes(a, K), [&] { launch_rowop(a, st_); });
+  else launch_rowop(a, st_);
+}
+
+template <class T>
+void Solver::spmm(int l, const DCsr& K, const T* Kv, int w, const T* x, T* y, double beta) {
+  const double sz = sizeof(T);
+  const double bytes = 4.0 * (K.m + 1) + (4.0 + sz) * K.nnz + sz * w * ((double)K.n + K.m * (beta != 0.0 ? 2 : 1));
+  if (l == 0) prof(0, bytes, [&] { launch_spmm<T>(K.m, w, K.rp, K.ci, Kv, x, y, beta, st_); });
+  else launch_spmm<T>(K.m, w, K.rp, K.ci, Kv, x, y, beta, st_);
+}
+
+template <class T>
+void Solver::dots(int l, const DotArgs<T>& a, const DCsr* K, double* out) {
+  const double sz = sizeof(T), w = a.w, r = a.nrows;
+  double b = (a.a && a.a != a.z ? sz * w * r : 0.0) + (a.y && a.y != a.z ? sz * w * r : 0.0);
+  if (a.Kv && K) b += 4.0 * (r + 1) + (4.0 + sz) * K->nnz + sz * w * K->n;
+  else b += sz * w * r;
+  if (l == 0 && a.Kv) prof(0, b, [&] { launch_dots(a, partial_, out, st_); });
+  else launch_dots(a, partial_, out, st_);
+}
+
+template <class T>
+void Solver::kacz(int l, const KaczArgs<T>& a, long nnz_colour) {
+  const double sz = sizeof(T), w = a.w, r = a.nrows, z = (double)nnz_colour;
+  double b = r * (8.0 + 4.0 + sz) + (4.0 + sz) * z + 2.0 * sz * w * z;
+  if (a.bv) b += sz * z;
+  if (a.lam) b += 2.0 * sz * r;
+  if (a.rmode == M_IDENT) b += sz * w * r;
+  if (a.kap) b += sz * w * r;
+  if (l == 0) prof(1, b, [&] { launch_kacz(a, st_); });
+  else launch_kacz(a, st_);
+}
+
+static double plan_bytes(const Plan& p) {
+  return 12.0 * p.L->nnz + 4.0 * p.L->m + 12.0 * p.Rt->nnz + 4.0 * p.Rt->m + 16.0 * p.nnz;
+}
+
+void Solver::prof_finish() {
+  if (pev_.empty()) return;
+  sync();
+  double ms[8] = {};
+  for (auto& e : pev_) {
+    float t = 0.0f;
+    HIPCHK(hipEventElapsedTime(&t, e.a, e.b));
+    ms[e.cls] += t;
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  pev_.clear();
+  for (int c = 0; c < 8; ++c) {
+    rep_.prof_ms[c] = ms[c];
+    rep_.prof_launches[c] = pn_[c];
+    rep_.prof_bytes[c] = pbytes_[c];
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+DCsr Solver::upload(const HCsr& h, bool with_values) {
+  DCsr d;
+  d.m = h.m; d.n = h.n; d.nnz = h.nnz();
+  d.rp = ar_.alloc<int>(h.m + 1);
+  d.ci = ar_.alloc<int>(d.nnz);
+  d.v = ar_.alloc<double>(d.nnz);
+  h2d(d.rp, h.rp, st_);
+  h2d(d.ci, h.ci, st_);
+  if (with_values && !h.v.empty()) h2d(d.v, h.v, st_);
+  if (mixed_) d.vf = ar_.alloc<float>(d.nnz);
+  return d;
+}
+
+void Solver::alloc_level_buffers(Level& L) {
+  const int mu = rows_u(L), mv = rows_v(L);
+  const int wmax = std::max(nt_, nb_);
+  auto& b = L.bd;
+  if (!spd_) {
+    b.Ut = ar_.alloc<double>((size_t)mu * nt_);
+    b.Vt = ar_.alloc<double>((size_t)mv * nt_);
+    double* UV = ar_.alloc<double>((size_t)(mu + mv) * nb_);
+    b.Ub = UV; b.Vb = UV + (size_t)mu * nb_;
+    double* KT = ar_.alloc<double>((size_t)(mu + mv) * nb_);
+    b.kap = KT; b.tau = KT + (size_t)mu * nb_;
+    b.tU = ar_.alloc<double>((size_t)mu * wmax);
+    b.tV = ar_.alloc<double>((size_t)mv * wmax);
+    b.tU2 = ar_.alloc<double>((size_t)mu * wmax);
+    b.tV2 = ar_.alloc<double>((size_t)mv * wmax);
+  } else {
+    b.Ut = ar_.alloc<double>((size_t)mu * nt_);
+    b.Ub = ar_.alloc<double>((size_t)mu * nb_);
+    b.kap = ar_.alloc<double>((size_t)mu * nb_);
+    b.tU = ar_.alloc<double>((size_t)mu * wmax);
+    b.tU2 = ar_.alloc<double>((size_t)mu * wmax);
+  }
+  L.ad.dinvB = ar_.alloc<double>(mu);
+  if (!spd_) L.ad.dinvC = ar_.alloc<double>(mv);
+  if (minimal_) {
+    L.ad.rnA = ar_.alloc<double>(L.m);
+    if (spd_) {
+      L.ad.rnAab = ar_.alloc<double>(L.m);
+      L.ad.rnAbb = ar_.alloc<double>(L.m);
+    } else {
+      L.ad.rnAt = ar_.alloc<double>(L.n);
+    }
+    L.smU = ar_.alloc<double>(mu);
+    if (!spd_) L.smV = ar_.alloc<double>(mv);
+  }
+  if (mixed_) {
+    auto& f = L.bf;
+    if (!spd_) {
+      float* UV = ar_.alloc<float>((size_t)(mu + mv) * nb_);
+      f.Ub = UV; f.Vb = UV + (size_t)mu * nb_;
+      float* KT = ar_.alloc<float>((size_t)(mu + mv) * nb_);
+      f.kap = KT; f.tau = KT + (size_t)mu * nb_;
+      f.tU = ar_.alloc<float>((size_t)mu * nb_);
+      f.tV = ar_.alloc<float>((size_t)mv * nb_);
+    } else {
+      f.Ub = ar_.alloc<float>((size_t)mu * nb_);
+      f.kap = ar_.alloc<float>((size_t)mu * nb_);
+      f.tU = ar_.alloc<float>((size_t)mu * nb_);
+    }
+    L.af.dinvB = ar_.alloc<float>(mu);
+    if (!spd_) L.af.dinvC = ar_.alloc<float>(mv);
+    if (minimal_) {
+      L.af.rnA = ar_.alloc<float>(L.m);
+      if (spd_) {
+        L.af.rnAab = ar_.alloc<float>(L.m);
+        L.af.rnAbb = ar_.alloc<float>(L.m);
+      } else {
+        L.af.rnAt = ar_.alloc<float>(L.n);
+      }
+    }
+  }
+}
+
+// Values derived from the level operators: diagonal inverses and Kaczmarz row sums.
+void Solver::refresh_level_aux(Level& L) {
+  launch_diag_inv(L.B.m, L.B.rp, L.B.ci, L.B.v, L.ad.dinvB, st_);
+  if (!spd_) launch_diag_inv(L.C.m, L.C.rp, L.C.ci, L.C.v, L.ad.dinvC, st_);
+  if (minimal_) {
+    if (spd_) {
+      launch_row_sq(L.m, L.A.rp, L.A.v, L.finest ? nullptr : L.B.v, L.ad.rnA, L.ad.rnAab, L.ad.rnAbb, L.A.ci, st_);
+      // Jacobi pre-smoothing of the LS fit uses N = A: 1 / diag(A)
+      launch_diag_inv(L.m, L.A.rp, L.A.ci, L.A.v, L.smU, st_);
+    } else {
+      launch_row_sq(L.m, L.A.rp, L.A.v, nullptr, L.ad.rnA, nullptr, nullptr, L.A.ci, st_);
+      launch_row_sq(L.n, L.At.rp, L.At.v, nullptr, L.ad.rnAt, nullptr, nullptr, L.At.ci, st_);
+      launch_recip(L.m, L.ad.rnA, L.smU, st_);    // diag(A A^t) = row norms^2 of A
+      launch_recip(L.n, L.ad.rnAt, L.smV, st_);   // diag(A^t A) = column norms^2
+    }
+  }
+  if (mixed_) {
+    auto cast = [&](const DCsr& a) { launch_copy_cast_df(a.v, a.vf, a.nnz, st_); };
+    cast(L.A);
+    if (!spd_) { cast(L.At); cast(L.C); }
+    cast(L.B);
+    launch_copy_cast_df(L.ad.dinvB, L.af.dinvB, L.B.m, st_);
+    if (!spd_) launch_copy_cast_df(L.ad.dinvC, L.af.dinvC, L.C.m, st_);
+    if (minimal_) {
+      launch_copy_cast_df(L.ad.rnA, L.af.rnA, L.m, st_);
+      if (spd_) {
+        launch_copy_cast_df(L.ad.rnAab, L.af.rnAab, L.m, st_);
+        launch_copy_cast_df(L.ad.rnAbb, L.af.rnAbb, L.m, st_);
+      } else {
+        launch_copy_cast_df(L.ad.rnAt, L.af.rnAt, L.n, st_);
+      }
+    }
+  }
+}
+
+static std::vector<long> colour_nnz(const HCsr& A, const std::vector<int>& rows, const std::vector<int>& cptr) {
+  std::vector<long> z(cptr.size() > 0 ? cptr.size() - 1 : 0, 0);
+  for (size_t c = 0; c + 1 < cptr.size(); ++c)
+    for (int t = cptr[c]; t < cptr[c + 1]; ++t) z[c] += A.rp[rows[t] + 1] - A.rp[rows[t]];
+  return z;
+}
+
+void Solver::colour(Level& L) {
+  if (!minimal_) return;
+  std::vector<int> rows, cptr;
+  if (spd_) {
+    HCsr pat = L.hA;   // B_l lives on A_l's pattern
+    colour_order(greedy_row_colouring(pat), rows, cptr);
+    L.kA_rows = ar_.alloc<int>(rows.size());
+    h2d(L.kA_rows, rows, st_);
+    L.kA_cptr = cptr;
+    L.kA_cnnz = colour_nnz(pat, rows, cptr);
+  } else {
+    colour_order(greedy_row_colouring(L.hA), rows, cptr);
+    L.kA_rows = ar_.alloc<int>(rows.size());
+    h2d(L.kA_rows, rows, st_);
+    L.kA_cptr = cptr;
+    L.kA_cnnz = colour_nnz(L.hA, rows, cptr);
+    std::vector<int> rows2, cptr2;
+    colour_order(greedy_row_colouring(L.hAt), rows2, cptr2);
+    L.kAt_rows = ar_.alloc<int>(rows2.size());
+    h2d(L.kAt_rows, rows2, st_);
+    L.kAt_cptr = cptr2;
+    L.kAt_cnnz = colour_nnz(L.hAt, rows2, cptr2);
+  }
+  sync();
+}
+
+// ------------------------------------------------------------------------------------------------
+void Solver::finest_level(const double* init_tests) {
+  auto L = std::make_unique<Level>();
+  L->finest = true;
+  L->m = A0_.m; L->n = A0_.n;
+  L->hA = A0_;
+  if (pb_.dA) {
+    L->A = *pb_.dA;
+    if (mixed_) L->A.vf = ar_.alloc<float>(L->A.nnz);
+  } else {
+    L->A = upload(A0_, true);
+  }
+  if (spd_) {
+    L->At = L->A;
+    L->B = L->A;
+    if (pb_.dB) {
+      L->B.v = pb_.dB->v;
+    } else {
+      HCsr Bh = A0_;   // identity on A's pattern
+      for (int i = 0; i < Bh.m; ++i)
+        for (int k = Bh.rp[i]; k < Bh.rp[i + 1]; ++k) Bh.v[k] = Bh.ci[k] == i ? 1.0 : 0.0;
+      L->B.v = ar_.alloc<double>(L->A.nnz);
+      h2d(L->B.v, Bh.v, st_);
+    }
+    if (mixed_) L->B.vf = ar_.alloc<float>(L->A.nnz);
+  } else if (pb_.dAt) {
+    L->hAt = transpose(A0_, &L->permAt);
+    L->At = *pb_.dAt;
+    if (mixed_) L->At.vf = ar_.alloc<float>(L->At.nnz);
+    auto identp = [&](int n) {
+      HCsr I;
+      I.m = I.n = n;
+      I.rp.resize(n + 1); I.ci.resize(n);
+      for (int i = 0; i <= n; ++i) I.rp[i] = i;
+      for (int i = 0; i < n; ++i) I.ci[i] = i;
+      return I;
+    };
+    L->hB = identp(L->m);
+    L->hC = identp(L->n);
+    L->B = *pb_.dB;
+    L->C = *pb_.dC;
+    if (mixed_) { L->B.vf = ar_.alloc<float>(L->B.nnz); L->C.vf = ar_.alloc<float>(L->C.nnz); }
+  } else {
+    L->hAt = transpose(A0_, &L->permAt);
+    L->At = upload(L->hAt, true);
+    auto ident = [&](int n) {
+      HCsr I;
+      I.m = I.n = n;
+      I.rp.resize(n + 1); I.ci.resize(n); I.v.assign(n, 1.0);
+      for (int i = 0; i <= n; ++i) I.rp[i] = i;
+      for (int i = 0; i < n; ++i) I.ci[i] = i;
+      return I;
+    };
+    L->hB = ident(L->m);
+    L->hC = ident(L->n);
+    L->B = upload(L->hB, true);
+    L->C = upload(L->hC, true);
+  }
+  alloc_level_buffers(*L);
+  refresh_level_aux(*L);
+  colour(*L);
+  // initial test vectors (column-major input -> row-major blocks)
+  const int mu = rows_u(*L), mv = rows_v(*L);
+  const int rows = spd_ ? mu : mu + mv;
+  if (init_tests) {
+    std::vector<double> U((size_t)mu * nt_), V(spd_ ? 0 : (size_t)mv * nt_);
+    for (int c = 0; c < nt_; ++c)
+      for (int r = 0; r < rows; ++r) {
+        double x = init_tests[(size_t)c * rows + r];
+        if (r < mu) U[(size_t)r * nt_ + c] = x;
+        else V[(size_t)(r - mu) * nt_ + c] = x;
+      }
+    h2d(L->bd.Ut, U, st_);
+    if (!spd_) h2d(L->bd.Vt, V, st_);
+  } else {
+    // SplitMix64 stream, column-major over [U_t; V_t], generated on the device
+    launch_splitmix_block(mu, spd_ ? 0 : mv, nt_, p_.seed, L->bd.Ut, spd_ ? nullptr : L->bd.Vt, st_);
+  }
+  lv_.push_back(std::move(L));
+}
+
+// ||A||_2 estimate: 30 power steps on A^t A from a SplitMix64 start vector.
+void Solver::norm_estimate() {
+  Level& L = *lv_[0];
+  const int m = L.m, n = L.n;
+  double* x = L.bd.tU2;          // size >= n (n <= m for SVD; equal for SPD)
+  double* t = L.bd.tU;           // size >= m
+  double* y = spd_ ? L.bd.kap : L.bd.tV;   // size >= n
+  launch_splitmix_block(n, 0, 1, p_.seed ^ NORM_SEED_XOR, x, nullptr, st_);
+  DotArgs<double> da;
+  da.nrows = n; da.w = 1; da.a = x; da.z = x;
+  launch_dots<double>(da, partial_, r1_, st_);
+  launch_scale_cols<double>(n, 1, x, r1_, 0, st_);
+  for (int it = 0; it < 30; ++it) {
+    launch_spmm<double>(m, 1, L.A.rp, L.A.ci, L.A.v, x, t, 0.0, st_);
+    launch_spmm<double>(n, 1, L.At.rp, L.At.ci, L.At.v, t, y, 0.0, st_);
+    da = DotArgs<double>{};
+    da.nrows = n; da.w = 1; da.a = y; da.z = y;
+    launch_dots<double>(da, partial_, r1_, st_);
+    HIPCHK(hipMemcpyAsync(x, y, sizeof(double) * n, hipMemcpyDeviceToDevice, st_));
+    launch_scale_cols<double>(n, 1, x, r1_, 0, st_);
+  }
+  launch_spmm<double>(m, 1, L.A.rp, L.A.ci, L.A.v, x, t, 0.0, st_);
+  da = DotArgs<double>{};
+  da.nrows = m; da.w = 1; da.a = t; da.z = t;
+  launch_dots<double>(da, partial_, r1_, st_);
+  std::vector<double> r;
+  d2h(r, r1_, 1, st_);
+  anorm_ = std::sqrt(r[0]);
+  if (!(anorm_ > 0.0)) throw SolverError{ST_E_INVALID, "matrix norm estimate is zero"};
+}
+
+// ------------------------------------------------------------------------------------------------
+// Hierarchy structure (first multiplicative cycle only)
+// ------------------------------------------------------------------------------------------------
+HCsr Solver::strength_operator(Level& L, bool u_side, bool finest) {
+  // Eigenproblems measure strength on A itself (§5.2); SVD on A A^t (u) and A^t A (v) (§3.7).
+  HCsr N;
+  if (spd_) {
+    N = L.hA;
+    if (finest) N.v = A0_.v;
+    else d2h(N.v, L.A.v, L.A.nnz, st_);
+    return N;
+  }
+  const bool filt = finest && p_.strength_rule == 2 && p_.df_filter > 0.0;
+  HCsr Af = L.hA;
+  if (filt) {
+    // rows (terms) appearing in more than df_filter * n columns are left out of the strength graph
+    HCsr F;
+    F.m = Af.m; F.n = Af.n;
+    F.rp.assign(Af.m + 1, 0);
+    for (int i = 0; i < Af.m; ++i) {
+      int len = Af.rp[i + 1] - Af.rp[i];
+      bool keep = len <= p_.df_filter * Af.n;
+      if (keep) {
+        for (int k = Af.rp[i]; k < Af.rp[i + 1]; ++k) {
+          F.ci.push_back(Af.ci[k]);
+          F.v.push_back(A0_.v[k]);
+        }
+      }
+      F.rp[i + 1] = (int)F.ci.size();
+    }
+    Af = F;
+  }
+  HCsr AfT = transpose(Af, nullptr);
+  DCsr dAf, dAfT;
+  if (filt) {
+    dAf = upload(Af, true);
+    dAfT = upload(AfT, true);
+  } else {
+    dAf = L.A;
+    dAfT = L.At;
+  }
+  N = u_side ? symbolic_product(Af, AfT) : symbolic_product(AfT, Af);
+  // numeric on the device: entries are dot products of rows of A (u) or of A^t (v)
+  std::vector<int> rowC(N.nnz());
+  for (int i = 0; i < N.m; ++i)
+    for (int k = N.rp[i]; k < N.rp[i + 1]; ++k) rowC[k] = i;
+  int* d_row = ar_.alloc<int>(rowC.size());
+  int* d_col = ar_.alloc<int>(N.nnz());
+  double* d_val = ar_.alloc<double>(N.nnz());
+  h2d(d_row, rowC, st_);
+  h2d(d_col, N.ci, st_);
+  const DCsr& M = u_side ? dAf : dAfT;
+  launch_spgemm_dot(N.nnz(), d_row, d_col, M.rp, M.ci, M.v, M.rp, M.ci, M.v, d_val, st_);
+  d2h(N.v, d_val, N.nnz(), st_);
+  return N;
+}
+
+void Solver::build_side(Level& L, Side& S, const HCsr& N, int npts) {
+  (void)L;
+  std::vector<int> Sp, Si;
+  strength_sets(N, p_.theta, p_.strength_rule, p_.top_s, Sp, Si);
+  S.npts = npts;
+  S.is_c = rs_coarsen(Sp, Si, npts);
+  std::vector<int> ptr, fine_cols;
+  interp_pattern(Sp, Si, N, S.is_c, nt_ - 1, ptr, fine_cols, S.capped);
+  std::vector<int> cidx(npts, -1);
+  S.cpts.clear();
+  for (int i = 0; i < npts; ++i)
+    if (S.is_c[i]) { cidx[i] = (int)S.cpts.size(); S.cpts.push_back(i); }
+  S.nc = (int)S.cpts.size();
+  S.Ppat.m = npts; S.Ppat.n = S.nc;
+  S.Ppat.rp = ptr;
+  S.Ppat.ci.resize(fine_cols.size());
+  S.Ppat.v.assign(fine_cols.size(), 0.0);
+  std::vector<int> F;
+  S.qmax = 0;
+  for (int i = 0; i < npts; ++i) {
+    for (int k = ptr[i]; k < ptr[i + 1]; ++k) S.Ppat.ci[k] = cidx[fine_cols[k]];
+    if (S.is_c[i]) S.Ppat.v[ptr[i]] = 1.0;
+    else { F.push_back(i); S.qmax = std::max(S.qmax, ptr[i + 1] - ptr[i]); }
+  }
+  S.nF = (int)F.size();
+  S.Ptpat = transpose(S.Ppat, &S.perm);
+}
+
+// Decide whether level l is coarsened (true) or becomes the coarsest level (false).
+bool Solver::build_structure(int l) {
+  Level& L = *lv_[l];
+  if (size_of(L) <= p_.coarse_max || l + 1 >= p_.max_levels) return false;
+  HCsr Nu = strength_operator(L, true, l == 0);
+  Side su, sv;
+  build_side(L, su, Nu, L.m);
+  HCsr Nv;
+  if (!spd_) {
+    Nv = strength_operator(L, false, l == 0);
+    build_side(L, sv, Nv, L.n);
+  }
+  const int nc = spd_ ? su.nc : su.nc + sv.nc;
+  if (nc > p_.stall_ratio * size_of(L)) return false;
+  const int need = nb_ + nt_;
+  if (su.nc < need || (!spd_ && sv.nc < need)) return false;
+  // device copies
+  auto devside = [&](Side& S) {
+    S.P = upload(S.Ppat, true);
+    S.Pt = upload(S.Ptpat, false);
+    S.d_perm = ar_.alloc<int>(S.perm.size());
+    h2d(S.d_perm, S.perm, st_);
+    S.d_cpts = ar_.alloc<int>(S.nc);
+    h2d(S.d_cpts, S.cpts, st_);
+    std::vector<int> F;
+    for (int i = 0; i < S.npts; ++i)
+      if (!S.is_c[i]) F.push_back(i);
+    S.d_F = ar_.alloc<int>(F.size());
+    h2d(S.d_F, F, st_);
+    S.d_prp = S.P.rp;
+    std::vector<int> fc(S.Ppat.ci.size());
+    for (int i = 0; i < S.npts; ++i)
+      for (int k = S.Ppat.rp[i]; k < S.Ppat.rp[i + 1]; ++k) fc[k] = S.cpts[S.Ppat.ci[k]];
+    S.d_fc = ar_.alloc<int>(fc.size());
+    h2d(S.d_fc, fc, st_);
+    launch_perm_gather(S.Pt.nnz, S.d_perm, S.P.v, S.Pt.v, st_);
+  };
+  devside(su);
+  if (!spd_) devside(sv);
+  L.su = std::move(su);
+  if (!spd_) L.sv = std::move(sv);
+  rep_.capped[l] = L.su.capped + (spd_ ? 0 : L.sv.capped);
+  make_coarse_level(l);
+  return true;
+}
+
+// Symbolic Galerkin products (§3.1) and the coarse level's storage.
+void Solver::make_coarse_level(int l) {
+  Level& L = *lv_[l];
+  auto C = std::make_unique<Level>();
+  auto mkplan = [&](const HCsr& pat, const DCsr* Lm, const DCsr* Rt, double* out) {
+    Plan pl;
+    pl.nnz = pat.nnz();
+    std::vector<int> rowC(pl.nnz);
+    for (int i = 0; i < pat.m; ++i)
+      for (int k = pat.rp[i]; k < pat.rp[i + 1]; ++k) rowC[k] = i;
+    pl.rowC = ar_.alloc<int>(pl.nnz);
+    h2d(pl.rowC, rowC, st_);
+    pl.L = Lm; pl.Rt = Rt; pl.out = out;
+    return pl;
+  };
+  Side& su = L.su;
+  if (spd_) {
+    HCsr S1 = symbolic_product(su.Ptpat, L.hA);            // P^t A
+    HCsr Ac = symbolic_product(S1, su.Ppat);               // P^t A P
+    L.S1 = upload(S1, false);
+    L.S2 = L.S1;
+    L.S2.v = ar_.alloc<double>(L.S1.nnz);                  // P^t B on the same pattern
+    C->m = C->n = su.nc;
+    C->hA = Ac;
+    C->A = upload(Ac, false);
+    C->At = C->A;
+    C->B = C->A;
+    C->B.v = ar_.alloc<double>(C->A.nnz);
+    if (mixed_) C->B.vf = ar_.alloc<float>(C->A.nnz);
+    L.plans.clear();
+    L.plans.push_back(mkplan(S1, &su.Pt, &L.A, L.S1.v));   // rows of P^t . rows of A (= A^t)
+    L.plans.push_back(mkplan(S1, &su.Pt, &L.B, L.S2.v));   // rows of P^t . rows of B
+    // A_c, B_c: rows of S . rows of P^t (columns of P)
+    L.pAc = mkplan(Ac, &L.S1, &su.Pt, C->A.v);
+    L.pBc = mkplan(Ac, &L.S2, &su.Pt, C->B.v);
+    L.pAc.colC = C->A.ci; L.pBc.colC = C->A.ci;
+    L.plans[0].colC = L.S1.ci; L.plans[1].colC = L.S1.ci;
+  } else {
+    Side& sv = L.sv;
+    HCsr S1 = symbolic_product(su.Ptpat, L.hA);            // P^t A      (mc x n)
+    HCsr Ac = symbolic_product(S1, sv.Ppat);               // P^t A Q    (mc x nc)
+    HCsr S2 = symbolic_product(su.Ptpat, L.hB);            // P^t B      (mc x m)
+    HCsr Bc = symbolic_product(S2, su.Ppat);               // P^t B P
+    HCsr S3 = symbolic_product(sv.Ptpat, L.hC);            // Q^t C      (nc x n)
+    HCsr Cc = symbolic_product(S3, sv.Ppat);               // Q^t C Q
+    L.S1 = upload(S1, false);
+    L.S2 = upload(S2, false);
+    L.S3 = upload(S3, false);
+    C->m = su.nc; C->n = sv.nc;
+    C->hA = Ac;
+    C->hAt = transpose(Ac, &C->permAt);
+    C->hB = Bc; C->hC = Cc;
+    C->A = upload(Ac, false);
+    C->At = upload(C->hAt, false);
+    C->d_permAt = ar_.alloc<int>(C->permAt.size());
+    h2d(C->d_permAt, C->permAt, st_);
+    C->B = upload(Bc, false);
+    C->C = upload(Cc, false);
+    L.plans.clear();
+    L.plans.push_back(mkplan(S1, &su.Pt, &L.At, L.S1.v));  // (P^t A)_{I j} = P^t row I . A^t row j
+    L.plans.push_back(mkplan(S2, &su.Pt, &L.B, L.S2.v));   // B symmetric
+    L.plans.push_back(mkplan(S3, &sv.Pt, &L.C, L.S3.v));
+    L.plans[0].colC = L.S1.ci; L.plans[1].colC = L.S2.ci; L.plans[2].colC = L.S3.ci;
+    L.pAc = mkplan(Ac, &L.S1, &sv.Pt, C->A.v); L.pAc.colC = C->A.ci;
+    L.pBc = mkplan(Bc, &L.S2, &su.Pt, C->B.v); L.pBc.colC = C->B.ci;
+    L.pCc = mkplan(Cc, &L.S3, &sv.Pt, C->C.v); L.pCc.colC = C->C.ci;
+  }
+  rep_.rows[l + 1] = C->m;
+  rep_.cols[l + 1] = C->n;
+  rep_.nnz[l + 1] = C->hA.nnz();
+  alloc_level_buffers(*C);
+  colour(*C);
+  lv_.push_back(std::move(C));
+}
+
+// ------------------------------------------------------------------------------------------------
+// Relaxation (§3.4, §3.5, §5.3)
+// ------------------------------------------------------------------------------------------------
+void Solver::relax_tests(int l) {
+  Level& L = *lv_[l];
+  auto& b = L.bd;
+  const int mu = rows_u(L), mv = rows_v(L);
+  DotArgs<double> da;
+  for (int it = 0; it < p_.mu_t; ++it) {
+    if (!minimal_) {
+      if (spd_) {
+        // x_bar = x - w D_B^-1 (B x - A x),  x = x_bar / ||x_bar||_B
+        RowOpArgs<double> a;
+        a.nrows = mu; a.w = nt_;
+        a.Krp = L.A.rp; a.Kci = L.A.ci; a.Kv = L.A.v; a.z = b.Ut;
+        a.mmode = L.finest ? M_IDENT : M_SHARED; a.Mv = L.B.v; a.y = b.Ut;
+        a.x = b.Ut; a.D = L.ad.dinvB; a.cmode = C_JAC_TEST; a.omega = p_.omega_J; a.out = b.tU;
+        rowop(l, a, &L.A);
+        std::swap(b.Ut, b.tU);
+        da = DotArgs<double>{};
+        da.nrows = mu; da.w = nt_; da.a = b.Ut; da.z = b.Ut;
+        if (!L.finest) { da.Krp = L.A.rp; da.Kci = L.A.ci; da.Kv = L.B.v; }
+        launch_dots(da, partial_, r1_, st_);
+        launch_scale_cols<double>(mu, nt_, b.Ut, r1_, 0, st_);
+      } else {
+        // v_bar = v - w D_C^-1 (C v - A^t u), normalised in C; then u likewise with A v and B
+        RowOpArgs<double> a;
+        a.nrows = mv; a.w = nt_;
+        a.Krp = L.At.rp; a.Kci = L.At.ci; a.Kv = L.At.v; a.z = b.Ut;
+        a.mmode = L.finest ? M_IDENT : M_CSR; a.Mrp = L.C.rp; a.Mci = L.C.ci; a.Mv = L.C.v; a.y = b.Vt;
+        a.x = b.Vt; a.D = L.ad.dinvC; a.cmode = C_JAC_TEST; a.omega = p_.omega_J; a.out = b.tV;
+        rowop(l, a, &L.At);
+        std::swap(b.Vt, b.tV);
+        da = DotArgs<double>{};
+        da.nrows = mv; da.w = nt_; da.a = b.Vt; da.z = b.Vt;
+        if (!L.finest) { da.Krp = L.C.rp; da.Kci = L.C.ci; da.Kv = L.C.v; }
+        launch_dots(da, partial_, r1_, st_);
+        launch_scale_cols<double>(mv, nt_, b.Vt, r1_, 0, st_);
+        RowOpArgs<double> c;
+        c.nrows = mu; c.w = nt_;
+        c.Krp = L.A.rp; c.Kci = L.A.ci; c.Kv = L.A.v; c.z = b.Vt;
+        c.mmode = L.finest ? M_IDENT : M_CSR; c.Mrp = L.B.rp; c.Mci = L.B.ci; c.Mv = L.B.v; c.y = b.Ut;
+        c.x = b.Ut; c.D = L.ad.dinvB; c.cmode = C_JAC_TEST; c.omega = p_.omega_J; c.out = b.tU;
+        rowop(l, c, &L.A);
+        std::swap(b.Ut, b.tU);
+        da = DotArgs<double>{};
+        da.nrows = mu; da.w = nt_; da.a = b.Ut; da.z = b.Ut;
+        if (!L.finest) { da.Krp = L.B.rp; da.Kci = L.B.ci; da.Kv = L.B.v; }
+        launch_dots(da, partial_, r1_, st_);
+        launch_scale_cols<double>(mu, nt_, b.Ut, r1_, 0, st_);
+      }
+    } else {
+      // Kaczmarz on A v = 0 (rows of A, updates v), then A^t u = 0; or A x = 0; then normalise
+      auto sweep = [&](const DCsr& M, const int* rows, const std::vector<int>& cptr, const double* rn, double* x,
+                       const std::vector<long>& cnnz) {
+        for (size_t c = 0; c + 1 < cptr.size(); ++c) {
+          KaczArgs<double> k;
+          k.nrows = cptr[c + 1] - cptr[c]; k.rows = rows + cptr[c]; k.w = nt_;
+          k.rp = M.rp; k.ci = M.ci; k.av = M.v; k.rn_aa = rn; k.x = x;
+          kacz(l, k, cnnz[c]);
+        }
+      };
+      if (spd_) {
+        sweep(L.A, L.kA_rows, L.kA_cptr, L.ad.rnA, b.Ut, L.kA_cnnz);
+        da = DotArgs<double>{};
+        da.nrows = mu; da.w = nt_; da.a = b.Ut; da.z = b.Ut;
+        if (!L.finest) { da.Krp = L.A.rp; da.Kci = L.A.ci; da.Kv = L.B.v; }
+        launch_dots(da, partial_, r1_, st_);
+        launch_scale_cols<double>(mu, nt_, b.Ut, r1_, 0, st_);
+      } else {
+        sweep(L.A, L.kA_rows, L.kA_cptr, L.ad.rnA, b.Vt, L.kA_cnnz);
+        da = DotArgs<double>{};
+        da.nrows = mv; da.w = nt_; da.a = b.Vt; da.z = b.Vt;
+        if (!L.finest) { da.Krp = L.C.rp; da.Kci = L.C.ci; da.Kv = L.C.v; }
+        launch_dots(da, partial_, r1_, st_);
+        launch_scale_cols<double>(mv, nt_, b.Vt, r1_, 0, st_);
+        sweep(L.At, L.kAt_rows, L.kAt_cptr, L.ad.rnAt, b.Ut, L.kAt_cnnz);
+        da = DotArgs<double>{};
+        da.nrows = mu; da.w = nt_; da.a = b.Ut; da.z = b.Ut;
+        if (!L.finest) { da.Krp = L.B.rp; da.Kci = L.B.ci; da.Kv = L.B.v; }
+        launch_dots(da, partial_, r1_, st_);
+        launch_scale_cols<double>(mu, nt_, b.Ut, r1_, 0, st_);
+      }
+    }
+  }
+}
+
+// One boot relaxation (no sigma update) on level l with right-hand sides kap, tau (null: zero).
+template <class T>
+void Solver::boot_relax(int l, const T* kap, const T* tau, const double* sig) {
+  Level& L = *lv_[l];
+  Blocks<T>& b = blocks<T>(L);
+  Aux<T>& x = aux<T>(L);
+  const int mu = rows_u(L), mv = rows_v(L);
+  if (!minimal_) {
+    if (spd_) {
+      // x <- x - w D_B^-1 (B x - (A x - kappa)/lambda)
+      RowOpArgs<T> a;
+      a.nrows = mu; a.w = nb_;
+      a.Krp = L.A.rp; a.Kci = L.A.ci; a.Kv = vals<T>(L.A); a.z = b.Ub;
+      a.mmode = L.finest ? M_IDENT : M_SHARED; a.Mv = vals<T>(L.B); a.y = b.Ub;
+      a.x = b.Ub; a.D = x.dinvB; a.kap = kap; a.sig = sig; a.cmode = C_JAC_BOOT; a.omega = p_.omega_J;
+      a.out = b.tU;
+      rowop(l, a, &L.A);
+      HIPCHK(hipMemcpyAsync(b.Ub, b.tU, sizeof(T) * (size_t)mu * nb_, hipMemcpyDeviceToDevice, st_));
+    } else {
+      // u <- u - w D_B^-1 (B u - (A v - kappa)/sigma); then v <- v - w D_C^-1 (C v - (A^t u - tau)/sigma)
+      RowOpArgs<T> a;
+      a.nrows = mu; a.w = nb_;
+      a.Krp = L.A.rp; a.Kci = L.A.ci; a.Kv = vals<T>(L.A); a.z = b.Vb;
+      a.mmode = L.finest ? M_IDENT : M_CSR; a.Mrp = L.B.rp; a.Mci = L.B.ci; a.Mv = vals<T>(L.B); a.y = b.Ub;
+      a.x = b.Ub; a.D = x.dinvB; a.kap = kap; a.sig = sig; a.cmode = C_JAC_BOOT; a.omega = p_.omega_J;
+      a.out = b.tU;
+      rowop(l, a, &L.A);
+      HIPCHK(hipMemcpyAsync(b.Ub, b.tU, sizeof(T) * (size_t)mu * nb_, hipMemcpyDeviceToDevice, st_));
+      RowOpArgs<T> c;
+      c.nrows = mv; c.w = nb_;
+      c.Krp = L.At.rp; c.Kci = L.At.ci; c.Kv = vals<T>(L.At); c.z = b.Ub;
+      c.mmode = L.finest ? M_IDENT : M_CSR; c.Mrp = L.C.rp; c.Mci = L.C.ci; c.Mv = vals<T>(L.C); c.y = b.Vb;
+      c.x = b.Vb; c.D = x.dinvC; c.kap = tau; c.sig = sig; c.cmode = C_JAC_BOOT; c.omega = p_.omega_J;
+      c.out = b.tV;
+      rowop(l, c, &L.At);
+      HIPCHK(hipMemcpyAsync(b.Vb, b.tV, sizeof(T) * (size_t)mv * nb_, hipMemcpyDeviceToDevice, st_));
+    }
+  } else {
+    if (spd_) {
+      // Kaczmarz on (A - lambda_j B) x = kappa
+      for (size_t c = 0; c + 1 < L.kA_cptr.size(); ++c) {
+        KaczArgs<T> k;
+        k.nrows = L.kA_cptr[c + 1] - L.kA_cptr[c]; k.rows = L.kA_rows + L.kA_cptr[c]; k.w = nb_;
+        k.rp = L.A.rp; k.ci = L.A.ci; k.av = vals<T>(L.A);
+        k.bv = L.finest ? nullptr : vals<T>(L.B); k.lam = sig;
+        k.rn_aa = x.rnA; k.rn_ab = x.rnAab; k.rn_bb = x.rnAbb;
+        k.kap = kap; k.x = b.Ub;
+        kacz(l, k, L.kA_cnnz[c]);
+      }
+    } else {
+      // v from A v = sigma B u + kappa (rows of A), then u from A^t u = sigma C v + tau (rows of A^t)
+      for (size_t c = 0; c + 1 < L.kA_cptr.size(); ++c) {
+        KaczArgs<T> k;
+        k.nrows = L.kA_cptr[c + 1] - L.kA_cptr[c]; k.rows = L.kA_rows + L.kA_cptr[c]; k.w = nb_;
+        k.rp = L.A.rp; k.ci = L.A.ci; k.av = vals<T>(L.A); k.rn_aa = x.rnA;
+        k.rmode = L.finest ? M_IDENT : M_CSR; k.Mrp = L.B.rp; k.Mci = L.B.ci; k.Mv = vals<T>(L.B);
+        k.y = b.Ub; k.rsig = sig; k.kap = kap; k.x = b.Vb;
+        kacz(l, k, L.kA_cnnz[c]);
+      }
+      for (size_t c = 0; c + 1 < L.kAt_cptr.size(); ++c) {
+        KaczArgs<T> k;
+        k.nrows = L.kAt_cptr[c + 1] - L.kAt_cptr[c]; k.rows = L.kAt_rows + L.kAt_cptr[c]; k.w = nb_;
+        k.rp = L.At.rp; k.ci = L.At.ci; k.av = vals<T>(L.At); k.rn_aa = x.rnAt;
+        k.rmode = L.finest ? M_IDENT : M_CSR; k.Mrp = L.C.rp; k.Mci = L.C.ci; k.Mv = vals<T>(L.C);
+        k.y = b.Vb; k.rsig = sig; k.kap = tau; k.x = b.Ub;
+        kacz(l, k, L.kAt_cnnz[c]);
+      }
+    }
+  }
+}
+
+// Multiplicative-phase boot relaxation: mu_b steps, each followed by the Rayleigh quotient (3.31)
+// and the sign check of §5.3.
+void Solver::boot_relax_rq(int l) {
+  Level& L = *lv_[l];
+  auto& b = L.bd;
+  const int mu = rows_u(L), mv = rows_v(L);
+  for (int it = 0; it < p_.mu_b; ++it) {
+    boot_relax<double>(l, nullptr, nullptr, sig_);
+    DotArgs<double> d1, d2, d3;
+    if (spd_) {
+      d1.nrows = mu; d1.w = nb_; d1.a = b.Ub; d1.Krp = L.A.rp; d1.Kci = L.A.ci; d1.Kv = L.A.v; d1.z = b.Ub;
+      dots(l, d1, &L.A, r1_);
+      d2.nrows = mu; d2.w = nb_; d2.a = b.Ub; d2.z = b.Ub;
+      if (!L.finest) { d2.Krp = L.A.rp; d2.Kci = L.A.ci; d2.Kv = L.B.v; }
+      launch_dots(d2, partial_, r2_, st_);
+      launch_rq_update(nb_, r1_, r2_, nullptr, sig_, flip_, st_);
+    } else {
+      d1.nrows = mu; d1.w = nb_; d1.a = b.Ub; d1.Krp = L.A.rp; d1.Kci = L.A.ci; d1.Kv = L.A.v; d1.z = b.Vb;
+      dots(l, d1, &L.A, r1_);
+      d2.nrows = mu; d2.w = nb_; d2.a = b.Ub; d2.z = b.Ub;
+      if (!L.finest) { d2.Krp = L.B.rp; d2.Kci = L.B.ci; d2.Kv = L.B.v; }
+      launch_dots(d2, partial_, r2_, st_);
+      d3.nrows = mv; d3.w = nb_; d3.a = b.Vb; d3.z = b.Vb;
+      if (!L.finest) { d3.Krp = L.C.rp; d3.Kci = L.C.ci; d3.Kv = L.C.v; }
+      launch_dots(d3, partial_, r3_, st_);
+      launch_rq_update(nb_, r1_, r2_, r3_, sig_, flip_, st_);
+    }
+    launch_scale_cols<double>(mu, nb_, b.Ub, flip_, 1, st_);
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// LS interpolation (§3.8), Galerkin operators (§3.1), injection (§3.3)
+// ------------------------------------------------------------------------------------------------
+void Solver::fit_interpolation(int l, int cycle) {
+  Level& L = *lv_[l];
+  auto& b = L.bd;
+  const int mu = rows_u(L), mv = rows_v(L);
+  const bool boots = cycle >= 2;
+  const int nf = nt_ + (boots ? nb_ : 0);
+  // Rayleigh-quotient weights of the fitted pairs (test pairs, then boot pairs)
+  auto rq_parts = [&](const double* U, const double* V, int w, int off) {
+    DotArgs<double> d1, d2, d3;
+    if (spd_) {
+      d1.nrows = mu; d1.w = w; d1.a = U; d1.Krp = L.A.rp; d1.Kci = L.A.ci; d1.Kv = L.A.v; d1.z = U;
+      d2.nrows = mu; d2.w = w; d2.a = U; d2.z = U;
+      if (!L.finest) { d2.Krp = L.A.rp; d2.Kci = L.A.ci; d2.Kv = L.B.v; }
+      launch_dots(d1, partial_, r1_ + off, st_);
+      launch_dots(d2, partial_, r2_ + off, st_);
+    } else {
+      d1.nrows = mu; d1.w = w; d1.a = U; d1.Krp = L.A.rp; d1.Kci = L.A.ci; d1.Kv = L.A.v; d1.z = V;
+      d2.nrows = mu; d2.w = w; d2.a = U; d2.z = U;
+      if (!L.finest) { d2.Krp = L.B.rp; d2.Kci = L.B.ci; d2.Kv = L.B.v; }
+      d3.nrows = mv; d3.w = w; d3.a = V; d3.z = V;
+      if (!L.finest) { d3.Krp = L.C.rp; d3.Kci = L.C.ci; d3.Kv = L.C.v; }
+      launch_dots(d1, partial_, r1_ + off, st_);
+      launch_dots(d2, partial_, r2_ + off, st_);
+      launch_dots(d3, partial_, r3_ + off, st_);
+    }
+  };
+  rq_parts(b.Ut, b.Vt, nt_, 0);
+  if (boots) rq_parts(b.Ub, b.Vb, nb_, nt_);
+  launch_rq_weights(nf, r1_, r2_, spd_ ? nullptr : r3_, minimal_ ? 1 : 0, 1e-12 * anorm_, wts_, st_);
+  // values fitted at the F-points: the vectors themselves, or (minimal) one Jacobi step on N z = 0
+  auto smooth = [&](bool u_side, const double* X, int w, double* tmp, double* out) {
+    RowOpArgs<double> a;
+    a.w = w; a.x = X; a.cmode = C_SMOOTH; a.omega = p_.omega_J; a.out = out;
+    if (spd_) {
+      a.nrows = mu; a.Krp = L.A.rp; a.Kci = L.A.ci; a.Kv = L.A.v; a.z = X; a.D = L.smU;
+    } else if (u_side) {
+      launch_spmm<double>(L.n, w, L.At.rp, L.At.ci, L.At.v, X, tmp, 0.0, st_);   // A^t u
+      a.nrows = mu; a.Krp = L.A.rp; a.Kci = L.A.ci; a.Kv = L.A.v; a.z = tmp; a.D = L.smU;
+    } else {
+      launch_spmm<double>(L.m, w, L.A.rp, L.A.ci, L.A.v, X, tmp, 0.0, st_);      // A v
+      a.nrows = mv; a.Krp = L.At.rp; a.Kci = L.At.ci; a.Kv = L.At.v; a.z = tmp; a.D = L.smV;
+    }
+    launch_rowop(a, st_);
+  };
+  auto fit_side = [&](Side& S, const double* Tb, const double* Bb, double* tmp_other, double* sm1, double* sm2,
+                      bool u_side) {
+    const double* B1 = Tb;
+    const double* B2 = Bb;
+    if (minimal_) {
+      smooth(u_side, Tb, nt_, tmp_other, sm1);
+      B1 = sm1;
+      if (boots) { smooth(u_side, Bb, nb_, tmp_other, sm2); B2 = sm2; }
+    }
+    launch_ls_fit(S.nF, S.d_F, S.d_prp, S.d_fc, nt_, Tb, boots ? nb_ : 0, Bb, B1, B2, wts_, S.P.v, S.qmax, st_);
+    launch_perm_gather(S.Pt.nnz, S.d_perm, S.P.v, S.Pt.v, st_);
+  };
+  if (spd_) {
+    fit_side(L.su, b.Ut, b.Ub, nullptr, b.tU, b.tU2, true);
+  } else {
+    fit_side(L.su, b.Ut, b.Ub, b.tV, b.tU, b.tU2, true);
+    fit_side(L.sv, b.Vt, b.Vb, b.tU, b.tV, b.tV2, false);
+  }
+}
+
+void Solver::galerkin(int l) {
+  Level& L = *lv_[l];
+  Level& C = *lv_[l + 1];
+  for (auto& pl : L.plans) prof(3, plan_bytes(pl), [&] { pl.run(st_); });
+  prof(3, plan_bytes(L.pAc), [&] { L.pAc.run(st_); });
+  prof(3, plan_bytes(L.pBc), [&] { L.pBc.run(st_); });
+  if (!spd_) {
+    prof(3, plan_bytes(L.pCc), [&] { L.pCc.run(st_); });
+    launch_perm_gather(C.At.nnz, C.d_permAt, C.A.v, C.At.v, st_);
+  }
+  refresh_level_aux(C);
+}
+
+void Solver::inject(int l, int cycle) {
+  Level& L = *lv_[l];
+  Level& C = *lv_[l + 1];
+  launch_gather_rows<double>(L.su.nc, nt_, L.su.d_cpts, L.bd.Ut, C.bd.Ut, st_);
+  if (!spd_) launch_gather_rows<double>(L.sv.nc, nt_, L.sv.d_cpts, L.bd.Vt, C.bd.Vt, st_);
+  if (cycle >= 2) {
+    launch_gather_rows<double>(L.su.nc, nb_, L.su.d_cpts, L.bd.Ub, C.bd.Ub, st_);
+    if (!spd_) launch_gather_rows<double>(L.sv.nc, nb_, L.sv.d_cpts, L.bd.Vb, C.bd.Vb, st_);
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Coarsest level (§3.6) and the dense additive solve (§4.2)
+// ------------------------------------------------------------------------------------------------
+void Solver::coarsest_mult() {
+  Level& L = *lv_.back();
+  const int m = L.m, n = L.n;
+  if (spd_) {
+    launch_fill(dA_, (size_t)m * m, 0.0, st_);
+    launch_fill(dB_, (size_t)m * m, 0.0, st_);
+    launch_csr_to_dense(m, L.A.rp, L.A.ci, L.A.v, dA_, m, 0, 0, false, st_);
+    launch_csr_to_dense(m, L.A.rp, L.A.ci, L.B.v, dB_, m, 0, 0, false, st_);
+    launch_coarse_gsvd(1, minimal_, m, m, nb_, dA_, dB_, nullptr, dwork_, sig_, L.bd.Ub, nullptr, status_, st_);
+  } else {
+    launch_fill(dA_, (size_t)m * n, 0.0, st_);
+    launch_fill(dB_, (size_t)m * m, 0.0, st_);
+    launch_fill(dC_, (size_t)n * n, 0.0, st_);
+    launch_csr_to_dense(m, L.A.rp, L.A.ci, L.A.v, dA_, n, 0, 0, false, st_);
+    launch_csr_to_dense(m, L.B.rp, L.B.ci, L.B.v, dB_, m, 0, 0, false, st_);
+    launch_csr_to_dense(n, L.C.rp, L.C.ci, L.C.v, dC_, n, 0, 0, false, st_);
+    launch_coarse_gsvd(0, minimal_, m, n, nb_, dA_, dB_, dC_, dwork_, sig_, L.bd.Ub, L.bd.Vb, status_, st_);
+  }
+}
+
+// Dense X = [[0, A], [A^t, 0]] and Y = diag(B, C) (SVD) or A and B (eigen) of the coarsest level.
+void Solver::dense_coarsest(double* X, double* Y) {
+  Level& L = *lv_.back();
+  const int N = NL_;
+  launch_fill(X, (size_t)N * N, 0.0, st_);
+  launch_fill(Y, (size_t)N * N, 0.0, st_);
+  if (spd_) {
+    launch_csr_to_dense(L.m, L.A.rp, L.A.ci, L.A.v, X, N, 0, 0, false, st_);
+    launch_csr_to_dense(L.m, L.A.rp, L.A.ci, L.B.v, Y, N, 0, 0, false, st_);
+  } else {
+    launch_csr_to_dense(L.m, L.A.rp, L.A.ci, L.A.v, X, N, 0, L.m, false, st_);
+    launch_csr_to_dense(L.m, L.A.rp, L.A.ci, L.A.v, X, N, L.m, 0, true, st_);
+    launch_csr_to_dense(L.m, L.B.rp, L.B.ci, L.B.v, Y, N, 0, 0, false, st_);
+    launch_csr_to_dense(L.n, L.C.rp, L.C.ci, L.C.v, Y, N, L.m, L.m, false, st_);
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Multiplicative cycle (§3.3)
+// ------------------------------------------------------------------------------------------------
+void Solver::mult_cycle(int c) {
+  int l = 0;
+  while (true) {
+    if (c == 1) {
+      if (!build_structure(l)) break;
+    } else if (l == (int)lv_.size() - 1) {
+      break;
+    }
+    relax_tests(l);
+    if (c >= 2) boot_relax_rq(l);
+    fit_interpolation(l, c);
+    galerkin(l);
+    inject(l, c);
+    ++l;
+    lastcheck();
+  }
+  if (c == 1) {
+    // the coarsest level is now known: dense workspaces
+    Level& L = *lv_.back();
+    const int m = L.m, n = L.n;
+    NL_ = spd_ ? m : m + n;
+    if (NL_ > 1024) throw SolverError{ST_E_NUMERIC, "coarsest level larger than 1024 (coarsening stalled)"};
+    if ((spd_ ? m : std::min(m, n)) < nb_) throw SolverError{ST_E_NUMERIC, "coarsest level smaller than n_b"};
+    const size_t mx = std::max(m, n);
+    dA_ = ar_.alloc<double>((size_t)m * std::max(m, n));
+    dB_ = ar_.alloc<double>((size_t)m * m);
+    dC_ = ar_.alloc<double>((size_t)n * n);
+    size_t wk = std::max<size_t>(3 * mx * mx + 2 * (size_t)m * n + 64 * mx + mx, (size_t)nb_ * 2 * NL_ * NL_);
+    wk = std::max(wk, (size_t)2 * NL_ * NL_);
+    dwork_ = ar_.alloc<double>(wk);
+    dX_ = ar_.alloc<double>((size_t)NL_ * NL_);
+    dY_ = ar_.alloc<double>((size_t)NL_ * NL_);
+    mu_ = ar_.alloc<double>(NL_);
+    Zp_ = ar_.alloc<double>((size_t)NL_ * NL_);
+    rep_.levels = (int)lv_.size();
+  }
+  coarsest_mult();
+  for (int k = (int)lv_.size() - 2; k >= 0; --k) {
+    Level& L = *lv_[k];
+    Level& C = *lv_[k + 1];
+    launch_spmm<double>(L.su.npts, nb_, L.su.P.rp, L.su.P.ci, L.su.P.v, C.bd.Ub, L.bd.Ub, 0.0, st_);
+    if (!spd_) launch_spmm<double>(L.sv.npts, nb_, L.sv.P.rp, L.sv.P.ci, L.sv.P.v, C.bd.Vb, L.bd.Vb, 0.0, st_);
+    boot_relax_rq(k);
+  }
+  if (p_.ritz_in_mult) ritz();
+  lastcheck();
+}
+
+// ------------------------------------------------------------------------------------------------
+// Additive V-cycle (§4.1-4.2), all n_b columns at once with sigma_j fixed.  rhsU / rhsV: finest
+// right-hand sides (null: zero).  On return the finest level's Ub/Vb hold the new iterate (or, in
+// the refinement form, the correction).
+// ------------------------------------------------------------------------------------------------
+template <class T>
+void Solver::additive_vcycle(const double* sig, T* rhsU, T* rhsV) {
+  const int nl = (int)lv_.size();
+  for (int l = 0; l + 1 < nl; ++l) {
+    Level& L = *lv_[l];
+    Level& C = *lv_[l + 1];
+    Blocks<T>& b = blocks<T>(L);
+    Blocks<T>& cb = blocks<T>(C);
+    const T* kap = l == 0 ? rhsU : b.kap;
+    const T* tau = l == 0 ? rhsV : b.tau;
+    for (int it = 0; it < p_.mu_b; ++it) boot_relax<T>(l, kap, tau, sig);
+    // residuals r = kappa - (A v - sigma B u), s = tau - (A^t u - sigma C v), then restriction
+    const int mu = rows_u(L), mv = rows_v(L);
+    RowOpArgs<T> a;
+    a.nrows = mu; a.w = nb_; a.Krp = L.A.rp; a.Kci = L.A.ci; a.Kv = vals<T>(L.A);
+    a.z = spd_ ? b.Ub : b.Vb;
+    if (spd_) { a.mmode = L.finest ? M_IDENT : M_SHARED; a.Mv = vals<T>(L.B); }
+    else { a.mmode = L.finest ? M_IDENT : M_CSR; a.Mrp = L.B.rp; a.Mci = L.B.ci; a.Mv = vals<T>(L.B); }
+    a.y = b.Ub; a.kap = kap; a.sig = sig; a.cmode = C_RESID; a.out = b.tU;
+    rowop(l, a, &L.A);
+    spmm<T>(l, L.su.Pt, vals<T>(L.su.Pt), nb_, b.tU, cb.kap, 0.0);
+    if (!spd_) {
+      RowOpArgs<T> s;
+      s.nrows = mv; s.w = nb_; s.Krp = L.At.rp; s.Kci = L.At.ci; s.Kv = vals<T>(L.At); s.z = b.Ub;
+      s.mmode = L.finest ? M_IDENT : M_CSR; s.Mrp = L.C.rp; s.Mci = L.C.ci; s.Mv = vals<T>(L.C);
+      s.y = b.Vb; s.kap = tau; s.sig = sig; s.cmode = C_RESID; s.out = b.tV;
+      rowop(l, s, &L.At);
+      spmm<T>(l, L.sv.Pt, vals<T>(L.sv.Pt), nb_, b.tV, cb.tau, 0.0);
+    }
+    if constexpr (std::is_same<T, double>::value) {
+      launch_fill(cb.Ub, (size_t)(rows_u(C) + (spd_ ? 0 : rows_v(C))) * nb_, 0.0, st_);
+    } else {
+      launch_fillf(cb.Ub, (size_t)(rows_u(C) + (spd_ ? 0 : rows_v(C))) * nb_, 0.0f, st_);
+    }
+  }
+  // coarsest: [u; v] = pinv(X - sigma_j Y) [kappa; tau] (FP64)
+  {
+    Level& L = *lv_.back();
+    Blocks<T>& b = blocks<T>(L);
+    const size_t n = (size_t)NL_ * nb_;
+    double* rhs = L.bd.kap;
+    double* sol = L.bd.Ub;
+    T* rk = nl == 1 ? rhsU : b.kap;
+    if constexpr (std::is_same<T, float>::value) {
+      launch_copy_cast_fd(rk, L.bd.kap, n, st_);
+    } else {
+      if (rk != L.bd.kap) HIPCHK(hipMemcpyAsync(rhs, rk, n * sizeof(double), hipMemcpyDeviceToDevice, st_));
+    }
+    if (p_.coarse_pinv == 0) prof(4, 0.0, [&] { launch_pinv_solve(NL_, nb_, dX_, dY_, sig, rhs, sol, dwork_, status_, st_); });
+    else prof(4, 0.0, [&] { launch_pencil_solve(NL_, nb_, mu_, Zp_, sig, rhs, sol, st_); });
+    if constexpr (std::is_same<T, float>::value) launch_copy_cast_df(sol, b.Ub, n, st_);
+  }
+  for (int l = nl - 2; l >= 0; --l) {
+    Level& L = *lv_[l];
+    Level& C = *lv_[l + 1];
+    Blocks<T>& b = blocks<T>(L);
+    Blocks<T>& cb = blocks<T>(C);
+    spmm<T>(l, L.su.P, vals<T>(L.su.P), nb_, cb.Ub, b.Ub, 1.0);
+    if (!spd_) spmm<T>(l, L.sv.P, vals<T>(L.sv.P), nb_, cb.Vb, b.Vb, 1.0);
+    const T* kap = l == 0 ? rhsU : b.kap;
+    const T* tau = l == 0 ? rhsV : b.tau;
+    for (int it = 0; it < p_.mu_b; ++it) boot_relax<T>(l, kap, tau, sig);
+  }
+}
+
+void Solver::additive_iteration() {
+  if (!mixed_) {
+    additive_vcycle<double>(sig_, nullptr, nullptr);
+    return;
+  }
+  // Refinement form: FP64 residual of the current iterate, FP32 V-cycle on the error equation
+  // with zero initial correction, FP64 update.  For fixed sigma every relaxation is affine, so in
+  // exact arithmetic this equals the additive V-cycle applied to the iterate.
+  Level& L = *lv_[0];
+  const int mu = rows_u(L), mv = rows_v(L);
+  RowOpArgs<double> a;
+  a.nrows = mu; a.w = nb_; a.Krp = L.A.rp; a.Kci = L.A.ci; a.Kv = L.A.v; a.z = spd_ ? L.bd.Ub : L.bd.Vb;
+  a.mmode = M_IDENT; a.y = L.bd.Ub; a.sig = sig_; a.cmode = C_RESID; a.out = L.bd.tU;
+  rowop(0, a, &L.A);
+  launch_copy_cast_df(L.bd.tU, L.bf.kap, (size_t)mu * nb_, st_);
+  if (!spd_) {
+    RowOpArgs<double> s;
+    s.nrows = mv; s.w = nb_; s.Krp = L.At.rp; s.Kci = L.At.ci; s.Kv = L.At.v; s.z = L.bd.Ub;
+    s.mmode = M_IDENT; s.y = L.bd.Vb; s.sig = sig_; s.cmode = C_RESID; s.out = L.bd.tV;
+    rowop(0, s, &L.At);
+    launch_copy_cast_df(L.bd.tV, L.bf.tau, (size_t)mv * nb_, st_);
+  }
+  launch_fillf(L.bf.Ub, (size_t)(mu + (spd_ ? 0 : mv)) * nb_, 0.0f, st_);
+  additive_vcycle<float>(sig_, L.bf.kap, spd_ ? nullptr : L.bf.tau);
+  launch_axpy_fd(L.bf.Ub, L.bd.Ub, (size_t)mu * nb_, st_);
+  if (!spd_) launch_axpy_fd(L.bf.Vb, L.bd.Vb, (size_t)mv * nb_, st_);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Ritz projection on the finest level (§4.3): Cholesky-QR2 of the boot blocks (MFMA Gram), the
+// projected n_b x n_b problem, rotation of the bases.
+// ------------------------------------------------------------------------------------------------
+void Solver::cholqr2(double* X, int rows, double* tmp, double* out) {
+  prof(2, 8.0 * rows * nb_, [&] { launch_gram(rows, nb_, X, X, partial_, gram_, st_); });
+  launch_chol_inv_upper(nb_, gram_, small1_, status_, st_);
+  launch_rotate<double>(rows, nb_, nb_, X, small1_, tmp, st_);
+  prof(2, 8.0 * rows * nb_, [&] { launch_gram(rows, nb_, tmp, tmp, partial_, gram_, st_); });
+  launch_chol_inv_upper(nb_, gram_, small1_, status_, st_);
+  launch_rotate<double>(rows, nb_, nb_, tmp, small1_, out, st_);
+}
+
+void Solver::ritz() {
+  Level& L = *lv_[0];
+  auto& b = L.bd;
+  const int mu = rows_u(L), mv = rows_v(L);
+  cholqr2(b.Ub, mu, b.tU, b.tU2);                 // U_hat in tU2
+  if (!spd_) {
+    cholqr2(b.Vb, mv, b.tV, b.tV2);               // V_hat in tV2
+    spmm<double>(0, L.A, L.A.v, nb_, b.tV2, b.tU, 0.0);   // W = A V_hat
+    prof(2, 16.0 * mu * nb_, [&] { launch_gram(mu, nb_, b.tU2, b.tU, partial_, gram_, st_); });                      // M = U_hat^t W
+    launch_small_ritz(nb_, 0, minimal_, gram_, small1_, small2_, sig_, small_work_, status_, st_);
+    launch_rotate<double>(mu, nb_, nb_, b.tU2, small1_, b.Ub, st_);
+    launch_rotate<double>(mv, nb_, nb_, b.tV2, small2_, b.Vb, st_);
+  } else {
+    spmm<double>(0, L.A, L.A.v, nb_, b.tU2, b.tU, 0.0);   // A X_hat
+    prof(2, 16.0 * mu * nb_, [&] { launch_gram(mu, nb_, b.tU2, b.tU, partial_, gram_, st_); });
+    launch_small_ritz(nb_, 1, minimal_, gram_, small1_, small2_, sig_, small_work_, status_, st_);
+    launch_rotate<double>(mu, nb_, nb_, b.tU2, small1_, b.Ub, st_);
+  }
+}
+
+// rho_j = max(||A v_j - s_j u_j||, ||A^t u_j - s_j v_j||) / ||A||_est  (unit vectors after Ritz)
+void Solver::residuals(std::vector<double>& rho) {
+  Level& L = *lv_[0];
+  auto& b = L.bd;
+  DotArgs<double> d1, d2;
+  d1.nrows = L.m; d1.w = nb_; d1.Krp = L.A.rp; d1.Kci = L.A.ci; d1.Kv = L.A.v;
+  d1.z = spd_ ? b.Ub : b.Vb; d1.y = b.Ub; d1.sig = sig_;
+  dots(0, d1, &L.A, r1_);
+  if (!spd_) {
+    d2.nrows = L.n; d2.w = nb_; d2.Krp = L.At.rp; d2.Kci = L.At.ci; d2.Kv = L.At.v;
+    d2.z = b.Ub; d2.y = b.Vb; d2.sig = sig_;
+    dots(0, d2, &L.At, r2_);
+  }
+  std::vector<double> h1, h2;
+  d2h(h1, r1_, nb_, st_);
+  if (!spd_) d2h(h2, r2_, nb_, st_);
+  rho.resize(nb_);
+  for (int j = 0; j < nb_; ++j) {
+    double r = std::sqrt(std::max(h1[j], 0.0));
+    if (!spd_) r = std::max(r, std::sqrt(std::max(h2[j], 0.0)));
+    rho[j] = r / anorm_;
+    if (!std::isfinite(rho[j])) throw SolverError{ST_E_NUMERIC, "non-finite residual"};
+  }
+}
+
+void Solver::check_status() {
+  std::vector<int> st;
+  d2h(st, status_, 1, st_);
+  if (st[0] != 0) throw SolverError{ST_E_NUMERIC, "dense factorisation breakdown on the device"};
+}
+
+// ------------------------------------------------------------------------------------------------
+void Solver::run(const double* init_tests, SolveOutput& out) {
+  using clk = std::chrono::steady_clock;
+  auto t0 = clk::now();
+  std::memset(&rep_, 0, sizeof(rep_));
+  if (nb_ > 16 || nt_ > 16) throw SolverError{ST_E_INVALID, "n_b and n_t must be at most 16"};
+  sig_ = ar_.alloc<double>(64);
+  flip_ = ar_.alloc<double>(64);
+  partial_ = ar_.alloc<double>((size_t)std::max(1024 * 32, 512 * 256));
+  r1_ = ar_.alloc<double>(64); r2_ = ar_.alloc<double>(64); r3_ = ar_.alloc<double>(64);
+  wts_ = ar_.alloc<double>(64);
+  gram_ = ar_.alloc<double>(256);
+  small1_ = ar_.alloc<double>(256);
+  small2_ = ar_.alloc<double>(256);
+  small_work_ = ar_.alloc<double>(4 * 32 * 32);
+  status_ = ar_.alloc<int>(4);
+  HIPCHK(hipMemsetAsync(status_, 0, 4 * sizeof(int), st_));
+  HIPCHK(hipMemsetAsync(sig_, 0, 64 * sizeof(double), st_));
+  rep_.rows[0] = A0_.m; rep_.cols[0] = A0_.n; rep_.nnz[0] = A0_.nnz();
+  pmask_ = p_.profile_mask;
+  finest_level(init_tests);
+  norm_estimate();
+  rep_.anorm = anorm_;
+  std::vector<double> rho;
+  std::vector<double> hs;
+  for (int c = 1; c <= p_.n_mult; ++c) {
+    mult_cycle(c);
+    rep_.mult_cycles = c;
+    if (c <= 32) {
+      d2h(hs, sig_, nb_, st_);
+      for (int j = 0; j < nb_; ++j) rep_.mult_sigma[c - 1][j] = hs[j];
+    }
+  }
+  if (!p_.ritz_in_mult) ritz();
+  check_status();
+  for (size_t l = 0; l < lv_.size(); ++l) {
+    rep_.rows[l] = lv_[l]->m;
+    rep_.cols[l] = lv_[l]->n;
+    rep_.nnz[l] = lv_[l]->hA.nnz();
+    rep_.colours[l] = (int)(lv_[l]->kA_cptr.empty() ? 0 : lv_[l]->kA_cptr.size() - 1);
+  }
+  residuals(rho);
+  double rmax = *std::max_element(rho.begin(), rho.end());
+  rep_.rho_history[0] = rmax;
+  auto t1 = clk::now();
+  // additive phase: frozen operators (dense coarsest matrices built once)
+  dense_coarsest(dX_, dY_);
+  if (p_.coarse_pinv == 1) {
+    double* Xc = dwork_;
+    double* Yc = dwork_ + (size_t)NL_ * NL_;
+    HIPCHK(hipMemcpyAsync(Xc, dX_, sizeof(double) * NL_ * NL_, hipMemcpyDeviceToDevice, st_));
+    HIPCHK(hipMemcpyAsync(Yc, dY_, sizeof(double) * NL_ * NL_, hipMemcpyDeviceToDevice, st_));
+    double* wk = ar_.alloc<double>((size_t)2 * NL_ * NL_);
+    launch_pencil_setup(NL_, Xc, Yc, mu_, Zp_, wk, status_, st_);
+  }
+  if (mixed_) {
+    for (auto& L : lv_) {
+      if (L->su.P.vf) launch_copy_cast_df(L->su.P.v, L->su.P.vf, L->su.P.nnz, st_);
+      if (L->su.Pt.vf) launch_copy_cast_df(L->su.Pt.v, L->su.Pt.vf, L->su.Pt.nnz, st_);
+      if (!spd_) {
+        if (L->sv.P.vf) launch_copy_cast_df(L->sv.P.v, L->sv.P.vf, L->sv.P.nnz, st_);
+        if (L->sv.Pt.vf) launch_copy_cast_df(L->sv.Pt.v, L->sv.Pt.vf, L->sv.Pt.nnz, st_);
+      }
+    }
+  }
+  int it = 0;
+  while (rmax > p_.tol && it < p_.max_add) {
+    additive_iteration();
+    ritz();
+    residuals(rho);
+    rmax = *std::max_element(rho.begin(), rho.end());
+    ++it;
+    if (it < 256) rep_.rho_history[it] = rmax;
+  }
+  check_status();
+  auto t2 = clk::now();
+  rep_.add_iters = it;
+  rep_.converged = rmax <= p_.tol ? 1 : 0;
+  rep_.t_setup_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  rep_.t_solve_ms = std::chrono::duration<double, std::milli>(t2 - t1).count();
+  for (int j = 0; j < nb_ && j < 16; ++j) {
+    rep_.resid[j] = rho[j];
+    rep_.err_bound[j] = rho[j] * anorm_;
+  }
+  prof_finish();
+  // outputs
+  Level& L = *lv_[0];
+  if (pb_.outU || pb_.outV) {
+    // device outputs: sign convention and scatter into the caller's column-major arrays
+    // reference column: the caller's v_j (x_j for eigenproblems)
+    const bool refU = spd_ || pb_.swapUV;
+    const double* ref = refU ? L.bd.Ub : L.bd.Vb;
+    const int rref = refU ? rows_u(L) : rows_v(L);
+    launch_sign_argmax(rref, nb_, ref, flip_, st_);
+    double* dstU = pb_.swapUV ? pb_.outV : pb_.outU;
+    double* dstV = pb_.swapUV ? pb_.outU : pb_.outV;
+    long ldu = pb_.swapUV ? pb_.ldV : pb_.ldU, ldv = pb_.swapUV ? pb_.ldU : pb_.ldV;
+    if (dstU) {
+      launch_fill(dstU, (size_t)ldu * nb_, 0.0, st_);
+      launch_scatter_out(rows_u(L), nb_, L.bd.Ub, pb_.keepU, flip_, dstU, ldu, st_);
+    }
+    if (!spd_ && dstV) {
+      launch_fill(dstV, (size_t)ldv * nb_, 0.0, st_);
+      launch_scatter_out(rows_v(L), nb_, L.bd.Vb, pb_.keepV, flip_, dstV, ldv, st_);
+    }
+    d2h(out.sigma, sig_, nb_, st_);
+  } else {
+    d2h(out.sigma, sig_, nb_, st_);
+    d2h(out.U, L.bd.Ub, (size_t)rows_u(L) * nb_, st_);
+    if (!spd_) d2h(out.V, L.bd.Vb, (size_t)rows_v(L) * nb_, st_);
+  }
+  out.rep = rep_;
+  out.status = rep_.converged ? ST_OK : ST_NOT_CONVERGED;
+}
+
+void run_solver(hipStream_t stream, size_t budget, const Problem& pb, const slamg_params& p,
+                const double* init_tests, SolveOutput& out) {
+  Solver s(stream, budget, pb, p);
+  s.run(init_tests, out);
+}
+
+}  // namespace slamg

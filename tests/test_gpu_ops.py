@@ -1,0 +1,319 @@
+"""Step-level parity of the HIP kernels with the oracle (one test per hot-path step).
+
+FP64 tolerance: the kernels and the oracle sum in different orders, so an entry may differ by
+(row length) * eps * sum_k |a_ik x_k|; tests use 1e-13 times that magnitude (eps = 2.2e-16 and
+rows of at most ~40 entries give < 1e-14), or a stated bound derived the same way.
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import slamg_oracle as O
+from paper_1102_0919_amd import workloads as W
+
+from .gpu_util import csr_dev, dev, host, hp, lib, ptr, release
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _keepalive():
+    yield
+    release()
+
+
+def _close(x, ref, mag, rel=1e-13):
+    x, ref, mag = np.asarray(x), np.asarray(ref), np.asarray(mag)
+    err = np.abs(x - ref)
+    ok = err <= rel * mag + 1e-300
+    assert ok.all(), f"max err {err.max():.3e}, max allowed {(rel * mag).max():.3e}"
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    assert torch.cuda.is_available()
+    return lib()
+
+
+@pytest.mark.parametrize("w", [1, 2, 3, 5, 8, 10, 16])
+def test_spmm_parity(L, w):
+    A = W.random_csr(3001, 1777, seed=w, mean_row=7).to_scipy()          # skewed, ragged, empty rows
+    X = W.seeded_block(1777, w, seed=100 + w)
+    Y0 = W.seeded_block(3001, w, seed=200 + w)
+    rp, ci, v = csr_dev(A)
+    dx, dy = dev(X), dev(Y0)
+    assert L.slamg_op_spmm(3001, w, ptr(rp), ptr(ci), ptr(v), ptr(dx), ptr(dy), 0.5, None) == 0
+    ref = A @ X + 0.5 * Y0
+    _close(host(dy), ref, abs(A) @ abs(X) + 0.5 * abs(Y0))
+
+
+def test_spmm_f32_parity(L):
+    import torch
+    A = W.random_csr(2000, 2000, seed=3, mean_row=7).to_scipy()
+    X = W.seeded_block(2000, 8, seed=4)
+    M = sp.csr_matrix(A); M.sort_indices()
+    rp, ci = dev(M.indptr, np.int32), dev(M.indices, np.int32)
+    v = dev(M.data.astype(np.float32))
+    dx = dev(X.astype(np.float32)); dy = dev(np.zeros((2000, 8), np.float32))
+    assert L.slamg_op_spmm_f32(2000, 8, ptr(rp), ptr(ci), ptr(v), ptr(dx), ptr(dy), 0.0, None) == 0
+    ref = M.astype(np.float64) @ X
+    # fp32 storage + fp32 accumulation: |err| <= (len + 2) u32 sum |a||x|, u32 = 6e-8
+    _close(host(dy), ref, abs(M) @ abs(X), rel=40 * 6e-8)
+
+
+def _svd_level(m, n, seed, coarse):
+    rng = np.random.default_rng(seed)
+    A = sp.csr_matrix(W.random_csr(m, n, seed=seed, mean_row=5, empty_rows=False).to_scipy())
+    if coarse:
+        Bh = sp.random(m, m, density=0.05, random_state=seed) ; Bd = sp.csr_matrix(Bh @ Bh.T + 3 * sp.identity(m))
+        Ch = sp.random(n, n, density=0.05, random_state=seed + 1); Cd = sp.csr_matrix(Ch @ Ch.T + 3 * sp.identity(n))
+    else:
+        Bd, Cd = sp.identity(m, format="csr"), sp.identity(n, format="csr")
+    for M in (A, Bd, Cd):
+        M.sort_indices()
+    return O.Level(A, Bd, Cd), rng
+
+
+@pytest.mark.parametrize("coarse", [False, True])
+def test_relaxation_dominant_svd_parity(L, coarse):
+    lev, rng = _svd_level(1500, 900, 7, coarse)
+    A, B, Cm = lev.A, lev.B, lev.C
+    w = 6
+    U, V = rng.uniform(-1, 1, (1500, w)), rng.uniform(-1, 1, (900, w))
+    a, at = csr_dev(A), csr_dev(A.T.tocsr())
+    b = csr_dev(B) if coarse else (None, None, None)
+    c = csr_dev(Cm) if coarse else (None, None, None)
+    du, dv = dev(U), dev(V)
+    assert L.slamg_op_relax_test(0, 1500, 900, w, *map(ptr, a), *map(ptr, at), *map(ptr, b), *map(ptr, c), 0.7,
+                                 ptr(du), ptr(dv), None) == 0
+    Ur, Vr = O.relax_test_dominant(lev, O.SVD, U, V, 0.7)
+    _close(host(du), Ur, np.abs(Ur) + 1e-3, rel=1e-12)
+    _close(host(dv), Vr, np.abs(Vr) + 1e-3, rel=1e-12)
+    sig = rng.uniform(1.0, 3.0, w)
+    kap, tau = rng.normal(size=(1500, w)), rng.normal(size=(900, w))
+    du, dv, ds, dk, dt = dev(U), dev(V), dev(sig), dev(kap), dev(tau)
+    assert L.slamg_op_relax_boot(0, 1500, 900, w, *map(ptr, a), *map(ptr, at), *map(ptr, b), *map(ptr, c),
+                                 ptr(ds), ptr(dk), ptr(dt), 0.7, ptr(du), ptr(dv), None) == 0
+    Ub, Vb = O.relax_boot_dominant(lev, O.SVD, U, V, sig, kap, tau, 0.7)
+    _close(host(du), Ub, np.abs(Ub) + 10, rel=1e-13)
+    _close(host(dv), Vb, np.abs(Vb) + 10, rel=1e-13)
+
+
+@pytest.mark.parametrize("coarse", [False, True])
+def test_relaxation_dominant_spd_parity(L, coarse):
+    A = sp.csr_matrix(W.laplace2d(40).to_scipy())
+    n = A.shape[0]
+    diag_mask = A.indices == np.repeat(np.arange(n), np.diff(A.indptr))
+    bdata = np.where(diag_mask, 2.0, 0.1)
+    if coarse:
+        Bd = sp.csr_matrix((bdata, A.indices.copy(), A.indptr.copy()), shape=A.shape)
+    else:
+        Bd = sp.identity(n, format="csr")
+    lev = O.Level(A, Bd, None)
+    rng = np.random.default_rng(1)
+    X = rng.uniform(-1, 1, (n, 8))
+    a = csr_dev(A)
+    bv = dev(bdata) if coarse else None
+    dx = dev(X)
+    assert L.slamg_op_relax_test(1, n, n, 8, *map(ptr, a), None, None, None, None, None, ptr(bv), None, None,
+                                 None, 0.7, ptr(dx), None, None) == 0
+    Xr, _ = O.relax_test_dominant(lev, O.SPD, X, None, 0.7)
+    _close(host(dx), Xr, np.abs(Xr) + 1e-3, rel=1e-12)
+    sig = rng.uniform(4.0, 8.0, 8); kap = rng.normal(size=(n, 8))
+    dx, ds, dk = dev(X), dev(sig), dev(kap)
+    assert L.slamg_op_relax_boot(1, n, n, 8, *map(ptr, a), None, None, None, None, None, ptr(bv), None, None,
+                                 None, ptr(ds), ptr(dk), None, 0.7, ptr(dx), None, None) == 0
+    Xb, _ = O.relax_boot_dominant(lev, O.SPD, X, None, sig, kap, None, 0.7)
+    _close(host(dx), Xb, np.abs(Xb) + 10, rel=1e-13)
+
+
+@pytest.mark.parametrize("shifted", [False, True])
+def test_kaczmarz_parity(L, shifted):
+    if shifted:
+        M = sp.csr_matrix(W.aniso3d(9, 0.01).to_scipy())
+    else:
+        M = sp.csr_matrix(W.gradient2d(30).to_scipy())
+    M.sort_indices()
+    nr, nc = M.shape
+    col = O.greedy_row_colouring(M)
+    groups = O.colour_groups(col)
+    rows = np.concatenate(groups).astype(np.int32)
+    cptr = np.concatenate([[0], np.cumsum([g.size for g in groups])]).astype(np.int32)
+    rng = np.random.default_rng(5)
+    w = 8
+    x0 = rng.uniform(-1, 1, (nc, w)); rhs = rng.normal(size=(nr, w))
+    lam = rng.uniform(0.0, 0.3, w)
+    rp, ci, v = csr_dev(M)
+    dx, dr = dev(x0), dev(rhs)
+    dl = dev(lam) if shifted else None
+    assert L.slamg_op_kaczmarz(nr, nc, w, ptr(rp), ptr(ci), ptr(v), None, ptr(dl), hp(rows), hp(cptr),
+                               len(groups), ptr(dr), ptr(dx), None) == 0
+    if shifted:
+        ref = x0.copy()
+        for j in range(w):
+            Mj = sp.csr_matrix(M - lam[j] * sp.identity(nr))
+            ref[:, j:j + 1] = O.kaczmarz_sweep(Mj, x0[:, j:j + 1], rhs[:, j:j + 1], groups)
+    else:
+        ref = O.kaczmarz_sweep(M, x0, rhs, groups)
+    _close(host(dx), ref, np.abs(ref) + 1.0, rel=1e-12)
+
+
+def test_residual_and_dots_parity(L):
+    lev, rng = _svd_level(1200, 700, 3, True)
+    A, B = lev.A, lev.B
+    w = 5
+    U, V = rng.normal(size=(1200, w)), rng.normal(size=(700, w))
+    kap = rng.normal(size=(1200, w)); sig = rng.uniform(0.5, 2, w)
+    a, b = csr_dev(A), csr_dev(B)
+    out = dev(np.zeros((1200, w)))
+    assert L.slamg_op_residual(1200, w, *map(ptr, a), ptr(dev(V)), *map(ptr, b), ptr(dev(U)), ptr(dev(kap)),
+                               ptr(dev(sig)), ptr(out), None) == 0
+    ref = kap - (A @ V - (B @ U) * sig)
+    _close(host(out), ref, abs(kap) + abs(A) @ abs(V) + (abs(B) @ abs(U)) * sig)
+    h = np.zeros(w)
+    assert L.slamg_op_dots(1200, w, ptr(dev(U)), *map(ptr, a), ptr(dev(V)), None, None, hp(h), None) == 0
+    refd = np.sum(U * (A @ V), axis=0)
+    _close(h, refd, np.sum(np.abs(U) * (abs(A) @ abs(V)), axis=0), rel=1e-12)
+    assert L.slamg_op_dots(1200, w, None, *map(ptr, a), ptr(dev(V)), ptr(dev(U)), ptr(dev(sig)), hp(h), None) == 0
+    _close(h, np.sum((A @ V - U * sig) ** 2, axis=0), np.sum((abs(A) @ abs(V) + abs(U) * sig) ** 2, axis=0),
+           rel=1e-12)
+
+
+@pytest.mark.parametrize("rows,w", [(1, 3), (37, 8), (5003, 8), (100003, 16), (4096, 10)])
+def test_gram_mfma_parity(L, rows, w):
+    X = W.seeded_block(rows, w, seed=rows)
+    Y = W.seeded_block(rows, w, seed=rows + 1)
+    g = np.zeros((w, w))
+    assert L.slamg_op_gram(rows, w, ptr(dev(X)), ptr(dev(Y)), hp(g), None) == 0
+    _close(g, X.T @ Y, np.abs(X).T @ np.abs(Y), rel=1e-12)     # non-symmetric: checks the lane layout
+
+
+@pytest.mark.parametrize("kind,target", [("svd", "dominant"), ("svd", "minimal"), ("spd", "minimal"),
+                                         ("spd", "dominant")])
+def test_ritz_parity(L, kind, target):
+    rng = np.random.default_rng(9)
+    if kind == "svd":
+        A = sp.csr_matrix(W.gradient2d(20).to_scipy())
+    else:
+        A = sp.csr_matrix(W.laplace2d(25).to_scipy())
+    m, n = A.shape
+    w = 6
+    U, V = rng.normal(size=(m, w)), rng.normal(size=(n, w))
+    sig_o, Uo, Vo = O.ritz(A, kind, target, U, V if kind == "svd" else None)
+    a = csr_dev(A)
+    du, dv = dev(U), dev(V)
+    hs = np.zeros(w)
+    assert L.slamg_op_ritz(1 if kind == "spd" else 0, 1 if target == "minimal" else 0, m, n, w, *map(ptr, a),
+                           ptr(du), ptr(dv) if kind == "svd" else None, hp(hs), None) == 0
+    assert np.allclose(hs, sig_o, rtol=1e-11, atol=1e-13 * abs(sig_o).max())
+    Ug = host(du)
+    # vectors: unique up to sign for simple Ritz values
+    for j in range(w):
+        s = np.sign(Ug[:, j] @ Uo[:, j])
+        assert np.allclose(Ug[:, j] * s, Uo[:, j], atol=1e-9)
+    assert np.allclose(Ug.T @ Ug, np.eye(w), atol=1e-12)
+    if kind == "svd":
+        Vg = host(dv)
+        assert np.allclose(A @ Vg - Ug * hs, Uo * 0 + (A @ Vo - Uo * sig_o) * np.sign(np.sum(Ug * Uo, 0)),
+                           atol=1e-10)
+
+
+@pytest.mark.parametrize("boots", [False, True])
+def test_ls_fit_parity(L, boots):
+    N = W.laplace2d(30).to_scipy()
+    Sp, Si = O.strength_sets(N, 0.06, 0)
+    is_c = O.rs_coarsen(Sp, Si, N.shape[0])
+    ptr_, cols, _ = O.interp_pattern(Sp, Si, N, is_c, 7)
+    rng = np.random.default_rng(3)
+    n = N.shape[0]
+    U1 = rng.normal(size=(n, 8)); U2 = rng.normal(size=(n, 4)) if boots else None
+    B1 = U1 + 0.01 * rng.normal(size=U1.shape)
+    wts = rng.uniform(0.1, 2.0, 12 if boots else 8)
+    Uf = np.hstack([U1, U2]) if boots else U1
+    Bf = np.hstack([B1, U2]) if boots else B1
+    P = O.ls_interpolation(ptr_, cols, is_c, Uf, Bf, wts)
+    pv = np.zeros(ptr_[-1])
+    assert L.slamg_op_ls_fit(n, hp(ptr_.astype(np.int32)), hp(cols.astype(np.int32)), hp(is_c.astype(np.int8)), 8,
+                             ptr(dev(U1)), ptr(dev(B1)), 4 if boots else 0, ptr(dev(U2)) if boots else None, None,
+                             ptr(dev(wts)), hp(pv), None) == 0
+    # normal equations solved by LU (oracle) and Cholesky (kernel): both backward stable
+    assert np.allclose(pv, P.data, rtol=1e-8, atol=1e-10)
+
+
+def test_galerkin_spgemm_parity(L):
+    A = sp.csr_matrix(W.gradient2d(25).to_scipy())
+    rng = np.random.default_rng(2)
+    m, n = A.shape
+    P = sp.csr_matrix(sp.random(m, m // 3, density=3.0 / (m // 3), random_state=1) + sp.eye(m, m // 3))
+    Q = sp.csr_matrix(sp.random(n, n // 2, density=3.0 / (n // 2), random_state=2) + sp.eye(n, n // 2))
+    for M in (P, Q):
+        M.sort_indices()
+    Pt, At, Qt = P.T.tocsr(), A.T.tocsr(), Q.T.tocsr()
+    S1 = O.structural_product(Pt, A)
+    Ac = O.structural_product(S1, Q)
+    # S1 = P^t A: rows of P^t . rows of A^t ; Ac = S1 Q: rows of S1 . rows of Q^t
+    def run(Cpat, Lm, Rt):
+        rowc = np.repeat(np.arange(Cpat.shape[0]), np.diff(Cpat.indptr)).astype(np.int32)
+        out = dev(np.zeros(Cpat.nnz))
+        assert L.slamg_op_spgemm(Cpat.nnz, ptr(dev(rowc)), ptr(dev(Cpat.indices, np.int32)), *map(ptr, csr_dev(Lm)),
+                                 *map(ptr, csr_dev(Rt)), ptr(out), None) == 0
+        return host(out)
+    s1 = run(S1, Pt, At)
+    assert np.allclose(s1, S1.data, rtol=1e-13, atol=1e-14)
+    S1g = sp.csr_matrix((s1, S1.indices, S1.indptr), shape=S1.shape)
+    ac = run(Ac, S1g, Qt)
+    assert np.allclose(ac, Ac.data, rtol=1e-12, atol=1e-13)
+
+
+@pytest.mark.parametrize("kind,target", [("svd", "dominant"), ("svd", "minimal"), ("spd", "minimal"),
+                                         ("spd", "dominant")])
+def test_coarse_gsvd_parity(L, kind, target):
+    rng = np.random.default_rng(4)
+    if kind == "svd":
+        m, n = 70, 40
+        Ad = rng.uniform(-1, 1, (m, n))
+        Bh = rng.uniform(-1, 1, (m, m)); Bd = Bh @ Bh.T / m + np.eye(m)
+        Ch = rng.uniform(-1, 1, (n, n)); Cd = Ch @ Ch.T / n + np.eye(n)
+        lev = O.Level(sp.csr_matrix(Ad), sp.csr_matrix(Bd), sp.csr_matrix(Cd))
+    else:
+        m = n = 90
+        Ah = rng.uniform(-1, 1, (m, m)); Ad = Ah @ Ah.T / m + 0.1 * np.eye(m)
+        Bh = rng.uniform(-1, 1, (m, m)); Bd = Bh @ Bh.T / m + np.eye(m)
+        Cd = None
+        lev = O.Level(sp.csr_matrix(Ad), sp.csr_matrix(Bd), None)
+    nb = 6
+    so, Uo, Vo = O.coarsest_gsvd(lev, kind, target, nb)
+    hs, hu, hv = np.zeros(nb), np.zeros((m, nb)), np.zeros((n, nb))
+    assert L.slamg_op_coarse_gsvd(1 if kind == "spd" else 0, 1 if target == "minimal" else 0, m, n, nb,
+                                  hp(np.ascontiguousarray(Ad)), hp(np.ascontiguousarray(Bd)),
+                                  hp(np.ascontiguousarray(Cd)) if Cd is not None else None, hp(hs), hp(hu),
+                                  hp(hv)) == 0
+    # eigen-decomposition of D^t D: sigma accurate to eps * sigma_max^2 / sigma
+    smax = np.linalg.svd(Ad, compute_uv=False)[0] * 10
+    assert np.allclose(hs, so, rtol=1e-9, atol=1e-14 * smax ** 2 / max(so.min(), 1e-3))
+    for j in range(nb):
+        s = np.sign(hu[:, j] @ Bd @ Uo[:, j])
+        assert np.allclose(hu[:, j] * s, Uo[:, j], atol=1e-7)
+        if kind == "svd":
+            assert np.allclose(hv[:, j] * s, Vo[:, j], atol=1e-7)
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_coarse_solve_parity(L, variant):
+    rng = np.random.default_rng(6)
+    m, n = 30, 20
+    Ad = rng.uniform(-1, 1, (m, n))
+    Bh = rng.uniform(-1, 1, (m, m)); Bd = Bh @ Bh.T / m + np.eye(m)
+    Ch = rng.uniform(-1, 1, (n, n)); Cd = Ch @ Ch.T / n + np.eye(n)
+    lev = O.Level(sp.csr_matrix(Ad), sp.csr_matrix(Bd), sp.csr_matrix(Cd))
+    X, Y = O.pencil_matrices(lev, O.SVD)
+    sig = np.array([0.3, 0.7, 1.3, 2.1])
+    rhs = rng.normal(size=(m + n, 4))
+    ref = (O.coarse_pinv_solve if variant == 0 else O.coarse_pencil_solve)(X, Y, sig, rhs)
+    out = np.zeros_like(rhs)
+    assert L.slamg_op_coarse_solve(variant, m + n, 4, hp(np.ascontiguousarray(X)), hp(np.ascontiguousarray(Y)),
+                                   hp(sig), hp(np.ascontiguousarray(rhs)), hp(out)) == 0
+    assert np.allclose(out, ref, rtol=1e-8, atol=1e-9 * np.abs(ref).max())

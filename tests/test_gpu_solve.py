@@ -1,0 +1,174 @@
+"""End-to-end parity of slamg_solve (HIP path through the C ABI) with the oracle and closed forms.
+
+Singular values / eigenvalues must agree with the closed form and the oracle to
+|s - s_ref| <= 1e-10 max(s_ref, 1e-8 ||A||) (FP64); residuals meet the requested tolerance; the
+hierarchy (levels and sizes) equals the oracle's, since both make the same deterministic choices.
+Vectors are compared through invariants (residuals, orthonormality) and, for simple values, up to
+sign.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import slamg_oracle as O
+from paper_1102_0919_amd import workloads as W
+
+from .gpu_util import lib
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    lib()
+    from paper_1102_0919_amd import api
+    c = api.Context(0)
+    yield c
+    c.close()
+
+
+def _sig_close(s, ref, anorm, rel=1e-10):
+    s, ref = np.asarray(s), np.asarray(ref)
+    tol = rel * np.maximum(np.abs(ref), 1e-8 * anorm)
+    assert np.all(np.abs(s - ref) <= tol), (s, ref, np.abs(s - ref) / np.maximum(np.abs(ref), 1e-300))
+
+
+def _check_triplets(A, r, kind, tol, anorm):
+    if kind == "spd":
+        res = np.linalg.norm(A @ r.U - r.U * r.sigma, axis=0) / anorm
+    else:
+        res = np.maximum(np.linalg.norm(A @ r.V - r.U * r.sigma, axis=0),
+                         np.linalg.norm(A.T @ r.U - r.V * r.sigma, axis=0)) / anorm
+        assert np.allclose(r.V.T @ r.V, np.eye(r.V.shape[1]), atol=1e-9)
+    assert np.all(res <= tol * 1.0001), res
+    assert np.allclose(r.U.T @ r.U, np.eye(r.U.shape[1]), atol=1e-9)
+
+
+def _run_both(ctx, name, scale=None, **over):
+    from paper_1102_0919_amd import api
+    wl = W.WORKLOADS[name]
+    A = W.build_workload_matrix(name, scale).to_scipy()
+    prm = dict(wl["params"]); prm.update(over)
+    p = api.params_init(wl["kind"], wl["target"], **prm)
+    r = api.solve(ctx, A, wl["kind"], wl["target"], wl["n_b"], p)
+    o = O.solve(A, wl["kind"], wl["target"], wl["n_b"], O.Params(**{k: v for k, v in prm.items()}))
+    return A, wl, r, o
+
+
+def test_laplace31_min4_vs_oracle_and_closed_form(ctx):
+    from paper_1102_0919_amd import api
+    A, wl, r, o = _run_both(ctx, "laplace2d_31_min4")
+    rep = api.report_dict(r.report)
+    assert r.converged and o.report["converged"]
+    ref = W.laplace2d_eigs(31)[:4]
+    _sig_close(r.sigma, ref, rep["anorm"])
+    _sig_close(r.sigma, o.sigma, rep["anorm"])
+    _check_triplets(A, r, "spd", 1e-8, rep["anorm"])
+    # same hierarchy as the oracle
+    assert rep["levels"] == o.report["levels"]
+    assert rep["sizes"] == [tuple(s) for s in o.report["sizes"]]
+    # iterate-level tracking over the first multiplicative cycle
+    ms = np.array([r.report.mult_sigma[0][j] for j in range(4)])
+    assert np.allclose(ms, o.report["mult_sigma"][0], rtol=1e-7)
+    assert abs(rep["add_iters"] - o.report["add_iters"]) <= 2
+    # invariant vectors: x_1 and x_4 are simple eigenvalues
+    for j in (0, 3):
+        assert abs(abs(r.U[:, j] @ o.U[:, j]) - 1.0) < 1e-8
+
+
+@pytest.mark.parametrize("target,col", [("minimal", 2), ("dominant", 1)])
+def test_table1_fd_32x32(ctx, target, col):
+    import os
+    rows = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "table1_fd.txt"))
+    from paper_1102_0919_amd import api
+    name = "laplace2d_32_min8" if target == "minimal" else "laplace2d_32_dom8"
+    wl = W.WORKLOADS[name]
+    A = W.laplace2d(32).to_scipy()
+    r = api.solve(ctx, A, "spd", target, 8, api.params_init("spd", target, **wl["params"]))
+    assert r.converged
+    assert np.allclose(r.sigma, rows[:, col], rtol=6e-8, atol=0)
+    ev = W.laplace2d_eigs(32)
+    ref = ev[:8] if target == "minimal" else ev[::-1][:8]
+    _sig_close(r.sigma, ref, r.report.anorm)
+
+
+def test_gradient32_dominant_vs_oracle(ctx):
+    A, wl, r, o = _run_both(ctx, "gradient2d_256_dom8", scale=32)
+    assert r.converged
+    ref = W.gradient2d_singular_values(32)[::-1][:8]
+    _sig_close(r.sigma, ref, r.report.anorm)
+    _sig_close(r.sigma, o.sigma, r.report.anorm)
+    _check_triplets(A, r, "svd", 1e-8, r.report.anorm)
+    assert r.report.levels == o.report["levels"]
+
+
+def test_square_nonsymmetric_minimal(ctx):
+    from paper_1102_0919_amd import api
+    k = 10
+    Lm = W.laplace2d(k).to_scipy().tolil()
+    for i in range(k * k - 1):
+        if (i + 1) % k:
+            Lm[i, i + 1] += -0.3
+            Lm[i + 1, i] += 0.3
+    A = sp.csr_matrix(Lm)
+    prm = dict(coarse_max=60, n_t=10, mu_t=8, theta=0.05, n_mult=10, tol=1e-10)
+    r = api.solve(ctx, A, "svd", "minimal", 3, api.params_init("svd", "minimal", **prm))
+    o = O.solve(A, "svd", "minimal", 3, O.Params(**prm))
+    sv = np.linalg.svd(A.toarray(), compute_uv=False)[::-1][:3]
+    assert r.converged
+    _sig_close(r.sigma, sv, r.report.anorm)
+    _sig_close(r.sigma, o.sigma, r.report.anorm)
+
+
+def test_init_tests_and_rectangular_transpose(ctx):
+    # explicit initial vectors; a wide matrix (m < n) is solved through its transpose
+    from paper_1102_0919_amd import api
+    G = W.gradient2d(16).to_scipy()
+    A = sp.csr_matrix(G.T)                                  # 256 x 480, m < n
+    prm = dict(coarse_max=100, n_t=8, theta=0.05, n_mult=6, tol=1e-9)
+    p = api.params_init("svd", "dominant", **prm)
+    m_, n_ = G.shape
+    init = W.initial_tests(m_ + n_, 8, 77)
+    r = api.solve(ctx, A, "svd", "dominant", 4, p, init_tests=init)
+    o = O.solve(A, "svd", "dominant", 4, O.Params(**prm), init=(init[:m_], init[m_:]))
+    assert r.converged
+    sv = np.linalg.svd(A.toarray(), compute_uv=False)[:4]
+    _sig_close(r.sigma, sv, r.report.anorm)
+    _sig_close(r.sigma, o.sigma, r.report.anorm)
+    assert r.U.shape == (256, 4) and r.V.shape == (480, 4)
+    assert np.allclose(A @ r.V, r.U * r.sigma, atol=1e-7)
+
+
+def test_mixed_precision_matches_fp64(ctx):
+    from paper_1102_0919_amd import api
+    wl = W.WORKLOADS["laplace2d_31_min4"]
+    A = W.laplace2d(31).to_scipy()
+    r64 = api.solve(ctx, A, "spd", "minimal", 4, api.params_init("spd", "minimal", **wl["params"]))
+    r32 = api.solve(ctx, A, "spd", "minimal", 4, api.params_init("spd", "minimal", precision="mixed_fp32",
+                                                                 **wl["params"]))
+    assert r32.converged
+    _sig_close(r32.sigma, r64.sigma, r64.report.anorm)
+    _check_triplets(A, r32, "spd", 1e-8, r64.report.anorm)
+
+
+def test_pencil_variant_same_triplets(ctx):
+    from paper_1102_0919_amd import api
+    wl = W.WORKLOADS["laplace2d_31_min4"]
+    A = W.laplace2d(31).to_scipy()
+    r = api.solve(ctx, A, "spd", "minimal", 4, api.params_init("spd", "minimal", coarse_pinv=1, **wl["params"]))
+    assert r.converged
+    _sig_close(r.sigma, W.laplace2d_eigs(31)[:4], r.report.anorm)
+
+
+def test_request_interface_matches_solve(ctx):
+    from paper_1102_0919_amd import api
+    A = W.laplace2d(20).to_scipy()
+    p = api.params_init("spd", "minimal", coarse_max=60, n_t=6, mu_t=8, n_mult=8)
+    r = api.solve(ctx, A, "spd", "minimal", 3, p)
+    ids = [api.submit(ctx, A, "spd", "minimal", 3, p) for _ in range(2)]
+    for rid in ids:
+        assert api.poll(ctx, rid)
+        f = api.fetch(ctx, rid, 400, 400, 3, "spd")
+        assert np.array_equal(f.sigma, r.sigma)
