@@ -74,13 +74,14 @@ struct RowOpArgs {
   int cmode = C_JAC_TEST;
   double omega = 0.7;
   T* out = nullptr;
+  int nnzK = -1;             // nonzeros of K (chooses the row split); -1: unknown
 };
 
 template <typename T> void launch_rowop(const RowOpArgs<T>& a, hipStream_t s);
 
 template <typename T>
 void launch_spmm(int m, int w, const int* rp, const int* ci, const T* v, const T* x, T* y,
-                 double beta, hipStream_t s);
+                 double beta, hipStream_t s, int nnz = -1);
 
 template <typename T>
 struct KaczArgs {
@@ -96,8 +97,14 @@ struct KaczArgs {
   const double* rsig = nullptr;
   const T* kap = nullptr;
   T* x = nullptr;
+  long nnz_total = -1, nnz_rows = 0;   // row-length statistics of the operator (row split)
 };
 template <typename T> void launch_kacz(const KaczArgs<T>& a, hipStream_t s);
+// nhalf (1 or 2) half-sweeps per sweep, nsweeps sweeps, all in one workgroup; halves[h].rows is the
+// colour-ordered row list and cptr[h] its device colour pointer (ncol[h] colours).
+template <typename T>
+void launch_kacz_wg(const KaczArgs<T>* halves, const int* const* cptr, const int* ncol, int nhalf, int nsweeps,
+                    hipStream_t s);
 
 // Column reductions: partial sums over a fixed grid, then a fixed-order finalisation.
 // value_ic = (K ? (K z)_ic : z_ic) - (y ? s_c y_ic : 0);  acc_c += a ? a_ic * value_ic : value_ic^2
@@ -108,6 +115,7 @@ struct DotArgs {
   const int* Krp = nullptr; const int* Kci = nullptr; const T* Kv = nullptr;
   const T* z = nullptr;
   const T* y = nullptr; const double* sig = nullptr;
+  int nnzK = -1;
 };
 template <typename T> void launch_dots(const DotArgs<T>& a, double* partial, double* out, hipStream_t s);
 int dots_grid(int nrows, int w);

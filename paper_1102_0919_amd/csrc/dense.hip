@@ -83,11 +83,14 @@ __device__ static void wg_transpose(const double* A, int r, int c, int lda, doub
 }
 
 // Two-sided cyclic Jacobi with the round-robin parallel ordering: A (n x n symmetric) is reduced to
-// diagonal form in place; V accumulates the rotations (A_in = V diag V^t).
+// diagonal form in place; V accumulates the rotations (A_in = V diag V^t).  A pair is rotated
+// when |a_pq| > 1e-15 sqrt(|a_pp a_qq|) (and above 1e-17 ||A||_F); the sweeps stop after one that
+// rotated nothing.
 __device__ static void wg_jacobi(double* A, int n, int ld, double* V, int ldv, int maxsweep) {
   __shared__ int P[MAXPAIR], Q[MAXPAIR];
   __shared__ double Cs[MAXPAIR], Sn[MAXPAIR];
-  __shared__ double red[DBLK], red2[DBLK];
+  __shared__ double red[DBLK];
+  __shared__ int rotated;
   for (long t = threadIdx.x; t < (long)n * n; t += DBLK) {
     int i = (int)(t / n), j = (int)(t % n);
     V[(long)i * ldv + j] = i == j ? 1.0 : 0.0;
@@ -95,24 +98,22 @@ __device__ static void wg_jacobi(double* A, int n, int ld, double* V, int ldv, i
   const int N = n + (n & 1);
   const int npair = N / 2;
   if (n <= 1) { wg_sync(); return; }
+  double tot = 0.0;
+  for (long t = threadIdx.x; t < (long)n * n; t += DBLK) {
+    int i = (int)(t / n), j = (int)(t % n);
+    double a = A[(long)i * ld + j];
+    tot += a * a;
+  }
+  red[threadIdx.x] = tot;
+  wg_sync();
+  for (int s = DBLK / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    wg_sync();
+  }
+  const double floor_abs = 1e-17 * sqrt(red[0]);
   for (int sweep = 0; sweep < maxsweep; ++sweep) {
+    if (threadIdx.x == 0) rotated = 0;
     wg_sync();
-    double off = 0.0, tot = 0.0;
-    for (long t = threadIdx.x; t < (long)n * n; t += DBLK) {
-      int i = (int)(t / n), j = (int)(t % n);
-      double a = A[(long)i * ld + j];
-      tot += a * a;
-      if (i != j) off += a * a;
-    }
-    red[threadIdx.x] = off; red2[threadIdx.x] = tot;
-    wg_sync();
-    for (int s = DBLK / 2; s > 0; s >>= 1) {
-      if ((int)threadIdx.x < s) { red[threadIdx.x] += red[threadIdx.x + s]; red2[threadIdx.x] += red2[threadIdx.x + s]; }
-      wg_sync();
-    }
-    const double offs = red[0], tots = red2[0];
-    wg_sync();
-    if (!(offs > 1e-32 * tots)) break;
     for (int r = 0; r < N - 1; ++r) {
       for (int k = threadIdx.x; k < npair; k += DBLK) {
         int a = k, b = N - 1 - k;
@@ -121,12 +122,14 @@ __device__ static void wg_jacobi(double* A, int n, int ld, double* V, int ldv, i
         if (p > q) { int tmp = p; p = q; q = tmp; }
         double c = 1.0, s = 0.0;
         if (q < n) {
-          double apq = A[(long)p * ld + q];
-          if (fabs(apq) > 1e-300) {
-            double tau = (A[(long)q * ld + q] - A[(long)p * ld + p]) / (2.0 * apq);
+          const double apq = A[(long)p * ld + q];
+          const double app = A[(long)p * ld + p], aqq = A[(long)q * ld + q];
+          if (fabs(apq) > fmax(1e-15 * sqrt(fabs(app * aqq)), floor_abs) && fabs(apq) > 1e-300) {
+            double tau = (aqq - app) / (2.0 * apq);
             double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + tt * tt);
             s = tt * c;
+            rotated = 1;
           }
         }
         P[k] = p; Q[k] = q; Cs[k] = c; Sn[k] = s;
@@ -156,6 +159,9 @@ __device__ static void wg_jacobi(double* A, int n, int ld, double* V, int ldv, i
       }
       wg_sync();
     }
+    const int any = rotated;
+    wg_sync();
+    if (!any) break;
   }
   wg_sync();
 }

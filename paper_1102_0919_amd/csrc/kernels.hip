@@ -25,6 +25,25 @@ static inline int lshift_of(int w) {
   return s;
 }
 
+// Rows with many nonzeros (coarse Galerkin levels) are split over SPLIT lane groups of the same
+// wavefront; each group takes every SPLIT-th nonzero and the partial sums meet by lane shuffles.
+// Lane layout of a row's group: lane = split * LPRc + column lane (LPRc = 1 << lshift).
+static inline int log2i(int v) { int s = 0; while ((1 << s) < v) ++s; return s; }
+static inline int split_of(long nnz, long rows, int lshift) {
+  if (nnz < 0 || rows <= 0) return 1;
+  const double avg = (double)nnz / (double)rows;
+  int sp = avg <= 10.0 ? 1 : avg <= 24.0 ? 4 : 16;
+  while (sp > 1 && ((1 << lshift) * sp) > 64) sp >>= 1;
+  return sp;
+}
+
+template <int SPLIT, typename T>
+__device__ __forceinline__ T split_sum(T v, int lprc) {
+#pragma unroll
+  for (int m = 1; m < SPLIT; m <<= 1) v += __shfl_xor(v, lprc * m);
+  return v;
+}
+
 template <typename T, int CPL>
 __device__ __forceinline__ void ldrow(const T* __restrict__ p, int c0, int w, T (&v)[CPL]) {
   if constexpr (CPL == 2) {
@@ -57,21 +76,25 @@ __device__ __forceinline__ void strow(T* __restrict__ p, int c0, int w, const T 
 // ------------------------------------------------------------------------------------------------
 // Block SpMM  y = A x (+ beta y)
 // ------------------------------------------------------------------------------------------------
-template <typename T, int CPL>
+template <typename T, int CPL, int SPLIT>
 __global__ __launch_bounds__(BLK) void k_spmm(int m, int w, int lshift, const int* __restrict__ rp,
                                               const int* __restrict__ ci, const T* __restrict__ v,
                                               const T* __restrict__ x, T* __restrict__ y, T beta) {
+  constexpr int LS = SPLIT == 1 ? 0 : SPLIT == 4 ? 2 : SPLIT == 8 ? 3 : 4;
+  const int gl = lshift + LS;
   long t = (long)blockIdx.x * BLK + threadIdx.x;
-  int row = (int)(t >> lshift);
-  int c0 = (int)(t & ((1 << lshift) - 1)) * CPL;
+  int row = (int)(t >> gl);
+  const int lane = (int)(t & ((1 << gl) - 1));
+  const int sidx = lane >> lshift;
+  int c0 = (lane & ((1 << lshift) - 1)) * CPL;
   if (row >= m || c0 >= w) return;
   T acc[CPL];
 #pragma unroll
   for (int c = 0; c < CPL; ++c) acc[c] = T(0);
-  int k = rp[row], ke = rp[row + 1];
-  for (; k + 1 < ke; k += 2) {
-    int j0 = ci[k], j1 = ci[k + 1];
-    T a0 = v[k], a1 = v[k + 1];
+  int k = rp[row] + sidx, ke = rp[row + 1];
+  for (; k + SPLIT < ke; k += 2 * SPLIT) {
+    int j0 = ci[k], j1 = ci[k + SPLIT];
+    T a0 = v[k], a1 = v[k + SPLIT];
     T x0[CPL], x1[CPL];
     ldrow<T, CPL>(x + (long)j0 * w, c0, w, x0);
     ldrow<T, CPL>(x + (long)j1 * w, c0, w, x1);
@@ -85,6 +108,9 @@ __global__ __launch_bounds__(BLK) void k_spmm(int m, int w, int lshift, const in
 #pragma unroll
     for (int c = 0; c < CPL; ++c) acc[c] += a * xv[c];
   }
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) acc[c] = split_sum<SPLIT>(acc[c], 1 << lshift);
+  if (sidx != 0) return;
   T* yr = y + (long)row * w;
   if (beta != T(0)) {
     T old[CPL];
@@ -95,16 +121,23 @@ __global__ __launch_bounds__(BLK) void k_spmm(int m, int w, int lshift, const in
   strow<T, CPL>(yr, c0, w, acc);
 }
 
+#define SLAMG_DISPATCH_SPLIT(KER, T, CPL, SP, GRID, ...)                                        \
+  do {                                                                                      \
+    if (SP == 1) hipLaunchKernelGGL((KER<T, CPL, 1>), dim3(GRID), dim3(BLK), 0, __VA_ARGS__);  \
+    else if (SP == 4) hipLaunchKernelGGL((KER<T, CPL, 4>), dim3(GRID), dim3(BLK), 0, __VA_ARGS__); \
+    else if (SP == 8) hipLaunchKernelGGL((KER<T, CPL, 8>), dim3(GRID), dim3(BLK), 0, __VA_ARGS__); \
+    else hipLaunchKernelGGL((KER<T, CPL, 16>), dim3(GRID), dim3(BLK), 0, __VA_ARGS__);        \
+  } while (0)
+
 template <typename T>
 void launch_spmm(int m, int w, const int* rp, const int* ci, const T* v, const T* x, T* y, double beta,
-                 hipStream_t s) {
+                 hipStream_t s, int nnz) {
   if (m <= 0) return;
   int sh = lshift_of(w);
-  int grid = ceil_div((long)m << sh, BLK);
-  if (cpl_of(w) == 2)
-    hipLaunchKernelGGL((k_spmm<T, 2>), dim3(grid), dim3(BLK), 0, s, m, w, sh, rp, ci, v, x, y, (T)beta);
-  else
-    hipLaunchKernelGGL((k_spmm<T, 1>), dim3(grid), dim3(BLK), 0, s, m, w, sh, rp, ci, v, x, y, (T)beta);
+  int sp = split_of(nnz, m, sh);
+  int grid = ceil_div((long)m << (sh + log2i(sp)), BLK);
+  if (cpl_of(w) == 2) SLAMG_DISPATCH_SPLIT(k_spmm, T, 2, sp, grid, s, m, w, sh, rp, ci, v, x, y, (T)beta);
+  else SLAMG_DISPATCH_SPLIT(k_spmm, T, 1, sp, grid, s, m, w, sh, rp, ci, v, x, y, (T)beta);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -135,11 +168,15 @@ __device__ __forceinline__ void coefs(int cmode, double om, double s, T& ca, T& 
   }
 }
 
-template <typename T, int CPL>
+template <typename T, int CPL, int SPLIT>
 __global__ __launch_bounds__(BLK) void k_rowop(RowOpPOD<T> a, int lshift) {
+  constexpr int LS = SPLIT == 1 ? 0 : SPLIT == 4 ? 2 : SPLIT == 8 ? 3 : 4;
+  const int gl = lshift + LS;
   long t = (long)blockIdx.x * BLK + threadIdx.x;
-  int row = (int)(t >> lshift);
-  int c0 = (int)(t & ((1 << lshift) - 1)) * CPL;
+  int row = (int)(t >> gl);
+  const int lane = (int)(t & ((1 << gl) - 1));
+  const int sidx = lane >> lshift;
+  int c0 = (lane & ((1 << lshift) - 1)) * CPL;
   const int w = a.w;
   if (row >= a.nrows || c0 >= w) return;
   T ca[CPL], cb[CPL], ce[CPL];
@@ -152,7 +189,7 @@ __global__ __launch_bounds__(BLK) void k_rowop(RowOpPOD<T> a, int lshift) {
 #pragma unroll
   for (int c = 0; c < CPL; ++c) { kz[c] = T(0); my[c] = T(0); }
   if (a.Kv) {
-    for (int k = a.Krp[row], ke = a.Krp[row + 1]; k < ke; ++k) {
+    for (int k = a.Krp[row] + sidx, ke = a.Krp[row + 1]; k < ke; k += SPLIT) {
       T zv[CPL];
       ldrow<T, CPL>(a.z + (long)a.Kci[k] * w, c0, w, zv);
       T av = a.Kv[k];
@@ -166,10 +203,8 @@ __global__ __launch_bounds__(BLK) void k_rowop(RowOpPOD<T> a, int lshift) {
       }
     }
   }
-  if (a.mmode == M_IDENT) {
-    ldrow<T, CPL>(a.y + (long)row * w, c0, w, my);
-  } else if (a.mmode == M_CSR) {
-    for (int k = a.Mrp[row], ke = a.Mrp[row + 1]; k < ke; ++k) {
+  if (a.mmode == M_CSR) {
+    for (int k = a.Mrp[row] + sidx, ke = a.Mrp[row + 1]; k < ke; k += SPLIT) {
       T yv[CPL];
       ldrow<T, CPL>(a.y + (long)a.Mci[k] * w, c0, w, yv);
       T mv = a.Mv[k];
@@ -177,6 +212,13 @@ __global__ __launch_bounds__(BLK) void k_rowop(RowOpPOD<T> a, int lshift) {
       for (int c = 0; c < CPL; ++c) my[c] += mv * yv[c];
     }
   }
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) {
+    kz[c] = split_sum<SPLIT>(kz[c], 1 << lshift);
+    my[c] = split_sum<SPLIT>(my[c], 1 << lshift);
+  }
+  if (sidx != 0) return;
+  if (a.mmode == M_IDENT) ldrow<T, CPL>(a.y + (long)row * w, c0, w, my);
   T kp[CPL];
   if (a.kap) ldrow<T, CPL>(a.kap + (long)row * w, c0, w, kp);
   else {
@@ -202,9 +244,10 @@ void launch_rowop(const RowOpArgs<T>& a, hipStream_t s) {
   RowOpPOD<T> p{a.nrows, a.w, a.Krp, a.Kci, a.Kv, a.z, a.mmode, a.Mrp, a.Mci, a.Mv, a.y,
                 a.x, a.D, a.kap, a.sig, a.cmode, a.omega, a.out};
   int sh = lshift_of(a.w);
-  int grid = ceil_div((long)a.nrows << sh, BLK);
-  if (cpl_of(a.w) == 2) hipLaunchKernelGGL((k_rowop<T, 2>), dim3(grid), dim3(BLK), 0, s, p, sh);
-  else hipLaunchKernelGGL((k_rowop<T, 1>), dim3(grid), dim3(BLK), 0, s, p, sh);
+  int sp = split_of(a.Kv ? a.nnzK : -1, a.nrows, sh);
+  int grid = ceil_div((long)a.nrows << (sh + log2i(sp)), BLK);
+  if (cpl_of(a.w) == 2) SLAMG_DISPATCH_SPLIT(k_rowop, T, 2, sp, grid, s, p, sh);
+  else SLAMG_DISPATCH_SPLIT(k_rowop, T, 1, sp, grid, s, p, sh);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -222,14 +265,9 @@ struct KaczPOD {
   T* x;
 };
 
-template <typename T, int CPL>
-__global__ __launch_bounds__(BLK) void k_kacz(KaczPOD<T> a, int lshift) {
-  long t = (long)blockIdx.x * BLK + threadIdx.x;
-  int idx = (int)(t >> lshift);
-  int c0 = (int)(t & ((1 << lshift) - 1)) * CPL;
+template <typename T, int CPL, int SPLIT>
+__device__ __forceinline__ void kacz_row(const KaczPOD<T>& a, int r, int c0, int sidx, int lprc) {
   const int w = a.w;
-  if (idx >= a.nrows || c0 >= w) return;
-  int r = a.rows[idx];
   T lam[CPL];
 #pragma unroll
   for (int c = 0; c < CPL; ++c) lam[c] = (a.lam && c0 + c < w) ? (T)a.lam[c0 + c] : T(0);
@@ -240,17 +278,20 @@ __global__ __launch_bounds__(BLK) void k_kacz(KaczPOD<T> a, int lshift) {
   for (int c = 0; c < CPL; ++c) rhs[c] = T(0);
   if (a.rmode == M_IDENT || a.rmode == M_CSR) {
     T my[CPL];
-    if (a.rmode == M_IDENT) ldrow<T, CPL>(a.y + (long)r * w, c0, w, my);
-    else {
+    if (a.rmode == M_IDENT) {
+      ldrow<T, CPL>(a.y + (long)r * w, c0, w, my);
+    } else {
 #pragma unroll
       for (int c = 0; c < CPL; ++c) my[c] = T(0);
-      for (int k = a.Mrp[r], ke = a.Mrp[r + 1]; k < ke; ++k) {
+      for (int k = a.Mrp[r] + sidx, ke = a.Mrp[r + 1]; k < ke; k += SPLIT) {
         T yv[CPL];
         ldrow<T, CPL>(a.y + (long)a.Mci[k] * w, c0, w, yv);
         T mv = a.Mv[k];
 #pragma unroll
         for (int c = 0; c < CPL; ++c) my[c] += mv * yv[c];
       }
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) my[c] = split_sum<SPLIT>(my[c], lprc);
     }
 #pragma unroll
     for (int c = 0; c < CPL; ++c) rhs[c] = (c0 + c < w ? (T)a.rsig[c0 + c] : T(0)) * my[c];
@@ -262,10 +303,10 @@ __global__ __launch_bounds__(BLK) void k_kacz(KaczPOD<T> a, int lshift) {
     for (int c = 0; c < CPL; ++c) rhs[c] += kp[c];
   }
   const int kb = a.rp[r], ke = a.rp[r + 1];
-  T res[CPL];
+  T dot[CPL];
 #pragma unroll
-  for (int c = 0; c < CPL; ++c) res[c] = rhs[c];
-  for (int k = kb; k < ke; ++k) {
+  for (int c = 0; c < CPL; ++c) dot[c] = T(0);
+  for (int k = kb + sidx; k < ke; k += SPLIT) {
     int j = a.ci[k];
     T xv[CPL];
     ldrow<T, CPL>(a.x + (long)j * w, c0, w, xv);
@@ -273,10 +314,10 @@ __global__ __launch_bounds__(BLK) void k_kacz(KaczPOD<T> a, int lshift) {
     if (shifted) {
       T bv = a.bv ? a.bv[k] : (j == r ? T(1) : T(0));
 #pragma unroll
-      for (int c = 0; c < CPL; ++c) res[c] -= (av - lam[c] * bv) * xv[c];
+      for (int c = 0; c < CPL; ++c) dot[c] += (av - lam[c] * bv) * xv[c];
     } else {
 #pragma unroll
-      for (int c = 0; c < CPL; ++c) res[c] -= av * xv[c];
+      for (int c = 0; c < CPL; ++c) dot[c] += av * xv[c];
     }
   }
   T coef[CPL];
@@ -284,10 +325,11 @@ __global__ __launch_bounds__(BLK) void k_kacz(KaczPOD<T> a, int lshift) {
   T ab = shifted ? a.rn_ab[r] : T(0), bb = shifted ? a.rn_bb[r] : T(0);
 #pragma unroll
   for (int c = 0; c < CPL; ++c) {
+    T res = rhs[c] - split_sum<SPLIT>(dot[c], lprc);
     T nr = shifted ? aa - T(2) * lam[c] * ab + lam[c] * lam[c] * bb : aa;
-    coef[c] = nr > T(0) ? res[c] / nr : T(0);
+    coef[c] = nr > T(0) ? res / nr : T(0);
   }
-  for (int k = kb; k < ke; ++k) {
+  for (int k = kb + sidx; k < ke; k += SPLIT) {
     int j = a.ci[k];
     T* xp = a.x + (long)j * w;
     T xv[CPL];
@@ -305,15 +347,100 @@ __global__ __launch_bounds__(BLK) void k_kacz(KaczPOD<T> a, int lshift) {
   }
 }
 
+template <typename T, int CPL, int SPLIT>
+__global__ __launch_bounds__(BLK) void k_kacz(KaczPOD<T> a, int lshift) {
+  constexpr int LS = SPLIT == 1 ? 0 : SPLIT == 4 ? 2 : SPLIT == 8 ? 3 : 4;
+  const int gl = lshift + LS;
+  long t = (long)blockIdx.x * BLK + threadIdx.x;
+  int idx = (int)(t >> gl);
+  const int lane = (int)(t & ((1 << gl) - 1));
+  const int sidx = lane >> lshift;
+  int c0 = (lane & ((1 << lshift) - 1)) * CPL;
+  if (idx >= a.nrows || c0 >= a.w) return;
+  kacz_row<T, CPL, SPLIT>(a, a.rows[idx], c0, sidx, 1 << lshift);
+}
+
+// Whole sweeps in one workgroup (small levels): for each of `nsweeps` sweeps, each half-sweep
+// (SVD: rows of A updating v, then rows of A^t updating u), each colour in order; a barrier
+// separates colours, so the result equals the colour-by-colour launches exactly.
+template <typename T>
+struct KaczWgPOD {
+  KaczPOD<T> h[2];
+  const int* cptr[2];     // device colour pointers of each half-sweep
+  int ncol[2];
+  int nhalf, nsweeps;
+};
+
+static constexpr int WGB = 1024;
+
+template <typename T, int CPL, int SPLIT>
+__global__ __launch_bounds__(WGB) void k_kacz_wg(KaczWgPOD<T> a, int lshift) {
+  constexpr int LS = SPLIT == 1 ? 0 : SPLIT == 4 ? 2 : SPLIT == 8 ? 3 : 4;
+  const int gl = lshift + LS;
+  const int per = WGB >> gl;
+  const int my = threadIdx.x >> gl;
+  const int lane = threadIdx.x & ((1 << gl) - 1);
+  const int sidx = lane >> lshift;
+  const int c0 = (lane & ((1 << lshift) - 1)) * CPL;
+  for (int s = 0; s < a.nsweeps; ++s) {
+    for (int h = 0; h < 2; ++h) {
+      if (h >= a.nhalf) break;
+      const KaczPOD<T> k = h == 0 ? a.h[0] : a.h[1];
+      const int* cp = h == 0 ? a.cptr[0] : a.cptr[1];
+      const int nc = h == 0 ? a.ncol[0] : a.ncol[1];
+      for (int c = 0; c < nc; ++c) {
+        const int rb = cp[c], re = cp[c + 1];
+        if (c0 < k.w)
+          for (int idx = rb + my; idx < re; idx += per) kacz_row<T, CPL, SPLIT>(k, k.rows[idx], c0, sidx, 1 << lshift);
+        __syncthreads();
+      }
+    }
+  }
+}
+
+template <typename T>
+void launch_kacz_wg(const KaczArgs<T>* halves, const int* const* cptr, const int* ncol, int nhalf, int nsweeps,
+                    hipStream_t s) {
+  KaczWgPOD<T> p{};
+  long nnz = 0, rows = 0;
+  for (int h = 0; h < nhalf; ++h) {
+    const KaczArgs<T>& a = halves[h];
+    p.h[h] = KaczPOD<T>{0, a.rows, a.w, a.rp, a.ci, a.av, a.bv, a.lam, a.rn_aa, a.rn_ab, a.rn_bb,
+                        a.rmode, a.Mrp, a.Mci, a.Mv, a.y, a.rsig, a.kap, a.x};
+    p.cptr[h] = cptr[h];
+    p.ncol[h] = ncol[h];
+    if (a.nnz_rows > 0 && (double)a.nnz_total / a.nnz_rows > (rows ? (double)nnz / rows : 0.0)) {
+      nnz = a.nnz_total; rows = a.nnz_rows;
+    }
+  }
+  p.nhalf = nhalf;
+  p.nsweeps = nsweeps;
+  const int w = halves[0].w;
+  int sh = lshift_of(w);
+  int sp = split_of(rows ? nnz : -1, rows, sh);
+  if (cpl_of(w) == 2) {
+    if (sp == 1) hipLaunchKernelGGL((k_kacz_wg<T, 2, 1>), dim3(1), dim3(WGB), 0, s, p, sh);
+    else if (sp == 4) hipLaunchKernelGGL((k_kacz_wg<T, 2, 4>), dim3(1), dim3(WGB), 0, s, p, sh);
+    else if (sp == 8) hipLaunchKernelGGL((k_kacz_wg<T, 2, 8>), dim3(1), dim3(WGB), 0, s, p, sh);
+    else hipLaunchKernelGGL((k_kacz_wg<T, 2, 16>), dim3(1), dim3(WGB), 0, s, p, sh);
+  } else {
+    if (sp == 1) hipLaunchKernelGGL((k_kacz_wg<T, 1, 1>), dim3(1), dim3(WGB), 0, s, p, sh);
+    else if (sp == 4) hipLaunchKernelGGL((k_kacz_wg<T, 1, 4>), dim3(1), dim3(WGB), 0, s, p, sh);
+    else if (sp == 8) hipLaunchKernelGGL((k_kacz_wg<T, 1, 8>), dim3(1), dim3(WGB), 0, s, p, sh);
+    else hipLaunchKernelGGL((k_kacz_wg<T, 1, 16>), dim3(1), dim3(WGB), 0, s, p, sh);
+  }
+}
+
 template <typename T>
 void launch_kacz(const KaczArgs<T>& a, hipStream_t s) {
   if (a.nrows <= 0) return;
   KaczPOD<T> p{a.nrows, a.rows, a.w, a.rp, a.ci, a.av, a.bv, a.lam, a.rn_aa, a.rn_ab, a.rn_bb,
                a.rmode, a.Mrp, a.Mci, a.Mv, a.y, a.rsig, a.kap, a.x};
   int sh = lshift_of(a.w);
-  int grid = ceil_div((long)a.nrows << sh, BLK);
-  if (cpl_of(a.w) == 2) hipLaunchKernelGGL((k_kacz<T, 2>), dim3(grid), dim3(BLK), 0, s, p, sh);
-  else hipLaunchKernelGGL((k_kacz<T, 1>), dim3(grid), dim3(BLK), 0, s, p, sh);
+  int sp = split_of(a.nnz_rows > 0 ? a.nnz_total : -1, a.nnz_rows, sh);
+  int grid = ceil_div((long)a.nrows << (sh + log2i(sp)), BLK);
+  if (cpl_of(a.w) == 2) SLAMG_DISPATCH_SPLIT(k_kacz, T, 2, sp, grid, s, p, sh);
+  else SLAMG_DISPATCH_SPLIT(k_kacz, T, 1, sp, grid, s, p, sh);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -330,35 +457,41 @@ int dots_grid(int nrows, int w) {
   return std::max(1, std::min(1024, ceil_div((long)nrows << sh, BLK)));
 }
 
-template <typename T, int CPL>
+template <typename T, int CPL, int SPLIT>
 __global__ __launch_bounds__(BLK) void k_dots(DotPOD<T> a, int lshift, double* partial) {
+  constexpr int LS = SPLIT == 1 ? 0 : SPLIT == 4 ? 2 : SPLIT == 8 ? 3 : 4;
   __shared__ double red[BLK * 2];
+  const int gl = lshift + LS;
   const int w = a.w;
-  int lane = threadIdx.x & ((1 << lshift) - 1);
-  int c0 = lane * CPL;
+  const int lane = threadIdx.x & ((1 << gl) - 1);
+  const int sidx = lane >> lshift;
+  int c0 = (lane & ((1 << lshift) - 1)) * CPL;
   double acc[CPL];
 #pragma unroll
   for (int c = 0; c < CPL; ++c) acc[c] = 0.0;
-  int stride = (gridDim.x * BLK) >> lshift;
+  int stride = (gridDim.x * BLK) >> gl;
   if (c0 < w) {
     double sc[CPL];
 #pragma unroll
     for (int c = 0; c < CPL; ++c) sc[c] = (a.sig && c0 + c < w) ? a.sig[c0 + c] : 0.0;
-    for (int row = (int)(((long)blockIdx.x * BLK + threadIdx.x) >> lshift); row < a.nrows; row += stride) {
+    for (int row = (int)(((long)blockIdx.x * BLK + threadIdx.x) >> gl); row < a.nrows; row += stride) {
       T val[CPL];
       if (a.Kv) {
 #pragma unroll
         for (int c = 0; c < CPL; ++c) val[c] = T(0);
-        for (int k = a.Krp[row], ke = a.Krp[row + 1]; k < ke; ++k) {
+        for (int k = a.Krp[row] + sidx, ke = a.Krp[row + 1]; k < ke; k += SPLIT) {
           T zv[CPL];
           ldrow<T, CPL>(a.z + (long)a.Kci[k] * w, c0, w, zv);
           T av = a.Kv[k];
 #pragma unroll
           for (int c = 0; c < CPL; ++c) val[c] += av * zv[c];
         }
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) val[c] = split_sum<SPLIT>(val[c], 1 << lshift);
       } else {
         ldrow<T, CPL>(a.z + (long)row * w, c0, w, val);
       }
+      if (sidx != 0) continue;
       if (a.y) {
         T yv[CPL];
         ldrow<T, CPL>(a.y + (long)row * w, c0, w, yv);
@@ -388,12 +521,21 @@ __global__ __launch_bounds__(BLK) void k_dots(DotPOD<T> a, int lshift, double* p
   }
 }
 
-__global__ void k_finalize(int nparts, int w, const double* __restrict__ partial, double* __restrict__ out) {
-  int c = threadIdx.x;
-  if (c >= w) return;
+// Fixed-order finalisation: one workgroup per output column; thread t sums partials t, t+256, ...
+// in order, then a fixed tree in LDS.
+__global__ __launch_bounds__(BLK) void k_finalize(int nparts, int w, const double* __restrict__ partial,
+                                                  double* __restrict__ out) {
+  __shared__ double red[BLK];
+  const int c = blockIdx.x;
   double s = 0.0;
-  for (int b = 0; b < nparts; ++b) s += partial[(long)b * w + c];
-  out[c] = s;
+  for (int b = threadIdx.x; b < nparts; b += BLK) s += partial[(long)b * w + c];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = BLK / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[c] = red[0];
 }
 
 template <typename T>
@@ -405,9 +547,10 @@ void launch_dots(const DotArgs<T>& a, double* partial, double* out, hipStream_t 
   }
   DotPOD<T> p{a.nrows, a.w, a.a, a.Krp, a.Kci, a.Kv, a.z, a.y, a.sig};
   int sh = lshift_of(a.w);
-  if (cpl_of(a.w) == 2) hipLaunchKernelGGL((k_dots<T, 2>), dim3(grid), dim3(BLK), 0, s, p, sh, partial);
-  else hipLaunchKernelGGL((k_dots<T, 1>), dim3(grid), dim3(BLK), 0, s, p, sh, partial);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, grid, a.w, partial, out);
+  int sp = split_of(a.Kv ? a.nnzK : -1, a.nrows, sh);
+  if (cpl_of(a.w) == 2) SLAMG_DISPATCH_SPLIT(k_dots, T, 2, sp, grid, s, p, sh, partial);
+  else SLAMG_DISPATCH_SPLIT(k_dots, T, 1, sp, grid, s, p, sh, partial);
+  hipLaunchKernelGGL(k_finalize, dim3(a.w), dim3(BLK), 0, s, grid, a.w, partial, out);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -442,19 +585,27 @@ __global__ __launch_bounds__(BLK) void k_gram(int rows, int w, const double* __r
   partial[(long)blockIdx.x * 256 + tt] = ((red[0][tt] + red[1][tt]) + red[2][tt]) + red[3][tt];
 }
 
-__global__ void k_gram_finalize(int nparts, int w, const double* __restrict__ partial, double* __restrict__ G) {
-  int t = threadIdx.x;       // 256 threads
-  int i = t >> 4, j = t & 15;
-  if (i >= w || j >= w) return;
+// one workgroup per entry (i, j) of the w x w result; fixed-order reduction over the partials
+__global__ __launch_bounds__(BLK) void k_gram_finalize(int nparts, int w, const double* __restrict__ partial,
+                                                       double* __restrict__ G) {
+  __shared__ double red[BLK];
+  const int i = blockIdx.x / w, j = blockIdx.x % w;
+  const int e = i * 16 + j;
   double s = 0.0;
-  for (int b = 0; b < nparts; ++b) s += partial[(long)b * 256 + t];
-  G[i * w + j] = s;
+  for (int b = threadIdx.x; b < nparts; b += BLK) s += partial[(long)b * 256 + e];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = BLK / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) G[i * w + j] = red[0];
 }
 
 void launch_gram(int rows, int w, const double* X, const double* Y, double* partial, double* G, hipStream_t s) {
   int grid = gram_grid(rows);
   hipLaunchKernelGGL(k_gram, dim3(grid), dim3(BLK), 0, s, rows, w, X, Y, partial);
-  hipLaunchKernelGGL(k_gram_finalize, dim3(1), dim3(256), 0, s, grid, w, partial, G);
+  hipLaunchKernelGGL(k_gram_finalize, dim3(w * w), dim3(BLK), 0, s, grid, w, partial, G);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -853,13 +1004,15 @@ void launch_scatter_out(int rows, int w, const double* X, const int* keep, const
 
 // explicit instantiations
 template void launch_spmm<double>(int, int, const int*, const int*, const double*, const double*, double*, double,
-                                  hipStream_t);
+                                  hipStream_t, int);
 template void launch_spmm<float>(int, int, const int*, const int*, const float*, const float*, float*, double,
-                                 hipStream_t);
+                                 hipStream_t, int);
 template void launch_rowop<double>(const RowOpArgs<double>&, hipStream_t);
 template void launch_rowop<float>(const RowOpArgs<float>&, hipStream_t);
 template void launch_kacz<double>(const KaczArgs<double>&, hipStream_t);
 template void launch_kacz<float>(const KaczArgs<float>&, hipStream_t);
+template void launch_kacz_wg<double>(const KaczArgs<double>*, const int* const*, const int*, int, int, hipStream_t);
+template void launch_kacz_wg<float>(const KaczArgs<float>*, const int* const*, const int*, int, int, hipStream_t);
 template void launch_dots<double>(const DotArgs<double>&, double*, double*, hipStream_t);
 template void launch_dots<float>(const DotArgs<float>&, double*, double*, hipStream_t);
 template void launch_rotate<double>(int, int, int, const double*, const double*, double*, hipStream_t);

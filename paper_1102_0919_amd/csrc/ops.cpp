@@ -61,6 +61,14 @@ void down(T* h, const T* d, size_t n, hipStream_t s) {
 
 bool bad_w(int w) { return w < 1 || w > 16; }
 
+// Nonzero count of a device CSR operator (its last row pointer); chooses the kernels' row split.
+int dev_nnz(const int* rp, int m, hipStream_t s) {
+  if (!rp || m <= 0) return -1;
+  int v = 0;
+  down(&v, rp + m, 1, s);
+  return v;
+}
+
 // one Jacobi-type half step: out = x + D (a K z - w M y ...) then optional normalisation; copy to x
 void jac_half(hipStream_t s, Tmp& t, int rows, int w, const int* krp, const int* kci, const double* kv,
               const double* z, int mmode, const int* mrp, const int* mci, const double* mv, double* x,
@@ -76,14 +84,15 @@ void jac_half(hipStream_t s, Tmp& t, int rows, int w, const int* krp, const int*
   a.nrows = rows; a.w = w; a.Krp = krp; a.Kci = kci; a.Kv = kv; a.z = z;
   a.mmode = mmode; a.Mrp = mrp; a.Mci = mci; a.Mv = mv; a.y = x; a.x = x; a.D = dinv; a.kap = kap; a.sig = sig;
   a.cmode = cmode; a.omega = omega; a.out = out;
+  a.nnzK = dev_nnz(krp, rows, s);
   launch_rowop(a, s);
   if (normalise) {
     double* part = t.get<double>(1024 * 16);
     double* nrm = t.get<double>(16);
     DotArgs<double> d;
     d.nrows = rows; d.w = w; d.a = out; d.z = out;
-    if (mmode == M_SHARED) { d.Krp = krp; d.Kci = kci; d.Kv = mv; }
-    if (mmode == M_CSR) { d.Krp = mrp; d.Kci = mci; d.Kv = mv; }
+    if (mmode == M_SHARED) { d.Krp = krp; d.Kci = kci; d.Kv = mv; d.nnzK = a.nnzK; }
+    if (mmode == M_CSR) { d.Krp = mrp; d.Kci = mci; d.Kv = mv; d.nnzK = dev_nnz(mrp, rows, s); }
     launch_dots(d, part, nrm, s);
     launch_scale_cols<double>(rows, w, out, nrm, 0, s);
   }
@@ -96,14 +105,14 @@ extern "C" slamg_status slamg_op_spmm(int32_t m, int32_t w, const int32_t* d_rp,
                                       const double* d_v, const double* d_x, double* d_y, double beta, void* stream) {
   if (m < 0 || bad_w(w)) return SLAMG_E_INVALID;
   hipStream_t s = (hipStream_t)stream;
-  return guarded(s, [&] { launch_spmm<double>(m, w, d_rp, d_ci, d_v, d_x, d_y, beta, s); });
+  return guarded(s, [&] { launch_spmm<double>(m, w, d_rp, d_ci, d_v, d_x, d_y, beta, s, dev_nnz(d_rp, m, s)); });
 }
 
 extern "C" slamg_status slamg_op_spmm_f32(int32_t m, int32_t w, const int32_t* d_rp, const int32_t* d_ci,
                                           const float* d_v, const float* d_x, float* d_y, double beta, void* stream) {
   if (m < 0 || bad_w(w)) return SLAMG_E_INVALID;
   hipStream_t s = (hipStream_t)stream;
-  return guarded(s, [&] { launch_spmm<float>(m, w, d_rp, d_ci, d_v, d_x, d_y, beta, s); });
+  return guarded(s, [&] { launch_spmm<float>(m, w, d_rp, d_ci, d_v, d_x, d_y, beta, s, dev_nnz(d_rp, m, s)); });
 }
 
 extern "C" slamg_status slamg_op_relax_test(int32_t spd, int32_t m, int32_t n, int32_t w, const int32_t* d_arp,
@@ -165,6 +174,7 @@ extern "C" slamg_status slamg_op_kaczmarz(int32_t nrows, int32_t ncols, int32_t 
     double* bb = t.get<double>(nrows);
     launch_row_sq(nrows, d_rp, d_v, d_bv, aa, ab, bb, d_ci, s);
     const int total = h_cptr[ncolours];
+    const long nnz = dev_nnz(d_rp, nrows, s);
     int* rows = t.get<int>(total);
     up(rows, h_rows, total, s);
     for (int c = 0; c < ncolours; ++c) {
@@ -172,6 +182,7 @@ extern "C" slamg_status slamg_op_kaczmarz(int32_t nrows, int32_t ncols, int32_t 
       k.nrows = h_cptr[c + 1] - h_cptr[c]; k.rows = rows + h_cptr[c]; k.w = w;
       k.rp = d_rp; k.ci = d_ci; k.av = d_v; k.bv = d_bv; k.lam = d_lam;
       k.rn_aa = aa; k.rn_ab = ab; k.rn_bb = bb; k.kap = d_rhs; k.x = d_x;
+      k.nnz_total = nnz; k.nnz_rows = nrows;
       launch_kacz(k, s);
     }
   });
@@ -188,6 +199,7 @@ extern "C" slamg_status slamg_op_residual(int32_t nrows, int32_t w, const int32_
     a.nrows = nrows; a.w = w; a.Krp = d_krp; a.Kci = d_kci; a.Kv = d_kv; a.z = d_z;
     a.mmode = d_mv ? M_CSR : M_IDENT; a.Mrp = d_mrp; a.Mci = d_mci; a.Mv = d_mv; a.y = d_y;
     a.kap = d_kap; a.sig = d_sig; a.cmode = C_RESID; a.out = d_out;
+    a.nnzK = dev_nnz(d_krp, nrows, s);
     launch_rowop(a, s);
   });
 }
@@ -204,6 +216,7 @@ extern "C" slamg_status slamg_op_dots(int32_t nrows, int32_t w, const double* d_
     DotArgs<double> d;
     d.nrows = nrows; d.w = w; d.a = d_a; d.Krp = d_krp; d.Kci = d_kci; d.Kv = d_kv; d.z = d_z; d.y = d_y;
     d.sig = d_sig;
+    if (d_kv) d.nnzK = dev_nnz(d_krp, nrows, s);
     launch_dots(d, part, out, s);
     down(h_out, out, w, s);
   });

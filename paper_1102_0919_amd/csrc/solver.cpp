@@ -114,6 +114,7 @@ template <class T>
 struct Blocks {
   T *Ut = nullptr, *Vt = nullptr;          // test vectors (mult phase, FP64 only)
   T *Ub = nullptr, *Vb = nullptr;          // boot vectors / additive iterates (contiguous)
+  T *Ua = nullptr, *Va = nullptr;          // second contiguous pair: relaxation writes here, then swaps
   T *kap = nullptr, *tau = nullptr;        // restricted residuals (contiguous)
   T *tU = nullptr, *tV = nullptr, *tU2 = nullptr, *tV2 = nullptr;
 };
@@ -133,6 +134,9 @@ struct Level {
   // Kaczmarz orders (minimal targets)
   int* kA_rows = nullptr;  std::vector<int> kA_cptr;  std::vector<long> kA_cnnz;
   int* kAt_rows = nullptr; std::vector<int> kAt_cptr; std::vector<long> kAt_cnnz;
+  int* d_kA_cptr = nullptr;
+  int* d_kAt_cptr = nullptr;
+  bool kacz_wg = false;     // small level: whole sweeps in one workgroup
   // minimal LS pre-smoothing scales
   double* smU = nullptr;    // 1 / diag(N_u)
   double* smV = nullptr;    // 1 / diag(N_v)
@@ -185,7 +189,7 @@ class Solver {
   void inject(int l, int cycle);
   void coarsest_mult();
   void mult_cycle(int c);
-  template <class T> void boot_relax(int l, const T* kap, const T* tau, const double* sig);
+  template <class T> void boot_relax(int l, const T* kap, const T* tau, const double* sig, int nsweeps = 1);
   template <class T> void additive_vcycle(const double* sig, T* rhsU, T* rhsV);
   void additive_iteration();
   void ritz();
@@ -236,9 +240,7 @@ class Solver {
   int pmask_ = 0;
   template <class F> void prof(int cls, double bytes, F&& f) {
     if (!((pmask_ >> cls) & 1)) { f(); return; }
-    ProfEv e{nullptr, nullptr, cls};
-    HIPCHK(hipEventCreate(&e.a));
-    HIPCHK(hipEventCreate(&e.b));
+    ProfEv e{event(), event(), cls};
     HIPCHK(hipEventRecord(e.a, st_));
     f();
     HIPCHK(hipEventRecord(e.b, st_));
@@ -247,6 +249,21 @@ class Solver {
     pn_[cls] += 1;
   }
   void prof_finish();
+  // events are reused across solves (creating one per launch would dominate the host time)
+  static std::vector<hipEvent_t>& event_pool() {
+    static std::vector<hipEvent_t> pool;
+    return pool;
+  }
+  size_t ev_used_ = 0;
+  hipEvent_t event() {
+    auto& pool = event_pool();
+    if (ev_used_ == pool.size()) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      pool.push_back(e);
+    }
+    return pool[ev_used_++];
+  }
   template <class T> void rowop(int l, const RowOpArgs<T>& a, const DCsr* K);
   template <class T> void spmm(int l, const DCsr& K, const T* Kv, int w, const T* x, T* y, double beta);
   template <class T> void dots(int l, const DotArgs<T>& a, const DCsr* K, double* out);
@@ -270,7 +287,9 @@ static double rowop_bytes(const RowOpArgs<T>& a, const DCsr* K) {
 }
 
 template <class T>
-void Solver::rowop(int l, const RowOpArgs<T>& a, const DCsr* K) {
+void Solver::rowop(int l, const RowOpArgs<T>& a0, const DCsr* K) {
+  RowOpArgs<T> a = a0;
+  if (a.nnzK < 0 && K) a.nnzK = K->nnz;
   if (l == 0) prof(0, rowop_bytes(a, K), [&] { launch_rowop(a, st_); });
   else launch_rowop(a, st_);
 }
@@ -279,8 +298,8 @@ template <class T>
 void Solver::spmm(int l, const DCsr& K, const T* Kv, int w, const T* x, T* y, double beta) {
   const double sz = sizeof(T);
   const double bytes = 4.0 * (K.m + 1) + (4.0 + sz) * K.nnz + sz * w * ((double)K.n + K.m * (beta != 0.0 ? 2 : 1));
-  if (l == 0) prof(0, bytes, [&] { launch_spmm<T>(K.m, w, K.rp, K.ci, Kv, x, y, beta, st_); });
-  else launch_spmm<T>(K.m, w, K.rp, K.ci, Kv, x, y, beta, st_);
+  if (l == 0) prof(0, bytes, [&] { launch_spmm<T>(K.m, w, K.rp, K.ci, Kv, x, y, beta, st_, K.nnz); });
+  else launch_spmm<T>(K.m, w, K.rp, K.ci, Kv, x, y, beta, st_, K.nnz);
 }
 
 template <class T>
@@ -294,7 +313,10 @@ void Solver::dots(int l, const DotArgs<T>& a, const DCsr* K, double* out) {
 }
 
 template <class T>
-void Solver::kacz(int l, const KaczArgs<T>& a, long nnz_colour) {
+void Solver::kacz(int l, const KaczArgs<T>& a0, long nnz_colour) {
+  KaczArgs<T> a = a0;
+  a.nnz_total = nnz_colour;
+  a.nnz_rows = a.nrows;
   const double sz = sizeof(T), w = a.w, r = a.nrows, z = (double)nnz_colour;
   double b = r * (8.0 + 4.0 + sz) + (4.0 + sz) * z + 2.0 * sz * w * z;
   if (a.bv) b += sz * z;
@@ -317,10 +339,9 @@ void Solver::prof_finish() {
     float t = 0.0f;
     HIPCHK(hipEventElapsedTime(&t, e.a, e.b));
     ms[e.cls] += t;
-    (void)hipEventDestroy(e.a);
-    (void)hipEventDestroy(e.b);
   }
   pev_.clear();
+  ev_used_ = 0;
   for (int c = 0; c < 8; ++c) {
     rep_.prof_ms[c] = ms[c];
     rep_.prof_launches[c] = pn_[c];
@@ -351,6 +372,8 @@ void Solver::alloc_level_buffers(Level& L) {
     b.Vt = ar_.alloc<double>((size_t)mv * nt_);
     double* UV = ar_.alloc<double>((size_t)(mu + mv) * nb_);
     b.Ub = UV; b.Vb = UV + (size_t)mu * nb_;
+    double* UV2 = ar_.alloc<double>((size_t)(mu + mv) * nb_);
+    b.Ua = UV2; b.Va = UV2 + (size_t)mu * nb_;
     double* KT = ar_.alloc<double>((size_t)(mu + mv) * nb_);
     b.kap = KT; b.tau = KT + (size_t)mu * nb_;
     b.tU = ar_.alloc<double>((size_t)mu * wmax);
@@ -360,6 +383,7 @@ void Solver::alloc_level_buffers(Level& L) {
   } else {
     b.Ut = ar_.alloc<double>((size_t)mu * nt_);
     b.Ub = ar_.alloc<double>((size_t)mu * nb_);
+    b.Ua = ar_.alloc<double>((size_t)mu * nb_);
     b.kap = ar_.alloc<double>((size_t)mu * nb_);
     b.tU = ar_.alloc<double>((size_t)mu * wmax);
     b.tU2 = ar_.alloc<double>((size_t)mu * wmax);
@@ -382,12 +406,15 @@ void Solver::alloc_level_buffers(Level& L) {
     if (!spd_) {
       float* UV = ar_.alloc<float>((size_t)(mu + mv) * nb_);
       f.Ub = UV; f.Vb = UV + (size_t)mu * nb_;
+      float* UV2 = ar_.alloc<float>((size_t)(mu + mv) * nb_);
+      f.Ua = UV2; f.Va = UV2 + (size_t)mu * nb_;
       float* KT = ar_.alloc<float>((size_t)(mu + mv) * nb_);
       f.kap = KT; f.tau = KT + (size_t)mu * nb_;
       f.tU = ar_.alloc<float>((size_t)mu * nb_);
       f.tV = ar_.alloc<float>((size_t)mv * nb_);
     } else {
       f.Ub = ar_.alloc<float>((size_t)mu * nb_);
+      f.Ua = ar_.alloc<float>((size_t)mu * nb_);
       f.kap = ar_.alloc<float>((size_t)mu * nb_);
       f.tU = ar_.alloc<float>((size_t)mu * nb_);
     }
@@ -440,6 +467,9 @@ void Solver::refresh_level_aux(Level& L) {
   }
 }
 
+// Levels with at most this many rows run whole Kaczmarz sweeps (all colours) in one workgroup.
+static const int KACZ_WG_MAX_ROWS = 4096;
+
 static std::vector<long> colour_nnz(const HCsr& A, const std::vector<int>& rows, const std::vector<int>& cptr) {
   std::vector<long> z(cptr.size() > 0 ? cptr.size() - 1 : 0, 0);
   for (size_t c = 0; c + 1 < cptr.size(); ++c)
@@ -457,6 +487,9 @@ void Solver::colour(Level& L) {
     h2d(L.kA_rows, rows, st_);
     L.kA_cptr = cptr;
     L.kA_cnnz = colour_nnz(pat, rows, cptr);
+    L.d_kA_cptr = ar_.alloc<int>(cptr.size());
+    h2d(L.d_kA_cptr, cptr, st_);
+    L.kacz_wg = L.m <= KACZ_WG_MAX_ROWS;
   } else {
     colour_order(greedy_row_colouring(L.hA), rows, cptr);
     L.kA_rows = ar_.alloc<int>(rows.size());
@@ -469,6 +502,11 @@ void Solver::colour(Level& L) {
     h2d(L.kAt_rows, rows2, st_);
     L.kAt_cptr = cptr2;
     L.kAt_cnnz = colour_nnz(L.hAt, rows2, cptr2);
+    L.d_kA_cptr = ar_.alloc<int>(cptr.size());
+    h2d(L.d_kA_cptr, cptr, st_);
+    L.d_kAt_cptr = ar_.alloc<int>(cptr2.size());
+    h2d(L.d_kAt_cptr, cptr2, st_);
+    L.kacz_wg = std::max(L.m, L.n) <= KACZ_WG_MAX_ROWS;
   }
   sync();
 }
@@ -567,15 +605,15 @@ void Solver::norm_estimate() {
   launch_dots<double>(da, partial_, r1_, st_);
   launch_scale_cols<double>(n, 1, x, r1_, 0, st_);
   for (int it = 0; it < 30; ++it) {
-    launch_spmm<double>(m, 1, L.A.rp, L.A.ci, L.A.v, x, t, 0.0, st_);
-    launch_spmm<double>(n, 1, L.At.rp, L.At.ci, L.At.v, t, y, 0.0, st_);
+    launch_spmm<double>(m, 1, L.A.rp, L.A.ci, L.A.v, x, t, 0.0, st_, L.A.nnz);
+    launch_spmm<double>(n, 1, L.At.rp, L.At.ci, L.At.v, t, y, 0.0, st_, L.At.nnz);
     da = DotArgs<double>{};
     da.nrows = n; da.w = 1; da.a = y; da.z = y;
     launch_dots<double>(da, partial_, r1_, st_);
     HIPCHK(hipMemcpyAsync(x, y, sizeof(double) * n, hipMemcpyDeviceToDevice, st_));
     launch_scale_cols<double>(n, 1, x, r1_, 0, st_);
   }
-  launch_spmm<double>(m, 1, L.A.rp, L.A.ci, L.A.v, x, t, 0.0, st_);
+  launch_spmm<double>(m, 1, L.A.rp, L.A.ci, L.A.v, x, t, 0.0, st_, L.A.nnz);
   da = DotArgs<double>{};
   da.nrows = m; da.w = 1; da.a = t; da.z = t;
   launch_dots<double>(da, partial_, r1_, st_);
@@ -805,40 +843,40 @@ void Solver::relax_tests(int l) {
         // x_bar = x - w D_B^-1 (B x - A x),  x = x_bar / ||x_bar||_B
         RowOpArgs<double> a;
         a.nrows = mu; a.w = nt_;
-        a.Krp = L.A.rp; a.Kci = L.A.ci; a.Kv = L.A.v; a.z = b.Ut;
+        a.Krp = L.A.rp; a.Kci = L.A.ci; a.nnzK = L.A.nnz; a.Kv = L.A.v; a.z = b.Ut;
         a.mmode = L.finest ? M_IDENT : M_SHARED; a.Mv = L.B.v; a.y = b.Ut;
         a.x = b.Ut; a.D = L.ad.dinvB; a.cmode = C_JAC_TEST; a.omega = p_.omega_J; a.out = b.tU;
         rowop(l, a, &L.A);
         std::swap(b.Ut, b.tU);
         da = DotArgs<double>{};
         da.nrows = mu; da.w = nt_; da.a = b.Ut; da.z = b.Ut;
-        if (!L.finest) { da.Krp = L.A.rp; da.Kci = L.A.ci; da.Kv = L.B.v; }
+        if (!L.finest) { da.Krp = L.A.rp; da.Kci = L.A.ci; da.nnzK = L.A.nnz; da.Kv = L.B.v; }
         launch_dots(da, partial_, r1_, st_);
         launch_scale_cols<double>(mu, nt_, b.Ut, r1_, 0, st_);
       } else {
         // v_bar = v - w D_C^-1 (C v - A^t u), normalised in C; then u likewise with A v and B
         RowOpArgs<double> a;
         a.nrows = mv; a.w = nt_;
-        a.Krp = L.At.rp; a.Kci = L.At.ci; a.Kv = L.At.v; a.z = b.Ut;
+        a.Krp = L.At.rp; a.Kci = L.At.ci; a.nnzK = L.At.nnz; a.Kv = L.At.v; a.z = b.Ut;
         a.mmode = L.finest ? M_IDENT : M_CSR; a.Mrp = L.C.rp; a.Mci = L.C.ci; a.Mv = L.C.v; a.y = b.Vt;
         a.x = b.Vt; a.D = L.ad.dinvC; a.cmode = C_JAC_TEST; a.omega = p_.omega_J; a.out = b.tV;
         rowop(l, a, &L.At);
         std::swap(b.Vt, b.tV);
         da = DotArgs<double>{};
         da.nrows = mv; da.w = nt_; da.a = b.Vt; da.z = b.Vt;
-        if (!L.finest) { da.Krp = L.C.rp; da.Kci = L.C.ci; da.Kv = L.C.v; }
+        if (!L.finest) { da.Krp = L.C.rp; da.Kci = L.C.ci; da.nnzK = L.C.nnz; da.Kv = L.C.v; }
         launch_dots(da, partial_, r1_, st_);
         launch_scale_cols<double>(mv, nt_, b.Vt, r1_, 0, st_);
         RowOpArgs<double> c;
         c.nrows = mu; c.w = nt_;
-        c.Krp = L.A.rp; c.Kci = L.A.ci; c.Kv = L.A.v; c.z = b.Vt;
+        c.Krp = L.A.rp; c.Kci = L.A.ci; c.nnzK = L.A.nnz; c.Kv = L.A.v; c.z = b.Vt;
         c.mmode = L.finest ? M_IDENT : M_CSR; c.Mrp = L.B.rp; c.Mci = L.B.ci; c.Mv = L.B.v; c.y = b.Ut;
         c.x = b.Ut; c.D = L.ad.dinvB; c.cmode = C_JAC_TEST; c.omega = p_.omega_J; c.out = b.tU;
         rowop(l, c, &L.A);
         std::swap(b.Ut, b.tU);
         da = DotArgs<double>{};
         da.nrows = mu; da.w = nt_; da.a = b.Ut; da.z = b.Ut;
-        if (!L.finest) { da.Krp = L.B.rp; da.Kci = L.B.ci; da.Kv = L.B.v; }
+        if (!L.finest) { da.Krp = L.B.rp; da.Kci = L.B.ci; da.nnzK = L.B.nnz; da.Kv = L.B.v; }
         launch_dots(da, partial_, r1_, st_);
         launch_scale_cols<double>(mu, nt_, b.Ut, r1_, 0, st_);
       }
@@ -853,24 +891,51 @@ void Solver::relax_tests(int l) {
           kacz(l, k, cnnz[c]);
         }
       };
-      if (spd_) {
+      if (L.kacz_wg) {
+        KaczArgs<double> h[2];
+        const int* cp[2];
+        int nc[2];
+        h[0].nnz_total = L.A.nnz; h[0].nnz_rows = L.A.m;
+        h[0].rows = L.kA_rows; h[0].w = nt_; h[0].rp = L.A.rp; h[0].ci = L.A.ci; h[0].av = L.A.v;
+        h[0].rn_aa = L.ad.rnA; h[0].x = spd_ ? b.Ut : b.Vt;
+        cp[0] = L.d_kA_cptr; nc[0] = (int)L.kA_cptr.size() - 1;
+        if (!spd_) {
+          h[1].nnz_total = L.At.nnz; h[1].nnz_rows = L.At.m;
+          h[1].rows = L.kAt_rows; h[1].w = nt_; h[1].rp = L.At.rp; h[1].ci = L.At.ci; h[1].av = L.At.v;
+          h[1].rn_aa = L.ad.rnAt; h[1].x = b.Ut;
+          cp[1] = L.d_kAt_cptr; nc[1] = (int)L.kAt_cptr.size() - 1;
+        }
+        launch_kacz_wg<double>(h, cp, nc, spd_ ? 1 : 2, 1, st_);
+        da = DotArgs<double>{};
+        da.nrows = mu; da.w = nt_; da.a = b.Ut; da.z = b.Ut;
+        if (!L.finest) { da.Krp = spd_ ? L.A.rp : L.B.rp; da.Kci = spd_ ? L.A.ci : L.B.ci; da.nnzK = spd_ ? L.A.nnz : L.B.nnz; da.Kv = L.B.v; }
+        launch_dots(da, partial_, r1_, st_);
+        launch_scale_cols<double>(mu, nt_, b.Ut, r1_, 0, st_);
+        if (!spd_) {
+          da = DotArgs<double>{};
+          da.nrows = mv; da.w = nt_; da.a = b.Vt; da.z = b.Vt;
+          if (!L.finest) { da.Krp = L.C.rp; da.Kci = L.C.ci; da.nnzK = L.C.nnz; da.Kv = L.C.v; }
+          launch_dots(da, partial_, r1_, st_);
+          launch_scale_cols<double>(mv, nt_, b.Vt, r1_, 0, st_);
+        }
+      } else if (spd_) {
         sweep(L.A, L.kA_rows, L.kA_cptr, L.ad.rnA, b.Ut, L.kA_cnnz);
         da = DotArgs<double>{};
         da.nrows = mu; da.w = nt_; da.a = b.Ut; da.z = b.Ut;
-        if (!L.finest) { da.Krp = L.A.rp; da.Kci = L.A.ci; da.Kv = L.B.v; }
+        if (!L.finest) { da.Krp = L.A.rp; da.Kci = L.A.ci; da.nnzK = L.A.nnz; da.Kv = L.B.v; }
         launch_dots(da, partial_, r1_, st_);
         launch_scale_cols<double>(mu, nt_, b.Ut, r1_, 0, st_);
       } else {
         sweep(L.A, L.kA_rows, L.kA_cptr, L.ad.rnA, b.Vt, L.kA_cnnz);
         da = DotArgs<double>{};
         da.nrows = mv; da.w = nt_; da.a = b.Vt; da.z = b.Vt;
-        if (!L.finest) { da.Krp = L.C.rp; da.Kci = L.C.ci; da.Kv = L.C.v; }
+        if (!L.finest) { da.Krp = L.C.rp; da.Kci = L.C.ci; da.nnzK = L.C.nnz; da.Kv = L.C.v; }
         launch_dots(da, partial_, r1_, st_);
         launch_scale_cols<double>(mv, nt_, b.Vt, r1_, 0, st_);
         sweep(L.At, L.kAt_rows, L.kAt_cptr, L.ad.rnAt, b.Ut, L.kAt_cnnz);
         da = DotArgs<double>{};
         da.nrows = mu; da.w = nt_; da.a = b.Ut; da.z = b.Ut;
-        if (!L.finest) { da.Krp = L.B.rp; da.Kci = L.B.ci; da.Kv = L.B.v; }
+        if (!L.finest) { da.Krp = L.B.rp; da.Kci = L.B.ci; da.nnzK = L.B.nnz; da.Kv = L.B.v; }
         launch_dots(da, partial_, r1_, st_);
         launch_scale_cols<double>(mu, nt_, b.Ut, r1_, 0, st_);
       }
@@ -880,40 +945,71 @@ void Solver::relax_tests(int l) {
 
 // One boot relaxation (no sigma update) on level l with right-hand sides kap, tau (null: zero).
 template <class T>
-void Solver::boot_relax(int l, const T* kap, const T* tau, const double* sig) {
+void Solver::boot_relax(int l, const T* kap, const T* tau, const double* sig, int nsweeps) {
   Level& L = *lv_[l];
   Blocks<T>& b = blocks<T>(L);
   Aux<T>& x = aux<T>(L);
   const int mu = rows_u(L), mv = rows_v(L);
+  if (minimal_ && L.kacz_wg) {
+    // all nsweeps sweeps, all colours, in one workgroup
+    KaczArgs<T> h[2];
+    const int* cp[2];
+    int nc[2];
+    if (spd_) {
+      h[0].nnz_total = L.A.nnz; h[0].nnz_rows = L.A.m;
+      h[0].rows = L.kA_rows; h[0].w = nb_; h[0].rp = L.A.rp; h[0].ci = L.A.ci; h[0].av = vals<T>(L.A);
+      h[0].bv = L.finest ? nullptr : vals<T>(L.B); h[0].lam = sig;
+      h[0].rn_aa = x.rnA; h[0].rn_ab = x.rnAab; h[0].rn_bb = x.rnAbb; h[0].kap = kap; h[0].x = b.Ub;
+      cp[0] = L.d_kA_cptr; nc[0] = (int)L.kA_cptr.size() - 1;
+      launch_kacz_wg<T>(h, cp, nc, 1, nsweeps, st_);
+    } else {
+      h[0].nnz_total = L.A.nnz; h[0].nnz_rows = L.A.m;
+      h[0].rows = L.kA_rows; h[0].w = nb_; h[0].rp = L.A.rp; h[0].ci = L.A.ci; h[0].av = vals<T>(L.A);
+      h[0].rn_aa = x.rnA; h[0].rmode = L.finest ? M_IDENT : M_CSR; h[0].Mrp = L.B.rp; h[0].Mci = L.B.ci;
+      h[0].Mv = vals<T>(L.B); h[0].y = b.Ub; h[0].rsig = sig; h[0].kap = kap; h[0].x = b.Vb;
+      h[1].nnz_total = L.At.nnz; h[1].nnz_rows = L.At.m;
+      h[1].rows = L.kAt_rows; h[1].w = nb_; h[1].rp = L.At.rp; h[1].ci = L.At.ci; h[1].av = vals<T>(L.At);
+      h[1].rn_aa = x.rnAt; h[1].rmode = L.finest ? M_IDENT : M_CSR; h[1].Mrp = L.C.rp; h[1].Mci = L.C.ci;
+      h[1].Mv = vals<T>(L.C); h[1].y = b.Vb; h[1].rsig = sig; h[1].kap = tau; h[1].x = b.Ub;
+      cp[0] = L.d_kA_cptr; nc[0] = (int)L.kA_cptr.size() - 1;
+      cp[1] = L.d_kAt_cptr; nc[1] = (int)L.kAt_cptr.size() - 1;
+      launch_kacz_wg<T>(h, cp, nc, 2, nsweeps, st_);
+    }
+    return;
+  }
+  if (nsweeps > 1) {
+    for (int it = 0; it < nsweeps; ++it) boot_relax<T>(l, kap, tau, sig, 1);
+    return;
+  }
   if (!minimal_) {
     if (spd_) {
       // x <- x - w D_B^-1 (B x - (A x - kappa)/lambda)
       RowOpArgs<T> a;
       a.nrows = mu; a.w = nb_;
-      a.Krp = L.A.rp; a.Kci = L.A.ci; a.Kv = vals<T>(L.A); a.z = b.Ub;
+      a.Krp = L.A.rp; a.Kci = L.A.ci; a.nnzK = L.A.nnz; a.Kv = vals<T>(L.A); a.z = b.Ub;
       a.mmode = L.finest ? M_IDENT : M_SHARED; a.Mv = vals<T>(L.B); a.y = b.Ub;
       a.x = b.Ub; a.D = x.dinvB; a.kap = kap; a.sig = sig; a.cmode = C_JAC_BOOT; a.omega = p_.omega_J;
-      a.out = b.tU;
+      a.out = b.Ua;
       rowop(l, a, &L.A);
-      HIPCHK(hipMemcpyAsync(b.Ub, b.tU, sizeof(T) * (size_t)mu * nb_, hipMemcpyDeviceToDevice, st_));
+      std::swap(b.Ub, b.Ua);
     } else {
       // u <- u - w D_B^-1 (B u - (A v - kappa)/sigma); then v <- v - w D_C^-1 (C v - (A^t u - tau)/sigma)
       RowOpArgs<T> a;
       a.nrows = mu; a.w = nb_;
-      a.Krp = L.A.rp; a.Kci = L.A.ci; a.Kv = vals<T>(L.A); a.z = b.Vb;
+      a.Krp = L.A.rp; a.Kci = L.A.ci; a.nnzK = L.A.nnz; a.Kv = vals<T>(L.A); a.z = b.Vb;
       a.mmode = L.finest ? M_IDENT : M_CSR; a.Mrp = L.B.rp; a.Mci = L.B.ci; a.Mv = vals<T>(L.B); a.y = b.Ub;
       a.x = b.Ub; a.D = x.dinvB; a.kap = kap; a.sig = sig; a.cmode = C_JAC_BOOT; a.omega = p_.omega_J;
-      a.out = b.tU;
+      a.out = b.Ua;
       rowop(l, a, &L.A);
-      HIPCHK(hipMemcpyAsync(b.Ub, b.tU, sizeof(T) * (size_t)mu * nb_, hipMemcpyDeviceToDevice, st_));
       RowOpArgs<T> c;
       c.nrows = mv; c.w = nb_;
-      c.Krp = L.At.rp; c.Kci = L.At.ci; c.Kv = vals<T>(L.At); c.z = b.Ub;
+      c.Krp = L.At.rp; c.Kci = L.At.ci; c.nnzK = L.At.nnz; c.Kv = vals<T>(L.At); c.z = b.Ua;
       c.mmode = L.finest ? M_IDENT : M_CSR; c.Mrp = L.C.rp; c.Mci = L.C.ci; c.Mv = vals<T>(L.C); c.y = b.Vb;
       c.x = b.Vb; c.D = x.dinvC; c.kap = tau; c.sig = sig; c.cmode = C_JAC_BOOT; c.omega = p_.omega_J;
-      c.out = b.tV;
+      c.out = b.Va;
       rowop(l, c, &L.At);
-      HIPCHK(hipMemcpyAsync(b.Vb, b.tV, sizeof(T) * (size_t)mv * nb_, hipMemcpyDeviceToDevice, st_));
+      std::swap(b.Ub, b.Ua);
+      std::swap(b.Vb, b.Va);
     }
   } else {
     if (spd_) {
@@ -959,20 +1055,20 @@ void Solver::boot_relax_rq(int l) {
     boot_relax<double>(l, nullptr, nullptr, sig_);
     DotArgs<double> d1, d2, d3;
     if (spd_) {
-      d1.nrows = mu; d1.w = nb_; d1.a = b.Ub; d1.Krp = L.A.rp; d1.Kci = L.A.ci; d1.Kv = L.A.v; d1.z = b.Ub;
+      d1.nrows = mu; d1.w = nb_; d1.a = b.Ub; d1.Krp = L.A.rp; d1.Kci = L.A.ci; d1.nnzK = L.A.nnz; d1.Kv = L.A.v; d1.z = b.Ub;
       dots(l, d1, &L.A, r1_);
       d2.nrows = mu; d2.w = nb_; d2.a = b.Ub; d2.z = b.Ub;
-      if (!L.finest) { d2.Krp = L.A.rp; d2.Kci = L.A.ci; d2.Kv = L.B.v; }
+      if (!L.finest) { d2.Krp = L.A.rp; d2.Kci = L.A.ci; d2.nnzK = L.A.nnz; d2.Kv = L.B.v; }
       launch_dots(d2, partial_, r2_, st_);
       launch_rq_update(nb_, r1_, r2_, nullptr, sig_, flip_, st_);
     } else {
-      d1.nrows = mu; d1.w = nb_; d1.a = b.Ub; d1.Krp = L.A.rp; d1.Kci = L.A.ci; d1.Kv = L.A.v; d1.z = b.Vb;
+      d1.nrows = mu; d1.w = nb_; d1.a = b.Ub; d1.Krp = L.A.rp; d1.Kci = L.A.ci; d1.nnzK = L.A.nnz; d1.Kv = L.A.v; d1.z = b.Vb;
       dots(l, d1, &L.A, r1_);
       d2.nrows = mu; d2.w = nb_; d2.a = b.Ub; d2.z = b.Ub;
-      if (!L.finest) { d2.Krp = L.B.rp; d2.Kci = L.B.ci; d2.Kv = L.B.v; }
+      if (!L.finest) { d2.Krp = L.B.rp; d2.Kci = L.B.ci; d2.nnzK = L.B.nnz; d2.Kv = L.B.v; }
       launch_dots(d2, partial_, r2_, st_);
       d3.nrows = mv; d3.w = nb_; d3.a = b.Vb; d3.z = b.Vb;
-      if (!L.finest) { d3.Krp = L.C.rp; d3.Kci = L.C.ci; d3.Kv = L.C.v; }
+      if (!L.finest) { d3.Krp = L.C.rp; d3.Kci = L.C.ci; d3.nnzK = L.C.nnz; d3.Kv = L.C.v; }
       launch_dots(d3, partial_, r3_, st_);
       launch_rq_update(nb_, r1_, r2_, r3_, sig_, flip_, st_);
     }
@@ -993,17 +1089,17 @@ void Solver::fit_interpolation(int l, int cycle) {
   auto rq_parts = [&](const double* U, const double* V, int w, int off) {
     DotArgs<double> d1, d2, d3;
     if (spd_) {
-      d1.nrows = mu; d1.w = w; d1.a = U; d1.Krp = L.A.rp; d1.Kci = L.A.ci; d1.Kv = L.A.v; d1.z = U;
+      d1.nrows = mu; d1.w = w; d1.a = U; d1.Krp = L.A.rp; d1.Kci = L.A.ci; d1.nnzK = L.A.nnz; d1.Kv = L.A.v; d1.z = U;
       d2.nrows = mu; d2.w = w; d2.a = U; d2.z = U;
-      if (!L.finest) { d2.Krp = L.A.rp; d2.Kci = L.A.ci; d2.Kv = L.B.v; }
+      if (!L.finest) { d2.Krp = L.A.rp; d2.Kci = L.A.ci; d2.nnzK = L.A.nnz; d2.Kv = L.B.v; }
       launch_dots(d1, partial_, r1_ + off, st_);
       launch_dots(d2, partial_, r2_ + off, st_);
     } else {
-      d1.nrows = mu; d1.w = w; d1.a = U; d1.Krp = L.A.rp; d1.Kci = L.A.ci; d1.Kv = L.A.v; d1.z = V;
+      d1.nrows = mu; d1.w = w; d1.a = U; d1.Krp = L.A.rp; d1.Kci = L.A.ci; d1.nnzK = L.A.nnz; d1.Kv = L.A.v; d1.z = V;
       d2.nrows = mu; d2.w = w; d2.a = U; d2.z = U;
-      if (!L.finest) { d2.Krp = L.B.rp; d2.Kci = L.B.ci; d2.Kv = L.B.v; }
+      if (!L.finest) { d2.Krp = L.B.rp; d2.Kci = L.B.ci; d2.nnzK = L.B.nnz; d2.Kv = L.B.v; }
       d3.nrows = mv; d3.w = w; d3.a = V; d3.z = V;
-      if (!L.finest) { d3.Krp = L.C.rp; d3.Kci = L.C.ci; d3.Kv = L.C.v; }
+      if (!L.finest) { d3.Krp = L.C.rp; d3.Kci = L.C.ci; d3.nnzK = L.C.nnz; d3.Kv = L.C.v; }
       launch_dots(d1, partial_, r1_ + off, st_);
       launch_dots(d2, partial_, r2_ + off, st_);
       launch_dots(d3, partial_, r3_ + off, st_);
@@ -1017,13 +1113,13 @@ void Solver::fit_interpolation(int l, int cycle) {
     RowOpArgs<double> a;
     a.w = w; a.x = X; a.cmode = C_SMOOTH; a.omega = p_.omega_J; a.out = out;
     if (spd_) {
-      a.nrows = mu; a.Krp = L.A.rp; a.Kci = L.A.ci; a.Kv = L.A.v; a.z = X; a.D = L.smU;
+      a.nrows = mu; a.Krp = L.A.rp; a.Kci = L.A.ci; a.nnzK = L.A.nnz; a.Kv = L.A.v; a.z = X; a.D = L.smU;
     } else if (u_side) {
-      launch_spmm<double>(L.n, w, L.At.rp, L.At.ci, L.At.v, X, tmp, 0.0, st_);   // A^t u
-      a.nrows = mu; a.Krp = L.A.rp; a.Kci = L.A.ci; a.Kv = L.A.v; a.z = tmp; a.D = L.smU;
+      launch_spmm<double>(L.n, w, L.At.rp, L.At.ci, L.At.v, X, tmp, 0.0, st_, L.At.nnz);   // A^t u
+      a.nrows = mu; a.Krp = L.A.rp; a.Kci = L.A.ci; a.nnzK = L.A.nnz; a.Kv = L.A.v; a.z = tmp; a.D = L.smU;
     } else {
-      launch_spmm<double>(L.m, w, L.A.rp, L.A.ci, L.A.v, X, tmp, 0.0, st_);      // A v
-      a.nrows = mv; a.Krp = L.At.rp; a.Kci = L.At.ci; a.Kv = L.At.v; a.z = tmp; a.D = L.smV;
+      launch_spmm<double>(L.m, w, L.A.rp, L.A.ci, L.A.v, X, tmp, 0.0, st_, L.A.nnz);      // A v
+      a.nrows = mv; a.Krp = L.At.rp; a.Kci = L.At.ci; a.nnzK = L.At.nnz; a.Kv = L.At.v; a.z = tmp; a.D = L.smV;
     }
     launch_rowop(a, st_);
   };
@@ -1177,11 +1273,11 @@ void Solver::additive_vcycle(const double* sig, T* rhsU, T* rhsV) {
     Blocks<T>& cb = blocks<T>(C);
     const T* kap = l == 0 ? rhsU : b.kap;
     const T* tau = l == 0 ? rhsV : b.tau;
-    for (int it = 0; it < p_.mu_b; ++it) boot_relax<T>(l, kap, tau, sig);
+    boot_relax<T>(l, kap, tau, sig, p_.mu_b);
     // residuals r = kappa - (A v - sigma B u), s = tau - (A^t u - sigma C v), then restriction
     const int mu = rows_u(L), mv = rows_v(L);
     RowOpArgs<T> a;
-    a.nrows = mu; a.w = nb_; a.Krp = L.A.rp; a.Kci = L.A.ci; a.Kv = vals<T>(L.A);
+    a.nrows = mu; a.w = nb_; a.Krp = L.A.rp; a.Kci = L.A.ci; a.nnzK = L.A.nnz; a.Kv = vals<T>(L.A);
     a.z = spd_ ? b.Ub : b.Vb;
     if (spd_) { a.mmode = L.finest ? M_IDENT : M_SHARED; a.Mv = vals<T>(L.B); }
     else { a.mmode = L.finest ? M_IDENT : M_CSR; a.Mrp = L.B.rp; a.Mci = L.B.ci; a.Mv = vals<T>(L.B); }
@@ -1190,7 +1286,7 @@ void Solver::additive_vcycle(const double* sig, T* rhsU, T* rhsV) {
     spmm<T>(l, L.su.Pt, vals<T>(L.su.Pt), nb_, b.tU, cb.kap, 0.0);
     if (!spd_) {
       RowOpArgs<T> s;
-      s.nrows = mv; s.w = nb_; s.Krp = L.At.rp; s.Kci = L.At.ci; s.Kv = vals<T>(L.At); s.z = b.Ub;
+      s.nrows = mv; s.w = nb_; s.Krp = L.At.rp; s.Kci = L.At.ci; s.nnzK = L.At.nnz; s.Kv = vals<T>(L.At); s.z = b.Ub;
       s.mmode = L.finest ? M_IDENT : M_CSR; s.Mrp = L.C.rp; s.Mci = L.C.ci; s.Mv = vals<T>(L.C);
       s.y = b.Vb; s.kap = tau; s.sig = sig; s.cmode = C_RESID; s.out = b.tV;
       rowop(l, s, &L.At);
@@ -1228,7 +1324,7 @@ void Solver::additive_vcycle(const double* sig, T* rhsU, T* rhsV) {
     if (!spd_) spmm<T>(l, L.sv.P, vals<T>(L.sv.P), nb_, cb.Vb, b.Vb, 1.0);
     const T* kap = l == 0 ? rhsU : b.kap;
     const T* tau = l == 0 ? rhsV : b.tau;
-    for (int it = 0; it < p_.mu_b; ++it) boot_relax<T>(l, kap, tau, sig);
+    boot_relax<T>(l, kap, tau, sig, p_.mu_b);
   }
 }
 
@@ -1243,13 +1339,13 @@ void Solver::additive_iteration() {
   Level& L = *lv_[0];
   const int mu = rows_u(L), mv = rows_v(L);
   RowOpArgs<double> a;
-  a.nrows = mu; a.w = nb_; a.Krp = L.A.rp; a.Kci = L.A.ci; a.Kv = L.A.v; a.z = spd_ ? L.bd.Ub : L.bd.Vb;
+  a.nrows = mu; a.w = nb_; a.Krp = L.A.rp; a.Kci = L.A.ci; a.nnzK = L.A.nnz; a.Kv = L.A.v; a.z = spd_ ? L.bd.Ub : L.bd.Vb;
   a.mmode = M_IDENT; a.y = L.bd.Ub; a.sig = sig_; a.cmode = C_RESID; a.out = L.bd.tU;
   rowop(0, a, &L.A);
   launch_copy_cast_df(L.bd.tU, L.bf.kap, (size_t)mu * nb_, st_);
   if (!spd_) {
     RowOpArgs<double> s;
-    s.nrows = mv; s.w = nb_; s.Krp = L.At.rp; s.Kci = L.At.ci; s.Kv = L.At.v; s.z = L.bd.Ub;
+    s.nrows = mv; s.w = nb_; s.Krp = L.At.rp; s.Kci = L.At.ci; s.nnzK = L.At.nnz; s.Kv = L.At.v; s.z = L.bd.Ub;
     s.mmode = M_IDENT; s.y = L.bd.Vb; s.sig = sig_; s.cmode = C_RESID; s.out = L.bd.tV;
     rowop(0, s, &L.At);
     launch_copy_cast_df(L.bd.tV, L.bf.tau, (size_t)mv * nb_, st_);
@@ -1298,11 +1394,11 @@ void Solver::residuals(std::vector<double>& rho) {
   Level& L = *lv_[0];
   auto& b = L.bd;
   DotArgs<double> d1, d2;
-  d1.nrows = L.m; d1.w = nb_; d1.Krp = L.A.rp; d1.Kci = L.A.ci; d1.Kv = L.A.v;
+  d1.nrows = L.m; d1.w = nb_; d1.Krp = L.A.rp; d1.Kci = L.A.ci; d1.nnzK = L.A.nnz; d1.Kv = L.A.v;
   d1.z = spd_ ? b.Ub : b.Vb; d1.y = b.Ub; d1.sig = sig_;
   dots(0, d1, &L.A, r1_);
   if (!spd_) {
-    d2.nrows = L.n; d2.w = nb_; d2.Krp = L.At.rp; d2.Kci = L.At.ci; d2.Kv = L.At.v;
+    d2.nrows = L.n; d2.w = nb_; d2.Krp = L.At.rp; d2.Kci = L.At.ci; d2.nnzK = L.At.nnz; d2.Kv = L.At.v;
     d2.z = b.Ub; d2.y = b.Vb; d2.sig = sig_;
     dots(0, d2, &L.At, r2_);
   }

@@ -38,9 +38,11 @@ def L():
     return lib()
 
 
-@pytest.mark.parametrize("w", [1, 2, 3, 5, 8, 10, 16])
-def test_spmm_parity(L, w):
-    A = W.random_csr(3001, 1777, seed=w, mean_row=7).to_scipy()          # skewed, ragged, empty rows
+@pytest.mark.parametrize("w,mean_row", [(1, 7), (2, 7), (3, 7), (5, 7), (8, 7), (10, 7), (16, 7),
+                                        (1, 20), (8, 20), (3, 80), (8, 80), (16, 40)])
+def test_spmm_parity(L, w, mean_row):
+    # skewed, ragged, empty rows; mean_row >= 20 takes the kernels' split-row variants
+    A = W.random_csr(3001, 1777, seed=w, mean_row=mean_row).to_scipy()
     X = W.seeded_block(1777, w, seed=100 + w)
     Y0 = W.seeded_block(3001, w, seed=200 + w)
     rp, ci, v = csr_dev(A)
@@ -130,13 +132,21 @@ def test_relaxation_dominant_spd_parity(L, coarse):
     _close(host(dx), Xb, np.abs(Xb) + 10, rel=1e-13)
 
 
-@pytest.mark.parametrize("shifted", [False, True])
-def test_kaczmarz_parity(L, shifted):
-    if shifted:
+@pytest.mark.parametrize("shifted,dense", [(False, False), (True, False), (False, True), (True, True)])
+def test_kaczmarz_parity(L, shifted, dense):
+    if dense:
+        # Galerkin-like operator: long rows (split-row kernels), shifted by a B on the same pattern
+        M = sp.csr_matrix(W.random_csr(700, 700, seed=9, mean_row=35, empty_rows=False).to_scipy()
+                          + 4 * sp.identity(700))
+    elif shifted:
         M = sp.csr_matrix(W.aniso3d(9, 0.01).to_scipy())
     else:
         M = sp.csr_matrix(W.gradient2d(30).to_scipy())
     M.sort_indices()
+    Bv = None
+    if dense and shifted:
+        Bv = np.where(M.indices == np.repeat(np.arange(M.shape[0]), np.diff(M.indptr)), 2.0,
+                      np.random.default_rng(3).uniform(-0.2, 0.2, M.nnz))
     nr, nc = M.shape
     col = O.greedy_row_colouring(M)
     groups = O.colour_groups(col)
@@ -149,21 +159,26 @@ def test_kaczmarz_parity(L, shifted):
     rp, ci, v = csr_dev(M)
     dx, dr = dev(x0), dev(rhs)
     dl = dev(lam) if shifted else None
-    assert L.slamg_op_kaczmarz(nr, nc, w, ptr(rp), ptr(ci), ptr(v), None, ptr(dl), hp(rows), hp(cptr),
+    db = dev(Bv) if Bv is not None else None
+    assert L.slamg_op_kaczmarz(nr, nc, w, ptr(rp), ptr(ci), ptr(v), ptr(db), ptr(dl), hp(rows), hp(cptr),
                                len(groups), ptr(dr), ptr(dx), None) == 0
     if shifted:
+        Bm = sp.csr_matrix((Bv, M.indices, M.indptr), shape=M.shape) if Bv is not None else sp.identity(nr)
         ref = x0.copy()
         for j in range(w):
-            Mj = sp.csr_matrix(M - lam[j] * sp.identity(nr))
+            Mj = sp.csr_matrix(M - lam[j] * Bm)
             ref[:, j:j + 1] = O.kaczmarz_sweep(Mj, x0[:, j:j + 1], rhs[:, j:j + 1], groups)
     else:
         ref = O.kaczmarz_sweep(M, x0, rhs, groups)
     _close(host(dx), ref, np.abs(ref) + 1.0, rel=1e-12)
 
 
-def test_residual_and_dots_parity(L):
+@pytest.mark.parametrize("mean_row", [5, 30])
+def test_residual_and_dots_parity(L, mean_row):
     lev, rng = _svd_level(1200, 700, 3, True)
-    A, B = lev.A, lev.B
+    B = lev.B
+    A = sp.csr_matrix(W.random_csr(1200, 700, seed=3, mean_row=mean_row, empty_rows=False).to_scipy())
+    A.sort_indices()
     w = 5
     U, V = rng.normal(size=(1200, w)), rng.normal(size=(700, w))
     kap = rng.normal(size=(1200, w)); sig = rng.uniform(0.5, 2, w)

@@ -172,3 +172,69 @@ def test_request_interface_matches_solve(ctx):
         assert api.poll(ctx, rid)
         f = api.fetch(ctx, rid, 400, 400, 3, "spd")
         assert np.array_equal(f.sigma, r.sigma)
+
+
+# ------------------------------------------------------------------------------------------------
+# Full-size workloads in the configuration bench.py times (prepared, device-resident matrix).
+# The oracle cannot run these to the end in test time; they are checked through properties that
+# hold at any size, and the first multiplicative cycle (iterate level) against the oracle.
+# ------------------------------------------------------------------------------------------------
+def _full(ctx, name, precision="fp64"):
+    import torch
+    from paper_1102_0919_amd import api
+    wl = W.WORKLOADS[name]
+    A = W.build_workload_matrix(name).to_scipy()
+    M = api.Matrix(ctx, A, wl["kind"])
+    p = api.params_init(wl["kind"], wl["target"], precision=precision, **wl["params"])
+    Ud = torch.zeros((wl["n_b"], A.shape[0]), dtype=torch.float64, device="cuda")
+    Vd = torch.zeros((wl["n_b"], A.shape[1]), dtype=torch.float64, device="cuda") if wl["kind"] == "svd" else None
+    r = api.solve_matrix(ctx, M, wl["target"], wl["n_b"], p, U_dev=Ud, V_dev=Vd)
+    U = Ud.cpu().numpy().T
+    V = None if Vd is None else Vd.cpu().numpy().T
+    M.close()
+    return A, wl, r, U, V
+
+
+def _props(A, r, U, V, kind, ref):
+    anorm = r.report.anorm
+    nb = len(r.sigma)
+    if kind == "spd":
+        res = np.linalg.norm(A @ U - U * r.sigma, axis=0) / anorm
+    else:
+        res = np.maximum(np.linalg.norm(A @ V - U * r.sigma, axis=0),
+                         np.linalg.norm(A.T @ U - V * r.sigma, axis=0)) / anorm
+        assert np.allclose(V.T @ V, np.eye(nb), atol=1e-9)
+    assert np.allclose(U.T @ U, np.eye(nb), atol=1e-9)
+    # the reported residuals are the recomputed ones
+    rep = np.array([r.report.resid[j] for j in range(nb)])
+    assert np.allclose(res, rep, rtol=1e-6, atol=1e-14)
+    # each sigma_j lies within rho_j ||A|| of a closed-form value of the extremal cluster
+    for j in range(nb):
+        assert np.min(np.abs(ref - r.sigma[j])) <= max(res[j] * anorm * 1.01, 1e-12 * anorm)
+    return res
+
+
+def test_full_aniso3d_128_min8_fp64_and_mixed(ctx):
+    ref = W.aniso3d_eigs_smallest(128, 0.01, 9)
+    A, wl, r, U, V = _full(ctx, "aniso3d_128_min8")
+    assert r.converged
+    res = _props(A, r, U, None, "spd", ref)
+    assert res.max() <= 1e-8 * 1.0001
+    _sig_close(r.sigma, ref[:8], r.report.anorm)
+    A, wl, r2, U2, _ = _full(ctx, "aniso3d_128_min8", "mixed_fp32")
+    assert r2.converged
+    _props(A, r2, U2, None, "spd", ref)
+    _sig_close(r2.sigma, ref[:8], r.report.anorm)
+
+
+def test_full_gradient256_dom8_properties_and_first_cycle(ctx):
+    ref = W.gradient2d_singular_values(256)[::-1][:12]
+    A, wl, r, U, V = _full(ctx, "gradient2d_256_dom8")
+    _props(A, r, U, V, "svd", ref)
+    # iterate-level parity of the first multiplicative cycle with the oracle on the same matrix
+    s = O.Solver(A, "svd", "dominant", 8, O.Params(**wl["params"]))
+    s.mult_cycle(1)
+    assert r.report.levels == len(s.levels)
+    assert [tuple(int(x) for x in (r.report.rows[l], r.report.cols[l])) for l in range(r.report.levels)] == \
+        [lv.A.shape for lv in s.levels]
+    assert np.allclose([r.report.mult_sigma[0][j] for j in range(8)], s.sig, rtol=1e-9)
