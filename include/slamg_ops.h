@@ -113,7 +113,9 @@ slamg_status slamg_op_coarse_gsvd(int32_t spd, int32_t minimal, int32_t mL, int3
                                   double* h_u, double* h_v);
 
 /* Additive coarsest solve (§4.2): per column j, variant 0 applies the pseudo-inverse of
- * X - sig_j Y from its SVD without the smallest singular component; variant 1 the pencil variant.
+ * X - sig_j Y from its SVD without the smallest singular component; variant 1 the pencil variant;
+ * variant 2 is variant 0 computed the way consecutive additive iterations compute it, starting from
+ * the eigenvectors of X - sig'_j Y at sig'_j = sig_j (1 + 1e-6).
  * Host dense inputs X, Y (N x N), h_rhs / h_out (N x nb) row-major. */
 slamg_status slamg_op_coarse_solve(int32_t variant, int32_t N, int32_t nb, const double* h_x, const double* h_y,
                                    const double* h_sig, const double* h_rhs, double* h_out);

@@ -163,8 +163,10 @@ void launch_small_ritz(int w, int spd, int minimal, const double* M, double* Y, 
                        double* work, int* status, hipStream_t s);
 void launch_coarse_gsvd(int spd, int minimal, int mL, int nL, int nb, double* A, double* B, double* C,
                         double* work, double* sig, double* U, double* V, int* status, hipStream_t s);
+// basis: nb N^2 eigenvector store; warm = 1 reuses it from the previous call (same X, Y, nearby sigma)
 void launch_pinv_solve(int N, int nb, const double* X, const double* Y, const double* sig,
-                       const double* rhs, double* out, double* work, int* status, hipStream_t s);
+                       const double* rhs, double* out, double* work, double* basis, int warm, int* status,
+                       hipStream_t s);
 void launch_pencil_setup(int N, double* X, double* Y, double* mu, double* Z, double* work,
                          int* status, hipStream_t s);
 void launch_pencil_solve(int N, int nb, const double* mu, const double* Z, const double* sig,

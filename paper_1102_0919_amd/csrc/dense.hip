@@ -451,37 +451,83 @@ void launch_coarse_gsvd(int spd, int minimal, int mL, int nL, int nb, double* A,
 // Additive coarsest solve (§4.2), one workgroup per column j: M = X - sigma_j Y is symmetric, so
 // its SVD is its eigen-decomposition with |eigenvalues|; the pseudo-inverse without the smallest
 // singular component is sum_{i != i*} q_i q_i^t / lambda_i, i* = argmin |lambda_i|.
+// basis (nb N^2) holds each column's eigenvectors Q_j.  Cold: Jacobi on M from the identity.  Warm:
+// sigma_j moved little since Q_j was computed, so Q_j^t M Q_j is nearly diagonal; Jacobi finishes it
+// in a sweep or two and Q_j <- Q_j V.  Both give the eigen-decomposition of M to rounding.
 // rhs / out: N x nb row-major.  work: nb * 2 N^2 doubles.
 // ------------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(DBLK) void k_pinv_solve(int N, int nb, const double* X, const double* Y,
                                                      const double* sig, const double* rhs, double* out,
-                                                     double* work, int use_lds) {
+                                                     double* work, double* basis, int warm, int use_lds) {
   extern __shared__ double dyn[];
   const int j = blockIdx.x;
   double* M = use_lds ? dyn : work + (long)j * 2 * N * N;
-  double* Qv = work + (long)j * 2 * N * N + (long)N * N;
+  double* W2 = work + (long)j * 2 * N * N + (long)N * N;
+  double* Q = basis + (long)j * N * N;
   __shared__ double cf[1024];
+  __shared__ double lam[1024];
   __shared__ int imin;
   const double s = sig[j];
-  for (long t = threadIdx.x; t < (long)N * N; t += DBLK) M[t] = X[t] - s * Y[t];
-  wg_jacobi(M, N, N, Qv, N, 60);
+  const long NN = (long)N * N;
+  if (!warm) {
+    for (long t = threadIdx.x; t < NN; t += DBLK) M[t] = X[t] - s * Y[t];
+    wg_jacobi(M, N, N, Q, N, 60);
+    for (int i = threadIdx.x; i < N; i += DBLK) lam[i] = M[(long)i * N + i];
+  } else {
+    // W2 = (X - s Y) Q ; M = Q^t W2 (symmetrised)
+    for (long t = threadIdx.x; t < NN; t += DBLK) {
+      const int i = (int)(t / N), c = (int)(t % N);
+      const double* xr = X + (long)i * N;
+      const double* yr = Y + (long)i * N;
+      double acc = 0.0;
+      for (int r = 0; r < N; ++r) acc += (xr[r] - s * yr[r]) * Q[(long)r * N + c];
+      W2[t] = acc;
+    }
+    wg_sync();
+    for (long t = threadIdx.x; t < NN; t += DBLK) {
+      const int i = (int)(t / N), c = (int)(t % N);
+      if (c < i) continue;
+      double a1 = 0.0, a2 = 0.0;
+      for (int r = 0; r < N; ++r) {
+        a1 += Q[(long)r * N + i] * W2[(long)r * N + c];
+        a2 += Q[(long)r * N + c] * W2[(long)r * N + i];
+      }
+      const double v = 0.5 * (a1 + a2);
+      M[(long)i * N + c] = v;
+      M[(long)c * N + i] = v;
+    }
+    wg_sync();
+    wg_jacobi(M, N, N, W2, N, 60);
+    for (int i = threadIdx.x; i < N; i += DBLK) lam[i] = M[(long)i * N + i];
+    wg_sync();
+    // Q <- Q W2, through M as the temporary
+    for (long t = threadIdx.x; t < NN; t += DBLK) {
+      const int i = (int)(t / N), c = (int)(t % N);
+      double acc = 0.0;
+      for (int r = 0; r < N; ++r) acc += Q[(long)i * N + r] * W2[(long)r * N + c];
+      M[t] = acc;
+    }
+    wg_sync();
+    for (long t = threadIdx.x; t < NN; t += DBLK) Q[t] = M[t];
+  }
+  wg_sync();
   if (threadIdx.x == 0) {
     int best = 0;
     for (int i = 1; i < N; ++i)
-      if (fabs(M[(long)i * N + i]) < fabs(M[(long)best * N + best])) best = i;
+      if (fabs(lam[i]) < fabs(lam[best])) best = i;
     imin = best;
   }
   wg_sync();
   for (int i = threadIdx.x; i < N; i += DBLK) {
     double d = 0.0;
-    for (int r = 0; r < N; ++r) d += Qv[(long)r * N + i] * rhs[(long)r * nb + j];
-    double lam = M[(long)i * N + i];
-    cf[i] = (i == imin || lam == 0.0) ? 0.0 : d / lam;
+    for (int r = 0; r < N; ++r) d += Q[(long)r * N + i] * rhs[(long)r * nb + j];
+    const double l = lam[i];
+    cf[i] = (i == imin || l == 0.0) ? 0.0 : d / l;
   }
   wg_sync();
   for (int r = threadIdx.x; r < N; r += DBLK) {
     double z = 0.0;
-    for (int i = 0; i < N; ++i) z += Qv[(long)r * N + i] * cf[i];
+    for (int i = 0; i < N; ++i) z += Q[(long)r * N + i] * cf[i];
     out[(long)r * nb + j] = z;
   }
 }
@@ -508,10 +554,11 @@ static size_t pinv_lds_bytes(int N) {
 }
 
 void launch_pinv_solve(int N, int nb, const double* X, const double* Y, const double* sig, const double* rhs,
-                       double* out, double* work, int* status, hipStream_t s) {
+                       double* out, double* work, double* basis, int warm, int* status, hipStream_t s) {
   (void)status;
   const size_t lds = pinv_lds_bytes(N);
-  hipLaunchKernelGGL(k_pinv_solve, dim3(nb), dim3(DBLK), lds, s, N, nb, X, Y, sig, rhs, out, work, lds ? 1 : 0);
+  hipLaunchKernelGGL(k_pinv_solve, dim3(nb), dim3(DBLK), lds, s, N, nb, X, Y, sig, rhs, out, work, basis, warm,
+                     lds ? 1 : 0);
 }
 
 // Pencil variant, set-up once per additive phase: Y = L L^t, K = L^-1 X L^-t = W diag(mu) W^t,

@@ -363,7 +363,7 @@ extern "C" slamg_status slamg_op_coarse_gsvd(int32_t spd, int32_t minimal, int32
 extern "C" slamg_status slamg_op_coarse_solve(int32_t variant, int32_t N, int32_t nb, const double* h_x,
                                               const double* h_y, const double* h_sig, const double* h_rhs,
                                               double* h_out) {
-  if (N < 1 || N > 1024 || nb < 1 || nb > 16 || (variant != 0 && variant != 1)) return SLAMG_E_INVALID;
+  if (N < 1 || N > 1024 || nb < 1 || nb > 16 || (variant < 0 || variant > 2)) return SLAMG_E_INVALID;
   hipStream_t s = nullptr;
   return guarded(s, [&] {
     Tmp t;
@@ -378,9 +378,18 @@ extern "C" slamg_status slamg_op_coarse_solve(int32_t variant, int32_t N, int32_
     up(Y, h_y, (size_t)N * N, s);
     up(sig, h_sig, nb, s);
     up(rhs, h_rhs, (size_t)N * nb, s);
-    if (variant == 0) {
+    if (variant == 0 || variant == 2) {
       double* work = t.get<double>((size_t)nb * 2 * N * N);
-      launch_pinv_solve(N, nb, X, Y, sig, rhs, out, work, status, s);
+      double* basis = t.get<double>((size_t)nb * N * N);
+      if (variant == 2) {
+        // warm start: eigenvectors of X - sigma'_j Y at sigma'_j = sigma_j (1 + 1e-6) first
+        double* sig2 = t.get<double>(nb);
+        std::vector<double> h2(h_sig, h_sig + nb);
+        for (auto& v : h2) v *= 1.0 + 1e-6;
+        up(sig2, h2.data(), nb, s);
+        launch_pinv_solve(N, nb, X, Y, sig2, rhs, out, work, basis, 0, status, s);
+      }
+      launch_pinv_solve(N, nb, X, Y, sig, rhs, out, work, basis, variant == 2 ? 1 : 0, status, s);
     } else {
       double* mu = t.get<double>(N);
       double* Z = t.get<double>((size_t)N * N);

@@ -316,18 +316,22 @@ def test_coarse_gsvd_parity(L, kind, target):
             assert np.allclose(hv[:, j] * s, Vo[:, j], atol=1e-7)
 
 
-@pytest.mark.parametrize("variant", [0, 1])
-def test_coarse_solve_parity(L, variant):
+@pytest.mark.parametrize("variant,m,n", [(0, 30, 20), (1, 30, 20), (2, 30, 20), (0, 120, 90), (2, 120, 90),
+                                         (1, 120, 90)])
+def test_coarse_solve_parity(L, variant, m, n):
+    # N = m + n: 50 keeps the eigensolve in LDS, 210 in global memory; variant 2 is the warm start
+    import scipy.linalg as sla
     rng = np.random.default_rng(6)
-    m, n = 30, 20
     Ad = rng.uniform(-1, 1, (m, n))
     Bh = rng.uniform(-1, 1, (m, m)); Bd = Bh @ Bh.T / m + np.eye(m)
     Ch = rng.uniform(-1, 1, (n, n)); Cd = Ch @ Ch.T / n + np.eye(n)
     lev = O.Level(sp.csr_matrix(Ad), sp.csr_matrix(Bd), sp.csr_matrix(Cd))
     X, Y = O.pencil_matrices(lev, O.SVD)
-    sig = np.array([0.3, 0.7, 1.3, 2.1])
+    mu = sla.eigh(X, Y, eigvals_only=True)
+    # one shift next to a generalized singular value: X - sigma Y nearly singular there
+    sig = np.array([mu[-1] * (1 + 1e-9), 0.7, 1.3, 2.1])
     rhs = rng.normal(size=(m + n, 4))
-    ref = (O.coarse_pinv_solve if variant == 0 else O.coarse_pencil_solve)(X, Y, sig, rhs)
+    ref = (O.coarse_pencil_solve if variant == 1 else O.coarse_pinv_solve)(X, Y, sig, rhs)
     out = np.zeros_like(rhs)
     assert L.slamg_op_coarse_solve(variant, m + n, 4, hp(np.ascontiguousarray(X)), hp(np.ascontiguousarray(Y)),
                                    hp(sig), hp(np.ascontiguousarray(rhs)), hp(out)) == 0
