@@ -156,10 +156,13 @@ def main():
         ach = per_launch / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": CLASS_NAMES[c],
-                "launches_per_step": int(tot_n[c] / args.steps), "avg_launch_us": round(avg_ms * 1e3, 3),
+                "timed_launches_per_step": int(tot_n[c] / args.steps), "avg_launch_us": round(avg_ms * 1e3, 3),
+                "timing_sample": "HIP events around every launch of the kernel in the multiplicative phase and "
+                                 "in the eagerly launched additive iterations (every 32nd; the others replay a "
+                                 "HIP graph of the iteration)",
                 "algorithmic_bytes_per_launch": int(per_launch),
-                "share_of_step": round(tot_ms[c] / args.steps / ms, 4),
-                "class_ms_per_step_in_warmup": {CLASS_NAMES[i]: round(warm_ms[i], 3) for i in range(NCLS)}}
+                "graph_iters_per_step": int(last.report.graph_iters),
+                "sampled_class_ms_in_warmup": {CLASS_NAMES[i]: round(warm_ms[i], 3) for i in range(NCLS)}}
     ref = _closed_form(name, n_b, target)
     acc = {"max_rel_residual": float(max(last.report.resid[j] for j in range(n_b))),
            "levels": int(last.report.levels), "add_iters": int(last.report.add_iters),

@@ -93,7 +93,10 @@ typedef struct {
                                a block with an operator product) on the finest level */
   int32_t verbose;          /* k > 0: one progress line on stderr after each multiplicative cycle
                                and every k additive iterations (0)                              */
-  int32_t reserved[3];
+  int32_t graphs;           /* 1: capture one additive iteration (V-cycle, Ritz step, residual
+                               reductions) in a HIP graph and replay it; 0: launch every kernel
+                               on the stream.  Both give bitwise the same results (1)           */
+  int32_t reserved[2];
 } slamg_params;
 
 /* Report of one solve.  Arrays are filled up to the counts given. */
@@ -112,6 +115,8 @@ typedef struct {
   double prof_ms[8];                         /* per profiled class: summed device time (ms)     */
   int64_t prof_launches[8];                  /*   number of launches                            */
   double prof_bytes[8];                      /*   summed algorithmic bytes of those launches    */
+  int32_t graph_iters;                       /* additive iterations run as graph replays        */
+  int32_t pad_;
 } slamg_report;
 
 typedef struct slamg_ctx slamg_ctx;

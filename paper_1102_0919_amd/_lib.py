@@ -31,7 +31,8 @@ class Params(C.Structure):
                 ("coarse_max", C.c_int32), ("max_levels", C.c_int32), ("stall_ratio", C.c_double),
                 ("tol", C.c_double), ("seed", C.c_uint64), ("precision", C.c_int32),
                 ("ritz_in_mult", C.c_int32), ("coarse_pinv", C.c_int32), ("profile_mask", C.c_int32),
-                ("verbose", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("verbose", C.c_int32), ("graphs", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
 
 class Report(C.Structure):
@@ -41,7 +42,7 @@ class Report(C.Structure):
                 ("anorm", C.c_double), ("resid", C.c_double * 16), ("rho_history", C.c_double * 256),
                 ("mult_sigma", (C.c_double * 16) * 32), ("t_setup_ms", C.c_double), ("t_solve_ms", C.c_double),
                 ("err_bound", C.c_double * 16), ("prof_ms", C.c_double * 8), ("prof_launches", C.c_int64 * 8),
-                ("prof_bytes", C.c_double * 8)]
+                ("prof_bytes", C.c_double * 8), ("graph_iters", C.c_int32), ("pad_", C.c_int32)]
 
 
 _P = C.c_void_p

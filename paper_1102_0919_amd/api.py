@@ -38,11 +38,14 @@ def params_init(kind: str = "svd", target: str = "dominant", **overrides) -> L.P
     st = lib.slamg_params_init(C.byref(p), L.KIND[kind], L.TARGET[target])
     if st != 0:
         raise SlamgError(st, "params_init")
+    names = {f[0] for f in L.Params._fields_}
     for k, v in overrides.items():
         if k == "precision" and isinstance(v, str):
             v = L.PRECISION[v]
         if k == "omega":
             k = "omega_J"
+        if k not in names or k == "reserved":
+            raise TypeError(f"params_init: unknown parameter {k!r}")
         setattr(p, k, v)
     return p
 

@@ -69,6 +69,7 @@ extern "C" slamg_status slamg_params_init(slamg_params* p, slamg_kind kind, slam
   p->precision = SLAMG_FP64;
   p->ritz_in_mult = 1;
   p->coarse_pinv = 0;
+  p->graphs = 1;
   (void)target;
   return SLAMG_OK;
 }

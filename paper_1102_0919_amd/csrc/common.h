@@ -75,6 +75,7 @@ struct RowOpArgs {
   double omega = 0.7;
   T* out = nullptr;
   int nnzK = -1;             // nonzeros of K (chooses the row split); -1: unknown
+  double avgM = 0.0;         // mean row length of M (M_CSR; also chooses the row split)
 };
 
 template <typename T> void launch_rowop(const RowOpArgs<T>& a, hipStream_t s);
@@ -98,6 +99,7 @@ struct KaczArgs {
   const T* kap = nullptr;
   T* x = nullptr;
   long nnz_total = -1, nnz_rows = 0;   // row-length statistics of the operator (row split)
+  double avgM = 0.0;                    // mean row length of the right-hand side operator (M_CSR)
 };
 template <typename T> void launch_kacz(const KaczArgs<T>& a, hipStream_t s);
 // nhalf (1 or 2) half-sweeps per sweep, nsweeps sweeps, all in one workgroup; halves[h].rows is the

@@ -13,6 +13,25 @@ static constexpr int MAXPAIR = 512;   // matrices up to 1024 x 1024
 
 __device__ static void wg_sync() { __syncthreads(); }
 
+// Visits every (i, j), 0 <= i < R, 0 <= j < n, with the workgroup's threads: consecutive threads take
+// consecutive j (coalesced rows), and the loop carries no integer division.
+template <class F>
+__device__ __forceinline__ void wg_for2(int R, int n, F&& f) {
+  if (n <= 0 || R <= 0) return;
+  if (n <= DBLK) {
+    const int G = DBLK / n, j = (int)threadIdx.x % n, g = (int)threadIdx.x / n;
+    if (g < G) {
+#pragma unroll 4
+      for (int i = g; i < R; i += G) f(i, j);
+    }
+  } else {
+    for (int j = threadIdx.x; j < n; j += DBLK) {
+#pragma unroll 4
+      for (int i = 0; i < R; ++i) f(i, j);
+    }
+  }
+}
+
 // A (n x n, ld) <- L (lower), A = L L^t.  Returns (in *info) 0 or the first failing pivot + 1;
 // a failing pivot is replaced by a tiny positive value so the factor stays finite.
 __device__ static void wg_chol(double* A, int n, int ld, int* info) {
@@ -83,34 +102,36 @@ __device__ static void wg_transpose(const double* A, int r, int c, int lda, doub
 }
 
 // Two-sided cyclic Jacobi with the round-robin parallel ordering: A (n x n symmetric) is reduced to
-// diagonal form in place; V accumulates the rotations (A_in = V diag V^t).  A pair is rotated
-// when |a_pq| > 1e-15 sqrt(|a_pp a_qq|) (and above 1e-17 ||A||_F); the sweeps stop after one that
-// rotated nothing.
-__device__ static void wg_jacobi(double* A, int n, int ld, double* V, int ldv, int maxsweep) {
+// diagonal form in place; V accumulates the rotations (A_in = V diag V^t; with init_v false, V
+// holds an orthogonal start basis and receives V J_1 J_2 ...).  A pair is rotated
+// when |a_pq| > 1e-15 sqrt(|a_pp a_qq|) and |a_pq| > 2^-53 ||A||_F; the sweeps stop after one that
+// rotated nothing.  The absolute floor is the backward-stable accuracy of any symmetric eigensolver
+// in double precision: below it the off-diagonal entries are rounding noise of earlier rotations,
+// and an indefinite matrix would keep producing such noise under the relative test alone.
+// Inlined at each call so that the compiler sees where A and V live (LDS or global memory) and
+// emits LDS instructions for LDS-resident matrices; the procedure is latency-bound.
+__device__ static __forceinline__ void wg_jacobi(double* A, int n, int ld, double* V, int ldv, int maxsweep,
+                                                 bool init_v = true) {
   __shared__ int P[MAXPAIR], Q[MAXPAIR];
   __shared__ double Cs[MAXPAIR], Sn[MAXPAIR];
   __shared__ double red[DBLK];
   __shared__ int rotated;
-  for (long t = threadIdx.x; t < (long)n * n; t += DBLK) {
-    int i = (int)(t / n), j = (int)(t % n);
-    V[(long)i * ldv + j] = i == j ? 1.0 : 0.0;
-  }
+  if (init_v) wg_for2(n, n, [&](int i, int j) { V[(long)i * ldv + j] = i == j ? 1.0 : 0.0; });
   const int N = n + (n & 1);
   const int npair = N / 2;
   if (n <= 1) { wg_sync(); return; }
   double tot = 0.0;
-  for (long t = threadIdx.x; t < (long)n * n; t += DBLK) {
-    int i = (int)(t / n), j = (int)(t % n);
-    double a = A[(long)i * ld + j];
+  wg_for2(n, n, [&](int i, int j) {
+    const double a = A[(long)i * ld + j];
     tot += a * a;
-  }
+  });
   red[threadIdx.x] = tot;
   wg_sync();
   for (int s = DBLK / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     wg_sync();
   }
-  const double floor_abs = 1e-17 * sqrt(red[0]);
+  const double floor_abs = 0x1p-53 * sqrt(red[0]);
   for (int sweep = 0; sweep < maxsweep; ++sweep) {
     if (threadIdx.x == 0) rotated = 0;
     wg_sync();
@@ -132,31 +153,36 @@ __device__ static void wg_jacobi(double* A, int n, int ld, double* V, int ldv, i
             rotated = 1;
           }
         }
+        // the pair with the padding index n (odd n) becomes (p, p) with the identity rotation, so the
+        // updates below need no branch
+        if (q >= n) q = p;
         P[k] = p; Q[k] = q; Cs[k] = c; Sn[k] = s;
       }
       wg_sync();
-      for (long t = threadIdx.x; t < (long)npair * n; t += DBLK) {
-        int k = (int)(t / n), j = (int)(t % n);
-        int p = P[k], q = Q[k];
-        if (q >= n || Sn[k] == 0.0) continue;
-        double c = Cs[k], s = Sn[k];
-        double apj = A[(long)p * ld + j], aqj = A[(long)q * ld + j];
-        A[(long)p * ld + j] = c * apj - s * aqj;
-        A[(long)q * ld + j] = s * apj + c * aqj;
-      }
-      wg_sync();
-      for (long t = threadIdx.x; t < (long)npair * n; t += DBLK) {
-        int k = (int)(t / n), i = (int)(t % n);
-        int p = P[k], q = Q[k];
-        if (q >= n || Sn[k] == 0.0) continue;
-        double c = Cs[k], s = Sn[k];
-        double aip = A[(long)i * ld + p], aiq = A[(long)i * ld + q];
-        A[(long)i * ld + p] = c * aip - s * aiq;
-        A[(long)i * ld + q] = s * aip + c * aiq;
-        double vip = V[(long)i * ldv + p], viq = V[(long)i * ldv + q];
-        V[(long)i * ldv + p] = c * vip - s * viq;
-        V[(long)i * ldv + q] = s * vip + c * viq;
-      }
+      // A <- R A R^t for the block-diagonal rotation R of this round: every 2 x 2 block (rows of
+      // pair a, columns of pair b) is independent, so one phase suffices: rotate the block's rows,
+      // then its columns (the same operations, in the same order, as a row pass followed by a
+      // column pass).  The padding pair is (p, p) with the identity rotation.
+      wg_for2(npair, npair, [&](int a, int b) {
+        const int pa = P[a], qa = Q[a], pb = P[b], qb = Q[b];
+        const double ca = Cs[a], sa = Sn[a], cb = Cs[b], sb = Sn[b];
+        const double x00 = A[(long)pa * ld + pb], x01 = A[(long)pa * ld + qb];
+        const double x10 = A[(long)qa * ld + pb], x11 = A[(long)qa * ld + qb];
+        const double r00 = ca * x00 - sa * x10, r10 = sa * x00 + ca * x10;   // rows, column pb
+        const double r01 = ca * x01 - sa * x11, r11 = sa * x01 + ca * x11;   // rows, column qb
+        A[(long)pa * ld + pb] = cb * r00 - sb * r01;
+        A[(long)pa * ld + qb] = sb * r00 + cb * r01;
+        A[(long)qa * ld + pb] = cb * r10 - sb * r11;
+        A[(long)qa * ld + qb] = sb * r10 + cb * r11;
+      });
+      // V <- V R^t
+      wg_for2(npair, n, [&](int b, int i) {
+        const int pb = P[b], qb = Q[b];
+        const double cb = Cs[b], sb = Sn[b];
+        const double vip = V[(long)i * ldv + pb], viq = V[(long)i * ldv + qb];
+        V[(long)i * ldv + pb] = cb * vip - sb * viq;
+        V[(long)i * ldv + qb] = sb * vip + cb * viq;
+      });
       wg_sync();
     }
     const int any = rotated;
@@ -166,20 +192,18 @@ __device__ static void wg_jacobi(double* A, int n, int ld, double* V, int ldv, i
   wg_sync();
 }
 
-// indices of the k extremal values of lam[0..n) (largest first if desc, else smallest first), by a
-// single thread (n small); ties to the lower index.
+// indices of the k extremal values of lam[0..n) (largest first if desc, else smallest first); ties
+// to the lower index.  Each thread ranks its own entries (the rank is the output position).
 __device__ static void select_extremal(const double* lam, int n, int k, bool desc, int* out) {
-  if (threadIdx.x == 0) {
-    for (int s = 0; s < k; ++s) {
-      int best = -1;
-      for (int i = 0; i < n; ++i) {
-        bool used = false;
-        for (int t = 0; t < s; ++t) used |= (out[t] == i);
-        if (used) continue;
-        if (best < 0 || (desc ? lam[i] > lam[best] : lam[i] < lam[best])) best = i;
-      }
-      out[s] = best;
+  wg_sync();
+  for (int i = threadIdx.x; i < n; i += DBLK) {
+    const double li = lam[i];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      const double lj = lam[j];
+      rank += (desc ? lj > li : lj < li) || (lj == li && j < i);
     }
+    if (rank < k) out[rank] = i;
   }
   wg_sync();
 }
@@ -224,12 +248,18 @@ __global__ __launch_bounds__(DBLK) void k_small_ritz(int w, int spd, int minimal
                                                      double* Z, double* sig, double* work, int* status) {
   __shared__ int ord[32];
   __shared__ double lam[32];
+  __shared__ double As[32 * 32], Vs[32 * 32];   // the (augmented) problem is at most 32 x 32
+  __shared__ double Ms[16 * 16], Ys[16 * 16], Zs[16 * 16], ss[16];
+  (void)work;
+  // the small serial steps below read and write LDS copies; results are stored at the end
+  for (int t = threadIdx.x; t < w * w; t += DBLK) Ms[t] = M[t];
+  wg_sync();
   if (spd) {
-    double* A = work;
-    double* V = work + w * w;
+    double* A = As;
+    double* V = Vs;
     for (int t = threadIdx.x; t < w * w; t += DBLK) {
       int i = t / w, j = t % w;
-      A[t] = 0.5 * (M[i * w + j] + M[j * w + i]);
+      A[t] = 0.5 * (Ms[i * w + j] + Ms[j * w + i]);
     }
     wg_jacobi(A, w, w, V, w, 60);
     for (int i = threadIdx.x; i < w; i += DBLK) lam[i] = A[i * w + i];
@@ -243,16 +273,25 @@ __global__ __launch_bounds__(DBLK) void k_small_ritz(int w, int spd, int minimal
     return;
   }
   const int n2 = 2 * w;
-  double* A = work;
-  double* V = work + n2 * n2;
+  double* A = As;
+  double* V = Vs;
+  // Jacobi on V0^t [[0, M], [M^t, 0]] V0 with V0 = [[I, I], [I, -I]] / sqrt(2): this is diag(s, -s)
+  // when M is diagonal, and the Ritz matrix of nearly converged iterates is nearly diagonal, so
+  // the sweeps start close to the answer; the eigenvectors of the augmented matrix are V0 W.
+  const double h = 0.70710678118654752440;
   for (int t = threadIdx.x; t < n2 * n2; t += DBLK) {
-    int i = t / n2, j = t % n2;
-    double v = 0.0;
-    if (i < w && j >= w) v = M[i * w + (j - w)];
-    if (i >= w && j < w) v = M[j * w + (i - w)];
+    const int i = t / n2, j = t % n2;
+    const int i0 = i < w ? i : i - w, j0 = j < w ? j : j - w;
+    const double mij = Ms[i0 * w + j0], mji = Ms[j0 * w + i0];
+    double v;
+    if (i < w && j < w) v = 0.5 * (mij + mji);
+    else if (i < w) v = 0.5 * (mji - mij);
+    else if (j < w) v = 0.5 * (mij - mji);
+    else v = -0.5 * (mij + mji);
     A[t] = v;
+    V[t] = i0 == j0 ? ((i >= w && j >= w) ? -h : h) : 0.0;
   }
-  wg_jacobi(A, n2, n2, V, n2, 60);
+  wg_jacobi(A, n2, n2, V, n2, 60, false);
   for (int i = threadIdx.x; i < n2; i += DBLK) lam[i] = A[i * n2 + i];
   wg_sync();
   select_extremal(lam, n2, n2, true, ord);   // descending: +sigma_1 ... -sigma_1
@@ -261,10 +300,13 @@ __global__ __launch_bounds__(DBLK) void k_small_ritz(int w, int spd, int minimal
   // y_k = M z_k / sigma_k, so that (y_k, z_k) is consistent inside degenerate clusters.  For
   // sigma_k ~ 0 the +-0 eigenvectors mix: y_k and z_k come from whichever of the two eigenvectors
   // carries more mass in the respective part, and y_k is orthogonalised against the other y.
-  if (threadIdx.x == 0) {
+  __shared__ int tinyk[16];
+  {
     double smax = 0.0;
     for (int k = 0; k < w; ++k) smax = fmax(smax, lam[ord[k]]);
-    for (int k = 0; k < w; ++k) {
+    // one thread per triplet k
+    if ((int)threadIdx.x < w) {
+      const int k = threadIdx.x;
       const int kp = ord[k], km = ord[n2 - 1 - k];
       double tp = 0.0, tm = 0.0, bp = 0.0, bm = 0.0;
       for (int i = 0; i < w; ++i) {
@@ -278,42 +320,53 @@ __global__ __launch_bounds__(DBLK) void k_small_ritz(int w, int spd, int minimal
       const int kz = (!tiny || bp >= bm) ? kp : km;
       const double nz = sqrt(kz == kp ? bp : bm);
       const int dst = minimal ? (w - 1 - k) : k;
-      for (int i = 0; i < w; ++i) Z[i * w + dst] = V[(w + i) * n2 + kz] / nz;
+      for (int i = 0; i < w; ++i) Zs[i * w + dst] = V[(w + i) * n2 + kz] / nz;
       if (!tiny) {
         for (int i = 0; i < w; ++i) {
           double s = 0.0;
-          for (int j = 0; j < w; ++j) s += M[i * w + j] * Z[j * w + dst];
-          Y[i * w + dst] = s;
+          for (int j = 0; j < w; ++j) s += Ms[i * w + j] * Zs[j * w + dst];
+          Ys[i * w + dst] = s;
         }
-      } else {
-        const int ky = tp >= tm ? kp : km;
-        for (int i = 0; i < w; ++i) Y[i * w + dst] = V[i * n2 + ky];
-      }
-      sig[dst] = sk;
-    }
-    // normalise y; for (numerically) zero sigma, orthogonalise against the other columns first
-    for (int pass = 0; pass < 2; ++pass) {
-      for (int k = 0; k < w; ++k) {
-        const bool tiny = !(sig[k] > 1e-13 * smax);
-        if (pass == 0 && tiny) continue;
-        if (pass == 1 && !tiny) continue;
-        if (tiny) {
-          for (int k2 = 0; k2 < w; ++k2) {
-            if (k2 == k || (!(sig[k2] > 1e-13 * smax) && k2 > k)) continue;
-            double d = 0.0;
-            for (int i = 0; i < w; ++i) d += Y[i * w + k] * Y[i * w + k2];
-            for (int i = 0; i < w; ++i) Y[i * w + k] -= d * Y[i * w + k2];
-          }
-        }
-        double nrm = 0.0;
-        for (int i = 0; i < w; ++i) nrm += Y[i * w + k] * Y[i * w + k];
+        double nrm = 0.0;   // normalise y (the columns of non-zero sigma are independent)
+        for (int i = 0; i < w; ++i) nrm += Ys[i * w + dst] * Ys[i * w + dst];
         nrm = sqrt(nrm);
         if (nrm > 0.0)
-          for (int i = 0; i < w; ++i) Y[i * w + k] /= nrm;
+          for (int i = 0; i < w; ++i) Ys[i * w + dst] /= nrm;
+      } else {
+        const int ky = tp >= tm ? kp : km;
+        for (int i = 0; i < w; ++i) Ys[i * w + dst] = V[i * n2 + ky];
+      }
+      ss[dst] = sk;
+      tinyk[dst] = tiny ? 1 : 0;
+    }
+    wg_sync();
+    // for (numerically) zero sigma: orthogonalise y against the other columns, in column order,
+    // then normalise
+    if (threadIdx.x == 0) {
+      for (int k = 0; k < w; ++k) {
+        if (!tinyk[k]) continue;
+        for (int k2 = 0; k2 < w; ++k2) {
+          if (k2 == k || (tinyk[k2] && k2 > k)) continue;
+          double d = 0.0;
+          for (int i = 0; i < w; ++i) d += Ys[i * w + k] * Ys[i * w + k2];
+          for (int i = 0; i < w; ++i) Ys[i * w + k] -= d * Ys[i * w + k2];
+        }
+        double nrm = 0.0;
+        for (int i = 0; i < w; ++i) nrm += Ys[i * w + k] * Ys[i * w + k];
+        nrm = sqrt(nrm);
+        if (nrm > 0.0)
+          for (int i = 0; i < w; ++i) Ys[i * w + k] /= nrm;
       }
     }
   }
+  wg_sync();
+  for (int t = threadIdx.x; t < w * w; t += DBLK) {
+    Y[t] = Ys[t];
+    Z[t] = Zs[t];
+  }
+  for (int k = threadIdx.x; k < w; k += DBLK) sig[k] = ss[k];
 }
+
 void launch_small_ritz(int w, int spd, int minimal, const double* M, double* Y, double* Z, double* sig, double* work,
                        int* status, hipStream_t s) {
   hipLaunchKernelGGL(k_small_ritz, dim3(1), dim3(DBLK), 0, s, w, spd, minimal, M, Y, Z, sig, work, status);
@@ -456,37 +509,48 @@ void launch_coarse_gsvd(int spd, int minimal, int mL, int nL, int nb, double* A,
 // in a sweep or two and Q_j <- Q_j V.  Both give the eigen-decomposition of M to rounding.
 // rhs / out: N x nb row-major.  work: nb * 2 N^2 doubles.
 // ------------------------------------------------------------------------------------------------
+template <int LDSMODE>
 __global__ __launch_bounds__(DBLK) void k_pinv_solve(int N, int nb, const double* X, const double* Y,
                                                      const double* sig, const double* rhs, double* out,
-                                                     double* work, double* basis, int warm, int use_lds) {
+                                                     double* work, double* basis, int warm) {
+  // LDSMODE 0: everything in global memory (L2); 1: M in LDS; 2: M, the rotation accumulator and
+  // the eigenvector copy in LDS (Q is read from / written back to `basis`)
+  constexpr int lds_mode = LDSMODE;
   extern __shared__ double dyn[];
   const int j = blockIdx.x;
-  double* M = use_lds ? dyn : work + (long)j * 2 * N * N;
-  double* W2 = work + (long)j * 2 * N * N + (long)N * N;
-  double* Q = basis + (long)j * N * N;
+  const long NN = (long)N * N;
+  double* Qg = basis + (long)j * NN;
+  double* M;
+  double* W2;
+  double* Q;
+  if constexpr (lds_mode >= 1) M = dyn; else M = work + (long)j * 2 * NN;
+  if constexpr (lds_mode == 2) { W2 = dyn + NN; Q = dyn + 2 * NN; }
+  else { W2 = work + (long)j * 2 * NN + NN; Q = Qg; }
   __shared__ double cf[1024];
   __shared__ double lam[1024];
+  __shared__ double rj[1024];
   __shared__ int imin;
   const double s = sig[j];
-  const long NN = (long)N * N;
   if (!warm) {
     for (long t = threadIdx.x; t < NN; t += DBLK) M[t] = X[t] - s * Y[t];
     wg_jacobi(M, N, N, Q, N, 60);
     for (int i = threadIdx.x; i < N; i += DBLK) lam[i] = M[(long)i * N + i];
   } else {
-    // W2 = (X - s Y) Q ; M = Q^t W2 (symmetrised)
-    for (long t = threadIdx.x; t < NN; t += DBLK) {
-      const int i = (int)(t / N), c = (int)(t % N);
-      const double* xr = X + (long)i * N;
-      const double* yr = Y + (long)i * N;
-      double acc = 0.0;
-      for (int r = 0; r < N; ++r) acc += (xr[r] - s * yr[r]) * Q[(long)r * N + c];
-      W2[t] = acc;
-    }
+    if constexpr (lds_mode == 2)
+      for (long t = threadIdx.x; t < NN; t += DBLK) Q[t] = Qg[t];
     wg_sync();
-    for (long t = threadIdx.x; t < NN; t += DBLK) {
-      const int i = (int)(t / N), c = (int)(t % N);
-      if (c < i) continue;
+    // M = X - s Y ; W2 = M Q ; M = Q^t W2 (symmetrised)
+    for (long t = threadIdx.x; t < NN; t += DBLK) M[t] = X[t] - s * Y[t];
+    wg_sync();
+    wg_for2(N, N, [&](int i, int c) {
+      const double* mr = M + (long)i * N;
+      double acc = 0.0;
+      for (int r = 0; r < N; ++r) acc += mr[r] * Q[(long)r * N + c];
+      W2[(long)i * N + c] = acc;
+    });
+    wg_sync();
+    wg_for2(N, N, [&](int i, int c) {
+      if (c < i) return;
       double a1 = 0.0, a2 = 0.0;
       for (int r = 0; r < N; ++r) {
         a1 += Q[(long)r * N + i] * W2[(long)r * N + c];
@@ -495,22 +559,23 @@ __global__ __launch_bounds__(DBLK) void k_pinv_solve(int N, int nb, const double
       const double v = 0.5 * (a1 + a2);
       M[(long)i * N + c] = v;
       M[(long)c * N + i] = v;
-    }
+    });
     wg_sync();
     wg_jacobi(M, N, N, W2, N, 60);
     for (int i = threadIdx.x; i < N; i += DBLK) lam[i] = M[(long)i * N + i];
     wg_sync();
     // Q <- Q W2, through M as the temporary
-    for (long t = threadIdx.x; t < NN; t += DBLK) {
-      const int i = (int)(t / N), c = (int)(t % N);
+    wg_for2(N, N, [&](int i, int c) {
       double acc = 0.0;
       for (int r = 0; r < N; ++r) acc += Q[(long)i * N + r] * W2[(long)r * N + c];
-      M[t] = acc;
-    }
+      M[(long)i * N + c] = acc;
+    });
     wg_sync();
     for (long t = threadIdx.x; t < NN; t += DBLK) Q[t] = M[t];
   }
   wg_sync();
+  if constexpr (lds_mode == 2)
+    for (long t = threadIdx.x; t < NN; t += DBLK) Qg[t] = Q[t];
   if (threadIdx.x == 0) {
     int best = 0;
     for (int i = 1; i < N; ++i)
@@ -518,9 +583,11 @@ __global__ __launch_bounds__(DBLK) void k_pinv_solve(int N, int nb, const double
     imin = best;
   }
   wg_sync();
+  for (int r = threadIdx.x; r < N; r += DBLK) rj[r] = rhs[(long)r * nb + j];
+  wg_sync();
   for (int i = threadIdx.x; i < N; i += DBLK) {
     double d = 0.0;
-    for (int r = 0; r < N; ++r) d += Q[(long)r * N + i] * rhs[(long)r * nb + j];
+    for (int r = 0; r < N; ++r) d += Q[(long)r * N + i] * rj[r];
     const double l = lam[i];
     cf[i] = (i == imin || l == 0.0) ? 0.0 : d / l;
   }
@@ -532,33 +599,42 @@ __global__ __launch_bounds__(DBLK) void k_pinv_solve(int N, int nb, const double
   }
 }
 
-// The eigensolve of X - sigma_j Y keeps the matrix in LDS when it fits the workgroup's share
-// (gfx950: 160 KB per CU); the rotation accumulator stays in global memory (L2).
-static size_t pinv_lds_bytes(int N) {
-  static int max_lds = -1;
-  if (max_lds < 0) {
+// The eigensolve of X - sigma_j Y keeps its working matrices in LDS when they fit the workgroup's
+// share (gfx950: 160 KB per CU): all three N x N arrays for small N, else the matrix alone.
+static int pinv_max_dyn_lds() {
+  static int max_dyn = -1;
+  if (max_dyn < 0) {
     int dev = 0, v = 0;
     (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) v = 65536;
-    max_lds = v;
-    if (v > 65536 &&
-        hipFuncSetAttribute((const void*)k_pinv_solve, hipFuncAttributeMaxDynamicSharedMemorySize, v - 32768) !=
-            hipSuccess) {
+    const int static_lds = 49152;   // Jacobi rotation tables, reductions, coefficients, eigenvalues
+    max_dyn = v - static_lds;
+    if (max_dyn > 0 &&
+        (hipFuncSetAttribute((const void*)k_pinv_solve<1>, hipFuncAttributeMaxDynamicSharedMemorySize, max_dyn) !=
+             hipSuccess ||
+         hipFuncSetAttribute((const void*)k_pinv_solve<2>, hipFuncAttributeMaxDynamicSharedMemorySize, max_dyn) !=
+             hipSuccess)) {
       (void)hipGetLastError();
-      max_lds = 65536;
+      max_dyn = 0;
     }
+    if (max_dyn < 0) max_dyn = 0;
   }
-  const size_t need = (size_t)N * N * sizeof(double);
-  const size_t static_lds = 32768;   // Jacobi rotation tables, reductions, coefficients
-  return need + static_lds <= (size_t)max_lds ? need : 0;
+  return max_dyn;
 }
 
 void launch_pinv_solve(int N, int nb, const double* X, const double* Y, const double* sig, const double* rhs,
                        double* out, double* work, double* basis, int warm, int* status, hipStream_t s) {
   (void)status;
-  const size_t lds = pinv_lds_bytes(N);
-  hipLaunchKernelGGL(k_pinv_solve, dim3(nb), dim3(DBLK), lds, s, N, nb, X, Y, sig, rhs, out, work, basis, warm,
-                     lds ? 1 : 0);
+  const size_t one = (size_t)N * N * sizeof(double);
+  const size_t max_dyn = (size_t)pinv_max_dyn_lds();
+  const int mode = 3 * one <= max_dyn ? 2 : one <= max_dyn ? 1 : 0;
+  const size_t lds = mode == 2 ? 3 * one : mode == 1 ? one : 0;
+  if (mode == 2)
+    hipLaunchKernelGGL(k_pinv_solve<2>, dim3(nb), dim3(DBLK), lds, s, N, nb, X, Y, sig, rhs, out, work, basis, warm);
+  else if (mode == 1)
+    hipLaunchKernelGGL(k_pinv_solve<1>, dim3(nb), dim3(DBLK), lds, s, N, nb, X, Y, sig, rhs, out, work, basis, warm);
+  else
+    hipLaunchKernelGGL(k_pinv_solve<0>, dim3(nb), dim3(DBLK), 0, s, N, nb, X, Y, sig, rhs, out, work, basis, warm);
 }
 
 // Pencil variant, set-up once per additive phase: Y = L L^t, K = L^-1 X L^-t = W diag(mu) W^t,

@@ -29,10 +29,12 @@ static inline int lshift_of(int w) {
 // wavefront; each group takes every SPLIT-th nonzero and the partial sums meet by lane shuffles.
 // Lane layout of a row's group: lane = split * LPRc + column lane (LPRc = 1 << lshift).
 static inline int log2i(int v) { int s = 0; while ((1 << s) < v) ++s; return s; }
-static inline int split_of(long nnz, long rows, int lshift) {
-  if (nnz < 0 || rows <= 0) return 1;
-  const double avg = (double)nnz / (double)rows;
-  int sp = avg <= 10.0 ? 1 : avg <= 24.0 ? 4 : 16;
+static inline int split_of(long nnz, long rows, int lshift, double avg_other = 0.0) {
+  double avg = (nnz < 0 || rows <= 0) ? 0.0 : (double)nnz / (double)rows;
+  if (avg_other > avg) avg = avg_other;
+  // short rows: one lane group; otherwise enough groups that each lane walks a few nonzeros (the
+  // walk is a chain of dependent index / value loads, so its length sets the latency)
+  int sp = avg < 3.0 ? 1 : avg < 12.0 ? 4 : 16;
   while (sp > 1 && ((1 << lshift) * sp) > 64) sp >>= 1;
   return sp;
 }
@@ -189,6 +191,7 @@ __global__ __launch_bounds__(BLK) void k_rowop(RowOpPOD<T> a, int lshift) {
 #pragma unroll
   for (int c = 0; c < CPL; ++c) { kz[c] = T(0); my[c] = T(0); }
   if (a.Kv) {
+    #pragma unroll 4
     for (int k = a.Krp[row] + sidx, ke = a.Krp[row + 1]; k < ke; k += SPLIT) {
       T zv[CPL];
       ldrow<T, CPL>(a.z + (long)a.Kci[k] * w, c0, w, zv);
@@ -204,6 +207,7 @@ __global__ __launch_bounds__(BLK) void k_rowop(RowOpPOD<T> a, int lshift) {
     }
   }
   if (a.mmode == M_CSR) {
+    #pragma unroll 4
     for (int k = a.Mrp[row] + sidx, ke = a.Mrp[row + 1]; k < ke; k += SPLIT) {
       T yv[CPL];
       ldrow<T, CPL>(a.y + (long)a.Mci[k] * w, c0, w, yv);
@@ -244,7 +248,7 @@ void launch_rowop(const RowOpArgs<T>& a, hipStream_t s) {
   RowOpPOD<T> p{a.nrows, a.w, a.Krp, a.Kci, a.Kv, a.z, a.mmode, a.Mrp, a.Mci, a.Mv, a.y,
                 a.x, a.D, a.kap, a.sig, a.cmode, a.omega, a.out};
   int sh = lshift_of(a.w);
-  int sp = split_of(a.Kv ? a.nnzK : -1, a.nrows, sh);
+  int sp = split_of(a.Kv ? a.nnzK : -1, a.nrows, sh, a.mmode == M_CSR ? a.avgM : 0.0);
   int grid = ceil_div((long)a.nrows << (sh + log2i(sp)), BLK);
   if (cpl_of(a.w) == 2) SLAMG_DISPATCH_SPLIT(k_rowop, T, 2, sp, grid, s, p, sh);
   else SLAMG_DISPATCH_SPLIT(k_rowop, T, 1, sp, grid, s, p, sh);
@@ -283,6 +287,7 @@ __device__ __forceinline__ void kacz_row(const KaczPOD<T>& a, int r, int c0, int
     } else {
 #pragma unroll
       for (int c = 0; c < CPL; ++c) my[c] = T(0);
+      #pragma unroll 4
       for (int k = a.Mrp[r] + sidx, ke = a.Mrp[r + 1]; k < ke; k += SPLIT) {
         T yv[CPL];
         ldrow<T, CPL>(a.y + (long)a.Mci[k] * w, c0, w, yv);
@@ -306,6 +311,7 @@ __device__ __forceinline__ void kacz_row(const KaczPOD<T>& a, int r, int c0, int
   T dot[CPL];
 #pragma unroll
   for (int c = 0; c < CPL; ++c) dot[c] = T(0);
+  #pragma unroll 4
   for (int k = kb + sidx; k < ke; k += SPLIT) {
     int j = a.ci[k];
     T xv[CPL];
@@ -329,6 +335,7 @@ __device__ __forceinline__ void kacz_row(const KaczPOD<T>& a, int r, int c0, int
     T nr = shifted ? aa - T(2) * lam[c] * ab + lam[c] * lam[c] * bb : aa;
     coef[c] = nr > T(0) ? res / nr : T(0);
   }
+  #pragma unroll 4
   for (int k = kb + sidx; k < ke; k += SPLIT) {
     int j = a.ci[k];
     T* xp = a.x + (long)j * w;
@@ -403,6 +410,7 @@ void launch_kacz_wg(const KaczArgs<T>* halves, const int* const* cptr, const int
                     hipStream_t s) {
   KaczWgPOD<T> p{};
   long nnz = 0, rows = 0;
+  double avgM = 0.0;
   for (int h = 0; h < nhalf; ++h) {
     const KaczArgs<T>& a = halves[h];
     p.h[h] = KaczPOD<T>{0, a.rows, a.w, a.rp, a.ci, a.av, a.bv, a.lam, a.rn_aa, a.rn_ab, a.rn_bb,
@@ -412,12 +420,13 @@ void launch_kacz_wg(const KaczArgs<T>* halves, const int* const* cptr, const int
     if (a.nnz_rows > 0 && (double)a.nnz_total / a.nnz_rows > (rows ? (double)nnz / rows : 0.0)) {
       nnz = a.nnz_total; rows = a.nnz_rows;
     }
+    if (a.rmode == M_CSR && a.avgM > avgM) avgM = a.avgM;
   }
   p.nhalf = nhalf;
   p.nsweeps = nsweeps;
   const int w = halves[0].w;
   int sh = lshift_of(w);
-  int sp = split_of(rows ? nnz : -1, rows, sh);
+  int sp = split_of(rows ? nnz : -1, rows, sh, avgM);
   if (cpl_of(w) == 2) {
     if (sp == 1) hipLaunchKernelGGL((k_kacz_wg<T, 2, 1>), dim3(1), dim3(WGB), 0, s, p, sh);
     else if (sp == 4) hipLaunchKernelGGL((k_kacz_wg<T, 2, 4>), dim3(1), dim3(WGB), 0, s, p, sh);
@@ -437,7 +446,7 @@ void launch_kacz(const KaczArgs<T>& a, hipStream_t s) {
   KaczPOD<T> p{a.nrows, a.rows, a.w, a.rp, a.ci, a.av, a.bv, a.lam, a.rn_aa, a.rn_ab, a.rn_bb,
                a.rmode, a.Mrp, a.Mci, a.Mv, a.y, a.rsig, a.kap, a.x};
   int sh = lshift_of(a.w);
-  int sp = split_of(a.nnz_rows > 0 ? a.nnz_total : -1, a.nnz_rows, sh);
+  int sp = split_of(a.nnz_rows > 0 ? a.nnz_total : -1, a.nnz_rows, sh, a.rmode == M_CSR ? a.avgM : 0.0);
   int grid = ceil_div((long)a.nrows << (sh + log2i(sp)), BLK);
   if (cpl_of(a.w) == 2) SLAMG_DISPATCH_SPLIT(k_kacz, T, 2, sp, grid, s, p, sh);
   else SLAMG_DISPATCH_SPLIT(k_kacz, T, 1, sp, grid, s, p, sh);
@@ -479,7 +488,8 @@ __global__ __launch_bounds__(BLK) void k_dots(DotPOD<T> a, int lshift, double* p
       if (a.Kv) {
 #pragma unroll
         for (int c = 0; c < CPL; ++c) val[c] = T(0);
-        for (int k = a.Krp[row] + sidx, ke = a.Krp[row + 1]; k < ke; k += SPLIT) {
+        #pragma unroll 4
+    for (int k = a.Krp[row] + sidx, ke = a.Krp[row + 1]; k < ke; k += SPLIT) {
           T zv[CPL];
           ldrow<T, CPL>(a.z + (long)a.Kci[k] * w, c0, w, zv);
           T av = a.Kv[k];

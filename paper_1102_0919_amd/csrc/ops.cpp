@@ -85,6 +85,7 @@ void jac_half(hipStream_t s, Tmp& t, int rows, int w, const int* krp, const int*
   a.mmode = mmode; a.Mrp = mrp; a.Mci = mci; a.Mv = mv; a.y = x; a.x = x; a.D = dinv; a.kap = kap; a.sig = sig;
   a.cmode = cmode; a.omega = omega; a.out = out;
   a.nnzK = dev_nnz(krp, rows, s);
+  if (mmode == M_CSR && rows > 0) a.avgM = (double)dev_nnz(mrp, rows, s) / rows;
   launch_rowop(a, s);
   if (normalise) {
     double* part = t.get<double>(1024 * 16);
@@ -200,6 +201,7 @@ extern "C" slamg_status slamg_op_residual(int32_t nrows, int32_t w, const int32_
     a.mmode = d_mv ? M_CSR : M_IDENT; a.Mrp = d_mrp; a.Mci = d_mci; a.Mv = d_mv; a.y = d_y;
     a.kap = d_kap; a.sig = d_sig; a.cmode = C_RESID; a.out = d_out;
     a.nnzK = dev_nnz(d_krp, nrows, s);
+    if (d_mv && nrows > 0) a.avgM = (double)dev_nnz(d_mrp, nrows, s) / nrows;
     launch_rowop(a, s);
   });
 }

@@ -1,0 +1,94 @@
+"""Summarise a rocprofv3 kernel-trace database into a short markdown table.
+
+    python -m paper_1102_0919_amd.prof_summary DB_OR_DIR --title T --cmd "C" [--kernel NAME ...] [--pmc]
+
+Prints, for the whole run: calls, total and average duration of every kernel; then, for each kernel
+named with --kernel, its launches grouped by grid size (the largest grids are the finest level).
+With --pmc the database holds counter samples (rocprofv3 --pmc): their per-dispatch averages are
+listed per kernel and grid size instead.
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import os
+import sqlite3
+
+
+def _short(name: str) -> str:
+    s = name.split("(")[0].replace("void ", "").replace("slamg::", "")
+    return s.strip()
+
+
+def _find_db(path: str) -> str:
+    if os.path.isfile(path):
+        return path
+    dbs = sorted(glob.glob(os.path.join(path, "**", "*_results.db"), recursive=True))
+    if not dbs:
+        raise SystemExit(f"no rocprofv3 results database under {path}")
+    return dbs[-1]
+
+
+def kernel_table(con) -> list[str]:
+    rows = list(con.execute("select name, count(*), sum(duration), avg(duration) from kernels group by name"))
+    rows.sort(key=lambda r: -r[2])
+    tot = sum(r[2] for r in rows)
+    out = [f"Total kernel time: {tot / 1e6:.3f} ms over {sum(r[1] for r in rows)} dispatches", "",
+           "| kernel | calls | total (ms) | average (us) | share |", "|---|---|---|---|---|"]
+    for n, c, t, a in rows[:30]:
+        out.append(f"| `{_short(n)}` | {c} | {t / 1e6:.3f} | {a / 1e3:.2f} | {100.0 * t / tot:.1f}% |")
+    return out
+
+
+def grid_table(con, kernel: str) -> list[str]:
+    rows = list(con.execute(
+        "select name, grid_x, count(*), avg(duration), min(duration), max(duration) from kernels "
+        "where name like ? group by name, grid_x order by grid_x desc", (f"%{kernel}%",)))
+    out = [f"Launches of `{kernel}` by grid size (threads; the largest grid is the finest level):", "",
+           "| instance | grid_x | calls | average (us) | min (us) | max (us) |", "|---|---|---|---|---|---|"]
+    for n, g, c, a, lo, hi in rows[:12]:
+        inst = n.split("(")[0].replace("void ", "").replace("slamg::", "")
+        out.append(f"| `{inst}` | {g} | {c} | {a / 1e3:.2f} | {lo / 1e3:.2f} | {hi / 1e3:.2f} |")
+    return out
+
+
+def pmc_table(con, kernel: str | None) -> list[str]:
+    q = ("select k.name, k.grid_x, p.counter_name, count(*), avg(p.value) from pmc_events p "
+         "join kernels k on k.dispatch_id = p.dispatch_id ")
+    args: tuple = ()
+    if kernel:
+        q += "where k.name like ? "
+        args = (f"%{kernel}%",)
+    q += "group by k.name, k.grid_x, p.counter_name order by k.grid_x desc"
+    try:
+        rows = list(con.execute(q, args))
+    except sqlite3.Error as e:   # schema differences between rocprofv3 versions
+        return [f"(counter table not readable: {e})"]
+    out = ["| kernel | grid_x | counter | dispatches | average per dispatch |", "|---|---|---|---|---|"]
+    for n, g, cn, c, v in rows[:40]:
+        out.append(f"| `{_short(n)}` | {g} | {cn} | {c} | {v:.1f} |")
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("path")
+    ap.add_argument("--title", required=True)
+    ap.add_argument("--cmd", required=True)
+    ap.add_argument("--kernel", action="append", default=[])
+    ap.add_argument("--pmc", action="store_true")
+    a = ap.parse_args(argv)
+    con = sqlite3.connect(_find_db(a.path))
+    lines = [f"# {a.title}", "", "Command (repository root, one MI355X):", "", "    " + a.cmd, ""]
+    if a.pmc:
+        for k in a.kernel or [None]:
+            lines += pmc_table(con, k) + [""]
+    else:
+        lines += kernel_table(con) + [""]
+        for k in a.kernel:
+            lines += grid_table(con, k) + [""]
+    print("\n".join(lines))
+
+
+if __name__ == "__main__":
+    main()

@@ -316,10 +316,11 @@ def test_coarse_gsvd_parity(L, kind, target):
             assert np.allclose(hv[:, j] * s, Vo[:, j], atol=1e-7)
 
 
-@pytest.mark.parametrize("variant,m,n", [(0, 30, 20), (1, 30, 20), (2, 30, 20), (0, 120, 90), (2, 120, 90),
+@pytest.mark.parametrize("variant,m,n", [(0, 30, 20), (1, 30, 20), (2, 30, 20), (0, 60, 40), (2, 60, 40), (0, 120, 90), (2, 120, 90),
                                          (1, 120, 90)])
 def test_coarse_solve_parity(L, variant, m, n):
-    # N = m + n: 50 keeps the eigensolve in LDS, 210 in global memory; variant 2 is the warm start
+    # N = m + n: 50 keeps all three eigensolve arrays in LDS, 100 the matrix only, 210 none; variant 2
+    # is the warm start
     import scipy.linalg as sla
     rng = np.random.default_rng(6)
     Ad = rng.uniform(-1, 1, (m, n))
