@@ -25,13 +25,41 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-CLASS_NAMES = {0: "k_rowop (finest-level fused relaxation / residual row kernel)",
-               1: "k_kacz (finest-level Kaczmarz colour sweep)", 2: "k_gram (MFMA FP64 Gram)",
+CLASS_NAMES = {0: "k_rowop, finest-level relaxation sweeps",
+               1: "k_kacz, finest-level Kaczmarz colour sweeps", 2: "k_gram (MFMA FP64 Gram)",
                3: "k_spgemm_dot (Galerkin SpGEMM)", 4: "coarsest dense solves (k_pinv_solve / k_pencil_solve)",
-               5: "k_spmm (finest-level block SpMM)", 6: "k_dots (finest-level operator reductions)"}
-NCLS = 7
+               5: "k_spmm, finest-level block SpMM", 6: "k_dots, finest-level operator reductions",
+               7: "k_rowop, finest-level residuals"}
+NCLS = 8
 ALL_CLASSES = (1 << NCLS) - 1
 DEFAULT_WORKLOAD = "gradient2d_256_dom8"
+
+# HBM traffic of the dominant kernel class, from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs
+# (profiles/pmc_*_gradient2d_256_dom8.md), per dispatch in KiB for the two finest-level k_rowop
+# launch shapes (u rows, v rows), scaled by the same counters of a 1 GiB device copy
+# (profiles/pmc_*_copy_1GiB.md: FETCH 524302.4 KiB, WRITE 1048576.0 KiB per 1 GiB).  Valid only
+# for the kernel source the counters were taken with.
+TRAFFIC = {
+    ("gradient2d_256_dom8", 0): dict(
+        kernels_sha256="c7afaa9f8ef15961e9c2d59b4a3c96997383b0dc3f560d30dad8f4ecc2c9a795",
+        fetch_kib=(12189.1, 9079.6), write_kib=(8160.0, 4096.0),
+        copy_fetch_kib=524302.4, copy_write_kib=1048576.0, copy_bytes=1 << 30),
+}
+
+
+def _traffic(name, cls):
+    import hashlib
+    t = TRAFFIC.get((name, cls))
+    if t is None:
+        return None, "no counter run for this workload and kernel"
+    with open(os.path.join(ROOT, "paper_1102_0919_amd", "csrc", "kernels.hip"), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != t["kernels_sha256"]:
+            return None, "kernel source changed since the counter runs"
+    ff = t["copy_bytes"] / (t["copy_fetch_kib"] * 1024.0)
+    fw = t["copy_bytes"] / (t["copy_write_kib"] * 1024.0)
+    per = [(fk * ff + wk * fw) * 1024.0 for fk, wk in zip(t["fetch_kib"], t["write_kib"])]
+    return sum(per) / len(per), (f"rocprofv3 FETCH_SIZE x {ff:.4f} + WRITE_SIZE x {fw:.4f} (copy-calibrated), "
+                                 "mean of the finest-level u-row and v-row launches")
 
 
 def _closed_form(name, n_b, target):
@@ -154,12 +182,15 @@ def main():
         avg_ms = tot_ms[c] / tot_n[c]
         per_launch = tot_b[c] / tot_n[c]
         ach = per_launch / (avg_ms * 1e-3) / 1e9
+        traffic, tnote = _traffic(name, c)
         roof = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": CLASS_NAMES[c],
+                "frac": round(ach / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else int(traffic), "traffic_note": tnote,
+                "kernel": CLASS_NAMES[c],
                 "timed_launches_per_step": int(tot_n[c] / args.steps), "avg_launch_us": round(avg_ms * 1e3, 3),
-                "timing_sample": "HIP events around every launch of the kernel in the multiplicative phase and "
+                "timing_sample": "a HIP event pair around every launch of the kernel on the library stream "
                                  "in the eagerly launched additive iterations (every 32nd; the others replay a "
-                                 "HIP graph of the iteration)",
+                                 "HIP graph of the iteration) and in the multiplicative phase",
                 "algorithmic_bytes_per_launch": int(per_launch),
                 "graph_iters_per_step": int(last.report.graph_iters),
                 "sampled_class_ms_in_warmup": {CLASS_NAMES[i]: round(warm_ms[i], 3) for i in range(NCLS)}}

@@ -86,11 +86,12 @@ typedef struct {
                                with the pencil eigenbasis of (X, Y) computed once (0)           */
   int32_t profile_mask;     /* bit c set: time every launch of kernel class c with HIP events on
                                the context stream and report it (0 = off).  Classes:
-                               0 fused row kernel on the finest level (Jacobi-type relaxation,
-                               residual), 1 Kaczmarz sweeps on the finest level, 2 MFMA Gram
-                               products, 3 Galerkin SpGEMM, 4 coarsest dense solves, 5 block
-                               SpMM on the finest level, 6 operator reductions (dot products of
-                               a block with an operator product) on the finest level */
+                               0 fused row kernel on the finest level (Jacobi-type relaxation),
+                               1 Kaczmarz sweeps on the finest level, 2 MFMA Gram products,
+                               3 Galerkin SpGEMM, 4 coarsest dense solves, 5 block SpMM on the
+                               finest level, 6 operator reductions (dot products of a block with
+                               an operator product) on the finest level, 7 fused row kernel
+                               computing residuals on the finest level */
   int32_t verbose;          /* k > 0: one progress line on stderr after each multiplicative cycle
                                and every k additive iterations (0)                              */
   int32_t graphs;           /* 1: capture one additive iteration (V-cycle, Ritz step, residual

@@ -284,7 +284,7 @@ class Solver {
     }
     return pool[ev_used_++];
   }
-  template <class T> void rowop(int l, const RowOpArgs<T>& a, const DCsr* K);
+  template <class T> void rowop(int l, const RowOpArgs<T>& a, const DCsr* K, int cls = 0);
   template <class T> void spmm(int l, const DCsr& K, const T* Kv, int w, const T* x, T* y, double beta);
   template <class T> void dots(int l, const DotArgs<T>& a, const DCsr* K, double* out);
   template <class T> void kacz(int l, const KaczArgs<T>& a, long nnz_colour);
@@ -307,10 +307,10 @@ static double rowop_bytes(const RowOpArgs<T>& a, const DCsr* K) {
 }
 
 template <class T>
-void Solver::rowop(int l, const RowOpArgs<T>& a0, const DCsr* K) {
+void Solver::rowop(int l, const RowOpArgs<T>& a0, const DCsr* K, int cls) {
   RowOpArgs<T> a = a0;
   if (a.nnzK < 0 && K) a.nnzK = K->nnz;
-  if (l == 0) prof(0, rowop_bytes(a, K), [&] { launch_rowop(a, st_); });
+  if (l == 0) prof(cls, rowop_bytes(a, K), [&] { launch_rowop(a, st_); });
   else launch_rowop(a, st_);
 }
 
@@ -1310,14 +1310,14 @@ void Solver::additive_vcycle(const double* sig, T* rhsU, T* rhsV) {
     if (spd_) { a.mmode = L.finest ? M_IDENT : M_SHARED; a.Mv = vals<T>(L.B); }
     else { a.mmode = L.finest ? M_IDENT : M_CSR; a.Mrp = L.B.rp; a.avgM = avg_row(L.B); a.Mci = L.B.ci; a.Mv = vals<T>(L.B); }
     a.y = b.Ub; a.kap = kap; a.sig = sig; a.cmode = C_RESID; a.out = b.tU;
-    rowop(l, a, &L.A);
+    rowop(l, a, &L.A, 7);
     spmm<T>(l, L.su.Pt, vals<T>(L.su.Pt), nb_, b.tU, cb.kap, 0.0);
     if (!spd_) {
       RowOpArgs<T> s;
       s.nrows = mv; s.w = nb_; s.Krp = L.At.rp; s.Kci = L.At.ci; s.nnzK = L.At.nnz; s.Kv = vals<T>(L.At); s.z = b.Ub;
       s.mmode = L.finest ? M_IDENT : M_CSR; s.Mrp = L.C.rp; s.avgM = avg_row(L.C); s.Mci = L.C.ci; s.Mv = vals<T>(L.C);
       s.y = b.Vb; s.kap = tau; s.sig = sig; s.cmode = C_RESID; s.out = b.tV;
-      rowop(l, s, &L.At);
+      rowop(l, s, &L.At, 7);
       spmm<T>(l, L.sv.Pt, vals<T>(L.sv.Pt), nb_, b.tV, cb.tau, 0.0);
     }
     if constexpr (std::is_same<T, double>::value) {
@@ -1373,13 +1373,13 @@ void Solver::additive_iteration() {
   RowOpArgs<double> a;
   a.nrows = mu; a.w = nb_; a.Krp = L.A.rp; a.Kci = L.A.ci; a.nnzK = L.A.nnz; a.Kv = L.A.v; a.z = spd_ ? L.bd.Ub : L.bd.Vb;
   a.mmode = M_IDENT; a.y = L.bd.Ub; a.sig = sig_; a.cmode = C_RESID; a.out = L.bd.tU;
-  rowop(0, a, &L.A);
+  rowop(0, a, &L.A, 7);
   launch_copy_cast_df(L.bd.tU, L.bf.kap, (size_t)mu * nb_, st_);
   if (!spd_) {
     RowOpArgs<double> s;
     s.nrows = mv; s.w = nb_; s.Krp = L.At.rp; s.Kci = L.At.ci; s.nnzK = L.At.nnz; s.Kv = L.At.v; s.z = L.bd.Ub;
     s.mmode = M_IDENT; s.y = L.bd.Vb; s.sig = sig_; s.cmode = C_RESID; s.out = L.bd.tV;
-    rowop(0, s, &L.At);
+    rowop(0, s, &L.At, 7);
     launch_copy_cast_df(L.bd.tV, L.bf.tau, (size_t)mv * nb_, st_);
   }
   launch_fillf(L.bf.Ub, (size_t)(mu + (spd_ ? 0 : mv)) * nb_, 0.0f, st_);

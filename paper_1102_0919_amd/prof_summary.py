@@ -53,18 +53,19 @@ def grid_table(con, kernel: str) -> list[str]:
 
 
 def pmc_table(con, kernel: str | None) -> list[str]:
-    q = ("select k.name, k.grid_x, p.counter_name, count(*), avg(p.value) from pmc_events p "
-         "join kernels k on k.dispatch_id = p.dispatch_id ")
+    q = ("select kernel_name, grid_size, counter_name, count(*), avg(value) from counters_collection ")
     args: tuple = ()
     if kernel:
-        q += "where k.name like ? "
+        q += "where kernel_name like ? "
         args = (f"%{kernel}%",)
-    q += "group by k.name, k.grid_x, p.counter_name order by k.grid_x desc"
+    q += "group by kernel_name, grid_size, counter_name order by grid_size desc"
     try:
         rows = list(con.execute(q, args))
     except sqlite3.Error as e:   # schema differences between rocprofv3 versions
         return [f"(counter table not readable: {e})"]
-    out = ["| kernel | grid_x | counter | dispatches | average per dispatch |", "|---|---|---|---|---|"]
+    title = f"`{kernel}`" if kernel else "all kernels"
+    out = [f"Counters of {title} by grid size (threads):", "",
+           "| kernel | grid | counter | dispatches | average per dispatch |", "|---|---|---|---|---|"]
     for n, g, cn, c, v in rows[:40]:
         out.append(f"| `{_short(n)}` | {g} | {cn} | {c} | {v:.1f} |")
     return out

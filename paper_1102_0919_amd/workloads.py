@@ -259,7 +259,7 @@ WORKLOADS = {
                                            mu_b=4, n_mult=3)),
     "aniso3d_128_min8": dict(desc="3-D anisotropic 7-point Dirichlet 128^3 (n=2097152, eps=0.01), 8 minimal eigenpairs",
                              kind="spd", target="minimal", n_b=8,
-                             params=dict(theta=0.06, n_t=8, mu_t=4, mu_b=4, n_mult=10)),
+                             params=dict(theta=0.06, n_t=8, mu_t=4, mu_b=4, n_mult=10, coarse_pinv=1)),
 }
 
 
