@@ -118,6 +118,8 @@ typedef struct {
   double prof_bytes[8];                      /*   summed algorithmic bytes of those launches    */
   int32_t graph_iters;                       /* additive iterations run as graph replays        */
   int32_t pad_;
+  int64_t device_bytes;                      /* device memory the solve allocated (all levels)  */
+  double t_queue_ms, t_latency_ms;           /* requests: submit -> start, submit -> result      */
 } slamg_report;
 
 typedef struct slamg_ctx slamg_ctx;
@@ -154,14 +156,29 @@ slamg_status slamg_solve_matrix(slamg_ctx* ctx, const slamg_matrix* M, slamg_tar
                                 const slamg_params* p, const double* init_tests, double* sigma, double* U,
                                 double* V, int32_t outputs_on_device, slamg_report* rep);
 
-/* Request interface: submit returns an id at once; the request is solved on the context's device
- * when slamg_poll or slamg_fetch is called (first come, first served).  fetch returns
- * SLAMG_E_BUSY while unfinished, else the request's status and outputs, and frees it. */
+/* Request interface (the problem of §1 as a stream of requests).  submit copies A, checks the
+ * request's device-memory estimate against the context's HBM budget (SLAMG_E_BUDGET if it can
+ * never fit) and returns an id at once.  Without the serving loop, the request is solved on the
+ * context stream when slamg_poll, slamg_wait or slamg_fetch asks for it (first come, first
+ * served).  poll sets *done; wait blocks until the request is done; fetch returns SLAMG_E_BUSY
+ * while unfinished, else the request's status, outputs (as slamg_solve) and report (with its
+ * queueing time and latency), and frees it. */
 slamg_status slamg_submit(slamg_ctx* ctx, const slamg_csr* A, slamg_kind kind, slamg_target target,
                           int32_t n_b, const slamg_params* p, uint64_t* request_id);
 slamg_status slamg_poll(slamg_ctx* ctx, uint64_t request_id, int32_t* done);
+slamg_status slamg_wait(slamg_ctx* ctx, uint64_t request_id);
 slamg_status slamg_fetch(slamg_ctx* ctx, uint64_t request_id, double* sigma, double* U, double* V,
                          slamg_report* rep);
+
+/* Serving loop: `slots` (1..64) worker threads, each with its own HIP stream on the context's
+ * device, solve submitted requests as they arrive.  A request starts when a slot is free and its
+ * device-memory estimate fits the context's HBM budget beside the running requests (first fit
+ * among the 64 oldest pending ones); its solve then overlaps on the device with the others and
+ * may use at most its estimate.  Results are the same as those of slamg_solve on the request
+ * alone.  stop finishes the pending requests, then joins the workers (slamg_destroy calls it).
+ * The context's API calls stay single-threaded; only the workers run concurrently. */
+slamg_status slamg_serve_start(slamg_ctx* ctx, int32_t slots);
+slamg_status slamg_serve_stop(slamg_ctx* ctx);
 
 const char* slamg_status_string(slamg_status s);
 const char* slamg_last_error(const slamg_ctx* ctx);

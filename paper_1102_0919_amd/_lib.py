@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(HERE, "libslamg.so")
 SLAMG_OK, SLAMG_NOT_CONVERGED = 0, 1
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "E_INVALID", -2: "E_OOM", -3: "E_BUDGET", -4: "E_DEVICE",
                 -5: "E_NUMERIC", -6: "E_BUSY"}
+STATUS_BUSY = -6
 KIND = {"svd": 0, "spd": 1}
 TARGET = {"dominant": 0, "minimal": 1}
 PRECISION = {"fp64": 0, "mixed_fp32": 1}
@@ -42,7 +43,8 @@ class Report(C.Structure):
                 ("anorm", C.c_double), ("resid", C.c_double * 16), ("rho_history", C.c_double * 256),
                 ("mult_sigma", (C.c_double * 16) * 32), ("t_setup_ms", C.c_double), ("t_solve_ms", C.c_double),
                 ("err_bound", C.c_double * 16), ("prof_ms", C.c_double * 8), ("prof_launches", C.c_int64 * 8),
-                ("prof_bytes", C.c_double * 8), ("graph_iters", C.c_int32), ("pad_", C.c_int32)]
+                ("prof_bytes", C.c_double * 8), ("graph_iters", C.c_int32), ("pad_", C.c_int32),
+                ("device_bytes", C.c_int64), ("t_queue_ms", C.c_double), ("t_latency_ms", C.c_double)]
 
 
 _P = C.c_void_p
@@ -60,6 +62,9 @@ SIGNATURES = {
     "slamg_solve_matrix": (_I, [_P, _P, _I, _I, C.POINTER(Params), _P, _P, _P, _P, _I, C.POINTER(Report)]),
     "slamg_submit": (_I, [_P, C.POINTER(Csr), _I, _I, _I, C.POINTER(Params), C.POINTER(C.c_uint64)]),
     "slamg_poll": (_I, [_P, C.c_uint64, C.POINTER(_I)]),
+    "slamg_wait": (_I, [_P, C.c_uint64]),
+    "slamg_serve_start": (_I, [_P, _I]),
+    "slamg_serve_stop": (_I, [_P]),
     "slamg_fetch": (_I, [_P, C.c_uint64, _P, _P, _P, C.POINTER(Report)]),
     "slamg_status_string": (C.c_char_p, [_I]),
     "slamg_last_error": (C.c_char_p, [_P]),

@@ -201,15 +201,36 @@ def poll(ctx: Context, rid: int) -> bool:
     return bool(done.value)
 
 
-def fetch(ctx: Context, rid: int, m: int, n: int, n_b: int, kind: str) -> Result:
+def wait(ctx: Context, rid: int) -> None:
+    """slamg_wait: block until the request is done."""
+    st = ctx.lib.slamg_wait(ctx.h, rid)
+    if st != 0:
+        raise SlamgError(st, ctx.last_error())
+
+
+def fetch(ctx: Context, rid: int, m: int, n: int, n_b: int, kind: str, raise_errors: bool = True) -> Result:
+    """slamg_fetch; with raise_errors False a failed request comes back as a Result with its status."""
     sig = np.zeros(n_b)
     U = np.zeros((n_b, m))
     V = np.zeros((n_b, n)) if kind == "svd" else None
     rep = L.Report()
     st = ctx.lib.slamg_fetch(ctx.h, rid, _ptr(sig), _ptr(U), _ptr(V) if V is not None else None, C.byref(rep))
-    if st not in (0, 1):
+    if st not in (0, 1) and (raise_errors or st == L.STATUS_BUSY):
         raise SlamgError(st, ctx.last_error())
     return Result(sig, U.T.copy(), None if V is None else V.T.copy(), st, rep)
+
+
+def serve_start(ctx: Context, slots: int) -> None:
+    """slamg_serve_start: solve submitted requests concurrently on `slots` streams."""
+    st = ctx.lib.slamg_serve_start(ctx.h, slots)
+    if st != 0:
+        raise SlamgError(st, ctx.last_error())
+
+
+def serve_stop(ctx: Context) -> None:
+    st = ctx.lib.slamg_serve_stop(ctx.h)
+    if st != 0:
+        raise SlamgError(st, ctx.last_error())
 
 
 def status_string(status: int) -> str:

@@ -3,12 +3,16 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
 #include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
+#include <thread>
 
 #include "../../include/slamg.h"
 #include "graph.h"
@@ -30,6 +34,10 @@ struct Request {
   slamg_status status = SLAMG_OK;
   std::vector<double> sigma, U, V;
   slamg_report rep{};
+  // serving loop
+  size_t est = 0;                                       // admission estimate of the footprint
+  std::string err;
+  std::chrono::steady_clock::time_point t_submit, t_start;
 };
 
 struct slamg_ctx {
@@ -41,12 +49,33 @@ struct slamg_ctx {
   uint64_t next_id = 1;
   std::deque<uint64_t> queue;
   std::map<uint64_t, std::unique_ptr<Request>> reqs;
+  // serving loop: worker threads, one HIP stream each; queue, reqs and the fields below are
+  // guarded by mu once it runs
+  std::mutex mu;
+  std::condition_variable cv;
+  std::vector<std::thread> workers;
+  std::vector<hipStream_t> wstreams;
+  bool serving = false, stopping = false;
+  size_t reserved = 0;     // admission estimates of the running requests
+  int running = 0;
 };
 
 static slamg_status fail(slamg_ctx* c, slamg_status s, const std::string& msg) {
   if (c) c->err = msg;
   return s;
 }
+static slamg_status fail(std::string& err, slamg_status s, const std::string& msg) {
+  err = msg;
+  return s;
+}
+
+// Where a solve runs: device, stream, device-memory budget of its arena.
+struct Exec {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  size_t budget = 0;
+};
+static Exec exec_of(const slamg_ctx* c) { return Exec{c->device, c->stream, c->budget}; }
 
 extern "C" slamg_status slamg_params_init(slamg_params* p, slamg_kind kind, slamg_target target) {
   if (!p) return SLAMG_E_INVALID;
@@ -99,8 +128,11 @@ extern "C" slamg_status slamg_create(slamg_ctx** ctx, int device, void* hip_stre
   return SLAMG_OK;
 }
 
+extern "C" slamg_status slamg_serve_stop(slamg_ctx* ctx);
+
 extern "C" void slamg_destroy(slamg_ctx* ctx) {
   if (!ctx) return;
+  (void)slamg_serve_stop(ctx);
   if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
@@ -167,10 +199,10 @@ struct Prepared {
   HCsr A;
 };
 
-static slamg_status prepare(slamg_ctx* c, int64_t m0, int64_t n0, const std::vector<int64_t>& rp,
+static slamg_status prepare(std::string& err, int64_t m0, int64_t n0, const std::vector<int64_t>& rp,
                             const std::vector<int32_t>& ci, const std::vector<double>& v, slamg_kind kind,
                             Prepared& P) {
-  if (kind == SLAMG_SPD_EIG && m0 != n0) return fail(c, SLAMG_E_INVALID, "SPD kind needs a square matrix");
+  if (kind == SLAMG_SPD_EIG && m0 != n0) return fail(err, SLAMG_E_INVALID, "SPD kind needs a square matrix");
   HCsr A;
   A.m = (int)m0; A.n = (int)n0;
   A.rp.resize(m0 + 1);
@@ -197,7 +229,7 @@ static slamg_status prepare(slamg_ctx* c, int64_t m0, int64_t n0, const std::vec
     for (int j = 0; j < A.n; ++j)
       if (colcnt[j] > 0) P.ckeep.push_back(j);
   }
-  if (P.rkeep.empty() || P.ckeep.empty()) return fail(c, SLAMG_E_INVALID, "matrix has no nonzero entries");
+  if (P.rkeep.empty() || P.ckeep.empty()) return fail(err, SLAMG_E_INVALID, "matrix has no nonzero entries");
   std::vector<int> cmap(A.n, -1);
   for (size_t j = 0; j < P.ckeep.size(); ++j) cmap[P.ckeep[j]] = (int)j;
   P.A = HCsr();
@@ -214,55 +246,55 @@ static slamg_status prepare(slamg_ctx* c, int64_t m0, int64_t n0, const std::vec
     for (int i = 0; i < P.A.m; ++i) {
       bool d = false;
       for (int k = P.A.rp[i]; k < P.A.rp[i + 1]; ++k) d |= P.A.ci[k] == i && P.A.v[k] > 0.0;
-      if (!d) return fail(c, SLAMG_E_INVALID, "SPD kind needs a positive diagonal");
+      if (!d) return fail(err, SLAMG_E_INVALID, "SPD kind needs a positive diagonal");
     }
   }
   return SLAMG_OK;
 }
 
-static slamg_status check_params(slamg_ctx* c, const Prepared& P, int32_t nb, const slamg_params& p) {
-  if (nb < 1 || nb > 16) return fail(c, SLAMG_E_INVALID, "n_b must be in 1..16");
-  if (!(p.tol > 0.0)) return fail(c, SLAMG_E_INVALID, "tol must be positive");
-  if (p.n_t < 2 || p.n_t > 16) return fail(c, SLAMG_E_INVALID, "n_t must be in 2..16");
-  if (p.mu_t < 0 || p.mu_b < 0 || p.n_mult < 1 || p.max_add < 0) return fail(c, SLAMG_E_INVALID, "bad counts");
+static slamg_status check_params(std::string& err, const Prepared& P, int32_t nb, const slamg_params& p) {
+  if (nb < 1 || nb > 16) return fail(err, SLAMG_E_INVALID, "n_b must be in 1..16");
+  if (!(p.tol > 0.0)) return fail(err, SLAMG_E_INVALID, "tol must be positive");
+  if (p.n_t < 2 || p.n_t > 16) return fail(err, SLAMG_E_INVALID, "n_t must be in 2..16");
+  if (p.mu_t < 0 || p.mu_b < 0 || p.n_mult < 1 || p.max_add < 0) return fail(err, SLAMG_E_INVALID, "bad counts");
   if (p.precision != SLAMG_FP64 && p.precision != SLAMG_MIXED_FP32)
-    return fail(c, SLAMG_E_INVALID, "unknown precision");
-  if (p.coarse_pinv != 0 && p.coarse_pinv != 1) return fail(c, SLAMG_E_INVALID, "unknown coarse_pinv");
-  if (p.strength_rule < 0 || p.strength_rule > 2) return fail(c, SLAMG_E_INVALID, "unknown strength rule");
-  if (nb > std::min(P.m0, P.n0)) return fail(c, SLAMG_E_INVALID, "n_b larger than min(m, n)");
-  if (nb > std::min(P.A.m, P.A.n)) return fail(c, SLAMG_E_INVALID, "n_b larger than the nonzero part of A");
+    return fail(err, SLAMG_E_INVALID, "unknown precision");
+  if (p.coarse_pinv != 0 && p.coarse_pinv != 1) return fail(err, SLAMG_E_INVALID, "unknown coarse_pinv");
+  if (p.strength_rule < 0 || p.strength_rule > 2) return fail(err, SLAMG_E_INVALID, "unknown strength rule");
+  if (nb > std::min(P.m0, P.n0)) return fail(err, SLAMG_E_INVALID, "n_b larger than min(m, n)");
+  if (nb > std::min(P.A.m, P.A.n)) return fail(err, SLAMG_E_INVALID, "n_b larger than the nonzero part of A");
   return SLAMG_OK;
 }
 
-static slamg_status run_guarded(slamg_ctx* c, Problem& pb, const slamg_params& p, const double* init_tests,
-                                SolveOutput& out) {
+static slamg_status run_guarded(const Exec& x, std::string& err, Problem& pb, const slamg_params& p,
+                                const double* init_tests, SolveOutput& out) {
   try {
-    if (hipSetDevice(c->device) != hipSuccess) return fail(c, SLAMG_E_DEVICE, "hipSetDevice failed");
-    run_solver(c->stream, c->budget, pb, p, init_tests, out);
+    if (hipSetDevice(x.device) != hipSuccess) return fail(err, SLAMG_E_DEVICE, "hipSetDevice failed");
+    run_solver(x.stream, x.budget, pb, p, init_tests, out);
   } catch (const SolverError& e) {
-    (void)hipStreamSynchronize(c->stream);
-    return fail(c, (slamg_status)e.code, e.msg);
+    (void)hipStreamSynchronize(x.stream);
+    return fail(err, (slamg_status)e.code, e.msg);
   } catch (const std::bad_alloc&) {
-    return fail(c, SLAMG_E_OOM, "host allocation failed");
+    return fail(err, SLAMG_E_OOM, "host allocation failed");
   }
   return SLAMG_OK;
 }
 
-static slamg_status solve_host(slamg_ctx* c, int64_t m0, int64_t n0, const std::vector<int64_t>& rp,
+static slamg_status solve_host(const Exec& x, std::string& err, int64_t m0, int64_t n0, const std::vector<int64_t>& rp,
                                const std::vector<int32_t>& ci, const std::vector<double>& v, slamg_kind kind,
                                slamg_target target, int32_t nb, const slamg_params& p, const double* init_tests,
                                std::vector<double>& sigma, std::vector<double>& Uc, std::vector<double>& Vc,
                                slamg_report* rep) {
   Prepared P;
-  slamg_status s = prepare(c, m0, n0, rp, ci, v, kind, P);
+  slamg_status s = prepare(err, m0, n0, rp, ci, v, kind, P);
   if (s != SLAMG_OK) return s;
-  s = check_params(c, P, nb, p);
+  s = check_params(err, P, nb, p);
   if (s != SLAMG_OK) return s;
   Problem pb;
   pb.kind = kind; pb.target = target; pb.nb = nb;
   pb.A = P.A;
   SolveOutput out;
-  s = run_guarded(c, pb, p, init_tests, out);
+  s = run_guarded(x, err, pb, p, init_tests, out);
   if (s != SLAMG_OK) return s;
   // scatter back, sign convention on the caller's v_j (x_j), column-major outputs
   const int mp = pb.A.m, np = pb.A.n;
@@ -292,10 +324,10 @@ static slamg_status solve_host(slamg_ctx* c, int64_t m0, int64_t n0, const std::
   Vc.swap(Vf);
   if (rep) *rep = out.rep;
   if (out.status == ST_NOT_CONVERGED) {
-    c->err = "tolerance not reached within max_add iterations";
+    err = "tolerance not reached within max_add iterations";
     return SLAMG_NOT_CONVERGED;
   }
-  c->err.clear();
+  err.clear();
   return SLAMG_OK;
 }
 
@@ -348,7 +380,7 @@ extern "C" slamg_status slamg_matrix_create(slamg_ctx* ctx, const slamg_csr* A, 
   if (s != SLAMG_OK) return s;
   auto M = std::make_unique<slamg_matrix>();
   M->ctx = ctx;
-  s = prepare(ctx, A->m, A->n, rp, ci, v, kind, M->P);
+  s = prepare(ctx->err, A->m, A->n, rp, ci, v, kind, M->P);
   if (s != SLAMG_OK) return s;
   try {
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SLAMG_E_DEVICE, "hipSetDevice failed");
@@ -397,7 +429,7 @@ extern "C" slamg_status slamg_solve_matrix(slamg_ctx* ctx, const slamg_matrix* M
   if (p) prm = *p;
   else slamg_params_init(&prm, (slamg_kind)M->P.kind, target);
   const Prepared& P = M->P;
-  slamg_status s = check_params(ctx, P, n_b, prm);
+  slamg_status s = check_params(ctx->err, P, n_b, prm);
   if (s != SLAMG_OK) return s;
   Problem pb;
   pb.kind = P.kind; pb.target = target; pb.nb = n_b;
@@ -415,7 +447,7 @@ extern "C" slamg_status slamg_solve_matrix(slamg_ctx* ctx, const slamg_matrix* M
     if (!pb.outU && !pb.outV) pb.outU = nullptr;
   }
   SolveOutput out;
-  s = run_guarded(ctx, pb, prm, init_tests, out);
+  s = run_guarded(exec_of(ctx), ctx->err, pb, prm, init_tests, out);
   if (s != SLAMG_OK) return s;
   std::copy(out.sigma.begin(), out.sigma.end(), sigma);
   if (!outputs_on_device && (U || V)) {
@@ -465,7 +497,7 @@ extern "C" slamg_status slamg_solve(slamg_ctx* ctx, const slamg_csr* A, slamg_ki
   slamg_status s = fetch_csr(ctx, A, rp, ci, v);
   if (s != SLAMG_OK) return s;
   std::vector<double> sg, Uc, Vc;
-  s = solve_host(ctx, A->m, A->n, rp, ci, v, kind, target, n_b, prm, init_tests, sg, Uc, Vc, rep);
+  s = solve_host(exec_of(ctx), ctx->err, A->m, A->n, rp, ci, v, kind, target, n_b, prm, init_tests, sg, Uc, Vc, rep);
   if (s != SLAMG_OK && s != SLAMG_NOT_CONVERGED) return s;
   std::copy(sg.begin(), sg.end(), sigma);
   if (U) std::copy(Uc.begin(), Uc.end(), U);
@@ -474,8 +506,30 @@ extern "C" slamg_status slamg_solve(slamg_ctx* ctx, const slamg_csr* A, slamg_ki
 }
 
 // ------------------------------------------------------------------------------------------------
-// Request interface: first come, first served on the context's device.
+// Request interface.  Without the serving loop, requests are solved first come, first served on
+// the context stream when poll / fetch asks for them.  With it (slamg_serve_start), worker threads
+// each own a HIP stream and take requests as they arrive: a request is admitted when a worker is
+// free and its footprint estimate fits the context's HBM budget next to those already running
+// (first fit among the oldest pending requests, so that small requests can pass a large one that
+// must wait for memory); its solve then overlaps on the device with the others.  Every solve
+// owns all of its device memory, and the kernels use no atomics, so a result does not depend on
+// what else runs.
 // ------------------------------------------------------------------------------------------------
+
+// Upper bound of a solve's device memory: operators and hierarchy (A, A^t, strength operators,
+// Galerkin products, interpolation: <= 400 B per nonzero of A), vector blocks of all levels
+// (test, boot, ping-pong, residual and scratch blocks, FP64 and FP32), and the dense coarsest
+// level (<= 1024 unknowns; X, Y, factors, work, per-column eigenvector stores).
+static size_t footprint_estimate(int64_t m, int64_t n, int64_t nnz, slamg_kind kind, int32_t nb,
+                                 const slamg_params& p) {
+  const double rows = (double)(kind == SLAMG_SVD ? m + n : m);
+  const double nc = std::min(1024.0, kind == SLAMG_SVD ? (double)(m + n) : (double)m);
+  const double w = (double)(4 * p.n_t + 12 * nb);
+  const double bytes = 64.0 * 1024 * 1024 + 400.0 * (double)nnz + 8.0 * rows * w * 2.0 +
+                       8.0 * (3.0 * nb + 10.0) * nc * nc;
+  return (size_t)bytes;
+}
+
 extern "C" slamg_status slamg_submit(slamg_ctx* ctx, const slamg_csr* A, slamg_kind kind, slamg_target target,
                                      int32_t n_b, const slamg_params* p, uint64_t* request_id) {
   if (!ctx || !request_id) return SLAMG_E_INVALID;
@@ -486,11 +540,23 @@ extern "C" slamg_status slamg_submit(slamg_ctx* ctx, const slamg_csr* A, slamg_k
   r->kind = kind; r->target = target; r->nb = n_b;
   if (p) r->p = *p;
   else slamg_params_init(&r->p, kind, target);
+  r->est = footprint_estimate(A->m, A->n, A->nnz, kind, n_b, r->p);
+  if (ctx->budget && r->est > ctx->budget)
+    return fail(ctx, SLAMG_E_BUDGET, "request footprint estimate exceeds the context's HBM budget");
+  r->t_submit = std::chrono::steady_clock::now();
+  std::lock_guard<std::mutex> lk(ctx->mu);
   r->id = ctx->next_id++;
   *request_id = r->id;
   ctx->queue.push_back(r->id);
   ctx->reqs[r->id] = std::move(r);
+  ctx->cv.notify_all();
   return SLAMG_OK;
+}
+
+static void finish(Request& r) {
+  const auto t = std::chrono::steady_clock::now();
+  r.rep.t_queue_ms = std::chrono::duration<double, std::milli>(r.t_start - r.t_submit).count();
+  r.rep.t_latency_ms = std::chrono::duration<double, std::milli>(t - r.t_submit).count();
 }
 
 static void process_until(slamg_ctx* ctx, uint64_t id) {
@@ -500,28 +566,126 @@ static void process_until(slamg_ctx* ctx, uint64_t id) {
     auto it = ctx->reqs.find(head);
     if (it == ctx->reqs.end()) continue;
     Request& r = *it->second;
-    r.status = solve_host(ctx, r.A.m, r.A.n, r.rp, r.ci, r.v, r.kind, r.target, r.nb, r.p, nullptr, r.sigma, r.U,
-                          r.V, &r.rep);
+    r.t_start = std::chrono::steady_clock::now();
+    r.status = solve_host(exec_of(ctx), ctx->err, r.A.m, r.A.n, r.rp, r.ci, r.v, r.kind, r.target, r.nb, r.p,
+                          nullptr, r.sigma, r.U, r.V, &r.rep);
+    r.err = ctx->err;
+    finish(r);
     r.done = true;
     if (head == id) break;
   }
 }
 
+// Worker thread of the serving loop.
+static void serve_worker(slamg_ctx* ctx, hipStream_t stream) {
+  (void)hipSetDevice(ctx->device);
+  std::unique_lock<std::mutex> lk(ctx->mu);
+  for (;;) {
+    Request* pick = nullptr;
+    size_t scanned = 0;
+    for (auto it = ctx->queue.begin(); it != ctx->queue.end() && scanned < 64; ++it, ++scanned) {
+      Request& r = *ctx->reqs.at(*it);
+      if (!ctx->budget || ctx->reserved + r.est <= ctx->budget) {
+        pick = &r;
+        ctx->queue.erase(it);
+        break;
+      }
+    }
+    if (!pick) {
+      if (ctx->stopping && ctx->queue.empty()) return;
+      ctx->cv.wait(lk);
+      continue;
+    }
+    ctx->reserved += pick->est;
+    ctx->running += 1;
+    pick->t_start = std::chrono::steady_clock::now();
+    lk.unlock();
+    Exec x{ctx->device, stream, ctx->budget ? pick->est : 0};
+    std::string err;
+    const slamg_status st = solve_host(x, err, pick->A.m, pick->A.n, pick->rp, pick->ci, pick->v, pick->kind,
+                                       pick->target, pick->nb, pick->p, nullptr, pick->sigma, pick->U, pick->V,
+                                       &pick->rep);
+    lk.lock();
+    pick->status = st;
+    pick->err = err;
+    finish(*pick);
+    pick->done = true;
+    ctx->reserved -= pick->est;
+    ctx->running -= 1;
+    ctx->cv.notify_all();
+  }
+}
+
+extern "C" slamg_status slamg_serve_start(slamg_ctx* ctx, int32_t slots) {
+  if (!ctx || slots < 1 || slots > 64) return SLAMG_E_INVALID;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (ctx->serving) return fail(ctx, SLAMG_E_INVALID, "the serving loop already runs");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SLAMG_E_DEVICE, "hipSetDevice failed");
+  for (int i = 0; i < slots; ++i) {
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      (void)hipGetLastError();
+      for (hipStream_t q : ctx->wstreams) (void)hipStreamDestroy(q);
+      ctx->wstreams.clear();
+      return fail(ctx, SLAMG_E_DEVICE, "stream creation failed");
+    }
+    ctx->wstreams.push_back(st);
+  }
+  ctx->stopping = false;
+  ctx->serving = true;
+  for (int i = 0; i < slots; ++i) ctx->workers.emplace_back(serve_worker, ctx, ctx->wstreams[i]);
+  return SLAMG_OK;
+}
+
+extern "C" slamg_status slamg_serve_stop(slamg_ctx* ctx) {
+  if (!ctx) return SLAMG_E_INVALID;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (!ctx->serving) return SLAMG_OK;
+    ctx->stopping = true;
+    ctx->cv.notify_all();
+  }
+  for (auto& t : ctx->workers) t.join();
+  ctx->workers.clear();
+  for (hipStream_t q : ctx->wstreams) (void)hipStreamDestroy(q);
+  ctx->wstreams.clear();
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->serving = false;
+  ctx->stopping = false;
+  return SLAMG_OK;
+}
+
 extern "C" slamg_status slamg_poll(slamg_ctx* ctx, uint64_t request_id, int32_t* done) {
   if (!ctx || !done) return SLAMG_E_INVALID;
+  std::lock_guard<std::mutex> lk(ctx->mu);
   auto it = ctx->reqs.find(request_id);
   if (it == ctx->reqs.end()) return fail(ctx, SLAMG_E_INVALID, "unknown request id");
-  if (!it->second->done) process_until(ctx, request_id);
+  if (!it->second->done && !ctx->serving) process_until(ctx, request_id);
   *done = it->second->done ? 1 : 0;
+  return SLAMG_OK;
+}
+
+extern "C" slamg_status slamg_wait(slamg_ctx* ctx, uint64_t request_id) {
+  if (!ctx) return SLAMG_E_INVALID;
+  std::unique_lock<std::mutex> lk(ctx->mu);
+  auto it = ctx->reqs.find(request_id);
+  if (it == ctx->reqs.end()) return fail(ctx, SLAMG_E_INVALID, "unknown request id");
+  Request& r = *it->second;
+  if (!ctx->serving) {
+    if (!r.done) process_until(ctx, request_id);
+    return SLAMG_OK;
+  }
+  ctx->cv.wait(lk, [&] { return r.done; });
   return SLAMG_OK;
 }
 
 extern "C" slamg_status slamg_fetch(slamg_ctx* ctx, uint64_t request_id, double* sigma, double* U, double* V,
                                     slamg_report* rep) {
   if (!ctx) return SLAMG_E_INVALID;
+  std::lock_guard<std::mutex> lk(ctx->mu);
   auto it = ctx->reqs.find(request_id);
   if (it == ctx->reqs.end()) return fail(ctx, SLAMG_E_INVALID, "unknown request id");
-  if (!it->second->done) process_until(ctx, request_id);
+  if (!it->second->done && !ctx->serving) process_until(ctx, request_id);
   Request& r = *it->second;
   if (!r.done) return SLAMG_E_BUSY;
   slamg_status s = r.status;
@@ -529,8 +693,9 @@ extern "C" slamg_status slamg_fetch(slamg_ctx* ctx, uint64_t request_id, double*
     if (sigma) std::copy(r.sigma.begin(), r.sigma.end(), sigma);
     if (U) std::copy(r.U.begin(), r.U.end(), U);
     if (V && r.kind == SLAMG_SVD) std::copy(r.V.begin(), r.V.end(), V);
-    if (rep) *rep = r.rep;
   }
+  if (rep) *rep = r.rep;
+  ctx->err = r.err;
   ctx->reqs.erase(it);
   return s;
 }

@@ -602,23 +602,23 @@ __global__ __launch_bounds__(DBLK) void k_pinv_solve(int N, int nb, const double
 // The eigensolve of X - sigma_j Y keeps its working matrices in LDS when they fit the workgroup's
 // share (gfx950: 160 KB per CU): all three N x N arrays for small N, else the matrix alone.
 static int pinv_max_dyn_lds() {
-  static int max_dyn = -1;
-  if (max_dyn < 0) {
+  // initialised once per process (thread-safe static initialisation)
+  static const int max_dyn = [] {
     int dev = 0, v = 0;
     (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) v = 65536;
     const int static_lds = 49152;   // Jacobi rotation tables, reductions, coefficients, eigenvalues
-    max_dyn = v - static_lds;
-    if (max_dyn > 0 &&
-        (hipFuncSetAttribute((const void*)k_pinv_solve<1>, hipFuncAttributeMaxDynamicSharedMemorySize, max_dyn) !=
+    int m = v - static_lds;
+    if (m > 0 &&
+        (hipFuncSetAttribute((const void*)k_pinv_solve<1>, hipFuncAttributeMaxDynamicSharedMemorySize, m) !=
              hipSuccess ||
-         hipFuncSetAttribute((const void*)k_pinv_solve<2>, hipFuncAttributeMaxDynamicSharedMemorySize, max_dyn) !=
+         hipFuncSetAttribute((const void*)k_pinv_solve<2>, hipFuncAttributeMaxDynamicSharedMemorySize, m) !=
              hipSuccess)) {
       (void)hipGetLastError();
-      max_dyn = 0;
+      m = 0;
     }
-    if (max_dyn < 0) max_dyn = 0;
-  }
+    return m < 0 ? 0 : m;
+  }();
   return max_dyn;
 }
 

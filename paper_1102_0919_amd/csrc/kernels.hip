@@ -32,9 +32,12 @@ static inline int log2i(int v) { int s = 0; while ((1 << s) < v) ++s; return s; 
 static inline int split_of(long nnz, long rows, int lshift, double avg_other = 0.0) {
   double avg = (nnz < 0 || rows <= 0) ? 0.0 : (double)nnz / (double)rows;
   if (avg_other > avg) avg = avg_other;
-  // short rows: one lane group; otherwise enough groups that each lane walks a few nonzeros (the
-  // walk is a chain of dependent index / value loads, so its length sets the latency)
-  int sp = avg < 3.0 ? 1 : avg < 12.0 ? 4 : 16;
+  // Short rows: one lane group.  Otherwise enough groups that each lane walks a few nonzeros (the
+  // walk is a chain of dependent index / value loads, so its length sets the latency) -- unless the
+  // rows alone already give the chip enough wavefronts (>= 4 per SIMD), where splitting only adds
+  // shuffles.
+  const bool many = (rows << lshift) >= (1L << 18);
+  int sp = many ? (avg < 12.0 ? 1 : avg < 48.0 ? 4 : 16) : (avg < 3.0 ? 1 : avg < 12.0 ? 4 : 16);
   while (sp > 1 && ((1 << lshift) * sp) > 64) sp >>= 1;
   return sp;
 }

@@ -270,8 +270,9 @@ class Solver {
   bool capturing_ = false, graph_off_ = false;
   void prof_finish();
   // events are reused across solves (creating one per launch would dominate the host time)
+  // (one pool per host thread: concurrent solves on several streams each own their events)
   static std::vector<hipEvent_t>& event_pool() {
-    static std::vector<hipEvent_t> pool;
+    thread_local std::vector<hipEvent_t> pool;
     return pool;
   }
   size_t ev_used_ = 0;
@@ -1629,6 +1630,7 @@ void Solver::run(const double* init_tests, SolveOutput& out) {
   auto t2 = clk::now();
   rep_.add_iters = it;
   rep_.converged = rmax <= p_.tol ? 1 : 0;
+  rep_.device_bytes = (int64_t)ar_.used();
   rep_.t_setup_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
   rep_.t_solve_ms = std::chrono::duration<double, std::milli>(t2 - t1).count();
   for (int j = 0; j < nb_ && j < 16; ++j) {
