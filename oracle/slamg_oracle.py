@@ -47,6 +47,8 @@ the design notes of the repository):
   R23 minimal SVD targets: after each Ritz step, u_j <- A v_j / ||A v_j|| for sigma_j > 1e-8 ||A||_est.
   R22 the extra F-point Jacobi step of the minimal LS fit (§3.8) uses weight omega_J on the
       strength operator N (A for eigenproblems, A A^t and A^t A for SVD).
+  R27 one-sided coarsening: on an SVD level where one side would keep fewer than n_b + n_t
+      C-points while the other coarsens, that side keeps all its points (identity interpolation).
 """
 from __future__ import annotations
 
@@ -596,6 +598,24 @@ def build_side(N, params, n_t):
     return Side(is_c, np.nonzero(is_c)[0], ptr, cols, capped)
 
 
+def identity_side(npts):
+    """Every point a C-point: the interpolation is the identity."""
+    return Side(np.ones(npts, dtype=bool), np.arange(npts), np.arange(npts + 1), np.arange(npts), 0)
+
+
+def one_sided_coarsening(su, sv, kind, need):
+    """R27: on an SVD level where one side would keep fewer than n_b + n_t C-points while the other
+    side coarsens, the first side is not coarsened (identity interpolation) instead of stopping."""
+    if kind == SPD:
+        return su, sv
+    cu, cv = int(su.is_c.sum()), int(sv.is_c.sum())
+    if cu < need <= cv:
+        su = identity_side(su.is_c.size)
+    elif cv < need <= cu:
+        sv = identity_side(sv.is_c.size)
+    return su, sv
+
+
 def minimal_presmooth(lev, kind, side_is_u, Vals, omega):
     """Extra Jacobi step on N z = 0 applied to the F-point values before the LS fit (§3.8, R22)."""
     A = lev.A
@@ -677,6 +697,7 @@ class Solver:
                 Nu, Nv = strength_operators(lev, kind, p, l == 0)
                 su = build_side(Nu, p, p.n_t)
                 sv = None if kind == SPD else build_side(Nv, p, p.n_t)
+                su, sv = one_sided_coarsening(su, sv, kind, self.n_b + p.n_t)
                 if not self._coarsening_ok(lev, su, sv):
                     break
                 lev.su, lev.sv = su, sv

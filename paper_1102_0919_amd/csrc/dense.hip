@@ -209,18 +209,28 @@ __device__ static void select_extremal(const double* lam, int n, int k, bool des
 }
 
 // ------------------------------------------------------------------------------------------------
-// Cholesky-QR step: G = R^t R, T = R^{-1} (upper), row-major w x w.  A non-positive pivot retries
-// once with a diagonal shift of 1e-14 trace; a second failure sets *status.
+// Cholesky-QR step: G = R^t R, T = R^{-1} (upper), row-major w x w, computed on the column-scaled
+// Gram matrix.  A non-positive pivot retries once with a diagonal shift of 1e-14 trace; a second
+// failure sets *status.
 // ------------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(DBLK) void k_chol_inv_upper(int w, const double* G, double* T, int* status) {
+  // Columns are first scaled to unit norm (D G D with D = diag(G)^-1/2, T = D R^-1): the span,
+  // and hence the Ritz step, is unchanged, and the factorisation then depends on the angles between
+  // the columns only, not on their norms (relaxations can grow some columns by many orders).
   __shared__ double L[16 * 16];
+  __shared__ double dsc[16];
   __shared__ int info;
+  for (int i = threadIdx.x; i < w; i += DBLK) {
+    const double g = G[i * w + i];
+    dsc[i] = g > 0.0 ? 1.0 / sqrt(g) : 1.0;
+  }
+  wg_sync();
   for (int attempt = 0; attempt < 2; ++attempt) {
     double tr = 0.0;
-    for (int i = 0; i < w; ++i) tr += G[i * w + i];
+    for (int i = 0; i < w; ++i) tr += G[i * w + i] * dsc[i] * dsc[i];
     for (int t = threadIdx.x; t < w * w; t += DBLK) {
       int i = t / w, j = t % w;
-      L[i * 16 + j] = G[t] + (attempt && i == j ? 1e-14 * tr : 0.0);
+      L[i * 16 + j] = G[t] * dsc[i] * dsc[j] + (attempt && i == j ? 1e-14 * tr : 0.0);
     }
     if (threadIdx.x == 0) info = 0;
     wg_sync();
@@ -229,9 +239,10 @@ __global__ __launch_bounds__(DBLK) void k_chol_inv_upper(int w, const double* G,
     if (attempt == 1 && threadIdx.x == 0) *status = ST_E_NUMERIC;
     wg_sync();
   }
-  // T = L^{-t}: solve L^t T = I
+  // T = D L^{-t}: solve L^t T' = I, then scale the rows
   for (int t = threadIdx.x; t < w * w; t += DBLK) T[t] = (t / w == t % w) ? 1.0 : 0.0;
   wg_trsm_lower_t(L, w, 16, T, w, w);
+  for (int t = threadIdx.x; t < w * w; t += DBLK) T[t] *= dsc[t / w];
 }
 void launch_chol_inv_upper(int w, const double* G, double* T, int* status, hipStream_t s) {
   hipLaunchKernelGGL(k_chol_inv_upper, dim3(1), dim3(DBLK), 0, s, w, G, T, status);

@@ -185,6 +185,8 @@ class Solver {
   void norm_estimate();
   bool build_structure(int l);
   void build_side(Level& L, Side& S, const HCsr& N, int npts);
+  void identity_side(Side& S, int npts);
+  void finish_side(Side& S, const std::vector<int>& ptr, const std::vector<int>& fine_cols);
   void make_coarse_level(int l);
   void refresh_level_aux(Level& L);
   void colour(Level& L);
@@ -716,23 +718,40 @@ void Solver::build_side(Level& L, Side& S, const HCsr& N, int npts) {
   S.is_c = rs_coarsen(Sp, Si, npts);
   std::vector<int> ptr, fine_cols;
   interp_pattern(Sp, Si, N, S.is_c, nt_ - 1, ptr, fine_cols, S.capped);
+  finish_side(S, ptr, fine_cols);
+}
+
+// Every point a C-point: the interpolation is the identity (one-sided coarsening of a level).
+void Solver::identity_side(Side& S, int npts) {
+  S.npts = npts;
+  S.is_c.assign(npts, 1);
+  S.capped = 0;
+  std::vector<int> ptr(npts + 1), fine_cols(npts);
+  for (int i = 0; i <= npts; ++i) ptr[i] = i;
+  for (int i = 0; i < npts; ++i) fine_cols[i] = i;
+  finish_side(S, ptr, fine_cols);
+}
+
+void Solver::finish_side(Side& S, const std::vector<int>& ptr, const std::vector<int>& fine_cols) {
+  const int npts = S.npts;
   std::vector<int> cidx(npts, -1);
   S.cpts.clear();
   for (int i = 0; i < npts; ++i)
     if (S.is_c[i]) { cidx[i] = (int)S.cpts.size(); S.cpts.push_back(i); }
   S.nc = (int)S.cpts.size();
+  S.Ppat = HCsr();
   S.Ppat.m = npts; S.Ppat.n = S.nc;
   S.Ppat.rp = ptr;
   S.Ppat.ci.resize(fine_cols.size());
   S.Ppat.v.assign(fine_cols.size(), 0.0);
-  std::vector<int> F;
   S.qmax = 0;
+  int nF = 0;
   for (int i = 0; i < npts; ++i) {
     for (int k = ptr[i]; k < ptr[i + 1]; ++k) S.Ppat.ci[k] = cidx[fine_cols[k]];
     if (S.is_c[i]) S.Ppat.v[ptr[i]] = 1.0;
-    else { F.push_back(i); S.qmax = std::max(S.qmax, ptr[i + 1] - ptr[i]); }
+    else { ++nF; S.qmax = std::max(S.qmax, ptr[i + 1] - ptr[i]); }
   }
-  S.nF = (int)F.size();
+  S.nF = nF;
   S.Ptpat = transpose(S.Ppat, &S.perm);
 }
 
@@ -748,9 +767,15 @@ bool Solver::build_structure(int l) {
     Nv = strength_operator(L, false, l == 0);
     build_side(L, sv, Nv, L.n);
   }
+  const int need = nb_ + nt_;
+  if (!spd_) {
+    // one-sided coarsening: a side that would keep fewer than n_b + n_t points while the other
+    // side coarsens keeps all of its points
+    if (su.nc < need && sv.nc >= need) identity_side(su, L.m);
+    else if (sv.nc < need && su.nc >= need) identity_side(sv, L.n);
+  }
   const int nc = spd_ ? su.nc : su.nc + sv.nc;
   if (nc > p_.stall_ratio * size_of(L)) return false;
-  const int need = nb_ + nt_;
   if (su.nc < need || (!spd_ && sv.nc < need)) return false;
   // device copies
   auto devside = [&](Side& S) {
@@ -978,6 +1003,7 @@ void Solver::boot_relax(int l, const T* kap, const T* tau, const double* sig, in
   Blocks<T>& b = blocks<T>(L);
   Aux<T>& x = aux<T>(L);
   const int mu = rows_u(L), mv = rows_v(L);
+  if (nsweeps <= 0) return;
   if (minimal_ && L.kacz_wg) {
     // all nsweeps sweeps, all colours, in one workgroup
     KaczArgs<T> h[2];
