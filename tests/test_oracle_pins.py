@@ -426,3 +426,27 @@ def test_table1_fd_reproduced(target, col):
     assert r.report["converged"]
     # printed with 8 significant digits
     assert np.allclose(r.sigma, rows[:, col], rtol=6e-8, atol=0)
+
+
+def test_one_sided_coarsening_identity_side_and_spectrum():
+    # R27 on a Zipf term-document matrix: the document side keeps all its points on level 1, so its
+    # interpolation is exactly the identity and C_2 = Q^t C_1 Q equals C_1; the leading singular
+    # values found through that hierarchy are those of ARPACK (a library routine independent of
+    # the oracle)
+    import scipy.sparse.linalg as spla
+    A = W.build_workload_matrix("termdoc_200k_dom10", 400).to_scipy()
+    wl = W.WORKLOADS["termdoc_200k_dom10"]
+    prm = dict(wl["params"], coarse_pinv=1, max_add=20)
+    s = O.Solver(A[np.diff(A.indptr) > 0], "svd", "dominant", 10, O.Params(**prm))
+    sig, _, _ = s.run()
+    lv1, lv2 = s.levels[1], s.levels[2]
+    assert lv1.A.shape[1] == lv2.A.shape[1] and lv1.sv.is_c.all()
+    Q = lv1.sv.P.toarray()
+    assert np.array_equal(Q, np.eye(Q.shape[0]))
+    assert abs(lv2.C - lv1.C).max() == 0.0
+    assert lv2.A.shape[0] < lv1.A.shape[0]
+    ref = spla.svds(A, k=12, tol=1e-13, return_singular_vectors=False)[::-1]
+    assert np.allclose(sig[:5], ref[:5], rtol=1e-10, atol=0)
+    # the side rule itself: identity only for a collapsing side next to a coarsening one
+    su = O.identity_side(5)
+    assert su.is_c.all() and list(su.cpts) == list(range(5)) and list(su.ptr) == list(range(6))
