@@ -43,11 +43,14 @@ static const uint64_t NORM_SEED_XOR = 0xA5A5A5A5A5A5A5A5ull;
 // ------------------------------------------------------------------------------------------------
 // Device memory arena (freed when the solve ends); enforces the context's HBM budget
 // ------------------------------------------------------------------------------------------------
+// Device memory of one solve.  Allocations are stream-ordered (hipMallocAsync / hipFreeAsync on the
+// solve's stream): a plain hipFree waits for the whole device, which would stall every other solve
+// running concurrently on other streams.
 class Arena {
  public:
-  explicit Arena(size_t budget) : budget_(budget) {}
+  Arena(size_t budget, hipStream_t s) : budget_(budget), st_(s) {}
   ~Arena() {
-    for (void* p : ptrs_) (void)hipFree(p);
+    for (void* p : ptrs_) (void)hipFreeAsync(p, st_);
   }
   template <class T>
   T* alloc(size_t n) {
@@ -56,9 +59,9 @@ class Arena {
     if (budget_ && used_ + bytes > budget_)
       throw SolverError{ST_E_BUDGET, "device footprint exceeds the HBM budget of the context"};
     void* p = nullptr;
-    if (hipMalloc(&p, bytes) != hipSuccess) {
+    if (hipMallocAsync(&p, bytes, st_) != hipSuccess) {
       (void)hipGetLastError();
-      throw SolverError{ST_E_OOM, "hipMalloc failed"};
+      throw SolverError{ST_E_OOM, "hipMallocAsync failed"};
     }
     ptrs_.push_back(p);
     used_ += bytes;
@@ -68,6 +71,7 @@ class Arena {
 
  private:
   size_t budget_, used_ = 0;
+  hipStream_t st_;
   std::vector<void*> ptrs_;
 };
 
@@ -166,7 +170,7 @@ template <> Aux<float>& aux<float>(Level& L) { return L.af; }
 class Solver {
  public:
   Solver(hipStream_t s, size_t budget, const Problem& pb, const slamg_params& p)
-      : st_(s), ar_(budget), p_(p), spd_(pb.kind == SLAMG_SPD_EIG), minimal_(pb.target == SLAMG_MINIMAL),
+      : st_(s), ar_(budget, s), p_(p), spd_(pb.kind == SLAMG_SPD_EIG), minimal_(pb.target == SLAMG_MINIMAL),
         nb_(pb.nb), nt_(p.n_t), mixed_(p.precision == SLAMG_MIXED_FP32), A0_(pb.A), pb_(pb) {}
   ~Solver() {
     if (igx_) (void)hipGraphExecDestroy(igx_);

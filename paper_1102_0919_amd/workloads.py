@@ -256,7 +256,7 @@ WORKLOADS = {
     "termdoc_200k_dom10": dict(desc="Zipf term-document matrix 200000x50000, 60 nnz/column, 10 dominant triplets",
                                kind="svd", target="dominant", n_b=10,
                                params=dict(strength_rule=2, top_s=4, df_filter=0.01, n_t=14, mu_t=1,
-                                           mu_b=4, n_mult=3)),
+                                           mu_b=4, n_mult=3, coarse_pinv=1)),
     "aniso3d_128_min8": dict(desc="3-D anisotropic 7-point Dirichlet 128^3 (n=2097152, eps=0.01), 8 minimal eigenpairs",
                              kind="spd", target="minimal", n_b=8,
                              params=dict(theta=0.06, n_t=8, mu_t=4, mu_b=4, n_mult=10, coarse_pinv=1)),
@@ -277,3 +277,45 @@ def build_workload_matrix(name: str, scale: int | None = None) -> CSR:
     if name.startswith("aniso3d_128"):
         return aniso3d(scale or 128, 0.01)
     raise KeyError(name)
+
+
+# --------------------------------------------------------------------------------------------
+# Serving stream: requests drawn from the three matrix families
+# --------------------------------------------------------------------------------------------
+FAMILY_PARAMS = {
+    ("laplace", "minimal"): WORKLOADS["laplace2d_32_min8"]["params"],
+    ("laplace", "dominant"): WORKLOADS["laplace2d_32_dom8"]["params"],
+    ("gradient", "minimal"): WORKLOADS["gradient2d_256_min8"]["params"],
+    ("gradient", "dominant"): WORKLOADS["gradient2d_256_dom8"]["params"],
+    ("termdoc", "minimal"): WORKLOADS["termdoc_200k_dom10"]["params"],
+    ("termdoc", "dominant"): WORKLOADS["termdoc_200k_dom10"]["params"],
+}
+
+
+def serving_requests(count: int, seed: int = 1102, n_lo: float = 1e3, n_hi: float = 2e5,
+                     rate: float = 1.0) -> list[dict]:
+    """A seeded request stream: family uniform over {2-D Laplacian with k = round(sqrt(n)), gradient
+    of a k x k grid with k = round(sqrt(n)), term-document with n documents, 4n terms and 60
+    nonzeros per document}; n log-uniform in [n_lo, n_hi]; n_b uniform in {1, 4, 8, 16}; dominant or
+    minimal with probability 1/2; Poisson arrivals at ``rate`` requests per second (arrival times
+    in seconds from the start).  Matrices are built on demand by ``serving_matrix``."""
+    rng = np.random.default_rng(seed)
+    reqs, t = [], 0.0
+    for i in range(count):
+        fam = ("laplace", "gradient", "termdoc")[int(rng.integers(3))]
+        n = float(np.exp(rng.uniform(math.log(n_lo), math.log(n_hi))))
+        nb = int((1, 4, 8, 16)[int(rng.integers(4))])
+        target = "dominant" if rng.random() < 0.5 else "minimal"
+        t += float(rng.exponential(1.0 / rate))
+        reqs.append(dict(id=i, family=fam, n=n, n_b=nb, target=target, arrival=t, seed=seed + 1 + i))
+    return reqs
+
+
+def serving_matrix(req: dict) -> tuple[CSR, str]:
+    """Matrix and kind ('spd' or 'svd') of a serving request."""
+    if req["family"] == "laplace":
+        return laplace2d(max(4, int(round(math.sqrt(req["n"]))))), "spd"
+    if req["family"] == "gradient":
+        return gradient2d(max(4, int(round(math.sqrt(req["n"]))))), "svd"
+    n = max(64, int(round(req["n"])))
+    return termdoc(4 * n, n, 60, seed=req["seed"]), "svd"
