@@ -105,7 +105,7 @@ __device__ static void wg_transpose(const double* A, int r, int c, int lda, doub
 // diagonal form in place; V accumulates the rotations (A_in = V diag V^t; with init_v false, V
 // holds an orthogonal start basis and receives V J_1 J_2 ...).  A pair is rotated
 // when |a_pq| > 1e-15 sqrt(|a_pp a_qq|) and |a_pq| > 2^-53 ||A||_F; the sweeps stop after one that
-// rotated nothing.  The absolute floor is the backward-stable accuracy of any symmetric eigensolver
+// rotated nothing or only by angles with |tan| <= 2^-26.  The absolute floor is the backward-stable accuracy of any symmetric eigensolver
 // in double precision: below it the off-diagonal entries are rounding noise of earlier rotations,
 // and an indefinite matrix would keep producing such noise under the relative test alone.
 // Inlined at each call so that the compiler sees where A and V live (LDS or global memory) and
@@ -115,7 +115,7 @@ __device__ static __forceinline__ void wg_jacobi(double* A, int n, int ld, doubl
   __shared__ int P[MAXPAIR], Q[MAXPAIR];
   __shared__ double Cs[MAXPAIR], Sn[MAXPAIR];
   __shared__ double red[DBLK];
-  __shared__ int rotated;
+  __shared__ int rotated, large;
   if (init_v) wg_for2(n, n, [&](int i, int j) { V[(long)i * ldv + j] = i == j ? 1.0 : 0.0; });
   const int N = n + (n & 1);
   const int npair = N / 2;
@@ -133,7 +133,7 @@ __device__ static __forceinline__ void wg_jacobi(double* A, int n, int ld, doubl
   }
   const double floor_abs = 0x1p-53 * sqrt(red[0]);
   for (int sweep = 0; sweep < maxsweep; ++sweep) {
-    if (threadIdx.x == 0) rotated = 0;
+    if (threadIdx.x == 0) { rotated = 0; large = 0; }
     wg_sync();
     for (int r = 0; r < N - 1; ++r) {
       for (int k = threadIdx.x; k < npair; k += DBLK) {
@@ -151,6 +151,7 @@ __device__ static __forceinline__ void wg_jacobi(double* A, int n, int ld, doubl
             c = 1.0 / sqrt(1.0 + tt * tt);
             s = tt * c;
             rotated = 1;
+            if (fabs(tt) > 0x1p-26) large = 1;
           }
         }
         // the pair with the padding index n (odd n) becomes (p, p) with the identity rotation, so the
@@ -185,9 +186,12 @@ __device__ static __forceinline__ void wg_jacobi(double* A, int n, int ld, doubl
       });
       wg_sync();
     }
-    const int any = rotated;
+    const int any = rotated, big = large;
     wg_sync();
-    if (!any) break;
+    // done after a sweep that rotated nothing, or whose rotations all had |tan| <= 2^-26: the
+    // entries such a sweep leaves off the diagonal are second order in those angles, below the
+    // 2^-53 ||A||_F floor, so a further sweep would rotate nothing
+    if (!any || !big) break;
   }
   wg_sync();
 }
