@@ -203,7 +203,8 @@ class Solver {
   void inject(int l, int cycle);
   void coarsest_mult();
   void mult_cycle(int c);
-  template <class T> void boot_relax(int l, const T* kap, const T* tau, const double* sig, int nsweeps = 1);
+  template <class T> void boot_relax(int l, const T* kap, const T* tau, const double* sig, int nsweeps = 1,
+                                      bool zero_start = false);
   template <class T> void additive_vcycle(const double* sig, T* rhsU, T* rhsV);
   void additive_iteration();
   void ritz();
@@ -1001,8 +1002,10 @@ void Solver::relax_tests(int l) {
 }
 
 // One boot relaxation (no sigma update) on level l with right-hand sides kap, tau (null: zero).
+// zero_start: the iterate is zero on entry (a coarse correction of the additive cycle), so the
+// first Jacobi-type sweep skips the products with it and need not read it.
 template <class T>
-void Solver::boot_relax(int l, const T* kap, const T* tau, const double* sig, int nsweeps) {
+void Solver::boot_relax(int l, const T* kap, const T* tau, const double* sig, int nsweeps, bool zero_start) {
   Level& L = *lv_[l];
   Blocks<T>& b = blocks<T>(L);
   Aux<T>& x = aux<T>(L);
@@ -1036,7 +1039,7 @@ void Solver::boot_relax(int l, const T* kap, const T* tau, const double* sig, in
     return;
   }
   if (nsweeps > 1) {
-    for (int it = 0; it < nsweeps; ++it) boot_relax<T>(l, kap, tau, sig, 1);
+    for (int it = 0; it < nsweeps; ++it) boot_relax<T>(l, kap, tau, sig, 1, zero_start && it == 0);
     return;
   }
   if (!minimal_) {
@@ -1048,6 +1051,7 @@ void Solver::boot_relax(int l, const T* kap, const T* tau, const double* sig, in
       a.mmode = L.finest ? M_IDENT : M_SHARED; a.Mv = vals<T>(L.B); a.y = b.Ub;
       a.x = b.Ub; a.D = x.dinvB; a.kap = kap; a.sig = sig; a.cmode = C_JAC_BOOT; a.omega = p_.omega_J;
       a.out = b.Ua;
+      if (zero_start) { a.Kv = nullptr; a.mmode = M_NONE; a.x = nullptr; }
       rowop(l, a, &L.A);
       std::swap(b.Ub, b.Ua);
     } else {
@@ -1058,6 +1062,7 @@ void Solver::boot_relax(int l, const T* kap, const T* tau, const double* sig, in
       a.mmode = L.finest ? M_IDENT : M_CSR; a.Mrp = L.B.rp; a.avgM = avg_row(L.B); a.Mci = L.B.ci; a.Mv = vals<T>(L.B); a.y = b.Ub;
       a.x = b.Ub; a.D = x.dinvB; a.kap = kap; a.sig = sig; a.cmode = C_JAC_BOOT; a.omega = p_.omega_J;
       a.out = b.Ua;
+      if (zero_start) { a.Kv = nullptr; a.mmode = M_NONE; a.x = nullptr; }
       rowop(l, a, &L.A);
       RowOpArgs<T> c;
       c.nrows = mv; c.w = nb_;
@@ -1065,6 +1070,7 @@ void Solver::boot_relax(int l, const T* kap, const T* tau, const double* sig, in
       c.mmode = L.finest ? M_IDENT : M_CSR; c.Mrp = L.C.rp; c.avgM = avg_row(L.C); c.Mci = L.C.ci; c.Mv = vals<T>(L.C); c.y = b.Vb;
       c.x = b.Vb; c.D = x.dinvC; c.kap = tau; c.sig = sig; c.cmode = C_JAC_BOOT; c.omega = p_.omega_J;
       c.out = b.Va;
+      if (zero_start) { c.mmode = M_NONE; c.x = nullptr; }
       rowop(l, c, &L.At);
       std::swap(b.Ub, b.Ua);
       std::swap(b.Vb, b.Va);
@@ -1325,6 +1331,7 @@ void Solver::mult_cycle(int c) {
 template <class T>
 void Solver::additive_vcycle(const double* sig, T* rhsU, T* rhsV) {
   const int nl = (int)lv_.size();
+  const bool zero_start_ok = !minimal_ && p_.mu_b > 0;
   for (int l = 0; l + 1 < nl; ++l) {
     Level& L = *lv_[l];
     Level& C = *lv_[l + 1];
@@ -1332,7 +1339,7 @@ void Solver::additive_vcycle(const double* sig, T* rhsU, T* rhsV) {
     Blocks<T>& cb = blocks<T>(C);
     const T* kap = l == 0 ? rhsU : b.kap;
     const T* tau = l == 0 ? rhsV : b.tau;
-    boot_relax<T>(l, kap, tau, sig, p_.mu_b);
+    boot_relax<T>(l, kap, tau, sig, p_.mu_b, l > 0 && zero_start_ok);
     // residuals r = kappa - (A v - sigma B u), s = tau - (A^t u - sigma C v), then restriction
     const int mu = rows_u(L), mv = rows_v(L);
     RowOpArgs<T> a;
@@ -1351,10 +1358,14 @@ void Solver::additive_vcycle(const double* sig, T* rhsU, T* rhsV) {
       rowop(l, s, &L.At, 7);
       spmm<T>(l, L.sv.Pt, vals<T>(L.sv.Pt), nb_, b.tV, cb.tau, 0.0);
     }
-    if constexpr (std::is_same<T, double>::value) {
-      launch_fill(cb.Ub, (size_t)(rows_u(C) + (spd_ ? 0 : rows_v(C))) * nb_, 0.0, st_);
-    } else {
-      launch_fillf(cb.Ub, (size_t)(rows_u(C) + (spd_ ? 0 : rows_v(C))) * nb_, 0.0f, st_);
+    // zero initial coarse correction: written explicitly for Kaczmarz (it updates in place); the
+    // Jacobi-type relaxation starts from zero without reading it, and the coarsest solve writes it
+    if (!zero_start_ok) {
+      if constexpr (std::is_same<T, double>::value) {
+        launch_fill(cb.Ub, (size_t)(rows_u(C) + (spd_ ? 0 : rows_v(C))) * nb_, 0.0, st_);
+      } else {
+        launch_fillf(cb.Ub, (size_t)(rows_u(C) + (spd_ ? 0 : rows_v(C))) * nb_, 0.0f, st_);
+      }
     }
   }
   // coarsest: [u; v] = pinv(X - sigma_j Y) [kappa; tau] (FP64)
