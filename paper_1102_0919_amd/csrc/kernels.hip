@@ -78,6 +78,50 @@ __device__ __forceinline__ void strow(T* __restrict__ p, int c0, int w, const T 
     if (c0 + c < w) p[c0 + c] = v[c];
 }
 
+// One lane's walk over the nonzeros k, k + SPLIT, k + 2 SPLIT, ... < ke of a CSR row, summing
+// a_k z(j_k) (and b_k z(j_k) when TWO).  Each step takes four nonzeros (two when TWO, to bound the
+// registers): their index and value loads are issued together, then their row gathers, so a lane
+// with at most four nonzeros waits for one index -> row chain.  Slots past the row's end load
+// nothing and add zero, which leaves the sums bitwise equal to the one-by-one walk.
+template <typename T, int CPL, int SPLIT, bool TWO>
+__device__ __forceinline__ void walk_row(int k, int ke, const int* __restrict__ ci, const T* __restrict__ av,
+                                         const T* __restrict__ bv, const T* __restrict__ z, int w, int c0,
+                                         T (&s1)[CPL], T (&s2)[CPL]) {
+  constexpr int U = TWO ? 2 : 4;
+  for (; k < ke; k += U * SPLIT) {
+    int j[U];
+    T a[U], b[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int kk = k + u * SPLIT;
+      j[u] = -1;
+      a[u] = T(0);
+      b[u] = T(0);
+      if (kk < ke) {
+        j[u] = ci[kk];
+        a[u] = av[kk];
+        if constexpr (TWO) b[u] = bv[kk];
+      }
+    }
+    T zr[U][CPL];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (j[u] >= 0) ldrow<T, CPL>(z + (long)j[u] * w, c0, w, zr[u]);
+      else {
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) zr[u][c] = T(0);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        s1[c] += a[u] * zr[u][c];
+        if constexpr (TWO) s2[c] += b[u] * zr[u][c];
+      }
+  }
+}
+
 // ------------------------------------------------------------------------------------------------
 // Block SpMM  y = A x (+ beta y)
 // ------------------------------------------------------------------------------------------------
@@ -93,33 +137,17 @@ __global__ __launch_bounds__(BLK) void k_spmm(int m, int w, int lshift, const in
   const int sidx = lane >> lshift;
   int c0 = (lane & ((1 << lshift) - 1)) * CPL;
   if (row >= m || c0 >= w) return;
-  T acc[CPL];
+  T* yr = y + (long)row * w;
+  T old[CPL];
+  if (beta != T(0) && sidx == 0) ldrow<T, CPL>(yr, c0, w, old);
+  T acc[CPL], unused[CPL];
 #pragma unroll
   for (int c = 0; c < CPL; ++c) acc[c] = T(0);
-  int k = rp[row] + sidx, ke = rp[row + 1];
-  for (; k + SPLIT < ke; k += 2 * SPLIT) {
-    int j0 = ci[k], j1 = ci[k + SPLIT];
-    T a0 = v[k], a1 = v[k + SPLIT];
-    T x0[CPL], x1[CPL];
-    ldrow<T, CPL>(x + (long)j0 * w, c0, w, x0);
-    ldrow<T, CPL>(x + (long)j1 * w, c0, w, x1);
-#pragma unroll
-    for (int c = 0; c < CPL; ++c) acc[c] += a0 * x0[c] + a1 * x1[c];
-  }
-  if (k < ke) {
-    T xv[CPL];
-    ldrow<T, CPL>(x + (long)ci[k] * w, c0, w, xv);
-    T a = v[k];
-#pragma unroll
-    for (int c = 0; c < CPL; ++c) acc[c] += a * xv[c];
-  }
+  walk_row<T, CPL, SPLIT, false>(rp[row] + sidx, rp[row + 1], ci, v, nullptr, x, w, c0, acc, unused);
 #pragma unroll
   for (int c = 0; c < CPL; ++c) acc[c] = split_sum<SPLIT>(acc[c], 1 << lshift);
   if (sidx != 0) return;
-  T* yr = y + (long)row * w;
   if (beta != T(0)) {
-    T old[CPL];
-    ldrow<T, CPL>(yr, c0, w, old);
 #pragma unroll
     for (int c = 0; c < CPL; ++c) acc[c] += beta * old[c];
   }
@@ -184,40 +212,31 @@ __global__ __launch_bounds__(BLK) void k_rowop(RowOpPOD<T> a, int lshift) {
   int c0 = (lane & ((1 << lshift) - 1)) * CPL;
   const int w = a.w;
   if (row >= a.nrows || c0 >= w) return;
-  T ca[CPL], cb[CPL], ce[CPL];
+  // the row's own operands first: their loads overlap the walks.  With M = I the row of y goes
+  // into the M-sum of the first lane group (the other groups add zeros to it, exactly).
+  double sg[CPL];
+  T kp[CPL], xv[CPL], kz[CPL], my[CPL];
 #pragma unroll
   for (int c = 0; c < CPL; ++c) {
-    double s = (a.sig && c0 + c < w) ? a.sig[c0 + c] : 1.0;
-    coefs<T>(a.cmode, a.omega, s, ca[c], cb[c], ce[c]);
+    sg[c] = (a.sig && c0 + c < w) ? a.sig[c0 + c] : 1.0;
+    kp[c] = T(0); xv[c] = T(0); kz[c] = T(0); my[c] = T(0);
   }
-  T kz[CPL], my[CPL];
-#pragma unroll
-  for (int c = 0; c < CPL; ++c) { kz[c] = T(0); my[c] = T(0); }
+  T d = T(1);
+  if (sidx == 0) {
+    if (a.kap) ldrow<T, CPL>(a.kap + (long)row * w, c0, w, kp);
+    if (a.x) ldrow<T, CPL>(a.x + (long)row * w, c0, w, xv);
+    if (a.mmode == M_IDENT) ldrow<T, CPL>(a.y + (long)row * w, c0, w, my);
+    if (a.D) d = a.D[row];
+  }
   if (a.Kv) {
-    #pragma unroll 4
-    for (int k = a.Krp[row] + sidx, ke = a.Krp[row + 1]; k < ke; k += SPLIT) {
-      T zv[CPL];
-      ldrow<T, CPL>(a.z + (long)a.Kci[k] * w, c0, w, zv);
-      T av = a.Kv[k];
-      if (a.mmode == M_SHARED) {
-        T bv = a.Mv[k];
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) { kz[c] += av * zv[c]; my[c] += bv * zv[c]; }
-      } else {
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) kz[c] += av * zv[c];
-      }
-    }
+    if (a.mmode == M_SHARED)
+      walk_row<T, CPL, SPLIT, true>(a.Krp[row] + sidx, a.Krp[row + 1], a.Kci, a.Kv, a.Mv, a.z, w, c0, kz, my);
+    else
+      walk_row<T, CPL, SPLIT, false>(a.Krp[row] + sidx, a.Krp[row + 1], a.Kci, a.Kv, nullptr, a.z, w, c0, kz, my);
   }
   if (a.mmode == M_CSR) {
-    #pragma unroll 4
-    for (int k = a.Mrp[row] + sidx, ke = a.Mrp[row + 1]; k < ke; k += SPLIT) {
-      T yv[CPL];
-      ldrow<T, CPL>(a.y + (long)a.Mci[k] * w, c0, w, yv);
-      T mv = a.Mv[k];
-#pragma unroll
-      for (int c = 0; c < CPL; ++c) my[c] += mv * yv[c];
-    }
+    T unused[CPL];
+    walk_row<T, CPL, SPLIT, false>(a.Mrp[row] + sidx, a.Mrp[row + 1], a.Mci, a.Mv, nullptr, a.y, w, c0, my, unused);
   }
 #pragma unroll
   for (int c = 0; c < CPL; ++c) {
@@ -225,20 +244,14 @@ __global__ __launch_bounds__(BLK) void k_rowop(RowOpPOD<T> a, int lshift) {
     my[c] = split_sum<SPLIT>(my[c], 1 << lshift);
   }
   if (sidx != 0) return;
-  if (a.mmode == M_IDENT) ldrow<T, CPL>(a.y + (long)row * w, c0, w, my);
-  T kp[CPL];
-  if (a.kap) ldrow<T, CPL>(a.kap + (long)row * w, c0, w, kp);
-  else {
-#pragma unroll
-    for (int c = 0; c < CPL; ++c) kp[c] = T(0);
-  }
-  T d = a.D ? a.D[row] : T(1);
   T r[CPL];
 #pragma unroll
-  for (int c = 0; c < CPL; ++c) r[c] = d * (ca[c] * kz[c] + cb[c] * my[c] + ce[c] * kp[c]);
+  for (int c = 0; c < CPL; ++c) {
+    T ca, cb, ce;
+    coefs<T>(a.cmode, a.omega, sg[c], ca, cb, ce);
+    r[c] = d * (ca * kz[c] + cb * my[c] + ce * kp[c]);
+  }
   if (a.x) {
-    T xv[CPL];
-    ldrow<T, CPL>(a.x + (long)row * w, c0, w, xv);
 #pragma unroll
     for (int c = 0; c < CPL; ++c) r[c] += xv[c];
   }
@@ -279,79 +292,103 @@ __device__ __forceinline__ void kacz_row(const KaczPOD<T>& a, int r, int c0, int
 #pragma unroll
   for (int c = 0; c < CPL; ++c) lam[c] = (a.lam && c0 + c < w) ? (T)a.lam[c0 + c] : T(0);
   const bool shifted = a.lam != nullptr;
+  // operands that do not depend on the walks, loaded first so that their latency overlaps them
+  T yid[CPL], kp[CPL], rs[CPL];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) {
+    yid[c] = T(0);
+    kp[c] = T(0);
+    rs[c] = (a.rmode != M_NONE && c0 + c < w) ? (T)a.rsig[c0 + c] : T(0);
+  }
+  if (a.rmode == M_IDENT) ldrow<T, CPL>(a.y + (long)r * w, c0, w, yid);
+  if (a.kap) ldrow<T, CPL>(a.kap + (long)r * w, c0, w, kp);
+  const T aa = a.rn_aa[r];
+  const T ab = shifted ? a.rn_ab[r] : T(0), bb = shifted ? a.rn_bb[r] : T(0);
+  const int kb = a.rp[r], ke = a.rp[r + 1];
   // right-hand side
   T rhs[CPL];
+  if (a.rmode == M_CSR) {
+    T my[CPL], unused[CPL];
 #pragma unroll
-  for (int c = 0; c < CPL; ++c) rhs[c] = T(0);
-  if (a.rmode == M_IDENT || a.rmode == M_CSR) {
-    T my[CPL];
-    if (a.rmode == M_IDENT) {
-      ldrow<T, CPL>(a.y + (long)r * w, c0, w, my);
-    } else {
+    for (int c = 0; c < CPL; ++c) my[c] = T(0);
+    walk_row<T, CPL, SPLIT, false>(a.Mrp[r] + sidx, a.Mrp[r + 1], a.Mci, a.Mv, nullptr, a.y, w, c0, my, unused);
 #pragma unroll
-      for (int c = 0; c < CPL; ++c) my[c] = T(0);
-      #pragma unroll 4
-      for (int k = a.Mrp[r] + sidx, ke = a.Mrp[r + 1]; k < ke; k += SPLIT) {
-        T yv[CPL];
-        ldrow<T, CPL>(a.y + (long)a.Mci[k] * w, c0, w, yv);
-        T mv = a.Mv[k];
+    for (int c = 0; c < CPL; ++c) rhs[c] = rs[c] * split_sum<SPLIT>(my[c], lprc) + kp[c];
+  } else {
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) my[c] += mv * yv[c];
-      }
-#pragma unroll
-      for (int c = 0; c < CPL; ++c) my[c] = split_sum<SPLIT>(my[c], lprc);
-    }
-#pragma unroll
-    for (int c = 0; c < CPL; ++c) rhs[c] = (c0 + c < w ? (T)a.rsig[c0 + c] : T(0)) * my[c];
+    for (int c = 0; c < CPL; ++c) rhs[c] = rs[c] * yid[c] + kp[c];
   }
-  if (a.kap) {
-    T kp[CPL];
-    ldrow<T, CPL>(a.kap + (long)r * w, c0, w, kp);
-#pragma unroll
-    for (int c = 0; c < CPL; ++c) rhs[c] += kp[c];
-  }
-  const int kb = a.rp[r], ke = a.rp[r + 1];
+  // residual of the row: four nonzeros per step (see walk_row); a lane whose nonzeros fit one step
+  // keeps their rows in registers for the update
+  constexpr int U = 4;
+  int j[U];
+  T av[U], bv[U], xr[U][CPL];
   T dot[CPL];
 #pragma unroll
   for (int c = 0; c < CPL; ++c) dot[c] = T(0);
-  #pragma unroll 4
-  for (int k = kb + sidx; k < ke; k += SPLIT) {
-    int j = a.ci[k];
-    T xv[CPL];
-    ldrow<T, CPL>(a.x + (long)j * w, c0, w, xv);
-    T av = a.av[k];
-    if (shifted) {
-      T bv = a.bv ? a.bv[k] : (j == r ? T(1) : T(0));
 #pragma unroll
-      for (int c = 0; c < CPL; ++c) dot[c] += (av - lam[c] * bv) * xv[c];
-    } else {
+  for (int u = 0; u < U; ++u) j[u] = -1;
+  const bool one = kb + sidx + U * SPLIT >= ke;
+  for (int k = kb + sidx; k < ke; k += U * SPLIT) {
 #pragma unroll
-      for (int c = 0; c < CPL; ++c) dot[c] += av * xv[c];
+    for (int u = 0; u < U; ++u) {
+      const int kk = k + u * SPLIT;
+      j[u] = -1;
+      av[u] = T(0);
+      bv[u] = T(0);
+      if (kk < ke) {
+        j[u] = a.ci[kk];
+        av[u] = a.av[kk];
+        if (shifted) bv[u] = a.bv ? a.bv[kk] : T(0);
+      }
     }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (shifted && !a.bv && j[u] == r) bv[u] = T(1);
+      if (j[u] >= 0) ldrow<T, CPL>(a.x + (long)j[u] * w, c0, w, xr[u]);
+      else {
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) xr[u][c] = T(0);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) dot[c] += (shifted ? av[u] - lam[c] * bv[u] : av[u]) * xr[u][c];
   }
   T coef[CPL];
-  T aa = a.rn_aa[r];
-  T ab = shifted ? a.rn_ab[r] : T(0), bb = shifted ? a.rn_bb[r] : T(0);
 #pragma unroll
   for (int c = 0; c < CPL; ++c) {
     T res = rhs[c] - split_sum<SPLIT>(dot[c], lprc);
     T nr = shifted ? aa - T(2) * lam[c] * ab + lam[c] * lam[c] * bb : aa;
     coef[c] = nr > T(0) ? res / nr : T(0);
   }
+  // update x on the row's pattern (the colour's rows share no column, so the rows held in
+  // registers are still current)
+  if (one) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (j[u] < 0) continue;
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) xr[u][c] += coef[c] * (shifted ? av[u] - lam[c] * bv[u] : av[u]);
+      strow<T, CPL>(a.x + (long)j[u] * w, c0, w, xr[u]);
+    }
+    return;
+  }
   #pragma unroll 4
   for (int k = kb + sidx; k < ke; k += SPLIT) {
-    int j = a.ci[k];
-    T* xp = a.x + (long)j * w;
+    int jj = a.ci[k];
+    T* xp = a.x + (long)jj * w;
     T xv[CPL];
     ldrow<T, CPL>(xp, c0, w, xv);
-    T av = a.av[k];
+    T avk = a.av[k];
     if (shifted) {
-      T bv = a.bv ? a.bv[k] : (j == r ? T(1) : T(0));
+      T bvk = a.bv ? a.bv[k] : (jj == r ? T(1) : T(0));
 #pragma unroll
-      for (int c = 0; c < CPL; ++c) xv[c] += coef[c] * (av - lam[c] * bv);
+      for (int c = 0; c < CPL; ++c) xv[c] += coef[c] * (avk - lam[c] * bvk);
     } else {
 #pragma unroll
-      for (int c = 0; c < CPL; ++c) xv[c] += coef[c] * av;
+      for (int c = 0; c < CPL; ++c) xv[c] += coef[c] * avk;
     }
     strow<T, CPL>(xp, c0, w, xv);
   }
@@ -487,18 +524,18 @@ __global__ __launch_bounds__(BLK) void k_dots(DotPOD<T> a, int lshift, double* p
 #pragma unroll
     for (int c = 0; c < CPL; ++c) sc[c] = (a.sig && c0 + c < w) ? a.sig[c0 + c] : 0.0;
     for (int row = (int)(((long)blockIdx.x * BLK + threadIdx.x) >> gl); row < a.nrows; row += stride) {
+      T yv[CPL], av[CPL];
+      if (sidx == 0) {
+        if (a.y) ldrow<T, CPL>(a.y + (long)row * w, c0, w, yv);
+        if (a.a) ldrow<T, CPL>(a.a + (long)row * w, c0, w, av);
+      }
       T val[CPL];
       if (a.Kv) {
+        T unused[CPL];
 #pragma unroll
         for (int c = 0; c < CPL; ++c) val[c] = T(0);
-        #pragma unroll 4
-    for (int k = a.Krp[row] + sidx, ke = a.Krp[row + 1]; k < ke; k += SPLIT) {
-          T zv[CPL];
-          ldrow<T, CPL>(a.z + (long)a.Kci[k] * w, c0, w, zv);
-          T av = a.Kv[k];
-#pragma unroll
-          for (int c = 0; c < CPL; ++c) val[c] += av * zv[c];
-        }
+        walk_row<T, CPL, SPLIT, false>(a.Krp[row] + sidx, a.Krp[row + 1], a.Kci, a.Kv, nullptr, a.z, w, c0, val,
+                                       unused);
 #pragma unroll
         for (int c = 0; c < CPL; ++c) val[c] = split_sum<SPLIT>(val[c], 1 << lshift);
       } else {
@@ -506,14 +543,10 @@ __global__ __launch_bounds__(BLK) void k_dots(DotPOD<T> a, int lshift, double* p
       }
       if (sidx != 0) continue;
       if (a.y) {
-        T yv[CPL];
-        ldrow<T, CPL>(a.y + (long)row * w, c0, w, yv);
 #pragma unroll
         for (int c = 0; c < CPL; ++c) val[c] -= (T)sc[c] * yv[c];
       }
       if (a.a) {
-        T av[CPL];
-        ldrow<T, CPL>(a.a + (long)row * w, c0, w, av);
 #pragma unroll
         for (int c = 0; c < CPL; ++c) acc[c] += (double)av[c] * (double)val[c];
       } else {
