@@ -79,10 +79,22 @@ struct RowOpArgs {
 };
 
 template <typename T> void launch_rowop(const RowOpArgs<T>& a, hipStream_t s);
+// two independent row operations (same w) in one launch
+template <typename T> void launch_rowop2(const RowOpArgs<T>& a, const RowOpArgs<T>& b, hipStream_t s);
 
 template <typename T>
 void launch_spmm(int m, int w, const int* rp, const int* ci, const T* v, const T* x, T* y,
                  double beta, hipStream_t s, int nnz = -1);
+
+// y = K x (+ beta y) for one operand set of a paired SpMM
+template <typename T>
+struct SpmmArgs {
+  int m = 0, nnz = -1;
+  const int* rp = nullptr; const int* ci = nullptr; const T* v = nullptr;
+  const T* x = nullptr; T* y = nullptr; double beta = 0.0;
+};
+// two independent products with w columns in one launch
+template <typename T> void launch_spmm2(const SpmmArgs<T>& a, const SpmmArgs<T>& b, int w, hipStream_t s);
 
 template <typename T>
 struct KaczArgs {
@@ -119,15 +131,26 @@ struct DotArgs {
   const T* y = nullptr; const double* sig = nullptr;
   int nnzK = -1;
 };
+// Column reductions and the Gram product: partials per workgroup, then a fixed-order finalisation
+// launch (bitwise reproducible).
 template <typename T> void launch_dots(const DotArgs<T>& a, double* partial, double* out, hipStream_t s);
 int dots_grid(int nrows, int w);
 
-void launch_gram(int rows, int w, const double* X, const double* Y, double* partial, double* G,
-                 hipStream_t s);
+void launch_gram(int rows, int w, const double* X, const double* Y, double* partial, double* G, hipStream_t s);
+// two independent reductions / Gram products in one launch (each with its own partials and output)
+template <typename T>
+void launch_dots2(const DotArgs<T>& a, double* pa, double* oa, const DotArgs<T>& b, double* pb, double* ob,
+                  hipStream_t s);
+void launch_gram2(int w, int rows_a, const double* Xa, const double* Ya, double* pa, double* Ga, int rows_b,
+                  const double* Xb, const double* Yb, double* pb, double* Gb, hipStream_t s);
 int gram_grid(int rows);
 
 template <typename T>
 void launch_rotate(int rows, int win, int wout, const T* X, const double* S, T* out, hipStream_t s);
+// out_a = X_a S_a and out_b = X_b S_b (w x w) in one launch
+template <typename T>
+void launch_rotate2(int w, int rows_a, const T* Xa, const double* Sa, T* outa, int rows_b, const T* Xb,
+                    const double* Sb, T* outb, hipStream_t s);
 template <typename T>
 void launch_gather_rows(int nout, int w, const int* idx, const T* X, T* out, hipStream_t s);
 template <typename T>
@@ -161,6 +184,9 @@ void launch_rq_weights(int nf, const double* num, const double* nu, const double
 
 // dense.hip (single-workgroup dense FP64 procedures)
 void launch_chol_inv_upper(int w, const double* G, double* T, int* status, hipStream_t s);
+// two factorisations (G0 -> T0, G1 -> T1) in one launch
+void launch_chol_inv_upper2(int w, const double* G0, double* T0, const double* G1, double* T1, int* status,
+                            hipStream_t s);
 void launch_small_ritz(int w, int spd, int minimal, const double* M, double* Y, double* Z, double* sig,
                        double* work, int* status, hipStream_t s);
 void launch_coarse_gsvd(int spd, int minimal, int mL, int nL, int nb, double* A, double* B, double* C,

@@ -6,6 +6,8 @@
 // (they are small and stay in L2); rotation parameters live in LDS.
 #include "common.h"
 
+#include <algorithm>
+
 namespace slamg {
 
 static constexpr int DBLK = 256;
@@ -15,17 +17,17 @@ __device__ static void wg_sync() { __syncthreads(); }
 
 // Visits every (i, j), 0 <= i < R, 0 <= j < n, with the workgroup's threads: consecutive threads take
 // consecutive j (coalesced rows), and the loop carries no integer division.
-template <class F>
+template <int BS = DBLK, class F>
 __device__ __forceinline__ void wg_for2(int R, int n, F&& f) {
   if (n <= 0 || R <= 0) return;
-  if (n <= DBLK) {
-    const int G = DBLK / n, j = (int)threadIdx.x % n, g = (int)threadIdx.x / n;
+  if (n <= BS) {
+    const int G = BS / n, j = (int)threadIdx.x % n, g = (int)threadIdx.x / n;
     if (g < G) {
 #pragma unroll 4
       for (int i = g; i < R; i += G) f(i, j);
     }
   } else {
-    for (int j = threadIdx.x; j < n; j += DBLK) {
+    for (int j = threadIdx.x; j < n; j += BS) {
 #pragma unroll 4
       for (int i = 0; i < R; ++i) f(i, j);
     }
@@ -34,6 +36,7 @@ __device__ __forceinline__ void wg_for2(int R, int n, F&& f) {
 
 // A (n x n, ld) <- L (lower), A = L L^t.  Returns (in *info) 0 or the first failing pivot + 1;
 // a failing pivot is replaced by a tiny positive value so the factor stays finite.
+template <int BS = DBLK>
 __device__ static void wg_chol(double* A, int n, int ld, int* info) {
   __shared__ double dk_s;
   for (int k = 0; k < n; ++k) {
@@ -50,16 +53,16 @@ __device__ static void wg_chol(double* A, int n, int ld, int* info) {
     }
     wg_sync();
     const double dk = dk_s;
-    for (int i = k + 1 + threadIdx.x; i < n; i += DBLK) A[(long)i * ld + k] /= dk;
+    for (int i = k + 1 + threadIdx.x; i < n; i += BS) A[(long)i * ld + k] /= dk;
     wg_sync();
     const int nt = n - k - 1;
-    for (long t = threadIdx.x; t < (long)nt * nt; t += DBLK) {
+    for (long t = threadIdx.x; t < (long)nt * nt; t += BS) {
       int i = k + 1 + (int)(t / nt), j = k + 1 + (int)(t % nt);
       if (j <= i) A[(long)i * ld + j] -= A[(long)i * ld + k] * A[(long)j * ld + k];
     }
   }
   wg_sync();
-  for (long t = threadIdx.x; t < (long)n * n; t += DBLK) {
+  for (long t = threadIdx.x; t < (long)n * n; t += BS) {
     int i = (int)(t / n), j = (int)(t % n);
     if (j > i) A[(long)i * ld + j] = 0.0;
   }
@@ -67,9 +70,10 @@ __device__ static void wg_chol(double* A, int n, int ld, int* info) {
 }
 
 // Solve L X = B in place (B: n x nc, ldb), L lower; one thread per right-hand side column.
+template <int BS = DBLK>
 __device__ static void wg_trsm_lower(const double* L, int n, int ld, double* B, int nc, int ldb) {
   wg_sync();
-  for (int c = threadIdx.x; c < nc; c += DBLK) {
+  for (int c = threadIdx.x; c < nc; c += BS) {
     for (int i = 0; i < n; ++i) {
       double s = B[(long)i * ldb + c];
       for (int k = 0; k < i; ++k) s -= L[(long)i * ld + k] * B[(long)k * ldb + c];
@@ -80,9 +84,10 @@ __device__ static void wg_trsm_lower(const double* L, int n, int ld, double* B, 
 }
 
 // Solve L^t X = B in place (B: n x nc), L lower.
+template <int BS = DBLK>
 __device__ static void wg_trsm_lower_t(const double* L, int n, int ld, double* B, int nc, int ldb) {
   wg_sync();
-  for (int c = threadIdx.x; c < nc; c += DBLK) {
+  for (int c = threadIdx.x; c < nc; c += BS) {
     for (int i = n - 1; i >= 0; --i) {
       double s = B[(long)i * ldb + c];
       for (int k = i + 1; k < n; ++k) s -= L[(long)k * ld + i] * B[(long)k * ldb + c];
@@ -92,9 +97,10 @@ __device__ static void wg_trsm_lower_t(const double* L, int n, int ld, double* B
   wg_sync();
 }
 
+template <int BS = DBLK>
 __device__ static void wg_transpose(const double* A, int r, int c, int lda, double* B, int ldb) {
   wg_sync();
-  for (long t = threadIdx.x; t < (long)r * c; t += DBLK) {
+  for (long t = threadIdx.x; t < (long)r * c; t += BS) {
     int i = (int)(t / c), j = (int)(t % c);
     B[(long)j * ldb + i] = A[(long)i * lda + j];
   }
@@ -110,24 +116,25 @@ __device__ static void wg_transpose(const double* A, int r, int c, int lda, doub
 // and an indefinite matrix would keep producing such noise under the relative test alone.
 // Inlined at each call so that the compiler sees where A and V live (LDS or global memory) and
 // emits LDS instructions for LDS-resident matrices; the procedure is latency-bound.
+template <int BS = DBLK>
 __device__ static __forceinline__ void wg_jacobi(double* A, int n, int ld, double* V, int ldv, int maxsweep,
                                                  bool init_v = true) {
   __shared__ int P[MAXPAIR], Q[MAXPAIR];
   __shared__ double Cs[MAXPAIR], Sn[MAXPAIR];
-  __shared__ double red[DBLK];
+  __shared__ double red[BS];
   __shared__ int rotated, large;
-  if (init_v) wg_for2(n, n, [&](int i, int j) { V[(long)i * ldv + j] = i == j ? 1.0 : 0.0; });
+  if (init_v) wg_for2<BS>(n, n, [&](int i, int j) { V[(long)i * ldv + j] = i == j ? 1.0 : 0.0; });
   const int N = n + (n & 1);
   const int npair = N / 2;
   if (n <= 1) { wg_sync(); return; }
   double tot = 0.0;
-  wg_for2(n, n, [&](int i, int j) {
+  wg_for2<BS>(n, n, [&](int i, int j) {
     const double a = A[(long)i * ld + j];
     tot += a * a;
   });
   red[threadIdx.x] = tot;
   wg_sync();
-  for (int s = DBLK / 2; s > 0; s >>= 1) {
+  for (int s = BS / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     wg_sync();
   }
@@ -136,16 +143,19 @@ __device__ static __forceinline__ void wg_jacobi(double* A, int n, int ld, doubl
     if (threadIdx.x == 0) { rotated = 0; large = 0; }
     wg_sync();
     for (int r = 0; r < N - 1; ++r) {
-      for (int k = threadIdx.x; k < npair; k += DBLK) {
-        int a = k, b = N - 1 - k;
-        int p = a == 0 ? 0 : ((a - 1 + r) % (N - 1)) + 1;
-        int q = b == 0 ? 0 : ((b - 1 + r) % (N - 1)) + 1;
+      for (int k = threadIdx.x; k < npair; k += BS) {
+        // round-robin schedule: index 0 stays, the others rotate by r (a - 1 + r < 2 (N - 1))
+        const int a = k, b = N - 1 - k;
+        int p = a - 1 + r, q = b - 1 + r;
+        p = a == 0 ? 0 : (p >= N - 1 ? p - (N - 1) : p) + 1;
+        q = b == 0 ? 0 : (q >= N - 1 ? q - (N - 1) : q) + 1;
         if (p > q) { int tmp = p; p = q; q = tmp; }
         double c = 1.0, s = 0.0;
         if (q < n) {
           const double apq = A[(long)p * ld + q];
           const double app = A[(long)p * ld + p], aqq = A[(long)q * ld + q];
-          if (fabs(apq) > fmax(1e-15 * sqrt(fabs(app * aqq)), floor_abs) && fabs(apq) > 1e-300) {
+          // |a_pq| > 1e-15 sqrt(|a_pp a_qq|), compared in squares
+          if (apq * apq > 1e-30 * fabs(app * aqq) && fabs(apq) > floor_abs && fabs(apq) > 1e-300) {
             double tau = (aqq - app) / (2.0 * apq);
             double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + tt * tt);
@@ -164,7 +174,7 @@ __device__ static __forceinline__ void wg_jacobi(double* A, int n, int ld, doubl
       // pair a, columns of pair b) is independent, so one phase suffices: rotate the block's rows,
       // then its columns (the same operations, in the same order, as a row pass followed by a
       // column pass).  The padding pair is (p, p) with the identity rotation.
-      wg_for2(npair, npair, [&](int a, int b) {
+      wg_for2<BS>(npair, npair, [&](int a, int b) {
         const int pa = P[a], qa = Q[a], pb = P[b], qb = Q[b];
         const double ca = Cs[a], sa = Sn[a], cb = Cs[b], sb = Sn[b];
         const double x00 = A[(long)pa * ld + pb], x01 = A[(long)pa * ld + qb];
@@ -177,7 +187,7 @@ __device__ static __forceinline__ void wg_jacobi(double* A, int n, int ld, doubl
         A[(long)qa * ld + qb] = sb * r10 + cb * r11;
       });
       // V <- V R^t
-      wg_for2(npair, n, [&](int b, int i) {
+      wg_for2<BS>(npair, n, [&](int b, int i) {
         const int pb = P[b], qb = Q[b];
         const double cb = Cs[b], sb = Sn[b];
         const double vip = V[(long)i * ldv + pb], viq = V[(long)i * ldv + qb];
@@ -198,9 +208,10 @@ __device__ static __forceinline__ void wg_jacobi(double* A, int n, int ld, doubl
 
 // indices of the k extremal values of lam[0..n) (largest first if desc, else smallest first); ties
 // to the lower index.  Each thread ranks its own entries (the rank is the output position).
+template <int BS = DBLK>
 __device__ static void select_extremal(const double* lam, int n, int k, bool desc, int* out) {
   wg_sync();
-  for (int i = threadIdx.x; i < n; i += DBLK) {
+  for (int i = threadIdx.x; i < n; i += BS) {
     const double li = lam[i];
     int rank = 0;
     for (int j = 0; j < n; ++j) {
@@ -217,39 +228,53 @@ __device__ static void select_extremal(const double* lam, int n, int k, bool des
 // Gram matrix.  A non-positive pivot retries once with a diagonal shift of 1e-14 trace; a second
 // failure sets *status.
 // ------------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(DBLK) void k_chol_inv_upper(int w, const double* G, double* T, int* status) {
+// The Cholesky-QR factor of the n_b x n_b Gram matrix runs on one wavefront: its steps are short
+// chains of LDS updates, and a barrier of a one-wave workgroup costs next to nothing.
+static constexpr int SB = 64;
+
+// workgroup b of the launch factors G_b into T_b (b = 0, 1: the U- and V-side passes of a pair)
+__global__ __launch_bounds__(SB) void k_chol_inv_upper(int w, const double* G0, double* T0, const double* G1, double* T1,
+                                                       int* status) {
+  const double* G = blockIdx.x == 0 ? G0 : G1;
+  double* T = blockIdx.x == 0 ? T0 : T1;
   // Columns are first scaled to unit norm (D G D with D = diag(G)^-1/2, T = D R^-1): the span,
   // and hence the Ritz step, is unchanged, and the factorisation then depends on the angles between
   // the columns only, not on their norms (relaxations can grow some columns by many orders).
-  __shared__ double L[16 * 16];
+  __shared__ double L[16 * 16], Ts[16 * 16], Gs[16 * 16];
   __shared__ double dsc[16];
   __shared__ int info;
-  for (int i = threadIdx.x; i < w; i += DBLK) {
-    const double g = G[i * w + i];
+  for (int t = threadIdx.x; t < w * w; t += SB) Gs[t] = G[t];
+  wg_sync();
+  for (int i = threadIdx.x; i < w; i += SB) {
+    const double g = Gs[i * w + i];
     dsc[i] = g > 0.0 ? 1.0 / sqrt(g) : 1.0;
   }
   wg_sync();
   for (int attempt = 0; attempt < 2; ++attempt) {
     double tr = 0.0;
-    for (int i = 0; i < w; ++i) tr += G[i * w + i] * dsc[i] * dsc[i];
-    for (int t = threadIdx.x; t < w * w; t += DBLK) {
+    for (int i = 0; i < w; ++i) tr += Gs[i * w + i] * dsc[i] * dsc[i];
+    for (int t = threadIdx.x; t < w * w; t += SB) {
       int i = t / w, j = t % w;
-      L[i * 16 + j] = G[t] * dsc[i] * dsc[j] + (attempt && i == j ? 1e-14 * tr : 0.0);
+      L[i * 16 + j] = Gs[t] * dsc[i] * dsc[j] + (attempt && i == j ? 1e-14 * tr : 0.0);
     }
     if (threadIdx.x == 0) info = 0;
     wg_sync();
-    wg_chol(L, w, 16, &info);
+    wg_chol<SB>(L, w, 16, &info);
     if (info == 0) break;
     if (attempt == 1 && threadIdx.x == 0) *status = ST_E_NUMERIC;
     wg_sync();
   }
   // T = D L^{-t}: solve L^t T' = I, then scale the rows
-  for (int t = threadIdx.x; t < w * w; t += DBLK) T[t] = (t / w == t % w) ? 1.0 : 0.0;
-  wg_trsm_lower_t(L, w, 16, T, w, w);
-  for (int t = threadIdx.x; t < w * w; t += DBLK) T[t] *= dsc[t / w];
+  for (int t = threadIdx.x; t < w * w; t += SB) Ts[t] = (t / w == t % w) ? 1.0 : 0.0;
+  wg_trsm_lower_t<SB>(L, w, 16, Ts, w, w);
+  for (int t = threadIdx.x; t < w * w; t += SB) T[t] = Ts[t] * dsc[t / w];
 }
 void launch_chol_inv_upper(int w, const double* G, double* T, int* status, hipStream_t s) {
-  hipLaunchKernelGGL(k_chol_inv_upper, dim3(1), dim3(DBLK), 0, s, w, G, T, status);
+  hipLaunchKernelGGL(k_chol_inv_upper, dim3(1), dim3(SB), 0, s, w, G, T, G, T, status);
+}
+void launch_chol_inv_upper2(int w, const double* G0, double* T0, const double* G1, double* T1, int* status,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_chol_inv_upper, dim3(2), dim3(SB), 0, s, w, G0, T0, G1, T1, status);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -276,10 +301,10 @@ __global__ __launch_bounds__(DBLK) void k_small_ritz(int w, int spd, int minimal
       int i = t / w, j = t % w;
       A[t] = 0.5 * (Ms[i * w + j] + Ms[j * w + i]);
     }
-    wg_jacobi(A, w, w, V, w, 60);
+    wg_jacobi<DBLK>(A, w, w, V, w, 60);
     for (int i = threadIdx.x; i < w; i += DBLK) lam[i] = A[i * w + i];
     wg_sync();
-    select_extremal(lam, w, w, !minimal, ord);
+    select_extremal<DBLK>(lam, w, w, !minimal, ord);
     for (int t = threadIdx.x; t < w * w; t += DBLK) {
       int i = t / w, k = t % w;
       Y[i * w + k] = V[i * w + ord[k]];
@@ -306,10 +331,10 @@ __global__ __launch_bounds__(DBLK) void k_small_ritz(int w, int spd, int minimal
     A[t] = v;
     V[t] = i0 == j0 ? ((i >= w && j >= w) ? -h : h) : 0.0;
   }
-  wg_jacobi(A, n2, n2, V, n2, 60, false);
+  wg_jacobi<DBLK>(A, n2, n2, V, n2, 60, false);
   for (int i = threadIdx.x; i < n2; i += DBLK) lam[i] = A[i * n2 + i];
   wg_sync();
-  select_extremal(lam, n2, n2, true, ord);   // descending: +sigma_1 ... -sigma_1
+  select_extremal<DBLK>(lam, n2, n2, true, ord);   // descending: +sigma_1 ... -sigma_1
   // z_k: normalised lower part of the +sigma_k eigenvector (for sigma > 0 it holds half of the
   // eigenvector's mass, and the lower parts of a degenerate eigenspace stay orthonormal);
   // y_k = M z_k / sigma_k, so that (y_k, z_k) is consistent inside degenerate clusters.  For
@@ -520,20 +545,63 @@ void launch_coarse_gsvd(int spd, int minimal, int mL, int nL, int nb, double* A,
 // its SVD is its eigen-decomposition with |eigenvalues|; the pseudo-inverse without the smallest
 // singular component is sum_{i != i*} q_i q_i^t / lambda_i, i* = argmin |lambda_i|.
 // basis (nb N^2) holds each column's eigenvectors Q_j.  Cold: Jacobi on M from the identity.  Warm:
-// sigma_j moved little since Q_j was computed, so Q_j^t M Q_j is nearly diagonal; Jacobi finishes it
-// in a sweep or two and Q_j <- Q_j V.  Both give the eigen-decomposition of M to rounding.
-// rhs / out: N x nb row-major.  work: nb * 2 N^2 doubles.
+// sigma_j moved little since Q_j was computed, so Q_j^t M Q_j is nearly diagonal; Jacobi (or the
+// first-order update below) finishes it and Q_j <- Q_j V.  Both give the eigen-decomposition of M to
+// rounding.  rhs / out: N x nb row-major.  work: nb * 2 N^2 doubles.
+//
+// The workgroup has 1024 threads: a Jacobi round is a chain of dependent LDS updates, and only nb
+// workgroups run, so four times the threads of the other dense kernels shorten each round's chain.
 // ------------------------------------------------------------------------------------------------
+static constexpr int PB = 1024;
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// C = op(A) op(B) for N x N row-major matrices in LDS, N <= 64, on the FP64 matrix cores: wave w of
+// the 16 computes the 16 x 16 tile (w / 4, w % 4) of the product padded to 64 x 64, four k per
+// instruction (lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] of the 16 x 4 and 4 x 16
+// slices; the tile's D[l / 16 + 4 v][l % 16] comes back in register v).  C aliases neither input;
+// the caller synchronises before and after.
+template <bool TA, bool TB>
+__device__ __forceinline__ void wg_mm64(const double* A, const double* B, double* C, int N) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int ti = w >> 2, tj = w & 3;
+  const int r = ti * 16 + (lane & 15), c = tj * 16 + (lane & 15), kk = lane >> 4;
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < N; k0 += 4) {
+    const int k = k0 + kk;
+    double a = 0.0, b = 0.0;
+    if (r < N && k < N) a = TA ? A[k * N + r] : A[r * N + k];
+    if (c < N && k < N) b = TB ? B[c * N + k] : B[k * N + c];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = ti * 16 + kk + 4 * v;
+    if (row < N && c < N) C[row * N + c] = acc[v];
+  }
+}
+
+// C = op(A) op(B), N x N row-major, any N: one output per thread per pass, k ascending
+template <bool TA, bool TB>
+__device__ __forceinline__ void wg_mm(const double* A, const double* B, double* C, int N) {
+  wg_for2<PB>(N, N, [&](int i, int c) {
+    double acc = 0.0;
+    for (int r = 0; r < N; ++r) acc += (TA ? A[(long)r * N + i] : A[(long)i * N + r]) * (TB ? B[(long)c * N + r] : B[(long)r * N + c]);
+    C[(long)i * N + c] = acc;
+  });
+}
+
 template <int LDSMODE>
-__global__ __launch_bounds__(DBLK) void k_pinv_solve(int N, int nb, const double* X, const double* Y,
-                                                     const double* sig, const double* rhs, double* out,
-                                                     double* work, double* basis, int warm) {
+__global__ __launch_bounds__(PB) void k_pinv_solve(int N, int nb, const double* X, const double* Y,
+                                                   const double* sig, const double* rhs, double* out,
+                                                   double* work, double* basis, int warm, int lds4) {
   // LDSMODE 0: everything in global memory (L2); 1: M in LDS; 2: M, the rotation accumulator and
-  // the eigenvector copy in LDS (Q is read from / written back to `basis`)
+  // the eigenvector copy in LDS (Q is read from / written back to `basis`), and for N <= 64 the
+  // dense products on the matrix cores
   constexpr int lds_mode = LDSMODE;
   extern __shared__ double dyn[];
   const int j = blockIdx.x;
   const long NN = (long)N * N;
+  const bool mm = lds_mode == 2 && N <= 64;
   double* Qg = basis + (long)j * NN;
   double* M;
   double* W2;
@@ -541,73 +609,151 @@ __global__ __launch_bounds__(DBLK) void k_pinv_solve(int N, int nb, const double
   if constexpr (lds_mode >= 1) M = dyn; else M = work + (long)j * 2 * NN;
   if constexpr (lds_mode == 2) { W2 = dyn + NN; Q = dyn + 2 * NN; }
   else { W2 = work + (long)j * 2 * NN + NN; Q = Qg; }
+  // fourth LDS array for the Newton-type steps (matrix-core products only)
+  double* Tm = (lds_mode == 2 && mm && lds4) ? dyn + 3 * NN : nullptr;
   __shared__ double cf[1024];
   __shared__ double lam[1024];
   __shared__ double rj[1024];
+  __shared__ double red[PB];
   __shared__ int imin;
   const double s = sig[j];
   if (!warm) {
-    for (long t = threadIdx.x; t < NN; t += DBLK) M[t] = X[t] - s * Y[t];
-    wg_jacobi(M, N, N, Q, N, 60);
-    for (int i = threadIdx.x; i < N; i += DBLK) lam[i] = M[(long)i * N + i];
+    for (long t = threadIdx.x; t < NN; t += PB) M[t] = X[t] - s * Y[t];
+    wg_jacobi<PB>(M, N, N, Q, N, 60);
+    for (int i = threadIdx.x; i < N; i += PB) lam[i] = M[(long)i * N + i];
   } else {
     if constexpr (lds_mode == 2)
-      for (long t = threadIdx.x; t < NN; t += DBLK) Q[t] = Qg[t];
-    wg_sync();
+      for (long t = threadIdx.x; t < NN; t += PB) Q[t] = Qg[t];
     // M = X - s Y ; W2 = M Q ; M = Q^t W2 (symmetrised)
-    for (long t = threadIdx.x; t < NN; t += DBLK) M[t] = X[t] - s * Y[t];
+    for (long t = threadIdx.x; t < NN; t += PB) M[t] = X[t] - s * Y[t];
     wg_sync();
-    wg_for2(N, N, [&](int i, int c) {
-      const double* mr = M + (long)i * N;
-      double acc = 0.0;
-      for (int r = 0; r < N; ++r) acc += mr[r] * Q[(long)r * N + c];
-      W2[(long)i * N + c] = acc;
-    });
+    if (mm) wg_mm64<false, false>(M, Q, W2, N);
+    else wg_mm<false, false>(M, Q, W2, N);
     wg_sync();
-    wg_for2(N, N, [&](int i, int c) {
-      if (c < i) return;
-      double a1 = 0.0, a2 = 0.0;
-      for (int r = 0; r < N; ++r) {
-        a1 += Q[(long)r * N + i] * W2[(long)r * N + c];
-        a2 += Q[(long)r * N + c] * W2[(long)r * N + i];
-      }
-      const double v = 0.5 * (a1 + a2);
+    if (mm) wg_mm64<true, false>(Q, W2, M, N);
+    else wg_mm<true, false>(Q, W2, M, N);
+    wg_sync();
+    wg_for2<PB>(N, N, [&](int i, int c) {
+      if (c <= i) return;
+      const double v = 0.5 * (M[(long)i * N + c] + M[(long)c * N + i]);
       M[(long)i * N + c] = v;
       M[(long)c * N + i] = v;
     });
     wg_sync();
-    wg_jacobi(M, N, N, W2, N, 60);
-    for (int i = threadIdx.x; i < N; i += DBLK) lam[i] = M[(long)i * N + i];
+    // M = D + E with E off the diagonal, K_pq = E_pq / (d_q - d_p) (zero where a Jacobi sweep would
+    // not rotate the pair), kmax = max |K_pq|.
+    //  * kmax <= 2^-26: every rotation of a sweep would have |tan| <= 2^-26 (the sweep after which
+    //    the eigensolver stops); first-order perturbation gives the eigenvectors to the same accuracy
+    //    in one step: W2 = I + K + K^2 / 2, eigenvalues d_q + sum_p E_pq K_pq.
+    //  * kmax <= 1e-4 (and a fourth N x N array in LDS): a Newton-type step M <- W^t M W, Q <- Q W
+    //    with W = I + K + K^2 / 2 (W^t W = I + K^4 / 4: orthogonal to rounding) leaves off-diagonal
+    //    entries of order kmax^2 relative to the gaps; repeat (at most three steps).
+    //  * otherwise Jacobi sweeps.
+    double fro = 0.0;
+    wg_for2<PB>(N, N, [&](int i, int c) {
+      const double a = M[(long)i * N + c];
+      fro += a * a;
+    });
+    red[threadIdx.x] = fro;
+    wg_sync();
+    for (int h = PB / 2; h > 0; h >>= 1) {
+      if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+      wg_sync();
+    }
+    const double floor_abs = 0x1p-53 * sqrt(red[0]);
+    wg_sync();
+    for (int step = 0;; ++step) {
+      // K into W2 (diagonal zero) and kmax
+      double kl = 0.0;
+      wg_for2<PB>(N, N, [&](int p, int q) {
+        double k = 0.0;
+        if (p != q) {
+          const double apq = M[(long)p * N + q], app = M[(long)p * N + p], aqq = M[(long)q * N + q];
+          if (apq * apq > 1e-30 * fabs(app * aqq) && fabs(apq) > floor_abs && fabs(apq) > 1e-300) {
+            const double g = aqq - app;
+            if (fabs(apq) < 0.25 * fabs(g)) k = apq / g;
+            kl = fmax(kl, fabs(apq) < 0.25 * fabs(g) ? fabs(k) : 1.0);
+          }
+        }
+        W2[(long)p * N + q] = k;
+      });
+      red[threadIdx.x] = kl;
+      wg_sync();
+      for (int h = PB / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
+        wg_sync();
+      }
+      const double kmax = red[0];
+      wg_sync();
+      if (kmax <= 0x1p-26) {
+        for (int q = threadIdx.x; q < N; q += PB) {
+          double l = M[(long)q * N + q];
+          for (int p = 0; p < N; ++p) l += M[(long)p * N + q] * W2[(long)p * N + q];
+          lam[q] = l;
+        }
+        wg_sync();
+        // M <- K^2, then W2 <- I + K + K^2 / 2
+        if (mm) wg_mm64<false, false>(W2, W2, M, N);
+        else wg_mm<false, false>(W2, W2, M, N);
+        wg_sync();
+        wg_for2<PB>(N, N, [&](int i, int c) {
+          W2[(long)i * N + c] += 0.5 * M[(long)i * N + c] + (i == c ? 1.0 : 0.0);
+        });
+        break;
+      }
+      if (!Tm || kmax > 1e-4 || step == 3) {
+        wg_jacobi<PB>(M, N, N, W2, N, 60);
+        for (int i = threadIdx.x; i < N; i += PB) lam[i] = M[(long)i * N + i];
+        break;
+      }
+      // W2 <- W = I + K + K^2 / 2 ; M <- W^t (M W) (symmetrised) ; Q <- Q W
+      wg_mm64<false, false>(W2, W2, Tm, N);
+      wg_sync();
+      wg_for2<PB>(N, N, [&](int i, int c) {
+        W2[(long)i * N + c] += 0.5 * Tm[(long)i * N + c] + (i == c ? 1.0 : 0.0);
+      });
+      wg_sync();
+      wg_mm64<false, false>(M, W2, Tm, N);
+      wg_sync();
+      wg_mm64<true, false>(W2, Tm, M, N);
+      wg_sync();
+      wg_for2<PB>(N, N, [&](int i, int c) {
+        if (c <= i) return;
+        const double v = 0.5 * (M[(long)i * N + c] + M[(long)c * N + i]);
+        M[(long)i * N + c] = v;
+        M[(long)c * N + i] = v;
+      });
+      wg_mm64<false, false>(Q, W2, Tm, N);
+      wg_sync();
+      for (long t = threadIdx.x; t < NN; t += PB) Q[t] = Tm[t];
+      wg_sync();
+    }
     wg_sync();
     // Q <- Q W2, through M as the temporary
-    wg_for2(N, N, [&](int i, int c) {
-      double acc = 0.0;
-      for (int r = 0; r < N; ++r) acc += Q[(long)i * N + r] * W2[(long)r * N + c];
-      M[(long)i * N + c] = acc;
-    });
+    if (mm) wg_mm64<false, false>(Q, W2, M, N);
+    else wg_mm<false, false>(Q, W2, M, N);
     wg_sync();
-    for (long t = threadIdx.x; t < NN; t += DBLK) Q[t] = M[t];
+    for (long t = threadIdx.x; t < NN; t += PB) Q[t] = M[t];
   }
   wg_sync();
   if constexpr (lds_mode == 2)
-    for (long t = threadIdx.x; t < NN; t += DBLK) Qg[t] = Q[t];
+    for (long t = threadIdx.x; t < NN; t += PB) Qg[t] = Q[t];
   if (threadIdx.x == 0) {
     int best = 0;
     for (int i = 1; i < N; ++i)
       if (fabs(lam[i]) < fabs(lam[best])) best = i;
     imin = best;
   }
+  for (int r = threadIdx.x; r < N; r += PB) rj[r] = rhs[(long)r * nb + j];
   wg_sync();
-  for (int r = threadIdx.x; r < N; r += DBLK) rj[r] = rhs[(long)r * nb + j];
-  wg_sync();
-  for (int i = threadIdx.x; i < N; i += DBLK) {
+  for (int i = threadIdx.x; i < N; i += PB) {
     double d = 0.0;
     for (int r = 0; r < N; ++r) d += Q[(long)r * N + i] * rj[r];
     const double l = lam[i];
     cf[i] = (i == imin || l == 0.0) ? 0.0 : d / l;
   }
   wg_sync();
-  for (int r = threadIdx.x; r < N; r += DBLK) {
+  for (int r = threadIdx.x; r < N; r += PB) {
     double z = 0.0;
     for (int i = 0; i < N; ++i) z += Q[(long)r * N + i] * cf[i];
     out[(long)r * nb + j] = z;
@@ -615,14 +761,21 @@ __global__ __launch_bounds__(DBLK) void k_pinv_solve(int N, int nb, const double
 }
 
 // The eigensolve of X - sigma_j Y keeps its working matrices in LDS when they fit the workgroup's
-// share (gfx950: 160 KB per CU): all three N x N arrays for small N, else the matrix alone.
+// share (gfx950: 160 KB per CU) beside the kernel's static arrays: all three N x N arrays for small
+// N, else the matrix alone.
 static int pinv_max_dyn_lds() {
   // initialised once per process (thread-safe static initialisation)
   static const int max_dyn = [] {
     int dev = 0, v = 0;
     (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) v = 65536;
-    const int static_lds = 49152;   // Jacobi rotation tables, reductions, coefficients, eigenvalues
+    hipFuncAttributes fa1{}, fa2{};
+    if (hipFuncGetAttributes(&fa1, (const void*)k_pinv_solve<1>) != hipSuccess ||
+        hipFuncGetAttributes(&fa2, (const void*)k_pinv_solve<2>) != hipSuccess) {
+      (void)hipGetLastError();
+      return 0;
+    }
+    const int static_lds = (int)std::max(fa1.sharedSizeBytes, fa2.sharedSizeBytes);
     int m = v - static_lds;
     if (m > 0 &&
         (hipFuncSetAttribute((const void*)k_pinv_solve<1>, hipFuncAttributeMaxDynamicSharedMemorySize, m) !=
@@ -643,13 +796,16 @@ void launch_pinv_solve(int N, int nb, const double* X, const double* Y, const do
   const size_t one = (size_t)N * N * sizeof(double);
   const size_t max_dyn = (size_t)pinv_max_dyn_lds();
   const int mode = 3 * one <= max_dyn ? 2 : one <= max_dyn ? 1 : 0;
-  const size_t lds = mode == 2 ? 3 * one : mode == 1 ? one : 0;
+  const int lds4 = (mode == 2 && N <= 64 && 4 * one <= max_dyn) ? 1 : 0;
+  const size_t lds = mode == 2 ? (lds4 ? 4 : 3) * one : mode == 1 ? one : 0;
   if (mode == 2)
-    hipLaunchKernelGGL(k_pinv_solve<2>, dim3(nb), dim3(DBLK), lds, s, N, nb, X, Y, sig, rhs, out, work, basis, warm);
+    hipLaunchKernelGGL(k_pinv_solve<2>, dim3(nb), dim3(PB), lds, s, N, nb, X, Y, sig, rhs, out, work, basis, warm,
+                       lds4);
   else if (mode == 1)
-    hipLaunchKernelGGL(k_pinv_solve<1>, dim3(nb), dim3(DBLK), lds, s, N, nb, X, Y, sig, rhs, out, work, basis, warm);
+    hipLaunchKernelGGL(k_pinv_solve<1>, dim3(nb), dim3(PB), lds, s, N, nb, X, Y, sig, rhs, out, work, basis, warm,
+                       0);
   else
-    hipLaunchKernelGGL(k_pinv_solve<0>, dim3(nb), dim3(DBLK), 0, s, N, nb, X, Y, sig, rhs, out, work, basis, warm);
+    hipLaunchKernelGGL(k_pinv_solve<0>, dim3(nb), dim3(PB), 0, s, N, nb, X, Y, sig, rhs, out, work, basis, warm, 0);
 }
 
 // Pencil variant, set-up once per additive phase: Y = L L^t, K = L^-1 X L^-t = W diag(mu) W^t,

@@ -8,6 +8,7 @@
 // LPR lanes of a 64-wide wavefront; lane l of the group owns columns [CPL*l, CPL*l + CPL).  The
 // column loads of a gathered vector row are therefore contiguous across the group.
 #include "common.h"
+#include "solver.h"
 
 #include <algorithm>
 #include <type_traits>
@@ -125,13 +126,24 @@ __device__ __forceinline__ void walk_row(int k, int ke, const int* __restrict__ 
 // ------------------------------------------------------------------------------------------------
 // Block SpMM  y = A x (+ beta y)
 // ------------------------------------------------------------------------------------------------
+template <typename T>
+struct SpmmPOD {
+  int m, w;
+  const int* rp; const int* ci; const T* v; const T* x; T* y; T beta;
+};
+
+// thread t of the product's own grid
 template <typename T, int CPL, int SPLIT>
-__global__ __launch_bounds__(BLK) void k_spmm(int m, int w, int lshift, const int* __restrict__ rp,
-                                              const int* __restrict__ ci, const T* __restrict__ v,
-                                              const T* __restrict__ x, T* __restrict__ y, T beta) {
+__device__ __forceinline__ void spmm_body(const SpmmPOD<T>& a, int lshift, long t) {
   constexpr int LS = SPLIT == 1 ? 0 : SPLIT == 4 ? 2 : SPLIT == 8 ? 3 : 4;
+  const int m = a.m, w = a.w;
+  const int* __restrict__ rp = a.rp;
+  const int* __restrict__ ci = a.ci;
+  const T* __restrict__ v = a.v;
+  const T* __restrict__ x = a.x;
+  T* __restrict__ y = a.y;
+  const T beta = a.beta;
   const int gl = lshift + LS;
-  long t = (long)blockIdx.x * BLK + threadIdx.x;
   int row = (int)(t >> gl);
   const int lane = (int)(t & ((1 << gl) - 1));
   const int sidx = lane >> lshift;
@@ -154,6 +166,19 @@ __global__ __launch_bounds__(BLK) void k_spmm(int m, int w, int lshift, const in
   strow<T, CPL>(yr, c0, w, acc);
 }
 
+template <typename T, int CPL, int SPLIT>
+__global__ __launch_bounds__(BLK) void k_spmm(SpmmPOD<T> a, int lshift) {
+  spmm_body<T, CPL, SPLIT>(a, lshift, (long)blockIdx.x * BLK + threadIdx.x);
+}
+
+// Two independent products in one launch (the u- and v-side transfers of a level): workgroups
+// [0, nb0) run the first, the others the second, so the two latency chains overlap.
+template <typename T, int CPL, int SPLIT>
+__global__ __launch_bounds__(BLK) void k_spmm2(SpmmPOD<T> a, SpmmPOD<T> b, int lshift, int nb0) {
+  if ((int)blockIdx.x < nb0) spmm_body<T, CPL, SPLIT>(a, lshift, (long)blockIdx.x * BLK + threadIdx.x);
+  else spmm_body<T, CPL, SPLIT>(b, lshift, (long)(blockIdx.x - nb0) * BLK + threadIdx.x);
+}
+
 #define SLAMG_DISPATCH_SPLIT(KER, T, CPL, SP, GRID, ...)                                        \
   do {                                                                                      \
     if (SP == 1) hipLaunchKernelGGL((KER<T, CPL, 1>), dim3(GRID), dim3(BLK), 0, __VA_ARGS__);  \
@@ -169,8 +194,21 @@ void launch_spmm(int m, int w, const int* rp, const int* ci, const T* v, const T
   int sh = lshift_of(w);
   int sp = split_of(nnz, m, sh);
   int grid = ceil_div((long)m << (sh + log2i(sp)), BLK);
-  if (cpl_of(w) == 2) SLAMG_DISPATCH_SPLIT(k_spmm, T, 2, sp, grid, s, m, w, sh, rp, ci, v, x, y, (T)beta);
-  else SLAMG_DISPATCH_SPLIT(k_spmm, T, 1, sp, grid, s, m, w, sh, rp, ci, v, x, y, (T)beta);
+  SpmmPOD<T> p{m, w, rp, ci, v, x, y, (T)beta};
+  if (cpl_of(w) == 2) SLAMG_DISPATCH_SPLIT(k_spmm, T, 2, sp, grid, s, p, sh);
+  else SLAMG_DISPATCH_SPLIT(k_spmm, T, 1, sp, grid, s, p, sh);
+}
+
+template <typename T>
+void launch_spmm2(const SpmmArgs<T>& a, const SpmmArgs<T>& b, int w, hipStream_t s) {
+  if (a.m <= 0) { launch_spmm<T>(b.m, w, b.rp, b.ci, b.v, b.x, b.y, b.beta, s, b.nnz); return; }
+  if (b.m <= 0) { launch_spmm<T>(a.m, w, a.rp, a.ci, a.v, a.x, a.y, a.beta, s, a.nnz); return; }
+  const int sh = lshift_of(w);
+  const int sp = std::max(split_of(a.nnz, a.m, sh), split_of(b.nnz, b.m, sh));
+  const int g0 = ceil_div((long)a.m << (sh + log2i(sp)), BLK), g1 = ceil_div((long)b.m << (sh + log2i(sp)), BLK);
+  SpmmPOD<T> pa{a.m, w, a.rp, a.ci, a.v, a.x, a.y, (T)a.beta}, pb{b.m, w, b.rp, b.ci, b.v, b.x, b.y, (T)b.beta};
+  if (cpl_of(w) == 2) SLAMG_DISPATCH_SPLIT(k_spmm2, T, 2, sp, g0 + g1, s, pa, pb, sh, g0);
+  else SLAMG_DISPATCH_SPLIT(k_spmm2, T, 1, sp, g0 + g1, s, pa, pb, sh, g0);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -201,11 +239,11 @@ __device__ __forceinline__ void coefs(int cmode, double om, double s, T& ca, T& 
   }
 }
 
+// thread t of the row operation's own grid
 template <typename T, int CPL, int SPLIT>
-__global__ __launch_bounds__(BLK) void k_rowop(RowOpPOD<T> a, int lshift) {
+__device__ __forceinline__ void rowop_body(const RowOpPOD<T>& a, int lshift, long t) {
   constexpr int LS = SPLIT == 1 ? 0 : SPLIT == 4 ? 2 : SPLIT == 8 ? 3 : 4;
   const int gl = lshift + LS;
-  long t = (long)blockIdx.x * BLK + threadIdx.x;
   int row = (int)(t >> gl);
   const int lane = (int)(t & ((1 << gl) - 1));
   const int sidx = lane >> lshift;
@@ -258,6 +296,19 @@ __global__ __launch_bounds__(BLK) void k_rowop(RowOpPOD<T> a, int lshift) {
   strow<T, CPL>(a.out + (long)row * w, c0, w, r);
 }
 
+template <typename T, int CPL, int SPLIT>
+__global__ __launch_bounds__(BLK) void k_rowop(RowOpPOD<T> a, int lshift) {
+  rowop_body<T, CPL, SPLIT>(a, lshift, (long)blockIdx.x * BLK + threadIdx.x);
+}
+
+// Two independent row operations in one launch (the u- and v-side residuals of a level):
+// workgroups [0, nb0) run the first, the others the second.
+template <typename T, int CPL, int SPLIT>
+__global__ __launch_bounds__(BLK) void k_rowop2(RowOpPOD<T> a, RowOpPOD<T> b, int lshift, int nb0) {
+  if ((int)blockIdx.x < nb0) rowop_body<T, CPL, SPLIT>(a, lshift, (long)blockIdx.x * BLK + threadIdx.x);
+  else rowop_body<T, CPL, SPLIT>(b, lshift, (long)(blockIdx.x - nb0) * BLK + threadIdx.x);
+}
+
 template <typename T>
 void launch_rowop(const RowOpArgs<T>& a, hipStream_t s) {
   if (a.nrows <= 0) return;
@@ -268,6 +319,25 @@ void launch_rowop(const RowOpArgs<T>& a, hipStream_t s) {
   int grid = ceil_div((long)a.nrows << (sh + log2i(sp)), BLK);
   if (cpl_of(a.w) == 2) SLAMG_DISPATCH_SPLIT(k_rowop, T, 2, sp, grid, s, p, sh);
   else SLAMG_DISPATCH_SPLIT(k_rowop, T, 1, sp, grid, s, p, sh);
+}
+
+template <typename T>
+static RowOpPOD<T> rowop_pod(const RowOpArgs<T>& a) {
+  return RowOpPOD<T>{a.nrows, a.w, a.Krp, a.Kci, a.Kv, a.z, a.mmode, a.Mrp, a.Mci, a.Mv, a.y,
+                     a.x, a.D, a.kap, a.sig, a.cmode, a.omega, a.out};
+}
+
+template <typename T>
+void launch_rowop2(const RowOpArgs<T>& a, const RowOpArgs<T>& b, hipStream_t s) {
+  if (a.nrows <= 0) { launch_rowop(b, s); return; }
+  if (b.nrows <= 0) { launch_rowop(a, s); return; }
+  const int sh = lshift_of(a.w);
+  const int sp = std::max(split_of(a.Kv ? a.nnzK : -1, a.nrows, sh, a.mmode == M_CSR ? a.avgM : 0.0),
+                          split_of(b.Kv ? b.nnzK : -1, b.nrows, sh, b.mmode == M_CSR ? b.avgM : 0.0));
+  const int g0 = ceil_div((long)a.nrows << (sh + log2i(sp)), BLK), g1 = ceil_div((long)b.nrows << (sh + log2i(sp)), BLK);
+  const RowOpPOD<T> pa = rowop_pod(a), pb = rowop_pod(b);
+  if (cpl_of(a.w) == 2) SLAMG_DISPATCH_SPLIT(k_rowop2, T, 2, sp, g0 + g1, s, pa, pb, sh, g0);
+  else SLAMG_DISPATCH_SPLIT(k_rowop2, T, 1, sp, g0 + g1, s, pa, pb, sh, g0);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -499,7 +569,41 @@ template <typename T>
 struct DotPOD {
   int nrows, w;
   const T* a; const int* Krp; const int* Kci; const T* Kv; const T* z; const T* y; const double* sig;
+  double* partial;
 };
+
+// Fixed-order finalisation of one or two reductions (bitwise reproducible): one workgroup per
+// output entry q; thread t sums partials t, t + 256, ... of entry q in ascending order, then a fixed
+// tree.  Workgroups [0, a.nq) finish the first reduction, the rest the second.  gw > 0: a Gram
+// product's 16 x 16 tiles (entry (i, j) of the gw x gw result at i * 16 + j of each tile); gw == 0:
+// column sums (entry q at q).
+struct FinPOD {
+  int nparts, nq, gw;
+  long stride;
+  const double* partial;
+  double* out;
+};
+
+__global__ __launch_bounds__(BLK) void k_finalize(FinPOD a, FinPOD b) {
+  __shared__ double red[BLK];
+  const bool first = (int)blockIdx.x < a.nq;
+  const FinPOD& f = first ? a : b;
+  const int q = first ? (int)blockIdx.x : (int)blockIdx.x - a.nq;
+  const long off = f.gw > 0 ? (long)(q / f.gw) * 16 + q % f.gw : (long)q;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < f.nparts; b += BLK) s += f.partial[(long)b * f.stride + off];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = BLK / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) f.out[q] = red[0];
+}
+
+static void launch_finalize(const FinPOD& a, const FinPOD* b, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(a.nq + (b ? b->nq : 0)), dim3(BLK), 0, s, a, b ? *b : a);
+}
 
 int dots_grid(int nrows, int w) {
   int sh = lshift_of(w);
@@ -507,9 +611,9 @@ int dots_grid(int nrows, int w) {
 }
 
 template <typename T, int CPL, int SPLIT>
-__global__ __launch_bounds__(BLK) void k_dots(DotPOD<T> a, int lshift, double* partial) {
+__device__ __forceinline__ void dots_body(const DotPOD<T>& a, int lshift, int blk, int nblk, double* red) {
   constexpr int LS = SPLIT == 1 ? 0 : SPLIT == 4 ? 2 : SPLIT == 8 ? 3 : 4;
-  __shared__ double red[BLK * 2];
+  double* partial = a.partial;
   const int gl = lshift + LS;
   const int w = a.w;
   const int lane = threadIdx.x & ((1 << gl) - 1);
@@ -518,12 +622,12 @@ __global__ __launch_bounds__(BLK) void k_dots(DotPOD<T> a, int lshift, double* p
   double acc[CPL];
 #pragma unroll
   for (int c = 0; c < CPL; ++c) acc[c] = 0.0;
-  int stride = (gridDim.x * BLK) >> gl;
+  int stride = (nblk * BLK) >> gl;
   if (c0 < w) {
     double sc[CPL];
 #pragma unroll
     for (int c = 0; c < CPL; ++c) sc[c] = (a.sig && c0 + c < w) ? a.sig[c0 + c] : 0.0;
-    for (int row = (int)(((long)blockIdx.x * BLK + threadIdx.x) >> gl); row < a.nrows; row += stride) {
+    for (int row = (int)(((long)blk * BLK + threadIdx.x) >> gl); row < a.nrows; row += stride) {
       T yv[CPL], av[CPL];
       if (sidx == 0) {
         if (a.y) ldrow<T, CPL>(a.y + (long)row * w, c0, w, yv);
@@ -563,25 +667,22 @@ __global__ __launch_bounds__(BLK) void k_dots(DotPOD<T> a, int lshift, double* p
     int ln = col / CPL, sub = col % CPL;
     double s = 0.0;
     for (int tt = ln; tt < BLK; tt += (1 << lshift)) s += red[tt * CPL + sub];
-    partial[(long)blockIdx.x * w + col] = s;
+    partial[(long)blk * w + col] = s;
   }
 }
 
-// Fixed-order finalisation: one workgroup per output column; thread t sums partials t, t+256, ...
-// in order, then a fixed tree in LDS.
-__global__ __launch_bounds__(BLK) void k_finalize(int nparts, int w, const double* __restrict__ partial,
-                                                  double* __restrict__ out) {
-  __shared__ double red[BLK];
-  const int c = blockIdx.x;
-  double s = 0.0;
-  for (int b = threadIdx.x; b < nparts; b += BLK) s += partial[(long)b * w + c];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int h = BLK / 2; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[c] = red[0];
+template <typename T, int CPL, int SPLIT>
+__global__ __launch_bounds__(BLK) void k_dots(DotPOD<T> a, int lshift) {
+  __shared__ double red[BLK * 2];
+  dots_body<T, CPL, SPLIT>(a, lshift, blockIdx.x, gridDim.x, red);
+}
+
+// two independent reductions (same w) in one launch: workgroups [0, nb0) take the first
+template <typename T, int CPL, int SPLIT>
+__global__ __launch_bounds__(BLK) void k_dots2(DotPOD<T> a, DotPOD<T> b, int lshift, int nb0) {
+  __shared__ double red[BLK * 2];
+  if ((int)blockIdx.x < nb0) dots_body<T, CPL, SPLIT>(a, lshift, blockIdx.x, nb0, red);
+  else dots_body<T, CPL, SPLIT>(b, lshift, blockIdx.x - nb0, gridDim.x - nb0, red);
 }
 
 template <typename T>
@@ -591,12 +692,31 @@ void launch_dots(const DotArgs<T>& a, double* partial, double* out, hipStream_t 
     launch_fill(out, a.w, 0.0, s);
     return;
   }
-  DotPOD<T> p{a.nrows, a.w, a.a, a.Krp, a.Kci, a.Kv, a.z, a.y, a.sig};
+  DotPOD<T> p{a.nrows, a.w, a.a, a.Krp, a.Kci, a.Kv, a.z, a.y, a.sig, partial};
   int sh = lshift_of(a.w);
   int sp = split_of(a.Kv ? a.nnzK : -1, a.nrows, sh);
-  if (cpl_of(a.w) == 2) SLAMG_DISPATCH_SPLIT(k_dots, T, 2, sp, grid, s, p, sh, partial);
-  else SLAMG_DISPATCH_SPLIT(k_dots, T, 1, sp, grid, s, p, sh, partial);
-  hipLaunchKernelGGL(k_finalize, dim3(a.w), dim3(BLK), 0, s, grid, a.w, partial, out);
+  if (cpl_of(a.w) == 2) SLAMG_DISPATCH_SPLIT(k_dots, T, 2, sp, grid, s, p, sh);
+  else SLAMG_DISPATCH_SPLIT(k_dots, T, 1, sp, grid, s, p, sh);
+  launch_finalize(FinPOD{grid, a.w, 0, a.w, partial, out}, nullptr, s);
+}
+
+template <typename T>
+void launch_dots2(const DotArgs<T>& a, double* pa, double* oa, const DotArgs<T>& b, double* pb, double* ob,
+                  hipStream_t s) {
+  if (a.nrows <= 0 || b.nrows <= 0) {
+    launch_dots(a, pa, oa, s);
+    launch_dots(b, pb, ob, s);
+    return;
+  }
+  const int g0 = dots_grid(a.nrows, a.w), g1 = dots_grid(b.nrows, b.w);
+  DotPOD<T> qa{a.nrows, a.w, a.a, a.Krp, a.Kci, a.Kv, a.z, a.y, a.sig, pa};
+  DotPOD<T> qb{b.nrows, b.w, b.a, b.Krp, b.Kci, b.Kv, b.z, b.y, b.sig, pb};
+  const int sh = lshift_of(a.w);
+  const int sp = std::max(split_of(a.Kv ? a.nnzK : -1, a.nrows, sh), split_of(b.Kv ? b.nnzK : -1, b.nrows, sh));
+  if (cpl_of(a.w) == 2) SLAMG_DISPATCH_SPLIT(k_dots2, T, 2, sp, g0 + g1, s, qa, qb, sh, g0);
+  else SLAMG_DISPATCH_SPLIT(k_dots2, T, 1, sp, g0 + g1, s, qa, qb, sh, g0);
+  const FinPOD fb{g1, b.w, 0, b.w, pb, ob};
+  launch_finalize(FinPOD{g0, a.w, 0, a.w, pa, oa}, &fb, s);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -608,11 +728,17 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 int gram_grid(int rows) { return std::max(1, std::min(512, ceil_div(rows, 4 * 4 * 16))); }
 
-__global__ __launch_bounds__(BLK) void k_gram(int rows, int w, const double* __restrict__ X,
-                                              const double* __restrict__ Y, double* __restrict__ partial) {
-  __shared__ double red[4][256];
+struct GramPOD {
+  int rows, w;
+  const double* X; const double* Y; double* partial;
+};
+
+__device__ __forceinline__ void gram_body(const GramPOD& a, int blk, int nblk, double (*red)[256]) {
+  const int rows = a.rows, w = a.w;
+  const double* __restrict__ X = a.X;
+  const double* __restrict__ Y = a.Y;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int gw = blockIdx.x * 4 + wv, nw = gridDim.x * 4;
+  const int gw = blk * 4 + wv, nw = nblk * 4;
   const int i = lane & 15, kk = lane >> 4;
   v4d acc = {0.0, 0.0, 0.0, 0.0};
   for (long r0 = (long)gw * 16; r0 < rows; r0 += (long)nw * 16) {
@@ -628,56 +754,95 @@ __global__ __launch_bounds__(BLK) void k_gram(int rows, int w, const double* __r
   for (int v = 0; v < 4; ++v) red[wv][(kk + 4 * v) * 16 + i] = acc[v];
   __syncthreads();
   int tt = threadIdx.x;
-  partial[(long)blockIdx.x * 256 + tt] = ((red[0][tt] + red[1][tt]) + red[2][tt]) + red[3][tt];
+  a.partial[(long)blk * 256 + tt] = ((red[0][tt] + red[1][tt]) + red[2][tt]) + red[3][tt];
 }
 
-// one workgroup per entry (i, j) of the w x w result; fixed-order reduction over the partials
-__global__ __launch_bounds__(BLK) void k_gram_finalize(int nparts, int w, const double* __restrict__ partial,
-                                                       double* __restrict__ G) {
-  __shared__ double red[BLK];
-  const int i = blockIdx.x / w, j = blockIdx.x % w;
-  const int e = i * 16 + j;
-  double s = 0.0;
-  for (int b = threadIdx.x; b < nparts; b += BLK) s += partial[(long)b * 256 + e];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int h = BLK / 2; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) G[i * w + j] = red[0];
+__global__ __launch_bounds__(BLK) void k_gram(GramPOD a) {
+  __shared__ double red[4][256];
+  gram_body(a, blockIdx.x, gridDim.x, red);
+}
+
+// two independent Gram products in one launch: workgroups [0, nb0) take the first
+__global__ __launch_bounds__(BLK) void k_gram2(GramPOD a, GramPOD b, int nb0) {
+  __shared__ double red[4][256];
+  if ((int)blockIdx.x < nb0) gram_body(a, blockIdx.x, nb0, red);
+  else gram_body(b, blockIdx.x - nb0, gridDim.x - nb0, red);
 }
 
 void launch_gram(int rows, int w, const double* X, const double* Y, double* partial, double* G, hipStream_t s) {
   int grid = gram_grid(rows);
-  hipLaunchKernelGGL(k_gram, dim3(grid), dim3(BLK), 0, s, rows, w, X, Y, partial);
-  hipLaunchKernelGGL(k_gram_finalize, dim3(w * w), dim3(BLK), 0, s, grid, w, partial, G);
+  hipLaunchKernelGGL(k_gram, dim3(grid), dim3(BLK), 0, s, GramPOD{rows, w, X, Y, partial});
+  launch_finalize(FinPOD{grid, w * w, w, 256, partial, G}, nullptr, s);
+}
+
+void launch_gram2(int w, int rows_a, const double* Xa, const double* Ya, double* pa, double* Ga, int rows_b,
+                  const double* Xb, const double* Yb, double* pb, double* Gb, hipStream_t s) {
+  const int g0 = gram_grid(rows_a), g1 = gram_grid(rows_b);
+  hipLaunchKernelGGL(k_gram2, dim3(g0 + g1), dim3(BLK), 0, s, GramPOD{rows_a, w, Xa, Ya, pa},
+                     GramPOD{rows_b, w, Xb, Yb, pb}, g0);
+  const FinPOD fb{g1, w * w, w, 256, pb, Gb};
+  launch_finalize(FinPOD{g0, w * w, w, 256, pa, Ga}, &fb, s);
 }
 
 // ------------------------------------------------------------------------------------------------
 // Rotation out = X S (S: win x wout, row-major), gather, column scaling
 // ------------------------------------------------------------------------------------------------
+// one output entry per thread; t < rows * wout < 2^31 (checked by the launcher)
+template <typename T>
+__device__ __forceinline__ void rotate_body(int rows, int win, int wout, const T* __restrict__ X,
+                                            const double* __restrict__ S, T* __restrict__ out, int blk,
+                                            double* Ss) {
+  for (int t = threadIdx.x; t < win * wout; t += BLK) Ss[t] = S[t];
+  __syncthreads();
+  const unsigned t = (unsigned)blk * BLK + threadIdx.x;
+  const unsigned row = t / (unsigned)wout;
+  const int c = (int)(t - row * (unsigned)wout);
+  if (row >= (unsigned)rows) return;
+  const T* xr = X + (long)row * win;
+  double acc = 0.0;
+  for (int k = 0; k < win; ++k) acc += (double)xr[k] * Ss[k * wout + c];
+  out[(long)row * wout + c] = (T)acc;
+}
+
 template <typename T>
 __global__ __launch_bounds__(BLK) void k_rotate(int rows, int win, int wout, const T* __restrict__ X,
                                                 const double* __restrict__ S, T* __restrict__ out) {
   __shared__ double Ss[16 * 16];
-  for (int t = threadIdx.x; t < win * wout; t += BLK) Ss[t] = S[t];
-  __syncthreads();
-  long t = (long)blockIdx.x * BLK + threadIdx.x;
-  long row = t / wout;
-  int c = (int)(t % wout);
-  if (row >= rows) return;
-  const T* xr = X + row * win;
-  double acc = 0.0;
-  for (int k = 0; k < win; ++k) acc += (double)xr[k] * Ss[k * wout + c];
-  out[row * wout + c] = (T)acc;
+  rotate_body<T>(rows, win, wout, X, S, out, blockIdx.x, Ss);
+}
+
+// the U- and V-side rotations (w x w) in one launch: workgroups [0, nb0) take the first
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_rotate2(int w, int rows_a, const T* __restrict__ Xa,
+                                                 const double* __restrict__ Sa, T* __restrict__ outa, int rows_b,
+                                                 const T* __restrict__ Xb, const double* __restrict__ Sb,
+                                                 T* __restrict__ outb, int nb0) {
+  __shared__ double Ss[16 * 16];
+  if ((int)blockIdx.x < nb0) rotate_body<T>(rows_a, w, w, Xa, Sa, outa, blockIdx.x, Ss);
+  else rotate_body<T>(rows_b, w, w, Xb, Sb, outb, blockIdx.x - nb0, Ss);
 }
 
 template <typename T>
 void launch_rotate(int rows, int win, int wout, const T* X, const double* S, T* out, hipStream_t s) {
   if (rows <= 0) return;
+  if ((long)rows * wout >= (1L << 31)) throw SolverError{ST_E_INVALID, "rotation too large"};
   hipLaunchKernelGGL((k_rotate<T>), dim3(ceil_div((long)rows * wout, BLK)), dim3(BLK), 0, s, rows, win,
                      wout, X, S, out);
+}
+
+template <typename T>
+void launch_rotate2(int w, int rows_a, const T* Xa, const double* Sa, T* outa, int rows_b, const T* Xb,
+                    const double* Sb, T* outb, hipStream_t s) {
+  if (rows_a <= 0 || rows_b <= 0) {
+    launch_rotate<T>(rows_a, w, w, Xa, Sa, outa, s);
+    launch_rotate<T>(rows_b, w, w, Xb, Sb, outb, s);
+    return;
+  }
+  if ((long)rows_a * w >= (1L << 31) || (long)rows_b * w >= (1L << 31))
+    throw SolverError{ST_E_INVALID, "rotation too large"};
+  const int g0 = ceil_div((long)rows_a * w, BLK), g1 = ceil_div((long)rows_b * w, BLK);
+  hipLaunchKernelGGL((k_rotate2<T>), dim3(g0 + g1), dim3(BLK), 0, s, w, rows_a, Xa, Sa, outa, rows_b, Xb, Sb,
+                     outb, g0);
 }
 
 template <typename T>
@@ -1055,14 +1220,22 @@ template void launch_spmm<float>(int, int, const int*, const int*, const float*,
                                  hipStream_t, int);
 template void launch_rowop<double>(const RowOpArgs<double>&, hipStream_t);
 template void launch_rowop<float>(const RowOpArgs<float>&, hipStream_t);
+template void launch_rowop2<double>(const RowOpArgs<double>&, const RowOpArgs<double>&, hipStream_t);
+template void launch_rowop2<float>(const RowOpArgs<float>&, const RowOpArgs<float>&, hipStream_t);
+template void launch_spmm2<double>(const SpmmArgs<double>&, const SpmmArgs<double>&, int, hipStream_t);
+template void launch_spmm2<float>(const SpmmArgs<float>&, const SpmmArgs<float>&, int, hipStream_t);
 template void launch_kacz<double>(const KaczArgs<double>&, hipStream_t);
 template void launch_kacz<float>(const KaczArgs<float>&, hipStream_t);
 template void launch_kacz_wg<double>(const KaczArgs<double>*, const int* const*, const int*, int, int, hipStream_t);
 template void launch_kacz_wg<float>(const KaczArgs<float>*, const int* const*, const int*, int, int, hipStream_t);
 template void launch_dots<double>(const DotArgs<double>&, double*, double*, hipStream_t);
 template void launch_dots<float>(const DotArgs<float>&, double*, double*, hipStream_t);
+template void launch_dots2<double>(const DotArgs<double>&, double*, double*, const DotArgs<double>&, double*,
+                                   double*, hipStream_t);
 template void launch_rotate<double>(int, int, int, const double*, const double*, double*, hipStream_t);
 template void launch_rotate<float>(int, int, int, const float*, const double*, float*, hipStream_t);
+template void launch_rotate2<double>(int, int, const double*, const double*, double*, int, const double*,
+                                    const double*, double*, hipStream_t);
 template void launch_gather_rows<double>(int, int, const int*, const double*, double*, hipStream_t);
 template void launch_gather_rows<float>(int, int, const int*, const float*, float*, hipStream_t);
 template void launch_scale_cols<double>(int, int, double*, const double*, int, hipStream_t);

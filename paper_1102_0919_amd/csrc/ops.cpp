@@ -263,21 +263,29 @@ extern "C" slamg_status slamg_op_ritz(int32_t spd, int32_t minimal, int32_t m, i
     double* tU = t.get<double>((size_t)m * w);
     double* Uh = t.get<double>((size_t)m * w);
     double* W = t.get<double>((size_t)m * w);
-    cholqr2(d_u, m, tU, Uh);
     if (spd) {
+      cholqr2(d_u, m, tU, Uh);
       launch_spmm<double>(m, w, d_arp, d_aci, d_av, Uh, W, 0.0, s);
       launch_gram(m, w, Uh, W, part, G, s);
       launch_small_ritz(w, 1, minimal, G, T1, T2, sig, work, status, s);
       launch_rotate<double>(m, w, w, Uh, T1, d_u, s);
     } else {
+      // the U- and V-side Cholesky-QR2 in paired launches, as the solver runs them
       double* tV = t.get<double>((size_t)n * w);
       double* Vh = t.get<double>((size_t)n * w);
-      cholqr2(d_v, n, tV, Vh);
+      double* part2 = t.get<double>((size_t)std::max(gram_grid(std::max(m, n)), 1) * 256);
+      double* G2 = t.get<double>(256);
+      double* T3 = t.get<double>(256);
+      launch_gram2(w, m, d_u, d_u, part, G, n, d_v, d_v, part2, G2, s);
+      launch_chol_inv_upper2(w, G, T1, G2, T3, status, s);
+      launch_rotate2<double>(w, m, d_u, T1, tU, n, d_v, T3, tV, s);
+      launch_gram2(w, m, tU, tU, part, G, n, tV, tV, part2, G2, s);
+      launch_chol_inv_upper2(w, G, T1, G2, T3, status, s);
+      launch_rotate2<double>(w, m, tU, T1, Uh, n, tV, T3, Vh, s);
       launch_spmm<double>(m, w, d_arp, d_aci, d_av, Vh, W, 0.0, s);
       launch_gram(m, w, Uh, W, part, G, s);
       launch_small_ritz(w, 0, minimal, G, T1, T2, sig, work, status, s);
-      launch_rotate<double>(m, w, w, Uh, T1, d_u, s);
-      launch_rotate<double>(n, w, w, Vh, T2, d_v, s);
+      launch_rotate2<double>(w, m, Uh, T1, d_u, n, Vh, T2, d_v, s);
     }
     int st = 0;
     down(&st, status, 1, s);
@@ -365,7 +373,7 @@ extern "C" slamg_status slamg_op_coarse_gsvd(int32_t spd, int32_t minimal, int32
 extern "C" slamg_status slamg_op_coarse_solve(int32_t variant, int32_t N, int32_t nb, const double* h_x,
                                               const double* h_y, const double* h_sig, const double* h_rhs,
                                               double* h_out) {
-  if (N < 1 || N > 1024 || nb < 1 || nb > 16 || (variant < 0 || variant > 2)) return SLAMG_E_INVALID;
+  if (N < 1 || N > 1024 || nb < 1 || nb > 16 || (variant < 0 || variant > 4)) return SLAMG_E_INVALID;
   hipStream_t s = nullptr;
   return guarded(s, [&] {
     Tmp t;
@@ -380,18 +388,20 @@ extern "C" slamg_status slamg_op_coarse_solve(int32_t variant, int32_t N, int32_
     up(Y, h_y, (size_t)N * N, s);
     up(sig, h_sig, nb, s);
     up(rhs, h_rhs, (size_t)N * nb, s);
-    if (variant == 0 || variant == 2) {
+    if (variant != 1) {
       double* work = t.get<double>((size_t)nb * 2 * N * N);
       double* basis = t.get<double>((size_t)nb * N * N);
-      if (variant == 2) {
-        // warm start: eigenvectors of X - sigma'_j Y at sigma'_j = sigma_j (1 + 1e-6) first
+      const bool warm = variant >= 2;
+      if (warm) {
+        // warm start: eigenvectors of X - sigma'_j Y at sigma'_j = sigma_j (1 + delta) first
+        const double delta = variant == 2 ? 1e-6 : variant == 3 ? 1e-12 : 1e-3;
         double* sig2 = t.get<double>(nb);
         std::vector<double> h2(h_sig, h_sig + nb);
-        for (auto& v : h2) v *= 1.0 + 1e-6;
+        for (auto& v : h2) v *= 1.0 + delta;
         up(sig2, h2.data(), nb, s);
         launch_pinv_solve(N, nb, X, Y, sig2, rhs, out, work, basis, 0, status, s);
       }
-      launch_pinv_solve(N, nb, X, Y, sig, rhs, out, work, basis, variant == 2 ? 1 : 0, status, s);
+      launch_pinv_solve(N, nb, X, Y, sig, rhs, out, work, basis, warm ? 1 : 0, status, s);
     } else {
       double* mu = t.get<double>(N);
       double* Z = t.get<double>((size_t)N * N);

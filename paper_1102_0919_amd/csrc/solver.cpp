@@ -209,6 +209,8 @@ class Solver {
   void additive_iteration();
   void ritz();
   void cholqr2(double* X, int rows, double* tmp, double* out);
+  void cholqr2_pair(double* Xa, int rows_a, double* tmpa, double* outa, double* Xb, int rows_b, double* tmpb,
+                    double* outb);
   void residuals(std::vector<double>& rho);
   void residual_launch();
   void residual_collect(std::vector<double>& rho);
@@ -237,6 +239,9 @@ class Solver {
   double* sig_ = nullptr;       // device sigma_b (nb)
   double* flip_ = nullptr;
   double* partial_ = nullptr;   // reduction partials
+  double* partial2_ = nullptr;  // partials of the second reduction of a paired launch
+  double* gram2_ = nullptr;     // second Gram matrix / factor of a paired Cholesky-QR
+  double* small3_ = nullptr;
   double* r1_ = nullptr;        // small device vectors (>= 64)
   double* r2_ = nullptr;
   double* r3_ = nullptr;
@@ -293,7 +298,12 @@ class Solver {
     return pool[ev_used_++];
   }
   template <class T> void rowop(int l, const RowOpArgs<T>& a, const DCsr* K, int cls = 0);
+  template <class T>
+  void rowop2(int l, const RowOpArgs<T>& a, const DCsr* Ka, const RowOpArgs<T>& b, const DCsr* Kb, int cls);
   template <class T> void spmm(int l, const DCsr& K, const T* Kv, int w, const T* x, T* y, double beta);
+  template <class T>
+  void spmm2(int l, const DCsr& Ka, const T* Kva, const T* xa, T* ya, const DCsr& Kb, const T* Kvb, const T* xb, T* yb,
+             double beta);
   template <class T> void dots(int l, const DotArgs<T>& a, const DCsr* K, double* out);
   template <class T> void kacz(int l, const KaczArgs<T>& a, long nnz_colour);
 };
@@ -323,11 +333,34 @@ void Solver::rowop(int l, const RowOpArgs<T>& a0, const DCsr* K, int cls) {
 }
 
 template <class T>
-void Solver::spmm(int l, const DCsr& K, const T* Kv, int w, const T* x, T* y, double beta) {
+void Solver::rowop2(int l, const RowOpArgs<T>& a0, const DCsr* Ka, const RowOpArgs<T>& b0, const DCsr* Kb, int cls) {
+  RowOpArgs<T> a = a0, b = b0;
+  if (a.nnzK < 0 && Ka) a.nnzK = Ka->nnz;
+  if (b.nnzK < 0 && Kb) b.nnzK = Kb->nnz;
+  if (l == 0) prof(cls, rowop_bytes(a, Ka) + rowop_bytes(b, Kb), [&] { launch_rowop2(a, b, st_); });
+  else launch_rowop2(a, b, st_);
+}
+
+template <class T>
+static double spmm_bytes(const DCsr& K, int w, double beta) {
   const double sz = sizeof(T);
-  const double bytes = 4.0 * (K.m + 1) + (4.0 + sz) * K.nnz + sz * w * ((double)K.n + K.m * (beta != 0.0 ? 2 : 1));
-  if (l == 0) prof(5, bytes, [&] { launch_spmm<T>(K.m, w, K.rp, K.ci, Kv, x, y, beta, st_, K.nnz); });
+  return 4.0 * (K.m + 1) + (4.0 + sz) * K.nnz + sz * w * ((double)K.n + K.m * (beta != 0.0 ? 2 : 1));
+}
+
+template <class T>
+void Solver::spmm(int l, const DCsr& K, const T* Kv, int w, const T* x, T* y, double beta) {
+  if (l == 0) prof(5, spmm_bytes<T>(K, w, beta), [&] { launch_spmm<T>(K.m, w, K.rp, K.ci, Kv, x, y, beta, st_, K.nnz); });
   else launch_spmm<T>(K.m, w, K.rp, K.ci, Kv, x, y, beta, st_, K.nnz);
+}
+
+template <class T>
+void Solver::spmm2(int l, const DCsr& Ka, const T* Kva, const T* xa, T* ya, const DCsr& Kb, const T* Kvb, const T* xb,
+                   T* yb, double beta) {
+  SpmmArgs<T> a, b;
+  a.m = Ka.m; a.nnz = Ka.nnz; a.rp = Ka.rp; a.ci = Ka.ci; a.v = Kva; a.x = xa; a.y = ya; a.beta = beta;
+  b.m = Kb.m; b.nnz = Kb.nnz; b.rp = Kb.rp; b.ci = Kb.ci; b.v = Kvb; b.x = xb; b.y = yb; b.beta = beta;
+  if (l == 0) prof(5, spmm_bytes<T>(Ka, nb_, beta) + spmm_bytes<T>(Kb, nb_, beta), [&] { launch_spmm2(a, b, nb_, st_); });
+  else launch_spmm2(a, b, nb_, st_);
 }
 
 template <class T>
@@ -1348,15 +1381,17 @@ void Solver::additive_vcycle(const double* sig, T* rhsU, T* rhsV) {
     if (spd_) { a.mmode = L.finest ? M_IDENT : M_SHARED; a.Mv = vals<T>(L.B); }
     else { a.mmode = L.finest ? M_IDENT : M_CSR; a.Mrp = L.B.rp; a.avgM = avg_row(L.B); a.Mci = L.B.ci; a.Mv = vals<T>(L.B); }
     a.y = b.Ub; a.kap = kap; a.sig = sig; a.cmode = C_RESID; a.out = b.tU;
-    rowop(l, a, &L.A, 7);
-    spmm<T>(l, L.su.Pt, vals<T>(L.su.Pt), nb_, b.tU, cb.kap, 0.0);
-    if (!spd_) {
+    if (spd_) {
+      rowop(l, a, &L.A, 7);
+      spmm<T>(l, L.su.Pt, vals<T>(L.su.Pt), nb_, b.tU, cb.kap, 0.0);
+    } else {
+      // the two residuals, then the two restrictions, each pair in one launch
       RowOpArgs<T> s;
       s.nrows = mv; s.w = nb_; s.Krp = L.At.rp; s.Kci = L.At.ci; s.nnzK = L.At.nnz; s.Kv = vals<T>(L.At); s.z = b.Ub;
       s.mmode = L.finest ? M_IDENT : M_CSR; s.Mrp = L.C.rp; s.avgM = avg_row(L.C); s.Mci = L.C.ci; s.Mv = vals<T>(L.C);
       s.y = b.Vb; s.kap = tau; s.sig = sig; s.cmode = C_RESID; s.out = b.tV;
-      rowop(l, s, &L.At, 7);
-      spmm<T>(l, L.sv.Pt, vals<T>(L.sv.Pt), nb_, b.tV, cb.tau, 0.0);
+      rowop2(l, a, &L.A, s, &L.At, 7);
+      spmm2<T>(l, L.su.Pt, vals<T>(L.su.Pt), b.tU, cb.kap, L.sv.Pt, vals<T>(L.sv.Pt), b.tV, cb.tau, 0.0);
     }
     // zero initial coarse correction: written explicitly for Kaczmarz (it updates in place); the
     // Jacobi-type relaxation starts from zero without reading it, and the coarsest solve writes it
@@ -1394,8 +1429,8 @@ void Solver::additive_vcycle(const double* sig, T* rhsU, T* rhsV) {
     Level& C = *lv_[l + 1];
     Blocks<T>& b = blocks<T>(L);
     Blocks<T>& cb = blocks<T>(C);
-    spmm<T>(l, L.su.P, vals<T>(L.su.P), nb_, cb.Ub, b.Ub, 1.0);
-    if (!spd_) spmm<T>(l, L.sv.P, vals<T>(L.sv.P), nb_, cb.Vb, b.Vb, 1.0);
+    if (spd_) spmm<T>(l, L.su.P, vals<T>(L.su.P), nb_, cb.Ub, b.Ub, 1.0);
+    else spmm2<T>(l, L.su.P, vals<T>(L.su.P), cb.Ub, b.Ub, L.sv.P, vals<T>(L.sv.P), cb.Vb, b.Vb, 1.0);
     const T* kap = l == 0 ? rhsU : b.kap;
     const T* tau = l == 0 ? rhsV : b.tau;
     boot_relax<T>(l, kap, tau, sig, p_.mu_b);
@@ -1415,13 +1450,15 @@ void Solver::additive_iteration() {
   RowOpArgs<double> a;
   a.nrows = mu; a.w = nb_; a.Krp = L.A.rp; a.Kci = L.A.ci; a.nnzK = L.A.nnz; a.Kv = L.A.v; a.z = spd_ ? L.bd.Ub : L.bd.Vb;
   a.mmode = M_IDENT; a.y = L.bd.Ub; a.sig = sig_; a.cmode = C_RESID; a.out = L.bd.tU;
-  rowop(0, a, &L.A, 7);
-  launch_copy_cast_df(L.bd.tU, L.bf.kap, (size_t)mu * nb_, st_);
-  if (!spd_) {
+  if (spd_) {
+    rowop(0, a, &L.A, 7);
+    launch_copy_cast_df(L.bd.tU, L.bf.kap, (size_t)mu * nb_, st_);
+  } else {
     RowOpArgs<double> s;
     s.nrows = mv; s.w = nb_; s.Krp = L.At.rp; s.Kci = L.At.ci; s.nnzK = L.At.nnz; s.Kv = L.At.v; s.z = L.bd.Ub;
     s.mmode = M_IDENT; s.y = L.bd.Vb; s.sig = sig_; s.cmode = C_RESID; s.out = L.bd.tV;
-    rowop(0, s, &L.At, 7);
+    rowop2(0, a, &L.A, s, &L.At, 7);
+    launch_copy_cast_df(L.bd.tU, L.bf.kap, (size_t)mu * nb_, st_);
     launch_copy_cast_df(L.bd.tV, L.bf.tau, (size_t)mv * nb_, st_);
   }
   launch_fillf(L.bf.Ub, (size_t)(mu + (spd_ ? 0 : mv)) * nb_, 0.0f, st_);
@@ -1443,19 +1480,35 @@ void Solver::cholqr2(double* X, int rows, double* tmp, double* out) {
   launch_rotate<double>(rows, nb_, nb_, tmp, small1_, out, st_);
 }
 
+// The U- and V-side Cholesky-QR2 are independent: each of their steps runs both in one launch.
+void Solver::cholqr2_pair(double* Xa, int rows_a, double* tmpa, double* outa, double* Xb, int rows_b, double* tmpb,
+                          double* outb) {
+  const double bytes = 8.0 * ((double)rows_a + rows_b) * nb_;
+  prof(2, bytes, [&] {
+    launch_gram2(nb_, rows_a, Xa, Xa, partial_, gram_, rows_b, Xb, Xb, partial2_, gram2_, st_);
+  });
+  launch_chol_inv_upper2(nb_, gram_, small1_, gram2_, small3_, status_, st_);
+  launch_rotate2<double>(nb_, rows_a, Xa, small1_, tmpa, rows_b, Xb, small3_, tmpb, st_);
+  prof(2, bytes, [&] {
+    launch_gram2(nb_, rows_a, tmpa, tmpa, partial_, gram_, rows_b, tmpb, tmpb, partial2_, gram2_,
+                 st_);
+  });
+  launch_chol_inv_upper2(nb_, gram_, small1_, gram2_, small3_, status_, st_);
+  launch_rotate2<double>(nb_, rows_a, tmpa, small1_, outa, rows_b, tmpb, small3_, outb, st_);
+}
+
 void Solver::ritz() {
   Level& L = *lv_[0];
   auto& b = L.bd;
   const int mu = rows_u(L), mv = rows_v(L);
-  cholqr2(b.Ub, mu, b.tU, b.tU2);                 // U_hat in tU2
   if (!spd_) {
-    cholqr2(b.Vb, mv, b.tV, b.tV2);               // V_hat in tV2
+    cholqr2_pair(b.Ub, mu, b.tU, b.tU2, b.Vb, mv, b.tV, b.tV2);   // U_hat in tU2, V_hat in tV2
     spmm<double>(0, L.A, L.A.v, nb_, b.tV2, b.tU, 0.0);   // W = A V_hat
     prof(2, 16.0 * mu * nb_, [&] { launch_gram(mu, nb_, b.tU2, b.tU, partial_, gram_, st_); });                      // M = U_hat^t W
     launch_small_ritz(nb_, 0, minimal_, gram_, small1_, small2_, sig_, small_work_, status_, st_);
-    launch_rotate<double>(mu, nb_, nb_, b.tU2, small1_, b.Ub, st_);
-    launch_rotate<double>(mv, nb_, nb_, b.tV2, small2_, b.Vb, st_);
+    launch_rotate2<double>(nb_, mu, b.tU2, small1_, b.Ub, mv, b.tV2, small2_, b.Vb, st_);
   } else {
+    cholqr2(b.Ub, mu, b.tU, b.tU2);               // U_hat in tU2
     spmm<double>(0, L.A, L.A.v, nb_, b.tU2, b.tU, 0.0);   // A X_hat
     prof(2, 16.0 * mu * nb_, [&] { launch_gram(mu, nb_, b.tU2, b.tU, partial_, gram_, st_); });
     launch_small_ritz(nb_, 1, minimal_, gram_, small1_, small2_, sig_, small_work_, status_, st_);
@@ -1470,11 +1523,12 @@ void Solver::residual_launch() {
   DotArgs<double> d1, d2;
   d1.nrows = L.m; d1.w = nb_; d1.Krp = L.A.rp; d1.Kci = L.A.ci; d1.nnzK = L.A.nnz; d1.Kv = L.A.v;
   d1.z = spd_ ? b.Ub : b.Vb; d1.y = b.Ub; d1.sig = sig_;
-  dots(0, d1, &L.A, r1_);
-  if (!spd_) {
+  if (spd_) {
+    dots(0, d1, &L.A, r1_);
+  } else {
     d2.nrows = L.n; d2.w = nb_; d2.Krp = L.At.rp; d2.Kci = L.At.ci; d2.nnzK = L.At.nnz; d2.Kv = L.At.v;
     d2.z = b.Ub; d2.y = b.Vb; d2.sig = sig_;
-    dots(0, d2, &L.At, r2_);
+    launch_dots2(d1, partial_, r1_, d2, partial2_, r2_, st_);
   }
 }
 
@@ -1587,6 +1641,9 @@ void Solver::run(const double* init_tests, SolveOutput& out) {
   small_work_ = ar_.alloc<double>(4 * 32 * 32);
   status_ = ar_.alloc<int>(4);
   HIPCHK(hipMemsetAsync(status_, 0, 4 * sizeof(int), st_));
+  partial2_ = ar_.alloc<double>((size_t)std::max(1024 * 32, 512 * 256));
+  gram2_ = ar_.alloc<double>(256);
+  small3_ = ar_.alloc<double>(256);
   HIPCHK(hipMemsetAsync(sig_, 0, 64 * sizeof(double), st_));
   rep_.rows[0] = A0_.m; rep_.cols[0] = A0_.n; rep_.nnz[0] = A0_.nnz();
   pmask_ = p_.profile_mask;
