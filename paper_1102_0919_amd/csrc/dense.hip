@@ -278,138 +278,150 @@ void launch_chol_inv_upper2(int w, const double* G0, double* T0, const double* G
 }
 
 // ------------------------------------------------------------------------------------------------
-// Ritz problem on the finest level (§4.3).  Eigenproblem: M = V diag V^t, Y = V sorted.
-// SVD: eigen-decomposition of [[0, M], [M^t, 0]] whose eigenvalues are +-sigma (Theorem 3.2);
-// y and z of each sigma are read from the +sigma and -sigma eigenvectors, normalised, and signed
-// so that y^t M z >= 0.  Order: descending (dominant) or ascending (minimal).
-// work: >= 2 (2w)^2 doubles.
+// Ritz problem on the finest level (§4.3).  Eigenproblem: M = V diag V^t (M symmetrised), Y = V
+// sorted; order descending (dominant) or ascending (minimal).
 // ------------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(DBLK) void k_small_ritz(int w, int spd, int minimal, const double* M, double* Y,
-                                                     double* Z, double* sig, double* work, int* status) {
+__global__ __launch_bounds__(DBLK) void k_small_eig(int w, int minimal, const double* M, double* Y, double* sig) {
   __shared__ int ord[32];
   __shared__ double lam[32];
-  __shared__ double As[32 * 32], Vs[32 * 32];   // the (augmented) problem is at most 32 x 32
-  __shared__ double Ms[16 * 16], Ys[16 * 16], Zs[16 * 16], ss[16];
-  (void)work;
-  // the small serial steps below read and write LDS copies; results are stored at the end
-  for (int t = threadIdx.x; t < w * w; t += DBLK) Ms[t] = M[t];
-  wg_sync();
-  if (spd) {
-    double* A = As;
-    double* V = Vs;
-    for (int t = threadIdx.x; t < w * w; t += DBLK) {
-      int i = t / w, j = t % w;
-      A[t] = 0.5 * (Ms[i * w + j] + Ms[j * w + i]);
-    }
-    wg_jacobi<DBLK>(A, w, w, V, w, 60);
-    for (int i = threadIdx.x; i < w; i += DBLK) lam[i] = A[i * w + i];
-    wg_sync();
-    select_extremal<DBLK>(lam, w, w, !minimal, ord);
-    for (int t = threadIdx.x; t < w * w; t += DBLK) {
-      int i = t / w, k = t % w;
-      Y[i * w + k] = V[i * w + ord[k]];
-    }
-    for (int k = threadIdx.x; k < w; k += DBLK) sig[k] = lam[ord[k]];
-    return;
+  __shared__ double A[16 * 16], V[16 * 16];
+  for (int t = threadIdx.x; t < w * w; t += DBLK) {
+    int i = t / w, j = t % w;
+    A[t] = 0.5 * (M[i * w + j] + M[j * w + i]);
   }
-  const int n2 = 2 * w;
-  double* A = As;
-  double* V = Vs;
-  // Jacobi on V0^t [[0, M], [M^t, 0]] V0 with V0 = [[I, I], [I, -I]] / sqrt(2): this is diag(s, -s)
-  // when M is diagonal, and the Ritz matrix of nearly converged iterates is nearly diagonal, so
-  // the sweeps start close to the answer; the eigenvectors of the augmented matrix are V0 W.
-  const double h = 0.70710678118654752440;
-  for (int t = threadIdx.x; t < n2 * n2; t += DBLK) {
-    const int i = t / n2, j = t % n2;
-    const int i0 = i < w ? i : i - w, j0 = j < w ? j : j - w;
-    const double mij = Ms[i0 * w + j0], mji = Ms[j0 * w + i0];
-    double v;
-    if (i < w && j < w) v = 0.5 * (mij + mji);
-    else if (i < w) v = 0.5 * (mji - mij);
-    else if (j < w) v = 0.5 * (mij - mji);
-    else v = -0.5 * (mij + mji);
-    A[t] = v;
-    V[t] = i0 == j0 ? ((i >= w && j >= w) ? -h : h) : 0.0;
-  }
-  wg_jacobi<DBLK>(A, n2, n2, V, n2, 60, false);
-  for (int i = threadIdx.x; i < n2; i += DBLK) lam[i] = A[i * n2 + i];
+  wg_jacobi(A, w, w, V, w, 60);
+  for (int i = threadIdx.x; i < w; i += DBLK) lam[i] = A[i * w + i];
   wg_sync();
-  select_extremal<DBLK>(lam, n2, n2, true, ord);   // descending: +sigma_1 ... -sigma_1
-  // z_k: normalised lower part of the +sigma_k eigenvector (for sigma > 0 it holds half of the
-  // eigenvector's mass, and the lower parts of a degenerate eigenspace stay orthonormal);
-  // y_k = M z_k / sigma_k, so that (y_k, z_k) is consistent inside degenerate clusters.  For
-  // sigma_k ~ 0 the +-0 eigenvectors mix: y_k and z_k come from whichever of the two eigenvectors
-  // carries more mass in the respective part, and y_k is orthogonalised against the other y.
-  __shared__ int tinyk[16];
-  {
-    double smax = 0.0;
-    for (int k = 0; k < w; ++k) smax = fmax(smax, lam[ord[k]]);
-    // one thread per triplet k
-    if ((int)threadIdx.x < w) {
-      const int k = threadIdx.x;
-      const int kp = ord[k], km = ord[n2 - 1 - k];
-      double tp = 0.0, tm = 0.0, bp = 0.0, bm = 0.0;
-      for (int i = 0; i < w; ++i) {
-        tp += V[i * n2 + kp] * V[i * n2 + kp];
-        tm += V[i * n2 + km] * V[i * n2 + km];
-        bp += V[(w + i) * n2 + kp] * V[(w + i) * n2 + kp];
-        bm += V[(w + i) * n2 + km] * V[(w + i) * n2 + km];
+  select_extremal(lam, w, w, !minimal, ord);
+  for (int t = threadIdx.x; t < w * w; t += DBLK) {
+    int i = t / w, k = t % w;
+    Y[i * w + k] = V[i * w + ord[k]];
+  }
+  for (int k = threadIdx.x; k < w; k += DBLK) sig[k] = lam[ord[k]];
+}
+
+// SVD of the n_b x n_b Ritz matrix (§4.3) by one-sided (Hestenes) Jacobi on one wavefront: pairs of
+// columns of M, and of V (from I), are rotated until every pair is orthogonal to 1e-15 relative;
+// then sigma_k = ||M e_k||, z_k = V e_k, y_k = M z_k / sigma_k (so y_k^t M z_k = sigma_k >= 0).  An
+// n_b-column problem takes n_b - 1 rounds per sweep (the augmented 2 n_b form takes 2 n_b - 1).  Lane
+// l serves pair slot l / 8 on rows l % 8 and l % 8 + 8; the three sums of a pair meet by lane
+// shuffles.  Numerically zero sigma (<= 1e-13 sigma_max) get y completed to an orthonormal set.
+// Output: Y, Z (w x w row-major, column k the k-th triplet), sig; order descending (dominant) or
+// ascending (minimal).
+__global__ __launch_bounds__(64) void k_small_svd(int w, int minimal, const double* M, double* Y, double* Z,
+                                                  double* sig) {
+  __shared__ double Ms[16 * 16], Vs[16 * 16];   // row-major, ld 16, zero beyond w
+  __shared__ double Ys[16 * 16], Zs[16 * 16], ss[16], sg[16];
+  __shared__ int ord[32], tinyk[16];
+  const int lane = threadIdx.x;
+  for (int t = lane; t < 256; t += 64) {
+    const int i = t >> 4, j = t & 15;
+    Ms[t] = (i < w && j < w) ? M[i * w + j] : 0.0;
+    Vs[t] = (i == j && i < w) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int W = w + (w & 1), np = W / 2;
+  const int slot = lane >> 3, r = lane & 7;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    int rotated = 0;
+    for (int rr = 0; rr < W - 1; ++rr) {
+      int p = 0, q = 0;
+      if (slot < np) {
+        const int a = slot, b = W - 1 - slot;
+        int pp = a - 1 + rr, qq = b - 1 + rr;
+        pp = a == 0 ? 0 : (pp >= W - 1 ? pp - (W - 1) : pp) + 1;
+        qq = b == 0 ? 0 : (qq >= W - 1 ? qq - (W - 1) : qq) + 1;
+        p = pp < qq ? pp : qq;
+        q = pp < qq ? qq : pp;
       }
-      const double sk = fmax(lam[kp], 0.0);
-      const bool tiny = !(sk > 1e-13 * smax);
-      const int kz = (!tiny || bp >= bm) ? kp : km;
-      const double nz = sqrt(kz == kp ? bp : bm);
-      const int dst = minimal ? (w - 1 - k) : k;
-      for (int i = 0; i < w; ++i) Zs[i * w + dst] = V[(w + i) * n2 + kz] / nz;
-      if (!tiny) {
-        for (int i = 0; i < w; ++i) {
-          double s = 0.0;
-          for (int j = 0; j < w; ++j) s += Ms[i * w + j] * Zs[j * w + dst];
-          Ys[i * w + dst] = s;
-        }
-        double nrm = 0.0;   // normalise y (the columns of non-zero sigma are independent)
-        for (int i = 0; i < w; ++i) nrm += Ys[i * w + dst] * Ys[i * w + dst];
-        nrm = sqrt(nrm);
-        if (nrm > 0.0)
-          for (int i = 0; i < w; ++i) Ys[i * w + dst] /= nrm;
-      } else {
-        const int ky = tp >= tm ? kp : km;
-        for (int i = 0; i < w; ++i) Ys[i * w + dst] = V[i * n2 + ky];
+      const bool act = slot < np && q < w;   // the padding column (odd w) pairs with nothing
+      double mp0 = 0.0, mq0 = 0.0, mp1 = 0.0, mq1 = 0.0, vp0 = 0.0, vq0 = 0.0, vp1 = 0.0, vq1 = 0.0;
+      if (act) {
+        mp0 = Ms[r * 16 + p]; mq0 = Ms[r * 16 + q]; mp1 = Ms[(r + 8) * 16 + p]; mq1 = Ms[(r + 8) * 16 + q];
+        vp0 = Vs[r * 16 + p]; vq0 = Vs[r * 16 + q]; vp1 = Vs[(r + 8) * 16 + p]; vq1 = Vs[(r + 8) * 16 + q];
       }
-      ss[dst] = sk;
-      tinyk[dst] = tiny ? 1 : 0;
+      double al = mp0 * mp0 + mp1 * mp1, be = mq0 * mq0 + mq1 * mq1, ga = mp0 * mq0 + mp1 * mq1;
+#pragma unroll
+      for (int m = 1; m < 8; m <<= 1) {
+        al += __shfl_xor(al, m);
+        be += __shfl_xor(be, m);
+        ga += __shfl_xor(ga, m);
+      }
+      if (act && ga * ga > 1e-30 * al * be && fabs(ga) > 1e-300) {
+        const double zeta = (be - al) / (2.0 * ga);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + t * t), sn = t * c;
+        rotated = 1;
+        Ms[r * 16 + p] = c * mp0 - sn * mq0;
+        Ms[r * 16 + q] = sn * mp0 + c * mq0;
+        Ms[(r + 8) * 16 + p] = c * mp1 - sn * mq1;
+        Ms[(r + 8) * 16 + q] = sn * mp1 + c * mq1;
+        Vs[r * 16 + p] = c * vp0 - sn * vq0;
+        Vs[r * 16 + q] = sn * vp0 + c * vq0;
+        Vs[(r + 8) * 16 + p] = c * vp1 - sn * vq1;
+        Vs[(r + 8) * 16 + q] = sn * vp1 + c * vq1;
+      }
+      __syncthreads();
     }
-    wg_sync();
-    // for (numerically) zero sigma: orthogonalise y against the other columns, in column order,
-    // then normalise
-    if (threadIdx.x == 0) {
-      for (int k = 0; k < w; ++k) {
-        if (!tinyk[k]) continue;
-        for (int k2 = 0; k2 < w; ++k2) {
-          if (k2 == k || (tinyk[k2] && k2 > k)) continue;
-          double d = 0.0;
-          for (int i = 0; i < w; ++i) d += Ys[i * w + k] * Ys[i * w + k2];
-          for (int i = 0; i < w; ++i) Ys[i * w + k] -= d * Ys[i * w + k2];
-        }
+    if (__ballot(rotated) == 0) break;
+  }
+  if (lane < w) {
+    double s2 = 0.0;
+    for (int i = 0; i < w; ++i) s2 += Ms[i * 16 + lane] * Ms[i * 16 + lane];
+    sg[lane] = sqrt(s2);
+  }
+  select_extremal<64>(sg, w, w, true, ord);   // descending
+  const double smax = sg[ord[0]];
+  if (lane < w) {
+    const int src = ord[lane], dst = minimal ? (w - 1 - lane) : lane;
+    const double sk = sg[src];
+    const bool tiny = !(sk > 1e-13 * smax);
+    for (int i = 0; i < w; ++i) {
+      Zs[i * w + dst] = Vs[i * 16 + src];
+      Ys[i * w + dst] = tiny ? 0.0 : Ms[i * 16 + src] / sk;
+    }
+    ss[dst] = sk;
+    tinyk[dst] = tiny ? 1 : 0;
+  }
+  __syncthreads();
+  // zero sigma: y_k from the first unit vector that keeps norm > 1/2 after two Gram-Schmidt passes
+  // against the columns already set (column order)
+  if (lane == 0) {
+    for (int k = 0; k < w; ++k) {
+      if (!tinyk[k]) continue;
+      for (int e = 0; e < w; ++e) {
+        for (int i = 0; i < w; ++i) Ys[i * w + k] = i == e ? 1.0 : 0.0;
+        for (int pass = 0; pass < 2; ++pass)
+          for (int k2 = 0; k2 < w; ++k2) {
+            if (k2 == k || (tinyk[k2] && k2 > k)) continue;
+            double d = 0.0;
+            for (int i = 0; i < w; ++i) d += Ys[i * w + k] * Ys[i * w + k2];
+            for (int i = 0; i < w; ++i) Ys[i * w + k] -= d * Ys[i * w + k2];
+          }
         double nrm = 0.0;
         for (int i = 0; i < w; ++i) nrm += Ys[i * w + k] * Ys[i * w + k];
         nrm = sqrt(nrm);
-        if (nrm > 0.0)
+        if (nrm > 0.5) {
           for (int i = 0; i < w; ++i) Ys[i * w + k] /= nrm;
+          break;
+        }
       }
     }
   }
-  wg_sync();
-  for (int t = threadIdx.x; t < w * w; t += DBLK) {
+  __syncthreads();
+  for (int t = lane; t < w * w; t += 64) {
     Y[t] = Ys[t];
     Z[t] = Zs[t];
   }
-  for (int k = threadIdx.x; k < w; k += DBLK) sig[k] = ss[k];
+  if (lane < w) sig[lane] = ss[lane];
 }
 
 void launch_small_ritz(int w, int spd, int minimal, const double* M, double* Y, double* Z, double* sig, double* work,
                        int* status, hipStream_t s) {
-  hipLaunchKernelGGL(k_small_ritz, dim3(1), dim3(DBLK), 0, s, w, spd, minimal, M, Y, Z, sig, work, status);
+  (void)work;
+  (void)status;
+  if (spd) hipLaunchKernelGGL(k_small_eig, dim3(1), dim3(DBLK), 0, s, w, minimal, M, Y, sig);
+  else hipLaunchKernelGGL(k_small_svd, dim3(1), dim3(64), 0, s, w, minimal, M, Y, Z, sig);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -647,8 +659,9 @@ __global__ __launch_bounds__(PB) void k_pinv_solve(int N, int nb, const double* 
     //    in one step: W2 = I + K + K^2 / 2, eigenvalues d_q + sum_p E_pq K_pq.
     //  * kmax <= 1e-4 (and a fourth N x N array in LDS): a Newton-type step M <- W^t M W, Q <- Q W
     //    with W = I + K + K^2 / 2 (W^t W = I + K^4 / 4: orthogonal to rounding) leaves off-diagonal
-    //    entries of order kmax^2 relative to the gaps; repeat (at most three steps).
-    //  * otherwise Jacobi sweeps.
+    //    entries of order kmax^2 relative to the gaps; repeat.
+    //  * kmax > 1e-4 (with the fourth array): one Jacobi sweep, then test again.
+    //  * without the fourth array, or after three steps: Jacobi sweeps to convergence.
     double fro = 0.0;
     wg_for2<PB>(N, N, [&](int i, int c) {
       const double a = M[(long)i * N + c];
@@ -701,10 +714,19 @@ __global__ __launch_bounds__(PB) void k_pinv_solve(int N, int nb, const double* 
         });
         break;
       }
-      if (!Tm || kmax > 1e-4 || step == 3) {
+      if (!Tm || step == 3) {
         wg_jacobi<PB>(M, N, N, W2, N, 60);
         for (int i = threadIdx.x; i < N; i += PB) lam[i] = M[(long)i * N + i];
         break;
+      }
+      if (kmax > 1e-4) {
+        // one Jacobi sweep (roughly squares max |K|), Q <- Q W2, then test again
+        wg_jacobi<PB>(M, N, N, W2, N, 1);
+        wg_mm64<false, false>(Q, W2, Tm, N);
+        wg_sync();
+        for (long t = threadIdx.x; t < NN; t += PB) Q[t] = Tm[t];
+        wg_sync();
+        continue;
       }
       // W2 <- W = I + K + K^2 / 2 ; M <- W^t (M W) (symmetrised) ; Q <- Q W
       wg_mm64<false, false>(W2, W2, Tm, N);
