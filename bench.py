@@ -41,8 +41,8 @@ DEFAULT_WORKLOAD = "gradient2d_256_dom8"
 # for the kernel source the counters were taken with.
 TRAFFIC = {
     ("gradient2d_256_dom8", 0): dict(
-        kernels_sha256="cc55aa97debcf578e1928dca74c7bf26ac32d70d784ed82ac273103a3c9234c8",
-        fetch_kib=(12189.1, 10351.7), write_kib=(8160.0, 4096.0),
+        kernels_sha256="50dcd9d43647a68860a3bf435195b2520981b2b8797ce60ce7cc98bddc1aadbd",
+        fetch_kib=(12220.1, 10364.9), write_kib=(8160.0, 4096.0),
         copy_fetch_kib=524302.4, copy_write_kib=1048576.0, copy_bytes=1 << 30),
 }
 
