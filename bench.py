@@ -37,13 +37,13 @@ DEFAULT_WORKLOAD = "gradient2d_256_dom8"
 # HBM traffic of the dominant kernel class, from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs
 # (profiles/pmc_*_gradient2d_256_dom8.md), per dispatch in KiB for the two finest-level k_rowop
 # launch shapes (u rows, v rows), scaled by the same counters of a 1 GiB device copy
-# (profiles/pmc_*_copy_1GiB.md: FETCH 524302.4 KiB, WRITE 1048576.0 KiB per 1 GiB).  Valid only
+# (profiles/pmc_*_copy_1GiB.md: FETCH 524303.5 KiB, WRITE 1048576.0 KiB per 1 GiB).  Valid only
 # for the kernel source the counters were taken with.
 TRAFFIC = {
     ("gradient2d_256_dom8", 0): dict(
-        kernels_sha256="50dcd9d43647a68860a3bf435195b2520981b2b8797ce60ce7cc98bddc1aadbd",
-        fetch_kib=(12220.1, 10364.9), write_kib=(8160.0, 4096.0),
-        copy_fetch_kib=524302.4, copy_write_kib=1048576.0, copy_bytes=1 << 30),
+        kernels_sha256="caa935a6621bd8a58a3cd6fce183756abbfa245ee8ba6e685337a5b8a5901f61",
+        fetch_kib=(12216.1, 10360.9), write_kib=(8160.0, 4096.0),
+        copy_fetch_kib=524303.5, copy_write_kib=1048576.0, copy_bytes=1 << 30),
 }
 
 

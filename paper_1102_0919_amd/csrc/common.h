@@ -135,6 +135,11 @@ struct DotArgs {
 // launch (bitwise reproducible).
 template <typename T> void launch_dots(const DotArgs<T>& a, double* partial, double* out, hipStream_t s);
 int dots_grid(int nrows, int w);
+// largest reduction grids: a partial buffer of DOTS_MAX_GRID * 16 (dots) or GRAM_MAX_GRID * 256 (Gram)
+// doubles serves every launch
+constexpr int DOTS_MAX_GRID = 8192;
+constexpr int GRAM_MAX_GRID = 2048;
+constexpr size_t PARTIAL_DOUBLES = (size_t)GRAM_MAX_GRID * 256;
 
 void launch_gram(int rows, int w, const double* X, const double* Y, double* partial, double* G, hipStream_t s);
 // two independent reductions / Gram products in one launch (each with its own partials and output)

@@ -50,6 +50,17 @@ __device__ __forceinline__ T split_sum(T v, int lprc) {
   return v;
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin (XCD = id mod 8), and each XCD has its own L2.
+// The logical workgroup index gives XCD x one contiguous range of the grid, so that neighbouring
+// rows, and the rows they gather, meet in one L2.  A bijection of [0, gridDim.x).  Used by the
+// Kaczmarz sweep, whose updates re-read what neighbouring rows just wrote (5% faster on a 7-point
+// operator); the gather-only kernels measured 5% slower with it.
+__device__ __forceinline__ int xcd_block() {
+  const int b = blockIdx.x, nb = gridDim.x;
+  const int q = nb >> 3, r = nb & 7, x = b & 7, k = b >> 3;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
+}
+
 template <typename T, int CPL>
 __device__ __forceinline__ void ldrow(const T* __restrict__ p, int c0, int w, T (&v)[CPL]) {
   if constexpr (CPL == 2) {
@@ -175,8 +186,9 @@ __global__ __launch_bounds__(BLK) void k_spmm(SpmmPOD<T> a, int lshift) {
 // [0, nb0) run the first, the others the second, so the two latency chains overlap.
 template <typename T, int CPL, int SPLIT>
 __global__ __launch_bounds__(BLK) void k_spmm2(SpmmPOD<T> a, SpmmPOD<T> b, int lshift, int nb0) {
-  if ((int)blockIdx.x < nb0) spmm_body<T, CPL, SPLIT>(a, lshift, (long)blockIdx.x * BLK + threadIdx.x);
-  else spmm_body<T, CPL, SPLIT>(b, lshift, (long)(blockIdx.x - nb0) * BLK + threadIdx.x);
+  const int bk = (int)blockIdx.x;
+  if (bk < nb0) spmm_body<T, CPL, SPLIT>(a, lshift, (long)bk * BLK + threadIdx.x);
+  else spmm_body<T, CPL, SPLIT>(b, lshift, (long)(bk - nb0) * BLK + threadIdx.x);
 }
 
 #define SLAMG_DISPATCH_SPLIT(KER, T, CPL, SP, GRID, ...)                                        \
@@ -305,8 +317,9 @@ __global__ __launch_bounds__(BLK) void k_rowop(RowOpPOD<T> a, int lshift) {
 // workgroups [0, nb0) run the first, the others the second.
 template <typename T, int CPL, int SPLIT>
 __global__ __launch_bounds__(BLK) void k_rowop2(RowOpPOD<T> a, RowOpPOD<T> b, int lshift, int nb0) {
-  if ((int)blockIdx.x < nb0) rowop_body<T, CPL, SPLIT>(a, lshift, (long)blockIdx.x * BLK + threadIdx.x);
-  else rowop_body<T, CPL, SPLIT>(b, lshift, (long)(blockIdx.x - nb0) * BLK + threadIdx.x);
+  const int bk = (int)blockIdx.x;
+  if (bk < nb0) rowop_body<T, CPL, SPLIT>(a, lshift, (long)bk * BLK + threadIdx.x);
+  else rowop_body<T, CPL, SPLIT>(b, lshift, (long)(bk - nb0) * BLK + threadIdx.x);
 }
 
 template <typename T>
@@ -468,7 +481,7 @@ template <typename T, int CPL, int SPLIT>
 __global__ __launch_bounds__(BLK) void k_kacz(KaczPOD<T> a, int lshift) {
   constexpr int LS = SPLIT == 1 ? 0 : SPLIT == 4 ? 2 : SPLIT == 8 ? 3 : 4;
   const int gl = lshift + LS;
-  long t = (long)blockIdx.x * BLK + threadIdx.x;
+  long t = (long)xcd_block() * BLK + threadIdx.x;
   int idx = (int)(t >> gl);
   const int lane = (int)(t & ((1 << gl) - 1));
   const int sidx = lane >> lshift;
@@ -607,7 +620,7 @@ static void launch_finalize(const FinPOD& a, const FinPOD* b, hipStream_t s) {
 
 int dots_grid(int nrows, int w) {
   int sh = lshift_of(w);
-  return std::max(1, std::min(1024, ceil_div((long)nrows << sh, BLK)));
+  return std::max(1, std::min(DOTS_MAX_GRID, ceil_div((long)nrows << sh, BLK)));
 }
 
 template <typename T, int CPL, int SPLIT>
@@ -622,12 +635,15 @@ __device__ __forceinline__ void dots_body(const DotPOD<T>& a, int lshift, int bl
   double acc[CPL];
 #pragma unroll
   for (int c = 0; c < CPL; ++c) acc[c] = 0.0;
-  int stride = (nblk * BLK) >> gl;
+  // workgroup blk takes the contiguous rows [r0, r1), BLK >> gl rows per pass
+  const int per = BLK >> gl;
+  const long chunk = (((long)a.nrows + nblk - 1) / nblk + per - 1) / per * per;
+  const int r0 = (int)std::min((long)a.nrows, (long)blk * chunk), r1 = (int)std::min((long)a.nrows, (long)r0 + chunk);
   if (c0 < w) {
     double sc[CPL];
 #pragma unroll
     for (int c = 0; c < CPL; ++c) sc[c] = (a.sig && c0 + c < w) ? a.sig[c0 + c] : 0.0;
-    for (int row = (int)(((long)blk * BLK + threadIdx.x) >> gl); row < a.nrows; row += stride) {
+    for (int row = r0 + (int)(threadIdx.x >> gl); row < r1; row += per) {
       T yv[CPL], av[CPL];
       if (sidx == 0) {
         if (a.y) ldrow<T, CPL>(a.y + (long)row * w, c0, w, yv);
@@ -674,15 +690,16 @@ __device__ __forceinline__ void dots_body(const DotPOD<T>& a, int lshift, int bl
 template <typename T, int CPL, int SPLIT>
 __global__ __launch_bounds__(BLK) void k_dots(DotPOD<T> a, int lshift) {
   __shared__ double red[BLK * 2];
-  dots_body<T, CPL, SPLIT>(a, lshift, blockIdx.x, gridDim.x, red);
+  dots_body<T, CPL, SPLIT>(a, lshift, (int)blockIdx.x, gridDim.x, red);
 }
 
 // two independent reductions (same w) in one launch: workgroups [0, nb0) take the first
 template <typename T, int CPL, int SPLIT>
 __global__ __launch_bounds__(BLK) void k_dots2(DotPOD<T> a, DotPOD<T> b, int lshift, int nb0) {
   __shared__ double red[BLK * 2];
-  if ((int)blockIdx.x < nb0) dots_body<T, CPL, SPLIT>(a, lshift, blockIdx.x, nb0, red);
-  else dots_body<T, CPL, SPLIT>(b, lshift, blockIdx.x - nb0, gridDim.x - nb0, red);
+  const int bk = (int)blockIdx.x;
+  if (bk < nb0) dots_body<T, CPL, SPLIT>(a, lshift, bk, nb0, red);
+  else dots_body<T, CPL, SPLIT>(b, lshift, bk - nb0, gridDim.x - nb0, red);
 }
 
 template <typename T>
@@ -726,7 +743,8 @@ void launch_dots2(const DotArgs<T>& a, double* pa, double* oa, const DotArgs<T>&
 // ------------------------------------------------------------------------------------------------
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-int gram_grid(int rows) { return std::max(1, std::min(512, ceil_div(rows, 4 * 4 * 16))); }
+// one 64-row pass per workgroup (4 waves x 16 rows) up to GRAM_MAX_GRID workgroups
+int gram_grid(int rows) { return std::max(1, std::min(GRAM_MAX_GRID, ceil_div(rows, 64))); }
 
 struct GramPOD {
   int rows, w;
@@ -738,15 +756,18 @@ __device__ __forceinline__ void gram_body(const GramPOD& a, int blk, int nblk, d
   const double* __restrict__ X = a.X;
   const double* __restrict__ Y = a.Y;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int gw = blk * 4 + wv, nw = nblk * 4;
   const int i = lane & 15, kk = lane >> 4;
+  // workgroup blk takes the contiguous rows [b0, b1) in passes of 64 (16 per wave)
+  const long chunk = (((long)rows + nblk - 1) / nblk + 63) / 64 * 64;
+  const long b0 = std::min((long)rows, (long)blk * chunk), b1 = std::min((long)rows, b0 + chunk);
   v4d acc = {0.0, 0.0, 0.0, 0.0};
-  for (long r0 = (long)gw * 16; r0 < rows; r0 += (long)nw * 16) {
+#pragma unroll 2
+  for (long r0 = b0 + wv * 16; r0 < b1; r0 += 64) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       long r = r0 + u * 4 + kk;
       double av = 0.0, bv = 0.0;
-      if (r < rows && i < w) { av = X[r * w + i]; bv = Y[r * w + i]; }
+      if (r < b1 && i < w) { av = X[r * w + i]; bv = Y[r * w + i]; }
       acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
     }
   }
@@ -759,14 +780,15 @@ __device__ __forceinline__ void gram_body(const GramPOD& a, int blk, int nblk, d
 
 __global__ __launch_bounds__(BLK) void k_gram(GramPOD a) {
   __shared__ double red[4][256];
-  gram_body(a, blockIdx.x, gridDim.x, red);
+  gram_body(a, (int)blockIdx.x, gridDim.x, red);
 }
 
 // two independent Gram products in one launch: workgroups [0, nb0) take the first
 __global__ __launch_bounds__(BLK) void k_gram2(GramPOD a, GramPOD b, int nb0) {
   __shared__ double red[4][256];
-  if ((int)blockIdx.x < nb0) gram_body(a, blockIdx.x, nb0, red);
-  else gram_body(b, blockIdx.x - nb0, gridDim.x - nb0, red);
+  const int bk = (int)blockIdx.x;
+  if (bk < nb0) gram_body(a, bk, nb0, red);
+  else gram_body(b, bk - nb0, gridDim.x - nb0, red);
 }
 
 void launch_gram(int rows, int w, const double* X, const double* Y, double* partial, double* G, hipStream_t s) {
@@ -808,7 +830,7 @@ template <typename T>
 __global__ __launch_bounds__(BLK) void k_rotate(int rows, int win, int wout, const T* __restrict__ X,
                                                 const double* __restrict__ S, T* __restrict__ out) {
   __shared__ double Ss[16 * 16];
-  rotate_body<T>(rows, win, wout, X, S, out, blockIdx.x, Ss);
+  rotate_body<T>(rows, win, wout, X, S, out, (int)blockIdx.x, Ss);
 }
 
 // the U- and V-side rotations (w x w) in one launch: workgroups [0, nb0) take the first
@@ -818,8 +840,9 @@ __global__ __launch_bounds__(BLK) void k_rotate2(int w, int rows_a, const T* __r
                                                  const T* __restrict__ Xb, const double* __restrict__ Sb,
                                                  T* __restrict__ outb, int nb0) {
   __shared__ double Ss[16 * 16];
-  if ((int)blockIdx.x < nb0) rotate_body<T>(rows_a, w, w, Xa, Sa, outa, blockIdx.x, Ss);
-  else rotate_body<T>(rows_b, w, w, Xb, Sb, outb, blockIdx.x - nb0, Ss);
+  const int bk = (int)blockIdx.x;
+  if (bk < nb0) rotate_body<T>(rows_a, w, w, Xa, Sa, outa, bk, Ss);
+  else rotate_body<T>(rows_b, w, w, Xb, Sb, outb, bk - nb0, Ss);
 }
 
 template <typename T>

@@ -88,7 +88,7 @@ void jac_half(hipStream_t s, Tmp& t, int rows, int w, const int* krp, const int*
   if (mmode == M_CSR && rows > 0) a.avgM = (double)dev_nnz(mrp, rows, s) / rows;
   launch_rowop(a, s);
   if (normalise) {
-    double* part = t.get<double>(1024 * 16);
+    double* part = t.get<double>((size_t)DOTS_MAX_GRID * 16);
     double* nrm = t.get<double>(16);
     DotArgs<double> d;
     d.nrows = rows; d.w = w; d.a = out; d.z = out;
@@ -213,7 +213,7 @@ extern "C" slamg_status slamg_op_dots(int32_t nrows, int32_t w, const double* d_
   hipStream_t s = (hipStream_t)stream;
   return guarded(s, [&] {
     Tmp t;
-    double* part = t.get<double>(1024 * 16);
+    double* part = t.get<double>((size_t)DOTS_MAX_GRID * 16);
     double* out = t.get<double>(16);
     DotArgs<double> d;
     d.nrows = nrows; d.w = w; d.a = d_a; d.Krp = d_krp; d.Kci = d_kci; d.Kv = d_kv; d.z = d_z; d.y = d_y;

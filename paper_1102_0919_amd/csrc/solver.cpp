@@ -1632,7 +1632,7 @@ void Solver::run(const double* init_tests, SolveOutput& out) {
   if (nb_ > 16 || nt_ > 16) throw SolverError{ST_E_INVALID, "n_b and n_t must be at most 16"};
   sig_ = ar_.alloc<double>(64);
   flip_ = ar_.alloc<double>(64);
-  partial_ = ar_.alloc<double>((size_t)std::max(1024 * 32, 512 * 256));
+  partial_ = ar_.alloc<double>(PARTIAL_DOUBLES);
   r1_ = ar_.alloc<double>(64); r2_ = ar_.alloc<double>(64); r3_ = ar_.alloc<double>(64);
   wts_ = ar_.alloc<double>(64);
   gram_ = ar_.alloc<double>(256);
@@ -1641,7 +1641,7 @@ void Solver::run(const double* init_tests, SolveOutput& out) {
   small_work_ = ar_.alloc<double>(4 * 32 * 32);
   status_ = ar_.alloc<int>(4);
   HIPCHK(hipMemsetAsync(status_, 0, 4 * sizeof(int), st_));
-  partial2_ = ar_.alloc<double>((size_t)std::max(1024 * 32, 512 * 256));
+  partial2_ = ar_.alloc<double>(PARTIAL_DOUBLES);
   gram2_ = ar_.alloc<double>(256);
   small3_ = ar_.alloc<double>(256);
   HIPCHK(hipMemsetAsync(sig_, 0, 64 * sizeof(double), st_));
