@@ -117,8 +117,9 @@ slamg_status slamg_op_coarse_gsvd(int32_t spd, int32_t minimal, int32_t mL, int3
  * variants 2, 3 and 4 are variant 0 computed the way consecutive additive iterations compute it,
  * starting from the eigenvectors of X - sig'_j Y at sig'_j = sig_j (1 + delta): delta = 1e-6
  * (variant 2: Newton-type steps when N <= 64, else Jacobi sweeps), 1e-12 (variant 3: the
- * first-order update) or 1e-3 (variant 4: Jacobi sweeps).  Returns SLAMG_E_INVALID for another
- * variant or N outside [1, 1024].
+ * first-order update) or 1e-3 (variant 4: Jacobi sweeps); variant 5 is variant 2 with the basis
+ * re-orthonormalised first (one Newton-Schulz step, as every 32nd additive iteration does).  Returns
+ * SLAMG_E_INVALID for another variant or N outside [1, 1024].
  * Host dense inputs X, Y (N x N), h_rhs / h_out (N x nb) row-major. */
 slamg_status slamg_op_coarse_solve(int32_t variant, int32_t N, int32_t nb, const double* h_x, const double* h_y,
                                    const double* h_sig, const double* h_rhs, double* h_out);

@@ -556,9 +556,10 @@ void launch_coarse_gsvd(int spd, int minimal, int mL, int nL, int nb, double* A,
 // Additive coarsest solve (§4.2), one workgroup per column j: M = X - sigma_j Y is symmetric, so
 // its SVD is its eigen-decomposition with |eigenvalues|; the pseudo-inverse without the smallest
 // singular component is sum_{i != i*} q_i q_i^t / lambda_i, i* = argmin |lambda_i|.
-// basis (nb N^2) holds each column's eigenvectors Q_j.  Cold: Jacobi on M from the identity.  Warm:
-// sigma_j moved little since Q_j was computed, so Q_j^t M Q_j is nearly diagonal; Jacobi (or the
-// first-order update below) finishes it and Q_j <- Q_j V.  Both give the eigen-decomposition of M to
+// basis (nb N^2) holds each column's eigenvectors Q_j.  warm = 0 (cold): Jacobi on M from the
+// identity.  warm = 1: sigma_j moved little since Q_j was computed, so Q_j^t M Q_j is nearly
+// diagonal; the updates below finish it and Q_j <- Q_j V.  warm = 2: as 1 after re-orthonormalising
+// Q_j (cold where the fourth LDS array is not available).  All give the eigen-decomposition of M to
 // rounding.  rhs / out: N x nb row-major.  work: nb * 2 N^2 doubles.
 //
 // The workgroup has 1024 threads: a Jacobi round is a chain of dependent LDS updates, and only nb
@@ -629,13 +630,27 @@ __global__ __launch_bounds__(PB) void k_pinv_solve(int N, int nb, const double* 
   __shared__ double red[PB];
   __shared__ int imin;
   const double s = sig[j];
-  if (!warm) {
+  if (!warm || (warm == 2 && !Tm)) {
     for (long t = threadIdx.x; t < NN; t += PB) M[t] = X[t] - s * Y[t];
     wg_jacobi<PB>(M, N, N, Q, N, 60);
     for (int i = threadIdx.x; i < N; i += PB) lam[i] = M[(long)i * N + i];
   } else {
     if constexpr (lds_mode == 2)
       for (long t = threadIdx.x; t < NN; t += PB) Q[t] = Qg[t];
+    if (warm == 2) {
+      // one Newton-Schulz step Q <- Q (3 I - Q^t Q) / 2: the products of many warm updates leave Q
+      // orthogonal only to rounding accumulated over the calls; this takes it back to rounding
+      wg_sync();
+      wg_mm64<true, false>(Q, Q, Tm, N);
+      wg_sync();
+      wg_for2<PB>(N, N, [&](int i, int c) {
+        Tm[(long)i * N + c] = (i == c ? 1.5 : 0.0) - 0.5 * Tm[(long)i * N + c];
+      });
+      wg_sync();
+      wg_mm64<false, false>(Q, Tm, W2, N);
+      wg_sync();
+      for (long t = threadIdx.x; t < NN; t += PB) Q[t] = W2[t];
+    }
     // M = X - s Y ; W2 = M Q ; M = Q^t W2 (symmetrised)
     for (long t = threadIdx.x; t < NN; t += PB) M[t] = X[t] - s * Y[t];
     wg_sync();

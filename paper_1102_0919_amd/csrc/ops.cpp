@@ -373,7 +373,7 @@ extern "C" slamg_status slamg_op_coarse_gsvd(int32_t spd, int32_t minimal, int32
 extern "C" slamg_status slamg_op_coarse_solve(int32_t variant, int32_t N, int32_t nb, const double* h_x,
                                               const double* h_y, const double* h_sig, const double* h_rhs,
                                               double* h_out) {
-  if (N < 1 || N > 1024 || nb < 1 || nb > 16 || (variant < 0 || variant > 4)) return SLAMG_E_INVALID;
+  if (N < 1 || N > 1024 || nb < 1 || nb > 16 || (variant < 0 || variant > 5)) return SLAMG_E_INVALID;
   hipStream_t s = nullptr;
   return guarded(s, [&] {
     Tmp t;
@@ -394,14 +394,14 @@ extern "C" slamg_status slamg_op_coarse_solve(int32_t variant, int32_t N, int32_
       const bool warm = variant >= 2;
       if (warm) {
         // warm start: eigenvectors of X - sigma'_j Y at sigma'_j = sigma_j (1 + delta) first
-        const double delta = variant == 2 ? 1e-6 : variant == 3 ? 1e-12 : 1e-3;
+        const double delta = (variant == 2 || variant == 5) ? 1e-6 : variant == 3 ? 1e-12 : 1e-3;
         double* sig2 = t.get<double>(nb);
         std::vector<double> h2(h_sig, h_sig + nb);
         for (auto& v : h2) v *= 1.0 + delta;
         up(sig2, h2.data(), nb, s);
         launch_pinv_solve(N, nb, X, Y, sig2, rhs, out, work, basis, 0, status, s);
       }
-      launch_pinv_solve(N, nb, X, Y, sig, rhs, out, work, basis, warm ? 1 : 0, status, s);
+      launch_pinv_solve(N, nb, X, Y, sig, rhs, out, work, basis, warm ? (variant == 5 ? 2 : 1) : 0, status, s);
     } else {
       double* mu = t.get<double>(N);
       double* Z = t.get<double>((size_t)N * N);

@@ -1418,7 +1418,10 @@ void Solver::additive_vcycle(const double* sig, T* rhsU, T* rhsV) {
     }
     if (p_.coarse_pinv == 0) {
       // the eigenvectors of the previous call start the next one; a cold start every 32 calls
-      const int warm = (pinv_calls_++ % 32) != 0;   // pinv_calls_ equals the iteration index
+      // the first call of the additive phase starts cold; every 32nd re-orthonormalises the basis
+      // (pinv_calls_ equals the iteration index)
+      const long c = pinv_calls_++;
+      const int warm = c == 0 ? 0 : (c % 32) == 0 ? 2 : 1;
       prof(4, 0.0, [&] { launch_pinv_solve(NL_, nb_, dX_, dY_, sig, rhs, sol, dwork_, pbasis_, warm, status_, st_); });
     }
     else prof(4, 0.0, [&] { launch_pencil_solve(NL_, nb_, mu_, Zp_, sig, rhs, sol, st_); });
@@ -1701,9 +1704,9 @@ void Solver::run(const double* init_tests, SolveOutput& out) {
   int it = 0;
   graph_off_ = !p_.graphs;
   while (rmax > p_.tol && it < p_.max_add) {
-    // every 32nd iteration runs eagerly: the literal coarsest solve restarts its eigensolve cold
-    // there (one call per iteration), and the profiled kernel classes are timed there; the other
-    // iterations replay the graph (captured with the warm start)
+    // every 32nd iteration runs eagerly: the literal coarsest solve re-orthonormalises its
+    // eigenvector basis there (starts cold in iteration 0), and the profiled kernel classes are
+    // timed there; the other iterations replay the graph (captured with the plain warm start)
     const bool eager = (it % 32) == 0;
     if (!eager && !graph_off_ && !igx_) capture_iteration();
     const bool replay = !eager && igx_ != nullptr;

@@ -316,7 +316,8 @@ def test_coarse_gsvd_parity(L, kind, target):
             assert np.allclose(hv[:, j] * s, Vo[:, j], atol=1e-7)
 
 
-@pytest.mark.parametrize("variant,m,n", [(0, 30, 20), (1, 30, 20), (2, 30, 20), (3, 30, 20), (4, 30, 20), (2, 34, 30),
+@pytest.mark.parametrize("variant,m,n", [(0, 30, 20), (1, 30, 20), (2, 30, 20), (3, 30, 20), (4, 30, 20), (5, 30, 20),
+                                         (5, 60, 40), (2, 34, 30),
                                          (3, 33, 30), (4, 34, 30), (2, 40, 25), (3, 40, 25), (0, 60, 40), (2, 60, 40),
                                          (3, 60, 40), (4, 60, 40), (0, 120, 90), (2, 120, 90), (3, 120, 90),
                                          (1, 120, 90)])
@@ -337,18 +338,18 @@ def test_coarse_solve_parity(L, variant, m, n):
     # one shift next to a generalized singular value: X - sigma Y nearly singular there
     sig = np.array([mu[-1] * (1 + 1e-9), 0.7, 1.3, 2.1])
     rhs = rng.normal(size=(m + n, 4))
-    if variant in (2, 3, 4):
+    if variant in (2, 3, 4, 5):
         # the inputs take the intended branch: in the eigenbasis at sigma (1 + delta), the largest
         # first-order ratio |E_pq| / |d_q - d_p| is far inside 2^-26 (variant 3), inside 1e-4
         # (variant 2) or above it (variant 4)
-        delta = {2: 1e-6, 3: 1e-12, 4: 1e-3}[variant]
+        delta = {2: 1e-6, 3: 1e-12, 4: 1e-3, 5: 1e-6}[variant]
         worst = 0.0
         for s in sig:
             lam2, Q2 = np.linalg.eigh(X - s * (1 + delta) * Y)
             Mq = Q2.T @ (X - s * Y) @ Q2
             gap = np.abs(lam2[:, None] - lam2[None, :]) + np.eye(m + n)
             worst = max(worst, (np.abs(Mq - np.diag(np.diag(Mq))) / gap).max())
-        assert {2: 1e-7 < worst < 1e-4, 3: worst < 2.0 ** -30, 4: worst > 1e-3}[variant], worst
+        assert {2: 1e-7 < worst < 1e-4, 3: worst < 2.0 ** -30, 4: worst > 1e-3, 5: 1e-7 < worst < 1e-4}[variant], worst
     ref = (O.coarse_pencil_solve if variant == 1 else O.coarse_pinv_solve)(X, Y, sig, rhs)
     out = np.zeros_like(rhs)
     assert L.slamg_op_coarse_solve(variant, m + n, 4, hp(np.ascontiguousarray(X)), hp(np.ascontiguousarray(Y)),
