@@ -1536,13 +1536,12 @@ void Solver::residual_launch() {
 }
 
 void Solver::residual_collect(std::vector<double>& rho) {
-  std::vector<double> h1, h2;
-  d2h(h1, r1_, nb_, st_);
-  if (!spd_) d2h(h2, r2_, nb_, st_);
+  std::vector<double> h;
+  d2h(h, r1_, spd_ ? (size_t)nb_ : (size_t)64 + nb_, st_);   // r1_[0..nb) and r2_ = r1_ + 64
   rho.resize(nb_);
   for (int j = 0; j < nb_; ++j) {
-    double r = std::sqrt(std::max(h1[j], 0.0));
-    if (!spd_) r = std::max(r, std::sqrt(std::max(h2[j], 0.0)));
+    double r = std::sqrt(std::max(h[j], 0.0));
+    if (!spd_) r = std::max(r, std::sqrt(std::max(h[64 + j], 0.0)));
     rho[j] = r / anorm_;
     if (!std::isfinite(rho[j])) throw SolverError{ST_E_NUMERIC, "non-finite residual"};
   }
@@ -1636,7 +1635,8 @@ void Solver::run(const double* init_tests, SolveOutput& out) {
   sig_ = ar_.alloc<double>(64);
   flip_ = ar_.alloc<double>(64);
   partial_ = ar_.alloc<double>(PARTIAL_DOUBLES);
-  r1_ = ar_.alloc<double>(64); r2_ = ar_.alloc<double>(64); r3_ = ar_.alloc<double>(64);
+  // r1_, r2_, r3_ adjacent: the residual norms of both sides come back in one copy
+  r1_ = ar_.alloc<double>(3 * 64); r2_ = r1_ + 64; r3_ = r1_ + 128;
   wts_ = ar_.alloc<double>(64);
   gram_ = ar_.alloc<double>(256);
   small1_ = ar_.alloc<double>(256);
