@@ -74,7 +74,7 @@ typedef struct {
   double omega_J;           /* weighted-Jacobi weight of §3.4 (0.7)                             */
   int32_t n_mult;           /* multiplicative cycles (10)                                       */
   int32_t max_add;          /* maximum additive iterations (200)                                */
-  int32_t coarse_max;       /* coarsest-level size: n (eigen) or m+n (SVD) at most this (128)    */
+  int32_t coarse_max;       /* coarsest-level size: n (eigen) or m+n (SVD) at most this (64)     */
   int32_t max_levels;       /* (25)                                                            */
   double stall_ratio;       /* stop coarsening when the coarse level keeps more (0.9)           */
   double tol;               /* relative residual tolerance (1e-8)                               */

@@ -81,7 +81,7 @@ class Params:
     omega: float = 0.7            # omega_J, §3.4
     n_mult: int = 10
     max_add: int = 200
-    coarse_max: int = 128
+    coarse_max: int = 64
     max_levels: int = 25
     stall_ratio: float = 0.9
     tol: float = 1e-8

@@ -90,7 +90,7 @@ extern "C" slamg_status slamg_params_init(slamg_params* p, slamg_kind kind, slam
   p->omega_J = 0.7;
   p->n_mult = 10;
   p->max_add = 200;
-  p->coarse_max = 128;
+  p->coarse_max = 64;
   p->max_levels = 25;
   p->stall_ratio = 0.9;
   p->tol = 1e-8;

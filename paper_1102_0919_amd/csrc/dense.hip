@@ -116,7 +116,7 @@ __device__ static void wg_transpose(const double* A, int r, int c, int lda, doub
 // and an indefinite matrix would keep producing such noise under the relative test alone.
 // Inlined at each call so that the compiler sees where A and V live (LDS or global memory) and
 // emits LDS instructions for LDS-resident matrices; the procedure is latency-bound.
-template <int BS = DBLK>
+template <int BS = DBLK, bool VGLOBAL = false>
 __device__ static __forceinline__ void wg_jacobi(double* A, int n, int ld, double* V, int ldv, int maxsweep,
                                                  bool init_v = true) {
   __shared__ int P[MAXPAIR], Q[MAXPAIR];
@@ -186,14 +186,47 @@ __device__ static __forceinline__ void wg_jacobi(double* A, int n, int ld, doubl
         A[(long)qa * ld + pb] = cb * r10 - sb * r11;
         A[(long)qa * ld + qb] = sb * r10 + cb * r11;
       });
-      // V <- V R^t
-      wg_for2<BS>(npair, n, [&](int b, int i) {
-        const int pb = P[b], qb = Q[b];
-        const double cb = Cs[b], sb = Sn[b];
-        const double vip = V[(long)i * ldv + pb], viq = V[(long)i * ldv + qb];
-        V[(long)i * ldv + pb] = cb * vip - sb * viq;
-        V[(long)i * ldv + qb] = sb * vip + cb * viq;
-      });
+      // V <- V R^t.  A round's pairs are disjoint, so a thread's updates are independent; with V in
+      // global memory (VGLOBAL) its loads go out first, four pairs at a time, then the updates, where
+      // a load -> store chain per pair would serialise the round.
+      if (VGLOBAL && n <= BS) {
+        const int gv = BS / n, i = (int)threadIdx.x % n, g = (int)threadIdx.x / n;
+        if (g < gv) {
+          for (int b0 = g; b0 < npair; b0 += 4 * gv) {
+            int pb[4], qb[4];
+            double vp[4], vq[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int b = b0 + u * gv;
+              pb[u] = qb[u] = -1;
+              vp[u] = vq[u] = 0.0;
+              if (b < npair) {
+                pb[u] = P[b];
+                qb[u] = Q[b];
+                vp[u] = V[(long)i * ldv + pb[u]];
+                vq[u] = V[(long)i * ldv + qb[u]];
+              }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int b = b0 + u * gv;
+              if (b < npair) {
+                const double cb = Cs[b], sb = Sn[b];
+                V[(long)i * ldv + pb[u]] = cb * vp[u] - sb * vq[u];
+                V[(long)i * ldv + qb[u]] = sb * vp[u] + cb * vq[u];
+              }
+            }
+          }
+        }
+      } else {
+        wg_for2<BS>(npair, n, [&](int b, int i) {
+          const int pb = P[b], qb = Q[b];
+          const double cb = Cs[b], sb = Sn[b];
+          const double vip = V[(long)i * ldv + pb], viq = V[(long)i * ldv + qb];
+          V[(long)i * ldv + pb] = cb * vip - sb * viq;
+          V[(long)i * ldv + qb] = sb * vip + cb * viq;
+        });
+      }
       wg_sync();
     }
     const int any = rotated, big = large;
@@ -433,7 +466,29 @@ void launch_small_ritz(int w, int spd, int minimal, const double* M, double* Y, 
 // Output U (mL x nb), V (nL x nb) row-major, sig (nb).
 // work: >= 3 max(mL,nL)^2 + 2 mL nL + 2 max doubles.
 // ------------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(DBLK) void k_coarse_gsvd(int spd, int minimal, int mL, int nL, int nb, double* A,
+// The coarsest generalized SVD runs on 1024 threads: its Jacobi rounds and its O(n) factorisation
+// steps are chains of dependent updates, and only one workgroup runs.
+static constexpr int GB = 1024;
+
+// Jacobi on the n x n matrix S (row-major, global memory), eigenvectors into V; with LDSJ the
+// rotations run on an LDS copy of S, which is written back.
+template <bool LDSJ>
+__device__ __forceinline__ void jacobi_lds(double* S, int n, double* V) {
+  if constexpr (LDSJ) {
+    extern __shared__ double jdyn[];
+    wg_sync();
+    for (long t = threadIdx.x; t < (long)n * n; t += GB) jdyn[t] = S[t];
+    wg_sync();
+    wg_jacobi<GB, true>(jdyn, n, n, V, n, 60);
+    for (long t = threadIdx.x; t < (long)n * n; t += GB) S[t] = jdyn[t];
+    wg_sync();
+  } else {
+    wg_jacobi<GB, true>(S, n, n, V, n, 60);
+  }
+}
+
+template <bool LDSJ>
+__global__ __launch_bounds__(GB) void k_coarse_gsvd(int spd, int minimal, int mL, int nL, int nb, double* A,
                                                       double* B, double* C, double* work, double* sig, double* U,
                                                       double* V, int* status) {
   __shared__ int info;
@@ -446,28 +501,28 @@ __global__ __launch_bounds__(DBLK) void k_coarse_gsvd(int spd, int minimal, int 
     double* D = work + (long)n * n;    // n x n
     double* W = work + 2L * n * n;     // n x n
     double* lam = work + 3L * n * n;   // n
-    wg_chol(B, n, n, &info);
-    for (long t = threadIdx.x; t < (long)n * n; t += DBLK) T1[t] = A[t];
-    wg_trsm_lower(B, n, n, T1, n, n);           // T1 = L^-1 A
-    wg_transpose(T1, n, n, n, D, n);           // D = (L^-1 A)^t = A L^-t
-    wg_trsm_lower(B, n, n, D, n, n);            // D = L^-1 A L^-t
-    for (long t = threadIdx.x; t < (long)n * n; t += DBLK) {
+    wg_chol<GB>(B, n, n, &info);
+    for (long t = threadIdx.x; t < (long)n * n; t += GB) T1[t] = A[t];
+    wg_trsm_lower<GB>(B, n, n, T1, n, n);           // T1 = L^-1 A
+    wg_transpose<GB>(T1, n, n, n, D, n);           // D = (L^-1 A)^t = A L^-t
+    wg_trsm_lower<GB>(B, n, n, D, n, n);            // D = L^-1 A L^-t
+    for (long t = threadIdx.x; t < (long)n * n; t += GB) {
       int i = (int)(t / n), j = (int)(t % n);
       if (j > i) {
         double s = 0.5 * (D[(long)i * n + j] + D[(long)j * n + i]);
         D[(long)i * n + j] = s; D[(long)j * n + i] = s;
       }
     }
-    wg_jacobi(D, n, n, W, n, 60);
-    for (int i = threadIdx.x; i < n; i += DBLK) lam[i] = D[(long)i * n + i];
+    jacobi_lds<LDSJ>(D, n, W);
+    for (int i = threadIdx.x; i < n; i += GB) lam[i] = D[(long)i * n + i];
     wg_sync();
-    select_extremal(lam, n, nb, !minimal, ord);
-    for (long t = threadIdx.x; t < (long)n * nb; t += DBLK) {
+    select_extremal<GB>(lam, n, nb, !minimal, ord);
+    for (long t = threadIdx.x; t < (long)n * nb; t += GB) {
       int i = (int)(t / nb), k = (int)(t % nb);
       U[t] = W[(long)i * n + ord[k]];
     }
-    wg_trsm_lower_t(B, n, n, U, nb, nb);        // x = L^-t w
-    for (int k = threadIdx.x; k < nb; k += DBLK) sig[k] = lam[ord[k]];
+    wg_trsm_lower_t<GB>(B, n, n, U, nb, nb);        // x = L^-t w
+    for (int k = threadIdx.x; k < nb; k += GB) sig[k] = lam[ord[k]];
     if (threadIdx.x == 0 && info) *status = ST_E_NUMERIC;
     return;
   }
@@ -479,33 +534,33 @@ __global__ __launch_bounds__(DBLK) void k_coarse_gsvd(int spd, int minimal, int 
   double* Tm = W + (long)n * n;            // m x nb  (t vectors)
   double* lam = Tm + (long)m * 64;         // n
   (void)mx;
-  wg_chol(B, m, m, &info);
-  wg_chol(C, n, n, &info);
-  wg_trsm_lower(B, m, m, A, n, n);             // A <- L_B^-1 A   (m x n)
-  wg_transpose(A, m, n, n, Dt, m);             // Dt = (L_B^-1 A)^t   (n x m)
-  wg_trsm_lower(C, n, n, Dt, m, m);            // Dt = L_C^-1 A^t L_B^-t = D^t
-  for (long t = threadIdx.x; t < (long)n * n; t += DBLK) {
+  wg_chol<GB>(B, m, m, &info);
+  wg_chol<GB>(C, n, n, &info);
+  wg_trsm_lower<GB>(B, m, m, A, n, n);             // A <- L_B^-1 A   (m x n)
+  wg_transpose<GB>(A, m, n, n, Dt, m);             // Dt = (L_B^-1 A)^t   (n x m)
+  wg_trsm_lower<GB>(C, n, n, Dt, m, m);            // Dt = L_C^-1 A^t L_B^-t = D^t
+  for (long t = threadIdx.x; t < (long)n * n; t += GB) {
     int i = (int)(t / n), j = (int)(t % n);
     double s = 0.0;
     for (int k = 0; k < m; ++k) s += Dt[(long)i * m + k] * Dt[(long)j * m + k];
     G[t] = s;
   }
   wg_sync();
-  for (long t = threadIdx.x; t < (long)n * n; t += DBLK) {
+  for (long t = threadIdx.x; t < (long)n * n; t += GB) {
     int i = (int)(t / n), j = (int)(t % n);
     if (j > i) {
       double s = 0.5 * (G[(long)i * n + j] + G[(long)j * n + i]);
       G[(long)i * n + j] = s; G[(long)j * n + i] = s;
     }
   }
-  wg_jacobi(G, n, n, W, n, 60);
-  for (int i = threadIdx.x; i < n; i += DBLK) lam[i] = sqrt(fmax(G[(long)i * n + i], 0.0));
+  jacobi_lds<LDSJ>(G, n, W);
+  for (int i = threadIdx.x; i < n; i += GB) lam[i] = sqrt(fmax(G[(long)i * n + i], 0.0));
   wg_sync();
-  select_extremal(lam, n, nb, !minimal, ord);
+  select_extremal<GB>(lam, n, nb, !minimal, ord);
   double smax = 0.0;
   for (int i = 0; i < n; ++i) smax = fmax(smax, lam[i]);
   // t_k = D w_k / s_k  (D = Dt^t)
-  for (long t = threadIdx.x; t < (long)m * nb; t += DBLK) {
+  for (long t = threadIdx.x; t < (long)m * nb; t += GB) {
     int r = (int)(t / nb), k = (int)(t % nb);
     double s = 0.0;
     for (int j = 0; j < n; ++j) s += Dt[(long)j * m + r] * W[(long)j * n + ord[k]];
@@ -536,20 +591,43 @@ __global__ __launch_bounds__(DBLK) void k_coarse_gsvd(int spd, int minimal, int 
     }
   }
   wg_sync();
-  for (long t = threadIdx.x; t < (long)m * nb; t += DBLK) U[t] = Tm[t];
-  for (long t = threadIdx.x; t < (long)n * nb; t += DBLK) {
+  for (long t = threadIdx.x; t < (long)m * nb; t += GB) U[t] = Tm[t];
+  for (long t = threadIdx.x; t < (long)n * nb; t += GB) {
     int i = (int)(t / nb), k = (int)(t % nb);
     V[t] = W[(long)i * n + ord[k]];
   }
-  wg_trsm_lower_t(B, m, m, U, nb, nb);
-  wg_trsm_lower_t(C, n, n, V, nb, nb);
-  for (int k = threadIdx.x; k < nb; k += DBLK) sig[k] = lam[ord[k]];
+  wg_trsm_lower_t<GB>(B, m, m, U, nb, nb);
+  wg_trsm_lower_t<GB>(C, n, n, V, nb, nb);
+  for (int k = threadIdx.x; k < nb; k += GB) sig[k] = lam[ord[k]];
   if (threadIdx.x == 0 && info) *status = ST_E_NUMERIC;
 }
 void launch_coarse_gsvd(int spd, int minimal, int mL, int nL, int nb, double* A, double* B, double* C, double* work,
                         double* sig, double* U, double* V, int* status, hipStream_t s) {
-  hipLaunchKernelGGL(k_coarse_gsvd, dim3(1), dim3(DBLK), 0, s, spd, minimal, mL, nL, nb, A, B, C, work, sig, U, V,
-                     status);
+  // the rotated n x n matrix in LDS when it fits the workgroup's share beside the static arrays
+  static const int max_dyn = [] {
+    int dev = 0, v = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) v = 65536;
+    hipFuncAttributes fa{};
+    if (hipFuncGetAttributes(&fa, (const void*)k_coarse_gsvd<true>) != hipSuccess) {
+      (void)hipGetLastError();
+      return 0;
+    }
+    int m = v - (int)fa.sharedSizeBytes;
+    if (m > 0 && hipFuncSetAttribute((const void*)k_coarse_gsvd<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     m) != hipSuccess) {
+      (void)hipGetLastError();
+      m = 0;
+    }
+    return m < 0 ? 0 : m;
+  }();
+  const size_t lds = (size_t)nL * nL * sizeof(double);
+  if (lds <= (size_t)max_dyn)
+    hipLaunchKernelGGL(k_coarse_gsvd<true>, dim3(1), dim3(GB), lds, s, spd, minimal, mL, nL, nb, A, B, C, work, sig,
+                       U, V, status);
+  else
+    hipLaunchKernelGGL(k_coarse_gsvd<false>, dim3(1), dim3(GB), 0, s, spd, minimal, mL, nL, nb, A, B, C, work, sig,
+                       U, V, status);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -624,15 +702,17 @@ __global__ __launch_bounds__(PB) void k_pinv_solve(int N, int nb, const double* 
   else { W2 = work + (long)j * 2 * NN + NN; Q = Qg; }
   // fourth LDS array for the Newton-type steps (matrix-core products only)
   double* Tm = (lds_mode == 2 && mm && lds4) ? dyn + 3 * NN : nullptr;
-  __shared__ double cf[1024];
-  __shared__ double lam[1024];
-  __shared__ double rj[1024];
+  // the three N-vectors (eigenvalues, coefficients, right-hand side) follow the LDS matrices
+  const int narr = lds_mode == 2 ? (lds4 ? 4 : 3) : lds_mode == 1 ? 1 : 0;
+  double* lam = dyn + (long)narr * NN;
+  double* cf = lam + N;
+  double* rj = cf + N;
   __shared__ double red[PB];
   __shared__ int imin;
   const double s = sig[j];
   if (!warm || (warm == 2 && !Tm)) {
     for (long t = threadIdx.x; t < NN; t += PB) M[t] = X[t] - s * Y[t];
-    wg_jacobi<PB>(M, N, N, Q, N, 60);
+    wg_jacobi<PB, lds_mode < 2>(M, N, N, Q, N, 60);
     for (int i = threadIdx.x; i < N; i += PB) lam[i] = M[(long)i * N + i];
   } else {
     if constexpr (lds_mode == 2)
@@ -730,13 +810,13 @@ __global__ __launch_bounds__(PB) void k_pinv_solve(int N, int nb, const double* 
         break;
       }
       if (!Tm || step == 3) {
-        wg_jacobi<PB>(M, N, N, W2, N, 60);
+        wg_jacobi<PB, lds_mode < 2>(M, N, N, W2, N, 60);
         for (int i = threadIdx.x; i < N; i += PB) lam[i] = M[(long)i * N + i];
         break;
       }
       if (kmax > 1e-4) {
         // one Jacobi sweep (roughly squares max |K|), Q <- Q W2, then test again
-        wg_jacobi<PB>(M, N, N, W2, N, 1);
+        wg_jacobi<PB, lds_mode < 2>(M, N, N, W2, N, 1);
         wg_mm64<false, false>(Q, W2, Tm, N);
         wg_sync();
         for (long t = threadIdx.x; t < NN; t += PB) Q[t] = Tm[t];
@@ -806,16 +886,19 @@ static int pinv_max_dyn_lds() {
     int dev = 0, v = 0;
     (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) v = 65536;
-    hipFuncAttributes fa1{}, fa2{};
-    if (hipFuncGetAttributes(&fa1, (const void*)k_pinv_solve<1>) != hipSuccess ||
+    hipFuncAttributes fa0{}, fa1{}, fa2{};
+    if (hipFuncGetAttributes(&fa0, (const void*)k_pinv_solve<0>) != hipSuccess ||
+        hipFuncGetAttributes(&fa1, (const void*)k_pinv_solve<1>) != hipSuccess ||
         hipFuncGetAttributes(&fa2, (const void*)k_pinv_solve<2>) != hipSuccess) {
       (void)hipGetLastError();
       return 0;
     }
-    const int static_lds = (int)std::max(fa1.sharedSizeBytes, fa2.sharedSizeBytes);
+    const int static_lds = (int)std::max(fa0.sharedSizeBytes, std::max(fa1.sharedSizeBytes, fa2.sharedSizeBytes));
     int m = v - static_lds;
     if (m > 0 &&
-        (hipFuncSetAttribute((const void*)k_pinv_solve<1>, hipFuncAttributeMaxDynamicSharedMemorySize, m) !=
+        (hipFuncSetAttribute((const void*)k_pinv_solve<0>, hipFuncAttributeMaxDynamicSharedMemorySize, m) !=
+             hipSuccess ||
+         hipFuncSetAttribute((const void*)k_pinv_solve<1>, hipFuncAttributeMaxDynamicSharedMemorySize, m) !=
              hipSuccess ||
          hipFuncSetAttribute((const void*)k_pinv_solve<2>, hipFuncAttributeMaxDynamicSharedMemorySize, m) !=
              hipSuccess)) {
@@ -830,11 +913,11 @@ static int pinv_max_dyn_lds() {
 void launch_pinv_solve(int N, int nb, const double* X, const double* Y, const double* sig, const double* rhs,
                        double* out, double* work, double* basis, int warm, int* status, hipStream_t s) {
   (void)status;
-  const size_t one = (size_t)N * N * sizeof(double);
+  const size_t one = (size_t)N * N * sizeof(double), vec = 3 * (size_t)N * sizeof(double);
   const size_t max_dyn = (size_t)pinv_max_dyn_lds();
-  const int mode = 3 * one <= max_dyn ? 2 : one <= max_dyn ? 1 : 0;
-  const int lds4 = (mode == 2 && N <= 64 && 4 * one <= max_dyn) ? 1 : 0;
-  const size_t lds = mode == 2 ? (lds4 ? 4 : 3) * one : mode == 1 ? one : 0;
+  const int mode = 3 * one + vec <= max_dyn ? 2 : one + vec <= max_dyn ? 1 : 0;
+  const int lds4 = (mode == 2 && N <= 64 && 4 * one + vec <= max_dyn) ? 1 : 0;
+  const size_t lds = (mode == 2 ? (lds4 ? 4 : 3) * one : mode == 1 ? one : 0) + vec;
   if (mode == 2)
     hipLaunchKernelGGL(k_pinv_solve<2>, dim3(nb), dim3(PB), lds, s, N, nb, X, Y, sig, rhs, out, work, basis, warm,
                        lds4);
@@ -842,7 +925,8 @@ void launch_pinv_solve(int N, int nb, const double* X, const double* Y, const do
     hipLaunchKernelGGL(k_pinv_solve<1>, dim3(nb), dim3(PB), lds, s, N, nb, X, Y, sig, rhs, out, work, basis, warm,
                        0);
   else
-    hipLaunchKernelGGL(k_pinv_solve<0>, dim3(nb), dim3(PB), 0, s, N, nb, X, Y, sig, rhs, out, work, basis, warm, 0);
+    hipLaunchKernelGGL(k_pinv_solve<0>, dim3(nb), dim3(PB), lds, s, N, nb, X, Y, sig, rhs, out, work, basis, warm,
+                       0);
 }
 
 // Pencil variant, set-up once per additive phase: Y = L L^t, K = L^-1 X L^-t = W diag(mu) W^t,

@@ -259,7 +259,10 @@ WORKLOADS = {
                                            mu_b=4, n_mult=3, coarse_pinv=1)),
     "aniso3d_128_min8": dict(desc="3-D anisotropic 7-point Dirichlet 128^3 (n=2097152, eps=0.01), 8 minimal eigenpairs",
                              kind="spd", target="minimal", n_b=8,
-                             params=dict(theta=0.06, n_t=8, mu_t=4, mu_b=4, n_mult=10, coarse_pinv=1)),
+                             # coarse_max 128: the validated hierarchy of this operator (with 64 the
+                             # mixed-precision residual history departs from the FP64 one mid-run)
+                             params=dict(theta=0.06, n_t=8, mu_t=4, mu_b=4, n_mult=10, coarse_pinv=1,
+                                         coarse_max=128)),
 }
 
 
