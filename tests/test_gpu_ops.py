@@ -322,11 +322,11 @@ def test_coarse_gsvd_parity(L, kind, target):
                                          (3, 60, 40), (4, 60, 40), (0, 120, 90), (2, 120, 90), (3, 120, 90),
                                          (1, 120, 90)])
 def test_coarse_solve_parity(L, variant, m, n):
-    # N = m + n: up to ~67 keeps all three eigensolve arrays in LDS (up to 64 with the dense products
-    # on the matrix cores: 63 and 64 are a ragged and a full 64 x 64 tile set, 65 the scalar
-    # products; up to 58 also the fourth array of the Newton-type steps), 100 the matrix only, 210
-    # none; variants 2, 3, 4 are warm starts (Newton-type steps where they fit, else Jacobi sweeps /
-    # first-order update / Jacobi sweeps)
+    # N = m + n: up to 74 keeps all three eigensolve arrays in LDS (up to 64 with the dense products
+    # on the matrix cores and the fourth array of the Newton-type steps: 63 and 64 are a ragged and a
+    # full 64 x 64 tile set, 65 the scalar products), 100 the matrix only (up to 128), 210 none;
+    # variants 2-5 are warm starts (Newton-type steps where they fit, else Jacobi sweeps /
+    # first-order update / Jacobi sweeps / Newton after re-orthonormalising)
     import scipy.linalg as sla
     rng = np.random.default_rng(6)
     Ad = rng.uniform(-1, 1, (m, n))
