@@ -37,13 +37,13 @@ DEFAULT_WORKLOAD = "gradient2d_256_dom8"
 # HBM traffic of the dominant kernel class, from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs
 # (profiles/pmc_*_gradient2d_256_dom8.md), per dispatch in KiB for the two finest-level k_rowop
 # launch shapes (u rows, v rows), scaled by the same counters of a 1 GiB device copy
-# (profiles/pmc_*_copy_1GiB.md: FETCH 524303.5 KiB, WRITE 1048576.0 KiB per 1 GiB).  Valid only
+# (profiles/pmc_*_copy_1GiB.md: FETCH 524304.4 KiB, WRITE 1048576.0 KiB per 1 GiB).  Valid only
 # for the kernel source the counters were taken with.
 TRAFFIC = {
     ("gradient2d_256_dom8", 0): dict(
-        kernels_sha256="caa935a6621bd8a58a3cd6fce183756abbfa245ee8ba6e685337a5b8a5901f61",
-        fetch_kib=(12216.1, 10360.9), write_kib=(8160.0, 4096.0),
-        copy_fetch_kib=524303.5, copy_write_kib=1048576.0, copy_bytes=1 << 30),
+        kernels_sha256="6c97123e88193b9af03c98f78c52d1718645b18b9e62d05f4519b9f99ee0f883",
+        fetch_kib=(12224.1, 10368.9), write_kib=(8160.0, 4096.0),
+        copy_fetch_kib=524304.4, copy_write_kib=1048576.0, copy_bytes=1 << 30),
 }
 
 
@@ -112,7 +112,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed_fp32"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed_fp32", "mixed_bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--max-add", type=int, default=6000,
@@ -206,7 +206,7 @@ def main():
         cpu = cpu_baseline(name, A, wl, int(last.report.add_iters))
     line = {"metric": "triplets/s at resid 1e-8", "value": round(value, 4), "unit": "triplets/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
-            "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+            "scaling": "weak", "vs_baseline": None, "dtype": {"fp64": "f64", "mixed_fp32": "f32+f64", "mixed_bf16": "bf16+f32+f64"}[args.precision],
             "data": "synthetic",
             "config": {"workload": name, "description": wl["desc"], "rows": int(A.shape[0]),
                        "cols": int(A.shape[1]), "nnz": int(A.nnz), "n_b": n_b, "kind": kind, "target": target,

@@ -48,7 +48,9 @@ typedef enum { SLAMG_DOMINANT = 0, SLAMG_MINIMAL = 1 } slamg_target;
 typedef enum { SLAMG_SVD = 0, SLAMG_SPD_EIG = 1 } slamg_kind;
 typedef enum {
   SLAMG_FP64 = 0,           /* every step in FP64                                               */
-  SLAMG_MIXED_FP32 = 1      /* FP32 V-cycles on the error equation inside an FP64 refinement     */
+  SLAMG_MIXED_FP32 = 1,     /* FP32 V-cycles on the error equation inside an FP64 refinement     */
+  SLAMG_MIXED_BF16 = 2      /* as MIXED_FP32 with the V-cycle's operator values stored in BF16
+                               (rounded to nearest even); vectors and sums stay FP32           */
 } slamg_precision;
 
 /* Sparse matrix in CSR: row_ptr (m+1, int64), col_idx (nnz, int32, sorted within a row, no

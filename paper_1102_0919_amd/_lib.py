@@ -16,7 +16,7 @@ STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "E_INVALID", -2: "E_OOM", -3: "
 STATUS_BUSY = -6
 KIND = {"svd": 0, "spd": 1}
 TARGET = {"dominant": 0, "minimal": 1}
-PRECISION = {"fp64": 0, "mixed_fp32": 1}
+PRECISION = {"fp64": 0, "mixed_fp32": 1, "mixed_bf16": 2}
 
 
 class Csr(C.Structure):

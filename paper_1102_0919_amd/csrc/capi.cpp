@@ -257,7 +257,7 @@ static slamg_status check_params(std::string& err, const Prepared& P, int32_t nb
   if (!(p.tol > 0.0)) return fail(err, SLAMG_E_INVALID, "tol must be positive");
   if (p.n_t < 2 || p.n_t > 16) return fail(err, SLAMG_E_INVALID, "n_t must be in 2..16");
   if (p.mu_t < 0 || p.mu_b < 0 || p.n_mult < 1 || p.max_add < 0) return fail(err, SLAMG_E_INVALID, "bad counts");
-  if (p.precision != SLAMG_FP64 && p.precision != SLAMG_MIXED_FP32)
+  if (p.precision != SLAMG_FP64 && p.precision != SLAMG_MIXED_FP32 && p.precision != SLAMG_MIXED_BF16)
     return fail(err, SLAMG_E_INVALID, "unknown precision");
   if (p.coarse_pinv != 0 && p.coarse_pinv != 1) return fail(err, SLAMG_E_INVALID, "unknown coarse_pinv");
   if (p.strength_rule < 0 || p.strength_rule > 2) return fail(err, SLAMG_E_INVALID, "unknown strength rule");

@@ -76,15 +76,17 @@ struct RowOpArgs {
   T* out = nullptr;
   int nnzK = -1;             // nonzeros of K (chooses the row split); -1: unknown
   double avgM = 0.0;         // mean row length of M (M_CSR; also chooses the row split)
+  int vbf = 0;               // Kv, Mv hold BF16 bit patterns (T = float only)
 };
 
 template <typename T> void launch_rowop(const RowOpArgs<T>& a, hipStream_t s);
-// two independent row operations (same w) in one launch
+// two independent row operations (same w, same value form vbf) in one launch
 template <typename T> void launch_rowop2(const RowOpArgs<T>& a, const RowOpArgs<T>& b, hipStream_t s);
 
+// vbf: v holds BF16 bit patterns (T = float only)
 template <typename T>
 void launch_spmm(int m, int w, const int* rp, const int* ci, const T* v, const T* x, T* y,
-                 double beta, hipStream_t s, int nnz = -1);
+                 double beta, hipStream_t s, int nnz = -1, int vbf = 0);
 
 // y = K x (+ beta y) for one operand set of a paired SpMM
 template <typename T>
@@ -92,8 +94,9 @@ struct SpmmArgs {
   int m = 0, nnz = -1;
   const int* rp = nullptr; const int* ci = nullptr; const T* v = nullptr;
   const T* x = nullptr; T* y = nullptr; double beta = 0.0;
+  int vbf = 0;               // v holds BF16 bit patterns (T = float only)
 };
-// two independent products with w columns in one launch
+// two independent products with w columns (same value form vbf) in one launch
 template <typename T> void launch_spmm2(const SpmmArgs<T>& a, const SpmmArgs<T>& b, int w, hipStream_t s);
 
 template <typename T>
@@ -112,6 +115,7 @@ struct KaczArgs {
   T* x = nullptr;
   long nnz_total = -1, nnz_rows = 0;   // row-length statistics of the operator (row split)
   double avgM = 0.0;                    // mean row length of the right-hand side operator (M_CSR)
+  int vbf = 0;                          // av, bv, Mv hold BF16 bit patterns (T = float only)
 };
 template <typename T> void launch_kacz(const KaczArgs<T>& a, hipStream_t s);
 // nhalf (1 or 2) half-sweeps per sweep, nsweeps sweeps, all in one workgroup; halves[h].rows is the
@@ -165,6 +169,8 @@ void launch_rq_update(int w, const double* num, const double* nu, const double* 
 void launch_fill(double* p, size_t n, double val, hipStream_t s);
 void launch_fillf(float* p, size_t n, float val, hipStream_t s);
 void launch_copy_cast_df(const double* in, float* out, size_t n, hipStream_t s);
+// FP64 -> BF16 bit patterns (out: n 16-bit words), rounded to FP32 and then to the nearest BF16
+void launch_cast_bf16(const double* in, void* out, size_t n, hipStream_t s);
 void launch_copy_cast_fd(const float* in, double* out, size_t n, hipStream_t s);
 void launch_axpy_fd(const float* in, double* out, size_t n, hipStream_t s);   // out += in
 void launch_splitmix_block(long ru, long rv, int w, unsigned long long seed, double* U, double* V, hipStream_t s);

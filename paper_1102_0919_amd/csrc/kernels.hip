@@ -90,12 +90,25 @@ __device__ __forceinline__ void strow(T* __restrict__ p, int c0, int w, const T 
     if (c0 + c < w) p[c0 + c] = v[c];
 }
 
+// Operator value k.  With BF (FP32 V-cycles with BF16 operator values) the array holds BF16 bit
+// patterns: the value is those 16 bits as the high half of an FP32 word.  BF is a template argument
+// so that each kernel's loop carries one load form and no branch per load.
+template <typename T, bool BF>
+__device__ __forceinline__ T ldval(const T* __restrict__ p, long k) {
+  if constexpr (BF) {
+    static_assert(std::is_same<T, float>::value, "BF16 values feed FP32 arithmetic only");
+    return __uint_as_float((unsigned)reinterpret_cast<const unsigned short*>(p)[k] << 16);
+  } else {
+    return p[k];
+  }
+}
+
 // One lane's walk over the nonzeros k, k + SPLIT, k + 2 SPLIT, ... < ke of a CSR row, summing
 // a_k z(j_k) (and b_k z(j_k) when TWO).  Each step takes four nonzeros (two when TWO, to bound the
 // registers): their index and value loads are issued together, then their row gathers, so a lane
 // with at most four nonzeros waits for one index -> row chain.  Slots past the row's end load
 // nothing and add zero, which leaves the sums bitwise equal to the one-by-one walk.
-template <typename T, int CPL, int SPLIT, bool TWO>
+template <typename T, int CPL, int SPLIT, bool TWO, bool BF = false>
 __device__ __forceinline__ void walk_row(int k, int ke, const int* __restrict__ ci, const T* __restrict__ av,
                                          const T* __restrict__ bv, const T* __restrict__ z, int w, int c0,
                                          T (&s1)[CPL], T (&s2)[CPL]) {
@@ -111,8 +124,8 @@ __device__ __forceinline__ void walk_row(int k, int ke, const int* __restrict__ 
       b[u] = T(0);
       if (kk < ke) {
         j[u] = ci[kk];
-        a[u] = av[kk];
-        if constexpr (TWO) b[u] = bv[kk];
+        a[u] = ldval<T, BF>(av, kk);
+        if constexpr (TWO) b[u] = ldval<T, BF>(bv, kk);
       }
     }
     T zr[U][CPL];
@@ -144,7 +157,7 @@ struct SpmmPOD {
 };
 
 // thread t of the product's own grid
-template <typename T, int CPL, int SPLIT>
+template <typename T, int CPL, int SPLIT, bool BF>
 __device__ __forceinline__ void spmm_body(const SpmmPOD<T>& a, int lshift, long t) {
   constexpr int LS = SPLIT == 1 ? 0 : SPLIT == 4 ? 2 : SPLIT == 8 ? 3 : 4;
   const int m = a.m, w = a.w;
@@ -166,7 +179,7 @@ __device__ __forceinline__ void spmm_body(const SpmmPOD<T>& a, int lshift, long 
   T acc[CPL], unused[CPL];
 #pragma unroll
   for (int c = 0; c < CPL; ++c) acc[c] = T(0);
-  walk_row<T, CPL, SPLIT, false>(rp[row] + sidx, rp[row + 1], ci, v, nullptr, x, w, c0, acc, unused);
+  walk_row<T, CPL, SPLIT, false, BF>(rp[row] + sidx, rp[row + 1], ci, v, nullptr, x, w, c0, acc, unused);
 #pragma unroll
   for (int c = 0; c < CPL; ++c) acc[c] = split_sum<SPLIT>(acc[c], 1 << lshift);
   if (sidx != 0) return;
@@ -177,18 +190,18 @@ __device__ __forceinline__ void spmm_body(const SpmmPOD<T>& a, int lshift, long 
   strow<T, CPL>(yr, c0, w, acc);
 }
 
-template <typename T, int CPL, int SPLIT>
+template <typename T, int CPL, int SPLIT, bool BF>
 __global__ __launch_bounds__(BLK) void k_spmm(SpmmPOD<T> a, int lshift) {
-  spmm_body<T, CPL, SPLIT>(a, lshift, (long)blockIdx.x * BLK + threadIdx.x);
+  spmm_body<T, CPL, SPLIT, BF>(a, lshift, (long)blockIdx.x * BLK + threadIdx.x);
 }
 
 // Two independent products in one launch (the u- and v-side transfers of a level): workgroups
 // [0, nb0) run the first, the others the second, so the two latency chains overlap.
-template <typename T, int CPL, int SPLIT>
+template <typename T, int CPL, int SPLIT, bool BF>
 __global__ __launch_bounds__(BLK) void k_spmm2(SpmmPOD<T> a, SpmmPOD<T> b, int lshift, int nb0) {
   const int bk = (int)blockIdx.x;
-  if (bk < nb0) spmm_body<T, CPL, SPLIT>(a, lshift, (long)bk * BLK + threadIdx.x);
-  else spmm_body<T, CPL, SPLIT>(b, lshift, (long)(bk - nb0) * BLK + threadIdx.x);
+  if (bk < nb0) spmm_body<T, CPL, SPLIT, BF>(a, lshift, (long)bk * BLK + threadIdx.x);
+  else spmm_body<T, CPL, SPLIT, BF>(b, lshift, (long)(bk - nb0) * BLK + threadIdx.x);
 }
 
 #define SLAMG_DISPATCH_SPLIT(KER, T, CPL, SP, GRID, ...)                                        \
@@ -199,28 +212,48 @@ __global__ __launch_bounds__(BLK) void k_spmm2(SpmmPOD<T> a, SpmmPOD<T> b, int l
     else hipLaunchKernelGGL((KER<T, CPL, 16>), dim3(GRID), dim3(BLK), 0, __VA_ARGS__);        \
   } while (0)
 
+// The same over kernels that read operator values, with their value form as the last template
+// argument: BF16 bit patterns (VBF != 0, FP32 kernels only) or T.
+#define SLAMG_DISPATCH_SPLIT_BF(KER, T, CPL, BF, SP, GRID, NT, ...)                                \
+  do {                                                                                           \
+    if (SP == 1) hipLaunchKernelGGL((KER<T, CPL, 1, BF>), dim3(GRID), dim3(NT), 0, __VA_ARGS__);     \
+    else if (SP == 4) hipLaunchKernelGGL((KER<T, CPL, 4, BF>), dim3(GRID), dim3(NT), 0, __VA_ARGS__); \
+    else if (SP == 8) hipLaunchKernelGGL((KER<T, CPL, 8, BF>), dim3(GRID), dim3(NT), 0, __VA_ARGS__); \
+    else hipLaunchKernelGGL((KER<T, CPL, 16, BF>), dim3(GRID), dim3(NT), 0, __VA_ARGS__);           \
+  } while (0)
+#define SLAMG_DISPATCH_VALS(KER, T, VBF, SP, W, GRID, NT, ...)                                     \
+  do {                                                                                           \
+    if constexpr (std::is_same<T, float>::value) {                                               \
+      if (VBF) {                                                                                 \
+        if (cpl_of(W) == 2) SLAMG_DISPATCH_SPLIT_BF(KER, T, 2, true, SP, GRID, NT, __VA_ARGS__); \
+        else SLAMG_DISPATCH_SPLIT_BF(KER, T, 1, true, SP, GRID, NT, __VA_ARGS__);               \
+        break;                                                                                   \
+      }                                                                                          \
+    }                                                                                            \
+    if (cpl_of(W) == 2) SLAMG_DISPATCH_SPLIT_BF(KER, T, 2, false, SP, GRID, NT, __VA_ARGS__);   \
+    else SLAMG_DISPATCH_SPLIT_BF(KER, T, 1, false, SP, GRID, NT, __VA_ARGS__);                  \
+  } while (0)
+
 template <typename T>
 void launch_spmm(int m, int w, const int* rp, const int* ci, const T* v, const T* x, T* y, double beta,
-                 hipStream_t s, int nnz) {
+                 hipStream_t s, int nnz, int vbf) {
   if (m <= 0) return;
   int sh = lshift_of(w);
   int sp = split_of(nnz, m, sh);
   int grid = ceil_div((long)m << (sh + log2i(sp)), BLK);
   SpmmPOD<T> p{m, w, rp, ci, v, x, y, (T)beta};
-  if (cpl_of(w) == 2) SLAMG_DISPATCH_SPLIT(k_spmm, T, 2, sp, grid, s, p, sh);
-  else SLAMG_DISPATCH_SPLIT(k_spmm, T, 1, sp, grid, s, p, sh);
+  SLAMG_DISPATCH_VALS(k_spmm, T, vbf, sp, w, grid, BLK, s, p, sh);
 }
 
 template <typename T>
 void launch_spmm2(const SpmmArgs<T>& a, const SpmmArgs<T>& b, int w, hipStream_t s) {
-  if (a.m <= 0) { launch_spmm<T>(b.m, w, b.rp, b.ci, b.v, b.x, b.y, b.beta, s, b.nnz); return; }
-  if (b.m <= 0) { launch_spmm<T>(a.m, w, a.rp, a.ci, a.v, a.x, a.y, a.beta, s, a.nnz); return; }
+  if (a.m <= 0) { launch_spmm<T>(b.m, w, b.rp, b.ci, b.v, b.x, b.y, b.beta, s, b.nnz, b.vbf); return; }
+  if (b.m <= 0) { launch_spmm<T>(a.m, w, a.rp, a.ci, a.v, a.x, a.y, a.beta, s, a.nnz, a.vbf); return; }
   const int sh = lshift_of(w);
   const int sp = std::max(split_of(a.nnz, a.m, sh), split_of(b.nnz, b.m, sh));
   const int g0 = ceil_div((long)a.m << (sh + log2i(sp)), BLK), g1 = ceil_div((long)b.m << (sh + log2i(sp)), BLK);
   SpmmPOD<T> pa{a.m, w, a.rp, a.ci, a.v, a.x, a.y, (T)a.beta}, pb{b.m, w, b.rp, b.ci, b.v, b.x, b.y, (T)b.beta};
-  if (cpl_of(w) == 2) SLAMG_DISPATCH_SPLIT(k_spmm2, T, 2, sp, g0 + g1, s, pa, pb, sh, g0);
-  else SLAMG_DISPATCH_SPLIT(k_spmm2, T, 1, sp, g0 + g1, s, pa, pb, sh, g0);
+  SLAMG_DISPATCH_VALS(k_spmm2, T, a.vbf, sp, w, g0 + g1, BLK, s, pa, pb, sh, g0);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -252,7 +285,7 @@ __device__ __forceinline__ void coefs(int cmode, double om, double s, T& ca, T& 
 }
 
 // thread t of the row operation's own grid
-template <typename T, int CPL, int SPLIT>
+template <typename T, int CPL, int SPLIT, bool BF>
 __device__ __forceinline__ void rowop_body(const RowOpPOD<T>& a, int lshift, long t) {
   constexpr int LS = SPLIT == 1 ? 0 : SPLIT == 4 ? 2 : SPLIT == 8 ? 3 : 4;
   const int gl = lshift + LS;
@@ -280,13 +313,13 @@ __device__ __forceinline__ void rowop_body(const RowOpPOD<T>& a, int lshift, lon
   }
   if (a.Kv) {
     if (a.mmode == M_SHARED)
-      walk_row<T, CPL, SPLIT, true>(a.Krp[row] + sidx, a.Krp[row + 1], a.Kci, a.Kv, a.Mv, a.z, w, c0, kz, my);
+      walk_row<T, CPL, SPLIT, true, BF>(a.Krp[row] + sidx, a.Krp[row + 1], a.Kci, a.Kv, a.Mv, a.z, w, c0, kz, my);
     else
-      walk_row<T, CPL, SPLIT, false>(a.Krp[row] + sidx, a.Krp[row + 1], a.Kci, a.Kv, nullptr, a.z, w, c0, kz, my);
+      walk_row<T, CPL, SPLIT, false, BF>(a.Krp[row] + sidx, a.Krp[row + 1], a.Kci, a.Kv, nullptr, a.z, w, c0, kz, my);
   }
   if (a.mmode == M_CSR) {
     T unused[CPL];
-    walk_row<T, CPL, SPLIT, false>(a.Mrp[row] + sidx, a.Mrp[row + 1], a.Mci, a.Mv, nullptr, a.y, w, c0, my, unused);
+    walk_row<T, CPL, SPLIT, false, BF>(a.Mrp[row] + sidx, a.Mrp[row + 1], a.Mci, a.Mv, nullptr, a.y, w, c0, my, unused);
   }
 #pragma unroll
   for (int c = 0; c < CPL; ++c) {
@@ -308,18 +341,18 @@ __device__ __forceinline__ void rowop_body(const RowOpPOD<T>& a, int lshift, lon
   strow<T, CPL>(a.out + (long)row * w, c0, w, r);
 }
 
-template <typename T, int CPL, int SPLIT>
+template <typename T, int CPL, int SPLIT, bool BF>
 __global__ __launch_bounds__(BLK) void k_rowop(RowOpPOD<T> a, int lshift) {
-  rowop_body<T, CPL, SPLIT>(a, lshift, (long)blockIdx.x * BLK + threadIdx.x);
+  rowop_body<T, CPL, SPLIT, BF>(a, lshift, (long)blockIdx.x * BLK + threadIdx.x);
 }
 
 // Two independent row operations in one launch (the u- and v-side residuals of a level):
 // workgroups [0, nb0) run the first, the others the second.
-template <typename T, int CPL, int SPLIT>
+template <typename T, int CPL, int SPLIT, bool BF>
 __global__ __launch_bounds__(BLK) void k_rowop2(RowOpPOD<T> a, RowOpPOD<T> b, int lshift, int nb0) {
   const int bk = (int)blockIdx.x;
-  if (bk < nb0) rowop_body<T, CPL, SPLIT>(a, lshift, (long)bk * BLK + threadIdx.x);
-  else rowop_body<T, CPL, SPLIT>(b, lshift, (long)(bk - nb0) * BLK + threadIdx.x);
+  if (bk < nb0) rowop_body<T, CPL, SPLIT, BF>(a, lshift, (long)bk * BLK + threadIdx.x);
+  else rowop_body<T, CPL, SPLIT, BF>(b, lshift, (long)(bk - nb0) * BLK + threadIdx.x);
 }
 
 template <typename T>
@@ -330,8 +363,7 @@ void launch_rowop(const RowOpArgs<T>& a, hipStream_t s) {
   int sh = lshift_of(a.w);
   int sp = split_of(a.Kv ? a.nnzK : -1, a.nrows, sh, a.mmode == M_CSR ? a.avgM : 0.0);
   int grid = ceil_div((long)a.nrows << (sh + log2i(sp)), BLK);
-  if (cpl_of(a.w) == 2) SLAMG_DISPATCH_SPLIT(k_rowop, T, 2, sp, grid, s, p, sh);
-  else SLAMG_DISPATCH_SPLIT(k_rowop, T, 1, sp, grid, s, p, sh);
+  SLAMG_DISPATCH_VALS(k_rowop, T, a.vbf, sp, a.w, grid, BLK, s, p, sh);
 }
 
 template <typename T>
@@ -349,8 +381,7 @@ void launch_rowop2(const RowOpArgs<T>& a, const RowOpArgs<T>& b, hipStream_t s) 
                           split_of(b.Kv ? b.nnzK : -1, b.nrows, sh, b.mmode == M_CSR ? b.avgM : 0.0));
   const int g0 = ceil_div((long)a.nrows << (sh + log2i(sp)), BLK), g1 = ceil_div((long)b.nrows << (sh + log2i(sp)), BLK);
   const RowOpPOD<T> pa = rowop_pod(a), pb = rowop_pod(b);
-  if (cpl_of(a.w) == 2) SLAMG_DISPATCH_SPLIT(k_rowop2, T, 2, sp, g0 + g1, s, pa, pb, sh, g0);
-  else SLAMG_DISPATCH_SPLIT(k_rowop2, T, 1, sp, g0 + g1, s, pa, pb, sh, g0);
+  SLAMG_DISPATCH_VALS(k_rowop2, T, a.vbf, sp, a.w, g0 + g1, BLK, s, pa, pb, sh, g0);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -368,7 +399,7 @@ struct KaczPOD {
   T* x;
 };
 
-template <typename T, int CPL, int SPLIT>
+template <typename T, int CPL, int SPLIT, bool BF>
 __device__ __forceinline__ void kacz_row(const KaczPOD<T>& a, int r, int c0, int sidx, int lprc) {
   const int w = a.w;
   T lam[CPL];
@@ -394,7 +425,7 @@ __device__ __forceinline__ void kacz_row(const KaczPOD<T>& a, int r, int c0, int
     T my[CPL], unused[CPL];
 #pragma unroll
     for (int c = 0; c < CPL; ++c) my[c] = T(0);
-    walk_row<T, CPL, SPLIT, false>(a.Mrp[r] + sidx, a.Mrp[r + 1], a.Mci, a.Mv, nullptr, a.y, w, c0, my, unused);
+    walk_row<T, CPL, SPLIT, false, BF>(a.Mrp[r] + sidx, a.Mrp[r + 1], a.Mci, a.Mv, nullptr, a.y, w, c0, my, unused);
 #pragma unroll
     for (int c = 0; c < CPL; ++c) rhs[c] = rs[c] * split_sum<SPLIT>(my[c], lprc) + kp[c];
   } else {
@@ -421,8 +452,8 @@ __device__ __forceinline__ void kacz_row(const KaczPOD<T>& a, int r, int c0, int
       bv[u] = T(0);
       if (kk < ke) {
         j[u] = a.ci[kk];
-        av[u] = a.av[kk];
-        if (shifted) bv[u] = a.bv ? a.bv[kk] : T(0);
+        av[u] = ldval<T, BF>(a.av, kk);
+        if (shifted) bv[u] = a.bv ? ldval<T, BF>(a.bv, kk) : T(0);
       }
     }
 #pragma unroll
@@ -464,9 +495,9 @@ __device__ __forceinline__ void kacz_row(const KaczPOD<T>& a, int r, int c0, int
     T* xp = a.x + (long)jj * w;
     T xv[CPL];
     ldrow<T, CPL>(xp, c0, w, xv);
-    T avk = a.av[k];
+    T avk = ldval<T, BF>(a.av, k);
     if (shifted) {
-      T bvk = a.bv ? a.bv[k] : (jj == r ? T(1) : T(0));
+      T bvk = a.bv ? ldval<T, BF>(a.bv, k) : (jj == r ? T(1) : T(0));
 #pragma unroll
       for (int c = 0; c < CPL; ++c) xv[c] += coef[c] * (avk - lam[c] * bvk);
     } else {
@@ -477,7 +508,7 @@ __device__ __forceinline__ void kacz_row(const KaczPOD<T>& a, int r, int c0, int
   }
 }
 
-template <typename T, int CPL, int SPLIT>
+template <typename T, int CPL, int SPLIT, bool BF>
 __global__ __launch_bounds__(BLK) void k_kacz(KaczPOD<T> a, int lshift) {
   constexpr int LS = SPLIT == 1 ? 0 : SPLIT == 4 ? 2 : SPLIT == 8 ? 3 : 4;
   const int gl = lshift + LS;
@@ -487,7 +518,7 @@ __global__ __launch_bounds__(BLK) void k_kacz(KaczPOD<T> a, int lshift) {
   const int sidx = lane >> lshift;
   int c0 = (lane & ((1 << lshift) - 1)) * CPL;
   if (idx >= a.nrows || c0 >= a.w) return;
-  kacz_row<T, CPL, SPLIT>(a, a.rows[idx], c0, sidx, 1 << lshift);
+  kacz_row<T, CPL, SPLIT, BF>(a, a.rows[idx], c0, sidx, 1 << lshift);
 }
 
 // Whole sweeps in one workgroup (small levels): for each of `nsweeps` sweeps, each half-sweep
@@ -503,7 +534,7 @@ struct KaczWgPOD {
 
 static constexpr int WGB = 1024;
 
-template <typename T, int CPL, int SPLIT>
+template <typename T, int CPL, int SPLIT, bool BF>
 __global__ __launch_bounds__(WGB) void k_kacz_wg(KaczWgPOD<T> a, int lshift) {
   constexpr int LS = SPLIT == 1 ? 0 : SPLIT == 4 ? 2 : SPLIT == 8 ? 3 : 4;
   const int gl = lshift + LS;
@@ -521,7 +552,7 @@ __global__ __launch_bounds__(WGB) void k_kacz_wg(KaczWgPOD<T> a, int lshift) {
       for (int c = 0; c < nc; ++c) {
         const int rb = cp[c], re = cp[c + 1];
         if (c0 < k.w)
-          for (int idx = rb + my; idx < re; idx += per) kacz_row<T, CPL, SPLIT>(k, k.rows[idx], c0, sidx, 1 << lshift);
+          for (int idx = rb + my; idx < re; idx += per) kacz_row<T, CPL, SPLIT, BF>(k, k.rows[idx], c0, sidx, 1 << lshift);
         __syncthreads();
       }
     }
@@ -550,17 +581,7 @@ void launch_kacz_wg(const KaczArgs<T>* halves, const int* const* cptr, const int
   const int w = halves[0].w;
   int sh = lshift_of(w);
   int sp = split_of(rows ? nnz : -1, rows, sh, avgM);
-  if (cpl_of(w) == 2) {
-    if (sp == 1) hipLaunchKernelGGL((k_kacz_wg<T, 2, 1>), dim3(1), dim3(WGB), 0, s, p, sh);
-    else if (sp == 4) hipLaunchKernelGGL((k_kacz_wg<T, 2, 4>), dim3(1), dim3(WGB), 0, s, p, sh);
-    else if (sp == 8) hipLaunchKernelGGL((k_kacz_wg<T, 2, 8>), dim3(1), dim3(WGB), 0, s, p, sh);
-    else hipLaunchKernelGGL((k_kacz_wg<T, 2, 16>), dim3(1), dim3(WGB), 0, s, p, sh);
-  } else {
-    if (sp == 1) hipLaunchKernelGGL((k_kacz_wg<T, 1, 1>), dim3(1), dim3(WGB), 0, s, p, sh);
-    else if (sp == 4) hipLaunchKernelGGL((k_kacz_wg<T, 1, 4>), dim3(1), dim3(WGB), 0, s, p, sh);
-    else if (sp == 8) hipLaunchKernelGGL((k_kacz_wg<T, 1, 8>), dim3(1), dim3(WGB), 0, s, p, sh);
-    else hipLaunchKernelGGL((k_kacz_wg<T, 1, 16>), dim3(1), dim3(WGB), 0, s, p, sh);
-  }
+  SLAMG_DISPATCH_VALS(k_kacz_wg, T, halves[0].vbf, sp, w, 1, WGB, s, p, sh);
 }
 
 template <typename T>
@@ -571,8 +592,7 @@ void launch_kacz(const KaczArgs<T>& a, hipStream_t s) {
   int sh = lshift_of(a.w);
   int sp = split_of(a.nnz_rows > 0 ? a.nnz_total : -1, a.nnz_rows, sh, a.rmode == M_CSR ? a.avgM : 0.0);
   int grid = ceil_div((long)a.nrows << (sh + log2i(sp)), BLK);
-  if (cpl_of(a.w) == 2) SLAMG_DISPATCH_SPLIT(k_kacz, T, 2, sp, grid, s, p, sh);
-  else SLAMG_DISPATCH_SPLIT(k_kacz, T, 1, sp, grid, s, p, sh);
+  SLAMG_DISPATCH_VALS(k_kacz, T, a.vbf, sp, a.w, grid, BLK, s, p, sh);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -947,6 +967,19 @@ __global__ void k_cast(const A* in, B* out, size_t n) {
   size_t t = (size_t)blockIdx.x * BLK + threadIdx.x;
   if (t < n) out[t] = (B)in[t];
 }
+// FP64 -> BF16 bit patterns: rounded to FP32, then to the nearest BF16 (ties to even)
+__global__ void k_cast_bf16(const double* __restrict__ in, unsigned short* __restrict__ out, size_t n) {
+  size_t t = (size_t)blockIdx.x * BLK + threadIdx.x;
+  if (t >= n) return;
+  const unsigned u = __float_as_uint((float)in[t]);
+  const bool nan = (u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu);
+  out[t] = nan ? (unsigned short)((u >> 16) | 0x40u) : (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+void launch_cast_bf16(const double* in, void* out, size_t n, hipStream_t s) {
+  if (n)
+    hipLaunchKernelGGL(k_cast_bf16, dim3(ceil_div((long)n, BLK)), dim3(BLK), 0, s, in, (unsigned short*)out, n);
+}
+
 void launch_copy_cast_df(const double* in, float* out, size_t n, hipStream_t s) {
   if (n) hipLaunchKernelGGL((k_cast<double, float>), dim3(ceil_div((long)n, BLK)), dim3(BLK), 0, s, in, out, n);
 }
@@ -1238,9 +1271,9 @@ void launch_scatter_out(int rows, int w, const double* X, const int* keep, const
 
 // explicit instantiations
 template void launch_spmm<double>(int, int, const int*, const int*, const double*, const double*, double*, double,
-                                  hipStream_t, int);
+                                  hipStream_t, int, int);
 template void launch_spmm<float>(int, int, const int*, const int*, const float*, const float*, float*, double,
-                                 hipStream_t, int);
+                                 hipStream_t, int, int);
 template void launch_rowop<double>(const RowOpArgs<double>&, hipStream_t);
 template void launch_rowop<float>(const RowOpArgs<float>&, hipStream_t);
 template void launch_rowop2<double>(const RowOpArgs<double>&, const RowOpArgs<double>&, hipStream_t);

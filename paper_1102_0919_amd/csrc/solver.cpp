@@ -171,7 +171,8 @@ class Solver {
  public:
   Solver(hipStream_t s, size_t budget, const Problem& pb, const slamg_params& p)
       : st_(s), ar_(budget, s), p_(p), spd_(pb.kind == SLAMG_SPD_EIG), minimal_(pb.target == SLAMG_MINIMAL),
-        nb_(pb.nb), nt_(p.n_t), mixed_(p.precision == SLAMG_MIXED_FP32), A0_(pb.A), pb_(pb) {}
+        nb_(pb.nb), nt_(p.n_t), mixed_(p.precision == SLAMG_MIXED_FP32 || p.precision == SLAMG_MIXED_BF16),
+        bf16_(p.precision == SLAMG_MIXED_BF16), A0_(pb.A), pb_(pb) {}
   ~Solver() {
     if (igx_) (void)hipGraphExecDestroy(igx_);
     if (ig_) (void)hipGraphDestroy(ig_);
@@ -232,6 +233,14 @@ class Solver {
   bool spd_, minimal_;
   int nb_, nt_;
   bool mixed_;
+  bool bf16_;   // the FP32 V-cycle reads BF16 operator values (their bit patterns in the .vf arrays)
+  // low-precision copy of an operator's values for the FP32 V-cycle: FP32, or BF16 bit patterns
+  void cast_vals(const DCsr& a) {
+    if (!a.vf) return;
+    if (bf16_) launch_cast_bf16(a.v, a.vf, a.nnz, st_);
+    else launch_copy_cast_df(a.v, a.vf, a.nnz, st_);
+  }
+  template <class T> int vbf() const { return std::is_same<T, float>::value && bf16_ ? 1 : 0; }
   const HCsr& A0_;
   const Problem& pb_;
   std::vector<std::unique_ptr<Level>> lv_;
@@ -311,10 +320,10 @@ class Solver {
 // Algorithmic bytes of one launch: every array the launch touches, counted once.
 template <class T>
 static double rowop_bytes(const RowOpArgs<T>& a, const DCsr* K) {
-  const double sz = sizeof(T), w = a.w, r = a.nrows;
+  const double sz = sizeof(T), vs = a.vbf ? 2.0 : sz, w = a.w, r = a.nrows;
   double b = 0.0;
-  if (a.Kv && K) b += 4.0 * (r + 1) + (4.0 + sz) * K->nnz + sz * w * K->n;
-  if (a.mmode == M_SHARED && K) b += sz * K->nnz;
+  if (a.Kv && K) b += 4.0 * (r + 1) + (4.0 + vs) * K->nnz + sz * w * K->n;
+  if (a.mmode == M_SHARED && K) b += vs * K->nnz;
   const bool own = a.x || a.mmode == M_IDENT;
   const bool same = a.Kv && (a.z == a.x || a.z == a.y);
   if (own && !same) b += sz * w * r;
@@ -328,6 +337,7 @@ template <class T>
 void Solver::rowop(int l, const RowOpArgs<T>& a0, const DCsr* K, int cls) {
   RowOpArgs<T> a = a0;
   if (a.nnzK < 0 && K) a.nnzK = K->nnz;
+  a.vbf = vbf<T>();
   if (l == 0) prof(cls, rowop_bytes(a, K), [&] { launch_rowop(a, st_); });
   else launch_rowop(a, st_);
 }
@@ -337,20 +347,22 @@ void Solver::rowop2(int l, const RowOpArgs<T>& a0, const DCsr* Ka, const RowOpAr
   RowOpArgs<T> a = a0, b = b0;
   if (a.nnzK < 0 && Ka) a.nnzK = Ka->nnz;
   if (b.nnzK < 0 && Kb) b.nnzK = Kb->nnz;
+  a.vbf = b.vbf = vbf<T>();
   if (l == 0) prof(cls, rowop_bytes(a, Ka) + rowop_bytes(b, Kb), [&] { launch_rowop2(a, b, st_); });
   else launch_rowop2(a, b, st_);
 }
 
 template <class T>
-static double spmm_bytes(const DCsr& K, int w, double beta) {
-  const double sz = sizeof(T);
-  return 4.0 * (K.m + 1) + (4.0 + sz) * K.nnz + sz * w * ((double)K.n + K.m * (beta != 0.0 ? 2 : 1));
+static double spmm_bytes(const DCsr& K, int w, double beta, int vbf) {
+  const double sz = sizeof(T), vs = vbf ? 2.0 : sz;
+  return 4.0 * (K.m + 1) + (4.0 + vs) * K.nnz + sz * w * ((double)K.n + K.m * (beta != 0.0 ? 2 : 1));
 }
 
 template <class T>
 void Solver::spmm(int l, const DCsr& K, const T* Kv, int w, const T* x, T* y, double beta) {
-  if (l == 0) prof(5, spmm_bytes<T>(K, w, beta), [&] { launch_spmm<T>(K.m, w, K.rp, K.ci, Kv, x, y, beta, st_, K.nnz); });
-  else launch_spmm<T>(K.m, w, K.rp, K.ci, Kv, x, y, beta, st_, K.nnz);
+  if (l == 0)
+    prof(5, spmm_bytes<T>(K, w, beta, vbf<T>()), [&] { launch_spmm<T>(K.m, w, K.rp, K.ci, Kv, x, y, beta, st_, K.nnz, vbf<T>()); });
+  else launch_spmm<T>(K.m, w, K.rp, K.ci, Kv, x, y, beta, st_, K.nnz, vbf<T>());
 }
 
 template <class T>
@@ -359,7 +371,8 @@ void Solver::spmm2(int l, const DCsr& Ka, const T* Kva, const T* xa, T* ya, cons
   SpmmArgs<T> a, b;
   a.m = Ka.m; a.nnz = Ka.nnz; a.rp = Ka.rp; a.ci = Ka.ci; a.v = Kva; a.x = xa; a.y = ya; a.beta = beta;
   b.m = Kb.m; b.nnz = Kb.nnz; b.rp = Kb.rp; b.ci = Kb.ci; b.v = Kvb; b.x = xb; b.y = yb; b.beta = beta;
-  if (l == 0) prof(5, spmm_bytes<T>(Ka, nb_, beta) + spmm_bytes<T>(Kb, nb_, beta), [&] { launch_spmm2(a, b, nb_, st_); });
+  a.vbf = b.vbf = vbf<T>();
+  if (l == 0) prof(5, spmm_bytes<T>(Ka, nb_, beta, a.vbf) + spmm_bytes<T>(Kb, nb_, beta, b.vbf), [&] { launch_spmm2(a, b, nb_, st_); });
   else launch_spmm2(a, b, nb_, st_);
 }
 
@@ -376,11 +389,12 @@ void Solver::dots(int l, const DotArgs<T>& a, const DCsr* K, double* out) {
 template <class T>
 void Solver::kacz(int l, const KaczArgs<T>& a0, long nnz_colour) {
   KaczArgs<T> a = a0;
+  a.vbf = vbf<T>();
   a.nnz_total = nnz_colour;
   a.nnz_rows = a.nrows;
-  const double sz = sizeof(T), w = a.w, r = a.nrows, z = (double)nnz_colour;
-  double b = r * (8.0 + 4.0 + sz) + (4.0 + sz) * z + 2.0 * sz * w * z;
-  if (a.bv) b += sz * z;
+  const double sz = sizeof(T), vs = a.vbf ? 2.0 : sz, w = a.w, r = a.nrows, z = (double)nnz_colour;
+  double b = r * (8.0 + 4.0 + sz) + (4.0 + vs) * z + 2.0 * sz * w * z;
+  if (a.bv) b += vs * z;
   if (a.lam) b += 2.0 * sz * r;
   if (a.rmode == M_IDENT) b += sz * w * r;
   if (a.kap) b += sz * w * r;
@@ -517,7 +531,7 @@ void Solver::refresh_level_aux(Level& L) {
     }
   }
   if (mixed_) {
-    auto cast = [&](const DCsr& a) { launch_copy_cast_df(a.v, a.vf, a.nnz, st_); };
+    auto cast = [&](const DCsr& a) { cast_vals(a); };
     cast(L.A);
     if (!spd_) { cast(L.At); cast(L.C); }
     cast(L.B);
@@ -1055,6 +1069,7 @@ void Solver::boot_relax(int l, const T* kap, const T* tau, const double* sig, in
       h[0].bv = L.finest ? nullptr : vals<T>(L.B); h[0].lam = sig;
       h[0].rn_aa = x.rnA; h[0].rn_ab = x.rnAab; h[0].rn_bb = x.rnAbb; h[0].kap = kap; h[0].x = b.Ub;
       cp[0] = L.d_kA_cptr; nc[0] = (int)L.kA_cptr.size() - 1;
+      h[0].vbf = vbf<T>();
       launch_kacz_wg<T>(h, cp, nc, 1, nsweeps, st_);
     } else {
       h[0].nnz_total = L.A.nnz; h[0].nnz_rows = L.A.m;
@@ -1067,6 +1082,7 @@ void Solver::boot_relax(int l, const T* kap, const T* tau, const double* sig, in
       h[1].Mv = vals<T>(L.C); h[1].y = b.Vb; h[1].rsig = sig; h[1].kap = tau; h[1].x = b.Ub;
       cp[0] = L.d_kA_cptr; nc[0] = (int)L.kA_cptr.size() - 1;
       cp[1] = L.d_kAt_cptr; nc[1] = (int)L.kAt_cptr.size() - 1;
+      h[0].vbf = h[1].vbf = vbf<T>();
       launch_kacz_wg<T>(h, cp, nc, 2, nsweeps, st_);
     }
     return;
@@ -1693,11 +1709,11 @@ void Solver::run(const double* init_tests, SolveOutput& out) {
   }
   if (mixed_) {
     for (auto& L : lv_) {
-      if (L->su.P.vf) launch_copy_cast_df(L->su.P.v, L->su.P.vf, L->su.P.nnz, st_);
-      if (L->su.Pt.vf) launch_copy_cast_df(L->su.Pt.v, L->su.Pt.vf, L->su.Pt.nnz, st_);
+      cast_vals(L->su.P);
+      cast_vals(L->su.Pt);
       if (!spd_) {
-        if (L->sv.P.vf) launch_copy_cast_df(L->sv.P.v, L->sv.P.vf, L->sv.P.nnz, st_);
-        if (L->sv.Pt.vf) launch_copy_cast_df(L->sv.Pt.v, L->sv.Pt.vf, L->sv.Pt.nnz, st_);
+        cast_vals(L->sv.P);
+        cast_vals(L->sv.Pt);
       }
     }
   }

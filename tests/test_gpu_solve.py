@@ -141,16 +141,36 @@ def test_init_tests_and_rectangular_transpose(ctx):
     assert np.allclose(A @ r.V, r.U * r.sigma, atol=1e-7)
 
 
-def test_mixed_precision_matches_fp64(ctx):
+@pytest.mark.parametrize("precision", ["mixed_fp32", "mixed_bf16"])
+def test_mixed_precision_matches_fp64(ctx, precision):
     from paper_1102_0919_amd import api
     wl = W.WORKLOADS["laplace2d_31_min4"]
     A = W.laplace2d(31).to_scipy()
     r64 = api.solve(ctx, A, "spd", "minimal", 4, api.params_init("spd", "minimal", **wl["params"]))
-    r32 = api.solve(ctx, A, "spd", "minimal", 4, api.params_init("spd", "minimal", precision="mixed_fp32",
+    r32 = api.solve(ctx, A, "spd", "minimal", 4, api.params_init("spd", "minimal", precision=precision,
                                                                  **wl["params"]))
     assert r32.converged
     _sig_close(r32.sigma, r64.sigma, r64.report.anorm)
     _check_triplets(A, r32, "spd", 1e-8, r64.report.anorm)
+
+
+def test_bf16_operator_values_rectangular_svd(ctx):
+    """BF16 operator values in the refinement form of a rectangular dominant solve: the FP64 outer
+    residual still reaches the tolerance, and the trajectory differs from the FP32-value run, which
+    shows that the V-cycle really read the 16-bit copies."""
+    from paper_1102_0919_amd import api
+    name = "gradient2d_256_dom8"
+    wl = W.WORKLOADS[name]
+    A = W.build_workload_matrix(name, 32).to_scipy()
+    res = {}
+    for prec in ("fp64", "mixed_fp32", "mixed_bf16"):
+        prm = dict(wl["params"]); prm["precision"] = prec
+        res[prec] = api.solve(ctx, A, wl["kind"], wl["target"], wl["n_b"], api.params_init(wl["kind"], wl["target"], **prm))
+        assert res[prec].converged, prec
+    sv = np.linalg.svd(A.toarray(), compute_uv=False)[:wl["n_b"]]
+    _sig_close(res["mixed_bf16"].sigma, sv, res["fp64"].report.anorm)
+    _check_triplets(A, res["mixed_bf16"], "svd", 1e-8, res["fp64"].report.anorm)
+    assert not np.array_equal(res["mixed_bf16"].U, res["mixed_fp32"].U)
 
 
 def test_pencil_variant_same_triplets(ctx):
