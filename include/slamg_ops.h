@@ -32,6 +32,13 @@ slamg_status slamg_op_spmm(int32_t m, int32_t w, const int32_t* d_rp, const int3
 /* The same product in FP32 (mixed-precision V-cycles). */
 slamg_status slamg_op_spmm_f32(int32_t m, int32_t w, const int32_t* d_rp, const int32_t* d_ci, const float* d_v,
                                const float* d_x, float* d_y, double beta, void* stream);
+/* The FP32 product reading BF16 operator values (SLAMG_MIXED_BF16 V-cycles): d_v holds nnz BF16 bit
+ * patterns (the high 16 bits of an FP32 word); x, y and the sums are FP32. */
+slamg_status slamg_op_spmm_bf16(int32_t m, int32_t w, const int32_t* d_rp, const int32_t* d_ci, const uint16_t* d_v,
+                                const float* d_x, float* d_y, double beta, void* stream);
+/* BF16 copy of n FP64 values as the SLAMG_MIXED_BF16 mode stores them: each value rounded to FP32,
+ * then to BF16, both to nearest with ties to even; a NaN stays a (quiet) NaN.  d_out: n uint16. */
+slamg_status slamg_op_cast_bf16(int64_t n, const double* d_in, uint16_t* d_out, void* stream);
 
 /* Test-vector relaxation, dominant targets (§3.4): one power step with one weighted-Jacobi inner
  * step of weight omega, normalised in the C / B norm.  SVD: A (m x n) and its transpose At, B

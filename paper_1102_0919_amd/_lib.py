@@ -70,6 +70,8 @@ SIGNATURES = {
     "slamg_last_error": (C.c_char_p, [_P]),
     "slamg_op_spmm": (_I, [_I, _I, _P, _P, _P, _P, _P, _D, _P]),
     "slamg_op_spmm_f32": (_I, [_I, _I, _P, _P, _P, _P, _P, _D, _P]),
+    "slamg_op_spmm_bf16": (_I, [_I, _I, _P, _P, _P, _P, _P, _D, _P]),
+    "slamg_op_cast_bf16": (_I, [C.c_int64, _P, _P, _P]),
     "slamg_op_relax_test": (_I, [_I, _I, _I, _I] + [_P] * 12 + [_D, _P, _P, _P]),
     "slamg_op_relax_boot": (_I, [_I, _I, _I, _I] + [_P] * 12 + [_P, _P, _P, _D, _P, _P, _P]),
     "slamg_op_kaczmarz": (_I, [_I, _I, _I, _P, _P, _P, _P, _P, _P, _P, _I, _P, _P, _P]),

@@ -116,6 +116,22 @@ extern "C" slamg_status slamg_op_spmm_f32(int32_t m, int32_t w, const int32_t* d
   return guarded(s, [&] { launch_spmm<float>(m, w, d_rp, d_ci, d_v, d_x, d_y, beta, s, dev_nnz(d_rp, m, s)); });
 }
 
+extern "C" slamg_status slamg_op_spmm_bf16(int32_t m, int32_t w, const int32_t* d_rp, const int32_t* d_ci,
+                                           const uint16_t* d_v, const float* d_x, float* d_y, double beta,
+                                           void* stream) {
+  if (m < 0 || bad_w(w)) return SLAMG_E_INVALID;
+  hipStream_t s = (hipStream_t)stream;
+  return guarded(s, [&] {
+    launch_spmm<float>(m, w, d_rp, d_ci, reinterpret_cast<const float*>(d_v), d_x, d_y, beta, s, dev_nnz(d_rp, m, s), 1);
+  });
+}
+
+extern "C" slamg_status slamg_op_cast_bf16(int64_t n, const double* d_in, uint16_t* d_out, void* stream) {
+  if (n < 0 || (n > 0 && (!d_in || !d_out))) return SLAMG_E_INVALID;
+  hipStream_t s = (hipStream_t)stream;
+  return guarded(s, [&] { launch_cast_bf16(d_in, d_out, (size_t)n, s); });
+}
+
 extern "C" slamg_status slamg_op_relax_test(int32_t spd, int32_t m, int32_t n, int32_t w, const int32_t* d_arp,
                                             const int32_t* d_aci, const double* d_av, const int32_t* d_atrp,
                                             const int32_t* d_atci, const double* d_atv, const int32_t* d_brp,

@@ -66,6 +66,77 @@ def test_spmm_f32_parity(L):
     _close(host(dy), ref, abs(M) @ abs(X), rel=40 * 6e-8)
 
 
+def _bf16_nearest(x):
+    """BF16 bit patterns of FP64 values by the definition: x rounded to FP32, then the nearer of the
+    two BF16 neighbours of that FP32 value (ties to the even pattern; past the largest finite BF16
+    the upper neighbour is 2^128, i.e. infinity).  NaN inputs are not handled here."""
+    f = np.asarray(x, np.float64).astype(np.float32)
+    u = f.view(np.uint32)
+    sign = u & np.uint32(0x80000000)
+    mag = u & np.uint32(0x7FFFFFFF)
+    lo = (mag >> 16).astype(np.uint64)                  # truncated pattern (toward zero)
+    hi = lo + 1
+    def val(pat):
+        pat = np.asarray(pat, np.uint64)
+        out = (pat.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+        return np.where(pat >= 0x7F80, 2.0 ** 128, out)
+    a = np.abs(f.astype(np.float64))
+    dlo, dhi = a - val(lo), val(hi) - a
+    pick_hi = (dhi < dlo) | ((dhi == dlo) & (lo % 2 == 1))
+    pat = np.where(np.isinf(f), 0x7F80, np.where(pick_hi, hi, lo)).astype(np.uint32)
+    return ((sign >> 16) | pat).astype(np.uint16)
+
+
+def test_cast_bf16_bit_exact(L):
+    rng = np.random.default_rng(16)
+    special = [  # (value, its BF16 pattern)
+        (0.0, 0x0000), (-0.0, 0x8000), (1.0, 0x3F80),
+        (1 + 2 ** -8, 0x3F80),        # halfway between 1 and 1 + 2^-7: the even pattern, 1
+        (1 + 3 * 2 ** -8, 0x3F82),    # halfway between 1 + 2^-7 and 1 + 2^-6: the even one, 1 + 2^-6
+        (-(1 + 2 ** -8), 0xBF80),
+        (2.0 ** -133, 0x0001),        # smallest subnormal BF16
+        (3.3895313892515355e38, 0x7F7F),   # largest finite BF16
+        (3.39e38, 0x7F7F),            # below the halfway point to 2^128
+        (3.4e38, 0x7F80),             # above it: infinity
+        (1e300, 0x7F80), (-1e300, 0xFF80), (np.inf, 0x7F80), (-np.inf, 0xFF80),
+    ]
+    x = np.concatenate([rng.standard_normal(20000) * 10.0 ** rng.uniform(-40, 40, 20000),
+                        [v for v, _ in special]])
+    d_in = dev(x)
+    d_out = dev(np.zeros(x.size, np.int16))
+    assert L.slamg_op_cast_bf16(x.size, ptr(d_in), ptr(d_out), None) == 0
+    got = host(d_out).view(np.uint16)
+    with np.errstate(over="ignore"):
+        ref = _bf16_nearest(x)
+    assert np.array_equal(got, ref), np.flatnonzero(got != ref)[:10]
+    for i, (v, pat) in enumerate(special):
+        assert got[20000 + i] == pat, (v, hex(got[20000 + i]))
+    nan = dev(np.array([np.nan, -np.nan]))
+    d2 = dev(np.zeros(2, np.int16))
+    assert L.slamg_op_cast_bf16(2, ptr(nan), ptr(d2), None) == 0
+    g = host(d2).view(np.uint16)
+    assert np.all((g & 0x7F80) == 0x7F80) and np.all((g & 0x7F) != 0)
+
+
+@pytest.mark.parametrize("w,mean_row", [(8, 7), (3, 7), (8, 40), (16, 80)])
+def test_spmm_bf16_parity(L, w, mean_row):
+    A = W.random_csr(2500, 1900, seed=40 + w, mean_row=mean_row).to_scipy()
+    M = sp.csr_matrix(A); M.sort_indices()
+    bits = _bf16_nearest(M.data)
+    vals = (bits.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    X = W.seeded_block(1900, w, seed=41 + w).astype(np.float32)
+    Y0 = W.seeded_block(2500, w, seed=42 + w).astype(np.float32)
+    rp, ci = dev(M.indptr, np.int32), dev(M.indices, np.int32)
+    v = dev(bits.view(np.int16))
+    dx, dy = dev(X), dev(Y0)
+    assert L.slamg_op_spmm_bf16(2500, w, ptr(rp), ptr(ci), ptr(v), ptr(dx), ptr(dy), 0.5, None) == 0
+    Mb = sp.csr_matrix((vals, M.indices, M.indptr), shape=M.shape)
+    ref = Mb @ X.astype(np.float64) + 0.5 * Y0.astype(np.float64)
+    # FP32 products and sums of exactly representable BF16 values: (len + 2) u32 sum |a||x|
+    row_len = np.diff(M.indptr).max()
+    _close(host(dy), ref, abs(Mb) @ abs(X.astype(np.float64)) + 0.5 * abs(Y0), rel=(row_len + 3) * 6e-8)
+
+
 def _svd_level(m, n, seed, coarse):
     rng = np.random.default_rng(seed)
     A = sp.csr_matrix(W.random_csr(m, n, seed=seed, mean_row=5, empty_rows=False).to_scipy())
