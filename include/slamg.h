@@ -99,7 +99,12 @@ typedef struct {
   int32_t graphs;           /* 1: capture one additive iteration (V-cycle, Ritz step, residual
                                reductions) in a HIP graph and replay it; 0: launch every kernel
                                on the stream.  Both give bitwise the same results (1)           */
-  int32_t reserved[2];
+  int32_t square_coarsening;  /* SVD of a square A (§5.1): strength, C/F split and interpolatory
+                               sets of both sides from A itself, so P and Q share one pattern and
+                               every level is square; the LS weights of P and Q are fitted
+                               separately.  Needs a square matrix without empty rows or
+                               columns (SLAMG_E_INVALID otherwise); ignored for SPD (0)         */
+  int32_t reserved[1];
 } slamg_params;
 
 /* Report of one solve.  Arrays are filled up to the counts given. */

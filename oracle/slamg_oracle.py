@@ -90,6 +90,7 @@ class Params:
     coarse_pinv: int = 0          # 0 Euclidean SVD pseudo-inverse (literal), 1 pencil variant
     ritz_in_mult: int = 1
     u_from_v: int = 0             # R23: minimal SVD, u_j <- A v_j / ||A v_j|| after each Ritz step
+    square_coarsening: int = 0    # §5.1: square A, both sides coarsened on A itself (R28)
 
 
 NORM_SEED_XOR = 0xA5A5A5A5A5A5A5A5
@@ -591,6 +592,13 @@ def strength_operators(lev, kind, params, finest=True):
     return structural_product(A, At), structural_product(At, A)
 
 
+def shared_side(su):
+    """§5.1 (R28): the v-side takes the u-side's C/F split and interpolatory sets; only the LS
+    weights (fitted to V instead of U) differ, so P and Q share one pattern and every A_l is
+    square."""
+    return Side(su.is_c.copy(), su.cpts.copy(), su.ptr.copy(), su.fine_cols.copy(), 0)
+
+
 def build_side(N, params, n_t):
     Sp, Si = strength_sets(N, params.theta, params.strength_rule, params.top_s)
     is_c = rs_coarsen(Sp, Si, N.shape[0])
@@ -694,9 +702,14 @@ class Solver:
             if c == 1:
                 if self._is_coarsest_size(l):
                     break
-                Nu, Nv = strength_operators(lev, kind, p, l == 0)
-                su = build_side(Nu, p, p.n_t)
-                sv = None if kind == SPD else build_side(Nv, p, p.n_t)
+                if kind == SVD and p.square_coarsening:
+                    # §5.1: strength, C/F split and patterns of both sides from A itself
+                    su = build_side(lev.A, p, p.n_t)
+                    sv = shared_side(su)
+                else:
+                    Nu, Nv = strength_operators(lev, kind, p, l == 0)
+                    su = build_side(Nu, p, p.n_t)
+                    sv = None if kind == SPD else build_side(Nv, p, p.n_t)
                 su, sv = one_sided_coarsening(su, sv, kind, self.n_b + p.n_t)
                 if not self._coarsening_ok(lev, su, sv):
                     break
@@ -888,6 +901,8 @@ def solve(A, kind, target, n_b, params: Params | None = None, init=None) -> Resu
     else:
         Ar = A[rows_keep][:, cols_keep]
     Ar = sp.csr_matrix(Ar); Ar.sort_indices()
+    if kind == SVD and params.square_coarsening and Ar.shape[0] != Ar.shape[1]:
+        raise ValueError("square coarsening needs a square matrix without empty rows or columns")
     s = Solver(Ar, kind, target, n_b, params, init)
     sig, U, V = s.run()
     Ufull = np.zeros((m, n_b)); Ufull[rows_keep] = U

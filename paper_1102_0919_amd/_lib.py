@@ -32,8 +32,8 @@ class Params(C.Structure):
                 ("coarse_max", C.c_int32), ("max_levels", C.c_int32), ("stall_ratio", C.c_double),
                 ("tol", C.c_double), ("seed", C.c_uint64), ("precision", C.c_int32),
                 ("ritz_in_mult", C.c_int32), ("coarse_pinv", C.c_int32), ("profile_mask", C.c_int32),
-                ("verbose", C.c_int32), ("graphs", C.c_int32),
-                ("reserved", C.c_int32 * 2)]
+                ("verbose", C.c_int32), ("graphs", C.c_int32), ("square_coarsening", C.c_int32),
+                ("reserved", C.c_int32 * 1)]
 
 
 class Report(C.Structure):

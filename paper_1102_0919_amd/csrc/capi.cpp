@@ -260,6 +260,10 @@ static slamg_status check_params(std::string& err, const Prepared& P, int32_t nb
   if (p.precision != SLAMG_FP64 && p.precision != SLAMG_MIXED_FP32 && p.precision != SLAMG_MIXED_BF16)
     return fail(err, SLAMG_E_INVALID, "unknown precision");
   if (p.coarse_pinv != 0 && p.coarse_pinv != 1) return fail(err, SLAMG_E_INVALID, "unknown coarse_pinv");
+  if (p.square_coarsening != 0 && p.square_coarsening != 1)
+    return fail(err, SLAMG_E_INVALID, "square_coarsening must be 0 or 1");
+  if (p.square_coarsening && P.kind == SLAMG_SVD && P.A.m != P.A.n)
+    return fail(err, SLAMG_E_INVALID, "square coarsening needs a square matrix without empty rows or columns");
   if (p.strength_rule < 0 || p.strength_rule > 2) return fail(err, SLAMG_E_INVALID, "unknown strength rule");
   if (nb > std::min(P.m0, P.n0)) return fail(err, SLAMG_E_INVALID, "n_b larger than min(m, n)");
   if (nb > std::min(P.A.m, P.A.n)) return fail(err, SLAMG_E_INVALID, "n_b larger than the nonzero part of A");

@@ -172,7 +172,8 @@ class Solver {
   Solver(hipStream_t s, size_t budget, const Problem& pb, const slamg_params& p)
       : st_(s), ar_(budget, s), p_(p), spd_(pb.kind == SLAMG_SPD_EIG), minimal_(pb.target == SLAMG_MINIMAL),
         nb_(pb.nb), nt_(p.n_t), mixed_(p.precision == SLAMG_MIXED_FP32 || p.precision == SLAMG_MIXED_BF16),
-        bf16_(p.precision == SLAMG_MIXED_BF16), A0_(pb.A), pb_(pb) {}
+        bf16_(p.precision == SLAMG_MIXED_BF16),
+        square_(pb.kind == SLAMG_SVD && p.square_coarsening != 0), A0_(pb.A), pb_(pb) {}
   ~Solver() {
     if (igx_) (void)hipGraphExecDestroy(igx_);
     if (ig_) (void)hipGraphDestroy(ig_);
@@ -234,6 +235,7 @@ class Solver {
   int nb_, nt_;
   bool mixed_;
   bool bf16_;   // the FP32 V-cycle reads BF16 operator values (their bit patterns in the .vf arrays)
+  bool square_; // SVD of a square A with both sides coarsened on A itself (§5.1)
   // low-precision copy of an operator's values for the FP32 V-cycle: FP32, or BF16 bit patterns
   void cast_vals(const DCsr& a) {
     if (!a.vf) return;
@@ -709,9 +711,10 @@ void Solver::norm_estimate() {
 // Hierarchy structure (first multiplicative cycle only)
 // ------------------------------------------------------------------------------------------------
 HCsr Solver::strength_operator(Level& L, bool u_side, bool finest) {
-  // Eigenproblems measure strength on A itself (§5.2); SVD on A A^t (u) and A^t A (v) (§3.7).
+  // Eigenproblems (§5.2) and square coarsening (§5.1) measure strength on A itself; SVD otherwise
+  // on A A^t (u) and A^t A (v) (§3.7).
   HCsr N;
-  if (spd_) {
+  if (spd_ || square_) {
     N = L.hA;
     if (finest) N.v = A0_.v;
     else d2h(N.v, L.A.v, L.A.nnz, st_);
@@ -815,7 +818,12 @@ bool Solver::build_structure(int l) {
   Side su, sv;
   build_side(L, su, Nu, L.m);
   HCsr Nv;
-  if (!spd_) {
+  if (square_) {
+    // §5.1: the v-side takes the u-side's C/F split and interpolatory sets (one pattern for P and
+    // Q, square levels); only its LS weights differ
+    sv = su;
+    sv.capped = 0;
+  } else if (!spd_) {
     Nv = strength_operator(L, false, l == 0);
     build_side(L, sv, Nv, L.n);
   }

@@ -79,6 +79,22 @@ def laplace2d(k: int) -> CSR:
     return _coo_to_csr(k * k, k * k, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals))
 
 
+def convdiff2d(k: int, c: float = 0.5) -> CSR:
+    """Upwind convection-diffusion -Laplace(u) + c (u_x + u_y), Dirichlet, k x k interior points,
+    id = y*k + x, in grid units: diagonal 4 + 2c, -(1 + c) to the west and south (upwind)
+    neighbours, -1 to the east and north ones.  A square nonsymmetric M-matrix."""
+    rows, cols, vals = [], [], []
+    idx = np.arange(k * k).reshape(k, k)          # [y, x]
+    rows.append(idx.ravel()); cols.append(idx.ravel()); vals.append(np.full(k * k, 4.0 + 2.0 * c))
+    for dy, dx, w in ((0, 1, -1.0), (0, -1, -1.0 - c), (1, 0, -1.0), (-1, 0, -1.0 - c)):
+        ys, xs = np.meshgrid(np.arange(k), np.arange(k), indexing="ij")
+        ny, nx = ys + dy, xs + dx
+        ok = (ny >= 0) & (ny < k) & (nx >= 0) & (nx < k)
+        rows.append(idx[ys[ok], xs[ok]]); cols.append(idx[ny[ok], nx[ok]])
+        vals.append(np.full(int(ok.sum()), w))
+    return _coo_to_csr(k * k, k * k, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals))
+
+
 def aniso3d(k: int, eps: float = 0.01) -> CSR:
     """7-point anisotropic Dirichlet diffusion on k^3 points, id = (z*k + y)*k + x.
 
@@ -253,6 +269,16 @@ WORKLOADS = {
     "gradient2d_256_min8": dict(desc="discrete gradient of the 256x256 grid graph (130560x65536), 8 minimal triplets, FP64",
                                 kind="svd", target="minimal", n_b=8,
                                 params=dict(theta=0.05, n_t=8, mu_t=4, mu_b=4, n_mult=10)),
+    # §6.1's square nonsymmetric case (31 x 31 interior points, n_b = 8, n_t = 5, mu_t = mu_b = 4,
+    # theta = 0.05, both sides coarsened on A); its FVE operator is not given, an upwind
+    # convection-diffusion matrix of the same size stands in.  The minimal run takes n_t = 8: with
+    # 5 test vectors it settles on interior triplets of this operator
+    "convdiff2d_31_dom8": dict(desc="upwind convection-diffusion 31x31 (n=961, nonsymmetric), 8 dominant triplets, square coarsening",
+                               kind="svd", target="dominant", n_b=8,
+                               params=dict(theta=0.05, n_t=5, mu_t=4, mu_b=4, n_mult=10, square_coarsening=1)),
+    "convdiff2d_31_min8": dict(desc="upwind convection-diffusion 31x31 (n=961, nonsymmetric), 8 minimal triplets, square coarsening",
+                               kind="svd", target="minimal", n_b=8,
+                               params=dict(theta=0.05, n_t=8, mu_t=4, mu_b=4, n_mult=10, square_coarsening=1)),
     "termdoc_200k_dom10": dict(desc="Zipf term-document matrix 200000x50000, 60 nnz/column, 10 dominant triplets",
                                kind="svd", target="dominant", n_b=10,
                                params=dict(strength_rule=2, top_s=4, df_filter=0.01, n_t=14, mu_t=1,
@@ -274,6 +300,8 @@ def build_workload_matrix(name: str, scale: int | None = None) -> CSR:
         return laplace2d(scale or 32)
     if name.startswith("gradient2d_256"):
         return gradient2d(scale or 256)
+    if name.startswith("convdiff2d_31"):
+        return convdiff2d(scale or 31)
     if name.startswith("termdoc_200k"):
         n = scale or 50000
         return termdoc(4 * n, n, 60, seed=1102)

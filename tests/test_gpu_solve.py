@@ -104,6 +104,33 @@ def test_gradient32_dominant_vs_oracle(ctx):
     assert r.report.levels == o.report["levels"]
 
 
+@pytest.mark.parametrize("name", ["convdiff2d_31_dom8", "convdiff2d_31_min8"])
+def test_square_coarsening_vs_oracle(ctx, name):
+    # §5.1 / §6.1 setup: both sides coarsened on A; device and oracle build the same square
+    # hierarchy and reach the extremal triplets of the dense SVD
+    from paper_1102_0919_amd import api
+    A, wl, r, o = _run_both(ctx, name)
+    rep = api.report_dict(r.report)
+    assert r.converged and o.report["converged"]
+    sv = np.linalg.svd(A.toarray(), compute_uv=False)
+    ref = sv[:8] if wl["target"] == "dominant" else np.sort(sv)[:8]
+    _sig_close(r.sigma, ref, rep["anorm"])
+    _sig_close(r.sigma, o.sigma, rep["anorm"])
+    _check_triplets(A, r, "svd", 1e-8, rep["anorm"])
+    assert rep["sizes"] == [tuple(s) for s in o.report["sizes"]]
+    assert all(a == b for a, b in rep["sizes"])
+    ms = np.array([r.report.mult_sigma[0][j] for j in range(8)])
+    assert np.allclose(ms, o.report["mult_sigma"][0], rtol=1e-7)
+    assert abs(rep["add_iters"] - o.report["add_iters"]) <= 2
+
+
+def test_square_coarsening_rejects_rectangular(ctx):
+    from paper_1102_0919_amd import api
+    A = W.gradient2d(8).to_scipy()
+    with pytest.raises(api.SlamgError, match="E_INVALID"):
+        api.solve(ctx, A, "svd", "dominant", 2, api.params_init("svd", "dominant", square_coarsening=1, n_t=4))
+
+
 def test_square_nonsymmetric_minimal(ctx):
     from paper_1102_0919_amd import api
     k = 10

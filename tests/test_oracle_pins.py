@@ -450,3 +450,47 @@ def test_one_sided_coarsening_identity_side_and_spectrum():
     # the side rule itself: identity only for a collapsing side next to a coarsening one
     su = O.identity_side(5)
     assert su.is_c.all() and list(su.cpts) == list(range(5)) and list(su.ptr) == list(range(6))
+
+
+# ---------------------------------------------------------------------------- §5.1 square coarsening
+def test_convdiff_matrix_definition():
+    # the stand-in operator: row sums 2c at interior points (diffusion sums to zero, the two
+    # upwind differences add c + c), west/south entries -(1 + c), east/north -1
+    k, c = 5, 0.5
+    A = W.convdiff2d(k, c).to_scipy().toarray()
+    i = 2 * k + 2
+    assert A[i, i] == 4 + 2 * c and A[i, i - 1] == -1 - c and A[i, i - k] == -1 - c
+    assert A[i, i + 1] == -1 and A[i, i + k] == -1
+    assert np.allclose(A.sum(axis=1)[i], 0.0)
+    assert not np.allclose(A, A.T)
+
+
+@pytest.mark.parametrize("name", ["convdiff2d_31_dom8", "convdiff2d_31_min8"])
+def test_square_coarsening_triplets_and_structure(name):
+    # §5.1 / §6.1: both sides coarsened on A keep every level square, P and Q share one pattern
+    # with their own weights, and the triplets are the extremal ones of the dense SVD
+    wl = W.WORKLOADS[name]
+    A = W.build_workload_matrix(name).to_scipy()
+    r = O.solve(A, "svd", wl["target"], wl["n_b"], O.Params(**wl["params"]))
+    sv = np.linalg.svd(A.toarray(), compute_uv=False)
+    ref = sv[:8] if wl["target"] == "dominant" else np.sort(sv)[:8]
+    assert r.report["converged"]
+    assert np.all(np.abs(r.sigma - ref) <= 1e-10 * ref)
+    assert all(a == b for a, b in r.report["sizes"])
+    assert r.report["levels"] >= 3
+    for lev in r.report["solver"].levels[:-1]:
+        su, sv_ = lev.su, lev.sv
+        assert np.array_equal(su.is_c, sv_.is_c) and np.array_equal(su.fine_cols, sv_.fine_cols)
+        assert np.array_equal(su.P.indptr, sv_.P.indptr) and np.array_equal(su.P.indices, sv_.P.indices)
+        assert not np.allclose(su.P.data, sv_.P.data)
+    # the default (A A^t / A^t A) coarsening of the same matrix gives different sides
+    p = dict(wl["params"]); p["square_coarsening"] = 0; p["max_add"] = 0
+    r0 = O.solve(A, "svd", wl["target"], wl["n_b"], O.Params(**p))
+    lev0 = r0.report["solver"].levels[0]
+    assert not np.array_equal(lev0.su.is_c, lev0.sv.is_c)
+
+
+def test_square_coarsening_rejects_rectangular():
+    A = W.gradient2d(6).to_scipy()
+    with pytest.raises(ValueError):
+        O.solve(A, "svd", "dominant", 2, O.Params(square_coarsening=1, n_t=4))
