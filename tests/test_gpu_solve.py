@@ -354,3 +354,52 @@ def test_termdoc_one_sided_coarsening_vs_oracle(ctx):
     for j in range(10):
         assert np.min(np.abs(s - r.sigma[j])) <= res[j] * r.report.anorm * 1.01 + 1e-12
     _sig_close(r.sigma[:5], s[:5], r.report.anorm, rel=1e-10)
+
+
+# ------------------------------------------------------------------------------------------------
+# Block-width extremes and empty rows / columns (R2) against the oracle and the dense spectrum
+# ------------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("kind,k,nb,prm", [
+    ("spd", 20, 1, dict(theta=0.06, n_t=6, mu_t=8, mu_b=4, n_mult=10)),
+    ("spd", 20, 16, dict(theta=0.06, n_t=8, mu_t=8, mu_b=4, n_mult=10)),
+    ("svd", 20, 1, dict(theta=0.05, n_t=8, mu_t=4, mu_b=4, n_mult=10)),
+])
+def test_block_width_extremes_vs_oracle(ctx, kind, k, nb, prm):
+    from paper_1102_0919_amd import api
+    A = (W.laplace2d(k) if kind == "spd" else W.gradient2d(k)).to_scipy()
+    prm = dict(prm, max_add=400)
+    r = api.solve(ctx, A, kind, "dominant", nb, api.params_init(kind, "dominant", **prm))
+    o = O.solve(A, kind, "dominant", nb, O.Params(**prm))
+    assert r.converged and o.report["converged"]
+    if kind == "spd":
+        ref = np.sort(np.linalg.eigvalsh(A.toarray()))[::-1][:nb]
+    else:
+        ref = np.linalg.svd(A.toarray(), compute_uv=False)[:nb]
+    _sig_close(r.sigma, ref, r.report.anorm)
+    _sig_close(r.sigma, o.sigma, r.report.anorm)
+    _check_triplets(A, r, kind, 1e-8, r.report.anorm)
+    assert abs(r.report.add_iters - o.report["add_iters"]) <= 2
+
+
+def test_empty_rows_and_columns_reinserted(ctx):
+    # R2: empty rows and columns are removed before the solve and come back as zero entries of the
+    # singular vectors
+    from paper_1102_0919_amd import api
+    G = W.gradient2d(12).to_scipy().tocoo()
+    m, n = G.shape
+    rng = np.random.default_rng(5)
+    rmap = np.sort(rng.choice(m + 20, m, replace=False))
+    cmap = np.sort(rng.choice(n + 10, n, replace=False))
+    A = sp.csr_matrix((G.data, (rmap[G.row], cmap[G.col])), shape=(m + 20, n + 10))
+    prm = dict(theta=0.05, n_t=8, mu_t=4, mu_b=4, n_mult=10, max_add=400)
+    r = api.solve(ctx, A, "svd", "dominant", 4, api.params_init("svd", "dominant", **prm))
+    o = O.solve(A, "svd", "dominant", 4, O.Params(**prm))
+    assert r.converged
+    sv = np.linalg.svd(A.toarray(), compute_uv=False)[:4]
+    _sig_close(r.sigma, sv, r.report.anorm)
+    _sig_close(r.sigma, o.sigma, r.report.anorm)
+    _check_triplets(A, r, "svd", 1e-8, r.report.anorm)
+    empty_r = np.setdiff1d(np.arange(m + 20), rmap)
+    empty_c = np.setdiff1d(np.arange(n + 10), cmap)
+    assert np.all(r.U[empty_r] == 0.0) and np.all(r.V[empty_c] == 0.0)
+    assert r.U.shape == (m + 20, 4) and r.V.shape == (n + 10, 4)
