@@ -119,7 +119,7 @@ def main():
                     help="additive iteration cap (the solve stops earlier once every residual is below 1e-8)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the single-GPU "
+        print(f"bench.py: this benchmark runs on one GPU only (asked for --gpus {args.gpus}); the single-GPU "
               "figure is the whole measurement", file=sys.stderr)
         sys.exit(2)
 

@@ -49,6 +49,8 @@ the design notes of the repository):
       strength operator N (A for eigenproblems, A A^t and A^t A for SVD).
   R27 one-sided coarsening: on an SVD level where one side would keep fewer than n_b + n_t
       C-points while the other coarsens, that side keeps all its points (identity interpolation).
+  R28 square coarsening (§5.1, optional): strength on A itself, and the v-side takes the u-side's
+      C/F split and interpolatory sets, so P and Q share one pattern and every level is square.
 """
 from __future__ import annotations
 
