@@ -133,6 +133,44 @@ def gradient2d(k: int) -> CSR:
     return _coo_to_csr(2 * nh, k * k, rows, cols, vals)
 
 
+def termdoc_topics(m: int, n: int, per_col: int = 60, n_topics: int = 40, zipf_s: float = 1.1,
+                   topic_s: float = 1.5, background: float = 0.15, geom_p: float = 0.3,
+                   seed: int = 1102) -> CSR:
+    """Synthetic term-document matrix (terms x documents) with topic structure and raw counts.
+
+    Topic k of ``n_topics`` has weight proportional to k^-topic_s; each document belongs to one
+    topic drawn from those weights.  A document's ``per_col`` distinct terms are drawn in order:
+    with probability ``background`` from a shared background vocabulary, else from its topic's;
+    within a vocabulary a term's rank follows a Zipf law with exponent ``zipf_s`` on 1..m (inverse
+    CDF of the normalised r^-s) and the rank maps to a term id through that vocabulary's seeded
+    permutation.  Entry (term, document) is the term's count, drawn from the geometric law on
+    {1, 2, ...} with success probability ``geom_p``.  numpy's PCG64 seeded with ``seed`` drives all
+    draws.  The dominant singular values then fall off with gaps like those of real term-document
+    data (a common-vocabulary value, then one per topic).
+    """
+    rng = np.random.default_rng(seed)
+    weights = np.arange(1, m + 1, dtype=np.float64) ** (-zipf_s)
+    cdf = np.cumsum(weights); cdf /= cdf[-1]
+    tw = np.arange(1, n_topics + 1, dtype=np.float64) ** (-topic_s); tw /= tw.sum()
+    perms = np.stack([rng.permutation(m) for _ in range(n_topics + 1)])   # row n_topics: background
+    topic = rng.choice(n_topics, size=n, p=tw)
+    rows = np.empty(n * per_col, dtype=np.int64)
+    cols = np.repeat(np.arange(n, dtype=np.int64), per_col)
+    vals = np.empty(n * per_col, dtype=np.float64)
+    for j in range(n):
+        picked = np.empty(0, dtype=np.int64)
+        while picked.size < per_col:
+            k = 2 * per_col
+            src = np.where(rng.random(k) < background, n_topics, topic[j])
+            ranks = np.minimum(np.searchsorted(cdf, rng.random(k), side="right"), m - 1)
+            cand = np.concatenate([picked, perms[src, ranks]])
+            _, first = np.unique(cand, return_index=True)
+            picked = cand[np.sort(first)][:per_col]
+        rows[j * per_col:(j + 1) * per_col] = picked
+        vals[j * per_col:(j + 1) * per_col] = rng.geometric(geom_p, per_col).astype(np.float64)
+    return _coo_to_csr(m, n, rows, cols, vals)
+
+
 def termdoc(m: int, n: int, per_col: int = 60, zipf_s: float = 1.1, geom_p: float = 0.3,
             seed: int = 1102) -> CSR:
     """Synthetic term-document matrix (terms x documents).
@@ -304,7 +342,7 @@ def build_workload_matrix(name: str, scale: int | None = None) -> CSR:
         return convdiff2d(scale or 31)
     if name.startswith("termdoc_200k"):
         n = scale or 50000
-        return termdoc(4 * n, n, 60, seed=1102)
+        return termdoc_topics(4 * n, n, 60, seed=1102)
     if name.startswith("aniso3d_128"):
         return aniso3d(scale or 128, 0.01)
     raise KeyError(name)

@@ -333,7 +333,7 @@ def test_termdoc_one_sided_coarsening_vs_oracle(ctx):
     import scipy.sparse.linalg as sla
     from paper_1102_0919_amd import api
     wl = W.WORKLOADS["termdoc_200k_dom10"]
-    A = W.build_workload_matrix("termdoc_200k_dom10", 400).to_scipy()
+    A = W.termdoc(1600, 400, 60, seed=1102).to_scipy()   # the single-vocabulary Zipf generator
     prm = dict(wl["params"], coarse_pinv=1, max_add=20)
     r = api.solve(ctx, A, "svd", "dominant", 10, api.params_init("svd", "dominant", **prm))
     o = O.solve(A, "svd", "dominant", 10, O.Params(**prm))
@@ -403,3 +403,18 @@ def test_empty_rows_and_columns_reinserted(ctx):
     empty_c = np.setdiff1d(np.arange(n + 10), cmap)
     assert np.all(r.U[empty_r] == 0.0) and np.all(r.V[empty_c] == 0.0)
     assert r.U.shape == (m + 20, 4) and r.V.shape == (n + 10, 4)
+
+
+def test_termdoc_topics_reduced_vs_oracle(ctx):
+    # the topic-structured term-document stand-in at 4000 x 1000: device and oracle build the same
+    # hierarchy and reach the ten dominant triplets of the dense SVD
+    from paper_1102_0919_amd import api
+    A, wl, r, o = _run_both(ctx, "termdoc_200k_dom10", scale=1000, max_add=200)
+    rep = api.report_dict(r.report)
+    assert r.converged and o.report["converged"]
+    sv = np.linalg.svd(A.toarray(), compute_uv=False)[:10]
+    _sig_close(r.sigma, sv, rep["anorm"])
+    _sig_close(r.sigma, o.sigma, rep["anorm"])
+    _check_triplets(A, r, "svd", 1e-8, rep["anorm"])
+    assert rep["sizes"] == [tuple(s) for s in o.report["sizes"]]
+    assert abs(rep["add_iters"] - o.report["add_iters"]) <= 3

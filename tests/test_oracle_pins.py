@@ -434,7 +434,7 @@ def test_one_sided_coarsening_identity_side_and_spectrum():
     # values found through that hierarchy are those of ARPACK (a library routine independent of
     # the oracle)
     import scipy.sparse.linalg as spla
-    A = W.build_workload_matrix("termdoc_200k_dom10", 400).to_scipy()
+    A = W.termdoc(1600, 400, 60, seed=1102).to_scipy()   # the single-vocabulary Zipf generator
     wl = W.WORKLOADS["termdoc_200k_dom10"]
     prm = dict(wl["params"], coarse_pinv=1, max_add=20)
     s = O.Solver(A[np.diff(A.indptr) > 0], "svd", "dominant", 10, O.Params(**prm))
