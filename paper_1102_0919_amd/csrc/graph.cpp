@@ -1,60 +1,99 @@
 // Host-side graph work of the first multiplicative cycle (§3.7): strength of connection,
 // Algorithm 1 (one-pass Ruge-Stueben coarsening), interpolatory sets and the sparsity patterns of
 // P and Q, plus the symbolic sparse products of the Galerkin operators, transposes and the greedy
-// multicolouring that orders the Kaczmarz sweeps.  These steps are sequential graph algorithms and
-// run once per level; every numeric step runs in the HIP kernels.
+// multicolouring that orders the Kaczmarz sweeps.  They run once per level; every numeric step runs
+// in the HIP kernels.  Algorithm 1 and the colouring are sequential; the strength sets and the
+// symbolic products are built row by row on several host threads (identical results).
 #include "graph.h"
 
 #include <algorithm>
 #include <cmath>
 #include <queue>
 #include <stdexcept>
+#include <thread>
 
 namespace slamg {
+
+// Row-parallel construction of a CSR pattern: rows [0, n) in contiguous chunks, one host thread
+// per chunk.  make_row() gives each chunk its own row builder (with its own scratch), and
+// row(i, out) appends row i's entries to the chunk's list.  The chunks are joined in row order, so
+// the result does not depend on the number of threads.
+template <class M>
+static void build_rows(int n, std::vector<int>& rp, std::vector<int>& ci, M make_row) {
+  const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const int nt = n >= 8192 ? (int)hw : 1;
+  std::vector<std::vector<int>> part(nt), len(nt);
+  auto work = [&](int t) {
+    const int r0 = (int)((long)n * t / nt), r1 = (int)((long)n * (t + 1) / nt);
+    auto row_fn = make_row();
+    len[t].resize(r1 - r0);
+    for (int i = r0; i < r1; ++i) {
+      const size_t before = part[t].size();
+      row_fn(i, part[t]);
+      len[t][i - r0] = (int)(part[t].size() - before);
+    }
+  };
+  if (nt == 1) {
+    work(0);
+  } else {
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t) th.emplace_back(work, t);
+    for (auto& x : th) x.join();
+  }
+  rp.assign(n + 1, 0);
+  size_t total = 0;
+  for (int t = 0; t < nt; ++t) total += part[t].size();
+  ci.clear();
+  ci.reserve(total);
+  int i = 0;
+  for (int t = 0; t < nt; ++t) {
+    for (int l : len[t]) { rp[i + 1] = rp[i] + l; ++i; }
+    ci.insert(ci.end(), part[t].begin(), part[t].end());
+  }
+}
 
 // S_i = { j != i : |n_ij| > 0 and the rule holds }, returned as a CSR pattern (sorted).
 //  rule 0: |n_ij| >= theta * sum_k |n_ik|   (the row-sum condition of §3.7, all k)
 //  rule 1: |n_ij| >= theta * max_{k != i} |n_ik|
 //  rule 2: the top_s largest off-diagonal |n_ij| (ties to the lower j)
 void strength_sets(const HCsr& N, double theta, int rule, int top_s, std::vector<int>& Sp, std::vector<int>& Si) {
-  const int n = N.m;
-  Sp.assign(n + 1, 0);
-  Si.clear();
-  std::vector<std::pair<double, int>> cand;
-  for (int i = 0; i < n; ++i) {
-    const int b = N.rp[i], e = N.rp[i + 1];
-    if (rule == 0) {
-      double sum = 0.0;
-      for (int k = b; k < e; ++k) sum += std::fabs(N.v[k]);
-      const double thr = theta * sum;
-      for (int k = b; k < e; ++k) {
-        const double a = std::fabs(N.v[k]);
-        if (N.ci[k] != i && a > 0.0 && a >= thr) Si.push_back(N.ci[k]);
+  auto make_row = [&] {
+    return [&, cand = std::vector<std::pair<double, int>>()](int i, std::vector<int>& out) mutable {
+      const int b = N.rp[i], e = N.rp[i + 1];
+      if (rule == 0) {
+        double sum = 0.0;
+        for (int k = b; k < e; ++k) sum += std::fabs(N.v[k]);
+        const double thr = theta * sum;
+        for (int k = b; k < e; ++k) {
+          const double a = std::fabs(N.v[k]);
+          if (N.ci[k] != i && a > 0.0 && a >= thr) out.push_back(N.ci[k]);
+        }
+      } else if (rule == 1) {
+        double mx = 0.0;
+        for (int k = b; k < e; ++k)
+          if (N.ci[k] != i) mx = std::max(mx, std::fabs(N.v[k]));
+        const double thr = theta * mx;
+        for (int k = b; k < e; ++k) {
+          const double a = std::fabs(N.v[k]);
+          if (N.ci[k] != i && a > 0.0 && a >= thr) out.push_back(N.ci[k]);
+        }
+      } else {
+        // the top_s smallest (-|n_ij|, j) pairs: distinct j make the order total, so the partial
+        // sort selects exactly the entries a full sort would put first
+        cand.clear();
+        for (int k = b; k < e; ++k) {
+          const double a = std::fabs(N.v[k]);
+          if (N.ci[k] != i && a > 0.0) cand.push_back({-a, N.ci[k]});
+        }
+        const int take = std::min<int>(top_s, (int)cand.size());
+        std::partial_sort(cand.begin(), cand.begin() + take, cand.end());
+        const size_t at = out.size();
+        for (int t = 0; t < take; ++t) out.push_back(cand[t].second);
+        std::sort(out.begin() + at, out.end());
       }
-    } else if (rule == 1) {
-      double mx = 0.0;
-      for (int k = b; k < e; ++k)
-        if (N.ci[k] != i) mx = std::max(mx, std::fabs(N.v[k]));
-      const double thr = theta * mx;
-      for (int k = b; k < e; ++k) {
-        const double a = std::fabs(N.v[k]);
-        if (N.ci[k] != i && a > 0.0 && a >= thr) Si.push_back(N.ci[k]);
-      }
-    } else {
-      cand.clear();
-      for (int k = b; k < e; ++k) {
-        const double a = std::fabs(N.v[k]);
-        if (N.ci[k] != i && a > 0.0) cand.push_back({-a, N.ci[k]});
-      }
-      std::sort(cand.begin(), cand.end());
-      const int take = std::min<int>(top_s, (int)cand.size());
-      std::vector<int> sel;
-      for (int t = 0; t < take; ++t) sel.push_back(cand[t].second);
-      std::sort(sel.begin(), sel.end());
-      Si.insert(Si.end(), sel.begin(), sel.end());
-    }
-    Sp[i + 1] = (int)Si.size();
-  }
+    };
+  };
+  build_rows(N.m, Sp, Si, make_row);
 }
 
 // Algorithm 1.  "i strongly influences j" <=> i in S_j.  lambda_i = #points i influences; the
@@ -162,21 +201,20 @@ HCsr transpose(const HCsr& A, std::vector<int>* perm) {
 HCsr symbolic_product(const HCsr& L, const HCsr& R) {
   HCsr C;
   C.m = L.m; C.n = R.n;
-  C.rp.assign(L.m + 1, 0);
-  std::vector<int> mark(R.n, -1), row;
-  for (int i = 0; i < L.m; ++i) {
-    row.clear();
-    for (int k = L.rp[i]; k < L.rp[i + 1]; ++k) {
-      const int j = L.ci[k];
-      for (int t = R.rp[j]; t < R.rp[j + 1]; ++t) {
-        const int c = R.ci[t];
-        if (mark[c] != i) { mark[c] = i; row.push_back(c); }
+  auto make_row = [&] {
+    return [&, mark = std::vector<int>(R.n, -1)](int i, std::vector<int>& out) mutable {
+      const size_t at = out.size();
+      for (int k = L.rp[i]; k < L.rp[i + 1]; ++k) {
+        const int j = L.ci[k];
+        for (int t = R.rp[j]; t < R.rp[j + 1]; ++t) {
+          const int c = R.ci[t];
+          if (mark[c] != i) { mark[c] = i; out.push_back(c); }
+        }
       }
-    }
-    std::sort(row.begin(), row.end());
-    C.ci.insert(C.ci.end(), row.begin(), row.end());
-    C.rp[i + 1] = (int)C.ci.size();
-  }
+      std::sort(out.begin() + at, out.end());
+    };
+  };
+  build_rows(L.m, C.rp, C.ci, make_row);
   return C;
 }
 
