@@ -91,6 +91,19 @@ def test_strength_rs_interp_bitexact(lib, rule, theta):
         assert np.array_equal(ptr, optr) and np.array_equal(cols[:ptr[-1]], ocols) and capped.value == ocap, name
 
 
+@pytest.mark.parametrize("rule,theta", [(0, 0.06), (1, 0.25), (2, 0.0)])
+def test_strength_bitexact_row_parallel(lib, rule, theta):
+    # above 8192 rows the strength sets are built on several host threads; the sets must equal the
+    # oracle's row by row (term-document A A^t pattern with ties in |n_ij|)
+    A = W.termdoc(12000, 3000, 20, seed=7).to_scipy()
+    N = O.structural_product(A, A.T.tocsr())
+    N = sp.csr_matrix((np.round(N.data * 7.0) % 5 + 1.0, N.indices, N.indptr), shape=N.shape)
+    assert N.shape[0] >= 8192
+    Sp, Si, _ = _strength(lib, N, theta, rule)
+    oSp, oSi = O.strength_sets(N, theta, rule, 4)
+    assert np.array_equal(Sp, oSp) and np.array_equal(Si, oSi)
+
+
 def test_colouring_bitexact(lib):
     for M in (W.gradient2d(9).to_scipy(), W.gradient2d(9).to_scipy().T.tocsr(), W.laplace2d(11).to_scipy(),
               W.random_csr(80, 50, seed=4, mean_row=4).to_scipy()):
