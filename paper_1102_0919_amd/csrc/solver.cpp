@@ -1352,7 +1352,11 @@ void Solver::mult_cycle(int c) {
     Level& L = *lv_.back();
     const int m = L.m, n = L.n;
     NL_ = spd_ ? m : m + n;
-    if (NL_ > 1024) throw SolverError{ST_E_NUMERIC, "coarsest level larger than 1024 (coarsening stalled)"};
+    if (NL_ > 1024) {
+      std::string sizes;
+      for (const auto& Lv : lv_) sizes += " " + std::to_string(Lv->m) + (spd_ ? "" : "x" + std::to_string(Lv->n));
+      throw SolverError{ST_E_NUMERIC, "coarsest level larger than 1024 unknowns (coarsening stalled); levels:" + sizes};
+    }
     if ((spd_ ? m : std::min(m, n)) < nb_) throw SolverError{ST_E_NUMERIC, "coarsest level smaller than n_b"};
     const size_t mx = std::max(m, n);
     dA_ = ar_.alloc<double>((size_t)m * std::max(m, n));
