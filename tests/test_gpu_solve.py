@@ -168,17 +168,20 @@ def test_init_tests_and_rectangular_transpose(ctx):
     assert np.allclose(A @ r.V, r.U * r.sigma, atol=1e-7)
 
 
-@pytest.mark.parametrize("precision", ["mixed_fp32", "mixed_bf16"])
-def test_mixed_precision_matches_fp64(ctx, precision):
+@pytest.mark.parametrize("name,precision", [("laplace2d_31_min4", "mixed_fp32"), ("laplace2d_31_min4", "mixed_bf16"),
+                                            ("laplace2d_32_dom8", "mixed_fp32"), ("laplace2d_32_dom8", "mixed_bf16")])
+def test_mixed_precision_matches_fp64(ctx, name, precision):
+    # Kaczmarz (minimal) and the Jacobi-type row kernel on B's shared pattern (dominant), with FP32
+    # or BF16 operator values inside the FP64 refinement
     from paper_1102_0919_amd import api
-    wl = W.WORKLOADS["laplace2d_31_min4"]
-    A = W.laplace2d(31).to_scipy()
-    r64 = api.solve(ctx, A, "spd", "minimal", 4, api.params_init("spd", "minimal", **wl["params"]))
-    r32 = api.solve(ctx, A, "spd", "minimal", 4, api.params_init("spd", "minimal", precision=precision,
-                                                                 **wl["params"]))
+    wl = W.WORKLOADS[name]
+    kind, target, nb = wl["kind"], wl["target"], wl["n_b"]
+    A = W.build_workload_matrix(name).to_scipy()
+    r64 = api.solve(ctx, A, kind, target, nb, api.params_init(kind, target, **wl["params"]))
+    r32 = api.solve(ctx, A, kind, target, nb, api.params_init(kind, target, precision=precision, **wl["params"]))
     assert r32.converged
     _sig_close(r32.sigma, r64.sigma, r64.report.anorm)
-    _check_triplets(A, r32, "spd", 1e-8, r64.report.anorm)
+    _check_triplets(A, r32, kind, 1e-8, r64.report.anorm)
 
 
 def test_bf16_operator_values_rectangular_svd(ctx):
