@@ -77,6 +77,11 @@ struct RowOpArgs {
   int nnzK = -1;             // nonzeros of K (chooses the row split); -1: unknown
   double avgM = 0.0;         // mean row length of M (M_CSR; also chooses the row split)
   int vbf = 0;               // Kv, Mv hold BF16 bit patterns (T = float only)
+  // rows with very many nonzeros in K or M: flag per row (1 = long) and the list of those rows;
+  // each long row gets a workgroup of its own (none: all rows by lane groups)
+  const unsigned char* lflag = nullptr;
+  const int* lrows = nullptr;
+  int nlong = 0;
 };
 
 template <typename T> void launch_rowop(const RowOpArgs<T>& a, hipStream_t s);

@@ -147,6 +147,48 @@ __device__ __forceinline__ void walk_row(int k, int ke, const int* __restrict__ 
   }
 }
 
+// The same walk with a run-time stride between a lane group's nonzeros (a whole workgroup on one
+// long row: nonzeros k, k + stride, k + 2 stride, ...).
+template <typename T, int CPL, bool TWO, bool BF = false>
+__device__ __forceinline__ void walk_row_strided(int k, int ke, int stride, const int* __restrict__ ci,
+                                                 const T* __restrict__ av, const T* __restrict__ bv,
+                                                 const T* __restrict__ z, int w, int c0, T (&s1)[CPL],
+                                                 T (&s2)[CPL]) {
+  constexpr int U = TWO ? 2 : 4;
+  for (; k < ke; k += U * stride) {
+    int j[U];
+    T a[U], b[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int kk = k + u * stride;
+      j[u] = -1;
+      a[u] = T(0);
+      b[u] = T(0);
+      if (kk < ke) {
+        j[u] = ci[kk];
+        a[u] = ldval<T, BF>(av, kk);
+        if constexpr (TWO) b[u] = ldval<T, BF>(bv, kk);
+      }
+    }
+    T zr[U][CPL];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (j[u] >= 0) ldrow<T, CPL>(z + (long)j[u] * w, c0, w, zr[u]);
+      else {
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) zr[u][c] = T(0);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        s1[c] += a[u] * zr[u][c];
+        if constexpr (TWO) s2[c] += b[u] * zr[u][c];
+      }
+  }
+}
+
 // ------------------------------------------------------------------------------------------------
 // Block SpMM  y = A x (+ beta y)
 // ------------------------------------------------------------------------------------------------
@@ -271,6 +313,9 @@ struct RowOpPOD {
   const T* x; const T* D; const T* kap; const double* sig;
   int cmode; double omega;
   T* out;
+  // rows with very many nonzeros (lflag[row] = 1) are skipped by the row-per-lane-group blocks
+  // [0, gmain) and handled one per workgroup by blocks gmain + i (row lrows[i])
+  const unsigned char* lflag; const int* lrows; int gmain;
 };
 
 template <typename T>
@@ -295,6 +340,7 @@ __device__ __forceinline__ void rowop_body(const RowOpPOD<T>& a, int lshift, lon
   int c0 = (lane & ((1 << lshift) - 1)) * CPL;
   const int w = a.w;
   if (row >= a.nrows || c0 >= w) return;
+  if (a.lflag && a.lflag[row]) return;
   // the row's own operands first: their loads overlap the walks.  With M = I the row of y goes
   // into the M-sum of the first lane group (the other groups add zeros to it, exactly).
   double sg[CPL];
@@ -341,35 +387,124 @@ __device__ __forceinline__ void rowop_body(const RowOpPOD<T>& a, int lshift, lon
   strow<T, CPL>(a.out + (long)row * w, c0, w, r);
 }
 
+// One long row in one workgroup: the 1 << lshift column lanes repeat over BLK >> lshift groups,
+// each walking every (BLK >> lshift)-th nonzero; the groups' sums meet by lane shuffles within a
+// wavefront, then in LDS across the wavefronts (fixed order), and the row's first lanes finish it
+// as rowop_body does.
+static constexpr int LONG_MAX_LANES = 8;   // w <= 16 with two columns per lane
+template <typename T, int CPL>
+using LongRed = T[BLK / 64][LONG_MAX_LANES][2][CPL];
+
+template <typename T, int CPL, bool BF>
+__device__ __forceinline__ void rowop_long(const RowOpPOD<T>& a, int lshift, int row, LongRed<T, CPL>& red) {
+  const int L = 1 << lshift, t = threadIdx.x;
+  const int lane = t & (L - 1), grp = t >> lshift, G = BLK >> lshift;
+  const int w = a.w, c0 = lane * CPL;
+  T kz[CPL], my[CPL];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) { kz[c] = T(0); my[c] = T(0); }
+  if (c0 < w) {
+    if (a.Kv) {
+      const int kb = a.Krp[row], ke = a.Krp[row + 1];
+      if (a.mmode == M_SHARED)
+        walk_row_strided<T, CPL, true, BF>(kb + grp, ke, G, a.Kci, a.Kv, a.Mv, a.z, w, c0, kz, my);
+      else
+        walk_row_strided<T, CPL, false, BF>(kb + grp, ke, G, a.Kci, a.Kv, nullptr, a.z, w, c0, kz, my);
+    }
+    if (a.mmode == M_CSR) {
+      T unused[CPL];
+      walk_row_strided<T, CPL, false, BF>(a.Mrp[row] + grp, a.Mrp[row + 1], G, a.Mci, a.Mv, nullptr, a.y, w, c0,
+                                          my, unused);
+    }
+  }
+  for (int m = L; m < 64; m <<= 1) {
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      kz[c] += __shfl_xor(kz[c], m);
+      my[c] += __shfl_xor(my[c], m);
+    }
+  }
+  const int wave = t >> 6;
+  if ((t & 63) < L) {
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) { red[wave][lane][0][c] = kz[c]; red[wave][lane][1][c] = my[c]; }
+  }
+  __syncthreads();
+  if (t >= L || c0 >= w) return;
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) {
+    kz[c] = red[0][lane][0][c];
+    my[c] = red[0][lane][1][c];
+  }
+  for (int v = 1; v < BLK / 64; ++v) {
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) { kz[c] += red[v][lane][0][c]; my[c] += red[v][lane][1][c]; }
+  }
+  T kp[CPL], xv[CPL], yv[CPL];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) { kp[c] = T(0); xv[c] = T(0); yv[c] = T(0); }
+  if (a.kap) ldrow<T, CPL>(a.kap + (long)row * w, c0, w, kp);
+  if (a.x) ldrow<T, CPL>(a.x + (long)row * w, c0, w, xv);
+  if (a.mmode == M_IDENT) {
+    ldrow<T, CPL>(a.y + (long)row * w, c0, w, yv);
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) my[c] += yv[c];
+  }
+  const T d = a.D ? a.D[row] : T(1);
+  T r[CPL];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) {
+    const double sg = (a.sig && c0 + c < w) ? a.sig[c0 + c] : 1.0;
+    T ca, cb, ce;
+    coefs<T>(a.cmode, a.omega, sg, ca, cb, ce);
+    r[c] = d * (ca * kz[c] + cb * my[c] + ce * kp[c]);
+    if (a.x) r[c] += xv[c];
+  }
+  strow<T, CPL>(a.out + (long)row * w, c0, w, r);
+}
+
+// block bk of one row operation's own grid
+template <typename T, int CPL, int SPLIT, bool BF>
+__device__ __forceinline__ void rowop_block(const RowOpPOD<T>& a, int lshift, int bk, LongRed<T, CPL>& red) {
+  if (a.lrows && bk >= a.gmain) rowop_long<T, CPL, BF>(a, lshift, a.lrows[bk - a.gmain], red);
+  else rowop_body<T, CPL, SPLIT, BF>(a, lshift, (long)bk * BLK + threadIdx.x);
+}
+
 template <typename T, int CPL, int SPLIT, bool BF>
 __global__ __launch_bounds__(BLK) void k_rowop(RowOpPOD<T> a, int lshift) {
-  rowop_body<T, CPL, SPLIT, BF>(a, lshift, (long)blockIdx.x * BLK + threadIdx.x);
+  __shared__ LongRed<T, CPL> red;
+  rowop_block<T, CPL, SPLIT, BF>(a, lshift, (int)blockIdx.x, red);
 }
 
 // Two independent row operations in one launch (the u- and v-side residuals of a level):
 // workgroups [0, nb0) run the first, the others the second.
 template <typename T, int CPL, int SPLIT, bool BF>
 __global__ __launch_bounds__(BLK) void k_rowop2(RowOpPOD<T> a, RowOpPOD<T> b, int lshift, int nb0) {
+  __shared__ LongRed<T, CPL> red;
   const int bk = (int)blockIdx.x;
-  if (bk < nb0) rowop_body<T, CPL, SPLIT, BF>(a, lshift, (long)bk * BLK + threadIdx.x);
-  else rowop_body<T, CPL, SPLIT, BF>(b, lshift, (long)(bk - nb0) * BLK + threadIdx.x);
+  if (bk < nb0) rowop_block<T, CPL, SPLIT, BF>(a, lshift, bk, red);
+  else rowop_block<T, CPL, SPLIT, BF>(b, lshift, bk - nb0, red);
+}
+
+// POD of a row operation whose row-per-lane-group part takes gmain blocks; its long rows (if any,
+// and if a row's lanes fit the long-row reduction) follow as one block each.  Returns the blocks.
+template <typename T>
+static int rowop_pod(const RowOpArgs<T>& a, int gmain, RowOpPOD<T>& p) {
+  const bool lng = a.nlong > 0 && a.lflag && a.lrows && (1 << lshift_of(a.w)) <= LONG_MAX_LANES;
+  p = RowOpPOD<T>{a.nrows, a.w, a.Krp, a.Kci, a.Kv, a.z, a.mmode, a.Mrp, a.Mci, a.Mv, a.y,
+                  a.x, a.D, a.kap, a.sig, a.cmode, a.omega, a.out,
+                  lng ? a.lflag : nullptr, lng ? a.lrows : nullptr, gmain};
+  return gmain + (lng ? a.nlong : 0);
 }
 
 template <typename T>
 void launch_rowop(const RowOpArgs<T>& a, hipStream_t s) {
   if (a.nrows <= 0) return;
-  RowOpPOD<T> p{a.nrows, a.w, a.Krp, a.Kci, a.Kv, a.z, a.mmode, a.Mrp, a.Mci, a.Mv, a.y,
-                a.x, a.D, a.kap, a.sig, a.cmode, a.omega, a.out};
   int sh = lshift_of(a.w);
   int sp = split_of(a.Kv ? a.nnzK : -1, a.nrows, sh, a.mmode == M_CSR ? a.avgM : 0.0);
-  int grid = ceil_div((long)a.nrows << (sh + log2i(sp)), BLK);
+  RowOpPOD<T> p;
+  const int grid = rowop_pod(a, ceil_div((long)a.nrows << (sh + log2i(sp)), BLK), p);
   SLAMG_DISPATCH_VALS(k_rowop, T, a.vbf, sp, a.w, grid, BLK, s, p, sh);
-}
-
-template <typename T>
-static RowOpPOD<T> rowop_pod(const RowOpArgs<T>& a) {
-  return RowOpPOD<T>{a.nrows, a.w, a.Krp, a.Kci, a.Kv, a.z, a.mmode, a.Mrp, a.Mci, a.Mv, a.y,
-                     a.x, a.D, a.kap, a.sig, a.cmode, a.omega, a.out};
 }
 
 template <typename T>
@@ -379,8 +514,9 @@ void launch_rowop2(const RowOpArgs<T>& a, const RowOpArgs<T>& b, hipStream_t s) 
   const int sh = lshift_of(a.w);
   const int sp = std::max(split_of(a.Kv ? a.nnzK : -1, a.nrows, sh, a.mmode == M_CSR ? a.avgM : 0.0),
                           split_of(b.Kv ? b.nnzK : -1, b.nrows, sh, b.mmode == M_CSR ? b.avgM : 0.0));
-  const int g0 = ceil_div((long)a.nrows << (sh + log2i(sp)), BLK), g1 = ceil_div((long)b.nrows << (sh + log2i(sp)), BLK);
-  const RowOpPOD<T> pa = rowop_pod(a), pb = rowop_pod(b);
+  RowOpPOD<T> pa, pb;
+  const int g0 = rowop_pod(a, ceil_div((long)a.nrows << (sh + log2i(sp)), BLK), pa);
+  const int g1 = rowop_pod(b, ceil_div((long)b.nrows << (sh + log2i(sp)), BLK), pb);
   SLAMG_DISPATCH_VALS(k_rowop2, T, a.vbf, sp, a.w, g0 + g1, BLK, s, pa, pb, sh, g0);
 }
 

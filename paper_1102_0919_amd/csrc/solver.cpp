@@ -130,8 +130,18 @@ struct Aux {
   T *rnA = nullptr, *rnAab = nullptr, *rnAbb = nullptr, *rnAt = nullptr;   // Kaczmarz row sums
 };
 
+// Rows of one side whose walk is far longer than the others' (a frequent term of a term-document
+// matrix): a flag per row and their list, on the device.
+struct LongRows {
+  bool done = false;
+  unsigned char* flag = nullptr;
+  int* rows = nullptr;
+  int n = 0;
+};
+
 struct Level {
   int m = 0, n = 0;
+  LongRows lgu, lgv;        // u-side rows (A, B) and v-side rows (A^t, C)
   HCsr hA, hAt, hB, hC;     // host patterns (hB/hC: SVD only)
   std::vector<int> permAt;
   DCsr A, At, B, C;         // SPD: At aliases A, B lives on A's pattern, C unused
@@ -243,6 +253,8 @@ class Solver {
     else launch_copy_cast_df(a.v, a.vf, a.nnz, st_);
   }
   template <class T> int vbf() const { return std::is_same<T, float>::value && bf16_ ? 1 : 0; }
+  void long_rows(Level& L);
+  template <class T> void attach_long(int l, RowOpArgs<T>& a);
   const HCsr& A0_;
   const Problem& pb_;
   std::vector<std::unique_ptr<Level>> lv_;
@@ -340,6 +352,7 @@ void Solver::rowop(int l, const RowOpArgs<T>& a0, const DCsr* K, int cls) {
   RowOpArgs<T> a = a0;
   if (a.nnzK < 0 && K) a.nnzK = K->nnz;
   a.vbf = vbf<T>();
+  attach_long(l, a);
   if (l == 0) prof(cls, rowop_bytes(a, K), [&] { launch_rowop(a, st_); });
   else launch_rowop(a, st_);
 }
@@ -350,6 +363,8 @@ void Solver::rowop2(int l, const RowOpArgs<T>& a0, const DCsr* Ka, const RowOpAr
   if (a.nnzK < 0 && Ka) a.nnzK = Ka->nnz;
   if (b.nnzK < 0 && Kb) b.nnzK = Kb->nnz;
   a.vbf = b.vbf = vbf<T>();
+  attach_long(l, a);
+  attach_long(l, b);
   if (l == 0) prof(cls, rowop_bytes(a, Ka) + rowop_bytes(b, Kb), [&] { launch_rowop2(a, b, st_); });
   else launch_rowop2(a, b, st_);
 }
@@ -402,6 +417,51 @@ void Solver::kacz(int l, const KaczArgs<T>& a0, long nnz_colour) {
   if (a.kap) b += sz * w * r;
   if (l == 0) prof(1, b, [&] { launch_kacz(a, st_); });
   else launch_kacz(a, st_);
+}
+
+// Long rows of a level's sides: a row is long when its operator row (A or A^t) or its B / C row
+// holds more than max(256, 8 x the mean row length) entries.  Built once per level (host copies of
+// the row pointers), before the additive phase captures its graph.
+void Solver::long_rows(Level& L) {
+  auto side = [&](LongRows& g, const DCsr& K, const DCsr* M, int rows) {
+    if (g.done) return;
+    g.done = true;
+    if (!K.rp || rows <= 0) return;
+    std::vector<int> kr, mr;
+    d2h(kr, K.rp, (size_t)rows + 1, st_);
+    if (M && M->rp) d2h(mr, M->rp, (size_t)rows + 1, st_);
+    const double tk = std::max(256.0, 8.0 * (double)(kr[rows] - kr[0]) / rows);
+    const double tm = mr.empty() ? 0.0 : std::max(256.0, 8.0 * (double)(mr[rows] - mr[0]) / rows);
+    std::vector<unsigned char> flag(rows, 0);
+    std::vector<int> list;
+    for (int i = 0; i < rows; ++i) {
+      const bool lng = kr[i + 1] - kr[i] > tk || (!mr.empty() && mr[i + 1] - mr[i] > tm);
+      if (lng) { flag[i] = 1; list.push_back(i); }
+    }
+    if (list.empty()) return;
+    g.flag = ar_.alloc<unsigned char>(rows);
+    h2d(g.flag, flag, st_);
+    g.rows = ar_.alloc<int>(list.size());
+    h2d(g.rows, list, st_);
+    g.n = (int)list.size();
+    sync();
+  };
+  side(L.lgu, L.A, L.finest ? nullptr : &L.B, L.m);
+  if (!spd_) side(L.lgv, L.At, L.finest ? nullptr : &L.C, L.n);
+}
+
+template <class T>
+void Solver::attach_long(int l, RowOpArgs<T>& a) {
+  Level& L = *lv_[l];
+  if (!a.Kv && a.mmode != M_CSR) return;   // no walk
+  if (!L.lgu.done || (!spd_ && !L.lgv.done)) {
+    if (capturing_) return;
+    long_rows(L);
+  }
+  const LongRows* g = nullptr;
+  if (a.Krp == L.A.rp && a.nrows == L.m) g = &L.lgu;
+  else if (!spd_ && a.Krp == L.At.rp && a.nrows == L.n) g = &L.lgv;
+  if (g && g->n > 0) { a.lflag = g->flag; a.lrows = g->rows; a.nlong = g->n; }
 }
 
 static double avg_row(const DCsr& M) { return M.m > 0 ? (double)M.nnz / M.m : 0.0; }
@@ -1729,6 +1789,7 @@ void Solver::run(const double* init_tests, SolveOutput& out) {
       }
     }
   }
+  for (auto& Lp : lv_) long_rows(*Lp);   // before any capture
   int it = 0;
   graph_off_ = !p_.graphs;
   while (rmax > p_.tol && it < p_.max_add) {
