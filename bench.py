@@ -37,13 +37,13 @@ DEFAULT_WORKLOAD = "gradient2d_256_dom8"
 # HBM traffic of the dominant kernel class, from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs
 # (profiles/pmc_*_gradient2d_256_dom8.md), per dispatch in KiB for the two finest-level k_rowop
 # launch shapes (u rows, v rows), scaled by the same counters of a 1 GiB device copy
-# (profiles/pmc_*_copy_1GiB.md: FETCH 524304.4 KiB, WRITE 1048576.0 KiB per 1 GiB).  Valid only
+# (profiles/pmc_*_copy_1GiB.md: FETCH 524304.5 KiB, WRITE 1048576.0 KiB per 1 GiB).  Valid only
 # for the kernel source the counters were taken with.
 TRAFFIC = {
     ("gradient2d_256_dom8", 0): dict(
-        kernels_sha256="6c97123e88193b9af03c98f78c52d1718645b18b9e62d05f4519b9f99ee0f883",
-        fetch_kib=(12224.1, 10368.9), write_kib=(8160.0, 4096.0),
-        copy_fetch_kib=524304.4, copy_write_kib=1048576.0, copy_bytes=1 << 30),
+        kernels_sha256="56df206b3531e9b5594c229e089abdefcc35af292738dcdd46269dfbf4342271",
+        fetch_kib=(12230.1, 10374.9), write_kib=(8160.0, 4096.0),
+        copy_fetch_kib=524304.5, copy_write_kib=1048576.0, copy_bytes=1 << 30),
 }
 
 

@@ -377,6 +377,19 @@ static double spmm_bytes(const DCsr& K, int w, double beta, int vbf) {
 
 template <class T>
 void Solver::spmm(int l, const DCsr& K, const T* Kv, int w, const T* x, T* y, double beta) {
+  if (beta == 0.0) {
+    // a product with A or A^t whose side has long rows runs as the row kernel (out = K x), which
+    // gives each long row a workgroup
+    Level& L = *lv_[l];
+    const LongRows* g = &K == &L.A ? &L.lgu : (!spd_ && &K == &L.At) ? &L.lgv : nullptr;
+    if (g && g->done && g->n > 0) {
+      RowOpArgs<T> a;
+      a.nrows = K.m; a.w = w; a.Krp = K.rp; a.Kci = K.ci; a.nnzK = K.nnz; a.Kv = Kv; a.z = x;
+      a.mmode = M_NONE; a.cmode = C_COPYK; a.out = y;
+      rowop(l, a, &K, 5);
+      return;
+    }
+  }
   if (l == 0)
     prof(5, spmm_bytes<T>(K, w, beta, vbf<T>()), [&] { launch_spmm<T>(K.m, w, K.rp, K.ci, Kv, x, y, beta, st_, K.nnz, vbf<T>()); });
   else launch_spmm<T>(K.m, w, K.rp, K.ci, Kv, x, y, beta, st_, K.nnz, vbf<T>());
@@ -1614,6 +1627,26 @@ void Solver::residual_launch() {
   DotArgs<double> d1, d2;
   d1.nrows = L.m; d1.w = nb_; d1.Krp = L.A.rp; d1.Kci = L.A.ci; d1.nnzK = L.A.nnz; d1.Kv = L.A.v;
   d1.z = spd_ ? b.Ub : b.Vb; d1.y = b.Ub; d1.sig = sig_;
+  if (L.lgu.n > 0 || L.lgv.n > 0) {
+    // sides with long rows: the residual blocks by the row kernel (a workgroup per long row), then
+    // their column norms
+    RowOpArgs<double> a, c;
+    a.nrows = L.m; a.w = nb_; a.Krp = L.A.rp; a.Kci = L.A.ci; a.nnzK = L.A.nnz; a.Kv = L.A.v;
+    a.z = spd_ ? b.Ub : b.Vb; a.mmode = M_IDENT; a.y = b.Ub; a.sig = sig_; a.cmode = C_RESID; a.out = b.tU;
+    DotArgs<double> e1, e2;
+    e1.nrows = L.m; e1.w = nb_; e1.z = b.tU;
+    if (spd_) {
+      rowop(0, a, &L.A, 7);
+      launch_dots(e1, partial_, r1_, st_);
+    } else {
+      c.nrows = L.n; c.w = nb_; c.Krp = L.At.rp; c.Kci = L.At.ci; c.nnzK = L.At.nnz; c.Kv = L.At.v;
+      c.z = b.Ub; c.mmode = M_IDENT; c.y = b.Vb; c.sig = sig_; c.cmode = C_RESID; c.out = b.tV;
+      rowop2(0, a, &L.A, c, &L.At, 7);
+      e2.nrows = L.n; e2.w = nb_; e2.z = b.tV;
+      launch_dots2(e1, partial_, r1_, e2, partial2_, r2_, st_);
+    }
+    return;
+  }
   if (spd_) {
     dots(0, d1, &L.A, r1_);
   } else {
