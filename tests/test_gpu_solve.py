@@ -410,7 +410,9 @@ def test_empty_rows_and_columns_reinserted(ctx):
 
 def test_termdoc_topics_reduced_vs_oracle(ctx):
     # the topic-structured term-document stand-in at 4000 x 1000: device and oracle build the same
-    # hierarchy and reach the ten dominant triplets of the dense SVD
+    # hierarchy and reach the ten dominant triplets of the dense SVD.  17 of its term rows exceed
+    # max(256, 8 x the mean) nonzeros, so the row kernel's one-workgroup-per-long-row path, the
+    # Ritz product and the residual blocks through it are all checked here
     from paper_1102_0919_amd import api
     A, wl, r, o = _run_both(ctx, "termdoc_200k_dom10", scale=1000, max_add=200)
     rep = api.report_dict(r.report)
