@@ -124,3 +124,14 @@ def test_solve_rejects_invalid_inputs_without_device(lib):
     sig = np.zeros(1)
     # NULL context
     assert lib.slamg_solve(None, C.byref(s), 0, 0, 1, C.byref(p), None, _p(sig), None, None, None) == -1
+
+
+def test_bf16_reference_rounding_worked_values():
+    # the GPU tests' BF16 reference, pinned on the host: nearest BF16 of the FP32 value, ties to the
+    # even pattern, infinity past the halfway point above the largest finite BF16
+    from .test_gpu_ops import _bf16_nearest
+    cases = [(1.0, 0x3F80), (1 + 2 ** -8, 0x3F80), (1 + 3 * 2 ** -8, 0x3F82), (1 + 2 ** -8 + 2 ** -20, 0x3F81),
+             (-2.5, 0xC020), (2.0 ** -133, 0x0001), (2.0 ** -134, 0x0000), (3 * 2.0 ** -135, 0x0001),
+             (3.3895313892515355e38, 0x7F7F), (3.4e38, 0x7F80), (np.inf, 0x7F80), (0.0, 0x0000), (-0.0, 0x8000)]
+    got = _bf16_nearest(np.array([v for v, _ in cases]))
+    assert [int(g) for g in got] == [p for _, p in cases]
