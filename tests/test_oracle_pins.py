@@ -494,3 +494,17 @@ def test_square_coarsening_rejects_rectangular():
     A = W.gradient2d(6).to_scipy()
     with pytest.raises(ValueError):
         O.solve(A, "svd", "dominant", 2, O.Params(square_coarsening=1, n_t=4))
+
+
+def test_termdoc_topics_generator_structure():
+    # the configuration-3 stand-in: every document holds exactly 60 distinct terms with positive
+    # integer counts, the draw is reproducible from its seed, and the dominant singular values fall
+    # off with gaps (not the single-vocabulary generator's sigma_1 >> one tight cluster)
+    A = W.termdoc_topics(4000, 1000, seed=1102).to_scipy().tocsc()
+    assert np.all(np.diff(A.indptr) == 60)
+    assert np.all(A.data >= 1.0) and np.all(A.data == np.round(A.data))
+    B = W.termdoc_topics(4000, 1000, seed=1102).to_scipy()
+    assert (abs(B - A.tocsr())).max() == 0.0
+    s = np.linalg.svd(A.toarray(), compute_uv=False)[:6]
+    ratios = s[:-1] / s[1:]
+    assert ratios[0] < 2.5 and np.all(ratios[:4] > 1.05)
