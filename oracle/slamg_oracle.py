@@ -46,7 +46,8 @@ the design notes of the repository):
       sign of u and of sigma (§5.3), for both targets.
   R23 minimal SVD targets: after each Ritz step, u_j <- A v_j / ||A v_j|| for sigma_j > 1e-8 ||A||_est.
   R22 the extra F-point Jacobi step of the minimal LS fit (§3.8) uses weight omega_J on the
-      strength operator N (A for eigenproblems, A A^t and A^t A for SVD).
+      operator strength is measured on (A for eigenproblems, A A^t and A^t A for SVD, A for both
+      sides under square coarsening); rows with a zero diagonal keep their values.
   R27 one-sided coarsening: on an SVD level where one side would keep fewer than n_b + n_t
       C-points while the other coarsens, that side keeps all its points (identity interpolation).
   R28 square coarsening (§5.1, optional): strength on A itself, and the v-side takes the u-side's
@@ -626,17 +627,21 @@ def one_sided_coarsening(su, sv, kind, need):
     return su, sv
 
 
-def minimal_presmooth(lev, kind, side_is_u, Vals, omega):
-    """Extra Jacobi step on N z = 0 applied to the F-point values before the LS fit (§3.8, R22)."""
+def minimal_presmooth(lev, kind, side_is_u, Vals, omega, square=False):
+    """Extra Jacobi step on N z = 0 applied to the F-point values before the LS fit (§3.8, R22).
+
+    N is the operator strength is measured on: A for eigenproblems, A A^t (u) and A^t A (v) for
+    SVD levels, and A itself for both sides under square coarsening (§5.1, R28).  Rows whose
+    diagonal of N is zero keep their values."""
     A = lev.A
-    if kind == SPD:
+    if kind == SPD or square:
         NZ = A @ Vals; d = _diag(A)
     elif side_is_u:
         NZ = A @ (A.T @ Vals); d = np.asarray(A.multiply(A).sum(axis=1)).ravel()
     else:
         NZ = A.T @ (A @ Vals); d = np.asarray(A.multiply(A).sum(axis=0)).ravel()
-    d = np.where(d > 0, d, 1.0)
-    return Vals - omega * NZ / d[:, None]
+    step = np.where(d != 0, 1.0 / np.where(d != 0, d, 1.0), 0.0)
+    return Vals - omega * NZ * step[:, None]
 
 
 def ls_weights(lev, kind, target, U, V, anorm):
@@ -792,7 +797,8 @@ class Solver:
     def _fit(self, lev, side, Vals, w, is_u):
         bvals = Vals
         if self.target == MINIMAL:
-            bvals = minimal_presmooth(lev, self.kind, is_u, Vals, self.p.omega)
+            bvals = minimal_presmooth(lev, self.kind, is_u, Vals, self.p.omega,
+                                      square=self.kind == SVD and bool(self.p.square_coarsening))
         side.P = ls_interpolation(side.ptr, side.fine_cols, side.is_c, Vals, bvals, w)
 
     # -------------------------------------------------------------- additive V-cycle (§4.1-4.2)

@@ -601,8 +601,15 @@ void Solver::refresh_level_aux(Level& L) {
     } else {
       launch_row_sq(L.m, L.A.rp, L.A.v, nullptr, L.ad.rnA, nullptr, nullptr, L.A.ci, st_);
       launch_row_sq(L.n, L.At.rp, L.At.v, nullptr, L.ad.rnAt, nullptr, nullptr, L.At.ci, st_);
-      launch_recip(L.m, L.ad.rnA, L.smU, st_);    // diag(A A^t) = row norms^2 of A
-      launch_recip(L.n, L.ad.rnAt, L.smV, st_);   // diag(A^t A) = column norms^2
+      if (square_) {
+        // square coarsening measures strength on A itself: the pre-smoothing step uses 1 / diag(A)
+        // on both sides
+        launch_diag_inv(L.m, L.A.rp, L.A.ci, L.A.v, L.smU, st_);
+        launch_diag_inv(L.m, L.A.rp, L.A.ci, L.A.v, L.smV, st_);
+      } else {
+        launch_recip(L.m, L.ad.rnA, L.smU, st_);    // diag(A A^t) = row norms^2 of A
+        launch_recip(L.n, L.ad.rnAt, L.smV, st_);   // diag(A^t A) = column norms^2
+      }
     }
   }
   if (mixed_) {
@@ -1306,8 +1313,10 @@ void Solver::fit_interpolation(int l, int cycle) {
   auto smooth = [&](bool u_side, const double* X, int w, double* tmp, double* out) {
     RowOpArgs<double> a;
     a.w = w; a.x = X; a.cmode = C_SMOOTH; a.omega = p_.omega_J; a.out = out;
-    if (spd_) {
-      a.nrows = mu; a.Krp = L.A.rp; a.Kci = L.A.ci; a.nnzK = L.A.nnz; a.Kv = L.A.v; a.z = X; a.D = L.smU;
+    if (spd_ || square_) {
+      // N = A (eigenproblems; both sides of a square-coarsened SVD)
+      a.nrows = mu; a.Krp = L.A.rp; a.Kci = L.A.ci; a.nnzK = L.A.nnz; a.Kv = L.A.v; a.z = X;
+      a.D = u_side ? L.smU : L.smV;
     } else if (u_side) {
       launch_spmm<double>(L.n, w, L.At.rp, L.At.ci, L.At.v, X, tmp, 0.0, st_, L.At.nnz);   // A^t u
       a.nrows = mu; a.Krp = L.A.rp; a.Kci = L.A.ci; a.nnzK = L.A.nnz; a.Kv = L.A.v; a.z = tmp; a.D = L.smU;

@@ -508,3 +508,123 @@ def test_termdoc_topics_generator_structure():
     s = np.linalg.svd(A.toarray(), compute_uv=False)[:6]
     ratios = s[:-1] / s[1:]
     assert ratios[0] < 2.5 and np.all(ratios[:4] > 1.05)
+
+
+# ---------------------------------------------------------------------------- pins of single steps
+def test_oracle_uniform_stream_published_outputs():
+    # the oracle's own SplitMix64 stream against the generator's published outputs (Vigna's
+    # reference code: seed 0 gives 0xE220A8397B1DCDAF first; seed 1234567 the three values below),
+    # mapped to [-1, 1) by 2 (z >> 11) 2^-53 - 1
+    def pm1(z):
+        return 2.0 * (z >> 11) * 2.0 ** -53 - 1.0
+    assert O._splitmix_uniform(0, 1)[0] == pm1(0xE220A8397B1DCDAF)
+    pub = [6457827717110365317, 3203168211198807973, 9817491932198370423]
+    assert list(O._splitmix_uniform(1234567, 3)) == [pm1(z) for z in pub]
+
+
+def test_ls_weights_are_rq_for_dominant_and_inverse_rq_for_minimal():
+    # §3.8 / §5.3: the k-th equation is weighted by the Rayleigh quotient of the pair (u_k, v_k)
+    # for dominant targets and by its inverse for minimal ones.  With exact singular pairs of a
+    # dense SVD the Rayleigh quotient is the singular value itself.
+    lev, U, s, V = _tiny_svd_level()
+    wd = O.ls_weights(lev, O.SVD, O.DOMINANT, U, V, anorm=s[0])
+    wm = O.ls_weights(lev, O.SVD, O.MINIMAL, U, V, anorm=s[0])
+    assert np.allclose(wd, s, rtol=1e-12)
+    assert np.allclose(wm, 1.0 / s, rtol=1e-12)
+    # the k-th u pairs with the k-th v: a permuted V changes the quotients
+    perm = np.roll(np.arange(V.shape[1]), 1)
+    assert not np.allclose(O.ls_weights(lev, O.SVD, O.DOMINANT, U, V[:, perm], s[0]), s)
+    # a pair with a zero quotient is capped at 1 / (1e-12 ||A||) for minimal targets
+    Ad = lev.A.toarray()
+    nullu = sla.null_space(Ad.T)[:, :1]
+    w0 = O.ls_weights(lev, O.SVD, O.MINIMAL, nullu, V[:, :1], anorm=2.0)
+    assert w0[0] == 1.0 / (1e-12 * 2.0)
+    # eigenproblems: x^t A x / x^t B x of an exact eigenvector is its eigenvalue
+    L = W.laplace2d(5).to_scipy()
+    ev, Ev = np.linalg.eigh(L.toarray())
+    levs = O.Level(L, sp.identity(25, format="csr"), None)
+    assert np.allclose(O.ls_weights(levs, O.SPD, O.DOMINANT, Ev[:, :4], None, 8.0), ev[:4])
+    assert np.allclose(O.ls_weights(levs, O.SPD, O.MINIMAL, Ev[:, :4], None, 8.0), 1.0 / ev[:4])
+
+
+def test_interpolatory_set_cap_keeps_the_strongest_connections():
+    # R13: an F-point with more strong C-neighbours than the cap keeps the `cap` connections of
+    # largest |n_ij|, ties to the lower index.  Point 0 is strongly influenced by C-points 1..5
+    # with magnitudes 5, 3, 3, 1, 4; with cap 3 it keeps 1 (5), 5 (4) and 2 (3, the lower of the
+    # tied 2 and 3).
+    N = np.zeros((7, 7))
+    N[0, [1, 2, 3, 4, 5]] = [-5.0, 3.0, -3.0, 1.0, -4.0]
+    N[0, 0] = 20.0
+    for i in range(1, 7):
+        N[i, i] = 1.0
+    N[6, 0] = -1.0
+    Ns = sp.csr_matrix(N)
+    S_ptr = np.array([0, 5, 5, 5, 5, 5, 5, 6]); S_idx = np.array([1, 2, 3, 4, 5, 0])
+    is_c = np.array([False, True, True, True, True, True, False])
+    ptr, cols, capped = O.interp_pattern(S_ptr, S_idx, Ns, is_c, 3)
+    assert list(cols[ptr[0]:ptr[1]]) == [1, 2, 5]
+    assert capped == 1
+    # below the cap nothing is dropped; C-points interpolate from themselves
+    ptr, cols, capped = O.interp_pattern(S_ptr, S_idx, Ns, is_c, 5)
+    assert list(cols[ptr[0]:ptr[1]]) == [1, 2, 3, 4, 5] and capped == 0
+    assert [list(cols[ptr[i]:ptr[i + 1]]) for i in range(1, 6)] == [[1], [2], [3], [4], [5]]
+    # the F-point 6 has no strong C-neighbour (its only strong neighbour 0 is an F-point)
+    assert ptr[7] - ptr[6] == 0
+
+
+def test_minimal_presmooth_on_closed_form_eigenvectors():
+    # §3.8, minimal targets: one weighted-Jacobi step (omega_J = 0.7) on N z = 0 at the F-point
+    # values, N the operator strength is measured on.  On an eigenvector of N the step is a
+    # scaling whose factor follows from the closed-form spectrum:
+    #  * eigenproblem, N = A = 5-point Laplacian (diagonal 4): z -> (1 - 0.7 lambda / 4) z;
+    #  * SVD u-side, N = A A^t of the discrete gradient (every row of A holds +1 and -1, so the
+    #    diagonal is 2): u = A v / sigma -> (1 - 0.7 sigma^2 / 2) u;
+    #  * SVD v-side, N = A^t A = the grid graph's Laplacian, diagonal = vertex degree:
+    #    v -> v - 0.7 sigma^2 v / deg, v(x, y) = cos(a pi (x + 1/2) / k) cos(b pi (y + 1/2) / k).
+    k = 7
+    L = W.laplace2d(k).to_scipy()
+    lev = O.Level(L, sp.identity(k * k, format="csr"), None)
+    ys, xs = np.meshgrid(np.arange(1, k + 1), np.arange(1, k + 1), indexing="ij")
+    for i, j in ((1, 1), (2, 3), (7, 5)):
+        z = (np.sin(i * np.pi * xs / (k + 1)) * np.sin(j * np.pi * ys / (k + 1))).ravel()[:, None]
+        lam = 4 * np.sin(i * np.pi / (2 * (k + 1))) ** 2 + 4 * np.sin(j * np.pi / (2 * (k + 1))) ** 2
+        out = O.minimal_presmooth(lev, O.SPD, True, z, 0.7)
+        assert np.allclose(out, (1 - 0.7 * lam / 4) * z, atol=1e-13)
+    G = W.gradient2d(k).to_scipy()
+    levg = O.Level(G, sp.identity(G.shape[0], format="csr"), sp.identity(G.shape[1], format="csr"))
+    ys, xs = np.meshgrid(np.arange(k), np.arange(k), indexing="ij")
+    deg = (4 - (xs == 0) - (xs == k - 1) - (ys == 0) - (ys == k - 1)).ravel().astype(float)
+    for a, b in ((1, 0), (2, 3), (6, 6)):
+        v = (np.cos(a * np.pi * (xs + 0.5) / k) * np.cos(b * np.pi * (ys + 0.5) / k)).ravel()
+        s2 = 4 * np.sin(a * np.pi / (2 * k)) ** 2 + 4 * np.sin(b * np.pi / (2 * k)) ** 2
+        outv = O.minimal_presmooth(levg, O.SVD, False, v[:, None], 0.7)[:, 0]
+        assert np.allclose(outv, v - 0.7 * s2 * v / deg, atol=1e-13)
+        u = G @ v / np.sqrt(s2)
+        outu = O.minimal_presmooth(levg, O.SVD, True, u[:, None], 0.7)[:, 0]
+        assert np.allclose(outu, (1 - 0.7 * s2 / 2) * u, atol=1e-13)
+
+
+def test_minimal_presmooth_square_coarsening_uses_a():
+    # §3.8 with §5.1 / §6.1: under square coarsening strength is measured on A itself, so the
+    # Jacobi step is taken on A z = 0 for both sides (R22).  The upwind convection-diffusion matrix
+    # is T (x) I + I (x) T with T = tridiag(-(1 + c), 2 + c, -1); T's eigenvectors are
+    # x_j = (1 + c)^(j/2) sin(j q pi / (k + 1)) with eigenvalues 2 + c - 2 sqrt(1 + c) cos(q pi / (k + 1)),
+    # so on z = x_q (x) x_r the step is the scaling 1 - 0.7 (mu_q + mu_r) / (4 + 2c).
+    k, c = 6, 0.5
+    A = W.convdiff2d(k, c).to_scipy()
+    lev = O.Level(A, sp.identity(k * k, format="csr"), sp.identity(k * k, format="csr"))
+    j = np.arange(1, k + 1)
+    for q, r in ((1, 1), (2, 5)):
+        xq = (1 + c) ** (j / 2) * np.sin(j * q * np.pi / (k + 1))
+        xr = (1 + c) ** (j / 2) * np.sin(j * r * np.pi / (k + 1))
+        mu = 2 * (2 + c) - 2 * np.sqrt(1 + c) * (np.cos(q * np.pi / (k + 1)) + np.cos(r * np.pi / (k + 1)))
+        z = np.outer(xr, xq).ravel()[:, None]          # id = y k + x: x varies fastest
+        z /= np.linalg.norm(z)
+        for side in (True, False):
+            out = O.minimal_presmooth(lev, O.SVD, side, z, 0.7, square=True)
+            assert np.allclose(out, (1 - 0.7 * mu / (4 + 2 * c)) * z, atol=1e-13)
+    # rows with a zero diagonal keep their values
+    Z = sp.csr_matrix(np.array([[0.0, 1.0], [1.0, 2.0]]))
+    levz = O.Level(Z, sp.identity(2, format="csr"), sp.identity(2, format="csr"))
+    out = O.minimal_presmooth(levz, O.SVD, True, np.array([[1.0], [1.0]]), 0.7, square=True)
+    assert out[0, 0] == 1.0 and out[1, 0] == 1.0 - 0.7 * 3.0 / 2.0
