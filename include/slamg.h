@@ -104,6 +104,15 @@ typedef struct {
                                every level is square; the LS weights of P and Q are fitted
                                separately.  Needs a square matrix without empty rows or
                                columns (SLAMG_E_INVALID otherwise); ignored for SPD (0)         */
+  int32_t n_guard;          /* guard pairs: the method runs on a block of n_b + n_guard pairs
+                               (coarsest selection, boot vectors, V-cycles and the Ritz step of
+                               §4.3 on the whole block); the stopping test and the outputs take
+                               the n_b extremal pairs.  n_b + n_guard <= 16 (0)                 */
+  int32_t mu_tJ, mu_bJ;     /* inner weighted-Jacobi steps per outer test / boot relaxation of
+                               dominant targets (§3.4, §3.5) (1, 1)                             */
+  int32_t kaczmarz_order;   /* row order of the Kaczmarz sweeps of minimal targets (§5.3): 0
+                               multicolour (rows of one colour share no column, colours
+                               ascending, rows ascending), 1 lexicographic (row by row) (0)     */
   int32_t reserved[1];
 } slamg_params;
 

@@ -52,6 +52,9 @@ the design notes of the repository):
       C-points while the other coarsens, that side keeps all its points (identity interpolation).
   R28 square coarsening (§5.1, optional): strength on A itself, and the v-side takes the u-side's
       C/F split and interpolatory sets, so P and Q share one pattern and every level is square.
+  R29 guard pairs (optional): the method runs with a block of n_b + n_guard pairs (coarsest
+      selection, boot vectors, V-cycles, Ritz step all on the larger block); the stopping test and
+      the outputs take the n_b extremal ones.
 """
 from __future__ import annotations
 
@@ -94,6 +97,9 @@ class Params:
     ritz_in_mult: int = 1
     u_from_v: int = 0             # R23: minimal SVD, u_j <- A v_j / ||A v_j|| after each Ritz step
     square_coarsening: int = 0    # §5.1: square A, both sides coarsened on A itself (R28)
+    n_guard: int = 0              # R29: extra pairs iterated in the block beyond the n_b wanted
+    mu_tJ: int = 1                # inner weighted-Jacobi steps of a test relaxation (§3.4)
+    mu_bJ: int = 1                # inner weighted-Jacobi steps of a boot relaxation (§3.5)
 
 
 NORM_SEED_XOR = 0xA5A5A5A5A5A5A5A5
@@ -322,24 +328,33 @@ def colour_groups(colour):
     return [np.nonzero(colour == c)[0] for c in range(int(colour.max()) + 1)]
 
 
-def kaczmarz_sweep(M, x, rhs, groups, rownorm2=None):
+def row_groups(M, groups):
+    """(rows, M[rows], M[rows]^t) for each group of rows."""
+    out = []
+    for rows in groups:
+        Mr = sp.csr_matrix(M[rows])
+        out.append((rows, Mr, Mr.T.tocsr()))
+    return out
+
+
+def kaczmarz_sweep(M, x, rhs, groups, rownorm2=None, parts=None):
     """One Kaczmarz sweep on M x = rhs (weight 1), row by row in the order of ``groups``.
 
     Rows of one group share no column, so processing a group at once equals processing its rows
     one after another.  Rows with zero norm are skipped.  x is (n, k), rhs is (nrows, k) or None;
-    ``rownorm2`` (nrows,) or (nrows, k) defaults to the squared row norms of M.
+    ``rownorm2`` (nrows,) or (nrows, k) defaults to the squared row norms of M.  ``parts`` may hold
+    ``row_groups(M, groups)`` computed beforehand.
     """
     M = sp.csr_matrix(M)
     if rownorm2 is None:
         rownorm2 = np.asarray(M.multiply(M).sum(axis=1)).ravel()
     x = x.copy()
-    for rows in groups:
-        Mr = M[rows]
+    for rows, Mr, MrT in (parts if parts is not None else row_groups(M, groups)):
         r = (rhs[rows] if rhs is not None else 0.0) - Mr @ x
         rn = rownorm2[rows]
         rn = rn[:, None] if rn.ndim == 1 else rn
         coef = np.where(rn > 0, r / np.where(rn > 0, rn, 1.0), 0.0)
-        x += Mr.T @ coef
+        x += MrT @ coef
     return x
 
 
@@ -364,6 +379,20 @@ class Level:
     C: sp.csr_matrix | None
     groups_A: list = field(default_factory=list)     # Kaczmarz order over rows of A
     groups_At: list = field(default_factory=list)    # over rows of A^t (SVD only)
+    _parts: dict = field(default_factory=dict)       # row_groups of the current operators
+
+    def kacz_parts(self, which):
+        """row_groups of A ("A"), A^t ("At") or B ("B", eigenproblems) in their Kaczmarz order,
+        kept while the level's operator objects stay the same."""
+        src = self.B if which == "B" else self.A
+        got = self._parts.get(which)
+        if got is None or got[0] is not src:
+            if which == "At":
+                got = (src, row_groups(self.A.T.tocsr(), self.groups_At))
+            else:
+                got = (src, row_groups(src, self.groups_A))
+            self._parts[which] = got
+        return got[1]
     su: Side | None = None
     sv: Side | None = None
 
@@ -389,20 +418,29 @@ def _bnorm(M, X):
     return np.sqrt(np.maximum(np.sum(X * (M @ X), axis=0), 0.0))
 
 
-def relax_test_dominant(lev, kind, U, V, omega):
-    """One outer power-method step with one weighted-Jacobi inner step (§3.4).
+def relax_test_dominant(lev, kind, U, V, omega, inner=1):
+    """One outer power-method step with ``inner`` weighted-Jacobi steps (mu_tJ, §3.4).
 
-    SVD: v_bar = v - omega D_C^-1 (C v - A^t u), v = v_bar / ||v_bar||_C, then
-         u_bar = u - omega D_B^-1 (B u - A v),   u = u_bar / ||u_bar||_B.
-    Eigenproblem: x_bar = x - omega D_B^-1 (B x - A x), x = x_bar / ||x_bar||_B.
+    SVD: solve C v_bar = A^t u by v_bar <- v_bar - omega D_C^-1 (C v_bar - A^t u) from v_bar = v,
+         v = v_bar / ||v_bar||_C; then B u_bar = A v likewise, u = u_bar / ||u_bar||_B.
+    Eigenproblem: B x_bar = A x from x_bar = x, x = x_bar / ||x_bar||_B.
     """
     A, B, C = lev.A, lev.B, lev.C
     if kind == SPD:
-        Xb = U - omega * (B @ U - A @ U) / _diag(B)[:, None]
+        rhs = A @ U
+        Xb = U
+        for _ in range(inner):
+            Xb = Xb - omega * (B @ Xb - rhs) / _diag(B)[:, None]
         return Xb / _bnorm(B, Xb), None
-    Vb = V - omega * (C @ V - A.T @ U) / _diag(C)[:, None]
+    rhs = A.T @ U
+    Vb = V
+    for _ in range(inner):
+        Vb = Vb - omega * (C @ Vb - rhs) / _diag(C)[:, None]
     V = Vb / _bnorm(C, Vb)
-    Ub = U - omega * (B @ U - A @ V) / _diag(B)[:, None]
+    rhs = A @ V
+    Ub = U
+    for _ in range(inner):
+        Ub = Ub - omega * (B @ Ub - rhs) / _diag(B)[:, None]
     U = Ub / _bnorm(B, Ub)
     return U, V
 
@@ -411,24 +449,33 @@ def relax_test_minimal(lev, kind, U, V):
     """One Kaczmarz sweep on A v = 0 then on A^t u = 0 (SVD) or on A x = 0, then B/C-normalise
     (§5.3, R6, R8)."""
     if kind == SPD:
-        X = kaczmarz_sweep(lev.A, U, None, lev.groups_A)
+        X = kaczmarz_sweep(lev.A, U, None, lev.groups_A, parts=lev.kacz_parts("A"))
         return X / _bnorm(lev.B, X), None
-    V = kaczmarz_sweep(lev.A, V, None, lev.groups_A)
+    V = kaczmarz_sweep(lev.A, V, None, lev.groups_A, parts=lev.kacz_parts("A"))
     V = V / _bnorm(lev.C, V)
-    U = kaczmarz_sweep(lev.At, U, None, lev.groups_At)
+    U = kaczmarz_sweep(lev.At, U, None, lev.groups_At, parts=lev.kacz_parts("At"))
     U = U / _bnorm(lev.B, U)
     return U, V
 
 
-def relax_boot_dominant(lev, kind, U, V, sig, kap, tau, omega):
-    """Block Gauss-Seidel with one weighted-Jacobi inner step per block (§3.5):
-    u <- u - omega D_B^-1 (B u - (A v - kappa)/sigma), then v <- v - omega D_C^-1 (C v - (A^t u - tau)/sigma).
-    Eigenproblem: x <- x - omega D_B^-1 (B x - (A x - kappa)/lambda)."""
+def relax_boot_dominant(lev, kind, U, V, sig, kap, tau, omega, inner=1):
+    """Block Gauss-Seidel with ``inner`` weighted-Jacobi steps per block (mu_bJ, §3.5):
+    u <- u - omega D_B^-1 (B u - (A v - kappa)/sigma) with v fixed, then
+    v <- v - omega D_C^-1 (C v - (A^t u - tau)/sigma) with the new u fixed.
+    Eigenproblem: x <- x - omega D_B^-1 (B x - (A x0 - kappa)/lambda), x0 the outer iterate."""
     A, B, C = lev.A, lev.B, lev.C
     if kind == SPD:
-        return U - omega * (B @ U - (A @ U - kap) / sig[None, :]) / _diag(B)[:, None], None
-    U = U - omega * (B @ U - (A @ V - kap) / sig[None, :]) / _diag(B)[:, None]
-    V = V - omega * (C @ V - (A.T @ U - tau) / sig[None, :]) / _diag(C)[:, None]
+        rhs = (A @ U - kap) / sig[None, :]
+        X = U
+        for _ in range(inner):
+            X = X - omega * (B @ X - rhs) / _diag(B)[:, None]
+        return X, None
+    rhs = (A @ V - kap) / sig[None, :]
+    for _ in range(inner):
+        U = U - omega * (B @ U - rhs) / _diag(B)[:, None]
+    rhs = (A.T @ U - tau) / sig[None, :]
+    for _ in range(inner):
+        V = V - omega * (C @ V - rhs) / _diag(C)[:, None]
     return U, V
 
 
@@ -437,13 +484,21 @@ def relax_boot_minimal(lev, kind, U, V, sig, kap, tau):
     from A^t u = sigma C v + tau.  Eigenproblem: Kaczmarz on (A - lambda_j B) x = kappa."""
     A, B, C = lev.A, lev.B, lev.C
     if kind == SPD:
+        # row i of A - lambda_j B is a_i - lambda_j b_i: its residual is
+        # kappa_i - (a_i x - lambda_j b_i x) and its squared norm
+        # a_i.a_i - 2 lambda_j a_i.b_i + lambda_j^2 b_i.b_i, for every column j at once
         X = U.copy()
-        for j in range(X.shape[1]):
-            Mj = sp.csr_matrix(A - sig[j] * B)
-            X[:, j:j + 1] = kaczmarz_sweep(Mj, X[:, j:j + 1], kap[:, j:j + 1], lev.groups_A)
+        for (rows, Ar, ArT), (_, Br, BrT) in zip(lev.kacz_parts("A"), lev.kacz_parts("B")):
+            aa = np.asarray(Ar.multiply(Ar).sum(axis=1)).ravel()[:, None]
+            ab = np.asarray(Ar.multiply(Br).sum(axis=1)).ravel()[:, None]
+            bb = np.asarray(Br.multiply(Br).sum(axis=1)).ravel()[:, None]
+            r = kap[rows] - (Ar @ X - (Br @ X) * sig[None, :])
+            rn = aa - 2.0 * sig[None, :] * ab + sig[None, :] ** 2 * bb
+            coef = np.where(rn > 0, r / np.where(rn > 0, rn, 1.0), 0.0)
+            X += ArT @ coef - BrT @ (coef * sig[None, :])
         return X, None
-    V = kaczmarz_sweep(A, V, sig[None, :] * (B @ U) + kap, lev.groups_A)
-    U = kaczmarz_sweep(A.T.tocsr(), U, sig[None, :] * (C @ V) + tau, lev.groups_At)
+    V = kaczmarz_sweep(A, V, sig[None, :] * (B @ U) + kap, lev.groups_A, parts=lev.kacz_parts("A"))
+    U = kaczmarz_sweep(lev.At, U, sig[None, :] * (C @ V) + tau, lev.groups_At, parts=lev.kacz_parts("At"))
     return U, V
 
 
@@ -461,7 +516,7 @@ def relax_boot_with_rq(lev, kind, target, U, V, sig, params):
     z_v = None if V is None else np.zeros_like(V)
     for _ in range(params.mu_b):
         if target == DOMINANT:
-            U, V = relax_boot_dominant(lev, kind, U, V, sig, z_u, z_v, params.omega)
+            U, V = relax_boot_dominant(lev, kind, U, V, sig, z_u, z_v, params.omega, params.mu_bJ)
         else:
             U, V = relax_boot_minimal(lev, kind, U, V, sig, z_u, z_v)
         sig = rayleigh(lev, kind, U, V)
@@ -681,7 +736,9 @@ class Solver:
     columns) matrix."""
 
     def __init__(self, A, kind, target, n_b, params: Params, init=None):
-        self.kind, self.target, self.n_b, self.p = kind, target, n_b, params
+        # R29: the block holds the n_b wanted pairs and n_guard more
+        self.kind, self.target, self.n_want, self.p = kind, target, n_b, params
+        self.n_b = n_b + params.n_guard
         A = sp.csr_matrix(A, dtype=np.float64)
         A.sort_indices()
         m, n = A.shape
@@ -727,7 +784,7 @@ class Solver:
             # relax test vectors (§3.4 / §5.3)
             for _ in range(p.mu_t):
                 if target == DOMINANT:
-                    Ut, Vt = relax_test_dominant(lev, kind, Ut, Vt, p.omega)
+                    Ut, Vt = relax_test_dominant(lev, kind, Ut, Vt, p.omega, p.mu_tJ)
                 else:
                     Ut, Vt = relax_test_minimal(lev, kind, Ut, Vt)
             tests_u[l], tests_v[l] = Ut, Vt
@@ -813,7 +870,7 @@ class Solver:
             lev = self.levels[l]
             for _ in range(p.mu_b):
                 if target == DOMINANT:
-                    U, V = relax_boot_dominant(lev, kind, U, V, sig, kap, tau, p.omega)
+                    U, V = relax_boot_dominant(lev, kind, U, V, sig, kap, tau, p.omega, p.mu_bJ)
                 else:
                     U, V = relax_boot_minimal(lev, kind, U, V, sig, kap, tau)
             return U, V
@@ -858,7 +915,8 @@ class Solver:
         rho = residuals(A0, self.kind, self.Ub, self.Vb, self.sig, self.anorm)
         self.report["rho"].append(rho)
         it = 0
-        while rho.max() > p.tol and it < p.max_add:
+        nw = self.n_want
+        while rho[:nw].max() > p.tol and it < p.max_add:
             self.additive_vcycle()
             self.sig, self.Ub, self.Vb = self._ritz(self.Ub, self.Vb)
             rho = residuals(A0, self.kind, self.Ub, self.Vb, self.sig, self.anorm)
@@ -866,8 +924,8 @@ class Solver:
             self.report["rho"].append(rho)
             self.report["add_sigma"].append(self.sig.copy())
         self.report["add_iters"] = it
-        self.report["converged"] = bool(rho.max() <= p.tol)
-        return self.sig, self.Ub, self.Vb
+        self.report["converged"] = bool(rho[:nw].max() <= p.tol)
+        return self.sig[:nw], self.Ub[:, :nw], None if self.Vb is None else self.Vb[:, :nw]
 
 
 def _sign_normalise(U, V):

@@ -99,6 +99,10 @@ extern "C" slamg_status slamg_params_init(slamg_params* p, slamg_kind kind, slam
   p->ritz_in_mult = 1;
   p->coarse_pinv = 0;
   p->graphs = 1;
+  p->n_guard = 0;
+  p->mu_tJ = 1;
+  p->mu_bJ = 1;
+  p->kaczmarz_order = 0;
   (void)target;
   return SLAMG_OK;
 }
@@ -254,6 +258,9 @@ static slamg_status prepare(std::string& err, int64_t m0, int64_t n0, const std:
 
 static slamg_status check_params(std::string& err, const Prepared& P, int32_t nb, const slamg_params& p) {
   if (nb < 1 || nb > 16) return fail(err, SLAMG_E_INVALID, "n_b must be in 1..16");
+  if (p.n_guard < 0 || nb + p.n_guard > 16) return fail(err, SLAMG_E_INVALID, "n_b + n_guard must be in 1..16");
+  if (p.mu_tJ < 1 || p.mu_bJ < 1) return fail(err, SLAMG_E_INVALID, "mu_tJ and mu_bJ must be at least 1");
+  if (p.kaczmarz_order != 0 && p.kaczmarz_order != 1) return fail(err, SLAMG_E_INVALID, "unknown kaczmarz_order");
   if (!(p.tol > 0.0)) return fail(err, SLAMG_E_INVALID, "tol must be positive");
   if (p.n_t < 2 || p.n_t > 16) return fail(err, SLAMG_E_INVALID, "n_t must be in 2..16");
   if (p.mu_t < 0 || p.mu_b < 0 || p.n_mult < 1 || p.max_add < 0) return fail(err, SLAMG_E_INVALID, "bad counts");
@@ -267,6 +274,8 @@ static slamg_status check_params(std::string& err, const Prepared& P, int32_t nb
   if (p.strength_rule < 0 || p.strength_rule > 2) return fail(err, SLAMG_E_INVALID, "unknown strength rule");
   if (nb > std::min(P.m0, P.n0)) return fail(err, SLAMG_E_INVALID, "n_b larger than min(m, n)");
   if (nb > std::min(P.A.m, P.A.n)) return fail(err, SLAMG_E_INVALID, "n_b larger than the nonzero part of A");
+  if (nb + p.n_guard > std::min(P.A.m, P.A.n))
+    return fail(err, SLAMG_E_INVALID, "n_b + n_guard larger than the nonzero part of A");
   return SLAMG_OK;
 }
 
@@ -528,9 +537,10 @@ static size_t footprint_estimate(int64_t m, int64_t n, int64_t nnz, slamg_kind k
                                  const slamg_params& p) {
   const double rows = (double)(kind == SLAMG_SVD ? m + n : m);
   const double nc = std::min(1024.0, kind == SLAMG_SVD ? (double)(m + n) : (double)m);
-  const double w = (double)(4 * p.n_t + 12 * nb);
+  const int32_t blk = nb + std::max(p.n_guard, 0);   // the block holds the guard pairs too
+  const double w = (double)(4 * p.n_t + 12 * blk);
   const double bytes = 64.0 * 1024 * 1024 + 400.0 * (double)nnz + 8.0 * rows * w * 2.0 +
-                       8.0 * (3.0 * nb + 10.0) * nc * nc;
+                       8.0 * (3.0 * blk + 10.0) * nc * nc;
   return (size_t)bytes;
 }
 

@@ -179,9 +179,9 @@ void launch_cast_bf16(const double* in, void* out, size_t n, hipStream_t s);
 void launch_copy_cast_fd(const float* in, double* out, size_t n, hipStream_t s);
 void launch_axpy_fd(const float* in, double* out, size_t n, hipStream_t s);   // out += in
 void launch_splitmix_block(long ru, long rv, int w, unsigned long long seed, double* U, double* V, hipStream_t s);
-void launch_sign_argmax(int rows, int w, const double* X, double* sgn, hipStream_t s);
-void launch_scatter_out(int rows, int w, const double* X, const int* keep, const double* sgn, double* out, long ld,
-                        hipStream_t s);
+void launch_sign_argmax(int rows, int ncols, int w, const double* X, double* sgn, hipStream_t s);
+void launch_scatter_out(int rows, int ncols, int w, const double* X, const int* keep, const double* sgn, double* out,
+                        long ld, hipStream_t s);
 void launch_recip(int n, const double* in, double* out, hipStream_t s);
 void launch_perm_gather(int n, const int* perm, const double* in, double* out, hipStream_t s);
 void launch_spgemm_dot(int nnz, const int* rowC, const int* colC, const int* rpL, const int* ciL,

@@ -1362,6 +1362,7 @@ void launch_splitmix_block(long ru, long rv, int w, unsigned long long seed, dou
 // Output convention: sgn_j = -1 when the entry of largest magnitude of column j (lowest index on
 // ties) is negative.  One workgroup per column.
 __global__ __launch_bounds__(BLK) void k_sign_argmax(int rows, int w, const double* __restrict__ X, double* sgn) {
+  // column j of the row-major block X with row stride w
   __shared__ double bv[BLK];
   __shared__ int bi[BLK];
   const int j = blockIdx.x;
@@ -1385,24 +1386,25 @@ __global__ __launch_bounds__(BLK) void k_sign_argmax(int rows, int w, const doub
   }
   if (threadIdx.x == 0) sgn[j] = (bi[0] < rows && X[(long)bi[0] * w + j] < 0.0) ? -1.0 : 1.0;
 }
-void launch_sign_argmax(int rows, int w, const double* X, double* sgn, hipStream_t s) {
-  hipLaunchKernelGGL(k_sign_argmax, dim3(w), dim3(BLK), 0, s, rows, w, X, sgn);
+void launch_sign_argmax(int rows, int ncols, int w, const double* X, double* sgn, hipStream_t s) {
+  hipLaunchKernelGGL(k_sign_argmax, dim3(ncols), dim3(BLK), 0, s, rows, w, X, sgn);
 }
 
-// out[keep[r] + j ld] = sgn_j X[r][j] (column-major output with leading dimension ld)
-__global__ void k_scatter_out(int rows, int w, const double* __restrict__ X, const int* __restrict__ keep,
+// out[keep[r] + j ld] = sgn_j X[r][j] for the first ncols columns of the row-major block X (row
+// stride w); column-major output with leading dimension ld
+__global__ void k_scatter_out(int rows, int ncols, int w, const double* __restrict__ X, const int* __restrict__ keep,
                               const double* __restrict__ sgn, double* __restrict__ out, long ld) {
   long t = (long)blockIdx.x * BLK + threadIdx.x;
-  long r = t / w;
-  int j = (int)(t % w);
+  long r = t / ncols;
+  int j = (int)(t % ncols);
   if (r >= rows) return;
   out[(long)keep[r] + (long)j * ld] = sgn[j] * X[r * w + j];
 }
-void launch_scatter_out(int rows, int w, const double* X, const int* keep, const double* sgn, double* out, long ld,
-                        hipStream_t s) {
-  if (rows > 0)
-    hipLaunchKernelGGL(k_scatter_out, dim3(ceil_div((long)rows * w, BLK)), dim3(BLK), 0, s, rows, w, X, keep, sgn,
-                       out, ld);
+void launch_scatter_out(int rows, int ncols, int w, const double* X, const int* keep, const double* sgn, double* out,
+                        long ld, hipStream_t s) {
+  if (rows > 0 && ncols > 0)
+    hipLaunchKernelGGL(k_scatter_out, dim3(ceil_div((long)rows * ncols, BLK)), dim3(BLK), 0, s, rows, ncols, w, X,
+                       keep, sgn, out, ld);
 }
 
 // explicit instantiations

@@ -181,7 +181,7 @@ class Solver {
  public:
   Solver(hipStream_t s, size_t budget, const Problem& pb, const slamg_params& p)
       : st_(s), ar_(budget, s), p_(p), spd_(pb.kind == SLAMG_SPD_EIG), minimal_(pb.target == SLAMG_MINIMAL),
-        nb_(pb.nb), nt_(p.n_t), mixed_(p.precision == SLAMG_MIXED_FP32 || p.precision == SLAMG_MIXED_BF16),
+        nb_(pb.nb + p.n_guard), nw_(pb.nb), nt_(p.n_t), mixed_(p.precision == SLAMG_MIXED_FP32 || p.precision == SLAMG_MIXED_BF16),
         bf16_(p.precision == SLAMG_MIXED_BF16),
         square_(pb.kind == SLAMG_SVD && p.square_coarsening != 0), A0_(pb.A), pb_(pb) {}
   ~Solver() {
@@ -206,6 +206,7 @@ class Solver {
   void make_coarse_level(int l);
   void refresh_level_aux(Level& L);
   void colour(Level& L);
+  std::vector<int> row_colours(const HCsr& M) const;
   HCsr strength_operator(Level& L, bool u_side, bool finest);
   // cycle pieces
   void relax_tests(int l);
@@ -242,7 +243,9 @@ class Solver {
   Arena ar_;
   slamg_params p_;
   bool spd_, minimal_;
-  int nb_, nt_;
+  int nb_;   // block width: the n_b wanted pairs and the guard pairs
+  int nw_;   // wanted pairs: the stopping test and the outputs
+  int nt_;
   bool mixed_;
   bool bf16_;   // the FP32 V-cycle reads BF16 operator values (their bit patterns in the .vf arrays)
   bool square_; // SVD of a square A with both sides coarsened on A itself (§5.1)
@@ -641,12 +644,23 @@ static std::vector<long> colour_nnz(const HCsr& A, const std::vector<int>& rows,
   return z;
 }
 
+// Kaczmarz row order (§5.3): multicolour (greedy first-fit colouring of "rows sharing a column"),
+// or lexicographic, every row its own colour.
+std::vector<int> Solver::row_colours(const HCsr& M) const {
+  if (p_.kaczmarz_order == 1) {
+    std::vector<int> c(M.m);
+    for (int i = 0; i < M.m; ++i) c[i] = i;
+    return c;
+  }
+  return greedy_row_colouring(M);
+}
+
 void Solver::colour(Level& L) {
   if (!minimal_) return;
   std::vector<int> rows, cptr;
   if (spd_) {
     HCsr pat = L.hA;   // B_l lives on A_l's pattern
-    colour_order(greedy_row_colouring(pat), rows, cptr);
+    colour_order(row_colours(pat), rows, cptr);
     L.kA_rows = ar_.alloc<int>(rows.size());
     h2d(L.kA_rows, rows, st_);
     L.kA_cptr = cptr;
@@ -655,13 +669,13 @@ void Solver::colour(Level& L) {
     h2d(L.d_kA_cptr, cptr, st_);
     L.kacz_wg = L.m <= KACZ_WG_MAX_ROWS;
   } else {
-    colour_order(greedy_row_colouring(L.hA), rows, cptr);
+    colour_order(row_colours(L.hA), rows, cptr);
     L.kA_rows = ar_.alloc<int>(rows.size());
     h2d(L.kA_rows, rows, st_);
     L.kA_cptr = cptr;
     L.kA_cnnz = colour_nnz(L.hA, rows, cptr);
     std::vector<int> rows2, cptr2;
-    colour_order(greedy_row_colouring(L.hAt), rows2, cptr2);
+    colour_order(row_colours(L.hAt), rows2, cptr2);
     L.kAt_rows = ar_.alloc<int>(rows2.size());
     h2d(L.kAt_rows, rows2, st_);
     L.kAt_cptr = cptr2;
@@ -1033,13 +1047,22 @@ void Solver::relax_tests(int l) {
   for (int it = 0; it < p_.mu_t; ++it) {
     if (!minimal_) {
       if (spd_) {
-        // x_bar = x - w D_B^-1 (B x - A x),  x = x_bar / ||x_bar||_B
+        // mu_tJ weighted-Jacobi steps on B x_bar = A x from x_bar = x:
+        // x_bar <- x_bar - w D_B^-1 (B x_bar - A x); then x = x_bar / ||x_bar||_B
         RowOpArgs<double> a;
         a.nrows = mu; a.w = nt_;
         a.Krp = L.A.rp; a.Kci = L.A.ci; a.nnzK = L.A.nnz; a.Kv = L.A.v; a.z = b.Ut;
         a.mmode = L.finest ? M_IDENT : M_SHARED; a.Mv = L.B.v; a.y = b.Ut;
         a.x = b.Ut; a.D = L.ad.dinvB; a.cmode = C_JAC_TEST; a.omega = p_.omega_J; a.out = b.tU;
         rowop(l, a, &L.A);
+        if (!L.finest) {   // B x_bar on B's own walk (the shared walk multiplies z only)
+          a.mmode = M_CSR; a.Mrp = L.A.rp; a.Mci = L.A.ci; a.avgM = avg_row(L.A);
+        }
+        for (int j = 1; j < p_.mu_tJ; ++j) {   // A x stays the product with the outer iterate
+          a.y = b.tU; a.x = b.tU; a.out = b.tU2;
+          rowop(l, a, &L.A);
+          std::swap(b.tU, b.tU2);
+        }
         std::swap(b.Ut, b.tU);
         da = DotArgs<double>{};
         da.nrows = mu; da.w = nt_; da.a = b.Ut; da.z = b.Ut;
@@ -1053,8 +1076,11 @@ void Solver::relax_tests(int l) {
         a.Krp = L.At.rp; a.Kci = L.At.ci; a.nnzK = L.At.nnz; a.Kv = L.At.v; a.z = b.Ut;
         a.mmode = L.finest ? M_IDENT : M_CSR; a.Mrp = L.C.rp; a.avgM = avg_row(L.C); a.Mci = L.C.ci; a.Mv = L.C.v; a.y = b.Vt;
         a.x = b.Vt; a.D = L.ad.dinvC; a.cmode = C_JAC_TEST; a.omega = p_.omega_J; a.out = b.tV;
-        rowop(l, a, &L.At);
-        std::swap(b.Vt, b.tV);
+        for (int j = 0; j < p_.mu_tJ; ++j) {   // mu_tJ Jacobi steps on C v_bar = A^t u
+          a.y = b.Vt; a.x = b.Vt; a.out = b.tV;
+          rowop(l, a, &L.At);
+          std::swap(b.Vt, b.tV);
+        }
         da = DotArgs<double>{};
         da.nrows = mv; da.w = nt_; da.a = b.Vt; da.z = b.Vt;
         if (!L.finest) { da.Krp = L.C.rp; da.Kci = L.C.ci; da.nnzK = L.C.nnz; da.Kv = L.C.v; }
@@ -1065,8 +1091,11 @@ void Solver::relax_tests(int l) {
         c.Krp = L.A.rp; c.Kci = L.A.ci; c.nnzK = L.A.nnz; c.Kv = L.A.v; c.z = b.Vt;
         c.mmode = L.finest ? M_IDENT : M_CSR; c.Mrp = L.B.rp; c.avgM = avg_row(L.B); c.Mci = L.B.ci; c.Mv = L.B.v; c.y = b.Ut;
         c.x = b.Ut; c.D = L.ad.dinvB; c.cmode = C_JAC_TEST; c.omega = p_.omega_J; c.out = b.tU;
-        rowop(l, c, &L.A);
-        std::swap(b.Ut, b.tU);
+        for (int j = 0; j < p_.mu_tJ; ++j) {   // mu_tJ Jacobi steps on B u_bar = A v
+          c.y = b.Ut; c.x = b.Ut; c.out = b.tU;
+          rowop(l, c, &L.A);
+          std::swap(b.Ut, b.tU);
+        }
         da = DotArgs<double>{};
         da.nrows = mu; da.w = nt_; da.a = b.Ut; da.z = b.Ut;
         if (!L.finest) { da.Krp = L.B.rp; da.Kci = L.B.ci; da.nnzK = L.B.nnz; da.Kv = L.B.v; }
@@ -1190,6 +1219,29 @@ void Solver::boot_relax(int l, const T* kap, const T* tau, const double* sig, in
       a.out = b.Ua;
       if (zero_start) { a.Kv = nullptr; a.mmode = M_NONE; a.x = nullptr; }
       rowop(l, a, &L.A);
+      if (p_.mu_bJ > 1) {
+        // further Jacobi steps on B x_new = (A x - kappa)/lambda, A x from the outer iterate
+        // (kept in the scratch block tU)
+        T* keep = b.tU;
+        if (zero_start) {
+          if (std::is_same<T, float>::value) launch_fillf((float*)keep, (size_t)mu * nb_, 0.0f, st_);
+          else launch_fill((double*)keep, (size_t)mu * nb_, 0.0, st_);
+        } else {
+          HIPCHK(hipMemcpyAsync(keep, b.Ub, sizeof(T) * (size_t)mu * nb_, hipMemcpyDeviceToDevice, st_));
+        }
+        a = RowOpArgs<T>{};
+        a.nrows = mu; a.w = nb_;
+        a.Krp = L.A.rp; a.Kci = L.A.ci; a.nnzK = L.A.nnz; a.Kv = vals<T>(L.A); a.z = keep;
+        // B x on B's own walk (B_l shares A_l's pattern; the shared walk multiplies z only)
+        a.mmode = L.finest ? M_IDENT : M_CSR; a.Mrp = L.A.rp; a.Mci = L.A.ci; a.avgM = avg_row(L.A);
+        a.Mv = vals<T>(L.B); a.D = x.dinvB; a.kap = kap; a.sig = sig;
+        a.cmode = C_JAC_BOOT; a.omega = p_.omega_J;
+        for (int j = 1; j < p_.mu_bJ; ++j) {
+          a.y = b.Ua; a.x = b.Ua; a.out = b.Ub;
+          rowop(l, a, &L.A);
+          std::swap(b.Ub, b.Ua);
+        }
+      }
       std::swap(b.Ub, b.Ua);
     } else {
       // u <- u - w D_B^-1 (B u - (A v - kappa)/sigma); then v <- v - w D_C^-1 (C v - (A^t u - tau)/sigma)
@@ -1201,6 +1253,11 @@ void Solver::boot_relax(int l, const T* kap, const T* tau, const double* sig, in
       a.out = b.Ua;
       if (zero_start) { a.Kv = nullptr; a.mmode = M_NONE; a.x = nullptr; }
       rowop(l, a, &L.A);
+      for (int j = 1; j < p_.mu_bJ; ++j) {   // further Jacobi steps on B u = (A v - kappa)/sigma
+        a.mmode = L.finest ? M_IDENT : M_CSR; a.y = b.Ua; a.x = b.Ua; a.out = b.Ub;
+        rowop(l, a, &L.A);
+        std::swap(b.Ub, b.Ua);
+      }
       RowOpArgs<T> c;
       c.nrows = mv; c.w = nb_;
       c.Krp = L.At.rp; c.Kci = L.At.ci; c.nnzK = L.At.nnz; c.Kv = vals<T>(L.At); c.z = b.Ua;
@@ -1209,6 +1266,11 @@ void Solver::boot_relax(int l, const T* kap, const T* tau, const double* sig, in
       c.out = b.Va;
       if (zero_start) { c.mmode = M_NONE; c.x = nullptr; }
       rowop(l, c, &L.At);
+      for (int j = 1; j < p_.mu_bJ; ++j) {   // further Jacobi steps on C v = (A^t u - tau)/sigma
+        c.mmode = L.finest ? M_IDENT : M_CSR; c.y = b.Va; c.x = b.Va; c.out = b.Vb;
+        rowop(l, c, &L.At);
+        std::swap(b.Vb, b.Va);
+      }
       std::swap(b.Ub, b.Ua);
       std::swap(b.Vb, b.Va);
     }
@@ -1807,7 +1869,7 @@ void Solver::run(const double* init_tests, SolveOutput& out) {
     rep_.colours[l] = (int)(lv_[l]->kA_cptr.empty() ? 0 : lv_[l]->kA_cptr.size() - 1);
   }
   residuals(rho);
-  double rmax = *std::max_element(rho.begin(), rho.end());
+  double rmax = *std::max_element(rho.begin(), rho.begin() + nw_);
   rep_.rho_history[0] = rmax;
   auto t1 = clk::now();
   // additive phase: frozen operators (dense coarsest matrices built once)
@@ -1849,7 +1911,7 @@ void Solver::run(const double* init_tests, SolveOutput& out) {
       iteration_body();
     }
     residual_collect(rho);
-    rmax = *std::max_element(rho.begin(), rho.end());
+    rmax = *std::max_element(rho.begin(), rho.begin() + nw_);
     ++it;
     if (it < 256) rep_.rho_history[it] = rmax;
     if (p_.verbose > 0 && it % p_.verbose == 0) {
@@ -1865,7 +1927,7 @@ void Solver::run(const double* init_tests, SolveOutput& out) {
   rep_.device_bytes = (int64_t)ar_.used();
   rep_.t_setup_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
   rep_.t_solve_ms = std::chrono::duration<double, std::milli>(t2 - t1).count();
-  for (int j = 0; j < nb_ && j < 16; ++j) {
+  for (int j = 0; j < nw_ && j < 16; ++j) {
     rep_.resid[j] = rho[j];
     rep_.err_bound[j] = rho[j] * anorm_;
   }
@@ -1878,23 +1940,31 @@ void Solver::run(const double* init_tests, SolveOutput& out) {
     const bool refU = spd_ || pb_.swapUV;
     const double* ref = refU ? L.bd.Ub : L.bd.Vb;
     const int rref = refU ? rows_u(L) : rows_v(L);
-    launch_sign_argmax(rref, nb_, ref, flip_, st_);
+    launch_sign_argmax(rref, nw_, nb_, ref, flip_, st_);
     double* dstU = pb_.swapUV ? pb_.outV : pb_.outU;
     double* dstV = pb_.swapUV ? pb_.outU : pb_.outV;
     long ldu = pb_.swapUV ? pb_.ldV : pb_.ldU, ldv = pb_.swapUV ? pb_.ldU : pb_.ldV;
     if (dstU) {
-      launch_fill(dstU, (size_t)ldu * nb_, 0.0, st_);
-      launch_scatter_out(rows_u(L), nb_, L.bd.Ub, pb_.keepU, flip_, dstU, ldu, st_);
+      launch_fill(dstU, (size_t)ldu * nw_, 0.0, st_);
+      launch_scatter_out(rows_u(L), nw_, nb_, L.bd.Ub, pb_.keepU, flip_, dstU, ldu, st_);
     }
     if (!spd_ && dstV) {
-      launch_fill(dstV, (size_t)ldv * nb_, 0.0, st_);
-      launch_scatter_out(rows_v(L), nb_, L.bd.Vb, pb_.keepV, flip_, dstV, ldv, st_);
+      launch_fill(dstV, (size_t)ldv * nw_, 0.0, st_);
+      launch_scatter_out(rows_v(L), nw_, nb_, L.bd.Vb, pb_.keepV, flip_, dstV, ldv, st_);
     }
-    d2h(out.sigma, sig_, nb_, st_);
+    d2h(out.sigma, sig_, nw_, st_);
   } else {
-    d2h(out.sigma, sig_, nb_, st_);
-    d2h(out.U, L.bd.Ub, (size_t)rows_u(L) * nb_, st_);
-    if (!spd_) d2h(out.V, L.bd.Vb, (size_t)rows_v(L) * nb_, st_);
+    // the wanted columns of the row-major blocks (the guard pairs are dropped)
+    auto wanted = [&](std::vector<double>& dst, const double* X, int rows) {
+      std::vector<double> h;
+      d2h(h, X, (size_t)rows * nb_, st_);
+      dst.resize((size_t)rows * nw_);
+      for (int r = 0; r < rows; ++r)
+        for (int j = 0; j < nw_; ++j) dst[(size_t)r * nw_ + j] = h[(size_t)r * nb_ + j];
+    };
+    d2h(out.sigma, sig_, nw_, st_);
+    wanted(out.U, L.bd.Ub, rows_u(L));
+    if (!spd_) wanted(out.V, L.bd.Vb, rows_v(L));
   }
   out.rep = rep_;
   out.status = rep_.converged ? ST_OK : ST_NOT_CONVERGED;

@@ -323,10 +323,12 @@ WORKLOADS = {
                                            mu_b=4, n_mult=3, coarse_pinv=1)),
     "aniso3d_128_min8": dict(desc="3-D anisotropic 7-point Dirichlet 128^3 (n=2097152, eps=0.01), 8 minimal eigenpairs",
                              kind="spd", target="minimal", n_b=8,
-                             # coarse_max 128: the validated hierarchy of this operator (with 64 the
-                             # mixed-precision residual history departs from the FP64 one mid-run)
-                             params=dict(theta=0.06, n_t=8, mu_t=4, mu_b=4, n_mult=10, coarse_pinv=1,
-                                         coarse_max=128)),
+                             # a diagonally dominant PDE discretisation: the max-based strength rule
+                             # of §3.7 with theta 0.25; 8 guard pairs (R29) keep the 8 wanted pairs
+                             # clear of the 9th, whose coarse-level representation limits the last
+                             # pair of the block
+                             params=dict(theta=0.25, strength_rule=1, n_t=8, mu_t=4, mu_b=4, n_mult=10,
+                                         coarse_pinv=1, coarse_max=128, n_guard=8)),
 }
 
 

@@ -628,3 +628,44 @@ def test_minimal_presmooth_square_coarsening_uses_a():
     levz = O.Level(Z, sp.identity(2, format="csr"), sp.identity(2, format="csr"))
     out = O.minimal_presmooth(levz, O.SVD, True, np.array([[1.0], [1.0]]), 0.7, square=True)
     assert out[0, 0] == 1.0 and out[1, 0] == 1.0 - 0.7 * 3.0 / 2.0
+
+
+def test_inner_jacobi_steps_converge_to_the_exact_block_solves():
+    # §3.4 / §3.5: the inner weighted-Jacobi steps approximate the solves of C v_bar = A^t u and
+    # B u_bar = A v (test vectors) and of B u = (A v - kappa)/sigma (boot vectors).  With B = C = I
+    # every step contracts the error by 1 - omega = 0.3, so 60 steps reach the exact power step
+    # v = A^t u / ||A^t u||, u = A v / ||A v|| and the exact block solve u = (A v - kappa)/sigma.
+    lev, U, s, V = _tiny_svd_level()
+    rng = np.random.default_rng(8)
+    U0 = rng.normal(size=U.shape); V0 = rng.normal(size=V.shape)
+    Ad = lev.A.toarray()
+    Ut, Vt = O.relax_test_dominant(lev, O.SVD, U0, V0, 0.7, inner=60)
+    v = Ad.T @ U0; v /= np.linalg.norm(v, axis=0)
+    u = Ad @ v; u /= np.linalg.norm(u, axis=0)
+    assert np.allclose(Vt, v, atol=1e-12) and np.allclose(Ut, u, atol=1e-12)
+    kap = rng.normal(size=U.shape); tau = rng.normal(size=V.shape); sig = np.array([0.5, 1.5, 2.0, 3.0, 1.0, 0.7])[:U.shape[1]]
+    Ub, Vb = O.relax_boot_dominant(lev, O.SVD, U0, V0, sig, kap, tau, 0.7, inner=60)
+    ub = (Ad @ V0 - kap) / sig
+    vb = (Ad.T @ ub - tau) / sig
+    assert np.allclose(Ub, ub, atol=1e-11) and np.allclose(Vb, vb, atol=1e-11)
+    # one inner step is the single step of the paper's formulas
+    U1, V1 = O.relax_boot_dominant(lev, O.SVD, U0, V0, sig, kap, tau, 0.7, inner=1)
+    u1 = U0 - 0.7 * (U0 - (Ad @ V0 - kap) / sig)
+    assert np.allclose(U1, u1, atol=1e-13)
+
+
+def test_guard_pairs_and_lexicographic_kaczmarz_end_to_end():
+    # R29: a block with guard pairs returns the n_b extremal pairs of the dense spectrum; the
+    # lexicographic Kaczmarz order (row by row) converges to the same eigenvalues
+    L = W.laplace2d(10).to_scipy()
+    ev = np.linalg.eigvalsh(L.toarray())
+    r = _run(L, O.SPD, O.MINIMAL, 3, coarse_max=30, n_t=6, mu_t=4, mu_b=4, n_mult=6, tol=1e-11, n_guard=3)
+    assert r.report["converged"] and r.U.shape == (100, 3) and r.sigma.shape == (3,)
+    assert np.allclose(r.sigma, ev[:3], rtol=1e-10)
+    assert len(r.report["rho"][-1]) == 6 and np.max(r.report["rho"][-1][:3]) <= 1e-11
+    r2 = _run(L, O.SPD, O.MINIMAL, 3, coarse_max=30, n_t=6, mu_t=4, mu_b=4, n_mult=6, tol=1e-11,
+              kaczmarz_order=1)
+    assert r2.report["converged"] and np.allclose(r2.sigma, ev[:3], rtol=1e-10)
+    # the lexicographic order is a different iteration (not the multicolour one)
+    r0 = _run(L, O.SPD, O.MINIMAL, 3, coarse_max=30, n_t=6, mu_t=4, mu_b=4, n_mult=6, tol=1e-11)
+    assert not np.allclose(r2.report["mult_sigma"][0], r0.report["mult_sigma"][0], rtol=1e-12)
