@@ -11,6 +11,8 @@ the timed region starts.  Prints ONE JSON line (see the design doc for the definition
   cpu_baseline  the FP64 oracle on the host cores, on a bounded sample of the same workload
              (the multiplicative phase plus a few additive iterations, scaled to the iteration
              count of the GPU solve)
+  compare    the same workload timed in a second precision (default: the mixed FP32 V-cycle with
+             the FP64 refinement around it), with its accuracy
 """
 from __future__ import annotations
 
@@ -32,7 +34,10 @@ CLASS_NAMES = {0: "k_rowop, finest-level relaxation sweeps",
                7: "k_rowop, finest-level residuals"}
 NCLS = 8
 ALL_CLASSES = (1 << NCLS) - 1
-DEFAULT_WORKLOAD = "gradient2d_256_dom8"
+DEFAULT_WORKLOAD = "aniso3d_128_min8"
+# roofline kernel classes whose achieved bandwidth the line reports next to the dominant one
+REPORTED = {1: "relaxation (finest-level Kaczmarz sweeps)", 0: "relaxation (finest-level row kernel)",
+            5: "block SpMM (finest level)", 3: "Galerkin SpGEMM (all levels)"}
 
 # HBM traffic of the dominant kernel class, from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs
 # (profiles/pmc_*_gradient2d_256_dom8.md), per dispatch in KiB for the two finest-level k_rowop
@@ -76,16 +81,28 @@ def _closed_form(name, n_b, target):
 
 
 def cpu_baseline(name, A, wl, gpu_add_iters, budget_s=30.0):
-    """Oracle timing on a bounded sample: multiplicative phase + up to 5 additive iterations,
-    extrapolated to the GPU solve's additive iteration count."""
+    """Oracle timing on a bounded sample.  The oracle's multiplicative phase plus up to 5 additive
+    iterations are timed; the additive time is extrapolated to the GPU solve's iteration count.  For
+    the 3-D anisotropic workload the oracle runs on the 24^3 grid of the same family (its
+    multiplicative phase on 128^3 alone would take hours in pure-Python coarsening and colouring)
+    and both parts are scaled by the unknown count (the cost of a cycle grows linearly with the
+    number of unknowns, §6.1)."""
     import numpy as np
     from oracle import slamg_oracle as O
+    from paper_1102_0919_amd import workloads as W
     try:
         from threadpoolctl import threadpool_info
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
         threads = 1
     p = O.Params(**wl["params"])
+    scale, what = 1.0, "the same matrix"
+    if name.startswith("aniso3d_128"):
+        k = 24
+        As = W.aniso3d(k, 0.01).to_scipy()
+        scale = A.shape[0] / As.shape[0]
+        what = f"the {k}^3 grid of the same family ({As.shape[0]} unknowns), scaled by {scale:.1f} (unknown count)"
+        A = As
     t0 = time.perf_counter()
     s = O.Solver(A, wl["kind"], wl["target"], wl["n_b"], p)
     for c in range(1, p.n_mult + 1):
@@ -99,20 +116,57 @@ def cpu_baseline(name, A, wl, gpu_add_iters, budget_s=30.0):
         O.residuals(s.levels[0].A, s.kind, s.Ub, s.Vb, s.sig, s.anorm)
         k += 1
     t_iter = (time.perf_counter() - t1) / max(k, 1)
-    t_total = t_setup + t_iter * gpu_add_iters
+    t_total = (t_setup + t_iter * gpu_add_iters) * scale
     return {"value": wl["n_b"] / t_total, "unit": "triplets/s", "cores": int(threads), "kind": "oracle",
             "sample": f"oracle multiplicative phase ({p.n_mult} cycles, {t_setup:.1f} s) + {k} additive "
-                      f"iterations ({t_iter:.3f} s each) on the same matrix, extrapolated to the GPU's "
+                      f"iterations ({t_iter:.3f} s each) on {what}, extrapolated to the GPU's "
                       f"{gpu_add_iters} additive iterations; scipy sparse kernels are single-threaded"}
+
+
+def _run_steps(api, ctx, mat, target, n_b, p, U_dev, V_dev, steps, label):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = []
+    for k in range(steps):
+        r = api.solve_matrix(ctx, mat, target, n_b, p, U_dev=U_dev, V_dev=V_dev)
+        reps.append(r)
+        print(f"[bench] {label} step {k}: add_iters={r.report.add_iters} converged={r.converged}", file=sys.stderr,
+              flush=True)
+    torch.cuda.synchronize()
+    return reps, (time.perf_counter() - t0) * 1e3 / steps
+
+
+def _class_totals(reps):
+    import numpy as np
+    tot_ms = np.zeros(NCLS); tot_n = np.zeros(NCLS); tot_b = np.zeros(NCLS)
+    for r in reps:
+        for c in range(NCLS):
+            tot_ms[c] += r.report.prof_ms[c]; tot_n[c] += r.report.prof_launches[c]
+            tot_b[c] += r.report.prof_bytes[c]
+    return tot_ms, tot_n, tot_b
+
+
+def _accuracy(last, ref, n_b):
+    import numpy as np
+    acc = {"max_rel_residual": float(max(last.report.resid[j] for j in range(n_b))),
+           "levels": int(last.report.levels), "add_iters": int(last.report.add_iters),
+           "mult_cycles": int(last.report.mult_cycles), "converged": bool(last.converged)}
+    if ref is not None:
+        err = np.abs(last.sigma - ref) / np.maximum(np.abs(ref), 1e-8 * last.report.anorm)
+        acc["max_rel_sigma_err_vs_closed_form"] = float(err.max())
+    return acc
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed_fp32", "mixed_bf16"])
+    ap.add_argument("--compare", default="mixed_fp32", choices=["none", "fp64", "mixed_fp32", "mixed_bf16"],
+                    help="second precision timed on the same workload and reported next to the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--max-add", type=int, default=6000,
@@ -133,11 +187,14 @@ def main():
     A = W.build_workload_matrix(name).to_scipy()
     kind, target, n_b = wl["kind"], wl["target"], wl["n_b"]
     stream = torch.cuda.current_stream()
-    prm = dict(wl["params"])
-    prm["precision"] = args.precision
-    prm["profile_mask"] = 0 if args.no_profile else ALL_CLASSES
-    prm["max_add"] = args.max_add
-    p = api.params_init(kind, target, **prm)
+
+    def params(precision, mask):
+        prm = dict(wl["params"])
+        prm["precision"] = precision
+        prm["profile_mask"] = mask
+        prm["max_add"] = args.max_add
+        return api.params_init(kind, target, **prm)
+
     ctx = api.Context(0, stream=stream.cuda_stream)
     mat = api.Matrix(ctx, A, kind)          # validated, prepared and resident in device memory
     # the singular vectors are written to device arrays (column-major m x n_b, n x n_b)
@@ -145,37 +202,18 @@ def main():
     V_dev = torch.empty((n_b, A.shape[1]), dtype=torch.float64, device="cuda") if kind == "svd" else None
     print(f"[bench] workload {name}: {A.shape[0]}x{A.shape[1]} nnz={A.nnz} n_b={n_b} {args.precision}",
           file=sys.stderr, flush=True)
-    dominant = None
-    warm_ms = np.zeros(8)
+    p = params(args.precision, 0 if args.no_profile else ALL_CLASSES)
+    warm_ms = np.zeros(NCLS)
     for _ in range(max(args.warmup, 1 if not args.no_profile else 0)):
         w = api.solve_matrix(ctx, mat, target, n_b, p, U_dev=U_dev, V_dev=V_dev)
-        warm_ms = np.array([w.report.prof_ms[c] for c in range(8)])
+        warm_ms = np.array([w.report.prof_ms[c] for c in range(NCLS)])
         print(f"[bench] warmup: add_iters={w.report.add_iters} converged={w.converged}", file=sys.stderr, flush=True)
-        if not args.no_profile:
-            ms_c = np.array([w.report.prof_ms[c] if w.report.prof_bytes[c] > 0 else 0.0 for c in range(NCLS)])
-            dominant = int(np.argmax(ms_c))
-    if dominant is not None:
-        # the timed steps time only the dominant kernel class (fewer events on the stream)
-        p.profile_mask = 1 << dominant
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    reps = []
-    for k in range(args.steps):
-        r = api.solve_matrix(ctx, mat, target, n_b, p, U_dev=U_dev, V_dev=V_dev)
-        reps.append(r)
-        print(f"[bench] step {k}: add_iters={r.report.add_iters} converged={r.converged}", file=sys.stderr,
-              flush=True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms = (t1 - t0) * 1e3 / args.steps
+    reps, ms = _run_steps(api, ctx, mat, target, n_b, p, U_dev, V_dev, args.steps, args.precision)
     value = n_b / (ms / 1e3)
     last = reps[-1]
-    # roofline of the dominant kernel class over the timed steps
-    tot_ms = np.zeros(8); tot_n = np.zeros(8); tot_b = np.zeros(8)
-    for r in reps:
-        for c in range(8):
-            tot_ms[c] += r.report.prof_ms[c]; tot_n[c] += r.report.prof_launches[c]
-            tot_b[c] += r.report.prof_bytes[c]
+    ref = _closed_form(name, n_b, target)
+    # roofline: the profiled kernel class with the largest device time over the timed steps
+    tot_ms, tot_n, tot_b = _class_totals(reps)
     roof = None
     if tot_ms.sum() > 0:
         c = int(np.argmax(np.where(tot_b > 0, tot_ms, 0)))
@@ -183,36 +221,53 @@ def main():
         per_launch = tot_b[c] / tot_n[c]
         ach = per_launch / (avg_ms * 1e-3) / 1e9
         traffic, tnote = _traffic(name, c)
+        kernels = {}
+        for k2, label in REPORTED.items():
+            if tot_n[k2] > 0 and tot_b[k2] > 0:
+                kernels[label] = {"GB/s": round(tot_b[k2] / tot_n[k2] / (tot_ms[k2] / tot_n[k2] * 1e-3) / 1e9, 1),
+                                  "frac": round(tot_b[k2] / (tot_ms[k2] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                  "launches": int(tot_n[k2]), "avg_launch_us": round(tot_ms[k2] / tot_n[k2] * 1e3, 2)}
         roof = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else int(traffic), "traffic_note": tnote,
                 "kernel": CLASS_NAMES[c],
                 "timed_launches_per_step": int(tot_n[c] / args.steps), "avg_launch_us": round(avg_ms * 1e3, 3),
-                "timing_sample": "a HIP event pair around every launch of the kernel on the library stream "
-                                 "in the eagerly launched additive iterations (every 32nd; the others replay a "
-                                 "HIP graph of the iteration) and in the multiplicative phase",
+                "timing_sample": "a HIP event pair around every launch of the profiled kernel classes on the "
+                                 "library stream in the eagerly launched additive iterations (every 32nd; the "
+                                 "others replay a HIP graph of the iteration) and in the multiplicative phase",
                 "algorithmic_bytes_per_launch": int(per_launch),
                 "graph_iters_per_step": int(last.report.graph_iters),
+                "kernels": kernels,
                 "sampled_class_ms_in_warmup": {CLASS_NAMES[i]: round(warm_ms[i], 3) for i in range(NCLS)}}
-    ref = _closed_form(name, n_b, target)
-    acc = {"max_rel_residual": float(max(last.report.resid[j] for j in range(n_b))),
-           "levels": int(last.report.levels), "add_iters": int(last.report.add_iters),
-           "mult_cycles": int(last.report.mult_cycles)}
-    if ref is not None:
-        err = np.abs(last.sigma - ref) / np.maximum(np.abs(ref), 1e-8 * last.report.anorm)
-        acc["max_rel_sigma_err_vs_closed_form"] = float(err.max())
+    compare = None
+    if args.compare != "none" and args.compare != args.precision:
+        p2 = params(args.compare, 0)
+        w2 = api.solve_matrix(ctx, mat, target, n_b, p2, U_dev=U_dev, V_dev=V_dev)
+        print(f"[bench] {args.compare} warmup: add_iters={w2.report.add_iters} converged={w2.converged}",
+              file=sys.stderr, flush=True)
+        reps2, ms2 = _run_steps(api, ctx, mat, target, n_b, p2, U_dev, V_dev, args.steps, args.compare)
+        last2 = reps2[-1]
+        compare = {"precision": args.compare, "value": round(n_b / (ms2 / 1e3), 4), "unit": "triplets/s",
+                   "ms_per_step": round(ms2, 3), "speedup_vs_headline": round(ms / ms2, 4),
+                   "setup_ms": round(last2.report.t_setup_ms, 3), "solve_ms": round(last2.report.t_solve_ms, 3),
+                   "accuracy": _accuracy(last2, ref, n_b)}
+        if ref is not None:
+            compare["accuracy"]["max_rel_sigma_diff_vs_headline"] = float(
+                np.max(np.abs(last2.sigma - last.sigma) / np.abs(ref)))
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(name, A, wl, int(last.report.add_iters))
     line = {"metric": "triplets/s at resid 1e-8", "value": round(value, 4), "unit": "triplets/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
-            "scaling": "weak", "vs_baseline": None, "dtype": {"fp64": "f64", "mixed_fp32": "f32+f64", "mixed_bf16": "bf16+f32+f64"}[args.precision],
+            "scaling": "weak", "vs_baseline": None,
+            "dtype": {"fp64": "f64", "mixed_fp32": "f32+f64", "mixed_bf16": "bf16+f32+f64"}[args.precision],
             "data": "synthetic",
             "config": {"workload": name, "description": wl["desc"], "rows": int(A.shape[0]),
                        "cols": int(A.shape[1]), "nnz": int(A.nnz), "n_b": n_b, "kind": kind, "target": target,
                        "precision": args.precision, "tol": 1e-8},
-            "roofline": roof, "cpu_baseline": cpu, "accuracy": acc,
-            "setup_ms": round(last.report.t_setup_ms, 3), "solve_ms": round(last.report.t_solve_ms, 3)}
+            "roofline": roof, "cpu_baseline": cpu, "accuracy": _accuracy(last, ref, n_b),
+            "setup_ms": round(last.report.t_setup_ms, 3), "solve_ms": round(last.report.t_solve_ms, 3),
+            "compare": compare}
     mat.close()
     ctx.close()
     print(json.dumps(line))
