@@ -89,6 +89,21 @@ slamg_status slamg_op_dots(int32_t nrows, int32_t w, const double* d_a, const in
 slamg_status slamg_op_gram(int32_t rows, int32_t w, const double* d_x, const double* d_y, double* h_g,
                            void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): slamg_op_gram with the result G = X^t Y (w x w,
+ * row-major) written to the device array d_g, and the reduction's per-workgroup partial sums kept
+ * in a fixed device array of slamg_op_gram_noalloc_scratch_bytes() bytes (4 MiB; one per GPU,
+ * held until the process ends) instead of memory it allocates.  It allocates and frees nothing,
+ * does not synchronise (the kernels are queued on `stream`; read d_g after the stream's work), and
+ * needs no zeroed scratch (every launch writes the slots it reads).  Every call on one GPU uses
+ * that GPU's one scratch array: calls that overlap on one GPU (several streams or host threads)
+ * race and must be serialised by the caller.  rows >= 0, w in 1..16 (SLAMG_E_INVALID otherwise;
+ * SLAMG_E_BUDGET if the reduction would need more scratch than the array holds), SLAMG_E_DEVICE
+ * on a HIP error at launch. */
+slamg_status slamg_op_gram_noalloc(int32_t rows, int32_t w, const double* d_x, const double* d_y, double* d_g,
+                                   void* stream);
+size_t slamg_op_gram_noalloc_scratch_bytes(void);
+
 /* Ritz projection on the finest level (§4.3): Cholesky-QR2 orthonormalisation of U (and V), the
  * projected w x w problem and the rotation of the bases.  spd = 1: X in d_u, eigenproblem.
  * minimal selects ascending order.  h_sig: w values (host). */

@@ -79,6 +79,8 @@ SIGNATURES = {
     "slamg_op_residual": (_I, [_I, _I, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "slamg_op_dots": (_I, [_I, _I, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "slamg_op_gram": (_I, [_I, _I, _P, _P, _P, _P]),
+    "slamg_op_gram_noalloc": (_I, [_I, _I, _P, _P, _P, _P]),
+    "slamg_op_gram_noalloc_scratch_bytes": (C.c_size_t, []),
     "slamg_op_ritz": (_I, [_I, _I, _I, _I, _I, _P, _P, _P, _P, _P, _P, _P]),
     "slamg_op_ls_fit": (_I, [_I, _P, _P, _P, _I, _P, _P, _I, _P, _P, _P, _P, _P]),
     "slamg_op_spgemm": (_I, [_I, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),

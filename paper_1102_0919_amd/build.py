@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libslamg.so")
-SOURCES = ["kernels.hip", "dense.hip", "graph.cpp", "solver.cpp", "capi.cpp", "ops.cpp"]
+SOURCES = ["kernels.hip", "dense.hip", "graph.cpp", "solver.cpp", "capi.cpp", "ops.cpp", "noalloc.hip"]
 ARCH = os.environ.get("SLAMG_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # packed FP32 instructions are kept out of the generated code
