@@ -11,6 +11,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <stdexcept>
 #include <string>
 #include <thread>
 
@@ -289,6 +290,10 @@ static slamg_status run_guarded(const Exec& x, std::string& err, Problem& pb, co
     return fail(err, (slamg_status)e.code, e.msg);
   } catch (const std::bad_alloc&) {
     return fail(err, SLAMG_E_OOM, "host allocation failed");
+  } catch (const std::length_error& e) {
+    return fail(err, SLAMG_E_OOM, std::string("host structure too large: ") + e.what());
+  } catch (const std::exception& e) {
+    return fail(err, SLAMG_E_DEVICE, std::string("unexpected host error: ") + e.what());
   }
   return SLAMG_OK;
 }

@@ -7,7 +7,9 @@
 #include "graph.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <exception>
 #include <queue>
 #include <stdexcept>
 #include <thread>
@@ -18,19 +20,32 @@ namespace slamg {
 // per chunk.  make_row() gives each chunk its own row builder (with its own scratch), and
 // row(i, out) appends row i's entries to the chunk's list.  The chunks are joined in row order, so
 // the result does not depend on the number of threads.
+// A pattern holds at most MAX_PATTERN_ENTRIES entries (int32 row pointers); a larger one (the
+// strength graph of a matrix with nearly dense A^t A, say) ends the build with std::length_error.
+static constexpr size_t MAX_PATTERN_ENTRIES = (size_t)2147483647;
+
 template <class M>
 static void build_rows(int n, std::vector<int>& rp, std::vector<int>& ci, M make_row) {
   const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   const int nt = n >= 8192 ? (int)hw : 1;
   std::vector<std::vector<int>> part(nt), len(nt);
+  std::atomic<size_t> built{0};
+  std::atomic<bool> too_large{false};
+  std::vector<std::exception_ptr> err(nt);
   auto work = [&](int t) {
-    const int r0 = (int)((long)n * t / nt), r1 = (int)((long)n * (t + 1) / nt);
-    auto row_fn = make_row();
-    len[t].resize(r1 - r0);
-    for (int i = r0; i < r1; ++i) {
-      const size_t before = part[t].size();
-      row_fn(i, part[t]);
-      len[t][i - r0] = (int)(part[t].size() - before);
+    try {
+      const int r0 = (int)((long)n * t / nt), r1 = (int)((long)n * (t + 1) / nt);
+      auto row_fn = make_row();
+      len[t].resize(r1 - r0);
+      for (int i = r0; i < r1 && !too_large.load(std::memory_order_relaxed); ++i) {
+        const size_t before = part[t].size();
+        row_fn(i, part[t]);
+        const size_t got = part[t].size() - before;
+        len[t][i - r0] = (int)got;
+        if (built.fetch_add(got, std::memory_order_relaxed) + got > MAX_PATTERN_ENTRIES) too_large = true;
+      }
+    } catch (...) {
+      err[t] = std::current_exception();
     }
   };
   if (nt == 1) {
@@ -40,6 +55,9 @@ static void build_rows(int n, std::vector<int>& rp, std::vector<int>& ci, M make
     for (int t = 0; t < nt; ++t) th.emplace_back(work, t);
     for (auto& x : th) x.join();
   }
+  for (auto& e : err)
+    if (e) std::rethrow_exception(e);
+  if (too_large) throw std::length_error("sparsity pattern with more than 2^31 - 1 entries");
   rp.assign(n + 1, 0);
   size_t total = 0;
   for (int t = 0; t < nt; ++t) total += part[t].size();

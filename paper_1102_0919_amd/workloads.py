@@ -13,8 +13,9 @@ it does not give are replaced by the synthetic stand-ins below):
 * ``gradient2d(k)``     – discrete gradient (edge-vertex incidence) of the k x k grid graph, a
                           rectangular matrix whose singular values are square roots of the Neumann
                           graph-Laplacian eigenvalues.
-* ``termdoc(m, n, ...)``– Zipf-distributed synthetic term-document matrix standing in for the
-                          MEDLINE matrix of §6.4, which is not available here.
+* ``termdoc(m, n, ...)``– Zipf-distributed synthetic term-document matrix (log(1 + count) values)
+                          standing in for the MEDLINE matrix of §6.4, which is not available here.
+* ``termdoc_topics(m, n, ...)`` – a topic-structured variant with raw counts.
 * ``aniso3d(k, eps)``   – 7-point anisotropic Dirichlet diffusion on a k^3 grid.
 """
 from __future__ import annotations
@@ -317,10 +318,18 @@ WORKLOADS = {
     "convdiff2d_31_min8": dict(desc="upwind convection-diffusion 31x31 (n=961, nonsymmetric), 8 minimal triplets, square coarsening",
                                kind="svd", target="minimal", n_b=8,
                                params=dict(theta=0.05, n_t=8, mu_t=4, mu_b=4, n_mult=10, square_coarsening=1)),
-    "termdoc_200k_dom10": dict(desc="Zipf term-document matrix 200000x50000, 60 nnz/column, 10 dominant triplets",
+    "termdoc_200k_dom10": dict(desc="Zipf(1.1) term-document matrix 200000x50000, 60 distinct terms per document, "
+                                    "values log(1+c) with c ~ Geometric(0.3), 10 dominant triplets",
                                kind="svd", target="dominant", n_b=10,
+                               # 6 guard pairs (R29): sigma_2 .. sigma_10 of this matrix form one tight
+                               # cluster, and the last pair of a 10-wide block stalls next to sigma_11
                                params=dict(strength_rule=2, top_s=4, df_filter=0.01, n_t=14, mu_t=1,
-                                           mu_b=4, n_mult=3, coarse_pinv=1)),
+                                           mu_b=4, n_mult=3, coarse_pinv=1, n_guard=6)),
+    "termdoc_topics_200k_dom10": dict(desc="topic-structured term-document matrix 200000x50000 (40 topics, raw "
+                                           "counts), 60 distinct terms per document, 10 dominant triplets",
+                                      kind="svd", target="dominant", n_b=10,
+                                      params=dict(strength_rule=2, top_s=4, df_filter=0.01, n_t=14, mu_t=1,
+                                                  mu_b=4, n_mult=3, coarse_pinv=1)),
     "aniso3d_128_min8": dict(desc="3-D anisotropic 7-point Dirichlet 128^3 (n=2097152, eps=0.01), 8 minimal eigenpairs",
                              kind="spd", target="minimal", n_b=8,
                              # a diagonally dominant PDE discretisation: the max-based strength rule
@@ -343,6 +352,9 @@ def build_workload_matrix(name: str, scale: int | None = None) -> CSR:
     if name.startswith("convdiff2d_31"):
         return convdiff2d(scale or 31)
     if name.startswith("termdoc_200k"):
+        n = scale or 50000
+        return termdoc(4 * n, n, 60, seed=1102)
+    if name.startswith("termdoc_topics_200k"):
         n = scale or 50000
         return termdoc_topics(4 * n, n, 60, seed=1102)
     if name.startswith("aniso3d_128"):

@@ -417,7 +417,7 @@ def test_termdoc_topics_reduced_vs_oracle(ctx):
     # max(256, 8 x the mean) nonzeros, so the row kernel's one-workgroup-per-long-row path, the
     # Ritz product and the residual blocks through it are all checked here
     from paper_1102_0919_amd import api
-    A, wl, r, o = _run_both(ctx, "termdoc_200k_dom10", scale=1000, max_add=200)
+    A, wl, r, o = _run_both(ctx, "termdoc_topics_200k_dom10", scale=1000, max_add=200)
     rep = api.report_dict(r.report)
     assert r.converged and o.report["converged"]
     sv = np.linalg.svd(A.toarray(), compute_uv=False)[:10]
