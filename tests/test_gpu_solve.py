@@ -331,35 +331,32 @@ def test_full_gradient256_dom8_to_tolerance(ctx):
     assert np.allclose([r.report.mult_sigma[0][j] for j in range(8)], s.sig, rtol=1e-9)
 
 
-def test_termdoc_one_sided_coarsening_vs_oracle(ctx):
-    # Zipf term-document matrix (1600 terms x 400 documents): the document side stops coarsening on
-    # level 1 and keeps all its points there (one-sided coarsening); hierarchy, the multiplicative
-    # phase and the first additive iterations follow the oracle, every Ritz value lies within its
-    # residual bound of the spectrum (ARPACK), and the leading five are exact after 20 iterations
+@pytest.mark.parametrize("n", [400, 1000])
+def test_termdoc_zipf_reduced_vs_oracle(ctx, n):
+    # the Zipf(1.1) term-document generator of configuration 3 at 4n x n with its parameters (top-s
+    # strength, 6 guard pairs): the document side stops coarsening on level 1 and keeps all its
+    # points there (one-sided coarsening, at n = 400); device and oracle build the same hierarchy,
+    # follow the same multiplicative phase and reach all ten dominant singular values of ARPACK
     import scipy.sparse.linalg as sla
     from paper_1102_0919_amd import api
     wl = W.WORKLOADS["termdoc_200k_dom10"]
-    A = W.termdoc(1600, 400, 60, seed=1102).to_scipy()   # the single-vocabulary Zipf generator
-    prm = dict(wl["params"], coarse_pinv=1, max_add=20)
+    A = W.termdoc(4 * n, n, 60, seed=1102).to_scipy()
+    prm = dict(wl["params"], max_add=200)
     r = api.solve(ctx, A, "svd", "dominant", 10, api.params_init("svd", "dominant", **prm))
     o = O.solve(A, "svd", "dominant", 10, O.Params(**prm))
-    assert r.report.levels == o.report["levels"] == 3
-    assert [(int(r.report.rows[l]), int(r.report.cols[l])) for l in range(3)] == list(o.report["sizes"])
-    assert int(r.report.cols[1]) == int(r.report.cols[2])          # documents kept whole on level 1
+    rep = api.report_dict(r.report)
+    assert r.converged and o.report["converged"]
+    assert rep["sizes"] == [tuple(s) for s in o.report["sizes"]]
+    if n == 400:
+        assert rep["levels"] == 3 and int(r.report.cols[1]) == int(r.report.cols[2])
     for c in range(3):
-        _sig_close([r.report.mult_sigma[c][j] for j in range(10)], o.report["mult_sigma"][c],
+        _sig_close([r.report.mult_sigma[c][j] for j in range(16)], o.report["mult_sigma"][c],
                    r.report.anorm, rel=1e-9)
-    # the additive phase of this matrix amplifies perturbations: the oracle's own residual history
-    # moves by 3e-7 when its initial vectors move by 1e-15 (the Jacobi-type relaxation for the
-    # smaller sigma_j grows the sigma_1 component ~50-fold per sweep), so the device, whose
-    # multiplicative phase agrees to 1e-9, is held to 1e-3 here
-    np.testing.assert_allclose([r.report.rho_history[k] for k in range(21)],
-                               [np.max(x) for x in o.report["rho"][:21]], rtol=1e-3)
-    s = sla.svds(A, k=14, tol=1e-13, return_singular_vectors=False)[::-1]
-    res = np.array([r.report.resid[j] for j in range(10)])
-    for j in range(10):
-        assert np.min(np.abs(s - r.sigma[j])) <= res[j] * r.report.anorm * 1.01 + 1e-12
-    _sig_close(r.sigma[:5], s[:5], r.report.anorm, rel=1e-10)
+    assert abs(rep["add_iters"] - o.report["add_iters"]) <= 2
+    s = sla.svds(A, k=12, tol=1e-13, return_singular_vectors=False)[::-1]
+    _sig_close(r.sigma, s[:10], r.report.anorm)
+    _sig_close(r.sigma, o.sigma, r.report.anorm)
+    _check_triplets(A, r, "svd", 1e-8, r.report.anorm)
 
 
 # ------------------------------------------------------------------------------------------------
