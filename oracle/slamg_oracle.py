@@ -862,6 +862,10 @@ class Solver:
     def additive_vcycle(self):
         kind, target, p, sig = self.kind, self.target, self.p, self.sig
         L = len(self.levels) - 1
+        if L == 0:
+            # one level: the multiplicative phase's coarsest generalized SVD is already exact and
+            # there is no coarse correction to add
+            return
         us, vs = [self.Ub], [self.Vb]
         kaps = [np.zeros_like(self.Ub)]
         taus = [None if kind == SPD else np.zeros_like(self.Vb)]

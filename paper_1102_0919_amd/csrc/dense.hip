@@ -239,16 +239,23 @@ __device__ static __forceinline__ void wg_jacobi(double* A, int n, int ld, doubl
   wg_sync();
 }
 
+// Ranking key: a NaN ranks after every other value (NaN compares false with everything, so ranking
+// it directly would give several entries one rank and leave output positions unwritten).
+__device__ __forceinline__ double rank_key(double x, bool desc) {
+  return x == x ? x : (desc ? -INFINITY : INFINITY);
+}
+
 // indices of the k extremal values of lam[0..n) (largest first if desc, else smallest first); ties
-// to the lower index.  Each thread ranks its own entries (the rank is the output position).
+// to the lower index.  Each thread ranks its own entries (the rank is the output position); every
+// entry gets a distinct rank in [0, n), so out[0..k) is always filled with indices below n.
 template <int BS = DBLK>
 __device__ static void select_extremal(const double* lam, int n, int k, bool desc, int* out) {
   wg_sync();
   for (int i = threadIdx.x; i < n; i += BS) {
-    const double li = lam[i];
+    const double li = rank_key(lam[i], desc);
     int rank = 0;
     for (int j = 0; j < n; ++j) {
-      const double lj = lam[j];
+      const double lj = rank_key(lam[j], desc);
       rank += (desc ? lj > li : lj < li) || (lj == li && j < i);
     }
     if (rank < k) out[rank] = i;
@@ -514,7 +521,10 @@ __global__ __launch_bounds__(GB) void k_coarse_gsvd(int spd, int minimal, int mL
       }
     }
     jacobi_lds<LDSJ>(D, n, W);
-    for (int i = threadIdx.x; i < n; i += GB) lam[i] = D[(long)i * n + i];
+    for (int i = threadIdx.x; i < n; i += GB) {
+      lam[i] = D[(long)i * n + i];
+      if (!isfinite(lam[i])) info = 1;
+    }
     wg_sync();
     select_extremal<GB>(lam, n, nb, !minimal, ord);
     for (long t = threadIdx.x; t < (long)n * nb; t += GB) {
@@ -554,7 +564,10 @@ __global__ __launch_bounds__(GB) void k_coarse_gsvd(int spd, int minimal, int mL
     }
   }
   jacobi_lds<LDSJ>(G, n, W);
-  for (int i = threadIdx.x; i < n; i += GB) lam[i] = sqrt(fmax(G[(long)i * n + i], 0.0));
+  for (int i = threadIdx.x; i < n; i += GB) {
+    lam[i] = sqrt(fmax(G[(long)i * n + i], 0.0));
+    if (!isfinite(G[(long)i * n + i])) info = 1;
+  }
   wg_sync();
   select_extremal<GB>(lam, n, nb, !minimal, ord);
   double smax = 0.0;

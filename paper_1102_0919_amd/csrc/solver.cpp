@@ -527,9 +527,12 @@ void Solver::alloc_level_buffers(Level& L) {
   const int mu = rows_u(L), mv = rows_v(L);
   const int wmax = std::max(nt_, nb_);
   auto& b = L.bd;
+  // The test blocks hold n_t columns but get the scratch blocks' capacity (max(n_t, n_b) columns):
+  // the test relaxation swaps Ut / tU and Vt / tV, and the scratch blocks are later written with n_b
+  // columns (Cholesky-QR, residual blocks)
   if (!spd_) {
-    b.Ut = ar_.alloc<double>((size_t)mu * nt_);
-    b.Vt = ar_.alloc<double>((size_t)mv * nt_);
+    b.Ut = ar_.alloc<double>((size_t)mu * wmax);
+    b.Vt = ar_.alloc<double>((size_t)mv * wmax);
     double* UV = ar_.alloc<double>((size_t)(mu + mv) * nb_);
     b.Ub = UV; b.Vb = UV + (size_t)mu * nb_;
     double* UV2 = ar_.alloc<double>((size_t)(mu + mv) * nb_);
@@ -541,7 +544,7 @@ void Solver::alloc_level_buffers(Level& L) {
     b.tU2 = ar_.alloc<double>((size_t)mu * wmax);
     b.tV2 = ar_.alloc<double>((size_t)mv * wmax);
   } else {
-    b.Ut = ar_.alloc<double>((size_t)mu * nt_);
+    b.Ut = ar_.alloc<double>((size_t)mu * wmax);
     b.Ub = ar_.alloc<double>((size_t)mu * nb_);
     b.Ua = ar_.alloc<double>((size_t)mu * nb_);
     b.kap = ar_.alloc<double>((size_t)mu * nb_);
@@ -1536,6 +1539,9 @@ void Solver::mult_cycle(int c) {
 template <class T>
 void Solver::additive_vcycle(const double* sig, T* rhsU, T* rhsV) {
   const int nl = (int)lv_.size();
+  // a single level is solved exactly by the coarsest generalized SVD of the multiplicative phase;
+  // there is no coarse correction to add
+  if (nl < 2) return;
   const bool zero_start_ok = !minimal_ && p_.mu_b > 0;
   for (int l = 0; l + 1 < nl; ++l) {
     Level& L = *lv_[l];
@@ -1850,10 +1856,15 @@ void Solver::run(const double* init_tests, SolveOutput& out) {
   for (int c = 1; c <= p_.n_mult; ++c) {
     mult_cycle(c);
     rep_.mult_cycles = c;
-    if (c <= 32) {
-      d2h(hs, sig_, nb_, st_);
+    d2h(hs, sig_, nb_, st_);
+    if (c <= 32)
       for (int j = 0; j < nb_; ++j) rep_.mult_sigma[c - 1][j] = hs[j];
-    }
+    // a breakdown ends the solve here, before non-finite values reach the next cycle
+    for (int j = 0; j < nb_; ++j)
+      if (!std::isfinite(hs[j]))
+        throw SolverError{ST_E_NUMERIC, "non-finite singular value estimate after multiplicative cycle " +
+                                            std::to_string(c)};
+    check_status();
     if (p_.verbose > 0) {
       std::fprintf(stderr, "[slamg] multiplicative cycle %d: %zu levels, %.1f ms\n", c, lv_.size(),
                    std::chrono::duration<double, std::milli>(clk::now() - t0).count());

@@ -322,9 +322,21 @@ WORKLOADS = {
                                     "values log(1+c) with c ~ Geometric(0.3), 10 dominant triplets",
                                kind="svd", target="dominant", n_b=10,
                                # 6 guard pairs (R29): sigma_2 .. sigma_10 of this matrix form one tight
-                               # cluster, and the last pair of a 10-wide block stalls next to sigma_11
+                               # cluster, and the last pair of a 10-wide block stalls next to sigma_11.
+                               # mu_b = 1: sigma_1 is ~7 sigma_2, and the Jacobi-type boot relaxation of
+                               # pair j (§3.5) multiplies the sigma_1 component by about
+                               # ((1 - omega) + omega sigma_1 / sigma_j)^2 ~ 26 per sweep, which with
+                               # mu_b = 4 makes a V-cycle's correction 1e12..1e20 times its residual
                                params=dict(strength_rule=2, top_s=4, df_filter=0.01, n_t=14, mu_t=1,
-                                           mu_b=4, n_mult=3, coarse_pinv=1, n_guard=6)),
+                                           mu_b=1, n_mult=3, coarse_pinv=1, n_guard=6)),
+    # §6.4's parameter set (n_t 14, mu_t 1, mu_b 4, 3 multiplicative cycles, 8 dominant triplets) at
+    # the MEDLINE submatrix's size: 5735 terms x 1033 documents, 50 distinct Zipf(1.1) terms per
+    # document (0.87% dense), log(1+c) values; top-s strength as for configuration 3
+    "termdoc_medline_dom8": dict(desc="Zipf(1.1) term-document matrix 5735x1033 (MEDLINE's shape), 50 terms per "
+                                      "document, 8 dominant triplets, the parameters of §6.4",
+                                 kind="svd", target="dominant", n_b=8,
+                                 params=dict(strength_rule=2, top_s=4, df_filter=0.01, n_t=14, mu_t=1, mu_b=4,
+                                             n_mult=3, coarse_pinv=1, max_add=300)),
     "termdoc_topics_200k_dom10": dict(desc="topic-structured term-document matrix 200000x50000 (40 topics, raw "
                                            "counts), 60 distinct terms per document, 10 dominant triplets",
                                       kind="svd", target="dominant", n_b=10,
@@ -354,6 +366,8 @@ def build_workload_matrix(name: str, scale: int | None = None) -> CSR:
     if name.startswith("termdoc_200k"):
         n = scale or 50000
         return termdoc(4 * n, n, 60, seed=1102)
+    if name.startswith("termdoc_medline"):
+        return termdoc(5735, 1033, 50, seed=1102)
     if name.startswith("termdoc_topics_200k"):
         n = scale or 50000
         return termdoc_topics(4 * n, n, 60, seed=1102)

@@ -168,20 +168,28 @@ def test_init_tests_and_rectangular_transpose(ctx):
     assert np.allclose(A @ r.V, r.U * r.sigma, atol=1e-7)
 
 
-@pytest.mark.parametrize("name,precision", [("laplace2d_31_min4", "mixed_fp32"), ("laplace2d_31_min4", "mixed_bf16"),
-                                            ("laplace2d_32_dom8", "mixed_fp32"), ("laplace2d_32_dom8", "mixed_bf16")])
-def test_mixed_precision_matches_fp64(ctx, name, precision):
-    # Kaczmarz (minimal) and the Jacobi-type row kernel on B's shared pattern (dominant), with FP32
-    # or BF16 operator values inside the FP64 refinement
+MIXED_CASES = [("laplace2d_31_min4", None), ("laplace2d_32_dom8", None), ("aniso3d_128_min8", 16),
+               ("gradient2d_256_dom8", 32), ("termdoc_200k_dom10", 1000), ("convdiff2d_31_min8", None)]
+
+
+@pytest.mark.parametrize("name,scale", MIXED_CASES)
+@pytest.mark.parametrize("precision", ["mixed_fp32", "mixed_bf16"])
+def test_mixed_precision_vs_fp64_oracle(ctx, name, scale, precision):
+    # the refinement form (FP32 V-cycle with FP32 or BF16 operator values inside the FP64 residual,
+    # Ritz step and norms) against the FP64 oracle: every singular value / eigenvalue within
+    # 1e-10 max(sigma, 1e-8 ||A||) of the oracle's, residuals below the tolerance.  Kaczmarz
+    # (minimal), the Jacobi-type row kernel on B's shared pattern and on separate B / C patterns
+    # (dominant), long term-document rows, square coarsening.
     from paper_1102_0919_amd import api
     wl = W.WORKLOADS[name]
     kind, target, nb = wl["kind"], wl["target"], wl["n_b"]
-    A = W.build_workload_matrix(name).to_scipy()
-    r64 = api.solve(ctx, A, kind, target, nb, api.params_init(kind, target, **wl["params"]))
-    r32 = api.solve(ctx, A, kind, target, nb, api.params_init(kind, target, precision=precision, **wl["params"]))
-    assert r32.converged
-    _sig_close(r32.sigma, r64.sigma, r64.report.anorm)
-    _check_triplets(A, r32, kind, 1e-8, r64.report.anorm)
+    A = W.build_workload_matrix(name, scale).to_scipy()
+    prm = dict(wl["params"], max_add=800)
+    r = api.solve(ctx, A, kind, target, nb, api.params_init(kind, target, precision=precision, **prm))
+    o = O.solve(A, kind, target, nb, O.Params(**prm))
+    assert r.converged and o.report["converged"]
+    _sig_close(r.sigma, o.sigma, r.report.anorm)
+    _check_triplets(A, r, kind, 1e-8, r.report.anorm)
 
 
 def test_bf16_operator_values_rectangular_svd(ctx):
@@ -497,3 +505,37 @@ def test_guard_pairs_outputs_vs_oracle(ctx):
     assert abs(r.report.add_iters - o.report["add_iters"]) <= 2
     for j in (0, 3):   # simple eigenvalues: the same vectors (the output sign rule fixes the sign)
         assert np.allclose(r.U[:, j], o.U[:, j], atol=1e-7)
+
+
+def test_termdoc_medline_shape_paper_parameters_vs_oracle(ctx):
+    # §6.4's parameter set at the MEDLINE submatrix's size (5735 x 1033, stand-in generator): same
+    # hierarchy and multiplicative phase as the oracle, the eight dominant singular values of ARPACK
+    import scipy.sparse.linalg as sla
+    from paper_1102_0919_amd import api
+    A, wl, r, o = _run_both(ctx, "termdoc_medline_dom8")
+    rep = api.report_dict(r.report)
+    assert r.converged and o.report["converged"]
+    assert rep["sizes"] == [tuple(s) for s in o.report["sizes"]]
+    for c in range(3):
+        _sig_close([r.report.mult_sigma[c][j] for j in range(8)], o.report["mult_sigma"][c], r.report.anorm,
+                   rel=1e-9)
+    assert abs(rep["add_iters"] - o.report["add_iters"]) <= 3
+    s = sla.svds(A, k=10, tol=1e-13, return_singular_vectors=False)[::-1]
+    _sig_close(r.sigma, s[:8], r.report.anorm)
+    _sig_close(r.sigma, o.sigma, r.report.anorm)
+    _check_triplets(A, r, "svd", 1e-8, r.report.anorm)
+
+
+def test_gradient_minimal_follows_oracle_not_converging(ctx):
+    # minimal singular triplets of the rectangular discrete gradient (configuration 2's minimal half)
+    # at 16 x 16: sigma_1 = 0 with a 225-dimensional null space of A^t.  The method as stated does
+    # not converge here, in the oracle as on the device (documented as an open problem); the device
+    # follows the oracle's hierarchy and multiplicative phase, and both find the zero singular value
+    from paper_1102_0919_amd import api
+    A, wl, r, o = _run_both(ctx, "gradient2d_256_min8", scale=16, max_add=30)
+    rep = api.report_dict(r.report)
+    assert rep["sizes"] == [tuple(s) for s in o.report["sizes"]]
+    assert np.allclose([r.report.mult_sigma[0][j] for j in range(8)], o.report["mult_sigma"][0],
+                       rtol=1e-8, atol=1e-12 * r.report.anorm)
+    assert not r.converged and not o.report["converged"]
+    assert r.sigma[0] <= 1e-8 * r.report.anorm and o.sigma[0] <= 1e-8 * r.report.anorm

@@ -436,7 +436,7 @@ def test_one_sided_coarsening_identity_side_and_spectrum():
     import scipy.sparse.linalg as spla
     A = W.termdoc(1600, 400, 60, seed=1102).to_scipy()   # the single-vocabulary Zipf generator
     wl = W.WORKLOADS["termdoc_200k_dom10"]
-    prm = dict(wl["params"], coarse_pinv=1, max_add=20)
+    prm = dict(wl["params"], coarse_pinv=1, max_add=200)
     s = O.Solver(A[np.diff(A.indptr) > 0], "svd", "dominant", 10, O.Params(**prm))
     sig, _, _ = s.run()
     lv1, lv2 = s.levels[1], s.levels[2]
@@ -669,3 +669,35 @@ def test_guard_pairs_and_lexicographic_kaczmarz_end_to_end():
     # the lexicographic order is a different iteration (not the multicolour one)
     r0 = _run(L, O.SPD, O.MINIMAL, 3, coarse_max=30, n_t=6, mu_t=4, mu_b=4, n_mult=6, tol=1e-11)
     assert not np.allclose(r2.report["mult_sigma"][0], r0.report["mult_sigma"][0], rtol=1e-12)
+
+
+def test_aniso3d_minimal_end_to_end_closed_form():
+    # the 3-D anisotropic family with configuration 4's parameters (max-based strength, 8 guard
+    # pairs) on a 16^3 grid: the eight smallest eigenvalues of the closed form
+    # 4 sin^2(i pi/34) + 4 sin^2(j pi/34) + 0.04 sin^2(k pi/34), residuals below the tolerance,
+    # orthonormal eigenvectors
+    wl = W.WORKLOADS["aniso3d_128_min8"]
+    k = 16
+    A = W.aniso3d(k, 0.01).to_scipy()
+    r = O.solve(A, "spd", "minimal", 8, O.Params(**dict(wl["params"], max_add=100)))
+    ref = W.aniso3d_eigs_smallest(k, 0.01, 8)
+    assert r.report["converged"]
+    assert np.all(np.abs(r.sigma - ref) <= 1e-10 * ref)
+    res = np.linalg.norm(A @ r.U - r.U * r.sigma, axis=0) / r.report["anorm"]
+    assert np.all(res <= 1e-8)
+    assert np.allclose(r.U.T @ r.U, np.eye(8), atol=1e-9)
+    assert r.report["levels"] >= 4
+
+
+@pytest.mark.slow
+def test_termdoc_medline_shape_against_arpack():
+    # §6.4's parameters at MEDLINE's size on the stand-in generator: the eight dominant singular
+    # values of ARPACK (a library routine independent of the oracle) to 1e-10
+    import scipy.sparse.linalg as spla
+    wl = W.WORKLOADS["termdoc_medline_dom8"]
+    A = W.build_workload_matrix("termdoc_medline_dom8").to_scipy()
+    r = O.solve(A, "svd", "dominant", 8, O.Params(**wl["params"]))
+    assert r.report["converged"]
+    ref = spla.svds(A, k=10, tol=1e-13, return_singular_vectors=False)[::-1][:8]
+    assert np.all(np.abs(r.sigma - ref) <= 1e-10 * ref)
+    assert np.allclose(A @ r.V, r.U * r.sigma, atol=1e-8 * r.report["anorm"])
