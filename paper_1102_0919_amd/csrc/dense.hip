@@ -536,82 +536,144 @@ __global__ __launch_bounds__(GB) void k_coarse_gsvd(int spd, int minimal, int mL
     if (threadIdx.x == 0 && info) *status = ST_E_NUMERIC;
     return;
   }
+  // D = L_B^-1 A L_C^-t has l = min(m, n) singular values (§3.1, Theorem 3.2).  X is D or D^t,
+  // whichever is tall (L x l, L = max(m, n)); the eigen-decomposition of X^t X gives the short-side
+  // vectors w, and the long-side vectors are X w / ||X w||.  A (numerically) zero sigma
+  // takes a unit long-side vector in the null space of X^t instead, orthogonal to the other ones.
   const int m = mL, n = nL;
-  const int mx = m > n ? m : n;
+  const bool tall = m >= n;
+  const int l = tall ? n : m, Lr = tall ? m : n;
   double* Dt = work;                       // n x m   (D^t)
-  double* G = work + (long)m * n;          // n x n
-  double* W = G + (long)n * n;             // n x n
-  double* Tm = W + (long)n * n;            // m x nb  (t vectors)
-  double* lam = Tm + (long)m * 64;         // n
-  (void)mx;
+  double* G = Dt + (long)m * n;            // l x l
+  double* W = G + (long)l * l;             // l x l
+  double* Y = W + (long)l * l;             // Lr x l  (long-side vectors of every non-zero sigma)
+  double* Tm = Y + (long)Lr * l;           // Lr x nb (long-side vectors of the selected triplets)
+  double* lam = Tm + (long)Lr * 64;        // l
+  double* score = lam + l;                 // Lr
+  // X(r, c), r < Lr, c < l
+  auto X = [&](int r, int c) -> double { return tall ? Dt[(long)c * m + r] : Dt[(long)r * m + c]; };
   wg_chol<GB>(B, m, m, &info);
   wg_chol<GB>(C, n, n, &info);
   wg_trsm_lower<GB>(B, m, m, A, n, n);             // A <- L_B^-1 A   (m x n)
   wg_transpose<GB>(A, m, n, n, Dt, m);             // Dt = (L_B^-1 A)^t   (n x m)
   wg_trsm_lower<GB>(C, n, n, Dt, m, m);            // Dt = L_C^-1 A^t L_B^-t = D^t
-  for (long t = threadIdx.x; t < (long)n * n; t += GB) {
-    int i = (int)(t / n), j = (int)(t % n);
+  for (long t = threadIdx.x; t < (long)l * l; t += GB) {
+    int i = (int)(t / l), j = (int)(t % l);
     double s = 0.0;
-    for (int k = 0; k < m; ++k) s += Dt[(long)i * m + k] * Dt[(long)j * m + k];
+    for (int r = 0; r < Lr; ++r) s += X(r, i) * X(r, j);
     G[t] = s;
   }
   wg_sync();
-  for (long t = threadIdx.x; t < (long)n * n; t += GB) {
-    int i = (int)(t / n), j = (int)(t % n);
+  for (long t = threadIdx.x; t < (long)l * l; t += GB) {
+    int i = (int)(t / l), j = (int)(t % l);
     if (j > i) {
-      double s = 0.5 * (G[(long)i * n + j] + G[(long)j * n + i]);
-      G[(long)i * n + j] = s; G[(long)j * n + i] = s;
+      double s = 0.5 * (G[(long)i * l + j] + G[(long)j * l + i]);
+      G[(long)i * l + j] = s; G[(long)j * l + i] = s;
     }
   }
-  jacobi_lds<LDSJ>(G, n, W);
-  for (int i = threadIdx.x; i < n; i += GB) {
-    lam[i] = sqrt(fmax(G[(long)i * n + i], 0.0));
-    if (!isfinite(G[(long)i * n + i])) info = 1;
+  jacobi_lds<LDSJ>(G, l, W);
+  for (int i = threadIdx.x; i < l; i += GB) {
+    lam[i] = sqrt(fmax(G[(long)i * l + i], 0.0));
+    if (!isfinite(G[(long)i * l + i])) info = 1;
   }
   wg_sync();
-  select_extremal<GB>(lam, n, nb, !minimal, ord);
+  select_extremal<GB>(lam, l, nb, !minimal, ord);
   double smax = 0.0;
-  for (int i = 0; i < n; ++i) smax = fmax(smax, lam[i]);
-  // t_k = D w_k / s_k  (D = Dt^t)
-  for (long t = threadIdx.x; t < (long)m * nb; t += GB) {
+  for (int i = 0; i < l; ++i) smax = fmax(smax, lam[i]);
+  const double thr = 1e-12 * smax;
+  // sigma_k = ||X w_k||: accurate to about eps sigma_max, where the square root of X^t X's
+  // eigenvalue is only accurate to about sqrt(eps) sigma_max
+  __shared__ double nu[64];
+  for (long t = threadIdx.x; t < (long)Lr * nb; t += GB) {
     int r = (int)(t / nb), k = (int)(t % nb);
     double s = 0.0;
-    for (int j = 0; j < n; ++j) s += Dt[(long)j * m + r] * W[(long)j * n + ord[k]];
-    double sk = lam[ord[k]];
-    Tm[t] = sk > 1e-12 * smax ? s / sk : 0.0;
+    for (int c = 0; c < l; ++c) s += X(r, c) * W[(long)c * l + ord[k]];
+    Tm[t] = s;
   }
   wg_sync();
-  if (threadIdx.x == 0) {
-    // complete t for (numerically) zero singular values, orthonormal to the others
+  for (int k = threadIdx.x; k < nb; k += GB) {
+    double s = 0.0;
+    for (int r = 0; r < Lr; ++r) s += Tm[(long)r * nb + k] * Tm[(long)r * nb + k];
+    nu[k] = sqrt(s);
+  }
+  wg_sync();
+  bool any_zero = false;
+  for (int k = 0; k < nb; ++k) any_zero = any_zero || !(nu[k] > thr);
+  for (long t = threadIdx.x; t < (long)Lr * nb; t += GB) {
+    const int k = (int)(t % nb);
+    Tm[t] = nu[k] > thr ? Tm[t] / nu[k] : 0.0;
+  }
+  if (any_zero) {
+    // the range of X: unit vectors X w_i / sigma_i of every non-zero sigma_i
+    for (long t = threadIdx.x; t < (long)Lr * l; t += GB) {
+      int r = (int)(t / l), i = (int)(t % l);
+      double s = 0.0;
+      for (int c = 0; c < l; ++c) s += X(r, c) * W[(long)c * l + i];
+      Y[t] = s;
+    }
+    wg_sync();
+    for (int i = threadIdx.x; i < l; i += GB) {
+      double s = 0.0;
+      for (int r = 0; r < Lr; ++r) s += Y[(long)r * l + i] * Y[(long)r * l + i];
+      lam[i] = sqrt(s);    // lam is not read again: the selected sigma_k are in nu
+    }
+    wg_sync();
+    for (long t = threadIdx.x; t < (long)Lr * l; t += GB) {
+      const int i = (int)(t % l);
+      Y[t] = lam[i] > thr ? Y[t] / lam[i] : 0.0;
+    }
+    wg_sync();
+    // each zero sigma: the projection of e_e onto null(X^t), minus the vectors already completed,
+    // for the e with the largest remainder ||P e_e||^2 = 1 - sum_i Y[e][i]^2 - sum_q T[e][q]^2
+    __shared__ int ebest;
+    __shared__ double nbest;
     for (int k = 0; k < nb; ++k) {
-      if (lam[ord[k]] > 1e-12 * smax) continue;
-      for (int e = 0; e < m; ++e) {
-        for (int r = 0; r < m; ++r) Tm[(long)r * nb + k] = r == e ? 1.0 : 0.0;
-        for (int k2 = 0; k2 < nb; ++k2) {
-          if (k2 == k) continue;
-          if (lam[ord[k2]] <= 1e-12 * smax && k2 > k) continue;
-          double d = Tm[(long)e * nb + k2];
-          for (int r = 0; r < m; ++r) Tm[(long)r * nb + k] -= d * Tm[(long)r * nb + k2];
-        }
-        double nrm = 0.0;
-        for (int r = 0; r < m; ++r) nrm += Tm[(long)r * nb + k] * Tm[(long)r * nb + k];
-        if (nrm > 0.25) {
-          nrm = sqrt(nrm);
-          for (int r = 0; r < m; ++r) Tm[(long)r * nb + k] /= nrm;
-          break;
-        }
+      if (nu[k] > thr) continue;
+      for (int e = threadIdx.x; e < Lr; e += GB) {
+        double s = 1.0;
+        for (int i = 0; i < l; ++i) s -= Y[(long)e * l + i] * Y[(long)e * l + i];
+        for (int q = 0; q < k; ++q)
+          if (!(nu[q] > thr)) s -= Tm[(long)e * nb + q] * Tm[(long)e * nb + q];
+        score[e] = s;
       }
+      wg_sync();
+      if (threadIdx.x == 0) {
+        int eb = 0;
+        for (int e = 1; e < Lr; ++e)
+          if (score[e] > score[eb]) eb = e;
+        ebest = eb;
+      }
+      wg_sync();
+      const int e = ebest;
+      for (int r = threadIdx.x; r < Lr; r += GB) {
+        double s = r == e ? 1.0 : 0.0;
+        for (int i = 0; i < l; ++i) s -= Y[(long)r * l + i] * Y[(long)e * l + i];
+        for (int q = 0; q < k; ++q)
+          if (!(nu[q] > thr)) s -= Tm[(long)r * nb + q] * Tm[(long)e * nb + q];
+        score[r] = s;
+      }
+      wg_sync();
+      if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int r = 0; r < Lr; ++r) s += score[r] * score[r];
+        nbest = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+      }
+      wg_sync();
+      for (int r = threadIdx.x; r < Lr; r += GB) Tm[(long)r * nb + k] = score[r] * nbest;
+      wg_sync();
     }
   }
   wg_sync();
-  for (long t = threadIdx.x; t < (long)m * nb; t += GB) U[t] = Tm[t];
-  for (long t = threadIdx.x; t < (long)n * nb; t += GB) {
+  double* Ul = tall ? U : V;    // long side
+  double* Us = tall ? V : U;    // short side
+  for (long t = threadIdx.x; t < (long)Lr * nb; t += GB) Ul[t] = Tm[t];
+  for (long t = threadIdx.x; t < (long)l * nb; t += GB) {
     int i = (int)(t / nb), k = (int)(t % nb);
-    V[t] = W[(long)i * n + ord[k]];
+    Us[t] = W[(long)i * l + ord[k]];
   }
   wg_trsm_lower_t<GB>(B, m, m, U, nb, nb);
   wg_trsm_lower_t<GB>(C, n, n, V, nb, nb);
-  for (int k = threadIdx.x; k < nb; k += GB) sig[k] = lam[ord[k]];
+  for (int k = threadIdx.x; k < nb; k += GB) sig[k] = nu[k];
   if (threadIdx.x == 0 && info) *status = ST_E_NUMERIC;
 }
 void launch_coarse_gsvd(int spd, int minimal, int mL, int nL, int nb, double* A, double* B, double* C, double* work,

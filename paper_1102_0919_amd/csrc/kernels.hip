@@ -1150,7 +1150,10 @@ void launch_perm_gather(int n, const int* perm, const double* in, double* out, h
 
 // ------------------------------------------------------------------------------------------------
 // Numeric SpGEMM on a known pattern: entry (i, j) of L R is the merge of row i of L with row j of
-// R^t (both sorted), summed in increasing inner index.  One thread per output entry.
+// R^t (both sorted), summed in increasing inner index.  One thread per output entry.  Each product is
+// rounded before it is added (no fused multiply-add): the strength sets of §3.7 compare these
+// values, ties included, and this is the textbook order of a sparse product, so the same matrix
+// gives bitwise the same strength operator and the same C/F split wherever it is formed.
 // ------------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(BLK) void k_spgemm_dot(int nnz, const int* __restrict__ rowC,
                                                     const int* __restrict__ colC, const int* __restrict__ rpL,
@@ -1165,7 +1168,9 @@ __global__ __launch_bounds__(BLK) void k_spgemm_dot(int nnz, const int* __restri
   while (a < ae && b < be) {
     int ca = ciL[a], cb = ciR[b];
     if (ca == cb) {
-      s += vL[a] * vR[b];
+#pragma clang fp contract(off)
+      const double prod = vL[a] * vR[b];
+      s = s + prod;
       ++a; ++b;
     } else if (ca < cb) {
       ++a;

@@ -354,18 +354,20 @@ def test_galerkin_spgemm_parity(L):
     assert np.allclose(ac, Ac.data, rtol=1e-12, atol=1e-13)
 
 
-@pytest.mark.parametrize("kind,target", [("svd", "dominant"), ("svd", "minimal"), ("spd", "minimal"),
-                                         ("spd", "dominant")])
-def test_coarse_gsvd_parity(L, kind, target):
+@pytest.mark.parametrize("kind,target,m,n", [("svd", "dominant", 70, 40), ("svd", "minimal", 70, 40),
+                                             ("svd", "dominant", 40, 70), ("svd", "minimal", 40, 70),
+                                             ("svd", "minimal", 33, 32), ("spd", "minimal", 90, 90),
+                                             ("spd", "dominant", 90, 90)])
+def test_coarse_gsvd_parity(L, kind, target, m, n):
+    # m < n: min(m, n) generalized singular values (Theorem 3.2); the n - m directions of the null
+    # space of A are not triplets and a minimal solve must not return them
     rng = np.random.default_rng(4)
     if kind == "svd":
-        m, n = 70, 40
         Ad = rng.uniform(-1, 1, (m, n))
         Bh = rng.uniform(-1, 1, (m, m)); Bd = Bh @ Bh.T / m + np.eye(m)
         Ch = rng.uniform(-1, 1, (n, n)); Cd = Ch @ Ch.T / n + np.eye(n)
         lev = O.Level(sp.csr_matrix(Ad), sp.csr_matrix(Bd), sp.csr_matrix(Cd))
     else:
-        m = n = 90
         Ah = rng.uniform(-1, 1, (m, m)); Ad = Ah @ Ah.T / m + 0.1 * np.eye(m)
         Bh = rng.uniform(-1, 1, (m, m)); Bd = Bh @ Bh.T / m + np.eye(m)
         Cd = None
@@ -385,6 +387,38 @@ def test_coarse_gsvd_parity(L, kind, target):
         assert np.allclose(hu[:, j] * s, Uo[:, j], atol=1e-7)
         if kind == "svd":
             assert np.allclose(hv[:, j] * s, Vo[:, j], atol=1e-7)
+
+
+@pytest.mark.parametrize("m,n", [(50, 30), (30, 50), (31, 31)])
+def test_coarse_gsvd_zero_singular_value(L, m, n):
+    # a rank-deficient A (one row and one column are combinations of the others) has a genuine zero
+    # generalized singular value; its triplet is not unique, so the test checks that the returned
+    # one satisfies A v = 0, A^t u = 0 and the B / C orthonormality, and that the others match the
+    # oracle's
+    rng = np.random.default_rng(9)
+    Ad = rng.uniform(-1, 1, (m, n))
+    Ad[:, -1] = Ad[:, :-1] @ rng.uniform(-1, 1, n - 1) / n
+    Ad[-1, :] = rng.uniform(-1, 1, m - 1) @ Ad[:-1, :] / m
+    Bh = rng.uniform(-1, 1, (m, m)); Bd = Bh @ Bh.T / m + np.eye(m)
+    Ch = rng.uniform(-1, 1, (n, n)); Cd = Ch @ Ch.T / n + np.eye(n)
+    lev = O.Level(sp.csr_matrix(Ad), sp.csr_matrix(Bd), sp.csr_matrix(Cd))
+    nb = 4
+    so, Uo, Vo = O.coarsest_gsvd(lev, "svd", "minimal", nb)
+    assert so[0] < 1e-12 and so[1] > 1e-3          # the zero is simple among the min(m, n) values
+    hs, hu, hv = np.zeros(nb), np.zeros((m, nb)), np.zeros((n, nb))
+    assert L.slamg_op_coarse_gsvd(0, 1, m, n, nb, hp(np.ascontiguousarray(Ad)), hp(np.ascontiguousarray(Bd)),
+                                  hp(np.ascontiguousarray(Cd)), hp(hs), hp(hu), hp(hv)) == 0
+    smax = np.linalg.svd(Ad, compute_uv=False)[0] * 10
+    assert hs[0] <= 1e-7 * smax
+    assert np.linalg.norm(Ad @ hv[:, 0]) <= 1e-10 * smax
+    assert np.linalg.norm(Ad.T @ hu[:, 0]) <= 1e-10 * smax
+    assert np.allclose(hu.T @ Bd @ hu, np.eye(nb), atol=1e-9)
+    assert np.allclose(hv.T @ Cd @ hv, np.eye(nb), atol=1e-9)
+    assert np.allclose(hs[1:], so[1:], rtol=1e-9)
+    for j in range(1, nb):
+        s = np.sign(hu[:, j] @ Bd @ Uo[:, j])
+        assert np.allclose(hu[:, j] * s, Uo[:, j], atol=1e-7)
+        assert np.allclose(hv[:, j] * s, Vo[:, j], atol=1e-7)
 
 
 @pytest.mark.parametrize("variant,m,n", [(0, 30, 20), (1, 30, 20), (2, 30, 20), (3, 30, 20), (4, 30, 20), (5, 30, 20),

@@ -516,9 +516,12 @@ def test_termdoc_medline_shape_paper_parameters_vs_oracle(ctx):
     rep = api.report_dict(r.report)
     assert r.converged and o.report["converged"]
     assert rep["sizes"] == [tuple(s) for s in o.report["sizes"]]
+    # iterate tracking: the boot relaxation divides by sigma_j, so each of its mu_b = 4 sweeps
+    # multiplies the sigma_1 component of pair 8 by about ((1 - omega) + omega sigma_1 / sigma_8)^2
+    # ~ 100 (omega 0.7, sigma_1 / sigma_8 ~ 14): rounding differences reach ~1e-8 per level visit
     for c in range(3):
         _sig_close([r.report.mult_sigma[c][j] for j in range(8)], o.report["mult_sigma"][c], r.report.anorm,
-                   rel=1e-9)
+                   rel=1e-8)
     assert abs(rep["add_iters"] - o.report["add_iters"]) <= 3
     s = sla.svds(A, k=10, tol=1e-13, return_singular_vectors=False)[::-1]
     _sig_close(r.sigma, s[:8], r.report.anorm)
@@ -526,16 +529,38 @@ def test_termdoc_medline_shape_paper_parameters_vs_oracle(ctx):
     _check_triplets(A, r, "svd", 1e-8, r.report.anorm)
 
 
-def test_gradient_minimal_follows_oracle_not_converging(ctx):
+def test_gradient_minimal_null_pair_and_valid_output(ctx):
     # minimal singular triplets of the rectangular discrete gradient (configuration 2's minimal half)
-    # at 16 x 16: sigma_1 = 0 with a 225-dimensional null space of A^t.  The method as stated does
-    # not converge here, in the oracle as on the device (documented as an open problem); the device
-    # follows the oracle's hierarchy and multiplicative phase, and both find the zero singular value
+    # at 16 x 16: sigma_1 = 0 with v_1 the constant vector, the next singular value is
+    # 2 sin(pi / 32), and A^t has a 225-dimensional null space.  The Kaczmarz sweeps on A^t u = 0
+    # pull every left test vector into that null space, so the Rayleigh quotients, and with them the
+    # minimal LS weights, are set by rounding: a relative change of 1e-15 in the oracle's own initial
+    # test vectors changes its hierarchy and its first-cycle estimates by O(1).  The iterates have no
+    # rounding-independent value to compare; the test compares what is unique (the zero pair) with the
+    # oracle and checks that everything else the device returns is a valid, consistently reported
+    # output.  Neither side converges to the wanted triplets in 30 additive iterations.
     from paper_1102_0919_amd import api
     A, wl, r, o = _run_both(ctx, "gradient2d_256_min8", scale=16, max_add=30)
+    anorm = r.report.anorm
     rep = api.report_dict(r.report)
-    assert rep["sizes"] == [tuple(s) for s in o.report["sizes"]]
-    assert np.allclose([r.report.mult_sigma[0][j] for j in range(8)], o.report["mult_sigma"][0],
-                       rtol=1e-8, atol=1e-12 * r.report.anorm)
-    assert not r.converged and not o.report["converged"]
-    assert r.sigma[0] <= 1e-8 * r.report.anorm and o.sigma[0] <= 1e-8 * r.report.anorm
+    assert not o.report["converged"]
+    if r.converged:                      # only the true spectrum passes the residual test
+        ref = W.gradient2d_singular_values(16)[:8]
+        _sig_close(r.sigma, ref, anorm)
+    # the zero pair: sigma_1 = 0 and u_1 in the null space of A^t; v_1 tends to +-1/16 (unique),
+    # which after 30 iterations of a run that does not converge is an iterate: within 1e-2
+    n = A.shape[1]
+    for res in (r, o):
+        assert res.sigma[0] <= 1e-8 * anorm
+        assert abs(res.V[:, 0].sum()) / np.sqrt(n) >= 0.99
+        assert np.linalg.norm(A.T @ res.U[:, 0]) <= 1e-8 * anorm
+    # a valid output: ascending non-negative estimates, orthonormal blocks, and the reported final
+    # residual is the residual of the returned triplets
+    assert np.all(np.diff(r.sigma) >= 0) and r.sigma[0] >= 0
+    assert np.allclose(r.U.T @ r.U, np.eye(8), atol=1e-9)
+    assert np.allclose(r.V.T @ r.V, np.eye(8), atol=1e-9)
+    rho = np.maximum(np.linalg.norm(A @ r.V - r.U * r.sigma, axis=0),
+                     np.linalg.norm(A.T @ r.U - r.V * r.sigma, axis=0)) / anorm
+    assert rep["add_iters"] == 30
+    assert abs(rho.max() - rep["rho_history"][30]) <= 1e-6 * rho.max()
+    assert rep["levels"] >= 2 and all(a[0] + a[1] > b[0] + b[1] for a, b in zip(rep["sizes"], rep["sizes"][1:]))
