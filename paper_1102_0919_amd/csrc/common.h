@@ -128,6 +128,12 @@ template <typename T> void launch_kacz(const KaczArgs<T>& a, hipStream_t s);
 template <typename T>
 void launch_kacz_wg(const KaczArgs<T>* halves, const int* const* cptr, const int* ncol, int nhalf, int nsweeps,
                     hipStream_t s);
+// Whole sweeps with one workgroup per block column, the updated vectors' column held in LDS
+// (nx[h]: length of half-sweep h's updated vector; with two half-sweeps each one's y is the other
+// one's x).  Returns false, having launched nothing, when the vectors do not fit one workgroup's LDS.
+template <typename T>
+bool launch_kacz_lds(const KaczArgs<T>* halves, const int* const* cptr, const int* ncol, const int* nx, int nhalf,
+                     int nsweeps, hipStream_t s);
 
 // Column reductions: partial sums over a fixed grid, then a fixed-order finalisation.
 // value_ic = (K ? (K z)_ic : z_ic) - (y ? s_c y_ic : 0);  acc_c += a ? a_ic * value_ic : value_ic^2

@@ -720,6 +720,207 @@ void launch_kacz_wg(const KaczArgs<T>* halves, const int* const* cptr, const int
   SLAMG_DISPATCH_VALS(k_kacz_wg, T, halves[0].vbf, sp, w, 1, WGB, s, p, sh);
 }
 
+// Whole sweeps with one workgroup per column j of the block.  The Kaczmarz update of column j
+// reads only column j of x and of y, and sigma_j / lambda_j (§5.3), so the columns are independent
+// and need no synchronisation across workgroups; a barrier separates the colours inside the
+// workgroup.  The workgroup keeps its column of every updated vector in LDS (SVD: v and u, each
+// also the other half-sweep's y), so a colour's gathers and updates never leave the CU; the
+// operator rows stream from L2.  The arithmetic per row is kacz_row's: the same lane split, the
+// same per-lane order of the nonzeros and the same butterfly reduction.
+template <typename T>
+struct KaczLdsPOD {
+  KaczPOD<T> h[2];
+  const int* cptr[2];
+  int ncol[2];
+  int nx[2];              // length of each half-sweep's updated vector
+  int nhalf, nsweeps;
+};
+
+static constexpr int KLB = 1024;
+
+template <typename T, int SPLIT, bool BF>
+__device__ __forceinline__ T kacz_coef(const KaczPOD<T>& a, int k, int r, T lam, bool shifted) {
+  T v = ldval<T, BF>(a.av, k);
+  if (shifted) v = v - lam * (a.bv ? ldval<T, BF>(a.bv, k) : (a.ci[k] == r ? T(1) : T(0)));
+  return v;
+}
+
+template <typename T, int SPLIT, bool BF>
+__device__ __forceinline__ void kacz_row_lds(const KaczPOD<T>& a, int r, int j, int sidx, T lam, T rs,
+                                             bool shifted, T* __restrict__ xs, const T* __restrict__ ys) {
+  const T kp = a.kap ? a.kap[(long)r * a.w + j] : T(0);
+  T rhs;
+  if (a.rmode == M_CSR) {
+    T my = T(0);
+    for (int k = a.Mrp[r] + sidx; k < a.Mrp[r + 1]; k += SPLIT) my += ldval<T, BF>(a.Mv, k) * ys[a.Mci[k]];
+    rhs = rs * split_sum<SPLIT>(my, 1) + kp;
+  } else if (a.rmode == M_IDENT) {
+    rhs = rs * ys[r] + kp;
+  } else {
+    rhs = kp;
+  }
+  const int kb = a.rp[r], ke = a.rp[r + 1];
+  // a lane's first four nonzeros stay in registers for the update
+  constexpr int U = 4;
+  int jc[U];
+  T cv[U];
+  T dot = T(0);
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int k = kb + sidx + u * SPLIT;
+    jc[u] = -1;
+    cv[u] = T(0);
+    if (k < ke) {
+      jc[u] = a.ci[k];
+      cv[u] = kacz_coef<T, SPLIT, BF>(a, k, r, lam, shifted);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (jc[u] >= 0) dot += cv[u] * xs[jc[u]];
+  for (int k = kb + sidx + U * SPLIT; k < ke; k += SPLIT) dot += kacz_coef<T, SPLIT, BF>(a, k, r, lam, shifted) * xs[a.ci[k]];
+  dot = split_sum<SPLIT>(dot, 1);
+  T nr = a.rn_aa[r];
+  if (shifted) nr = nr - T(2) * lam * a.rn_ab[r] + lam * lam * a.rn_bb[r];
+  const T coef = nr > T(0) ? (rhs - dot) / nr : T(0);
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (jc[u] >= 0) xs[jc[u]] += coef * cv[u];
+  for (int k = kb + sidx + U * SPLIT; k < ke; k += SPLIT) xs[a.ci[k]] += coef * kacz_coef<T, SPLIT, BF>(a, k, r, lam, shifted);
+}
+
+template <typename T, int SPLIT, bool BF>
+__global__ __launch_bounds__(KLB) void k_kacz_lds(KaczLdsPOD<T> a) {
+  extern __shared__ __align__(16) unsigned char kl_smem[];
+  T* xs0 = reinterpret_cast<T*>(kl_smem);
+  T* xs1 = xs0 + a.nx[0];
+  const int j = blockIdx.x;
+  const int w = a.h[0].w;
+  for (int h = 0; h < a.nhalf; ++h) {
+    T* xs = h ? xs1 : xs0;
+    const T* xg = a.h[h].x;
+    for (int r = threadIdx.x; r < a.nx[h]; r += KLB) xs[r] = xg[(long)r * w + j];
+  }
+  __syncthreads();
+  const int grp = threadIdx.x / SPLIT, sidx = threadIdx.x % SPLIT;
+  constexpr int NG = KLB / SPLIT;
+  for (int s = 0; s < a.nsweeps; ++s) {
+    for (int h = 0; h < a.nhalf; ++h) {
+      const KaczPOD<T> k = h == 0 ? a.h[0] : a.h[1];
+      T* xs = h ? xs1 : xs0;
+      const T* ys = h ? xs0 : xs1;
+      const bool shifted = k.lam != nullptr;
+      const T lam = shifted ? (T)k.lam[j] : T(0);
+      const T rs = k.rmode != M_NONE ? (T)k.rsig[j] : T(0);
+      const int* cp = h == 0 ? a.cptr[0] : a.cptr[1];
+      const int nc = h == 0 ? a.ncol[0] : a.ncol[1];
+      for (int c = 0; c < nc; ++c) {
+        const int rb = cp[c], re = cp[c + 1];
+        for (int idx = rb + grp; idx < re; idx += NG)
+          kacz_row_lds<T, SPLIT, BF>(k, k.rows[idx], j, sidx, lam, rs, shifted, xs, ys);
+        __syncthreads();
+      }
+    }
+  }
+  for (int h = 0; h < a.nhalf; ++h) {
+    const T* xs = h ? xs1 : xs0;
+    T* xg = a.h[h].x;
+    for (int r = threadIdx.x; r < a.nx[h]; r += KLB) xg[(long)r * w + j] = xs[r];
+  }
+}
+
+// Largest dynamic LDS one workgroup of k_kacz_lds may take (the device limit; the kernel has no
+// static LDS), and the opt-in above the default limit, once per instantiation.
+static int kacz_lds_max() {
+  static const int v = [] {
+    int dev = 0, x = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&x, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+      (void)hipGetLastError();
+      x = 65536;
+    }
+    return x;
+  }();
+  return v;
+}
+
+template <typename T, int SPLIT, bool BF>
+static bool kacz_lds_optin() {
+  static const bool ok = [] {
+    if (hipFuncSetAttribute((const void*)k_kacz_lds<T, SPLIT, BF>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            kacz_lds_max()) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    return true;
+  }();
+  return ok;
+}
+
+// every instantiation opts in on the first launch of any, which the multiplicative phase makes
+// eagerly, so that no attribute call falls inside a captured iteration
+template <typename T>
+static bool kacz_lds_optin_all() {
+  static const bool ok = [] {
+    bool r = kacz_lds_optin<T, 4, false>() & kacz_lds_optin<T, 8, false>() & kacz_lds_optin<T, 16, false>() &
+             kacz_lds_optin<T, 32, false>();
+    if constexpr (std::is_same<T, float>::value)
+      r = r & kacz_lds_optin<T, 4, true>() & kacz_lds_optin<T, 8, true>() & kacz_lds_optin<T, 16, true>() &
+          kacz_lds_optin<T, 32, true>();
+    return r;
+  }();
+  return ok;
+}
+
+template <typename T, int SPLIT, bool BF>
+static bool kacz_lds_go(const KaczLdsPOD<T>& p, int w, size_t lds, hipStream_t s) {
+  if (lds > 65536 && !kacz_lds_optin_all<T>()) return false;
+  hipLaunchKernelGGL((k_kacz_lds<T, SPLIT, BF>), dim3(w), dim3(KLB), lds, s, p);
+  return true;
+}
+
+template <typename T, bool BF>
+static bool kacz_lds_split(const KaczLdsPOD<T>& p, int sp, int w, size_t lds, hipStream_t s) {
+  if (sp == 4) return kacz_lds_go<T, 4, BF>(p, w, lds, s);
+  if (sp == 8) return kacz_lds_go<T, 8, BF>(p, w, lds, s);
+  if (sp == 16) return kacz_lds_go<T, 16, BF>(p, w, lds, s);
+  return kacz_lds_go<T, 32, BF>(p, w, lds, s);
+}
+
+template <typename T>
+bool launch_kacz_lds(const KaczArgs<T>* halves, const int* const* cptr, const int* ncol, const int* nx, int nhalf,
+                     int nsweeps, hipStream_t s) {
+  size_t lds = 0;
+  for (int h = 0; h < nhalf; ++h) lds += (size_t)nx[h] * sizeof(T);
+  if (lds == 0 || lds > (size_t)kacz_lds_max() || halves[0].w <= 0) return false;
+  // a right-hand side operator reads the other half-sweep's vector, which must be the one in LDS
+  for (int h = 0; h < nhalf; ++h) {
+    if (halves[h].rmode == M_NONE) continue;
+    if (nhalf != 2 || halves[h].y != halves[1 - h].x) return false;
+  }
+  KaczLdsPOD<T> p{};
+  double avg = 0.0;
+  for (int h = 0; h < nhalf; ++h) {
+    const KaczArgs<T>& a = halves[h];
+    p.h[h] = KaczPOD<T>{0, a.rows, a.w, a.rp, a.ci, a.av, a.bv, a.lam, a.rn_aa, a.rn_ab, a.rn_bb,
+                        a.rmode, a.Mrp, a.Mci, a.Mv, a.y, a.rsig, a.kap, a.x};
+    p.cptr[h] = cptr[h];
+    p.ncol[h] = ncol[h];
+    p.nx[h] = nx[h];
+    if (a.nnz_rows > 0) avg = std::max(avg, (double)a.nnz_total / (double)a.nnz_rows);
+    if (a.rmode == M_CSR) avg = std::max(avg, a.avgM);
+  }
+  p.nhalf = nhalf;
+  p.nsweeps = nsweeps;
+  // lanes per row: about four nonzeros per lane, so that a lane's share stays in registers
+  const int sp = avg <= 16.0 ? 4 : avg <= 32.0 ? 8 : avg <= 64.0 ? 16 : 32;
+  const int w = halves[0].w;
+  if constexpr (std::is_same<T, float>::value) {
+    if (halves[0].vbf) return kacz_lds_split<T, true>(p, sp, w, lds, s);
+  }
+  return kacz_lds_split<T, false>(p, sp, w, lds, s);
+}
+
 template <typename T>
 void launch_kacz(const KaczArgs<T>& a, hipStream_t s) {
   if (a.nrows <= 0) return;
@@ -1427,6 +1628,10 @@ template void launch_kacz<double>(const KaczArgs<double>&, hipStream_t);
 template void launch_kacz<float>(const KaczArgs<float>&, hipStream_t);
 template void launch_kacz_wg<double>(const KaczArgs<double>*, const int* const*, const int*, int, int, hipStream_t);
 template void launch_kacz_wg<float>(const KaczArgs<float>*, const int* const*, const int*, int, int, hipStream_t);
+template bool launch_kacz_lds<double>(const KaczArgs<double>*, const int* const*, const int*, const int*, int, int,
+                                      hipStream_t);
+template bool launch_kacz_lds<float>(const KaczArgs<float>*, const int* const*, const int*, const int*, int, int,
+                                     hipStream_t);
 template void launch_dots<double>(const DotArgs<double>&, double*, double*, hipStream_t);
 template void launch_dots<float>(const DotArgs<float>&, double*, double*, hipStream_t);
 template void launch_dots2<double>(const DotArgs<double>&, double*, double*, const DotArgs<double>&, double*,

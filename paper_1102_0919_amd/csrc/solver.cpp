@@ -1116,10 +1116,13 @@ void Solver::relax_tests(int l) {
           kacz(l, k, cnnz[c]);
         }
       };
-      if (L.kacz_wg) {
+      // whole sweeps in one launch: per-column workgroups with the vectors in LDS where they fit,
+      // else one workgroup for the block on small levels, else one launch per colour
+      bool whole = false;
+      {
         KaczArgs<double> h[2];
-        const int* cp[2];
-        int nc[2];
+        const int* cp[2] = {nullptr, nullptr};
+        int nc[2] = {0, 0};
         h[0].nnz_total = L.A.nnz; h[0].nnz_rows = L.A.m;
         h[0].rows = L.kA_rows; h[0].w = nt_; h[0].rp = L.A.rp; h[0].ci = L.A.ci; h[0].av = L.A.v;
         h[0].rn_aa = L.ad.rnA; h[0].x = spd_ ? b.Ut : b.Vt;
@@ -1130,7 +1133,14 @@ void Solver::relax_tests(int l) {
           h[1].rn_aa = L.ad.rnAt; h[1].x = b.Ut;
           cp[1] = L.d_kAt_cptr; nc[1] = (int)L.kAt_cptr.size() - 1;
         }
-        launch_kacz_wg<double>(h, cp, nc, spd_ ? 1 : 2, 1, st_);
+        const int nx[2] = {spd_ ? L.m : L.n, L.m};
+        whole = launch_kacz_lds<double>(h, cp, nc, nx, spd_ ? 1 : 2, 1, st_);
+        if (!whole && L.kacz_wg) {
+          launch_kacz_wg<double>(h, cp, nc, spd_ ? 1 : 2, 1, st_);
+          whole = true;
+        }
+      }
+      if (whole) {
         da = DotArgs<double>{};
         da.nrows = mu; da.w = nt_; da.a = b.Ut; da.z = b.Ut;
         if (!L.finest) { da.Krp = spd_ ? L.A.rp : L.B.rp; da.Kci = spd_ ? L.A.ci : L.B.ci; da.nnzK = spd_ ? L.A.nnz : L.B.nnz; da.Kv = L.B.v; }
@@ -1178,11 +1188,13 @@ void Solver::boot_relax(int l, const T* kap, const T* tau, const double* sig, in
   Aux<T>& x = aux<T>(L);
   const int mu = rows_u(L), mv = rows_v(L);
   if (nsweeps <= 0) return;
-  if (minimal_ && L.kacz_wg) {
-    // all nsweeps sweeps, all colours, in one workgroup
+  if (minimal_) {
+    // all nsweeps sweeps, all colours, in one launch: per-column workgroups with the vectors in
+    // LDS where they fit, else one workgroup for the block on small levels
     KaczArgs<T> h[2];
-    const int* cp[2];
-    int nc[2];
+    const int* cp[2] = {nullptr, nullptr};
+    int nc[2] = {0, 0};
+    const int nx[2] = {spd_ ? L.m : L.n, L.m};
     if (spd_) {
       h[0].nnz_total = L.A.nnz; h[0].nnz_rows = L.A.m;
       h[0].rows = L.kA_rows; h[0].w = nb_; h[0].rp = L.A.rp; h[0].ci = L.A.ci; h[0].av = vals<T>(L.A);
@@ -1190,7 +1202,12 @@ void Solver::boot_relax(int l, const T* kap, const T* tau, const double* sig, in
       h[0].rn_aa = x.rnA; h[0].rn_ab = x.rnAab; h[0].rn_bb = x.rnAbb; h[0].kap = kap; h[0].x = b.Ub;
       cp[0] = L.d_kA_cptr; nc[0] = (int)L.kA_cptr.size() - 1;
       h[0].vbf = vbf<T>();
-      launch_kacz_wg<T>(h, cp, nc, 1, nsweeps, st_);
+      h[0].nnz_total = L.A.nnz; h[0].nnz_rows = L.A.m;
+      if (launch_kacz_lds<T>(h, cp, nc, nx, 1, nsweeps, st_)) return;
+      if (L.kacz_wg) {
+        launch_kacz_wg<T>(h, cp, nc, 1, nsweeps, st_);
+        return;
+      }
     } else {
       h[0].nnz_total = L.A.nnz; h[0].nnz_rows = L.A.m;
       h[0].rows = L.kA_rows; h[0].w = nb_; h[0].rp = L.A.rp; h[0].ci = L.A.ci; h[0].av = vals<T>(L.A);
@@ -1203,9 +1220,12 @@ void Solver::boot_relax(int l, const T* kap, const T* tau, const double* sig, in
       cp[0] = L.d_kA_cptr; nc[0] = (int)L.kA_cptr.size() - 1;
       cp[1] = L.d_kAt_cptr; nc[1] = (int)L.kAt_cptr.size() - 1;
       h[0].vbf = h[1].vbf = vbf<T>();
-      launch_kacz_wg<T>(h, cp, nc, 2, nsweeps, st_);
+      if (launch_kacz_lds<T>(h, cp, nc, nx, 2, nsweeps, st_)) return;
+      if (L.kacz_wg) {
+        launch_kacz_wg<T>(h, cp, nc, 2, nsweeps, st_);
+        return;
+      }
     }
-    return;
   }
   if (nsweeps > 1) {
     for (int it = 0; it < nsweeps; ++it) boot_relax<T>(l, kap, tau, sig, 1, zero_start && it == 0);
