@@ -568,9 +568,10 @@ __device__ __forceinline__ void kacz_row(const KaczPOD<T>& a, int r, int c0, int
 #pragma unroll
     for (int c = 0; c < CPL; ++c) rhs[c] = rs[c] * yid[c] + kp[c];
   }
-  // residual of the row: four nonzeros per step (see walk_row); a lane whose nonzeros fit one step
-  // keeps their rows in registers for the update
-  constexpr int U = 4;
+  // residual of the row: eight nonzeros per step; a lane whose nonzeros fit one step (a 7-point
+  // row on one lane, rows of up to 32 nonzeros on four) keeps their x rows in registers for the
+  // update instead of gathering them again
+  constexpr int U = 8;
   int j[U];
   T av[U], bv[U], xr[U][CPL];
   T dot[CPL];
@@ -760,8 +761,8 @@ __device__ __forceinline__ void kacz_row_lds(const KaczPOD<T>& a, int r, int j, 
     rhs = kp;
   }
   const int kb = a.rp[r], ke = a.rp[r + 1];
-  // a lane's first four nonzeros stay in registers for the update
-  constexpr int U = 4;
+  // a lane's first eight nonzeros stay in registers for the update
+  constexpr int U = 8;
   int jc[U];
   T cv[U];
   T dot = T(0);
@@ -912,7 +913,7 @@ bool launch_kacz_lds(const KaczArgs<T>* halves, const int* const* cptr, const in
   }
   p.nhalf = nhalf;
   p.nsweeps = nsweeps;
-  // lanes per row: about four nonzeros per lane, so that a lane's share stays in registers
+  // lanes per row: about four nonzeros per lane (a lane keeps up to eight in registers)
   const int sp = avg <= 16.0 ? 4 : avg <= 32.0 ? 8 : avg <= 64.0 ? 16 : 32;
   const int w = halves[0].w;
   if constexpr (std::is_same<T, float>::value) {
