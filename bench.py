@@ -40,15 +40,23 @@ REPORTED = {1: "relaxation (finest-level Kaczmarz sweeps)", 0: "relaxation (fine
             5: "block SpMM (finest level)", 3: "Galerkin SpGEMM (all levels)"}
 
 # HBM traffic of the dominant kernel class, from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs
-# (profiles/pmc_*_gradient2d_256_dom8.md), per dispatch in KiB for the two finest-level k_rowop
-# launch shapes (u rows, v rows), scaled by the same counters of a 1 GiB device copy
-# (profiles/pmc_*_copy_1GiB.md: FETCH 524304.5 KiB, WRITE 1048576.0 KiB per 1 GiB).  Valid only
-# for the kernel source the counters were taken with.
+# (profiles/pmc_*_<workload>.md), per dispatch in KiB, scaled by the same counters of a 1 GiB device
+# copy (profiles/pmc_*_copy_1GiB.md: FETCH 524304.5 KiB, WRITE 1048576.0 KiB per 1 GiB).  Valid
+# only for the kernel source the counters were taken with.
 TRAFFIC = {
+    # the two finest-level k_rowop launch shapes (u rows, v rows)
     ("gradient2d_256_dom8", 0): dict(
         kernels_sha256="56df206b3531e9b5594c229e089abdefcc35af292738dcdd46269dfbf4342271",
         fetch_kib=(12230.1, 10374.9), write_kib=(8160.0, 4096.0),
-        copy_fetch_kib=524304.5, copy_write_kib=1048576.0, copy_bytes=1 << 30),
+        copy_fetch_kib=524304.5, copy_write_kib=1048576.0, copy_bytes=1 << 30,
+        note="mean of the finest-level u-row and v-row launches"),
+    # every finest-level k_kacz launch of the multiplicative phase and one additive iteration
+    ("aniso3d_128_min8", 1): dict(
+        kernels_sha256="7008812433c3f5d8b83a2c403201c7b4cbb238e9a72449e454b2b314a84183f5",
+        fetch_kib=(117666.0,), write_kib=(154373.4,),
+        copy_fetch_kib=524304.5, copy_write_kib=1048576.0, copy_bytes=1 << 30,
+        note="mean over the 1240 finest-level Kaczmarz colour launches of the multiplicative phase and "
+             "one additive iteration"),
 }
 
 
@@ -64,7 +72,7 @@ def _traffic(name, cls):
     fw = t["copy_bytes"] / (t["copy_write_kib"] * 1024.0)
     per = [(fk * ff + wk * fw) * 1024.0 for fk, wk in zip(t["fetch_kib"], t["write_kib"])]
     return sum(per) / len(per), (f"rocprofv3 FETCH_SIZE x {ff:.4f} + WRITE_SIZE x {fw:.4f} (copy-calibrated), "
-                                 "mean of the finest-level u-row and v-row launches")
+                                 + t["note"])
 
 
 def _closed_form(name, n_b, target):
@@ -188,11 +196,12 @@ def main():
     kind, target, n_b = wl["kind"], wl["target"], wl["n_b"]
     stream = torch.cuda.current_stream()
 
-    def params(precision, mask):
+    def params(precision, mask, graphs=1):
         prm = dict(wl["params"])
         prm["precision"] = precision
         prm["profile_mask"] = mask
         prm["max_add"] = args.max_add
+        prm["graphs"] = graphs
         return api.params_init(kind, target, **prm)
 
     ctx = api.Context(0, stream=stream.cuda_stream)
@@ -203,20 +212,24 @@ def main():
     print(f"[bench] workload {name}: {A.shape[0]}x{A.shape[1]} nnz={A.nnz} n_b={n_b} {args.precision}",
           file=sys.stderr, flush=True)
     p = params(args.precision, 0 if args.no_profile else ALL_CLASSES)
+    # the untimed warmup runs every additive iteration eagerly (no graph replay), so that its
+    # class times cover every launch of the solve: they pick the dominant kernel class
+    pw = params(args.precision, 0 if args.no_profile else ALL_CLASSES, graphs=0)
     warm_ms = np.zeros(NCLS)
     for _ in range(max(args.warmup, 1 if not args.no_profile else 0)):
-        w = api.solve_matrix(ctx, mat, target, n_b, p, U_dev=U_dev, V_dev=V_dev)
+        w = api.solve_matrix(ctx, mat, target, n_b, pw, U_dev=U_dev, V_dev=V_dev)
         warm_ms = np.array([w.report.prof_ms[c] for c in range(NCLS)])
         print(f"[bench] warmup: add_iters={w.report.add_iters} converged={w.converged}", file=sys.stderr, flush=True)
     reps, ms = _run_steps(api, ctx, mat, target, n_b, p, U_dev, V_dev, args.steps, args.precision)
     value = n_b / (ms / 1e3)
     last = reps[-1]
     ref = _closed_form(name, n_b, target)
-    # roofline: the profiled kernel class with the largest device time over the timed steps
+    # roofline: the profiled kernel class with the largest device time over the whole warmup solve;
+    # its bytes and launch durations from the launches sampled in the timed steps
     tot_ms, tot_n, tot_b = _class_totals(reps)
     roof = None
     if tot_ms.sum() > 0:
-        c = int(np.argmax(np.where(tot_b > 0, tot_ms, 0)))
+        c = int(np.argmax(np.where(tot_b > 0, warm_ms if warm_ms.sum() > 0 else tot_ms, 0)))
         avg_ms = tot_ms[c] / tot_n[c]
         per_launch = tot_b[c] / tot_n[c]
         ach = per_launch / (avg_ms * 1e-3) / 1e9
@@ -238,7 +251,7 @@ def main():
                 "algorithmic_bytes_per_launch": int(per_launch),
                 "graph_iters_per_step": int(last.report.graph_iters),
                 "kernels": kernels,
-                "sampled_class_ms_in_warmup": {CLASS_NAMES[i]: round(warm_ms[i], 3) for i in range(NCLS)}}
+                "class_ms_in_warmup_solve": {CLASS_NAMES[i]: round(warm_ms[i], 3) for i in range(NCLS)}}
     compare = None
     if args.compare != "none" and args.compare != args.precision:
         p2 = params(args.compare, 0)

@@ -3,7 +3,8 @@
     python -m paper_1102_0919_amd.prof_summary DB_OR_DIR --title T --cmd "C" [--kernel NAME ...] [--pmc]
 
 Prints, for the whole run: calls, total and average duration of every kernel; then, for each kernel
-named with --kernel, its launches grouped by grid size (the largest grids are the finest level).
+named with --kernel (a substring of the full name, template arguments included), its launches grouped
+by grid size, largest total time first.
 With --pmc the database holds counter samples (rocprofv3 --pmc): their per-dispatch averages are
 listed per kernel and grid size instead.
 """
@@ -42,13 +43,13 @@ def kernel_table(con) -> list[str]:
 
 def grid_table(con, kernel: str) -> list[str]:
     rows = list(con.execute(
-        "select name, grid_x, count(*), avg(duration), min(duration), max(duration) from kernels "
-        "where name like ? group by name, grid_x order by grid_x desc", (f"%{kernel}%",)))
-    out = [f"Launches of `{kernel}` by grid size (threads; the largest grid is the finest level):", "",
-           "| instance | grid_x | calls | average (us) | min (us) | max (us) |", "|---|---|---|---|---|---|"]
-    for n, g, c, a, lo, hi in rows[:12]:
-        inst = n.split("(")[0].replace("void ", "").replace("slamg::", "")
-        out.append(f"| `{inst}` | {g} | {c} | {a / 1e3:.2f} | {lo / 1e3:.2f} | {hi / 1e3:.2f} |")
+        "select name, grid_x, count(*), sum(duration), avg(duration), min(duration), max(duration) from kernels "
+        "where name like ? group by name, grid_x order by sum(duration) desc", (f"%{kernel}%",)))
+    out = [f"Launches of `{kernel}` by launch shape (grid in threads), the 12 largest by total time:", "",
+           "| instance | grid_x | calls | total (ms) | average (us) | min (us) | max (us) |",
+           "|---|---|---|---|---|---|---|"]
+    for n, g, c, t, a, lo, hi in rows[:12]:
+        out.append(f"| `{_short(n)}` | {g} | {c} | {t / 1e6:.3f} | {a / 1e3:.2f} | {lo / 1e3:.2f} | {hi / 1e3:.2f} |")
     return out
 
 
@@ -68,6 +69,15 @@ def pmc_table(con, kernel: str | None) -> list[str]:
            "| kernel | grid | counter | dispatches | average per dispatch |", "|---|---|---|---|---|"]
     for n, g, cn, c, v in rows[:40]:
         out.append(f"| `{_short(n)}` | {g} | {cn} | {c} | {v:.1f} |")
+    # all matching dispatches together
+    tot: dict = {}
+    for n, g, cn, c, v in rows:
+        d, s_ = tot.get(cn, (0, 0.0))
+        tot[cn] = (d + c, s_ + c * v)
+    if tot:
+        out += ["", "| counter | dispatches | average per dispatch (all shapes) |", "|---|---|---|"]
+        for cn, (d, s_) in sorted(tot.items()):
+            out.append(f"| {cn} | {d} | {s_ / d:.1f} |")
     return out
 
 
