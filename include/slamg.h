@@ -113,7 +113,12 @@ typedef struct {
   int32_t kaczmarz_order;   /* row order of the Kaczmarz sweeps of minimal targets (§5.3): 0
                                multicolour (rows of one colour share no column, colours
                                ascending, rows ascending), 1 lexicographic (row by row) (0)     */
-  int32_t reserved[1];
+  int32_t coarse_dense_max; /* completed C-sets: where coarsening would stop at a level of more
+                               than this many unknowns, each side with fewer than n_b + n_guard
+                               + n_t C-points gets its most influential F-points as further
+                               C-points (Algorithm 1's initial measure, lowest index on ties)
+                               and coarsening continues.  1 .. 1024, the largest coarsest level
+                               the dense coarsest solves take (1024)                            */
 } slamg_params;
 
 /* Report of one solve.  Arrays are filled up to the counts given. */

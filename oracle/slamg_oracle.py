@@ -55,6 +55,12 @@ the design notes of the repository):
   R29 guard pairs (optional): the method runs with a block of n_b + n_guard pairs (coarsest
       selection, boot vectors, V-cycles, Ritz step all on the larger block); the stopping test and
       the outputs take the n_b extremal ones.
+  R30 completed C-sets: where the rules above would stop coarsening at a level larger than
+      ``coarse_dense_max`` unknowns (more than the dense coarsest solves take), each side with
+      fewer than n_b + n_t C-points of Algorithm 1's split gets more: its F-points that strongly
+      influence the most points (lowest index on ties) become C-points until it has n_b + n_t
+      (a side with at most n_b + n_t points keeps them all), the interpolatory sets follow, and
+      coarsening continues.
 """
 from __future__ import annotations
 
@@ -100,6 +106,7 @@ class Params:
     n_guard: int = 0              # R29: extra pairs iterated in the block beyond the n_b wanted
     mu_tJ: int = 1                # inner weighted-Jacobi steps of a test relaxation (§3.4)
     mu_bJ: int = 1                # inner weighted-Jacobi steps of a boot relaxation (§3.5)
+    coarse_dense_max: int = 1024  # R30: largest level (unknowns) a coarsening may stop at
 
 
 NORM_SEED_XOR = 0xA5A5A5A5A5A5A5A5
@@ -661,7 +668,31 @@ def build_side(N, params, n_t):
     Sp, Si = strength_sets(N, params.theta, params.strength_rule, params.top_s)
     is_c = rs_coarsen(Sp, Si, N.shape[0])
     ptr, cols, capped = interp_pattern(Sp, Si, N, is_c, n_t - 1)
-    return Side(is_c, np.nonzero(is_c)[0], ptr, cols, capped)
+    side = Side(is_c, np.nonzero(is_c)[0], ptr, cols, capped)
+    side.strength = (N, Sp, Si)
+    return side
+
+
+def complete_c_set(side, need, n_t):
+    """R30: a side with fewer than ``need`` C-points gets its F-points that strongly influence the
+    most points (the initial lambda of Algorithm 1; lowest index on ties) as further C-points until
+    it has ``need``; its interpolatory sets are rebuilt on the same strength sets.  A side with at
+    most ``need`` points keeps all of them."""
+    npts = side.is_c.size
+    if int(side.is_c.sum()) >= need:
+        return side
+    if npts <= need:
+        return identity_side(npts)
+    N, Sp, Si = side.strength
+    influence = np.bincount(Si, minlength=npts)
+    f = np.nonzero(~side.is_c)[0]
+    order = f[np.lexsort((f, -influence[f]))]
+    is_c = side.is_c.copy()
+    is_c[order[:need - int(side.is_c.sum())]] = True
+    ptr, cols, capped = interp_pattern(Sp, Si, N, is_c, n_t - 1)
+    out = Side(is_c, np.nonzero(is_c)[0], ptr, cols, capped)
+    out.strength = side.strength
+    return out
 
 
 def identity_side(npts):
@@ -774,9 +805,17 @@ class Solver:
                     Nu, Nv = strength_operators(lev, kind, p, l == 0)
                     su = build_side(Nu, p, p.n_t)
                     sv = None if kind == SPD else build_side(Nv, p, p.n_t)
+                su0, sv0 = su, sv
                 su, sv = one_sided_coarsening(su, sv, kind, self.n_b + p.n_t)
                 if not self._coarsening_ok(lev, su, sv):
-                    break
+                    if level_size(lev, kind) <= p.coarse_dense_max:
+                        break
+                    # R30: complete the short sides of Algorithm 1's split instead of stopping
+                    su = complete_c_set(su0, self.n_b + p.n_t, p.n_t)
+                    if kind == SVD:
+                        sv = shared_side(su) if p.square_coarsening else complete_c_set(sv0, self.n_b + p.n_t, p.n_t)
+                    if not self._coarsening_ok(lev, su, sv):
+                        break
                 lev.su, lev.sv = su, sv
                 self.report["capped"].append(su.capped + (0 if sv is None else sv.capped))
             elif l == len(self.levels) - 1:

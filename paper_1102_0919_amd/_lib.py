@@ -34,7 +34,7 @@ class Params(C.Structure):
                 ("ritz_in_mult", C.c_int32), ("coarse_pinv", C.c_int32), ("profile_mask", C.c_int32),
                 ("verbose", C.c_int32), ("graphs", C.c_int32), ("square_coarsening", C.c_int32),
                 ("n_guard", C.c_int32), ("mu_tJ", C.c_int32), ("mu_bJ", C.c_int32),
-                ("kaczmarz_order", C.c_int32), ("reserved", C.c_int32 * 1)]
+                ("kaczmarz_order", C.c_int32), ("coarse_dense_max", C.c_int32)]
 
 
 class Report(C.Structure):

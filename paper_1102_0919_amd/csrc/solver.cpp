@@ -200,7 +200,12 @@ class Solver {
   void finest_level(const double* init_tests);
   void norm_estimate();
   bool build_structure(int l);
-  void build_side(Level& L, Side& S, const HCsr& N, int npts);
+  // strength sets of a side, kept while its level's coarsening is decided
+  struct Strength {
+    std::vector<int> Sp, Si;
+  };
+  void build_side(Level& L, Side& S, const HCsr& N, int npts, Strength* keep = nullptr);
+  void complete_side(Side& S, const HCsr& N, const Strength& st, int need);
   void identity_side(Side& S, int npts);
   void finish_side(Side& S, const std::vector<int>& ptr, const std::vector<int>& fine_cols);
   void make_coarse_level(int l);
@@ -862,7 +867,7 @@ HCsr Solver::strength_operator(Level& L, bool u_side, bool finest) {
   return N;
 }
 
-void Solver::build_side(Level& L, Side& S, const HCsr& N, int npts) {
+void Solver::build_side(Level& L, Side& S, const HCsr& N, int npts, Strength* keep) {
   (void)L;
   std::vector<int> Sp, Si;
   strength_sets(N, p_.theta, p_.strength_rule, p_.top_s, Sp, Si);
@@ -870,6 +875,32 @@ void Solver::build_side(Level& L, Side& S, const HCsr& N, int npts) {
   S.is_c = rs_coarsen(Sp, Si, npts);
   std::vector<int> ptr, fine_cols;
   interp_pattern(Sp, Si, N, S.is_c, nt_ - 1, ptr, fine_cols, S.capped);
+  finish_side(S, ptr, fine_cols);
+  if (keep) {
+    keep->Sp = std::move(Sp);
+    keep->Si = std::move(Si);
+  }
+}
+
+// Completed C-set of a side with fewer than `need` C-points: its F-points that strongly influence
+// the most points (Algorithm 1's initial measure; lowest index on ties) become C-points until it
+// has `need`, and its interpolatory sets are rebuilt on the same strength sets.  A side with at
+// most `need` points keeps all of them.
+void Solver::complete_side(Side& S, const HCsr& N, const Strength& st, int need) {
+  if (S.nc >= need) return;
+  if (S.npts <= need) {
+    identity_side(S, S.npts);
+    return;
+  }
+  std::vector<int> infl(S.npts, 0);
+  for (int k : st.Si) ++infl[k];
+  std::vector<int> f;
+  for (int i = 0; i < S.npts; ++i)
+    if (!S.is_c[i]) f.push_back(i);
+  std::stable_sort(f.begin(), f.end(), [&](int a, int b) { return infl[a] > infl[b]; });
+  for (int t = 0; t < need - S.nc; ++t) S.is_c[f[t]] = 1;
+  std::vector<int> ptr, fine_cols;
+  interp_pattern(st.Sp, st.Si, N, S.is_c, nt_ - 1, ptr, fine_cols, S.capped);
   finish_side(S, ptr, fine_cols);
 }
 
@@ -913,7 +944,8 @@ bool Solver::build_structure(int l) {
   if (size_of(L) <= p_.coarse_max || l + 1 >= p_.max_levels) return false;
   HCsr Nu = strength_operator(L, true, l == 0);
   Side su, sv;
-  build_side(L, su, Nu, L.m);
+  Strength stu, stv;
+  build_side(L, su, Nu, L.m, &stu);
   HCsr Nv;
   if (square_) {
     // §5.1: the v-side takes the u-side's C/F split and interpolatory sets (one pattern for P and
@@ -922,18 +954,35 @@ bool Solver::build_structure(int l) {
     sv.capped = 0;
   } else if (!spd_) {
     Nv = strength_operator(L, false, l == 0);
-    build_side(L, sv, Nv, L.n);
+    build_side(L, sv, Nv, L.n, &stv);
   }
   const int need = nb_ + nt_;
+  const Side su0 = su, sv0 = sv;
   if (!spd_) {
     // one-sided coarsening: a side that would keep fewer than n_b + n_t points while the other
     // side coarsens keeps all of its points
     if (su.nc < need && sv.nc >= need) identity_side(su, L.m);
     else if (sv.nc < need && su.nc >= need) identity_side(sv, L.n);
   }
-  const int nc = spd_ ? su.nc : su.nc + sv.nc;
-  if (nc > p_.stall_ratio * size_of(L)) return false;
-  if (su.nc < need || (!spd_ && sv.nc < need)) return false;
+  auto coarsens = [&] {
+    const int nc = spd_ ? su.nc : su.nc + sv.nc;
+    return !(nc > p_.stall_ratio * size_of(L)) && su.nc >= need && (spd_ || sv.nc >= need);
+  };
+  if (!coarsens()) {
+    if (size_of(L) <= p_.coarse_dense_max) return false;
+    // completed C-sets of Algorithm 1's split instead of a coarsest level too large for the
+    // dense coarsest solves
+    su = su0;
+    complete_side(su, Nu, stu, need);
+    if (square_) {
+      sv = su;
+      sv.capped = 0;
+    } else if (!spd_) {
+      sv = sv0;
+      complete_side(sv, Nv, stv, need);
+    }
+    if (!coarsens()) return false;
+  }
   // device copies
   auto devside = [&](Side& S) {
     S.P = upload(S.Ppat, true);

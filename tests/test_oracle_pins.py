@@ -701,3 +701,47 @@ def test_termdoc_medline_shape_against_arpack():
     ref = spla.svds(A, k=10, tol=1e-13, return_singular_vectors=False)[::-1][:8]
     assert np.all(np.abs(r.sigma - ref) <= 1e-10 * ref)
     assert np.allclose(A @ r.V, r.U * r.sigma, atol=1e-8 * r.report["anorm"])
+
+
+def test_completed_c_set_takes_the_most_influential_f_points():
+    # R30 on a hand-built strength graph.  S_i lists the points i depends on strongly; point k
+    # strongly influences every i with k in S_i.  Influence counts: 0 -> 1, 1 -> 3, 2 -> 3, 3 -> 0,
+    # 4 -> 2, 5 -> 1; C-set {0}.  Completing to 4 points takes the F-points of largest influence,
+    # lowest index on ties: 1 and 2 (3 each), then 4 (2); 3 and 5 stay F.
+    S = [[1], [2], [1, 4], [1, 2], [2, 5], [0, 4]]
+    Sp = np.cumsum([0] + [len(r) for r in S])
+    Si = np.array([k for r in S for k in r])
+    npts = len(S)
+    N = sp.csr_matrix(np.ones((npts, npts)))
+    is_c = np.zeros(npts, dtype=bool); is_c[0] = True
+    ptr, cols, capped = O.interp_pattern(Sp, Si, N, is_c, 3)
+    side = O.Side(is_c, np.nonzero(is_c)[0], ptr, cols, capped)
+    side.strength = (N, Sp, Si)
+    out = O.complete_c_set(side, 4, 4)
+    assert list(np.nonzero(out.is_c)[0]) == [0, 1, 2, 4]
+    # interpolatory sets rebuilt: C^i = S_i intersected with the new C-set
+    got = [list(out.fine_cols[out.ptr[i]:out.ptr[i + 1]]) for i in range(npts)]
+    assert got == [[0], [1], [2], [1, 2], [4], [0, 4]]
+    # a side that already has enough C-points is returned unchanged; a side with at most `need`
+    # points keeps all of them
+    assert O.complete_c_set(out, 4, 4) is out
+    small = O.complete_c_set(side, 6, 4)
+    assert small.is_c.all() and list(small.fine_cols) == list(range(npts))
+
+
+def test_completed_c_sets_only_where_a_coarsest_level_would_be_too_large():
+    # the Zipf term-document matrix at 4000 x 1000 with the configuration-3 parameters stops at a
+    # 211 x 238 coarsest level (449 unknowns); with coarse_dense_max below that, both sides of that
+    # level are completed to n_b + n_guard + n_t = 30 C-points and coarsening continues
+    wl = W.WORKLOADS["termdoc_200k_dom10"]
+    A = W.termdoc(4000, 1000).to_scipy()
+    sizes = {}
+    for cdm in (1024, 200):
+        prm = dict(wl["params"], n_mult=1, max_add=0, coarse_dense_max=cdm)
+        o = O.solve(A, "svd", "dominant", wl["n_b"], O.Params(**prm))
+        sizes[cdm] = [tuple(s) for s in o.report["sizes"]]
+    need = wl["n_b"] + wl["params"]["n_guard"] + wl["params"]["n_t"]
+    assert sizes[200][:len(sizes[1024])] == sizes[1024]
+    assert len(sizes[200]) == len(sizes[1024]) + 1
+    last, prev = sizes[200][-1], sizes[200][-2]
+    assert sum(prev) > 200 and last == (need, need)
