@@ -94,7 +94,8 @@ def cpu_baseline(name, A, wl, gpu_add_iters, budget_s=30.0):
     the 3-D anisotropic workload the oracle runs on the 24^3 grid of the same family (its
     multiplicative phase on 128^3 alone would take hours in pure-Python coarsening and colouring)
     and both parts are scaled by the unknown count (the cost of a cycle grows linearly with the
-    number of unknowns, §6.1)."""
+    number of unknowns, §6.1); for the term-document workload on the same generator at 4000 x 1000,
+    scaled by the nonzero count."""
     import numpy as np
     from oracle import slamg_oracle as O
     from paper_1102_0919_amd import workloads as W
@@ -111,6 +112,16 @@ def cpu_baseline(name, A, wl, gpu_add_iters, budget_s=30.0):
         scale = A.shape[0] / As.shape[0]
         what = f"the {k}^3 grid of the same family ({As.shape[0]} unknowns), scaled by {scale:.1f} (unknown count)"
         A = As
+    elif name == "termdoc_200k_dom10":
+        # the same generator at 4000 x 1000 (the oracle's pure-Python coarsening of the full matrix
+        # takes tens of minutes), scaled by the nonzero count
+        As = W.termdoc(4000, 1000, 60, seed=1102).to_scipy().tocsr()
+        As = As[As.getnnz(axis=1) > 0][:, As.getnnz(axis=0) > 0]
+        scale = A.nnz / As.nnz
+        what = (f"the same Zipf generator at {As.shape[0]} x {As.shape[1]} (empty rows removed, {As.nnz} "
+                f"nonzeros), scaled by {scale:.1f} (nonzero count)")
+        A = As
+    print(f"[bench] cpu baseline: oracle on {what}", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     s = O.Solver(A, wl["kind"], wl["target"], wl["n_b"], p)
     for c in range(1, p.n_mult + 1):

@@ -322,6 +322,21 @@ def test_full_aniso3d_128_min8_to_tolerance(ctx, precision):
     _sig_close(r.sigma, ref[:8], r.report.anorm)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed_fp32", "mixed_bf16"])
+def test_full_termdoc_200k_dom10_to_tolerance(ctx, precision):
+    # configuration 3 at full size: the Zipf(1.1) term-document matrix, 200 000 x 50 000, 3 M
+    # nonzeros, 10 dominant triplets.  The hierarchy ends with completed C-sets (R30) at 30 x 30;
+    # every precision converges to 1e-8 and its ten singular values equal ARPACK's to 1e-10
+    # relative (the dense reference of this size; the oracle is compared at reduced sizes)
+    import scipy.sparse.linalg as sla
+    A, wl, r, U, V = _full(ctx, "termdoc_200k_dom10", precision, max_add=1000)
+    assert r.converged
+    ref = sla.svds(A, k=12, tol=1e-13, return_singular_vectors=False)[::-1]
+    res = _props(A, r, U, V, "svd", ref)
+    assert res.max() <= 1e-8 * 1.0001
+    _sig_close(r.sigma, ref[:10], r.report.anorm)
+
+
 def test_full_gradient256_dom8_to_tolerance(ctx):
     # the bench configuration: run to 1e-8 (a few thousand additive iterations)
     ref = W.gradient2d_singular_values(256)[::-1][:12]
