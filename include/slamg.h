@@ -139,7 +139,7 @@ typedef struct {
   double prof_bytes[8];                      /*   summed algorithmic bytes of those launches    */
   int32_t graph_iters;                       /* additive iterations run as graph replays        */
   int32_t pad_;
-  int64_t device_bytes;                      /* device memory the solve allocated (all levels)  */
+  int64_t device_bytes;                      /* peak device memory the solve held (all levels)  */
   double t_queue_ms, t_latency_ms;           /* requests: submit -> start, submit -> result      */
 } slamg_report;
 

@@ -537,8 +537,8 @@ extern "C" slamg_status slamg_solve(slamg_ctx* ctx, const slamg_csr* A, slamg_ki
 // what else runs.
 // ------------------------------------------------------------------------------------------------
 
-// Upper bound of a solve's device memory: operators and hierarchy (A, A^t, strength operators,
-// Galerkin products, interpolation: <= 400 B per nonzero of A), vector blocks of all levels
+// Upper bound of a solve's device memory: operators and hierarchy (A, A^t, Galerkin products,
+// interpolation: <= 400 B per nonzero of A), the strength products' device chunk, vector blocks of all levels
 // (test, boot, ping-pong, residual and scratch blocks, FP64 and FP32), and the dense coarsest
 // level (<= 1024 unknowns; X, Y, factors, work, per-column eigenvector stores).
 static size_t footprint_estimate(int64_t m, int64_t n, int64_t nnz, slamg_kind kind, int32_t nb,
@@ -547,8 +547,10 @@ static size_t footprint_estimate(int64_t m, int64_t n, int64_t nnz, slamg_kind k
   const double nc = std::min(1024.0, kind == SLAMG_SVD ? (double)(m + n) : (double)m);
   const int32_t blk = nb + std::max(p.n_guard, 0);   // the block holds the guard pairs too
   const double w = (double)(4 * p.n_t + 12 * blk);
+  // SVD: the strength products' entries pass through the device in chunks of 2^25 (16 B each)
+  const double strength = kind == SLAMG_SVD ? 16.0 * std::min(33554432.0, 64.0 * (double)nnz) : 0.0;
   const double bytes = 64.0 * 1024 * 1024 + 400.0 * (double)nnz + 8.0 * rows * w * 2.0 +
-                       8.0 * (3.0 * blk + 10.0) * nc * nc;
+                       8.0 * (3.0 * blk + 10.0) * nc * nc + strength;
   return (size_t)bytes;
 }
 

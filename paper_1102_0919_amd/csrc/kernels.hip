@@ -858,8 +858,10 @@ static bool kacz_lds_optin() {
   return ok;
 }
 
-// every instantiation opts in on the first launch of any, which the multiplicative phase makes
-// eagerly, so that no attribute call falls inside a captured iteration
+// Every instantiation opts in on the first launch of any, which the multiplicative phase makes
+// eagerly, so that no attribute call falls inside a captured iteration.  Every launch, whatever its
+// LDS size, passes through this one-time initialisation first: solves on other host threads (the
+// serving loop) then never launch a kernel while its attributes are being set.
 template <typename T>
 static bool kacz_lds_optin_all() {
   static const bool ok = [] {
@@ -875,7 +877,8 @@ static bool kacz_lds_optin_all() {
 
 template <typename T, int SPLIT, bool BF>
 static bool kacz_lds_go(const KaczLdsPOD<T>& p, int w, size_t lds, hipStream_t s) {
-  if (lds > 65536 && !kacz_lds_optin_all<T>()) return false;
+  const bool optin = kacz_lds_optin_all<T>();
+  if (lds > 65536 && !optin) return false;
   hipLaunchKernelGGL((k_kacz_lds<T, SPLIT, BF>), dim3(w), dim3(KLB), lds, s, p);
   return true;
 }

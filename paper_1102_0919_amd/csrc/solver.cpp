@@ -64,15 +64,32 @@ class Arena {
       throw SolverError{ST_E_OOM, "hipMallocAsync failed"};
     }
     ptrs_.push_back(p);
+    sizes_.push_back(bytes);
     used_ += bytes;
+    peak_ = std::max(peak_, used_);
     return static_cast<T*>(p);
   }
+  // Returns one allocation before the solve ends (stream-ordered: work queued on the solve's
+  // stream that still reads it completes first); null is ignored.
+  void release(const void* p) {
+    if (!p) return;
+    for (size_t i = ptrs_.size(); i-- > 0;) {
+      if (ptrs_[i] != p) continue;
+      (void)hipFreeAsync(ptrs_[i], st_);
+      used_ -= sizes_[i];
+      ptrs_.erase(ptrs_.begin() + (long)i);
+      sizes_.erase(sizes_.begin() + (long)i);
+      return;
+    }
+  }
   size_t used() const { return used_; }
+  size_t peak() const { return peak_; }
 
  private:
-  size_t budget_, used_ = 0;
+  size_t budget_, used_ = 0, peak_ = 0;
   hipStream_t st_;
   std::vector<void*> ptrs_;
+  std::vector<size_t> sizes_;
 };
 
 template <class T>
@@ -812,6 +829,9 @@ void Solver::norm_estimate() {
 // ------------------------------------------------------------------------------------------------
 // Hierarchy structure (first multiplicative cycle only)
 // ------------------------------------------------------------------------------------------------
+// Entries of a strength product computed per device pass (16 bytes each while on the device).
+static const size_t STRENGTH_CHUNK = size_t(1) << 25;
+
 HCsr Solver::strength_operator(Level& L, bool u_side, bool finest) {
   // Eigenproblems (§5.2) and square coarsening (§5.1) measure strength on A itself; SVD otherwise
   // on A A^t (u) and A^t A (v) (§3.7).
@@ -852,18 +872,37 @@ HCsr Solver::strength_operator(Level& L, bool u_side, bool finest) {
     dAfT = L.At;
   }
   N = u_side ? symbolic_product(Af, AfT) : symbolic_product(AfT, Af);
-  // numeric on the device: entries are dot products of rows of A (u) or of A^t (v)
+  // numeric on the device: entries are dot products of rows of A (u) or of A^t (v), computed in
+  // chunks of at most STRENGTH_CHUNK entries so that the product's device arrays stay bounded
   std::vector<int> rowC(N.nnz());
   for (int i = 0; i < N.m; ++i)
     for (int k = N.rp[i]; k < N.rp[i + 1]; ++k) rowC[k] = i;
-  int* d_row = ar_.alloc<int>(rowC.size());
-  int* d_col = ar_.alloc<int>(N.nnz());
-  double* d_val = ar_.alloc<double>(N.nnz());
-  h2d(d_row, rowC, st_);
-  h2d(d_col, N.ci, st_);
+  const size_t total = (size_t)N.nnz(), chunk = std::min<size_t>(total, STRENGTH_CHUNK);
+  int* d_row = ar_.alloc<int>(chunk);
+  int* d_col = ar_.alloc<int>(chunk);
+  double* d_val = ar_.alloc<double>(chunk);
   const DCsr& M = u_side ? dAf : dAfT;
-  launch_spgemm_dot(N.nnz(), d_row, d_col, M.rp, M.ci, M.v, M.rp, M.ci, M.v, d_val, st_);
-  d2h(N.v, d_val, N.nnz(), st_);
+  N.v.resize(total);
+  for (size_t e0 = 0; e0 < total; e0 += chunk) {
+    const size_t cnt = std::min(chunk, total - e0);
+    HIPCHK(hipMemcpyAsync(d_row, rowC.data() + e0, cnt * sizeof(int), hipMemcpyHostToDevice, st_));
+    HIPCHK(hipMemcpyAsync(d_col, N.ci.data() + e0, cnt * sizeof(int), hipMemcpyHostToDevice, st_));
+    launch_spgemm_dot((int)cnt, d_row, d_col, M.rp, M.ci, M.v, M.rp, M.ci, M.v, d_val, st_);
+    HIPCHK(hipMemcpyAsync(N.v.data() + e0, d_val, cnt * sizeof(double), hipMemcpyDeviceToHost, st_));
+    HIPCHK(hipStreamSynchronize(st_));
+  }
+  // the product's entries are on the host now: its device arrays (and the filtered operator's)
+  // go back to the solve's budget
+  ar_.release(d_row);
+  ar_.release(d_col);
+  ar_.release(d_val);
+  if (filt) {
+    for (const DCsr* d : {&dAf, &dAfT}) {
+      ar_.release(d->rp);
+      ar_.release(d->ci);
+      ar_.release(d->v);
+    }
+  }
   return N;
 }
 
@@ -2004,7 +2043,7 @@ void Solver::run(const double* init_tests, SolveOutput& out) {
   auto t2 = clk::now();
   rep_.add_iters = it;
   rep_.converged = rmax <= p_.tol ? 1 : 0;
-  rep_.device_bytes = (int64_t)ar_.used();
+  rep_.device_bytes = (int64_t)ar_.peak();
   rep_.t_setup_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
   rep_.t_solve_ms = std::chrono::duration<double, std::milli>(t2 - t1).count();
   for (int j = 0; j < nw_ && j < 16; ++j) {

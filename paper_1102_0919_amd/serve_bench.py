@@ -25,6 +25,8 @@ def _build(api, W, req, max_add):
     A, kind = W.serving_matrix(req)
     # verbose: each solve reports its progress every 50 additive iterations on stderr
     prm = dict(W.FAMILY_PARAMS[(req["family"], req["target"])], max_add=max_add, verbose=50)
+    # the block holds at most 16 pairs: guard pairs fill what n_b leaves
+    prm["n_guard"] = max(0, min(prm.get("n_guard", 0), 16 - req["n_b"]))
     return A.to_scipy(), kind, api.params_init(kind, req["target"], **prm)
 
 
