@@ -119,6 +119,14 @@ typedef struct {
                                C-points (Algorithm 1's initial measure, lowest index on ties)
                                and coarsening continues.  1 .. 1024, the largest coarsest level
                                the dense coarsest solves take (1024)                            */
+  int32_t redo_p;           /* redetermined interpolation in the additive phase (§6.3): a pair
+                               counts as converged once its sigma changes by at most redo_tol
+                               relative between two iterations; whenever that set grows while a
+                               pair of the block is not converged, one downward sweep of the
+                               multiplicative phase refits P, Q and the coarse operators, the LS
+                               weights of the test vectors and of the converged pairs multiplied
+                               by 1e-3; the iterates are kept (0)                               */
+  double redo_tol;          /* relative change of sigma that counts as converged (1e-14)         */
 } slamg_params;
 
 /* Report of one solve.  Arrays are filled up to the counts given. */
@@ -138,7 +146,7 @@ typedef struct {
   int64_t prof_launches[8];                  /*   number of launches                            */
   double prof_bytes[8];                      /*   summed algorithmic bytes of those launches    */
   int32_t graph_iters;                       /* additive iterations run as graph replays        */
-  int32_t pad_;
+  int32_t redo_count;                        /* redetermined interpolations (redo_p)            */
   int64_t device_bytes;                      /* peak device memory the solve held (all levels)  */
   double t_queue_ms, t_latency_ms;           /* requests: submit -> start, submit -> result      */
 } slamg_report;

@@ -61,6 +61,14 @@ the design notes of the repository):
       influence the most points (lowest index on ties) become C-points until it has n_b + n_t
       (a side with at most n_b + n_t points keeps them all), the interpolatory sets follow, and
       coarsening continues.
+  R33 redetermined interpolation (§6.3, optional): in the additive phase a pair counts as converged
+      once its Ritz value changes by at most ``redo_tol`` (1e-14) relative from one iteration to
+      the next (the observable stand-in for the relative error the paper plots).  Whenever that
+      set grows while some pair of the block is not converged, one downward sweep of the
+      multiplicative phase refits P (and Q) and the coarse operators: the test vectors, and copies
+      of the current iterates, are relaxed (mu_t; mu_b with Rayleigh quotients) and injected as in
+      a cycle, and the LS weights of the test vectors and of the converged pairs are multiplied by
+      1e-3.  The iterates themselves are not changed.
 """
 from __future__ import annotations
 
@@ -107,6 +115,11 @@ class Params:
     mu_tJ: int = 1                # inner weighted-Jacobi steps of a test relaxation (§3.4)
     mu_bJ: int = 1                # inner weighted-Jacobi steps of a boot relaxation (§3.5)
     coarse_dense_max: int = 1024  # R30: largest level (unknowns) a coarsening may stop at
+    redo_p: int = 0               # R33: redetermine P, Q in the additive phase (§6.3)
+    redo_tol: float = 1e-14       # R33: relative change of a Ritz value that counts as converged
+
+
+REDO_DOWN = 1e-3                  # §6.3: LS weight factor of test vectors and converged pairs
 
 
 NORM_SEED_XOR = 0xA5A5A5A5A5A5A5A5
@@ -783,7 +796,7 @@ class Solver:
         self.anorm = norm_estimate(A, params.seed)
         self.sig = None; self.Ub = None; self.Vb = None
         self.report = dict(levels=0, sizes=[], mult_sigma=[], add_sigma=[], rho=[], capped=[],
-                           colours=[], mult_cycles=0, add_iters=0, anorm=self.anorm)
+                           colours=[], mult_cycles=0, add_iters=0, anorm=self.anorm, redo=[])
 
     # -------------------------------------------------------------- multiplicative cycle (§3.3)
     def mult_cycle(self, c):
@@ -947,6 +960,39 @@ class Solver:
             us[l], vs[l] = relax(l, U, V, kaps[l], taus[l])
         self.Ub, self.Vb = us[0], vs[0]
 
+    # -------------------------------------------------------------- redetermined P (§6.3, R33)
+    def redo_interpolation(self, conv):
+        """One downward sweep of the multiplicative phase during the additive phase: P, Q and the
+        coarse operators are refitted, with the LS weights of the test vectors and of the pairs
+        marked in ``conv`` multiplied by REDO_DOWN.  The additive iterates are not changed."""
+        kind, target, p = self.kind, self.target, self.p
+        Ut, Vt = self.Ut, self.Vt
+        Ub = self.Ub.copy()
+        Vb = None if self.Vb is None else self.Vb.copy()
+        sig = self.sig.copy()
+        scale = np.concatenate([np.full(p.n_t, REDO_DOWN), np.where(conv, REDO_DOWN, 1.0)])
+        for l in range(len(self.levels) - 1):
+            lev = self.levels[l]
+            for _ in range(p.mu_t):
+                if target == DOMINANT:
+                    Ut, Vt = relax_test_dominant(lev, kind, Ut, Vt, p.omega, p.mu_tJ)
+                else:
+                    Ut, Vt = relax_test_minimal(lev, kind, Ut, Vt)
+            if l == 0:
+                self.Ut, self.Vt = Ut, Vt
+            Ub, Vb, sig = relax_boot_with_rq(lev, kind, target, Ub, Vb, sig, p)
+            Uf = np.hstack([Ut, Ub]); Vf = None if kind == SPD else np.hstack([Vt, Vb])
+            w = ls_weights(lev, kind, target, Uf, Vf, self.anorm) * scale
+            self._fit(lev, lev.su, Uf, w, True)
+            if kind == SVD:
+                self._fit(lev, lev.sv, Vf, w, False)
+            coarse = galerkin(lev, kind)
+            old = self.levels[l + 1]
+            old.A, old.B, old.C = coarse.A, coarse.B, coarse.C
+            Ut = Ut[lev.su.cpts]; Ub = Ub[lev.su.cpts]
+            if kind == SVD:
+                Vt = Vt[lev.sv.cpts]; Vb = Vb[lev.sv.cpts]
+
     # -------------------------------------------------------------- driver (§3.3, §4)
     def run(self):
         p, A0 = self.p, self.levels[0].A
@@ -959,6 +1005,8 @@ class Solver:
         self.report["rho"].append(rho)
         it = 0
         nw = self.n_want
+        conv = np.zeros(self.n_b, dtype=bool)
+        prev = self.sig.copy()
         while rho[:nw].max() > p.tol and it < p.max_add:
             self.additive_vcycle()
             self.sig, self.Ub, self.Vb = self._ritz(self.Ub, self.Vb)
@@ -966,6 +1014,13 @@ class Solver:
             it += 1
             self.report["rho"].append(rho)
             self.report["add_sigma"].append(self.sig.copy())
+            if p.redo_p:
+                now = np.abs(self.sig - prev) <= p.redo_tol * np.abs(self.sig)
+                prev = self.sig.copy()
+                if (now & ~conv).any() and not now.all() and rho[:nw].max() > p.tol:
+                    conv |= now
+                    self.redo_interpolation(conv.copy())
+                    self.report["redo"].append(it)
         self.report["add_iters"] = it
         self.report["converged"] = bool(rho[:nw].max() <= p.tol)
         return self.sig[:nw], self.Ub[:, :nw], None if self.Vb is None else self.Vb[:, :nw]

@@ -34,7 +34,8 @@ class Params(C.Structure):
                 ("ritz_in_mult", C.c_int32), ("coarse_pinv", C.c_int32), ("profile_mask", C.c_int32),
                 ("verbose", C.c_int32), ("graphs", C.c_int32), ("square_coarsening", C.c_int32),
                 ("n_guard", C.c_int32), ("mu_tJ", C.c_int32), ("mu_bJ", C.c_int32),
-                ("kaczmarz_order", C.c_int32), ("coarse_dense_max", C.c_int32)]
+                ("kaczmarz_order", C.c_int32), ("coarse_dense_max", C.c_int32),
+                ("redo_p", C.c_int32), ("redo_tol", C.c_double)]
 
 
 class Report(C.Structure):
@@ -44,7 +45,7 @@ class Report(C.Structure):
                 ("anorm", C.c_double), ("resid", C.c_double * 16), ("rho_history", C.c_double * 256),
                 ("mult_sigma", (C.c_double * 16) * 32), ("t_setup_ms", C.c_double), ("t_solve_ms", C.c_double),
                 ("err_bound", C.c_double * 16), ("prof_ms", C.c_double * 8), ("prof_launches", C.c_int64 * 8),
-                ("prof_bytes", C.c_double * 8), ("graph_iters", C.c_int32), ("pad_", C.c_int32),
+                ("prof_bytes", C.c_double * 8), ("graph_iters", C.c_int32), ("redo_count", C.c_int32),
                 ("device_bytes", C.c_int64), ("t_queue_ms", C.c_double), ("t_latency_ms", C.c_double)]
 
 

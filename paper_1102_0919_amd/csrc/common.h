@@ -201,8 +201,9 @@ void launch_csr_to_dense(int m, const int* rp, const int* ci, const double* v, d
 void launch_ls_fit(int nF, const int* Fpts, const int* prp, const int* fine_cols, int w1,
                    const double* U1, int w2, const double* U2, const double* B1, const double* B2,
                    const double* wts, double* pval, int qmax, hipStream_t s);
+// LS weights of the fitted pairs (R19), each multiplied by scale[c] when scale is given
 void launch_rq_weights(int nf, const double* num, const double* nu, const double* nv, int minimal,
-                       double floor_abs, double* w, hipStream_t s);
+                       double floor_abs, const double* scale, double* w, hipStream_t s);
 
 // dense.hip (single-workgroup dense FP64 procedures)
 void launch_chol_inv_upper(int w, const double* G, double* T, int* status, hipStream_t s);

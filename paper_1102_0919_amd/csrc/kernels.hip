@@ -1279,16 +1279,16 @@ void launch_rq_update(int w, const double* num, const double* nu, const double* 
 
 // LS weights from Rayleigh quotients: |rq| (dominant) or 1 / max(|rq|, floor) (minimal)
 __global__ void k_rq_weights(int nf, const double* num, const double* nu, const double* nv, int minimal,
-                             double floor_abs, double* w) {
+                             double floor_abs, const double* scale, double* w) {
   int c = threadIdx.x;
   if (c >= nf) return;
   double q = nv ? num[c] / sqrt(nu[c] * nv[c]) : num[c] / nu[c];
   q = fabs(q);
-  w[c] = minimal ? 1.0 / fmax(q, floor_abs) : q;
+  w[c] = (minimal ? 1.0 / fmax(q, floor_abs) : q) * (scale ? scale[c] : 1.0);
 }
 void launch_rq_weights(int nf, const double* num, const double* nu, const double* nv, int minimal,
-                       double floor_abs, double* w, hipStream_t s) {
-  hipLaunchKernelGGL(k_rq_weights, dim3(1), dim3(64), 0, s, nf, num, nu, nv, minimal, floor_abs, w);
+                       double floor_abs, const double* scale, double* w, hipStream_t s) {
+  hipLaunchKernelGGL(k_rq_weights, dim3(1), dim3(64), 0, s, nf, num, nu, nv, minimal, floor_abs, scale, w);
 }
 
 template <typename T>

@@ -234,6 +234,9 @@ class Solver {
   void relax_tests(int l);
   void boot_relax_rq(int l);
   void fit_interpolation(int l, int cycle);
+  void redo_interpolation(const std::vector<char>& conv);
+  void coarse_setup();
+  void cast_transfers();
   void galerkin(int l);
   void inject(int l, int cycle);
   void coarsest_mult();
@@ -303,6 +306,11 @@ class Solver {
   int NL_ = 0;
   double* pbasis_ = nullptr;   // eigenvectors of X - sigma_j Y from the previous coarsest solve
   long pinv_calls_ = 0;
+  // redetermined interpolation (§6.3): LS weight factors of the refit, the kept iterate
+  double* wscale_ = nullptr;
+  bool redo_weights_ = false;
+  double* redo_keep_ = nullptr;
+  double* pencil_wk_ = nullptr;
   double *dX_ = nullptr, *dY_ = nullptr, *dwork_ = nullptr, *dA_ = nullptr, *dB_ = nullptr, *dC_ = nullptr;
   double *mu_ = nullptr, *Zp_ = nullptr;
   bool pencil_ready_ = false;
@@ -1481,7 +1489,8 @@ void Solver::fit_interpolation(int l, int cycle) {
   };
   rq_parts(b.Ut, b.Vt, nt_, 0);
   if (boots) rq_parts(b.Ub, b.Vb, nb_, nt_);
-  launch_rq_weights(nf, r1_, r2_, spd_ ? nullptr : r3_, minimal_ ? 1 : 0, 1e-12 * anorm_, wts_, st_);
+  launch_rq_weights(nf, r1_, r2_, spd_ ? nullptr : r3_, minimal_ ? 1 : 0, 1e-12 * anorm_,
+                    redo_weights_ ? wscale_ : nullptr, wts_, st_);
   // values fitted at the F-points: the vectors themselves, or (minimal) one Jacobi step on N z = 0
   auto smooth = [&](bool u_side, const double* X, int w, double* tmp, double* out) {
     RowOpArgs<double> a;
@@ -1931,6 +1940,72 @@ void Solver::check_status() {
   if (st[0] != 0) throw SolverError{ST_E_NUMERIC, "dense factorisation breakdown on the device"};
 }
 
+// The additive phase's coarsest-level structures: dense X, Y (and the pencil eigenbasis).
+void Solver::coarse_setup() {
+  dense_coarsest(dX_, dY_);
+  pinv_calls_ = 0;
+  if (p_.coarse_pinv == 1) {
+    double* Xc = dwork_;
+    double* Yc = dwork_ + (size_t)NL_ * NL_;
+    HIPCHK(hipMemcpyAsync(Xc, dX_, sizeof(double) * NL_ * NL_, hipMemcpyDeviceToDevice, st_));
+    HIPCHK(hipMemcpyAsync(Yc, dY_, sizeof(double) * NL_ * NL_, hipMemcpyDeviceToDevice, st_));
+    if (!pencil_wk_) pencil_wk_ = ar_.alloc<double>((size_t)2 * NL_ * NL_);
+    launch_pencil_setup(NL_, Xc, Yc, mu_, Zp_, pencil_wk_, status_, st_);
+  }
+}
+
+// FP32 copies of the transfer operators' values (mixed precision)
+void Solver::cast_transfers() {
+  for (auto& L : lv_) {
+    cast_vals(L->su.P);
+    cast_vals(L->su.Pt);
+    if (!spd_) {
+      cast_vals(L->sv.P);
+      cast_vals(L->sv.Pt);
+    }
+  }
+}
+
+// Redetermined interpolation during the additive phase (§6.3): one downward sweep of the
+// multiplicative phase (test and boot relaxations, LS fits, Galerkin products, injection) refits
+// P, Q and the coarse operators, with the LS weights of the test vectors and of the pairs marked in
+// conv multiplied by 1e-3.  The sweep relaxes a copy of the iterate: the finest boot block and
+// sigma are restored afterwards.
+void Solver::redo_interpolation(const std::vector<char>& conv) {
+  Level& F = *lv_[0];
+  const size_t nu = (size_t)rows_u(F) * nb_, nv = spd_ ? 0 : (size_t)rows_v(F) * nb_;
+  if (!redo_keep_) {
+    redo_keep_ = ar_.alloc<double>(nu + nv + 64);
+    wscale_ = ar_.alloc<double>(64);
+  }
+  double* kU = redo_keep_;
+  double* kV = redo_keep_ + nu;
+  double* kS = redo_keep_ + nu + nv;
+  HIPCHK(hipMemcpyAsync(kU, F.bd.Ub, nu * sizeof(double), hipMemcpyDeviceToDevice, st_));
+  if (nv) HIPCHK(hipMemcpyAsync(kV, F.bd.Vb, nv * sizeof(double), hipMemcpyDeviceToDevice, st_));
+  HIPCHK(hipMemcpyAsync(kS, sig_, nb_ * sizeof(double), hipMemcpyDeviceToDevice, st_));
+  std::vector<double> sc(nt_ + nb_, 1.0);
+  for (int i = 0; i < nt_; ++i) sc[i] = 1e-3;
+  for (int j = 0; j < nb_; ++j)
+    if (conv[j]) sc[nt_ + j] = 1e-3;
+  h2d(wscale_, sc, st_);
+  redo_weights_ = true;
+  for (int l = 0; l + 1 < (int)lv_.size(); ++l) {
+    relax_tests(l);
+    boot_relax_rq(l);
+    fit_interpolation(l, 2);
+    galerkin(l);
+    inject(l, 2);
+  }
+  redo_weights_ = false;
+  HIPCHK(hipMemcpyAsync(F.bd.Ub, kU, nu * sizeof(double), hipMemcpyDeviceToDevice, st_));
+  if (nv) HIPCHK(hipMemcpyAsync(F.bd.Vb, kV, nv * sizeof(double), hipMemcpyDeviceToDevice, st_));
+  HIPCHK(hipMemcpyAsync(sig_, kS, nb_ * sizeof(double), hipMemcpyDeviceToDevice, st_));
+  coarse_setup();
+  if (mixed_) cast_transfers();
+  check_status();
+}
+
 // ------------------------------------------------------------------------------------------------
 void Solver::run(const double* init_tests, SolveOutput& out) {
   using clk = std::chrono::steady_clock;
@@ -1991,35 +2066,23 @@ void Solver::run(const double* init_tests, SolveOutput& out) {
   double rmax = *std::max_element(rho.begin(), rho.begin() + nw_);
   rep_.rho_history[0] = rmax;
   auto t1 = clk::now();
-  // additive phase: frozen operators (dense coarsest matrices built once)
-  dense_coarsest(dX_, dY_);
-  pinv_calls_ = 0;
-  if (p_.coarse_pinv == 1) {
-    double* Xc = dwork_;
-    double* Yc = dwork_ + (size_t)NL_ * NL_;
-    HIPCHK(hipMemcpyAsync(Xc, dX_, sizeof(double) * NL_ * NL_, hipMemcpyDeviceToDevice, st_));
-    HIPCHK(hipMemcpyAsync(Yc, dY_, sizeof(double) * NL_ * NL_, hipMemcpyDeviceToDevice, st_));
-    double* wk = ar_.alloc<double>((size_t)2 * NL_ * NL_);
-    launch_pencil_setup(NL_, Xc, Yc, mu_, Zp_, wk, status_, st_);
-  }
-  if (mixed_) {
-    for (auto& L : lv_) {
-      cast_vals(L->su.P);
-      cast_vals(L->su.Pt);
-      if (!spd_) {
-        cast_vals(L->sv.P);
-        cast_vals(L->sv.Pt);
-      }
-    }
-  }
+  // additive phase: frozen operators (dense coarsest matrices built once, and again after a
+  // redetermined interpolation)
+  coarse_setup();
+  if (mixed_) cast_transfers();
   for (auto& Lp : lv_) long_rows(*Lp);   // before any capture
-  int it = 0;
+  int it = 0, it0 = 0;
   graph_off_ = !p_.graphs;
+  // redetermined interpolation (§6.3): pairs whose sigma has settled, and the previous sigma
+  std::vector<char> conv(nb_, 0);
+  std::vector<double> sprev, snow;
+  if (p_.redo_p) d2h(sprev, sig_, nb_, st_);
   while (rmax > p_.tol && it < p_.max_add) {
-    // every 32nd iteration runs eagerly: the literal coarsest solve re-orthonormalises its
-    // eigenvector basis there (starts cold in iteration 0), and the profiled kernel classes are
-    // timed there; the other iterations replay the graph (captured with the plain warm start)
-    const bool eager = (it % 32) == 0;
+    // every 32nd iteration (counted from the additive phase's start or its last redetermined
+    // interpolation) runs eagerly: the literal coarsest solve re-orthonormalises its eigenvector
+    // basis there (starts cold in the first), and the profiled kernel classes are timed there; the
+    // other iterations replay the graph (captured with the plain warm start)
+    const bool eager = ((it - it0) % 32) == 0;
     if (!eager && !graph_off_ && !igx_) capture_iteration();
     const bool replay = !eager && igx_ != nullptr;
     if (replay) {
@@ -2033,6 +2096,29 @@ void Solver::run(const double* init_tests, SolveOutput& out) {
     rmax = *std::max_element(rho.begin(), rho.begin() + nw_);
     ++it;
     if (it < 256) rep_.rho_history[it] = rmax;
+    if (p_.redo_p) {
+      d2h(snow, sig_, nb_, st_);
+      bool grew = false, all = true;
+      for (int j = 0; j < nb_; ++j) {
+        const bool now = std::fabs(snow[j] - sprev[j]) <= p_.redo_tol * std::fabs(snow[j]);
+        all = all && now;
+        grew = grew || (now && !conv[j]);
+      }
+      if (grew && !all && rmax > p_.tol) {
+        for (int j = 0; j < nb_; ++j)
+          if (std::fabs(snow[j] - sprev[j]) <= p_.redo_tol * std::fabs(snow[j])) conv[j] = 1;
+        redo_interpolation(conv);
+        ++rep_.redo_count;
+        // the captured iteration used the old coarsest solve: capture again, cold start first
+        if (igx_) (void)hipGraphExecDestroy(igx_);
+        if (ig_) (void)hipGraphDestroy(ig_);
+        igx_ = nullptr;
+        ig_ = nullptr;
+        pinv_calls_ = 0;
+        it0 = it;
+      }
+      sprev = snow;
+    }
     if (p_.verbose > 0 && it % p_.verbose == 0) {
       std::fprintf(stderr, "[slamg] additive iteration %d: max relative residual %.3e, %.1f ms\n", it, rmax,
                    std::chrono::duration<double, std::milli>(clk::now() - t1).count());

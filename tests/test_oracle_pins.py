@@ -745,3 +745,51 @@ def test_completed_c_sets_only_where_a_coarsest_level_would_be_too_large():
     assert len(sizes[200]) == len(sizes[1024]) + 1
     last, prev = sizes[200][-1], sizes[200][-2]
     assert sum(prev) > 200 and last == (need, need)
+
+
+def test_redo_interpolation_weight_factors_and_kept_iterates():
+    # R33 (§6.3): with every pair converged the refit multiplies all LS weights by the same factor,
+    # which leaves the weighted least-squares solution (and R12's trace-scaled regularisation)
+    # unchanged: P and Q equal those of a refit with unit factors.  With no pair converged only
+    # the test vectors are down-weighted and P changes.  The additive iterates are never changed.
+    import copy
+    A = W.gradient2d(12).to_scipy()
+    prm = dict(theta=0.05, n_t=8, mu_t=2, mu_b=2, n_mult=3, max_add=0)
+    s0 = O.Solver(A, "svd", "dominant", 4, O.Params(**prm))
+    for c in range(1, 4):
+        s0.mult_cycle(c)
+
+    def refit(conv, down):
+        s = copy.deepcopy(s0)
+        keep = O.REDO_DOWN
+        O.REDO_DOWN = down
+        try:
+            s.redo_interpolation(np.array(conv, dtype=bool))
+        finally:
+            O.REDO_DOWN = keep
+        return s
+
+    a, b, c = refit([True] * 4, 1e-3), refit([True] * 4, 1.0), refit([False] * 4, 1e-3)
+    assert len(a.levels) >= 3
+    changed = False
+    for la, lb, lc in zip(a.levels[:-1], b.levels[:-1], c.levels[:-1]):
+        for side in ("su", "sv"):
+            pa, pb, pc = (getattr(x, side).P.toarray() for x in (la, lb, lc))
+            assert np.allclose(pa, pb, rtol=1e-8, atol=1e-11)
+            changed = changed or not np.allclose(pa, pc, rtol=1e-6, atol=1e-9)
+    assert changed
+    for s in (a, b, c):
+        np.testing.assert_array_equal(s.Ub, s0.Ub)
+        np.testing.assert_array_equal(s.Vb, s0.Vb)
+        np.testing.assert_array_equal(s.sig, s0.sig)
+
+
+def test_redo_interpolation_end_to_end_closed_form():
+    # with redetermined interpolation the solve still reaches the closed-form singular values
+    # (gradient of the 16 x 16 grid, 4 dominant triplets), and the redo sweeps happen
+    A = W.gradient2d(16).to_scipy()
+    prm = dict(W.WORKLOADS["gradient2d_256_dom8"]["params"], max_add=400, redo_p=1)
+    o = O.solve(A, "svd", "dominant", 4, O.Params(**prm))
+    assert o.report["converged"] and len(o.report["redo"]) >= 1
+    ref = W.gradient2d_singular_values(16)[::-1][:4]
+    assert np.allclose(o.sigma, ref, rtol=1e-10)
