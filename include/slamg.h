@@ -127,6 +127,10 @@ typedef struct {
                                weights of the test vectors and of the converged pairs multiplied
                                by 1e-3; the iterates are kept (0)                               */
   double redo_tol;          /* relative change of sigma that counts as converged (1e-14)         */
+  int32_t cycle_gamma;      /* additive cycle (§3.3): 1 V-cycle, 2 W-cycle (every level but the
+                               last one above the coarsest visits its coarser level twice, the
+                               second visit from the first one's correction) (1)                */
+  int32_t reserved2;
 } slamg_params;
 
 /* Report of one solve.  Arrays are filled up to the counts given. */

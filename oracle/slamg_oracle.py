@@ -69,6 +69,10 @@ the design notes of the repository):
       of the current iterates, are relaxed (mu_t; mu_b with Rayleigh quotients) and injected as in
       a cycle, and the LS weights of the test vectors and of the converged pairs are multiplied by
       1e-3.  The iterates themselves are not changed.
+  R34 W-cycles (§3.3, optional): with cycle_gamma 2 every level of the additive cycle but the
+      last one above the coarsest visits its next coarser level twice per visit of its own (the
+      second visit starts from the first one's correction, with the same restricted residual);
+      the last one above the coarsest solves the coarsest level once per visit.
 """
 from __future__ import annotations
 
@@ -117,6 +121,7 @@ class Params:
     coarse_dense_max: int = 1024  # R30: largest level (unknowns) a coarsening may stop at
     redo_p: int = 0               # R33: redetermine P, Q in the additive phase (§6.3)
     redo_tol: float = 1e-14       # R33: relative change of a Ritz value that counts as converged
+    cycle_gamma: int = 1          # R34: coarse visits per level in the additive cycle (1 V, 2 W)
 
 
 REDO_DOWN = 1e-3                  # §6.3: LS weight factor of test vectors and converged pairs
@@ -910,17 +915,18 @@ class Solver:
                                       square=self.kind == SVD and bool(self.p.square_coarsening))
         side.P = ls_interpolation(side.ptr, side.fine_cols, side.is_c, Vals, bvals, w)
 
-    # -------------------------------------------------------------- additive V-cycle (§4.1-4.2)
+    # -------------------------------------------------------------- additive cycle (§4.1-4.2)
     def additive_vcycle(self):
+        """One additive cycle for all n_b columns with sigma fixed: a V-cycle (cycle_gamma 1) or,
+        with cycle_gamma 2, a W-cycle (§3.3, R34): every level above the last one before the
+        coarsest visits its coarse level twice, the second visit starting from the first one's
+        correction; the coarsest level is solved once per visit of the level above it."""
         kind, target, p, sig = self.kind, self.target, self.p, self.sig
         L = len(self.levels) - 1
         if L == 0:
             # one level: the multiplicative phase's coarsest generalized SVD is already exact and
             # there is no coarse correction to add
             return
-        us, vs = [self.Ub], [self.Vb]
-        kaps = [np.zeros_like(self.Ub)]
-        taus = [None if kind == SPD else np.zeros_like(self.Vb)]
 
         def relax(l, U, V, kap, tau):
             lev = self.levels[l]
@@ -931,34 +937,42 @@ class Solver:
                     U, V = relax_boot_minimal(lev, kind, U, V, sig, kap, tau)
             return U, V
 
-        for l in range(L):
-            lev = self.levels[l]
-            U, V = relax(l, us[l], vs[l], kaps[l], taus[l])
-            us[l], vs[l] = U, V
+        def coarsest(kap, tau):
+            X, Y = pencil_matrices(self.levels[L], kind)
+            rhs = kap if kind == SPD else np.vstack([kap, tau])
+            z = (coarse_pinv_solve if p.coarse_pinv == 0 else coarse_pencil_solve)(X, Y, sig, rhs)
+            self.report["coarse_solves"] = self.report.get("coarse_solves", 0) + 1
             if kind == SPD:
-                r = kaps[l] - (lev.A @ U - (lev.B @ U) * sig[None, :])
-                kaps.append(lev.su.P.T @ r); taus.append(None)
-                us.append(np.zeros((lev.su.cpts.size, self.n_b))); vs.append(None)
-            else:
-                r = kaps[l] - (lev.A @ V - (lev.B @ U) * sig[None, :])
-                s = taus[l] - (lev.A.T @ U - (lev.C @ V) * sig[None, :])
-                kaps.append(lev.su.P.T @ r); taus.append(lev.sv.P.T @ s)
-                us.append(np.zeros((lev.su.cpts.size, self.n_b)))
-                vs.append(np.zeros((lev.sv.cpts.size, self.n_b)))
-        X, Y = pencil_matrices(self.levels[L], kind)
-        rhs = kaps[L] if kind == SPD else np.vstack([kaps[L], taus[L]])
-        z = (coarse_pinv_solve if p.coarse_pinv == 0 else coarse_pencil_solve)(X, Y, sig, rhs)
-        if kind == SPD:
-            us[L] = z
-        else:
+                return z, None
             mL = self.levels[L].A.shape[0]
-            us[L], vs[L] = z[:mL], z[mL:]
-        for l in range(L - 1, -1, -1):
+            return z[:mL], z[mL:]
+
+        def cycle(l, U, V, kap, tau):
             lev = self.levels[l]
-            U = us[l] + lev.su.P @ us[l + 1]
-            V = None if kind == SPD else vs[l] + lev.sv.P @ vs[l + 1]
-            us[l], vs[l] = relax(l, U, V, kaps[l], taus[l])
-        self.Ub, self.Vb = us[0], vs[0]
+            U, V = relax(l, U, V, kap, tau)
+            # residuals (4.1) and restriction (4.2)
+            if kind == SPD:
+                r = kap - (lev.A @ U - (lev.B @ U) * sig[None, :])
+                kc, tc = lev.su.P.T @ r, None
+            else:
+                r = kap - (lev.A @ V - (lev.B @ U) * sig[None, :])
+                t = tau - (lev.A.T @ U - (lev.C @ V) * sig[None, :])
+                kc, tc = lev.su.P.T @ r, lev.sv.P.T @ t
+            if l + 1 == L:
+                Uc, Vc = coarsest(kc, tc)
+            else:
+                Uc = np.zeros((lev.su.cpts.size, self.n_b))
+                Vc = None if kind == SPD else np.zeros((lev.sv.cpts.size, self.n_b))
+                for _ in range(p.cycle_gamma):
+                    Uc, Vc = cycle(l + 1, Uc, Vc, kc, tc)
+            # correction (4.3) and post-relaxation
+            U = U + lev.su.P @ Uc
+            V = None if kind == SPD else V + lev.sv.P @ Vc
+            return relax(l, U, V, kap, tau)
+
+        kap0 = np.zeros_like(self.Ub)
+        tau0 = None if kind == SPD else np.zeros_like(self.Vb)
+        self.Ub, self.Vb = cycle(0, self.Ub, self.Vb, kap0, tau0)
 
     # -------------------------------------------------------------- redetermined P (§6.3, R33)
     def redo_interpolation(self, conv):

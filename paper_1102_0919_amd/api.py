@@ -44,7 +44,7 @@ def params_init(kind: str = "svd", target: str = "dominant", **overrides) -> L.P
             v = L.PRECISION[v]
         if k == "omega":
             k = "omega_J"
-        if k not in names or k == "reserved":
+        if k not in names or k.startswith("reserved"):
             raise TypeError(f"params_init: unknown parameter {k!r}")
         setattr(p, k, v)
     return p

@@ -235,6 +235,9 @@ class Solver {
   void boot_relax_rq(int l);
   void fit_interpolation(int l, int cycle);
   void redo_interpolation(const std::vector<char>& conv);
+  template <class T> void cycle_level(int l, const double* sig, T* rhsU, T* rhsV, bool zero_iterate);
+  template <class T> void coarsest_additive(const double* sig);
+  long coarse_calls_per_iter() const;
   void coarse_setup();
   void cast_transfers();
   void galerkin(int l);
@@ -306,6 +309,7 @@ class Solver {
   int NL_ = 0;
   double* pbasis_ = nullptr;   // eigenvectors of X - sigma_j Y from the previous coarsest solve
   long pinv_calls_ = 0;
+  bool pinv_reortho_ = false;    // the next literal coarsest solve re-orthonormalises its basis
   // redetermined interpolation (§6.3): LS weight factors of the refit, the kept iterate
   double* wscale_ = nullptr;
   bool redo_weights_ = false;
@@ -1659,16 +1663,26 @@ void Solver::additive_vcycle(const double* sig, T* rhsU, T* rhsV) {
   // a single level is solved exactly by the coarsest generalized SVD of the multiplicative phase;
   // there is no coarse correction to add
   if (nl < 2) return;
+  cycle_level<T>(0, sig, rhsU, rhsV, false);
+}
+
+// One visit of level l (above the coarsest) in the additive cycle: pre-relaxation, residual and
+// restriction, the coarse correction (the coarsest solve, or p_.cycle_gamma visits of level l + 1:
+// 1 a V-cycle, 2 a W-cycle), prolongation and post-relaxation.  zero_iterate: level l's correction is
+// zero on entry (first visit of a coarse level).
+template <class T>
+void Solver::cycle_level(int l, const double* sig, T* rhsU, T* rhsV, bool zero_iterate) {
+  const int nl = (int)lv_.size();
   const bool zero_start_ok = !minimal_ && p_.mu_b > 0;
-  for (int l = 0; l + 1 < nl; ++l) {
-    Level& L = *lv_[l];
-    Level& C = *lv_[l + 1];
-    Blocks<T>& b = blocks<T>(L);
-    Blocks<T>& cb = blocks<T>(C);
-    const T* kap = l == 0 ? rhsU : b.kap;
-    const T* tau = l == 0 ? rhsV : b.tau;
-    boot_relax<T>(l, kap, tau, sig, p_.mu_b, l > 0 && zero_start_ok);
-    // residuals r = kappa - (A v - sigma B u), s = tau - (A^t u - sigma C v), then restriction
+  Level& L = *lv_[l];
+  Level& C = *lv_[l + 1];
+  Blocks<T>& b = blocks<T>(L);
+  Blocks<T>& cb = blocks<T>(C);
+  const T* kap = l == 0 ? rhsU : b.kap;
+  const T* tau = l == 0 ? rhsV : b.tau;
+  boot_relax<T>(l, kap, tau, sig, p_.mu_b, zero_iterate && zero_start_ok);
+  // residuals r = kappa - (A v - sigma B u), s = tau - (A^t u - sigma C v), then restriction
+  {
     const int mu = rows_u(L), mv = rows_v(L);
     RowOpArgs<T> a;
     a.nrows = mu; a.w = nb_; a.Krp = L.A.rp; a.Kci = L.A.ci; a.nnzK = L.A.nnz; a.Kv = vals<T>(L.A);
@@ -1688,51 +1702,53 @@ void Solver::additive_vcycle(const double* sig, T* rhsU, T* rhsV) {
       rowop2(l, a, &L.A, s, &L.At, 7);
       spmm2<T>(l, L.su.Pt, vals<T>(L.su.Pt), b.tU, cb.kap, L.sv.Pt, vals<T>(L.sv.Pt), b.tV, cb.tau, 0.0);
     }
-    // zero initial coarse correction: written explicitly for Kaczmarz (it updates in place); the
-    // Jacobi-type relaxation starts from zero without reading it, and the coarsest solve writes it
-    if (!zero_start_ok) {
-      if constexpr (std::is_same<T, double>::value) {
-        launch_fill(cb.Ub, (size_t)(rows_u(C) + (spd_ ? 0 : rows_v(C))) * nb_, 0.0, st_);
-      } else {
-        launch_fillf(cb.Ub, (size_t)(rows_u(C) + (spd_ ? 0 : rows_v(C))) * nb_, 0.0f, st_);
-      }
-    }
   }
-  // coarsest: [u; v] = pinv(X - sigma_j Y) [kappa; tau] (FP64)
-  {
-    Level& L = *lv_.back();
-    Blocks<T>& b = blocks<T>(L);
-    const size_t n = (size_t)NL_ * nb_;
-    double* rhs = L.bd.kap;
-    double* sol = L.bd.Ub;
-    T* rk = nl == 1 ? rhsU : b.kap;
-    if constexpr (std::is_same<T, float>::value) {
-      launch_copy_cast_fd(rk, L.bd.kap, n, st_);
+  // zero initial coarse correction: written explicitly for Kaczmarz (it updates in place); the
+  // Jacobi-type relaxation starts from zero without reading it, and the coarsest solve writes it
+  if (!zero_start_ok) {
+    if constexpr (std::is_same<T, double>::value) {
+      launch_fill(cb.Ub, (size_t)(rows_u(C) + (spd_ ? 0 : rows_v(C))) * nb_, 0.0, st_);
     } else {
-      if (rk != L.bd.kap) HIPCHK(hipMemcpyAsync(rhs, rk, n * sizeof(double), hipMemcpyDeviceToDevice, st_));
+      launch_fillf(cb.Ub, (size_t)(rows_u(C) + (spd_ ? 0 : rows_v(C))) * nb_, 0.0f, st_);
     }
-    if (p_.coarse_pinv == 0) {
-      // the eigenvectors of the previous call start the next one; a cold start every 32 calls
-      // the first call of the additive phase starts cold; every 32nd re-orthonormalises the basis
-      // (pinv_calls_ equals the iteration index)
-      const long c = pinv_calls_++;
-      const int warm = c == 0 ? 0 : (c % 32) == 0 ? 2 : 1;
-      prof(4, 0.0, [&] { launch_pinv_solve(NL_, nb_, dX_, dY_, sig, rhs, sol, dwork_, pbasis_, warm, status_, st_); });
-    }
-    else prof(4, 0.0, [&] { launch_pencil_solve(NL_, nb_, mu_, Zp_, sig, rhs, sol, st_); });
-    if constexpr (std::is_same<T, float>::value) launch_copy_cast_df(sol, b.Ub, n, st_);
   }
-  for (int l = nl - 2; l >= 0; --l) {
-    Level& L = *lv_[l];
-    Level& C = *lv_[l + 1];
-    Blocks<T>& b = blocks<T>(L);
-    Blocks<T>& cb = blocks<T>(C);
-    if (spd_) spmm<T>(l, L.su.P, vals<T>(L.su.P), nb_, cb.Ub, b.Ub, 1.0);
-    else spmm2<T>(l, L.su.P, vals<T>(L.su.P), cb.Ub, b.Ub, L.sv.P, vals<T>(L.sv.P), cb.Vb, b.Vb, 1.0);
-    const T* kap = l == 0 ? rhsU : b.kap;
-    const T* tau = l == 0 ? rhsV : b.tau;
-    boot_relax<T>(l, kap, tau, sig, p_.mu_b);
+  if (l + 2 == nl) {
+    coarsest_additive<T>(sig);
+  } else {
+    for (int v = 0; v < p_.cycle_gamma; ++v) cycle_level<T>(l + 1, sig, rhsU, rhsV, v == 0);
   }
+  if (spd_) spmm<T>(l, L.su.P, vals<T>(L.su.P), nb_, cb.Ub, b.Ub, 1.0);
+  else spmm2<T>(l, L.su.P, vals<T>(L.su.P), cb.Ub, b.Ub, L.sv.P, vals<T>(L.sv.P), cb.Vb, b.Vb, 1.0);
+  boot_relax<T>(l, kap, tau, sig, p_.mu_b);
+}
+
+// Coarsest level of the additive cycle: [u; v] = pinv(X - sigma_j Y) [kappa; tau] (FP64), from and
+// into the coarsest level's blocks.
+template <class T>
+void Solver::coarsest_additive(const double* sig) {
+  Level& L = *lv_.back();
+  Blocks<T>& b = blocks<T>(L);
+  const size_t n = (size_t)NL_ * nb_;
+  double* rhs = L.bd.kap;
+  double* sol = L.bd.Ub;
+  T* rk = b.kap;
+  if constexpr (std::is_same<T, float>::value) {
+    launch_copy_cast_fd(rk, L.bd.kap, n, st_);
+  } else {
+    if (rk != L.bd.kap) HIPCHK(hipMemcpyAsync(rhs, rk, n * sizeof(double), hipMemcpyDeviceToDevice, st_));
+  }
+  if (p_.coarse_pinv == 0) {
+    // the eigenvectors of the previous call start the next one; the first call of the additive
+    // phase starts cold, and the first call of every eagerly run iteration (every 32nd)
+    // re-orthonormalises the basis, so that captured iterations (plain warm start) and eager ones
+    // take the same steps whatever the number of coarsest solves per iteration
+    const long c = pinv_calls_++;
+    const int warm = c == 0 ? 0 : pinv_reortho_ ? 2 : 1;
+    pinv_reortho_ = false;
+    prof(4, 0.0, [&] { launch_pinv_solve(NL_, nb_, dX_, dY_, sig, rhs, sol, dwork_, pbasis_, warm, status_, st_); });
+  }
+  else prof(4, 0.0, [&] { launch_pencil_solve(NL_, nb_, mu_, Zp_, sig, rhs, sol, st_); });
+  if constexpr (std::is_same<T, float>::value) launch_copy_cast_df(sol, b.Ub, n, st_);
 }
 
 void Solver::additive_iteration() {
@@ -1940,6 +1956,13 @@ void Solver::check_status() {
   if (st[0] != 0) throw SolverError{ST_E_NUMERIC, "dense factorisation breakdown on the device"};
 }
 
+// Coarsest solves per additive iteration: cycle_gamma^(levels - 2).
+long Solver::coarse_calls_per_iter() const {
+  long c = 1;
+  for (int l = 2; l < (int)lv_.size(); ++l) c *= p_.cycle_gamma;
+  return c;
+}
+
 // The additive phase's coarsest-level structures: dense X, Y (and the pencil eigenbasis).
 void Solver::coarse_setup() {
   dense_coarsest(dX_, dY_);
@@ -2083,11 +2106,12 @@ void Solver::run(const double* init_tests, SolveOutput& out) {
     // basis there (starts cold in the first), and the profiled kernel classes are timed there; the
     // other iterations replay the graph (captured with the plain warm start)
     const bool eager = ((it - it0) % 32) == 0;
+    pinv_reortho_ = eager;
     if (!eager && !graph_off_ && !igx_) capture_iteration();
     const bool replay = !eager && igx_ != nullptr;
     if (replay) {
       HIPCHK(hipGraphLaunch(igx_, st_));
-      if (p_.coarse_pinv == 0) ++pinv_calls_;
+      if (p_.coarse_pinv == 0) pinv_calls_ += coarse_calls_per_iter();
       ++rep_.graph_iters;
     } else {
       iteration_body();

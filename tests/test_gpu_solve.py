@@ -241,6 +241,7 @@ def test_request_interface_matches_solve(ctx):
     ("laplace2d_31_min4", None, {"coarse_pinv": 1}),               # pencil variant
     ("laplace2d_31_min4", None, {"precision": "mixed_fp32"}),      # refinement form
     ("gradient2d_256_dom8", 32, {}),                               # Jacobi-type, rectangular SVD
+    ("laplace2d_31_min4", None, {"cycle_gamma": 2}),               # W-cycle: 8 coarsest solves per iteration
 ])
 def test_graph_replay_bitwise_equals_eager(ctx, name, scale, over):
     from paper_1102_0919_amd import api
@@ -613,3 +614,25 @@ def test_redo_interpolation_vs_oracle(ctx, precision):
     _sig_close(r.sigma, ref, r.report.anorm)
     _sig_close(r.sigma, o.sigma, r.report.anorm)
     _check_triplets(A, r, "svd", 1e-8, r.report.anorm)
+
+
+@pytest.mark.parametrize("name,scale,kind,ref,n_exact", [
+    ("laplace2d_31_min4", None, "spd", lambda: W.laplace2d_eigs(31)[:4], 4),
+    ("aniso3d_128_min8", 16, "spd", lambda: W.aniso3d_eigs_smallest(16, 0.01, 8), 5),
+])
+def test_w_cycle_vs_oracle(ctx, name, scale, kind, ref, n_exact):
+    # W-cycles in the additive phase (cycle_gamma 2, R34): the device's recursive cycle against the
+    # oracle's: same hierarchy, additive iterations within 2, eigenpairs equal to the oracle's and
+    # valid.  The 31^2 Laplacian needs 7 W-cycles instead of 27 V-cycles and finds the 4 smallest
+    # eigenvalues; on the 3-D anisotropic operator at 16^3 the W-cycle converges, in the oracle as
+    # on the device, to lambda_1..lambda_5 and three eigenpairs near 0.17 instead of
+    # lambda_6..lambda_8 (the V-cycle finds all eight)
+    from paper_1102_0919_amd import api
+    A, wl, r, o = _run_both(ctx, name, scale=scale, cycle_gamma=2, max_add=400)
+    rep = api.report_dict(r.report)
+    assert r.converged and o.report["converged"]
+    assert rep["sizes"] == [tuple(x) for x in o.report["sizes"]]
+    assert abs(rep["add_iters"] - o.report["add_iters"]) <= 2
+    _sig_close(r.sigma[:n_exact], ref()[:n_exact], rep["anorm"])
+    _sig_close(r.sigma, o.sigma, rep["anorm"])
+    _check_triplets(A, r, kind, 1e-8, rep["anorm"])

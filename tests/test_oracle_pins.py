@@ -793,3 +793,15 @@ def test_redo_interpolation_end_to_end_closed_form():
     assert o.report["converged"] and len(o.report["redo"]) >= 1
     ref = W.gradient2d_singular_values(16)[::-1][:4]
     assert np.allclose(o.sigma, ref, rtol=1e-10)
+
+
+def test_w_cycle_closed_form_and_visit_count():
+    # R34: with cycle_gamma 2 every level above the last one before the coarsest visits its coarser
+    # level twice, so an additive iteration solves the coarsest level 2^(levels - 2) times; the
+    # W-cycle reaches the closed-form eigenvalues of the 5-point Laplacian (4 smallest, 24 x 24)
+    A = W.laplace2d(24).to_scipy()
+    prm = dict(W.WORKLOADS["laplace2d_31_min4"]["params"], max_add=200, cycle_gamma=2)
+    o = O.solve(A, "spd", "minimal", 4, O.Params(**prm))
+    assert o.report["converged"] and o.report["levels"] >= 3
+    assert o.report["coarse_solves"] == o.report["add_iters"] * 2 ** (o.report["levels"] - 2)
+    assert np.allclose(o.sigma, W.laplace2d_eigs(24)[:4], rtol=1e-10)
