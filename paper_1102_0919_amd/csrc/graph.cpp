@@ -2,14 +2,18 @@
 // Algorithm 1 (one-pass Ruge-Stueben coarsening), interpolatory sets and the sparsity patterns of
 // P and Q, plus the symbolic sparse products of the Galerkin operators, transposes and the greedy
 // multicolouring that orders the Kaczmarz sweeps.  They run once per level; every numeric step runs
-// in the HIP kernels.  Algorithm 1 and the colouring are sequential; the strength sets and the
+// in the HIP kernels.  Algorithm 1 and the colouring are sequential (the solver colours a level on
+// a host thread of its own while it builds the level's coarsening); the strength sets and the
 // symbolic products are built row by row on several host threads (identical results).
 #include "graph.h"
 
 #include <algorithm>
 #include <atomic>
+#include <climits>
 #include <cmath>
+#include <cstdint>
 #include <exception>
+#include <memory>
 #include <queue>
 #include <stdexcept>
 #include <thread>
@@ -129,14 +133,18 @@ std::vector<char> rs_coarsen(const std::vector<int>& Sp, const std::vector<int>&
   std::vector<long> lam(n);
   for (int i = 0; i < n; ++i) lam[i] = Tp[i + 1] - Tp[i];
   std::vector<char> state(n, 0);   // 0 undecided, 1 C, 2 F
-  // max-heap on (lambda, -index)
-  std::priority_queue<std::pair<long, int>> heap;
-  for (int i = 0; i < n; ++i) heap.push({lam[i], -i});
+  // max-heap on (lambda, -index), packed into one 64-bit key: lambda in the high word, the
+  // complement of the index in the low word (the largest key is the lowest index among maximal
+  // lambda); stale entries are skipped when popped
+  auto key = [](long l, int i) { return ((uint64_t)l << 32) | (uint64_t)(uint32_t)(INT32_MAX - i); };
+  std::vector<uint64_t> init(n);
+  for (int i = 0; i < n; ++i) init[i] = key(lam[i], i);
+  std::priority_queue<uint64_t> heap(std::less<uint64_t>(), std::move(init));
   while (!heap.empty()) {
-    auto top = heap.top();
+    const uint64_t top = heap.top();
     heap.pop();
-    const int i = -top.second;
-    if (state[i] != 0 || top.first != lam[i]) continue;
+    const int i = INT32_MAX - (int)(uint32_t)(top & 0xffffffffu);
+    if (state[i] != 0 || (long)(top >> 32) != lam[i]) continue;
     state[i] = 1;
     for (int t = Tp[i]; t < Tp[i + 1]; ++t) {
       const int j = Ti[t];
@@ -146,7 +154,7 @@ std::vector<char> rs_coarsen(const std::vector<int>& Sp, const std::vector<int>&
         const int kk = Si[k];
         if (state[kk] == 0) {
           lam[kk] += 1;
-          heap.push({lam[kk], -kk});
+          heap.push(key(lam[kk], kk));
         }
       }
     }

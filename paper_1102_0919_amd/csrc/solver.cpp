@@ -11,6 +11,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <future>
 #include <memory>
 
 #include "graph.h"
@@ -156,8 +157,18 @@ struct LongRows {
   int n = 0;
 };
 
+// Kaczmarz row order of a level's sides, computed on the host (rows of A; SVD: also rows of A^t)
+struct ColourJob {
+  std::vector<int> rows, cptr, rows2, cptr2;
+  std::vector<long> cnnz, cnnz2;
+};
+
 struct Level {
   int m = 0, n = 0;
+  // the Kaczmarz colouring, computed on a host thread of its own from the level's pattern and
+  // uploaded when the level's first Kaczmarz sweep needs it
+  std::future<ColourJob> colour_job;
+  bool coloured = true;
   LongRows lgu, lgv;        // u-side rows (A, B) and v-side rows (A^t, C)
   HCsr hA, hAt, hB, hC;     // host patterns (hB/hC: SVD only)
   std::vector<int> permAt;
@@ -228,6 +239,7 @@ class Solver {
   void make_coarse_level(int l);
   void refresh_level_aux(Level& L);
   void colour(Level& L);
+  void ensure_colours(Level& L);
   std::vector<int> row_colours(const HCsr& M) const;
   HCsr strength_operator(Level& L, bool u_side, bool finest);
   // cycle pieces
@@ -238,6 +250,16 @@ class Solver {
   template <class T> void cycle_level(int l, const double* sig, T* rhsU, T* rhsV, bool zero_iterate);
   template <class T> void coarsest_additive(const double* sig);
   long coarse_calls_per_iter() const;
+  // set-up timing on stderr (verbose >= 2): host time since the previous mark
+  std::chrono::steady_clock::time_point vt_ = std::chrono::steady_clock::now();
+  void vmark(const char* what, int l) {
+    if (p_.verbose < 2) return;
+    const auto t = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "[slamg]   level %d %s: %.1f ms\n", l, what,
+                 std::chrono::duration<double, std::milli>(t - vt_).count());
+    std::fflush(stderr);
+    vt_ = t;
+  }
   void coarse_setup();
   void cast_transfers();
   void galerkin(int l);
@@ -692,35 +714,46 @@ std::vector<int> Solver::row_colours(const HCsr& M) const {
   return greedy_row_colouring(M);
 }
 
+// Starts the colouring of a level's Kaczmarz order on a host thread: it needs the level's pattern
+// only (host copies that do not change afterwards), and the set-up of the level's coarsening runs
+// meanwhile.
 void Solver::colour(Level& L) {
   if (!minimal_) return;
-  std::vector<int> rows, cptr;
+  const HCsr* a = &L.hA;
+  const HCsr* at = spd_ ? nullptr : &L.hAt;   // eigenproblems: B_l lives on A_l's pattern
+  L.coloured = false;
+  L.colour_job = std::async(std::launch::async, [this, a, at] {
+    ColourJob j;
+    colour_order(row_colours(*a), j.rows, j.cptr);
+    j.cnnz = colour_nnz(*a, j.rows, j.cptr);
+    if (at) {
+      colour_order(row_colours(*at), j.rows2, j.cptr2);
+      j.cnnz2 = colour_nnz(*at, j.rows2, j.cptr2);
+    }
+    return j;
+  });
+}
+
+// Waits for a level's colouring and uploads it (once).
+void Solver::ensure_colours(Level& L) {
+  if (L.coloured) return;
+  ColourJob j = L.colour_job.get();
+  L.coloured = true;
+  L.kA_rows = ar_.alloc<int>(j.rows.size());
+  h2d(L.kA_rows, j.rows, st_);
+  L.kA_cptr = j.cptr;
+  L.kA_cnnz = j.cnnz;
+  L.d_kA_cptr = ar_.alloc<int>(j.cptr.size());
+  h2d(L.d_kA_cptr, j.cptr, st_);
   if (spd_) {
-    HCsr pat = L.hA;   // B_l lives on A_l's pattern
-    colour_order(row_colours(pat), rows, cptr);
-    L.kA_rows = ar_.alloc<int>(rows.size());
-    h2d(L.kA_rows, rows, st_);
-    L.kA_cptr = cptr;
-    L.kA_cnnz = colour_nnz(pat, rows, cptr);
-    L.d_kA_cptr = ar_.alloc<int>(cptr.size());
-    h2d(L.d_kA_cptr, cptr, st_);
     L.kacz_wg = L.m <= KACZ_WG_MAX_ROWS;
   } else {
-    colour_order(row_colours(L.hA), rows, cptr);
-    L.kA_rows = ar_.alloc<int>(rows.size());
-    h2d(L.kA_rows, rows, st_);
-    L.kA_cptr = cptr;
-    L.kA_cnnz = colour_nnz(L.hA, rows, cptr);
-    std::vector<int> rows2, cptr2;
-    colour_order(row_colours(L.hAt), rows2, cptr2);
-    L.kAt_rows = ar_.alloc<int>(rows2.size());
-    h2d(L.kAt_rows, rows2, st_);
-    L.kAt_cptr = cptr2;
-    L.kAt_cnnz = colour_nnz(L.hAt, rows2, cptr2);
-    L.d_kA_cptr = ar_.alloc<int>(cptr.size());
-    h2d(L.d_kA_cptr, cptr, st_);
-    L.d_kAt_cptr = ar_.alloc<int>(cptr2.size());
-    h2d(L.d_kAt_cptr, cptr2, st_);
+    L.kAt_rows = ar_.alloc<int>(j.rows2.size());
+    h2d(L.kAt_rows, j.rows2, st_);
+    L.kAt_cptr = j.cptr2;
+    L.kAt_cnnz = j.cnnz2;
+    L.d_kAt_cptr = ar_.alloc<int>(j.cptr2.size());
+    h2d(L.d_kAt_cptr, j.cptr2, st_);
     L.kacz_wg = std::max(L.m, L.n) <= KACZ_WG_MAX_ROWS;
   }
   sync();
@@ -993,10 +1026,13 @@ void Solver::finish_side(Side& S, const std::vector<int>& ptr, const std::vector
 bool Solver::build_structure(int l) {
   Level& L = *lv_[l];
   if (size_of(L) <= p_.coarse_max || l + 1 >= p_.max_levels) return false;
+  vmark("(before set-up of the level)", l);
   HCsr Nu = strength_operator(L, true, l == 0);
+  vmark("strength operator", l);
   Side su, sv;
   Strength stu, stv;
   build_side(L, su, Nu, L.m, &stu);
+  vmark("strength sets, Algorithm 1, interpolatory sets", l);
   HCsr Nv;
   if (square_) {
     // §5.1: the v-side takes the u-side's C/F split and interpolatory sets (one pattern for P and
@@ -1057,6 +1093,7 @@ bool Solver::build_structure(int l) {
   };
   devside(su);
   if (!spd_) devside(sv);
+  vmark("transfer uploads", l);
   L.su = std::move(su);
   if (!spd_) L.sv = std::move(sv);
   rep_.capped[l] = L.su.capped + (spd_ ? 0 : L.sv.capped);
@@ -1134,8 +1171,10 @@ void Solver::make_coarse_level(int l) {
   rep_.rows[l + 1] = C->m;
   rep_.cols[l + 1] = C->n;
   rep_.nnz[l + 1] = C->hA.nnz();
+  vmark("Galerkin symbolic products and plans", l);
   alloc_level_buffers(*C);
   colour(*C);
+  vmark("coarse buffers and Kaczmarz colouring", l + 1);
   lv_.push_back(std::move(C));
 }
 
@@ -1144,6 +1183,7 @@ void Solver::make_coarse_level(int l) {
 // ------------------------------------------------------------------------------------------------
 void Solver::relax_tests(int l) {
   Level& L = *lv_[l];
+  ensure_colours(L);
   auto& b = L.bd;
   const int mu = rows_u(L), mv = rows_v(L);
   DotArgs<double> da;
@@ -1284,6 +1324,7 @@ void Solver::relax_tests(int l) {
 template <class T>
 void Solver::boot_relax(int l, const T* kap, const T* tau, const double* sig, int nsweeps, bool zero_start) {
   Level& L = *lv_[l];
+  ensure_colours(L);
   Blocks<T>& b = blocks<T>(L);
   Aux<T>& x = aux<T>(L);
   const int mu = rows_u(L), mv = rows_v(L);
@@ -2054,8 +2095,11 @@ void Solver::run(const double* init_tests, SolveOutput& out) {
   HIPCHK(hipMemsetAsync(sig_, 0, 64 * sizeof(double), st_));
   rep_.rows[0] = A0_.m; rep_.cols[0] = A0_.n; rep_.nnz[0] = A0_.nnz();
   pmask_ = p_.profile_mask;
+  vt_ = std::chrono::steady_clock::now();
   finest_level(init_tests);
+  vmark("finest level (uploads, transpose, colouring)", 0);
   norm_estimate();
+  vmark("norm estimate", 0);
   rep_.anorm = anorm_;
   std::vector<double> rho;
   std::vector<double> hs;
@@ -2080,6 +2124,7 @@ void Solver::run(const double* init_tests, SolveOutput& out) {
   if (!p_.ritz_in_mult) ritz();
   check_status();
   for (size_t l = 0; l < lv_.size(); ++l) {
+    ensure_colours(*lv_[l]);
     rep_.rows[l] = lv_[l]->m;
     rep_.cols[l] = lv_[l]->n;
     rep_.nnz[l] = lv_[l]->hA.nnz();

@@ -135,3 +135,24 @@ def test_bf16_reference_rounding_worked_values():
              (3.3895313892515355e38, 0x7F7F), (3.4e38, 0x7F80), (np.inf, 0x7F80), (0.0, 0x0000), (-0.0, 0x8000)]
     got = _bf16_nearest(np.array([v for v, _ in cases]))
     assert [int(g) for g in got] == [p for _, p in cases]
+
+
+def test_colouring_and_coarsening_bitexact_large(lib):
+    # colours and the C/F split of Algorithm 1 (a heap with packed keys) on larger and wider
+    # patterns must equal the oracle's
+    A = W.aniso3d(28, 0.01).to_scipy()
+    G = sp.csr_matrix(O.structural_product(A, A))          # a wider, Galerkin-like pattern
+    R = W.random_csr(20000, 15000, seed=3, mean_row=6).to_scipy()
+    for M in (A, G, sp.csr_matrix(R)):
+        M.sort_indices()
+        m, n = M.shape
+        assert m >= 16384
+        col = np.zeros(m, np.int32)
+        assert lib.slamg_graph_colour(m, n, _p(_i32(M.indptr)), _p(_i32(M.indices)), _p(col)) == 0
+        assert np.array_equal(col, O.greedy_row_colouring(M))
+    N = sp.csr_matrix(A)
+    Sp, Si, _ = _strength(lib, N, 0.25, 1)
+    isc = np.zeros(N.shape[0], np.int8)
+    assert lib.slamg_graph_rs(N.shape[0], _p(Sp), _p(_i32(Si)), _p(isc)) == 0
+    oSp, oSi = O.strength_sets(N, 0.25, 1, 4)
+    assert np.array_equal(isc.astype(bool), O.rs_coarsen(oSp, oSi, N.shape[0]))
