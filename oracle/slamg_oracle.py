@@ -73,6 +73,11 @@ the design notes of the repository):
       last one above the coarsest visits its next coarser level twice per visit of its own (the
       second visit starts from the first one's correction, with the same restricted residual);
       the last one above the coarsest solves the coarsest level once per visit.
+  R35 Ritz on coarse levels (§4.3, optional): in the upward sweep of a multiplicative cycle, after
+      the boot relaxation of a level below the finest, the level's boot triplets are replaced by
+      the Ritz triplets of their span: a B-orthonormal basis of span(U_b) and a C-orthonormal one
+      of span(V_b) (eigenproblems: a B-orthonormal basis of span(X_b)), the n_b x n_b projected
+      problem, ordered by the target.
 """
 from __future__ import annotations
 
@@ -122,6 +127,7 @@ class Params:
     redo_p: int = 0               # R33: redetermine P, Q in the additive phase (§6.3)
     redo_tol: float = 1e-14       # R33: relative change of a Ritz value that counts as converged
     cycle_gamma: int = 1          # R34: coarse visits per level in the additive cycle (1 V, 2 W)
+    ritz_coarse: int = 0          # R35: Ritz step on the coarse levels of the multiplicative phase
 
 
 REDO_DOWN = 1e-3                  # §6.3: LS weight factor of test vectors and converged pairs
@@ -635,6 +641,29 @@ def ritz(A, kind, target, U, V, u_from_v=False, anorm=1.0):
     return s, U, V
 
 
+def metric_orthonormal(M, X):
+    """A basis of span(X) orthonormal in the inner product of the SPD matrix M: X L^-t with
+    L L^t = X^t M X (§4.3)."""
+    L = np.linalg.cholesky(X.T @ (M @ X))
+    return sla.solve_triangular(L, X.T, lower=True).T
+
+
+def ritz_level(lev, kind, target, U, V):
+    """§4.3's Ritz step on a level with its B and C (R35): the extremal triplets of the projected
+    problem on span(U) x span(V) in the B and C metrics, ordered by the target."""
+    if kind == SPD:
+        Xh = metric_orthonormal(lev.B, U)
+        M = Xh.T @ (lev.A @ Xh)
+        lam, Yv = np.linalg.eigh(0.5 * (M + M.T))
+        order = np.argsort(lam) if target == MINIMAL else np.argsort(-lam)
+        return lam[order], Xh @ Yv[:, order], None
+    Uh = metric_orthonormal(lev.B, U)
+    Vh = metric_orthonormal(lev.C, V)
+    Y, s, Zt = np.linalg.svd(Uh.T @ (lev.A @ Vh))
+    order = np.argsort(s) if target == MINIMAL else np.argsort(-s)
+    return s[order], Uh @ Y[:, order], Vh @ Zt.T[:, order]
+
+
 def residuals(A, kind, U, V, sig, anorm):
     """R18: rho_j (unit vectors assumed)."""
     if kind == SPD:
@@ -884,6 +913,8 @@ class Solver:
             Ub = lev.su.P @ Ub
             Vb = None if kind == SPD else lev.sv.P @ Vb
             Ub, Vb, sig = relax_boot_with_rq(lev, kind, target, Ub, Vb, sig, p)
+            if p.ritz_coarse and l > 0:
+                sig, Ub, Vb = ritz_level(lev, kind, target, Ub, Vb)
         self.Ut, self.Vt = tests_u[0], tests_v[0]
         if p.ritz_in_mult:
             sig, Ub, Vb = self._ritz(Ub, Vb)

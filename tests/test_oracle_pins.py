@@ -805,3 +805,31 @@ def test_w_cycle_closed_form_and_visit_count():
     assert o.report["converged"] and o.report["levels"] >= 3
     assert o.report["coarse_solves"] == o.report["add_iters"] * 2 ** (o.report["levels"] - 2)
     assert np.allclose(o.sigma, W.laplace2d_eigs(24)[:4], rtol=1e-10)
+
+
+@pytest.mark.parametrize("kind", ["svd", "spd"])
+def test_ritz_level_recovers_exact_generalized_triplets(kind):
+    # R35 (§4.3 with B and C): spans of exact generalized singular triplets (or eigenpairs of the
+    # pencil (A, B)), given in a mixed, non-orthonormal basis, give back the triplets themselves:
+    # sigma exactly, vectors up to sign, u^t B u = v^t C v = 1.  The Euclidean inner product in
+    # place of B / C fails this.
+    rng = np.random.default_rng(21)
+    m, n, nb = (30, 20, 4) if kind == "svd" else (25, 25, 4)
+    Bh = rng.uniform(-1, 1, (m, m)); Bd = Bh @ Bh.T / m + np.eye(m)
+    if kind == "svd":
+        Ad = rng.uniform(-1, 1, (m, n))
+        Ch = rng.uniform(-1, 1, (n, n)); Cd = Ch @ Ch.T / n + np.eye(n)
+        lev = O.Level(sp.csr_matrix(Ad), sp.csr_matrix(Bd), sp.csr_matrix(Cd))
+    else:
+        Ah = rng.uniform(-1, 1, (m, m)); Ad = Ah @ Ah.T / m + 0.5 * np.eye(m)
+        lev = O.Level(sp.csr_matrix(Ad), sp.csr_matrix(Bd), None)
+    s0, U0, V0 = O.coarsest_gsvd(lev, kind, "dominant", nb)
+    Q = rng.uniform(-1, 1, (nb, nb)) + 3 * np.eye(nb)
+    s1, U1, V1 = O.ritz_level(lev, kind, "dominant", U0 @ Q, None if V0 is None else V0 @ Q)
+    assert np.allclose(s1, s0, rtol=1e-10)
+    assert np.allclose(U1.T @ Bd @ U1, np.eye(nb), atol=1e-10)
+    for j in range(nb):
+        sgn = np.sign(U1[:, j] @ Bd @ U0[:, j])
+        assert np.allclose(U1[:, j] * sgn, U0[:, j], atol=1e-8)
+        if kind == "svd":
+            assert np.allclose(V1[:, j] * sgn, V0[:, j], atol=1e-8)
