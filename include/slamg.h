@@ -130,7 +130,10 @@ typedef struct {
   int32_t cycle_gamma;      /* additive cycle (§3.3): 1 V-cycle, 2 W-cycle (every level but the
                                last one above the coarsest visits its coarser level twice, the
                                second visit from the first one's correction) (1)                */
-  int32_t reserved2;
+  int32_t ritz_coarse;      /* Ritz step on coarse levels (§4.3): in the upward sweep of a
+                               multiplicative cycle, after each coarse level's boot relaxation, the
+                               boot triplets become the Ritz triplets of their span in the B and C
+                               metrics (0)                                                       */
 } slamg_params;
 
 /* Report of one solve.  Arrays are filled up to the counts given. */

@@ -36,7 +36,7 @@ class Params(C.Structure):
                 ("n_guard", C.c_int32), ("mu_tJ", C.c_int32), ("mu_bJ", C.c_int32),
                 ("kaczmarz_order", C.c_int32), ("coarse_dense_max", C.c_int32),
                 ("redo_p", C.c_int32), ("redo_tol", C.c_double), ("cycle_gamma", C.c_int32),
-                ("reserved2", C.c_int32)]
+                ("ritz_coarse", C.c_int32)]
 
 
 class Report(C.Structure):

@@ -108,6 +108,7 @@ extern "C" slamg_status slamg_params_init(slamg_params* p, slamg_kind kind, slam
   p->redo_p = 0;
   p->redo_tol = 1e-14;
   p->cycle_gamma = 1;
+  p->ritz_coarse = 0;
   (void)target;
   return SLAMG_OK;
 }
@@ -271,6 +272,7 @@ static slamg_status check_params(std::string& err, const Prepared& P, int32_t nb
   if (p.redo_p != 0 && p.redo_p != 1) return fail(err, SLAMG_E_INVALID, "redo_p must be 0 or 1");
   if (p.redo_p && !(p.redo_tol > 0.0 && p.redo_tol < 1.0)) return fail(err, SLAMG_E_INVALID, "redo_tol must lie in (0, 1)");
   if (p.cycle_gamma != 1 && p.cycle_gamma != 2) return fail(err, SLAMG_E_INVALID, "cycle_gamma must be 1 or 2");
+  if (p.ritz_coarse != 0 && p.ritz_coarse != 1) return fail(err, SLAMG_E_INVALID, "ritz_coarse must be 0 or 1");
   if (!(p.tol > 0.0)) return fail(err, SLAMG_E_INVALID, "tol must be positive");
   if (p.n_t < 2 || p.n_t > 16) return fail(err, SLAMG_E_INVALID, "n_t must be in 2..16");
   if (p.mu_t < 0 || p.mu_b < 0 || p.n_mult < 1 || p.max_add < 0) return fail(err, SLAMG_E_INVALID, "bad counts");

@@ -271,6 +271,7 @@ class Solver {
   template <class T> void additive_vcycle(const double* sig, T* rhsU, T* rhsV);
   void additive_iteration();
   void ritz();
+  void ritz_level(int l);
   void cholqr2(double* X, int rows, double* tmp, double* out);
   void cholqr2_pair(double* Xa, int rows_a, double* tmpa, double* outa, double* Xb, int rows_b, double* tmpb,
                     double* outb);
@@ -1688,6 +1689,7 @@ void Solver::mult_cycle(int c) {
     launch_spmm<double>(L.su.npts, nb_, L.su.P.rp, L.su.P.ci, L.su.P.v, C.bd.Ub, L.bd.Ub, 0.0, st_);
     if (!spd_) launch_spmm<double>(L.sv.npts, nb_, L.sv.P.rp, L.sv.P.ci, L.sv.P.v, C.bd.Vb, L.bd.Vb, 0.0, st_);
     boot_relax_rq(k);
+    if (p_.ritz_coarse && k >= 1) ritz_level(k);
   }
   if (p_.ritz_in_mult) ritz();
   lastcheck();
@@ -1868,6 +1870,38 @@ void Solver::ritz() {
     prof(2, 16.0 * mu * nb_, [&] { launch_gram(mu, nb_, b.tU2, b.tU, partial_, gram_, st_); });
     launch_small_ritz(nb_, 1, minimal_, gram_, small1_, small2_, sig_, small_work_, status_, st_);
     launch_rotate<double>(mu, nb_, nb_, b.tU2, small1_, b.Ub, st_);
+  }
+}
+
+// §4.3's Ritz step on coarse level l: bases of span(U_b) and span(V_b) orthonormal in the B and
+// C metrics (Cholesky-QR2 on X^t M X), the projected n_b x n_b problem, and the rotated blocks.
+void Solver::ritz_level(int l) {
+  Level& L = *lv_[l];
+  auto& b = L.bd;
+  const int mu = rows_u(L), mv = rows_v(L);
+  auto orth = [&](const DCsr& M, double* X, int rows, double* tmp, double* mx, double* out) {
+    spmm<double>(l, M, M.v, nb_, X, mx, 0.0);
+    launch_gram(rows, nb_, X, mx, partial_, gram_, st_);
+    launch_chol_inv_upper(nb_, gram_, small1_, status_, st_);
+    launch_rotate<double>(rows, nb_, nb_, X, small1_, tmp, st_);
+    spmm<double>(l, M, M.v, nb_, tmp, mx, 0.0);
+    launch_gram(rows, nb_, tmp, mx, partial_, gram_, st_);
+    launch_chol_inv_upper(nb_, gram_, small1_, status_, st_);
+    launch_rotate<double>(rows, nb_, nb_, tmp, small1_, out, st_);
+  };
+  if (spd_) {
+    orth(L.B, b.Ub, mu, b.tU, b.Ua, b.tU2);                  // X_hat in tU2 (B on A's pattern)
+    spmm<double>(l, L.A, L.A.v, nb_, b.tU2, b.tU, 0.0);      // A X_hat
+    launch_gram(mu, nb_, b.tU2, b.tU, partial_, gram_, st_);
+    launch_small_ritz(nb_, 1, minimal_, gram_, small1_, small2_, sig_, small_work_, status_, st_);
+    launch_rotate<double>(mu, nb_, nb_, b.tU2, small1_, b.Ub, st_);
+  } else {
+    orth(L.B, b.Ub, mu, b.tU, b.Ua, b.tU2);                  // U_hat in tU2
+    orth(L.C, b.Vb, mv, b.tV, b.Va, b.tV2);                  // V_hat in tV2
+    spmm<double>(l, L.A, L.A.v, nb_, b.tV2, b.tU, 0.0);      // A V_hat
+    launch_gram(mu, nb_, b.tU2, b.tU, partial_, gram_, st_);
+    launch_small_ritz(nb_, 0, minimal_, gram_, small1_, small2_, sig_, small_work_, status_, st_);
+    launch_rotate2<double>(nb_, mu, b.tU2, small1_, b.Ub, mv, b.tV2, small2_, b.Vb, st_);
   }
 }
 

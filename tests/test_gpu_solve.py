@@ -636,3 +636,30 @@ def test_w_cycle_vs_oracle(ctx, name, scale, kind, ref, n_exact):
     _sig_close(r.sigma[:n_exact], ref()[:n_exact], rep["anorm"])
     _sig_close(r.sigma, o.sigma, rep["anorm"])
     _check_triplets(A, r, kind, 1e-8, rep["anorm"])
+
+
+@pytest.mark.parametrize("name,kind,nb,ref", [
+    ("laplace2d_31_min4", "spd", 4, lambda: W.laplace2d_eigs(31)[:4]),
+    ("convdiff2d_31_min8", "svd", 8, None),
+])
+def test_ritz_coarse_vs_oracle(ctx, name, kind, nb, ref):
+    # the Ritz step on coarse levels (§4.3 applied in the upward sweep, R35): the boot triplets of
+    # each coarse level become the Ritz triplets of their span in that level's B and C metrics.
+    # The device tracks the oracle's first multiplicative cycle (the step changes it), needs the
+    # same additive iterations within 2 and returns the oracle's triplets
+    from paper_1102_0919_amd import api
+    A, wl, r, o = _run_both(ctx, name, ritz_coarse=1, max_add=400)
+    r0 = api.solve(ctx, A, wl["kind"], wl["target"], nb,
+                   api.params_init(wl["kind"], wl["target"], **dict(wl["params"], max_add=400)))
+    rep = api.report_dict(r.report)
+    assert r.converged and o.report["converged"]
+    assert rep["sizes"] == [tuple(x) for x in o.report["sizes"]]
+    ms = np.array([r.report.mult_sigma[0][j] for j in range(nb)])
+    ms0 = np.array([r0.report.mult_sigma[0][j] for j in range(nb)])
+    assert np.allclose(ms, o.report["mult_sigma"][0], rtol=1e-7)
+    assert not np.allclose(ms, ms0, rtol=1e-7)        # the option is live
+    assert abs(rep["add_iters"] - o.report["add_iters"]) <= 2
+    if ref is not None:
+        _sig_close(r.sigma, ref(), rep["anorm"])
+    _sig_close(r.sigma, o.sigma, rep["anorm"])
+    _check_triplets(A, r, kind, 1e-8, rep["anorm"])
