@@ -52,8 +52,8 @@ TRAFFIC = {
         note="mean of the finest-level u-row and v-row launches"),
     # every finest-level k_kacz launch of the multiplicative phase and one additive iteration
     ("aniso3d_128_min8", 1): dict(
-        kernels_sha256="7008812433c3f5d8b83a2c403201c7b4cbb238e9a72449e454b2b314a84183f5",
-        fetch_kib=(117666.0,), write_kib=(154373.4,),
+        kernels_sha256="b8402ea628376bd7bbb3bd1d724b1725898e3178809b613c5542830f62487ce5",
+        fetch_kib=(117671.3,), write_kib=(154372.1,),
         copy_fetch_kib=524304.5, copy_write_kib=1048576.0, copy_bytes=1 << 30,
         note="mean over the 1240 finest-level Kaczmarz colour launches of the multiplicative phase and "
              "one additive iteration"),
