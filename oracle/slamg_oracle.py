@@ -78,6 +78,22 @@ the design notes of the repository):
       the Ritz triplets of their span: a B-orthonormal basis of span(U_b) and a C-orthonormal one
       of span(V_b) (eigenproblems: a B-orthonormal basis of span(X_b)), the n_b x n_b projected
       problem, ordered by the target.
+  R36 LOBPCG solve phase (§7 names it as a replacement of the multigrid-Ritz additive phase,
+      optional): the preconditioned residual of a column is the change the additive cycle makes to
+      it, W = C(X) - X, with C the cycle of the additive phase at the current Ritz values.  The
+      Ritz step then runs on span[X, W, P] instead of span[C(X)], P the previous iteration's
+      search direction (none in the first iteration).  The basis is built block by block: X
+      orthonormalised; W with the components along X removed (two passes) and orthonormalised;
+      P with the components along X and W removed (two passes), and dropped for that iteration
+      when a column keeps less than 1e-8 of its norm or the Cholesky factorisation of its
+      column-scaled Gram matrix fails.  SVD: the same on
+      both sides (P dropped on both when either fails), Ritz triplets from the SVD of
+      Q_u^t A Q_v.  For minimal SVD targets the left blocks are the blocks of A Q_v, so that the
+      Ritz values are the singular values of A Q_v and none lies below sigma_min(A) (a two-sided
+      projection of the enlarged spaces has spurious singular values below it); u_j is then
+      A v_j / sigma_j, which makes R23 redundant.  The n_b triplets ordered by the target are
+      kept; the new P is the part of each new Ritz vector in the W and P blocks (orthogonal to
+      the old X).
 """
 from __future__ import annotations
 
@@ -128,6 +144,7 @@ class Params:
     redo_tol: float = 1e-14       # R33: relative change of a Ritz value that counts as converged
     cycle_gamma: int = 1          # R34: coarse visits per level in the additive cycle (1 V, 2 W)
     ritz_coarse: int = 0          # R35: Ritz step on the coarse levels of the multiplicative phase
+    solve_phase: int = 0          # R36: 0 multigrid-Ritz additive phase (§4), 1 LOBPCG (§7)
 
 
 REDO_DOWN = 1e-3                  # §6.3: LS weight factor of test vectors and converged pairs
@@ -664,6 +681,80 @@ def ritz_level(lev, kind, target, U, V):
     return s[order], Uh @ Y[:, order], Vh @ Zt.T[:, order]
 
 
+def remove_components(Y, bases):
+    """Y with its components along the orthonormal blocks in ``bases`` removed, two passes (R36)."""
+    for _ in range(2):
+        for Q in bases:
+            Y = Y - Q @ (Q.T @ Y)
+    return Y
+
+
+def keep_direction(Y0, Y):
+    """R36's test for keeping the P block Y0, Y what is left of it after the components along the
+    X and W blocks are removed: every column keeps at least 1e-8 of its norm, and the Gram matrix
+    of Y with its columns scaled to unit norm has a Cholesky factorisation."""
+    d = np.linalg.norm(Y, axis=0)
+    if np.any(d < 1e-8 * np.linalg.norm(Y0, axis=0)) or np.any(d == 0.0):
+        return False
+    Ys = Y / d[None, :]
+    try:
+        np.linalg.cholesky(Ys.T @ Ys)
+    except np.linalg.LinAlgError:
+        return False
+    return True
+
+
+def orthonormal_basis(Y):
+    """An orthonormal basis of span(Y) (Householder QR of the column-scaled block)."""
+    d = np.linalg.norm(Y, axis=0)
+    d[d == 0.0] = 1.0
+    Q, _ = np.linalg.qr(Y / d[None, :])
+    return Q
+
+
+def lobpcg_ritz(A, kind, target, n_b, X, W, P):
+    """R36's Rayleigh-Ritz step on span[X, W, P] (§7): X, W, P are (U, V) pairs of blocks (V None
+    for eigenproblems), P None when there is no search direction.  Returns sigma, the new Ritz
+    pair, the new search direction and whether the P block was kept."""
+    one_sided = kind == SVD and target == MINIMAL
+    QV = None
+    if kind == SVD:
+        QV = [orthonormal_basis(X[1])]
+        QV.append(orthonormal_basis(remove_components(W[1], QV)))
+    left = [A @ Q for Q in QV] if one_sided else [X[0], W[0]]
+    QU = [orthonormal_basis(left[0])]
+    QU.append(orthonormal_basis(remove_components(left[1], QU)))
+    kept = False
+    if P is not None:
+        PV = None if kind == SPD else remove_components(P[1], QV)
+        okv = kind == SPD or keep_direction(P[1], PV)
+        PU0 = A @ orthonormal_basis(PV) if one_sided and okv else P[0]
+        PU = remove_components(PU0, QU)
+        if okv and keep_direction(PU0, PU):
+            QU.append(orthonormal_basis(PU))
+            if kind == SVD:
+                QV.append(orthonormal_basis(PV))
+            kept = True
+    Qu = np.hstack(QU)
+    if kind == SPD:
+        M = Qu.T @ (A @ Qu)
+        lam, Yv = np.linalg.eigh(0.5 * (M + M.T))
+        order = np.argsort(lam) if target == MINIMAL else np.argsort(-lam)
+        sel = order[:n_b]
+        Ysel = Yv[:, sel]
+        Xn = Qu @ Ysel
+        Pn = Qu[:, n_b:] @ Ysel[n_b:, :]
+        return lam[sel], (Xn, None), (Pn, None), kept
+    Qv = np.hstack(QV)
+    Yl, s, Zt = np.linalg.svd(Qu.T @ (A @ Qv))
+    order = np.argsort(s) if target == MINIMAL else np.argsort(-s)
+    sel = order[:n_b]
+    Ysel, Zsel = Yl[:, sel], Zt.T[:, sel]
+    Un, Vn = Qu @ Ysel, Qv @ Zsel
+    Pn = (Qu[:, n_b:] @ Ysel[n_b:, :], Qv[:, n_b:] @ Zsel[n_b:, :])
+    return s[sel], (Un, Vn), Pn, kept
+
+
 def residuals(A, kind, U, V, sig, anorm):
     """R18: rho_j (unit vectors assumed)."""
     if kind == SPD:
@@ -1005,6 +1096,18 @@ class Solver:
         tau0 = None if kind == SPD else np.zeros_like(self.Vb)
         self.Ub, self.Vb = cycle(0, self.Ub, self.Vb, kap0, tau0)
 
+    def lobpcg_iteration(self, P):
+        """One iteration of R36's LOBPCG solve phase (§7): W = C(X) - X from the additive cycle
+        and the Ritz step on span[X, W, P].  Returns the new search direction."""
+        X = (self.Ub.copy(), None if self.Vb is None else self.Vb.copy())
+        self.additive_vcycle()
+        W = (self.Ub - X[0], None if self.Vb is None else self.Vb - X[1])
+        sig, (U, V), Pn, kept = lobpcg_ritz(self.levels[0].A, self.kind, self.target, self.n_b, X, W, P)
+        self.sig, self.Ub, self.Vb = sig, U, V
+        if P is not None and not kept:
+            self.report["p_dropped"] = self.report.get("p_dropped", 0) + 1
+        return Pn
+
     # -------------------------------------------------------------- redetermined P (§6.3, R33)
     def redo_interpolation(self, conv):
         """One downward sweep of the multiplicative phase during the additive phase: P, Q and the
@@ -1052,9 +1155,13 @@ class Solver:
         nw = self.n_want
         conv = np.zeros(self.n_b, dtype=bool)
         prev = self.sig.copy()
+        P = None
         while rho[:nw].max() > p.tol and it < p.max_add:
-            self.additive_vcycle()
-            self.sig, self.Ub, self.Vb = self._ritz(self.Ub, self.Vb)
+            if p.solve_phase == 1:
+                P = self.lobpcg_iteration(P)
+            else:
+                self.additive_vcycle()
+                self.sig, self.Ub, self.Vb = self._ritz(self.Ub, self.Vb)
             rho = residuals(A0, self.kind, self.Ub, self.Vb, self.sig, self.anorm)
             it += 1
             self.report["rho"].append(rho)

@@ -833,3 +833,91 @@ def test_ritz_level_recovers_exact_generalized_triplets(kind):
         assert np.allclose(U1[:, j] * sgn, U0[:, j], atol=1e-8)
         if kind == "svd":
             assert np.allclose(V1[:, j] * sgn, V0[:, j], atol=1e-8)
+
+
+# ---------------------------------------------------------------------------- LOBPCG phase (R36)
+def _laplace_dirichlet_vectors(n, pairs):
+    # closed-form eigenvectors sin(i pi x / (n+1)) sin(j pi y / (n+1)) of the 5-point Laplacian
+    x = np.arange(1, n + 1)
+    cols = [np.outer(np.sin(i * np.pi * x / (n + 1)), np.sin(j * np.pi * x / (n + 1))).ravel() for i, j in pairs]
+    return np.array(cols).T
+
+
+@pytest.mark.parametrize("target", ["spd_minimal", "svd_dominant", "svd_minimal"])
+def test_lobpcg_ritz_exact_when_span_holds_wanted_vectors(target):
+    # Rayleigh-Ritz on span[X, W, P] (§7, R36): when the span holds the wanted eigenvectors (right
+    # singular vectors) the step returns the closed-form eigenvalues (singular values) exactly, by
+    # interlacing; X and P are noise.  A two-sided projection for the minimal SVD target (left
+    # blocks X_u, W_u instead of A Q_v) returns values below sigma_min here and fails
+    rng = np.random.default_rng(36)
+    if target == "spd_minimal":
+        n = 12
+        A = W.laplace2d(n).to_scipy()
+        E = _laplace_dirichlet_vectors(n, [(1, 1), (1, 2), (2, 1), (2, 2)])
+        ref = W.laplace2d_eigs(n)[:4]
+        X = (E @ rng.uniform(-1, 1, (4, 4)) + 0.3 * rng.standard_normal((n * n, 4)), None)
+        Wd = (E, None)
+        P = (rng.standard_normal((n * n, 4)), None)
+        sig, (U, _), _, kept = O.lobpcg_ritz(A, "spd", "minimal", 4, X, Wd, P)
+        assert kept
+        assert np.allclose(sig, ref, rtol=1e-12)
+        assert np.allclose(A @ U - U * sig, 0.0, atol=1e-10)
+        return
+    A = W.gradient2d(8).to_scipy()
+    m, n = A.shape
+    sv = np.sort(W.gradient2d_singular_values(8))
+    dom = target == "svd_dominant"
+    ref = sv[::-1][:4] if dom else sv[:4]
+    Ud, s, Vt = np.linalg.svd(A.toarray(), full_matrices=False)
+    idx = np.argsort(-s)[:4] if dom else np.argsort(s)[:4]
+    Eu, Ev = Ud[:, idx], Vt.T[:, idx]
+    # a left block of noise plus a Q_u^t A Q_v coupling that a two-sided projection would exploit
+    X = (rng.standard_normal((m, 4)), Ev @ rng.uniform(-1, 1, (4, 4)) + 0.3 * rng.standard_normal((n, 4)))
+    Wd = (Eu if dom else Eu + 0.5 * rng.standard_normal((m, 4)), Ev)
+    sig, (U, V), _, kept = O.lobpcg_ritz(A, "svd", target.split("_")[1], 4, X, Wd, None)
+    assert not kept
+    assert np.allclose(sig, ref, atol=1e-12 * sv[-1])
+    assert np.allclose(A @ V - U * sig, 0.0, atol=1e-10)
+    assert np.allclose(A.T @ U - V * sig, 0.0, atol=1e-10) or not dom and np.allclose(
+        (A.T @ U - V * sig)[:, sig > 1e-8], 0.0, atol=1e-10)
+
+
+def test_lobpcg_search_direction_rules():
+    # R36: a P block inside span[X, W] is dropped and changes nothing; an independent one is kept,
+    # and the new P lies in span[X_old, W, P] and is orthogonal to the old X (it is the part of the
+    # new Ritz vectors in the W and P blocks)
+    rng = np.random.default_rng(7)
+    n = 10
+    A = W.laplace2d(n).to_scipy()
+    X = (np.linalg.qr(rng.standard_normal((n * n, 4)))[0], None)
+    Wd = (rng.standard_normal((n * n, 4)), None)
+    s0, (U0, _), _, k0 = O.lobpcg_ritz(A, "spd", "minimal", 4, X, Wd, None)
+    Pdep = (X[0] @ rng.uniform(-1, 1, (4, 4)) + Wd[0] @ rng.uniform(-1, 1, (4, 4)), None)
+    s1, (U1, _), _, k1 = O.lobpcg_ritz(A, "spd", "minimal", 4, X, Wd, Pdep)
+    assert not k0 and not k1
+    assert np.array_equal(s0, s1) and np.array_equal(U0, U1)
+    P = (rng.standard_normal((n * n, 4)), None)
+    s2, (U2, _), (Pn, _), k2 = O.lobpcg_ritz(A, "spd", "minimal", 4, X, Wd, P)
+    assert k2
+    assert np.all(s2 <= s0 + 1e-12)                      # a larger space: Ritz values no larger
+    assert np.abs(X[0].T @ Pn).max() < 1e-12
+    S = np.hstack([X[0], Wd[0], P[0]])
+    coef = np.linalg.lstsq(S, np.hstack([U2, Pn]), rcond=None)[0]
+    assert np.abs(S @ coef - np.hstack([U2, Pn])).max() < 1e-10
+    Rx = U2 - Pn                                         # the X part of the new Ritz vectors
+    assert np.abs(Rx - X[0] @ (X[0].T @ Rx)).max() < 1e-10
+
+
+@pytest.mark.parametrize("name,scale,ref,max_iters", [
+    ("laplace2d_31_min4", None, lambda: W.laplace2d_eigs(31)[:4], 12),
+    ("gradient2d_256_dom8", 32, lambda: np.sort(W.gradient2d_singular_values(32))[::-1][:8], 25),
+])
+def test_lobpcg_phase_converges_to_closed_form(name, scale, ref, max_iters):
+    # R36 end to end: the LOBPCG phase on the learned hierarchy reaches the closed form; with the
+    # search direction it takes at most max_iters iterations (10 and 21 here; without P, 20 and 52;
+    # the multigrid-Ritz phase 27 and 119)
+    wl = W.WORKLOADS[name]
+    A = W.build_workload_matrix(name, scale).to_scipy()
+    o = O.solve(A, wl["kind"], wl["target"], wl["n_b"], O.Params(**dict(wl["params"], solve_phase=1, max_add=200)))
+    assert o.report["converged"] and o.report["add_iters"] <= max_iters
+    assert np.allclose(o.sigma, ref(), rtol=1e-10)
