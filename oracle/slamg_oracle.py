@@ -85,8 +85,11 @@ the design notes of the repository):
       search direction (none in the first iteration).  The basis is built block by block: X
       orthonormalised; W with the components along X removed (two passes) and orthonormalised;
       P with the components along X and W removed (two passes), and dropped for that iteration
+      when one of its columns (a part of a unit Ritz vector) has norm below 1e-10 on either side,
       when a column keeps less than 1e-8 of its norm or the Cholesky factorisation of its
-      column-scaled Gram matrix fails.  SVD: the same on
+      column-scaled Gram matrix fails or has a pivot below 1e-10 (a condition number of the
+      scaled block above about 1e5: a decision well inside FP64's range, so that rounding does
+      not decide it).  SVD: the same on
       both sides (P dropped on both when either fails), Ritz triplets from the SVD of
       Q_u^t A Q_v.  For minimal SVD targets the left blocks are the blocks of A Q_v, so that the
       Ritz values are the singular values of A Q_v and none lies below sigma_min(A) (a two-sided
@@ -692,16 +695,17 @@ def remove_components(Y, bases):
 def keep_direction(Y0, Y):
     """R36's test for keeping the P block Y0, Y what is left of it after the components along the
     X and W blocks are removed: every column keeps at least 1e-8 of its norm, and the Gram matrix
-    of Y with its columns scaled to unit norm has a Cholesky factorisation."""
+    of Y with its columns scaled to unit norm has a Cholesky factorisation L L^t whose pivots
+    L_ii^2 are all at least 1e-10."""
     d = np.linalg.norm(Y, axis=0)
     if np.any(d < 1e-8 * np.linalg.norm(Y0, axis=0)) or np.any(d == 0.0):
         return False
     Ys = Y / d[None, :]
     try:
-        np.linalg.cholesky(Ys.T @ Ys)
+        L = np.linalg.cholesky(Ys.T @ Ys)
     except np.linalg.LinAlgError:
         return False
-    return True
+    return bool(np.min(np.diag(L)) ** 2 >= 1e-10)
 
 
 def orthonormal_basis(Y):
@@ -725,7 +729,8 @@ def lobpcg_ritz(A, kind, target, n_b, X, W, P):
     QU = [orthonormal_basis(left[0])]
     QU.append(orthonormal_basis(remove_components(left[1], QU)))
     kept = False
-    if P is not None:
+    moving = P is not None and all(np.linalg.norm(B, axis=0).min() >= 1e-10 for B in P if B is not None)
+    if moving:
         PV = None if kind == SPD else remove_components(P[1], QV)
         okv = kind == SPD or keep_direction(P[1], PV)
         PU0 = A @ orthonormal_basis(PV) if one_sided and okv else P[0]
