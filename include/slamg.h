@@ -134,6 +134,16 @@ typedef struct {
                                multiplicative cycle, after each coarse level's boot relaxation, the
                                boot triplets become the Ritz triplets of their span in the B and C
                                metrics (0)                                                       */
+  int32_t solve_phase;      /* 0 the multigrid-Ritz additive phase of §4; 1 LOBPCG on the learned
+                               hierarchy (§7 names it as a replacement): the preconditioned
+                               direction of a pair is the change the additive cycle makes to it,
+                               and the Ritz step of §4.3 runs on the span of the pairs, those
+                               directions and the previous search directions (3 n_b columns; the
+                               previous directions are left out in an iteration where they are
+                               numerically dependent on the others).  Minimal SVD targets take
+                               the left basis from A times the right one.  Iterations run
+                               without graph replay (0)                                         */
+  int32_t reserved3;
 } slamg_params;
 
 /* Report of one solve.  Arrays are filled up to the counts given. */
@@ -156,6 +166,9 @@ typedef struct {
   int32_t redo_count;                        /* redetermined interpolations (redo_p)            */
   int64_t device_bytes;                      /* peak device memory the solve held (all levels)  */
   double t_queue_ms, t_latency_ms;           /* requests: submit -> start, submit -> result      */
+  int32_t p_dropped;                         /* LOBPCG iterations that left out the previous
+                                                search directions (solve_phase 1)              */
+  int32_t reserved_r;
 } slamg_report;
 
 typedef struct slamg_ctx slamg_ctx;

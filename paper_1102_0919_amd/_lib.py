@@ -36,7 +36,8 @@ class Params(C.Structure):
                 ("n_guard", C.c_int32), ("mu_tJ", C.c_int32), ("mu_bJ", C.c_int32),
                 ("kaczmarz_order", C.c_int32), ("coarse_dense_max", C.c_int32),
                 ("redo_p", C.c_int32), ("redo_tol", C.c_double), ("cycle_gamma", C.c_int32),
-                ("ritz_coarse", C.c_int32)]
+                ("ritz_coarse", C.c_int32),
+                ("solve_phase", C.c_int32), ("reserved3", C.c_int32)]
 
 
 class Report(C.Structure):
@@ -47,7 +48,8 @@ class Report(C.Structure):
                 ("mult_sigma", (C.c_double * 16) * 32), ("t_setup_ms", C.c_double), ("t_solve_ms", C.c_double),
                 ("err_bound", C.c_double * 16), ("prof_ms", C.c_double * 8), ("prof_launches", C.c_int64 * 8),
                 ("prof_bytes", C.c_double * 8), ("graph_iters", C.c_int32), ("redo_count", C.c_int32),
-                ("device_bytes", C.c_int64), ("t_queue_ms", C.c_double), ("t_latency_ms", C.c_double)]
+                ("device_bytes", C.c_int64), ("t_queue_ms", C.c_double), ("t_latency_ms", C.c_double),
+                ("p_dropped", C.c_int32), ("reserved_r", C.c_int32)]
 
 
 _P = C.c_void_p

@@ -244,4 +244,5 @@ def report_dict(rep: L.Report) -> dict:
                 nnz=[int(rep.nnz[i]) for i in range(max(lv, 1))],
                 colours=[int(rep.colours[i]) for i in range(max(lv, 1))],
                 anorm=rep.anorm, t_setup_ms=rep.t_setup_ms, t_solve_ms=rep.t_solve_ms,
-                rho_history=[rep.rho_history[i] for i in range(min(rep.add_iters + 1, 256))])
+                rho_history=[rep.rho_history[i] for i in range(min(rep.add_iters + 1, 256))],
+                p_dropped=rep.p_dropped)

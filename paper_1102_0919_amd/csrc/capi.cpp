@@ -109,6 +109,7 @@ extern "C" slamg_status slamg_params_init(slamg_params* p, slamg_kind kind, slam
   p->redo_tol = 1e-14;
   p->cycle_gamma = 1;
   p->ritz_coarse = 0;
+  p->solve_phase = 0;
   (void)target;
   return SLAMG_OK;
 }
@@ -273,6 +274,7 @@ static slamg_status check_params(std::string& err, const Prepared& P, int32_t nb
   if (p.redo_p && !(p.redo_tol > 0.0 && p.redo_tol < 1.0)) return fail(err, SLAMG_E_INVALID, "redo_tol must lie in (0, 1)");
   if (p.cycle_gamma != 1 && p.cycle_gamma != 2) return fail(err, SLAMG_E_INVALID, "cycle_gamma must be 1 or 2");
   if (p.ritz_coarse != 0 && p.ritz_coarse != 1) return fail(err, SLAMG_E_INVALID, "ritz_coarse must be 0 or 1");
+  if (p.solve_phase != 0 && p.solve_phase != 1) return fail(err, SLAMG_E_INVALID, "solve_phase must be 0 or 1");
   if (!(p.tol > 0.0)) return fail(err, SLAMG_E_INVALID, "tol must be positive");
   if (p.n_t < 2 || p.n_t > 16) return fail(err, SLAMG_E_INVALID, "n_t must be in 2..16");
   if (p.mu_t < 0 || p.mu_b < 0 || p.n_mult < 1 || p.max_add < 0) return fail(err, SLAMG_E_INVALID, "bad counts");
@@ -557,8 +559,10 @@ static size_t footprint_estimate(int64_t m, int64_t n, int64_t nnz, slamg_kind k
   const double w = (double)(4 * p.n_t + 12 * blk);
   // SVD: the strength products' entries pass through the device in chunks of 2^25 (16 B each)
   const double strength = kind == SLAMG_SVD ? 16.0 * std::min(33554432.0, 64.0 * (double)nnz) : 0.0;
+  // LOBPCG: six further blocks per side
+  const double lob = p.solve_phase == 1 ? 48.0 * rows * blk : 0.0;
   const double bytes = 64.0 * 1024 * 1024 + 400.0 * (double)nnz + 8.0 * rows * w * 2.0 +
-                       8.0 * (3.0 * blk + 10.0) * nc * nc + strength;
+                       8.0 * (3.0 * blk + 10.0) * nc * nc + strength + lob;
   return (size_t)bytes;
 }
 

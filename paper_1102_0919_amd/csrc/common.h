@@ -178,6 +178,13 @@ void launch_scale_cols(int rows, int w, T* X, const double* d, int mode, hipStre
 void launch_rq_update(int w, const double* num, const double* nu, const double* nv, double* sig,
                       double* flip, hipStream_t s);
 void launch_fill(double* p, size_t n, double val, hipStream_t s);
+void launch_axpby(size_t n, double a, const double* x, double b, const double* y, double* out, hipStream_t s);
+// out = Y + alpha X S (rows x w blocks, S w x w row-major, w <= 16); out may be Y, not X
+void launch_rotate_acc(int rows, int w, const double* X, const double* S, double alpha, const double* Y, double* out,
+                       hipStream_t s);
+// a w x w block G into the ld-wide row-major M at (r0, c0); sym also at (c0, r0) transposed
+void launch_place_block(int w, const double* G, double* M, int ld, int r0, int c0, int sym, hipStream_t s);
+void launch_eye(int k, double* M, hipStream_t s);
 void launch_fillf(float* p, size_t n, float val, hipStream_t s);
 void launch_copy_cast_df(const double* in, float* out, size_t n, hipStream_t s);
 // FP64 -> BF16 bit patterns (out: n 16-bit words), rounded to FP32 and then to the nearest BF16
@@ -207,6 +214,9 @@ void launch_rq_weights(int nf, const double* num, const double* nu, const double
 
 // dense.hip (single-workgroup dense FP64 procedures)
 void launch_chol_inv_upper(int w, const double* G, double* T, int* status, hipStream_t s);
+// the same; *pivot_min = the smallest pivot of the unshifted factorisation of the column-scaled
+// matrix, -1 when it failed
+void launch_chol_inv_upper_pivot(int w, const double* G, double* T, int* status, double* pivot_min, hipStream_t s);
 // two factorisations (G0 -> T0, G1 -> T1) in one launch
 void launch_chol_inv_upper2(int w, const double* G0, double* T0, const double* G1, double* T1, int* status,
                             hipStream_t s);

@@ -1303,6 +1303,64 @@ void launch_fillf(float* p, size_t n, float val, hipStream_t s) {
   if (n) hipLaunchKernelGGL((k_fill<float>), dim3(ceil_div((long)n, BLK)), dim3(BLK), 0, s, p, n, val);
 }
 
+// out = a x + b y, elementwise
+__global__ void k_axpby(size_t n, double a, const double* __restrict__ x, double b, const double* __restrict__ y,
+                        double* __restrict__ out) {
+  size_t t = (size_t)blockIdx.x * BLK + threadIdx.x;
+  if (t < n) out[t] = a * x[t] + b * y[t];
+}
+void launch_axpby(size_t n, double a, const double* x, double b, const double* y, double* out, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_axpby, dim3(ceil_div((long)n, BLK)), dim3(BLK), 0, s, n, a, x, b, y, out);
+}
+
+// out = Y + alpha X S for rows x w blocks (S: w x w row-major, w <= 16); out may be Y, not X
+__global__ __launch_bounds__(BLK) void k_rotate_acc(int rows, int w, const double* __restrict__ X,
+                                                    const double* __restrict__ S, double alpha, const double* Y,
+                                                    double* out) {
+  __shared__ double Ss[16 * 16];
+  for (int t = threadIdx.x; t < w * w; t += BLK) Ss[t] = S[t];
+  __syncthreads();
+  const unsigned t = (unsigned)blockIdx.x * BLK + threadIdx.x;
+  const unsigned row = t / (unsigned)w;
+  const int c = (int)(t - row * (unsigned)w);
+  if (row >= (unsigned)rows) return;
+  const double* xr = X + (long)row * w;
+  double acc = 0.0;
+  for (int k = 0; k < w; ++k) acc += xr[k] * Ss[k * w + c];
+  const long o = (long)row * w + c;
+  out[o] = Y[o] + alpha * acc;
+}
+void launch_rotate_acc(int rows, int w, const double* X, const double* S, double alpha, const double* Y, double* out,
+                       hipStream_t s) {
+  if (rows <= 0) return;
+  if (w < 1 || w > 16 || (long)rows * w >= (1L << 31)) throw SolverError{ST_E_INVALID, "rotation shape"};
+  hipLaunchKernelGGL(k_rotate_acc, dim3(ceil_div((long)rows * w, BLK)), dim3(BLK), 0, s, rows, w, X, S, alpha, Y,
+                     out);
+}
+
+// M[r0 + i][c0 + j] = G[i][j] for a w x w block of the ld-wide row-major M; sym also writes
+// M[c0 + j][r0 + i]
+__global__ void k_place_block(int w, const double* __restrict__ G, double* __restrict__ M, int ld, int r0, int c0,
+                              int sym) {
+  const int t = (int)threadIdx.x;
+  if (t >= w * w) return;
+  const int i = t / w, j = t % w;
+  M[(long)(r0 + i) * ld + c0 + j] = G[t];
+  if (sym) M[(long)(c0 + j) * ld + r0 + i] = G[t];
+}
+void launch_place_block(int w, const double* G, double* M, int ld, int r0, int c0, int sym, hipStream_t s) {
+  hipLaunchKernelGGL(k_place_block, dim3(1), dim3(256), 0, s, w, G, M, ld, r0, c0, sym);
+}
+
+// k x k identity, row-major
+__global__ void k_eye(int k, double* M) {
+  const long t = (long)blockIdx.x * BLK + threadIdx.x;
+  if (t < (long)k * k) M[t] = (t / k == t % k) ? 1.0 : 0.0;
+}
+void launch_eye(int k, double* M, hipStream_t s) {
+  if (k > 0) hipLaunchKernelGGL(k_eye, dim3(ceil_div((long)k * k, BLK)), dim3(BLK), 0, s, k, M);
+}
+
 template <typename A, typename B>
 __global__ void k_cast(const A* in, B* out, size_t n) {
   size_t t = (size_t)blockIdx.x * BLK + threadIdx.x;

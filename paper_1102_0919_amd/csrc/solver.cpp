@@ -272,6 +272,11 @@ class Solver {
   void additive_iteration();
   void ritz();
   void ritz_level(int l);
+  void lobpcg_setup();
+  void lobpcg_iteration();
+  void lob_remove(double* Y, int rows, std::initializer_list<const double*> bases);
+  bool lob_pcheck(const double* P0, double* Pq, int rows, std::initializer_list<const double*> bases, double* tmp,
+                  const char* side);
   void cholqr2(double* X, int rows, double* tmp, double* out);
   void cholqr2_pair(double* Xa, int rows_a, double* tmpa, double* outa, double* Xb, int rows_b, double* tmpb,
                     double* outb);
@@ -338,6 +343,16 @@ class Solver {
   bool redo_weights_ = false;
   double* redo_keep_ = nullptr;
   double* pencil_wk_ = nullptr;
+  // LOBPCG solve phase (§7): per side the old X, the W, P and projected-P blocks, an operator
+  // product and a Cholesky-QR temporary (rows x n_b each), the k x k projected problem
+  struct LobSide {
+    double *X = nullptr, *W = nullptr, *P = nullptr, *Pq = nullptr, *T = nullptr, *tmp = nullptr;
+  };
+  LobSide lbu_, lbv_;
+  double *lobM_ = nullptr, *lobB_ = nullptr, *lobC_ = nullptr, *lobY_ = nullptr, *lobZ_ = nullptr;
+  double *lobwork_ = nullptr, *lobchk_ = nullptr;   // lobchk_: two Gram matrices and a pivot
+  int* lobflag_ = nullptr;   // status of the P blocks' factorisations (a failure only drops P)
+  bool lob_have_p_ = false;
   double *dX_ = nullptr, *dY_ = nullptr, *dwork_ = nullptr, *dA_ = nullptr, *dB_ = nullptr, *dC_ = nullptr;
   double *mu_ = nullptr, *Zp_ = nullptr;
   bool pencil_ready_ = false;
@@ -1905,6 +1920,169 @@ void Solver::ritz_level(int l) {
   }
 }
 
+// ------------------------------------------------------------------------------------------------
+// LOBPCG solve phase on the learned hierarchy (§7 names it as a replacement of the multigrid-Ritz
+// additive phase).  The preconditioned direction of a column is the change the additive cycle
+// makes to it, W = C(X) - X; the Ritz step runs on span[X, W, P] with P the previous search
+// direction.  Bases block by block: Cholesky-QR2 of X; W with its X components removed (two
+// passes), Cholesky-QR2; P with its X and W components removed (two passes), kept only when every
+// column of P (a part of a unit Ritz vector) has norm at least 1e-10 on each side, every column
+// keeps at least 1e-8 of its norm and the unshifted Cholesky factorisation of its
+// column-scaled Gram matrix has no pivot below 1e-10 (a condition number below about 1e5, so that
+// rounding does not decide).  SVD: both sides, P kept on both or neither; for minimal
+// targets the left blocks are those of A Q_v (a two-sided projection of the enlarged spaces has
+// singular values below sigma_min(A)).  The k x k projected problem (k = 2 n_b or 3 n_b) goes to
+// the dense solver of the coarsest level with identity metrics; the new P is the part of each
+// new Ritz vector in the W and P blocks.
+// ------------------------------------------------------------------------------------------------
+void Solver::lobpcg_setup() {
+  Level& L = *lv_[0];
+  const size_t nu = (size_t)rows_u(L) * nb_, nv = (size_t)rows_v(L) * nb_;
+  auto side = [&](LobSide& b, size_t n) {
+    for (double** f : {&b.X, &b.W, &b.P, &b.Pq, &b.T, &b.tmp}) *f = ar_.alloc<double>(n);
+  };
+  side(lbu_, nu);
+  if (!spd_) side(lbv_, nv);
+  const int kmax = 3 * nb_;
+  lobM_ = ar_.alloc<double>((size_t)kmax * kmax);
+  lobB_ = ar_.alloc<double>((size_t)kmax * kmax);
+  lobC_ = ar_.alloc<double>((size_t)kmax * kmax);
+  lobY_ = ar_.alloc<double>((size_t)kmax * nb_);
+  lobZ_ = ar_.alloc<double>((size_t)kmax * nb_);
+  lobwork_ = ar_.alloc<double>((size_t)8 * kmax * kmax + 64 * kmax + 64);
+  lobchk_ = ar_.alloc<double>(512);
+  lobflag_ = ar_.alloc<int>(4);
+  HIPCHK(hipMemsetAsync(lobchk_, 0, 512 * sizeof(double), st_));
+  lob_have_p_ = false;
+}
+
+// Y minus its components along the orthonormal blocks, two passes
+void Solver::lob_remove(double* Y, int rows, std::initializer_list<const double*> bases) {
+  for (int pass = 0; pass < 2; ++pass)
+    for (const double* Q : bases) {
+      launch_gram(rows, nb_, Q, Y, partial_, gram_, st_);   // Q^t Y
+      launch_rotate_acc(rows, nb_, Q, gram_, -1.0, Y, Y, st_);
+    }
+}
+
+// Pq (a copy of P0) projected and orthonormalised; returns whether the P block is kept
+bool Solver::lob_pcheck(const double* P0, double* Pq, int rows, std::initializer_list<const double*> bases,
+                        double* tmp, const char* side) {
+  const size_t w2 = (size_t)nb_ * nb_;
+  launch_gram(rows, nb_, P0, P0, partial_, gram_, st_);
+  HIPCHK(hipMemcpyAsync(lobchk_, gram_, w2 * sizeof(double), hipMemcpyDeviceToDevice, st_));
+  lob_remove(Pq, rows, bases);
+  launch_gram(rows, nb_, Pq, Pq, partial_, gram_, st_);
+  HIPCHK(hipMemcpyAsync(lobchk_ + 256, gram_, w2 * sizeof(double), hipMemcpyDeviceToDevice, st_));
+  // Cholesky-QR2; a failed factorisation only drops the block (status into lobflag_)
+  launch_chol_inv_upper_pivot(nb_, gram_, small1_, lobflag_, lobchk_ + 511, st_);
+  launch_rotate<double>(rows, nb_, nb_, Pq, small1_, tmp, st_);
+  launch_gram(rows, nb_, tmp, tmp, partial_, gram_, st_);
+  launch_chol_inv_upper(nb_, gram_, small1_, lobflag_, st_);
+  launch_rotate<double>(rows, nb_, nb_, tmp, small1_, Pq, st_);
+  std::vector<double> h;
+  d2h(h, lobchk_, 512, st_);
+  double ratio = 1.0;
+  for (int j = 0; j < nb_; ++j) {
+    const double g0 = h[(size_t)j * nb_ + j], g = h[256 + (size_t)j * nb_ + j];
+    ratio = g > 0.0 ? std::min(ratio, std::sqrt(g / g0)) : 0.0;
+    if (!(g > 0.0)) break;
+  }
+  const double piv = h[511];
+  const bool keep = ratio >= 1e-8 && piv >= 1e-10;
+  if (p_.verbose >= 2) {
+    std::fprintf(stderr, "[slamg] LOBPCG %s-side search directions: smallest kept norm fraction %.3e, smallest pivot %.3e%s\n",
+                 side, ratio, piv, keep ? "" : ", left out");
+    std::fflush(stderr);
+  }
+  return keep;
+}
+
+void Solver::lobpcg_iteration() {
+  Level& L = *lv_[0];
+  auto& b = L.bd;
+  const int mu = rows_u(L), mv = rows_v(L);
+  const size_t nu = (size_t)mu * nb_, nv = (size_t)mv * nb_;
+  const bool svd = !spd_, one_sided = svd && minimal_;
+  HIPCHK(hipMemcpyAsync(lbu_.X, b.Ub, nu * sizeof(double), hipMemcpyDeviceToDevice, st_));
+  if (svd) HIPCHK(hipMemcpyAsync(lbv_.X, b.Vb, nv * sizeof(double), hipMemcpyDeviceToDevice, st_));
+  additive_iteration();
+  launch_axpby(nu, 1.0, b.Ub, -1.0, lbu_.X, lbu_.W, st_);   // W = C(X) - X
+  if (svd) {
+    launch_axpby(nv, 1.0, b.Vb, -1.0, lbv_.X, lbv_.W, st_);
+    cholqr2(lbv_.X, mv, lbv_.tmp, lbv_.X);
+    lob_remove(lbv_.W, mv, {lbv_.X});
+    cholqr2(lbv_.W, mv, lbv_.tmp, lbv_.W);
+  }
+  if (one_sided) {
+    spmm<double>(0, L.A, L.A.v, nb_, lbv_.X, lbu_.X, 0.0);
+    spmm<double>(0, L.A, L.A.v, nb_, lbv_.W, lbu_.W, 0.0);
+  }
+  cholqr2(lbu_.X, mu, lbu_.tmp, lbu_.X);
+  lob_remove(lbu_.W, mu, {lbu_.X});
+  cholqr2(lbu_.W, mu, lbu_.tmp, lbu_.W);
+  bool keep = false;
+  if (lob_have_p_) {
+    // columns of P at least 1e-10 on each side (a smaller one: a Ritz vector that no longer moves)
+    const size_t w2 = (size_t)nb_ * nb_;
+    launch_gram(mu, nb_, lbu_.P, lbu_.P, partial_, gram_, st_);
+    HIPCHK(hipMemcpyAsync(lobchk_, gram_, w2 * sizeof(double), hipMemcpyDeviceToDevice, st_));
+    if (svd) {
+      launch_gram(mv, nb_, lbv_.P, lbv_.P, partial_, gram_, st_);
+      HIPCHK(hipMemcpyAsync(lobchk_ + 256, gram_, w2 * sizeof(double), hipMemcpyDeviceToDevice, st_));
+    }
+    std::vector<double> h;
+    d2h(h, lobchk_, 512, st_);
+    bool moving = true;
+    for (int j = 0; j < nb_; ++j) {
+      moving = moving && h[(size_t)j * nb_ + j] >= 1e-20;
+      if (svd) moving = moving && h[256 + (size_t)j * nb_ + j] >= 1e-20;
+    }
+    bool okv = moving;
+    if (svd && moving) {
+      HIPCHK(hipMemcpyAsync(lbv_.Pq, lbv_.P, nv * sizeof(double), hipMemcpyDeviceToDevice, st_));
+      okv = lob_pcheck(lbv_.P, lbv_.Pq, mv, {lbv_.X, lbv_.W}, lbv_.tmp, "V");
+    }
+    if (okv && moving) {
+      const double* P0 = lbu_.P;
+      if (one_sided) {
+        spmm<double>(0, L.A, L.A.v, nb_, lbv_.Pq, lbu_.T, 0.0);
+        P0 = lbu_.T;
+      }
+      HIPCHK(hipMemcpyAsync(lbu_.Pq, P0, nu * sizeof(double), hipMemcpyDeviceToDevice, st_));
+      keep = lob_pcheck(P0, lbu_.Pq, mu, {lbu_.X, lbu_.W}, lbu_.tmp, svd ? "U" : "X");
+    }
+    if (!keep) ++rep_.p_dropped;
+  }
+  const int nblk = keep ? 3 : 2, k = nblk * nb_;
+  const double* Qu[3] = {lbu_.X, lbu_.W, lbu_.Pq};
+  const double* Qv[3] = {svd ? lbv_.X : lbu_.X, svd ? lbv_.W : lbu_.W, svd ? lbv_.Pq : lbu_.Pq};
+  for (int c = 0; c < nblk; ++c) {
+    spmm<double>(0, L.A, L.A.v, nb_, Qv[c], lbu_.T, 0.0);   // A Q_c
+    for (int a = 0; a < nblk; ++a) {
+      if (!svd && a > c) continue;   // symmetric: block (c, a) is the transpose of (a, c)
+      launch_gram(mu, nb_, Qu[a], lbu_.T, partial_, gram_, st_);
+      launch_place_block(nb_, gram_, lobM_, k, a * nb_, c * nb_, !svd && a != c, st_);
+    }
+  }
+  launch_eye(k, lobB_, st_);
+  if (svd) launch_eye(k, lobC_, st_);
+  launch_coarse_gsvd(spd_, minimal_, k, k, nb_, lobM_, lobB_, svd ? lobC_ : nullptr, lobwork_, sig_, lobY_,
+                     svd ? lobZ_ : nullptr, status_, st_);
+  // new Ritz vectors Q Y and search directions (the W and P block parts)
+  const size_t w2 = (size_t)nb_ * nb_;
+  auto update = [&](const double* const* Q, const double* Y, int rows, double* X, double* P) {
+    launch_rotate<double>(rows, nb_, nb_, Q[0], Y, X, st_);
+    launch_rotate<double>(rows, nb_, nb_, Q[1], Y + w2, P, st_);
+    if (nblk == 3) launch_rotate_acc(rows, nb_, Q[2], Y + 2 * w2, 1.0, P, P, st_);
+    launch_axpby((size_t)rows * nb_, 1.0, X, 1.0, P, X, st_);
+  };
+  update(Qu, lobY_, mu, b.Ub, lbu_.P);
+  if (svd) update(Qv, lobZ_, mv, b.Vb, lbv_.P);
+  lob_have_p_ = true;
+  residual_launch();
+}
+
 // rho_j = max(||A v_j - s_j u_j||, ||A^t u_j - s_j v_j||) / ||A||_est  (unit vectors after Ritz)
 void Solver::residual_launch() {
   Level& L = *lv_[0];
@@ -2174,7 +2352,8 @@ void Solver::run(const double* init_tests, SolveOutput& out) {
   if (mixed_) cast_transfers();
   for (auto& Lp : lv_) long_rows(*Lp);   // before any capture
   int it = 0, it0 = 0;
-  graph_off_ = !p_.graphs;
+  graph_off_ = !p_.graphs || p_.solve_phase == 1;   // LOBPCG decides on P on the host
+  if (p_.solve_phase == 1) lobpcg_setup();
   // redetermined interpolation (§6.3): pairs whose sigma has settled, and the previous sigma
   std::vector<char> conv(nb_, 0);
   std::vector<double> sprev, snow;
@@ -2192,6 +2371,8 @@ void Solver::run(const double* init_tests, SolveOutput& out) {
       HIPCHK(hipGraphLaunch(igx_, st_));
       if (p_.coarse_pinv == 0) pinv_calls_ += coarse_calls_per_iter();
       ++rep_.graph_iters;
+    } else if (p_.solve_phase == 1) {
+      lobpcg_iteration();
     } else {
       iteration_body();
     }
