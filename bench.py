@@ -186,6 +186,10 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed_fp32", "mixed_bf16"])
     ap.add_argument("--compare", default="mixed_fp32", choices=["none", "fp64", "mixed_fp32", "mixed_bf16"],
                     help="second precision timed on the same workload and reported next to the headline")
+    ap.add_argument("--solve-phase", type=int, default=0, choices=[0, 1],
+                    help="0 the multigrid-Ritz additive phase (the method's own), 1 LOBPCG on the learned hierarchy")
+    ap.add_argument("--no-alt-phase", action="store_true",
+                    help="skip timing the other solve phase (FP64) next to the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--max-add", type=int, default=6000,
@@ -207,9 +211,10 @@ def main():
     kind, target, n_b = wl["kind"], wl["target"], wl["n_b"]
     stream = torch.cuda.current_stream()
 
-    def params(precision, mask, graphs=1):
+    def params(precision, mask, graphs=1, phase=None):
         prm = dict(wl["params"])
         prm["precision"] = precision
+        prm["solve_phase"] = args.solve_phase if phase is None else phase
         prm["profile_mask"] = mask
         prm["max_add"] = args.max_add
         prm["graphs"] = graphs
@@ -278,6 +283,19 @@ def main():
         if ref is not None:
             compare["accuracy"]["max_rel_sigma_diff_vs_headline"] = float(
                 np.max(np.abs(last2.sigma - last.sigma) / np.abs(ref)))
+    alt = None
+    if not args.no_alt_phase:
+        ph = 1 - args.solve_phase
+        p3 = params("fp64", 0, phase=ph)
+        w3 = api.solve_matrix(ctx, mat, target, n_b, p3, U_dev=U_dev, V_dev=V_dev)
+        print(f"[bench] solve phase {ph} warmup: add_iters={w3.report.add_iters} converged={w3.converged}",
+              file=sys.stderr, flush=True)
+        reps3, ms3 = _run_steps(api, ctx, mat, target, n_b, p3, U_dev, V_dev, args.steps, f"phase {ph}")
+        last3 = reps3[-1]
+        alt = {"solve_phase": ph, "name": ["multigrid-Ritz", "LOBPCG"][ph], "precision": "fp64",
+               "value": round(n_b / (ms3 / 1e3), 4), "unit": "triplets/s", "ms_per_step": round(ms3, 3),
+               "speedup_vs_headline": round(ms / ms3, 4), "setup_ms": round(last3.report.t_setup_ms, 3),
+               "solve_ms": round(last3.report.t_solve_ms, 3), "accuracy": _accuracy(last3, ref, n_b)}
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(name, A, wl, int(last.report.add_iters))
@@ -288,10 +306,11 @@ def main():
             "data": "synthetic",
             "config": {"workload": name, "description": wl["desc"], "rows": int(A.shape[0]),
                        "cols": int(A.shape[1]), "nnz": int(A.nnz), "n_b": n_b, "kind": kind, "target": target,
-                       "precision": args.precision, "tol": 1e-8},
+                       "precision": args.precision, "tol": 1e-8,
+                       "solve_phase": ["multigrid-Ritz", "LOBPCG"][args.solve_phase]},
             "roofline": roof, "cpu_baseline": cpu, "accuracy": _accuracy(last, ref, n_b),
             "setup_ms": round(last.report.t_setup_ms, 3), "solve_ms": round(last.report.t_solve_ms, 3),
-            "compare": compare}
+            "compare": compare, "alt_phase": alt}
     mat.close()
     ctx.close()
     print(json.dumps(line))
