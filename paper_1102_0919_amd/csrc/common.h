@@ -185,6 +185,8 @@ void launch_rotate_acc(int rows, int w, const double* X, const double* S, double
 // a w x w block G into the ld-wide row-major M at (r0, c0); sym also at (c0, r0) transposed
 void launch_place_block(int w, const double* G, double* M, int ld, int r0, int c0, int sym, hipStream_t s);
 void launch_eye(int k, double* M, hipStream_t s);
+// rowC[k] = i for the entries k of row i of an m-row CSR pattern
+void launch_row_index(int m, const int* rp, int* rowC, hipStream_t s);
 void launch_fillf(float* p, size_t n, float val, hipStream_t s);
 void launch_copy_cast_df(const double* in, float* out, size_t n, hipStream_t s);
 // FP64 -> BF16 bit patterns (out: n 16-bit words), rounded to FP32 and then to the nearest BF16

@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdint>
 #include <exception>
+#include <functional>
 #include <memory>
 #include <queue>
 #include <stdexcept>
@@ -41,12 +42,20 @@ static void build_rows(int n, std::vector<int>& rp, std::vector<int>& ci, M make
       const int r0 = (int)((long)n * t / nt), r1 = (int)((long)n * (t + 1) / nt);
       auto row_fn = make_row();
       len[t].resize(r1 - r0);
-      for (int i = r0; i < r1 && !too_large.load(std::memory_order_relaxed); ++i) {
+      // the shared entry count is updated every 4096 rows (a per-row atomic on one cache line
+      // serialises the threads)
+      size_t pending = 0;
+      for (int i = r0; i < r1; ++i) {
         const size_t before = part[t].size();
         row_fn(i, part[t]);
         const size_t got = part[t].size() - before;
         len[t][i - r0] = (int)got;
-        if (built.fetch_add(got, std::memory_order_relaxed) + got > MAX_PATTERN_ENTRIES) too_large = true;
+        pending += got;
+        if (((i - r0) & 4095) == 4095 || i + 1 == r1 || pending > MAX_PATTERN_ENTRIES) {
+          if (built.fetch_add(pending, std::memory_order_relaxed) + pending > MAX_PATTERN_ENTRIES) too_large = true;
+          pending = 0;
+          if (too_large.load(std::memory_order_relaxed)) break;
+        }
       }
     } catch (...) {
       err[t] = std::current_exception();
@@ -130,21 +139,45 @@ std::vector<char> rs_coarsen(const std::vector<int>& Sp, const std::vector<int>&
     for (int j = 0; j < n; ++j)
       for (int k = Sp[j]; k < Sp[j + 1]; ++k) Ti[pos[Si[k]]++] = j;
   }
-  std::vector<long> lam(n);
-  for (int i = 0; i < n; ++i) lam[i] = Tp[i + 1] - Tp[i];
+  std::vector<int> lam(n);
+  int lmax = 0;
+  for (int i = 0; i < n; ++i) {
+    lam[i] = Tp[i + 1] - Tp[i];
+    lmax = std::max(lmax, lam[i]);
+  }
   std::vector<char> state(n, 0);   // 0 undecided, 1 C, 2 F
-  // max-heap on (lambda, -index), packed into one 64-bit key: lambda in the high word, the
-  // complement of the index in the low word (the largest key is the lowest index among maximal
-  // lambda); stale entries are skipped when popped
-  auto key = [](long l, int i) { return ((uint64_t)l << 32) | (uint64_t)(uint32_t)(INT32_MAX - i); };
-  std::vector<uint64_t> init(n);
-  for (int i = 0; i < n; ++i) init[i] = key(lam[i], i);
-  std::priority_queue<uint64_t> heap(std::less<uint64_t>(), std::move(init));
-  while (!heap.empty()) {
-    const uint64_t top = heap.top();
-    heap.pop();
-    const int i = INT32_MAX - (int)(uint32_t)(top & 0xffffffffu);
-    if (state[i] != 0 || (long)(top >> 32) != lam[i]) continue;
+  // Buckets by lambda.  Bucket l holds the points whose lambda started at l, in index order (a
+  // counting sort, consumed through a cursor), and a min-heap of the points whose lambda grew to
+  // l.  An entry is valid while its point is undecided and still has that lambda; the next C-point
+  // is the lowest valid index of the highest bucket with a valid entry, the order a max-heap on
+  // (lambda, -index) gives.
+  std::vector<int> bstart(lmax + 2, 0), members(n);
+  for (int i = 0; i < n; ++i) bstart[lam[i] + 1]++;
+  for (int l = 0; l <= lmax; ++l) bstart[l + 1] += bstart[l];
+  std::vector<int> cursor(bstart.begin(), bstart.end() - 1);
+  {
+    std::vector<int> pos(cursor);
+    for (int i = 0; i < n; ++i) members[pos[lam[i]]++] = i;
+  }
+  using MinHeap = std::priority_queue<int, std::vector<int>, std::greater<int>>;
+  std::vector<MinHeap> grown(lmax + 1);
+  auto valid = [&](int i, int l) { return state[i] == 0 && lam[i] == l; };
+  int top = lmax;
+  while (top >= 0) {
+    const int l = top;
+    const int cend = l + 1 < (int)bstart.size() ? bstart[l + 1] : 0;
+    int& cur = cursor[l];   // buckets above lmax start empty
+    while (l <= lmax && cur < cend && !valid(members[cur], l)) ++cur;
+    MinHeap& hp = grown[l];
+    while (!hp.empty() && !valid(hp.top(), l)) hp.pop();
+    const bool from_init = l <= lmax && cur < cend;
+    if (!from_init && hp.empty()) {
+      --top;
+      continue;
+    }
+    int i;
+    if (from_init && (hp.empty() || members[cur] < hp.top())) i = members[cur++];
+    else { i = hp.top(); hp.pop(); }
     state[i] = 1;
     for (int t = Tp[i]; t < Tp[i + 1]; ++t) {
       const int j = Ti[t];
@@ -153,8 +186,13 @@ std::vector<char> rs_coarsen(const std::vector<int>& Sp, const std::vector<int>&
       for (int k = Sp[j]; k < Sp[j + 1]; ++k) {
         const int kk = Si[k];
         if (state[kk] == 0) {
-          lam[kk] += 1;
-          heap.push(key(lam[kk], kk));
+          const int nl = ++lam[kk];
+          if (nl >= (int)grown.size()) {
+            grown.resize(nl + 1);
+            cursor.resize(nl + 1, 0);
+          }
+          grown[nl].push(kk);
+          top = std::max(top, nl);
         }
       }
     }

@@ -1352,6 +1352,16 @@ void launch_place_block(int w, const double* G, double* M, int ld, int r0, int c
   hipLaunchKernelGGL(k_place_block, dim3(1), dim3(256), 0, s, w, G, M, ld, r0, c0, sym);
 }
 
+// rowC[k] = i for every entry k of row i of a CSR pattern (one thread per row)
+__global__ void k_row_index(int m, const int* __restrict__ rp, int* __restrict__ rowC) {
+  const int i = (int)(blockIdx.x * BLK + threadIdx.x);
+  if (i >= m) return;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) rowC[k] = i;
+}
+void launch_row_index(int m, const int* rp, int* rowC, hipStream_t s) {
+  if (m > 0) hipLaunchKernelGGL(k_row_index, dim3(ceil_div((long)m, BLK)), dim3(BLK), 0, s, m, rp, rowC);
+}
+
 // k x k identity, row-major
 __global__ void k_eye(int k, double* M) {
   const long t = (long)blockIdx.x * BLK + threadIdx.x;

@@ -1121,14 +1121,12 @@ bool Solver::build_structure(int l) {
 void Solver::make_coarse_level(int l) {
   Level& L = *lv_[l];
   auto C = std::make_unique<Level>();
-  auto mkplan = [&](const HCsr& pat, const DCsr* Lm, const DCsr* Rt, double* out) {
+  // a plan over the device copy of its pattern: the row of every entry expanded on the device
+  auto mkplan = [&](const DCsr& pat, const DCsr* Lm, const DCsr* Rt, double* out) {
     Plan pl;
-    pl.nnz = pat.nnz();
-    std::vector<int> rowC(pl.nnz);
-    for (int i = 0; i < pat.m; ++i)
-      for (int k = pat.rp[i]; k < pat.rp[i + 1]; ++k) rowC[k] = i;
+    pl.nnz = pat.nnz;
     pl.rowC = ar_.alloc<int>(pl.nnz);
-    h2d(pl.rowC, rowC, st_);
+    launch_row_index(pat.m, pat.rp, pl.rowC, st_);
     pl.L = Lm; pl.Rt = Rt; pl.out = out;
     return pl;
   };
@@ -1147,11 +1145,11 @@ void Solver::make_coarse_level(int l) {
     C->B.v = ar_.alloc<double>(C->A.nnz);
     if (mixed_) C->B.vf = ar_.alloc<float>(C->A.nnz);
     L.plans.clear();
-    L.plans.push_back(mkplan(S1, &su.Pt, &L.A, L.S1.v));   // rows of P^t . rows of A (= A^t)
-    L.plans.push_back(mkplan(S1, &su.Pt, &L.B, L.S2.v));   // rows of P^t . rows of B
+    L.plans.push_back(mkplan(L.S1, &su.Pt, &L.A, L.S1.v));   // rows of P^t . rows of A (= A^t)
+    L.plans.push_back(mkplan(L.S1, &su.Pt, &L.B, L.S2.v));   // rows of P^t . rows of B
     // A_c, B_c: rows of S . rows of P^t (columns of P)
-    L.pAc = mkplan(Ac, &L.S1, &su.Pt, C->A.v);
-    L.pBc = mkplan(Ac, &L.S2, &su.Pt, C->B.v);
+    L.pAc = mkplan(C->A, &L.S1, &su.Pt, C->A.v);
+    L.pBc = mkplan(C->A, &L.S2, &su.Pt, C->B.v);
     L.pAc.colC = C->A.ci; L.pBc.colC = C->A.ci;
     L.plans[0].colC = L.S1.ci; L.plans[1].colC = L.S1.ci;
   } else {
@@ -1176,13 +1174,13 @@ void Solver::make_coarse_level(int l) {
     C->B = upload(Bc, false);
     C->C = upload(Cc, false);
     L.plans.clear();
-    L.plans.push_back(mkplan(S1, &su.Pt, &L.At, L.S1.v));  // (P^t A)_{I j} = P^t row I . A^t row j
-    L.plans.push_back(mkplan(S2, &su.Pt, &L.B, L.S2.v));   // B symmetric
-    L.plans.push_back(mkplan(S3, &sv.Pt, &L.C, L.S3.v));
+    L.plans.push_back(mkplan(L.S1, &su.Pt, &L.At, L.S1.v));  // (P^t A)_{I j} = P^t row I . A^t row j
+    L.plans.push_back(mkplan(L.S2, &su.Pt, &L.B, L.S2.v));   // B symmetric
+    L.plans.push_back(mkplan(L.S3, &sv.Pt, &L.C, L.S3.v));
     L.plans[0].colC = L.S1.ci; L.plans[1].colC = L.S2.ci; L.plans[2].colC = L.S3.ci;
-    L.pAc = mkplan(Ac, &L.S1, &sv.Pt, C->A.v); L.pAc.colC = C->A.ci;
-    L.pBc = mkplan(Bc, &L.S2, &su.Pt, C->B.v); L.pBc.colC = C->B.ci;
-    L.pCc = mkplan(Cc, &L.S3, &sv.Pt, C->C.v); L.pCc.colC = C->C.ci;
+    L.pAc = mkplan(C->A, &L.S1, &sv.Pt, C->A.v); L.pAc.colC = C->A.ci;
+    L.pBc = mkplan(C->B, &L.S2, &su.Pt, C->B.v); L.pBc.colC = C->B.ci;
+    L.pCc = mkplan(C->C, &L.S3, &sv.Pt, C->C.v); L.pCc.colC = C->C.ci;
   }
   rep_.rows[l + 1] = C->m;
   rep_.cols[l + 1] = C->n;

@@ -138,7 +138,7 @@ def test_bf16_reference_rounding_worked_values():
 
 
 def test_colouring_and_coarsening_bitexact_large(lib):
-    # colours and the C/F split of Algorithm 1 (a heap with packed keys) on larger and wider
+    # colours and the C/F split of Algorithm 1 (buckets by lambda) on larger and wider
     # patterns must equal the oracle's
     A = W.aniso3d(28, 0.01).to_scipy()
     G = sp.csr_matrix(O.structural_product(A, A))          # a wider, Galerkin-like pattern
@@ -150,9 +150,14 @@ def test_colouring_and_coarsening_bitexact_large(lib):
         col = np.zeros(m, np.int32)
         assert lib.slamg_graph_colour(m, n, _p(_i32(M.indptr)), _p(_i32(M.indices)), _p(col)) == 0
         assert np.array_equal(col, O.greedy_row_colouring(M))
-    N = sp.csr_matrix(A)
-    Sp, Si, _ = _strength(lib, N, 0.25, 1)
-    isc = np.zeros(N.shape[0], np.int8)
-    assert lib.slamg_graph_rs(N.shape[0], _p(Sp), _p(_i32(Si)), _p(isc)) == 0
-    oSp, oSi = O.strength_sets(N, 0.25, 1, 4)
-    assert np.array_equal(isc.astype(bool), O.rs_coarsen(oSp, oSi, N.shape[0]))
+    # Algorithm 1 on the stencil, on the wider pattern (many measures grow) and on a random square
+    # pattern with the row-sum rule
+    Rs = W.random_csr(16384, 16384, seed=5, mean_row=9).to_scipy()
+    Rs = sp.csr_matrix(Rs + Rs.T)
+    for N, theta, rule in ((sp.csr_matrix(A), 0.25, 1), (G, 0.25, 1), (Rs, 0.06, 0)):
+        N.sort_indices()
+        Sp, Si, _ = _strength(lib, N, theta, rule)
+        isc = np.zeros(N.shape[0], np.int8)
+        assert lib.slamg_graph_rs(N.shape[0], _p(Sp), _p(_i32(Si)), _p(isc)) == 0
+        oSp, oSi = O.strength_sets(N, theta, rule, 4)
+        assert np.array_equal(isc.astype(bool), O.rs_coarsen(oSp, oSi, N.shape[0]))
