@@ -97,6 +97,11 @@ the design notes of the repository):
       A v_j / sigma_j, which makes R23 redundant.  The n_b triplets ordered by the target are
       kept; the new P is the part of each new Ritz vector in the W and P blocks (orthogonal to
       the old X).
+  R37 FMG cycles (§3.3 names them, optional): the finest block's residual of (4.1) is restricted
+      through every level (no relaxation in between), the coarsest level is solved (§4.2), and
+      from the coarsest upwards every coarse level starts from the prolonged correction of the
+      level below it and runs one additive cycle (V or W) against its restricted residual; the
+      finest block adds the prolonged correction and runs one cycle.
 """
 from __future__ import annotations
 
@@ -148,6 +153,7 @@ class Params:
     cycle_gamma: int = 1          # R34: coarse visits per level in the additive cycle (1 V, 2 W)
     ritz_coarse: int = 0          # R35: Ritz step on the coarse levels of the multiplicative phase
     solve_phase: int = 0          # R36: 0 multigrid-Ritz additive phase (§4), 1 LOBPCG (§7)
+    fmg: int = 0                  # R37: FMG cycles in the additive phase (§3.3)
 
 
 REDO_DOWN = 1e-3                  # §6.3: LS weight factor of test vectors and converged pairs
@@ -1043,17 +1049,12 @@ class Solver:
         side.P = ls_interpolation(side.ptr, side.fine_cols, side.is_c, Vals, bvals, w)
 
     # -------------------------------------------------------------- additive cycle (§4.1-4.2)
-    def additive_vcycle(self):
-        """One additive cycle for all n_b columns with sigma fixed: a V-cycle (cycle_gamma 1) or,
-        with cycle_gamma 2, a W-cycle (§3.3, R34): every level above the last one before the
-        coarsest visits its coarse level twice, the second visit starting from the first one's
-        correction; the coarsest level is solved once per visit of the level above it."""
+    def _additive_cycle_fns(self):
+        """The pieces of the additive cycle with sigma fixed: cycle(l, U, V, kappa, tau) is one
+        visit of level l above the coarsest (§4.1-§4.3; cycle_gamma visits of the next level, R34),
+        coarsest(kappa, tau) the coarsest solve (§4.2)."""
         kind, target, p, sig = self.kind, self.target, self.p, self.sig
         L = len(self.levels) - 1
-        if L == 0:
-            # one level: the multiplicative phase's coarsest generalized SVD is already exact and
-            # there is no coarse correction to add
-            return
 
         def relax(l, U, V, kap, tau):
             lev = self.levels[l]
@@ -1078,13 +1079,7 @@ class Solver:
             lev = self.levels[l]
             U, V = relax(l, U, V, kap, tau)
             # residuals (4.1) and restriction (4.2)
-            if kind == SPD:
-                r = kap - (lev.A @ U - (lev.B @ U) * sig[None, :])
-                kc, tc = lev.su.P.T @ r, None
-            else:
-                r = kap - (lev.A @ V - (lev.B @ U) * sig[None, :])
-                t = tau - (lev.A.T @ U - (lev.C @ V) * sig[None, :])
-                kc, tc = lev.su.P.T @ r, lev.sv.P.T @ t
+            kc, tc = restrict(l, U, V, kap, tau)
             if l + 1 == L:
                 Uc, Vc = coarsest(kc, tc)
             else:
@@ -1097,15 +1092,72 @@ class Solver:
             V = None if kind == SPD else V + lev.sv.P @ Vc
             return relax(l, U, V, kap, tau)
 
+        def restrict(l, U, V, kap, tau):
+            lev = self.levels[l]
+            if kind == SPD:
+                r = kap - (lev.A @ U - (lev.B @ U) * sig[None, :])
+                return lev.su.P.T @ r, None
+            r = kap - (lev.A @ V - (lev.B @ U) * sig[None, :])
+            t = tau - (lev.A.T @ U - (lev.C @ V) * sig[None, :])
+            return lev.su.P.T @ r, lev.sv.P.T @ t
+
+        return cycle, coarsest, restrict
+
+    def additive_vcycle(self):
+        """One additive cycle for all n_b columns with sigma fixed: a V-cycle (cycle_gamma 1) or,
+        with cycle_gamma 2, a W-cycle (§3.3, R34): every level above the last one before the
+        coarsest visits its coarse level twice, the second visit starting from the first one's
+        correction; the coarsest level is solved once per visit of the level above it."""
+        if len(self.levels) == 1:
+            # one level: the multiplicative phase's coarsest generalized SVD is already exact and
+            # there is no coarse correction to add
+            return
+        cycle, _, _ = self._additive_cycle_fns()
         kap0 = np.zeros_like(self.Ub)
-        tau0 = None if kind == SPD else np.zeros_like(self.Vb)
+        tau0 = None if self.kind == SPD else np.zeros_like(self.Vb)
         self.Ub, self.Vb = cycle(0, self.Ub, self.Vb, kap0, tau0)
+
+    def additive_fmg(self):
+        """R37's FMG cycle (§3.3 names FMG): the finest block's residual restricted to every level,
+        the coarsest level solved, then from the coarsest upwards every coarse level takes the
+        prolonged correction of the level below it and one cycle against its restricted residual;
+        the finest block takes the prolonged correction and one cycle."""
+        L = len(self.levels) - 1
+        if L == 0:
+            return
+        kind = self.kind
+        cycle, coarsest, restrict = self._additive_cycle_fns()
+        kap = [None] * (L + 1)
+        tau = [None] * (L + 1)
+        z0 = np.zeros_like(self.Ub)
+        kap[1], tau[1] = restrict(0, self.Ub, self.Vb, z0, None if kind == SPD else np.zeros_like(self.Vb))
+        for l in range(1, L):
+            lev = self.levels[l]
+            kap[l + 1] = lev.su.P.T @ kap[l]
+            tau[l + 1] = None if kind == SPD else lev.sv.P.T @ tau[l]
+        Uc, Vc = coarsest(kap[L], tau[L])
+        for l in range(L - 1, 0, -1):
+            lev = self.levels[l]
+            U = lev.su.P @ Uc
+            V = None if kind == SPD else lev.sv.P @ Vc
+            Uc, Vc = cycle(l, U, V, kap[l], tau[l])
+        lev = self.levels[0]
+        U = self.Ub + lev.su.P @ Uc
+        V = None if kind == SPD else self.Vb + lev.sv.P @ Vc
+        self.Ub, self.Vb = cycle(0, U, V, z0, None if kind == SPD else np.zeros_like(self.Vb))
+
+    def additive_cycle(self):
+        """The additive phase's cycle: FMG (R37) or a V-/W-cycle."""
+        if self.p.fmg:
+            self.additive_fmg()
+        else:
+            self.additive_vcycle()
 
     def lobpcg_iteration(self, P):
         """One iteration of R36's LOBPCG solve phase (§7): W = C(X) - X from the additive cycle
         and the Ritz step on span[X, W, P].  Returns the new search direction."""
         X = (self.Ub.copy(), None if self.Vb is None else self.Vb.copy())
-        self.additive_vcycle()
+        self.additive_cycle()
         W = (self.Ub - X[0], None if self.Vb is None else self.Vb - X[1])
         sig, (U, V), Pn, kept = lobpcg_ritz(self.levels[0].A, self.kind, self.target, self.n_b, X, W, P)
         self.sig, self.Ub, self.Vb = sig, U, V
@@ -1165,7 +1217,7 @@ class Solver:
             if p.solve_phase == 1:
                 P = self.lobpcg_iteration(P)
             else:
-                self.additive_vcycle()
+                self.additive_cycle()
                 self.sig, self.Ub, self.Vb = self._ritz(self.Ub, self.Vb)
             rho = residuals(A0, self.kind, self.Ub, self.Vb, self.sig, self.anorm)
             it += 1

@@ -925,3 +925,19 @@ def test_lobpcg_phase_converges_to_closed_form(name, scale, ref, max_iters):
     o = O.solve(A, wl["kind"], wl["target"], wl["n_b"], O.Params(**dict(wl["params"], solve_phase=1, max_add=200)))
     assert o.report["converged"] and o.report["add_iters"] <= max_iters
     assert np.allclose(o.sigma, ref(), rtol=1e-10)
+
+
+# ---------------------------------------------------------------------------- FMG cycles (R37)
+def test_fmg_visit_count_and_closed_form():
+    # R37 (§3.3 names FMG): one FMG cycle solves the coarsest level once, then once per cycle from
+    # each level above it (V-cycles: levels solves per iteration), and reaches the closed-form
+    # eigenvalues of the 5-point Laplacian; on the 31^2 grid it needs at most 10 FMG cycles where
+    # V-cycles need 27 (an FMG that skipped the prolonged correction or the restricted residual
+    # of a coarse level needs more or does not converge)
+    A = W.laplace2d(31).to_scipy()
+    prm = dict(W.WORKLOADS["laplace2d_31_min4"]["params"], max_add=100, fmg=1)
+    o = O.solve(A, "spd", "minimal", 4, O.Params(**prm))
+    assert o.report["converged"] and o.report["levels"] >= 3
+    assert o.report["add_iters"] <= 10
+    assert o.report["coarse_solves"] == o.report["add_iters"] * o.report["levels"]
+    assert np.allclose(o.sigma, W.laplace2d_eigs(31)[:4], rtol=1e-10)
