@@ -143,7 +143,13 @@ typedef struct {
                                numerically dependent on the others).  Minimal SVD targets take
                                the left basis from A times the right one.  Iterations run
                                without graph replay (0)                                         */
-  int32_t reserved3;
+  int32_t fmg;              /* additive cycle (§3.3 names FMG): 1 an FMG cycle: the finest block's
+                               residual restricted through every level, the coarsest level solved,
+                               then from the coarsest upwards every coarse level starts from the
+                               prolonged correction of the level below it and runs one cycle
+                               (cycle_gamma) against its restricted residual; the finest block
+                               adds the prolonged correction and runs one cycle.  0 the cycle of
+                               cycle_gamma alone (0)                                            */
 } slamg_params;
 
 /* Report of one solve.  Arrays are filled up to the counts given. */

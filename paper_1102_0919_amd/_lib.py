@@ -37,7 +37,7 @@ class Params(C.Structure):
                 ("kaczmarz_order", C.c_int32), ("coarse_dense_max", C.c_int32),
                 ("redo_p", C.c_int32), ("redo_tol", C.c_double), ("cycle_gamma", C.c_int32),
                 ("ritz_coarse", C.c_int32),
-                ("solve_phase", C.c_int32), ("reserved3", C.c_int32)]
+                ("solve_phase", C.c_int32), ("fmg", C.c_int32)]
 
 
 class Report(C.Structure):

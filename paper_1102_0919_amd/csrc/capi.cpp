@@ -110,6 +110,7 @@ extern "C" slamg_status slamg_params_init(slamg_params* p, slamg_kind kind, slam
   p->cycle_gamma = 1;
   p->ritz_coarse = 0;
   p->solve_phase = 0;
+  p->fmg = 0;
   (void)target;
   return SLAMG_OK;
 }
@@ -275,6 +276,7 @@ static slamg_status check_params(std::string& err, const Prepared& P, int32_t nb
   if (p.cycle_gamma != 1 && p.cycle_gamma != 2) return fail(err, SLAMG_E_INVALID, "cycle_gamma must be 1 or 2");
   if (p.ritz_coarse != 0 && p.ritz_coarse != 1) return fail(err, SLAMG_E_INVALID, "ritz_coarse must be 0 or 1");
   if (p.solve_phase != 0 && p.solve_phase != 1) return fail(err, SLAMG_E_INVALID, "solve_phase must be 0 or 1");
+  if (p.fmg != 0 && p.fmg != 1) return fail(err, SLAMG_E_INVALID, "fmg must be 0 or 1");
   if (!(p.tol > 0.0)) return fail(err, SLAMG_E_INVALID, "tol must be positive");
   if (p.n_t < 2 || p.n_t > 16) return fail(err, SLAMG_E_INVALID, "n_t must be in 2..16");
   if (p.mu_t < 0 || p.mu_b < 0 || p.n_mult < 1 || p.max_add < 0) return fail(err, SLAMG_E_INVALID, "bad counts");

@@ -269,6 +269,12 @@ class Solver {
   template <class T> void boot_relax(int l, const T* kap, const T* tau, const double* sig, int nsweeps = 1,
                                       bool zero_start = false);
   template <class T> void additive_vcycle(const double* sig, T* rhsU, T* rhsV);
+  template <class T> void additive_fmg(const double* sig, T* rhsU, T* rhsV);
+  template <class T> void additive_cycle(const double* sig, T* rhsU, T* rhsV) {
+    if (p_.fmg) additive_fmg<T>(sig, rhsU, rhsV);
+    else additive_vcycle<T>(sig, rhsU, rhsV);
+  }
+  template <class T> void level_residual_restrict(int l, const T* kap, const T* tau, const double* sig);
   void additive_iteration();
   void ritz();
   void ritz_level(int l);
@@ -1737,7 +1743,34 @@ void Solver::cycle_level(int l, const double* sig, T* rhsU, T* rhsV, bool zero_i
   const T* kap = l == 0 ? rhsU : b.kap;
   const T* tau = l == 0 ? rhsV : b.tau;
   boot_relax<T>(l, kap, tau, sig, p_.mu_b, zero_iterate && zero_start_ok);
-  // residuals r = kappa - (A v - sigma B u), s = tau - (A^t u - sigma C v), then restriction
+  level_residual_restrict<T>(l, kap, tau, sig);
+  // zero initial coarse correction: written explicitly for Kaczmarz (it updates in place); the
+  // Jacobi-type relaxation starts from zero without reading it, and the coarsest solve writes it
+  if (!zero_start_ok) {
+    if constexpr (std::is_same<T, double>::value) {
+      launch_fill(cb.Ub, (size_t)(rows_u(C) + (spd_ ? 0 : rows_v(C))) * nb_, 0.0, st_);
+    } else {
+      launch_fillf(cb.Ub, (size_t)(rows_u(C) + (spd_ ? 0 : rows_v(C))) * nb_, 0.0f, st_);
+    }
+  }
+  if (l + 2 == nl) {
+    coarsest_additive<T>(sig);
+  } else {
+    for (int v = 0; v < p_.cycle_gamma; ++v) cycle_level<T>(l + 1, sig, rhsU, rhsV, v == 0);
+  }
+  if (spd_) spmm<T>(l, L.su.P, vals<T>(L.su.P), nb_, cb.Ub, b.Ub, 1.0);
+  else spmm2<T>(l, L.su.P, vals<T>(L.su.P), cb.Ub, b.Ub, L.sv.P, vals<T>(L.sv.P), cb.Vb, b.Vb, 1.0);
+  boot_relax<T>(l, kap, tau, sig, p_.mu_b);
+}
+
+// Residuals of level l's blocks, r = kappa - (A v - sigma B u) and s = tau - (A^t u - sigma C v),
+// restricted into level l + 1's kappa and tau (§4.1, §4.2).
+template <class T>
+void Solver::level_residual_restrict(int l, const T* kap, const T* tau, const double* sig) {
+  Level& L = *lv_[l];
+  Level& C = *lv_[l + 1];
+  Blocks<T>& b = blocks<T>(L);
+  Blocks<T>& cb = blocks<T>(C);
   {
     const int mu = rows_u(L), mv = rows_v(L);
     RowOpArgs<T> a;
@@ -1759,23 +1792,34 @@ void Solver::cycle_level(int l, const double* sig, T* rhsU, T* rhsV, bool zero_i
       spmm2<T>(l, L.su.Pt, vals<T>(L.su.Pt), b.tU, cb.kap, L.sv.Pt, vals<T>(L.sv.Pt), b.tV, cb.tau, 0.0);
     }
   }
-  // zero initial coarse correction: written explicitly for Kaczmarz (it updates in place); the
-  // Jacobi-type relaxation starts from zero without reading it, and the coarsest solve writes it
-  if (!zero_start_ok) {
-    if constexpr (std::is_same<T, double>::value) {
-      launch_fill(cb.Ub, (size_t)(rows_u(C) + (spd_ ? 0 : rows_v(C))) * nb_, 0.0, st_);
-    } else {
-      launch_fillf(cb.Ub, (size_t)(rows_u(C) + (spd_ ? 0 : rows_v(C))) * nb_, 0.0f, st_);
-    }
+}
+
+// FMG cycle of the additive phase (§3.3 names FMG): the finest block's residual restricted through
+// every level, the coarsest solve, then upwards: each coarse level starts from the prolonged
+// correction of the level below it and runs one cycle against its restricted residual; the finest
+// block adds the prolonged correction and runs one cycle.
+template <class T>
+void Solver::additive_fmg(const double* sig, T* rhsU, T* rhsV) {
+  const int nl = (int)lv_.size();
+  if (nl < 2) return;
+  level_residual_restrict<T>(0, rhsU, rhsV, sig);
+  for (int l = 1; l + 1 < nl; ++l) {
+    Level& L = *lv_[l];
+    Blocks<T>& b = blocks<T>(L);
+    Blocks<T>& cb = blocks<T>(*lv_[l + 1]);
+    if (spd_) spmm<T>(l, L.su.Pt, vals<T>(L.su.Pt), nb_, b.kap, cb.kap, 0.0);
+    else spmm2<T>(l, L.su.Pt, vals<T>(L.su.Pt), b.kap, cb.kap, L.sv.Pt, vals<T>(L.sv.Pt), b.tau, cb.tau, 0.0);
   }
-  if (l + 2 == nl) {
-    coarsest_additive<T>(sig);
-  } else {
-    for (int v = 0; v < p_.cycle_gamma; ++v) cycle_level<T>(l + 1, sig, rhsU, rhsV, v == 0);
+  coarsest_additive<T>(sig);
+  for (int l = nl - 2; l >= 0; --l) {
+    Level& L = *lv_[l];
+    Blocks<T>& b = blocks<T>(L);
+    Blocks<T>& cb = blocks<T>(*lv_[l + 1]);
+    const double beta = l == 0 ? 1.0 : 0.0;   // coarse levels start from the prolonged correction
+    if (spd_) spmm<T>(l, L.su.P, vals<T>(L.su.P), nb_, cb.Ub, b.Ub, beta);
+    else spmm2<T>(l, L.su.P, vals<T>(L.su.P), cb.Ub, b.Ub, L.sv.P, vals<T>(L.sv.P), cb.Vb, b.Vb, beta);
+    cycle_level<T>(l, sig, rhsU, rhsV, false);
   }
-  if (spd_) spmm<T>(l, L.su.P, vals<T>(L.su.P), nb_, cb.Ub, b.Ub, 1.0);
-  else spmm2<T>(l, L.su.P, vals<T>(L.su.P), cb.Ub, b.Ub, L.sv.P, vals<T>(L.sv.P), cb.Vb, b.Vb, 1.0);
-  boot_relax<T>(l, kap, tau, sig, p_.mu_b);
 }
 
 // Coarsest level of the additive cycle: [u; v] = pinv(X - sigma_j Y) [kappa; tau] (FP64), from and
@@ -1809,7 +1853,7 @@ void Solver::coarsest_additive(const double* sig) {
 
 void Solver::additive_iteration() {
   if (!mixed_) {
-    additive_vcycle<double>(sig_, nullptr, nullptr);
+    additive_cycle<double>(sig_, nullptr, nullptr);
     return;
   }
   // Refinement form: FP64 residual of the current iterate, FP32 V-cycle on the error equation
@@ -1832,7 +1876,7 @@ void Solver::additive_iteration() {
     launch_copy_cast_df(L.bd.tV, L.bf.tau, (size_t)mv * nb_, st_);
   }
   launch_fillf(L.bf.Ub, (size_t)(mu + (spd_ ? 0 : mv)) * nb_, 0.0f, st_);
-  additive_vcycle<float>(sig_, L.bf.kap, spd_ ? nullptr : L.bf.tau);
+  additive_cycle<float>(sig_, L.bf.kap, spd_ ? nullptr : L.bf.tau);
   launch_axpy_fd(L.bf.Ub, L.bd.Ub, (size_t)mu * nb_, st_);
   if (!spd_) launch_axpy_fd(L.bf.Vb, L.bd.Vb, (size_t)mv * nb_, st_);
 }
@@ -2209,8 +2253,16 @@ void Solver::check_status() {
 
 // Coarsest solves per additive iteration: cycle_gamma^(levels - 2).
 long Solver::coarse_calls_per_iter() const {
-  long c = 1;
-  for (int l = 2; l < (int)lv_.size(); ++l) c *= p_.cycle_gamma;
+  // a cycle from level l solves the coarsest level gamma^(levels - 2 - l) times
+  const int nl = (int)lv_.size();
+  auto from = [&](int l) {
+    long c = 1;
+    for (int k = l + 2; k < nl; ++k) c *= p_.cycle_gamma;
+    return c;
+  };
+  if (!p_.fmg) return from(0);
+  long c = 1;   // FMG: the first coarsest solve, then one cycle from every level above it
+  for (int l = nl - 2; l >= 0; --l) c += from(l);
   return c;
 }
 

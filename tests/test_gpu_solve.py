@@ -242,6 +242,7 @@ def test_request_interface_matches_solve(ctx):
     ("laplace2d_31_min4", None, {"precision": "mixed_fp32"}),      # refinement form
     ("gradient2d_256_dom8", 32, {}),                               # Jacobi-type, rectangular SVD
     ("laplace2d_31_min4", None, {"cycle_gamma": 2}),               # W-cycle: 8 coarsest solves per iteration
+    ("laplace2d_31_min4", None, {"fmg": 1}),                       # FMG: 5 coarsest solves per iteration
 ])
 def test_graph_replay_bitwise_equals_eager(ctx, name, scale, over):
     from paper_1102_0919_amd import api
@@ -700,3 +701,25 @@ def test_lobpcg_phase_vs_oracle(ctx, name, scale, precision, ref):
     # P is left out once a column's movement falls below 1e-10; the two iterates agree to about
     # 1e-4 relative after the first iterations, so the iteration of each crossing may shift by one
     assert abs(rep["p_dropped"] - o.report.get("p_dropped", 0)) <= 2
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed_fp32"])
+def test_fmg_vs_oracle(ctx, precision):
+    # FMG cycles in the additive phase (§3.3, R37) on the 31^2 Laplacian, 4 smallest eigenpairs:
+    # the device's FMG against the oracle's: same hierarchy, the residual history of the first
+    # iterations, iteration counts within 2 (8 FMG cycles where V-cycles take 27), the closed form
+    from paper_1102_0919_amd import api
+    wl = W.WORKLOADS["laplace2d_31_min4"]
+    A = W.build_workload_matrix("laplace2d_31_min4").to_scipy()
+    prm = dict(wl["params"], fmg=1, max_add=100)
+    r = api.solve(ctx, A, "spd", "minimal", 4, api.params_init("spd", "minimal", precision=precision, **prm))
+    o = O.solve(A, "spd", "minimal", 4, O.Params(**prm))
+    rep = api.report_dict(r.report)
+    assert r.converged and o.report["converged"]
+    assert rep["sizes"] == [tuple(x) for x in o.report["sizes"]]
+    assert rep["add_iters"] <= 12 and abs(rep["add_iters"] - o.report["add_iters"]) <= 2
+    orho = [float(np.max(x[:4])) for x in o.report["rho"]]
+    assert np.allclose(rep["rho_history"][:3], orho[:3], rtol=1e-4)
+    _sig_close(r.sigma, W.laplace2d_eigs(31)[:4], rep["anorm"])
+    _sig_close(r.sigma, o.sigma, rep["anorm"])
+    _check_triplets(A, r, "spd", 1e-8, rep["anorm"])
