@@ -240,7 +240,7 @@ void interp_pattern(const std::vector<int>& Sp, const std::vector<int>& Si, cons
 }
 
 // Transpose of a pattern; perm[e] = index in A of the e-th entry of A^t (rows of A^t sorted).
-HCsr transpose(const HCsr& A, std::vector<int>* perm) {
+HCsr transpose(const HCsr& A, std::vector<int>* perm, bool values) {
   HCsr T;
   T.m = A.n; T.n = A.m;
   T.rp.assign(A.n + 1, 0);
@@ -248,14 +248,15 @@ HCsr transpose(const HCsr& A, std::vector<int>* perm) {
   for (int k = 0; k < nnz; ++k) T.rp[A.ci[k] + 1]++;
   for (int i = 0; i < A.n; ++i) T.rp[i + 1] += T.rp[i];
   T.ci.resize(nnz);
-  if (!A.v.empty()) T.v.resize(nnz);
+  const bool vals = values && !A.v.empty();
+  if (vals) T.v.resize(nnz);
   if (perm) perm->resize(nnz);
   std::vector<int> pos(T.rp.begin(), T.rp.end() - 1);
   for (int i = 0; i < A.m; ++i)
     for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) {
       const int d = pos[A.ci[k]]++;
       T.ci[d] = i;
-      if (!A.v.empty()) T.v[d] = A.v[k];
+      if (vals) T.v[d] = A.v[k];
       if (perm) (*perm)[d] = k;
     }
   return T;
@@ -286,19 +287,19 @@ HCsr symbolic_product(const HCsr& L, const HCsr& R) {
 // column.  Returns the colour of every row; colours ascending, rows ascending within a colour
 // give the Kaczmarz order.
 std::vector<int> greedy_row_colouring(const HCsr& A) {
-  HCsr T = transpose(A, nullptr);
+  HCsr T = transpose(A, nullptr, false);
   std::vector<int> colour(A.m, -1);
   std::vector<int> stamp;
   for (int i = 0; i < A.m; ++i) {
     for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) {
       const int c = A.ci[k];
+      // the rows of a column come in ascending order: only those before i are coloured
       for (int t = T.rp[c]; t < T.rp[c + 1]; ++t) {
         const int r = T.ci[t];
-        if (r < i) {
-          const int col = colour[r];
-          if (col >= (int)stamp.size()) stamp.resize(col + 1, -1);
-          stamp[col] = i;
-        }
+        if (r >= i) break;
+        const int col = colour[r];
+        if (col >= (int)stamp.size()) stamp.resize(col + 1, -1);
+        stamp[col] = i;
       }
     }
     int c = 0;

@@ -12,7 +12,8 @@ std::vector<char> rs_coarsen(const std::vector<int>& Sp, const std::vector<int>&
 void interp_pattern(const std::vector<int>& Sp, const std::vector<int>& Si, const HCsr& N,
                     const std::vector<char>& is_c, int cap, std::vector<int>& ptr, std::vector<int>& fine_cols,
                     int& capped);
-HCsr transpose(const HCsr& A, std::vector<int>* perm);
+// values = false: the pattern only (T.v stays empty)
+HCsr transpose(const HCsr& A, std::vector<int>* perm, bool values = true);
 HCsr symbolic_product(const HCsr& L, const HCsr& R);
 std::vector<int> greedy_row_colouring(const HCsr& A);
 void colour_order(const std::vector<int>& colour, std::vector<int>& rows, std::vector<int>& cptr);
