@@ -1144,8 +1144,8 @@ void Solver::make_coarse_level(int l) {
     L.S2 = L.S1;
     L.S2.v = ar_.alloc<double>(L.S1.nnz);                  // P^t B on the same pattern
     C->m = C->n = su.nc;
-    C->hA = Ac;
     C->A = upload(Ac, false);
+    C->hA = std::move(Ac);
     C->At = C->A;
     C->B = C->A;
     C->B.v = ar_.alloc<double>(C->A.nnz);
@@ -1170,15 +1170,16 @@ void Solver::make_coarse_level(int l) {
     L.S2 = upload(S2, false);
     L.S3 = upload(S3, false);
     C->m = su.nc; C->n = sv.nc;
-    C->hA = Ac;
     C->hAt = transpose(Ac, &C->permAt);
-    C->hB = Bc; C->hC = Cc;
     C->A = upload(Ac, false);
     C->At = upload(C->hAt, false);
     C->d_permAt = ar_.alloc<int>(C->permAt.size());
     h2d(C->d_permAt, C->permAt, st_);
     C->B = upload(Bc, false);
     C->C = upload(Cc, false);
+    C->hA = std::move(Ac);
+    C->hB = std::move(Bc);
+    C->hC = std::move(Cc);
     L.plans.clear();
     L.plans.push_back(mkplan(L.S1, &su.Pt, &L.At, L.S1.v));  // (P^t A)_{I j} = P^t row I . A^t row j
     L.plans.push_back(mkplan(L.S2, &su.Pt, &L.B, L.S2.v));   // B symmetric
