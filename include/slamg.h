@@ -68,7 +68,7 @@ typedef struct {
 typedef struct {
   double theta;             /* strength threshold of §3.7 (0.06)                                */
   int32_t strength_rule;    /* 0 row-sum rule of §3.7, 1 max-based rule, 2 top-s rule (0)       */
-  int32_t top_s;            /* s of the top-s rule (4)                                          */
+  int32_t top_s;            /* s of the top-s rule, 1..16 (4)                                   */
   double df_filter;         /* top-s rule: rows with more than df_filter*n nonzeros are ignored
                                when measuring strength on the finest level (0 = off)            */
   int32_t n_t;              /* number of test vectors (8)                                       */

@@ -288,6 +288,7 @@ static slamg_status check_params(std::string& err, const Prepared& P, int32_t nb
   if (p.square_coarsening && P.kind == SLAMG_SVD && P.A.m != P.A.n)
     return fail(err, SLAMG_E_INVALID, "square coarsening needs a square matrix without empty rows or columns");
   if (p.strength_rule < 0 || p.strength_rule > 2) return fail(err, SLAMG_E_INVALID, "unknown strength rule");
+  if (p.strength_rule == 2 && (p.top_s < 1 || p.top_s > 16)) return fail(err, SLAMG_E_INVALID, "top_s must be in 1..16");
   if (nb > std::min(P.m0, P.n0)) return fail(err, SLAMG_E_INVALID, "n_b larger than min(m, n)");
   if (nb > std::min(P.A.m, P.A.n)) return fail(err, SLAMG_E_INVALID, "n_b larger than the nonzero part of A");
   if (nb + p.n_guard > std::min(P.A.m, P.A.n))

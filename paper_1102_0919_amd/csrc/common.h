@@ -187,6 +187,12 @@ void launch_place_block(int w, const double* G, double* M, int ld, int r0, int c
 void launch_eye(int k, double* M, hipStream_t s);
 // rowC[k] = i for the entries k of row i of an m-row CSR pattern
 void launch_row_index(int m, const int* rp, int* rowC, hipStream_t s);
+// rowC[k] = the row of entry e0 + k (k < cnt) of a CSR pattern whose rows [r0, r1) hold those entries
+void launch_row_index_range(int r0, int r1, const int* rp, long e0, long cnt, int* rowC, hipStream_t s);
+// top-s rule (§3.7) per row of a strength operator chunk: rows [r0, r1), entries rp[i] - e0 ..
+// rp[i + 1] - e0 of col / val; out (rows x s): the selected (j, n_ij) ascending in j, -1 after
+void launch_topsel(int r0, int r1, const int* rp, long e0, const int* col, const double* val, int s, int* out_col,
+                   double* out_val, hipStream_t st);
 void launch_fillf(float* p, size_t n, float val, hipStream_t s);
 void launch_copy_cast_df(const double* in, float* out, size_t n, hipStream_t s);
 // FP64 -> BF16 bit patterns (out: n 16-bit words), rounded to FP32 and then to the nearest BF16

@@ -1362,6 +1362,104 @@ void launch_row_index(int m, const int* rp, int* rowC, hipStream_t s) {
   if (m > 0) hipLaunchKernelGGL(k_row_index, dim3(ceil_div((long)m, BLK)), dim3(BLK), 0, s, m, rp, rowC);
 }
 
+// rowC[k] = the row of entry e0 + k of a CSR pattern, k < cnt, for the rows [r0, r1) that hold
+// those entries (one thread per entry, a binary search of the row pointers)
+__global__ void k_row_index_range(int r0, int r1, const int* __restrict__ rp, long e0, long cnt,
+                                  int* __restrict__ rowC) {
+  const long k = (long)blockIdx.x * BLK + threadIdx.x;
+  if (k >= cnt) return;
+  const long g = e0 + k;
+  int lo = r0, hi = r1 - 1;   // the last row i in [r0, r1) with rp[i] <= g
+  while (lo < hi) {
+    const int mid = lo + (hi - lo + 1) / 2;
+    if ((long)rp[mid] <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  rowC[k] = lo;
+}
+void launch_row_index_range(int r0, int r1, const int* rp, long e0, long cnt, int* rowC, hipStream_t s) {
+  if (cnt > 0 && r1 > r0)
+    hipLaunchKernelGGL(k_row_index_range, dim3(ceil_div(cnt, BLK)), dim3(BLK), 0, s, r0, r1, rp, e0, cnt, rowC);
+}
+
+// The top-s rule of §3.7 on a strength operator held in chunks: for each row i of [r0, r0 + grid)
+// (entries rp[i] - e0 .. rp[i + 1] - e0 of col / val) the top_s off-diagonal entries with
+// |n_ij| > 0 in the order (-|n_ij|, j), written as (j, n_ij) ascending in j, -1 after the last.
+// One workgroup per row: each thread keeps its best top_s of a strided share, then the lists are
+// merged in pairs through LDS.
+constexpr int TOPS_MAX = 16;
+__device__ __forceinline__ bool tops_better(double a1, int j1, double a2, int j2) {
+  return a1 > a2 || (a1 == a2 && j1 < j2);
+}
+__global__ __launch_bounds__(256) void k_topsel(int r0, const int* __restrict__ rp, long e0,
+                                                const int* __restrict__ col, const double* __restrict__ val, int s,
+                                                int* __restrict__ out_col, double* __restrict__ out_val) {
+  __shared__ int sj[256 * TOPS_MAX];      // 16 KB
+  __shared__ double sv[256 * TOPS_MAX];   // 32 KB (|n_ij| compared as fabs of it)
+  __shared__ int sn[256];
+  const int i = r0 + (int)blockIdx.x, t = (int)threadIdx.x;
+  const long b = (long)rp[i] - e0, e = (long)rp[i + 1] - e0;
+  double la[TOPS_MAX], lv[TOPS_MAX];
+  int lj[TOPS_MAX];
+  int n = 0;
+  for (long k = b + t; k < e; k += 256) {
+    const int j = col[k];
+    const double v = val[k], a = fabs(v);
+    if (j == i || !(a > 0.0)) continue;
+    if (n == s && !tops_better(a, j, la[s - 1], lj[s - 1])) continue;
+    int q = n < s ? n++ : s - 1;
+    while (q > 0 && tops_better(a, j, la[q - 1], lj[q - 1])) {
+      la[q] = la[q - 1]; lj[q] = lj[q - 1]; lv[q] = lv[q - 1];
+      --q;
+    }
+    la[q] = a; lj[q] = j; lv[q] = v;
+  }
+  for (int q = 0; q < n; ++q) {
+    sj[t * TOPS_MAX + q] = lj[q]; sv[t * TOPS_MAX + q] = lv[q];
+  }
+  sn[t] = n;
+  __syncthreads();
+  for (int h = 128; h >= 1; h >>= 1) {
+    if (t < h) {
+      // merge list t + h into list t (both ordered best first), keeping the best s
+      const int o = t + h, n1 = sn[t], n2 = sn[o];
+      int p1 = 0, p2 = 0, m = 0;
+      while (m < s && (p1 < n1 || p2 < n2)) {
+        const bool take1 = p2 >= n2 || (p1 < n1 && tops_better(fabs(sv[t * TOPS_MAX + p1]), sj[t * TOPS_MAX + p1],
+                                                               fabs(sv[o * TOPS_MAX + p2]), sj[o * TOPS_MAX + p2]));
+        if (take1) { lj[m] = sj[t * TOPS_MAX + p1]; lv[m] = sv[t * TOPS_MAX + p1]; ++p1; }
+        else { lj[m] = sj[o * TOPS_MAX + p2]; lv[m] = sv[o * TOPS_MAX + p2]; ++p2; }
+        ++m;
+      }
+      for (int q = 0; q < m; ++q) {
+        sj[t * TOPS_MAX + q] = lj[q]; sv[t * TOPS_MAX + q] = lv[q];
+      }
+      sn[t] = m;
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const int m = sn[0];
+    for (int q = 0; q < m; ++q) { lj[q] = sj[q]; lv[q] = sv[q]; }
+    for (int q = 1; q < m; ++q) {   // ascending in j
+      const int j = lj[q];
+      const double v = lv[q];
+      int r = q;
+      while (r > 0 && lj[r - 1] > j) { lj[r] = lj[r - 1]; lv[r] = lv[r - 1]; --r; }
+      lj[r] = j; lv[r] = v;
+    }
+    for (int q = 0; q < s; ++q) {
+      out_col[(long)i * s + q] = q < m ? lj[q] : -1;
+      out_val[(long)i * s + q] = q < m ? lv[q] : 0.0;
+    }
+  }
+}
+void launch_topsel(int r0, int r1, const int* rp, long e0, const int* col, const double* val, int s, int* out_col,
+                   double* out_val, hipStream_t st) {
+  if (s < 1 || s > TOPS_MAX) throw SolverError{ST_E_INVALID, "top_s outside 1..16"};
+  if (r1 > r0) hipLaunchKernelGGL(k_topsel, dim3(r1 - r0), dim3(256), 0, st, r0, rp, e0, col, val, s, out_col, out_val);
+}
+
 // k x k identity, row-major
 __global__ void k_eye(int k, double* M) {
   const long t = (long)blockIdx.x * BLK + threadIdx.x;

@@ -938,28 +938,102 @@ HCsr Solver::strength_operator(Level& L, bool u_side, bool finest) {
     dAf = L.A;
     dAfT = L.At;
   }
+  const int lev = (int)(std::find_if(lv_.begin(), lv_.end(), [&](const auto& q) { return q.get() == &L; }) - lv_.begin());
+  vmark(u_side ? "  strength A A^t: copies, transpose" : "  strength A^t A: copies, transpose", lev);
   N = u_side ? symbolic_product(Af, AfT) : symbolic_product(AfT, Af);
+  vmark("  strength: symbolic product", lev);
   // numeric on the device: entries are dot products of rows of A (u) or of A^t (v), computed in
-  // chunks of at most STRENGTH_CHUNK entries so that the product's device arrays stay bounded
-  std::vector<int> rowC(N.nnz());
-  for (int i = 0; i < N.m; ++i)
-    for (int k = N.rp[i]; k < N.rp[i + 1]; ++k) rowC[k] = i;
+  // chunks of at most STRENGTH_CHUNK entries so that the product's device arrays stay bounded; a
+  // chunk's row indices are expanded on the device from the row pointers
+  int* d_rp = ar_.alloc<int>((size_t)N.m + 1);
+  h2d(d_rp, N.rp, st_);
+  const DCsr& M = u_side ? dAf : dAfT;
+  if (p_.strength_rule == 2) {
+    // top-s rule: only the s strongest off-diagonal entries of a row are ever read (strength sets,
+    // interpolatory sets), so the device selects them per row and the operator comes back with
+    // those entries alone; chunks hold whole rows
+    const int ts = p_.top_s;
+    std::vector<std::pair<int, int>> ranges;
+    size_t maxc = 0;
+    for (int r = 0; r < N.m;) {
+      int r1 = r + 1;
+      while (r1 < N.m && (size_t)(N.rp[r1 + 1] - N.rp[r]) <= STRENGTH_CHUNK) ++r1;
+      ranges.push_back({r, r1});
+      maxc = std::max(maxc, (size_t)(N.rp[r1] - N.rp[r]));
+      r = r1;
+    }
+    maxc = std::max<size_t>(maxc, 1);
+    int* d_row = ar_.alloc<int>(maxc);
+    int* d_col = ar_.alloc<int>(maxc);
+    double* d_val = ar_.alloc<double>(maxc);
+    int* d_sc = ar_.alloc<int>((size_t)N.m * ts);
+    double* d_sv = ar_.alloc<double>((size_t)N.m * ts);
+    for (const auto& rg : ranges) {
+      const long e0 = N.rp[rg.first], cnt = (long)N.rp[rg.second] - e0;
+      launch_row_index_range(rg.first, rg.second, d_rp, e0, cnt, d_row, st_);
+      if (cnt > 0)
+        HIPCHK(hipMemcpyAsync(d_col, N.ci.data() + e0, cnt * sizeof(int), hipMemcpyHostToDevice, st_));
+      launch_spgemm_dot((int)cnt, d_row, d_col, M.rp, M.ci, M.v, M.rp, M.ci, M.v, d_val, st_);
+      launch_topsel(rg.first, rg.second, d_rp, e0, d_col, d_val, ts, d_sc, d_sv, st_);
+    }
+    std::vector<int> sc;
+    std::vector<double> sv;
+    d2h(sc, d_sc, (size_t)N.m * ts, st_);
+    d2h(sv, d_sv, (size_t)N.m * ts, st_);
+    if (p_.verbose >= 2) {
+      std::fprintf(stderr, "[slamg]   strength product of level %d: %d entries, top %d per row kept\n", lev, N.nnz(), ts);
+      std::fflush(stderr);
+    }
+    HCsr R;
+    R.m = N.m; R.n = N.n;
+    R.rp.assign((size_t)N.m + 1, 0);
+    for (int i = 0; i < N.m; ++i) {
+      for (int q = 0; q < ts; ++q) {
+        const int j = sc[(size_t)i * ts + q];
+        if (j < 0) break;
+        R.ci.push_back(j);
+        R.v.push_back(sv[(size_t)i * ts + q]);
+      }
+      R.rp[i + 1] = (int)R.ci.size();
+    }
+    vmark("  strength: device products, top-s selection", lev);
+    for (const void* d : {(const void*)d_rp, (const void*)d_row, (const void*)d_col, (const void*)d_val,
+                          (const void*)d_sc, (const void*)d_sv})
+      ar_.release(d);
+    if (filt) {
+      for (const DCsr* d : {&dAf, &dAfT}) {
+        ar_.release(d->rp);
+        ar_.release(d->ci);
+        ar_.release(d->v);
+      }
+    }
+    return R;
+  }
   const size_t total = (size_t)N.nnz(), chunk = std::min<size_t>(total, STRENGTH_CHUNK);
   int* d_row = ar_.alloc<int>(chunk);
   int* d_col = ar_.alloc<int>(chunk);
   double* d_val = ar_.alloc<double>(chunk);
-  const DCsr& M = u_side ? dAf : dAfT;
   N.v.resize(total);
+  vmark("  strength: value array", lev);
   for (size_t e0 = 0; e0 < total; e0 += chunk) {
     const size_t cnt = std::min(chunk, total - e0);
-    HIPCHK(hipMemcpyAsync(d_row, rowC.data() + e0, cnt * sizeof(int), hipMemcpyHostToDevice, st_));
+    // rows [r0, r1) hold the entries [e0, e0 + cnt)
+    const int r0 = (int)(std::upper_bound(N.rp.begin(), N.rp.end(), (int)e0) - N.rp.begin()) - 1;
+    const int r1 = (int)(std::lower_bound(N.rp.begin(), N.rp.end(), (int)(e0 + cnt)) - N.rp.begin());
+    launch_row_index_range(r0, r1, d_rp, (long)e0, (long)cnt, d_row, st_);
     HIPCHK(hipMemcpyAsync(d_col, N.ci.data() + e0, cnt * sizeof(int), hipMemcpyHostToDevice, st_));
     launch_spgemm_dot((int)cnt, d_row, d_col, M.rp, M.ci, M.v, M.rp, M.ci, M.v, d_val, st_);
     HIPCHK(hipMemcpyAsync(N.v.data() + e0, d_val, cnt * sizeof(double), hipMemcpyDeviceToHost, st_));
     HIPCHK(hipStreamSynchronize(st_));
   }
+  if (p_.verbose >= 2) {
+    std::fprintf(stderr, "[slamg]   strength product of level %d: %zu entries\n", lev, total);
+    std::fflush(stderr);
+  }
+  vmark("  strength: device products and transfers", lev);
   // the product's entries are on the host now: its device arrays (and the filtered operator's)
   // go back to the solve's budget
+  ar_.release(d_rp);
   ar_.release(d_row);
   ar_.release(d_col);
   ar_.release(d_val);
