@@ -52,8 +52,8 @@ TRAFFIC = {
         note="mean of the finest-level u-row and v-row launches"),
     # every finest-level k_kacz launch of the multiplicative phase and one additive iteration
     ("aniso3d_128_min8", 1): dict(
-        kernels_sha256="36ded5f367c2be073c1fdb5e10be4f855f16b0bf41153e6839c0c8c54655d3c3",
-        fetch_kib=(117669.0,), write_kib=(154374.0,),
+        kernels_sha256="638b24dfeeba679741954e4e00386d8d35bbae2cd5665c343558d3f3fbbc7416",
+        fetch_kib=(117666.6,), write_kib=(154370.1,),
         copy_fetch_kib=524304.5, copy_write_kib=1048576.0, copy_bytes=1 << 30,
         note="mean over the 1240 finest-level Kaczmarz colour launches of the multiplicative phase and "
              "one additive iteration"),

@@ -276,7 +276,16 @@ HCsr symbolic_product(const HCsr& L, const HCsr& R) {
           if (mark[c] != i) { mark[c] = i; out.push_back(c); }
         }
       }
-      std::sort(out.begin() + at, out.end());
+      // a dense row (more than 1/16 of the columns) comes out in column order from a scan of the
+      // marks, a sparse one from a sort: the same entries in the same order
+      const size_t cnt = out.size() - at;
+      if (cnt * 16 > (size_t)R.n) {
+        out.resize(at);
+        for (int c = 0; c < R.n; ++c)
+          if (mark[c] == i) out.push_back(c);
+      } else {
+        std::sort(out.begin() + at, out.end());
+      }
     };
   };
   build_rows(L.m, C.rp, C.ci, make_row);
