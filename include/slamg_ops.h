@@ -127,6 +127,13 @@ slamg_status slamg_op_spgemm(int32_t nnz, const int32_t* d_rowc, const int32_t* 
                              const int32_t* d_lci, const double* d_lv, const int32_t* d_rtrp, const int32_t* d_rtci,
                              const double* d_rtv, double* d_out, void* stream);
 
+/* Top-s rule of §3.7 on a strength operator: for every row i of the m-row CSR matrix (device
+ * row pointers d_rp, columns d_col, values d_val) the s (1..16) off-diagonal entries with the
+ * largest |n_ij| > 0, ties to the lower j, written to d_out_col / d_out_val (m x s, row-major) in
+ * ascending j, -1 (and 0.0) after the last.  SLAMG_E_INVALID for s outside 1..16 or m < 0. */
+slamg_status slamg_op_topsel(int32_t m, const int32_t* d_rp, const int32_t* d_col, const double* d_val, int32_t s,
+                             int32_t* d_out_col, double* d_out_val, void* stream);
+
 /* Coarsest generalized SVD (§3.6, Theorem 3.1): n_b extremal triplets of dense A (mL x nL) w.r.t.
  * SPD B (mL x mL) and C (nL x nL), or (spd = 1) eigenpairs of the pencil (A, B).  Host dense
  * row-major inputs; h_u (mL x nb), h_v (nL x nb) row-major, h_sig (nb). */

@@ -353,6 +353,13 @@ extern "C" slamg_status slamg_op_spgemm(int32_t nnz, const int32_t* d_rowc, cons
   });
 }
 
+extern "C" slamg_status slamg_op_topsel(int32_t m, const int32_t* d_rp, const int32_t* d_col, const double* d_val,
+                                        int32_t s, int32_t* d_out_col, double* d_out_val, void* stream) {
+  if (m < 0 || s < 1 || s > 16) return SLAMG_E_INVALID;
+  hipStream_t st = (hipStream_t)stream;
+  return guarded(st, [&] { launch_topsel(0, m, d_rp, 0, d_col, d_val, s, d_out_col, d_out_val, st); });
+}
+
 extern "C" slamg_status slamg_op_coarse_gsvd(int32_t spd, int32_t minimal, int32_t mL, int32_t nL, int32_t nb,
                                              const double* h_a, const double* h_b, const double* h_c, double* h_sig,
                                              double* h_u, double* h_v) {

@@ -354,6 +354,36 @@ def test_galerkin_spgemm_parity(L):
     assert np.allclose(ac, Ac.data, rtol=1e-12, atol=1e-13)
 
 
+@pytest.mark.parametrize("s", [1, 4, 16])
+def test_topsel_parity(L, s):
+    # the top-s rule of §3.7 on the device (one workgroup per row, per-thread lists merged in LDS)
+    # against the oracle's strength sets: values from a small integer set (ties broken to the lower
+    # column), explicit zeros and the diagonal left out, rows longer than a workgroup and empty rows
+    rng = np.random.default_rng(11 + s)
+    m, n = 300, 2000
+    rows = []
+    for i in range(m):
+        k = 0 if i % 37 == 0 else int(rng.integers(1, 900 if i % 5 == 0 else 40))
+        cols = np.sort(rng.choice(n, size=k, replace=False))
+        rows.append(cols)
+    indptr = np.concatenate([[0], np.cumsum([len(c) for c in rows])]).astype(np.int32)
+    indices = np.concatenate(rows).astype(np.int32) if indptr[-1] else np.zeros(0, np.int32)
+    data = rng.integers(-4, 5, size=indices.size).astype(np.float64) * 0.5
+    N = sp.csr_matrix((data, indices, indptr), shape=(m, n))
+    oc = dev(np.zeros(m * s, np.int32))
+    ov = dev(np.zeros(m * s))
+    assert L.slamg_op_topsel(m, ptr(dev(indptr)), ptr(dev(indices)), ptr(dev(data)), s, ptr(oc), ptr(ov), None) == 0
+    gc, gv = host(oc).reshape(m, s), host(ov).reshape(m, s)
+    Sp, Si = O.strength_sets(N, 0.0, 2, top_s=s)
+    for i in range(m):
+        want = np.asarray(Si[Sp[i]:Sp[i + 1]])
+        got = gc[i][gc[i] >= 0]
+        assert np.array_equal(got, want), (i, got, want)
+        assert np.array_equal(gv[i][: got.size], np.array([N[i, j] for j in got]))
+        assert np.all(gc[i][got.size:] == -1)
+    assert L.slamg_op_topsel(m, ptr(dev(indptr)), ptr(dev(indices)), ptr(dev(data)), 17, ptr(oc), ptr(ov), None) != 0
+
+
 @pytest.mark.parametrize("kind,target,m,n", [("svd", "dominant", 70, 40), ("svd", "minimal", 70, 40),
                                              ("svd", "dominant", 40, 70), ("svd", "minimal", 40, 70),
                                              ("svd", "minimal", 33, 32), ("spd", "minimal", 90, 90),
