@@ -232,9 +232,13 @@ def main():
     # class times cover every launch of the solve: they pick the dominant kernel class
     pw = params(args.precision, 0 if args.no_profile else ALL_CLASSES, graphs=0)
     warm_ms = np.zeros(NCLS)
+    warm_n = np.zeros(NCLS)
+    warm_b = np.zeros(NCLS)
     for _ in range(max(args.warmup, 1 if not args.no_profile else 0)):
         w = api.solve_matrix(ctx, mat, target, n_b, pw, U_dev=U_dev, V_dev=V_dev)
         warm_ms = np.array([w.report.prof_ms[c] for c in range(NCLS)])
+        warm_n = np.array([w.report.prof_launches[c] for c in range(NCLS)], dtype=float)
+        warm_b = np.array([w.report.prof_bytes[c] for c in range(NCLS)])
         print(f"[bench] warmup: add_iters={w.report.add_iters} converged={w.converged}", file=sys.stderr, flush=True)
     reps, ms = _run_steps(api, ctx, mat, target, n_b, p, U_dev, V_dev, args.steps, args.precision)
     value = n_b / (ms / 1e3)
@@ -268,6 +272,17 @@ def main():
                 "graph_iters_per_step": int(last.report.graph_iters),
                 "kernels": kernels,
                 "class_ms_in_warmup_solve": {CLASS_NAMES[i]: round(warm_ms[i], 3) for i in range(NCLS)}}
+        if warm_n[c] > 0:
+            # every launch of the class in one whole solve (the warmup runs every iteration
+            # eagerly, each launch between HIP events): the sample rocprofv3's average covers
+            wa = warm_ms[c] / warm_n[c]
+            wb = warm_b[c] / warm_n[c]
+            roof["whole_solve_sample"] = {
+                "launches": int(warm_n[c]), "avg_launch_us": round(wa * 1e3, 3),
+                "algorithmic_bytes_per_launch": int(wb), "GB/s": round(wb / (wa * 1e-3) / 1e9, 2),
+                "frac": round(wb / (wa * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "note": "the untimed warmup solve, all additive iterations eager: graph replays in the timed "
+                        "solves cannot be timed per launch (HIP does not time events recorded by graph nodes)"}
     compare = None
     if args.compare != "none" and args.compare != args.precision:
         p2 = params(args.compare, 0)
