@@ -84,9 +84,10 @@ the design notes of the repository):
       Ritz step then runs on span[X, W, P] instead of span[C(X)], P the previous iteration's
       search direction (none in the first iteration).  The basis is built block by block: X
       orthonormalised; W with the components along X removed (two passes) and orthonormalised;
-      P with the components along X and W removed (two passes), and dropped for that iteration
-      when one of its columns (a part of a unit Ritz vector) has norm below 1e-10 on either side,
-      when a column keeps less than 1e-8 of its norm or the Cholesky factorisation of its
+      P with the components along X and W removed (two passes).  A column of P (a part of a unit
+      Ritz vector) with norm below 1e-10 on either side (a Ritz vector that no longer moves) is
+      left out; the block of the others is dropped for that iteration when none remains, when a
+      column keeps less than 1e-8 of its norm or the Cholesky factorisation of its
       column-scaled Gram matrix fails or has a pivot below 1e-10 (a condition number of the
       scaled block above about 1e5: a decision well inside FP64's range, so that rounding does
       not decide it).  SVD: the same on
@@ -735,8 +736,14 @@ def lobpcg_ritz(A, kind, target, n_b, X, W, P):
     QU = [orthonormal_basis(left[0])]
     QU.append(orthonormal_basis(remove_components(left[1], QU)))
     kept = False
-    moving = P is not None and all(np.linalg.norm(B, axis=0).min() >= 1e-10 for B in P if B is not None)
-    if moving:
+    if P is not None:
+        # columns of P that still move (1e-10 on each side), in column order
+        act = np.ones(P[0].shape[1], dtype=bool)
+        for B in P:
+            if B is not None:
+                act &= np.linalg.norm(B, axis=0) >= 1e-10
+        P = (P[0][:, act], None if P[1] is None else P[1][:, act]) if act.any() else None
+    if P is not None:
         PV = None if kind == SPD else remove_components(P[1], QV)
         okv = kind == SPD or keep_direction(P[1], PV)
         PU0 = A @ orthonormal_basis(PV) if one_sided and okv else P[0]

@@ -896,11 +896,16 @@ def test_lobpcg_search_direction_rules():
     s1, (U1, _), _, k1 = O.lobpcg_ritz(A, "spd", "minimal", 4, X, Wd, Pdep)
     assert not k0 and not k1
     assert np.array_equal(s0, s1) and np.array_equal(U0, U1)
-    # a column below 1e-10 (a Ritz vector that no longer moves) drops the block as well
+    # a column below 1e-10 (a Ritz vector that no longer moves) is left out, the others kept; all
+    # below 1e-10: no P
     P = (rng.standard_normal((n * n, 4)), None)
-    Ptiny = (P[0] * np.array([1.0, 1.0, 1e-11, 1.0]), None)
+    Ptiny = (P[0] * np.array([1.0, 1.0, 1e-13, 1.0]), None)
     s3, (U3, _), _, k3 = O.lobpcg_ritz(A, "spd", "minimal", 4, X, Wd, Ptiny)
-    assert not k3 and np.array_equal(s3, s0) and np.array_equal(U3, U0)
+    s4, (U4, _), _, k4 = O.lobpcg_ritz(A, "spd", "minimal", 4, X, Wd, (P[0][:, [0, 1, 3]], None))
+    assert k3 and k4 and np.array_equal(s3, s4) and np.array_equal(U3, U4)
+    assert np.all(s3 <= s0 + 1e-12)
+    s5, (U5, _), _, k5 = O.lobpcg_ritz(A, "spd", "minimal", 4, X, Wd, (P[0] * 1e-13, None))
+    assert not k5 and np.array_equal(s5, s0) and np.array_equal(U5, U0)
     s2, (U2, _), (Pn, _), k2 = O.lobpcg_ritz(A, "spd", "minimal", 4, X, Wd, P)
     assert k2
     assert np.all(s2 <= s0 + 1e-12)                      # a larger space: Ritz values no larger
@@ -918,7 +923,7 @@ def test_lobpcg_search_direction_rules():
 ])
 def test_lobpcg_phase_converges_to_closed_form(name, scale, ref, max_iters):
     # R36 end to end: the LOBPCG phase on the learned hierarchy reaches the closed form; with the
-    # search direction it takes at most max_iters iterations (11 and 22 here; without P, 20 and 52;
+    # search direction it takes at most max_iters iterations (10 and 21 here; without P, 20 and 52;
     # the multigrid-Ritz phase 27 and 119)
     wl = W.WORKLOADS[name]
     A = W.build_workload_matrix(name, scale).to_scipy()
