@@ -182,8 +182,12 @@ void launch_axpby(size_t n, double a, const double* x, double b, const double* y
 // out = Y + alpha X S (rows x w blocks, S w x w row-major, w <= 16); out may be Y, not X
 void launch_rotate_acc(int rows, int w, const double* X, const double* S, double alpha, const double* Y, double* out,
                        hipStream_t s);
-// a w x w block G into the ld-wide row-major M at (r0, c0); sym also at (c0, r0) transposed
-void launch_place_block(int w, const double* G, double* M, int ld, int r0, int c0, int sym, hipStream_t s);
+// the leading wr x wc part of a w x w block G into the ld-wide row-major M at (r0, c0); sym also at
+// (c0, r0) transposed
+void launch_place_block(int w, int wr, int wc, const double* G, double* M, int ld, int r0, int c0, int sym,
+                        hipStream_t s);
+// dst (rows x w) = the columns idx[0..n) of src (rows x w), then zero columns (w <= 16)
+void launch_gather_cols(int rows, int w, const int* idx, int n, const double* src, double* dst, hipStream_t s);
 void launch_eye(int k, double* M, hipStream_t s);
 // rowC[k] = i for the entries k of row i of an m-row CSR pattern
 void launch_row_index(int m, const int* rp, int* rowC, hipStream_t s);
@@ -222,9 +226,10 @@ void launch_rq_weights(int nf, const double* num, const double* nu, const double
 
 // dense.hip (single-workgroup dense FP64 procedures)
 void launch_chol_inv_upper(int w, const double* G, double* T, int* status, hipStream_t s);
-// the same; *pivot_min = the smallest pivot of the unshifted factorisation of the column-scaled
-// matrix, -1 when it failed
-void launch_chol_inv_upper_pivot(int w, const double* G, double* T, int* status, double* pivot_min, hipStream_t s);
+// the same; *pivot_min = the smallest of the first wpiv pivots of the unshifted factorisation of
+// the column-scaled matrix, -1 when it failed within them
+void launch_chol_inv_upper_pivot(int w, int wpiv, const double* G, double* T, int* status, double* pivot_min,
+                                 hipStream_t s);
 // two factorisations (G0 -> T0, G1 -> T1) in one launch
 void launch_chol_inv_upper2(int w, const double* G0, double* T0, const double* G1, double* T1, int* status,
                             hipStream_t s);

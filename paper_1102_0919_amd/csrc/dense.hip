@@ -266,8 +266,9 @@ __device__ static void select_extremal(const double* lam, int n, int k, bool des
 // ------------------------------------------------------------------------------------------------
 // Cholesky-QR step: G = R^t R, T = R^{-1} (upper), row-major w x w, computed on the column-scaled
 // Gram matrix.  A non-positive pivot retries once with a diagonal shift of 1e-14 trace; a second
-// failure sets *status.  With pivot_min given, it receives the smallest pivot L_ii^2 of the
-// unshifted factorisation of the column-scaled matrix, or -1 when that factorisation failed.
+// failure sets *status.  With pivot_min given, it receives the smallest of the first wpiv pivots
+// L_ii^2 of the unshifted factorisation of the column-scaled matrix, or -1 when that factorisation
+// failed within them (a failure at a later pivot leaves the first wpiv unchanged).
 // ------------------------------------------------------------------------------------------------
 // The Cholesky-QR factor of the n_b x n_b Gram matrix runs on one wavefront: its steps are short
 // chains of LDS updates, and a barrier of a one-wave workgroup costs next to nothing.
@@ -275,7 +276,7 @@ static constexpr int SB = 64;
 
 // workgroup b of the launch factors G_b into T_b (b = 0, 1: the U- and V-side passes of a pair)
 __global__ __launch_bounds__(SB) void k_chol_inv_upper(int w, const double* G0, double* T0, const double* G1, double* T1,
-                                                       int* status, double* pivot_min) {
+                                                       int* status, double* pivot_min, int wpiv) {
   const double* G = blockIdx.x == 0 ? G0 : G1;
   double* T = blockIdx.x == 0 ? T0 : T1;
   // Columns are first scaled to unit norm (D G D with D = diag(G)^-1/2, T = D R^-1): the span,
@@ -302,8 +303,9 @@ __global__ __launch_bounds__(SB) void k_chol_inv_upper(int w, const double* G0, 
     wg_sync();
     wg_chol<SB>(L, w, 16, &info);
     if (pivot_min && attempt == 0 && threadIdx.x == 0) {
-      double pm = info != 0 ? -1.0 : L[0] * L[0];
-      for (int i = 1; info == 0 && i < w; ++i) pm = fmin(pm, L[i * 16 + i] * L[i * 16 + i]);
+      const bool failed = info != 0 && info <= wpiv;
+      double pm = failed ? -1.0 : L[0] * L[0];
+      for (int i = 1; !failed && i < wpiv; ++i) pm = fmin(pm, L[i * 16 + i] * L[i * 16 + i]);
       *pivot_min = pm;
     }
     if (info == 0) break;
@@ -316,14 +318,15 @@ __global__ __launch_bounds__(SB) void k_chol_inv_upper(int w, const double* G0, 
   for (int t = threadIdx.x; t < w * w; t += SB) T[t] = Ts[t] * dsc[t / w];
 }
 void launch_chol_inv_upper(int w, const double* G, double* T, int* status, hipStream_t s) {
-  hipLaunchKernelGGL(k_chol_inv_upper, dim3(1), dim3(SB), 0, s, w, G, T, G, T, status, (double*)nullptr);
+  hipLaunchKernelGGL(k_chol_inv_upper, dim3(1), dim3(SB), 0, s, w, G, T, G, T, status, (double*)nullptr, w);
 }
-void launch_chol_inv_upper_pivot(int w, const double* G, double* T, int* status, double* pivot_min, hipStream_t s) {
-  hipLaunchKernelGGL(k_chol_inv_upper, dim3(1), dim3(SB), 0, s, w, G, T, G, T, status, pivot_min);
+void launch_chol_inv_upper_pivot(int w, int wpiv, const double* G, double* T, int* status, double* pivot_min,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(k_chol_inv_upper, dim3(1), dim3(SB), 0, s, w, G, T, G, T, status, pivot_min, wpiv);
 }
 void launch_chol_inv_upper2(int w, const double* G0, double* T0, const double* G1, double* T1, int* status,
                             hipStream_t s) {
-  hipLaunchKernelGGL(k_chol_inv_upper, dim3(2), dim3(SB), 0, s, w, G0, T0, G1, T1, status, (double*)nullptr);
+  hipLaunchKernelGGL(k_chol_inv_upper, dim3(2), dim3(SB), 0, s, w, G0, T0, G1, T1, status, (double*)nullptr, w);
 }
 
 // ------------------------------------------------------------------------------------------------

@@ -1338,18 +1338,40 @@ void launch_rotate_acc(int rows, int w, const double* X, const double* S, double
                      out);
 }
 
-// M[r0 + i][c0 + j] = G[i][j] for a w x w block of the ld-wide row-major M; sym also writes
-// M[c0 + j][r0 + i]
-__global__ void k_place_block(int w, const double* __restrict__ G, double* __restrict__ M, int ld, int r0, int c0,
-                              int sym) {
+// M[r0 + i][c0 + j] = G[i][j] (i < wr, j < wc) from a w x w block G into the ld-wide row-major M;
+// sym also writes M[c0 + j][r0 + i]
+__global__ void k_place_block(int w, int wr, int wc, const double* __restrict__ G, double* __restrict__ M, int ld,
+                              int r0, int c0, int sym) {
   const int t = (int)threadIdx.x;
   if (t >= w * w) return;
   const int i = t / w, j = t % w;
+  if (i >= wr || j >= wc) return;
   M[(long)(r0 + i) * ld + c0 + j] = G[t];
   if (sym) M[(long)(c0 + j) * ld + r0 + i] = G[t];
 }
-void launch_place_block(int w, const double* G, double* M, int ld, int r0, int c0, int sym, hipStream_t s) {
-  hipLaunchKernelGGL(k_place_block, dim3(1), dim3(256), 0, s, w, G, M, ld, r0, c0, sym);
+void launch_place_block(int w, int wr, int wc, const double* G, double* M, int ld, int r0, int c0, int sym,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_place_block, dim3(1), dim3(256), 0, s, w, wr, wc, G, M, ld, r0, c0, sym);
+}
+
+// dst (rows x w) = the columns idx[0..n) of src (rows x w) in that order, then zero columns
+struct ColSel {
+  int idx[16];
+  int n;
+};
+__global__ void k_gather_cols(int rows, int w, ColSel sel, const double* __restrict__ src, double* __restrict__ dst) {
+  const long t = (long)blockIdx.x * BLK + threadIdx.x;
+  if (t >= (long)rows * w) return;
+  const long r = t / w;
+  const int c = (int)(t - r * w);
+  dst[t] = c < sel.n ? src[r * w + sel.idx[c]] : 0.0;
+}
+void launch_gather_cols(int rows, int w, const int* idx, int n, const double* src, double* dst, hipStream_t s) {
+  if (w < 1 || w > 16 || n < 0 || n > w) throw SolverError{ST_E_INVALID, "column selection"};
+  ColSel sel{};
+  for (int q = 0; q < n; ++q) sel.idx[q] = idx[q];
+  sel.n = n;
+  if (rows > 0) hipLaunchKernelGGL(k_gather_cols, dim3(ceil_div((long)rows * w, BLK)), dim3(BLK), 0, s, rows, w, sel, src, dst);
 }
 
 // rowC[k] = i for every entry k of row i of a CSR pattern (one thread per row)

@@ -281,8 +281,8 @@ class Solver {
   void lobpcg_setup();
   void lobpcg_iteration();
   void lob_remove(double* Y, int rows, std::initializer_list<const double*> bases);
-  bool lob_pcheck(const double* P0, double* Pq, int rows, std::initializer_list<const double*> bases, double* tmp,
-                  const char* side);
+  bool lob_pcheck(const double* P0, double* Pq, int rows, int nact, std::initializer_list<const double*> bases,
+                  double* tmp, const char* side);
   void cholqr2(double* X, int rows, double* tmp, double* out);
   void cholqr2_pair(double* Xa, int rows_a, double* tmpa, double* outa, double* Xb, int rows_b, double* tmpb,
                     double* outb);
@@ -2042,9 +2042,10 @@ void Solver::ritz_level(int l) {
 // additive phase).  The preconditioned direction of a column is the change the additive cycle
 // makes to it, W = C(X) - X; the Ritz step runs on span[X, W, P] with P the previous search
 // direction.  Bases block by block: Cholesky-QR2 of X; W with its X components removed (two
-// passes), Cholesky-QR2; P with its X and W components removed (two passes), kept only when every
-// column of P (a part of a unit Ritz vector) has norm at least 1e-10 on each side, every column
-// keeps at least 1e-8 of its norm and the unshifted Cholesky factorisation of its
+// passes), Cholesky-QR2; P with its X and W components removed (two passes).  A column of P (a
+// part of a unit Ritz vector) below 1e-10 on either side is left out (its Ritz vector no longer
+// moves: the others come first, zero columns after them); the block of the others is kept only
+// when one remains, every column keeps at least 1e-8 of its norm and the unshifted Cholesky factorisation of its
 // column-scaled Gram matrix has no pivot below 1e-10 (a condition number below about 1e5, so that
 // rounding does not decide).  SVD: both sides, P kept on both or neither; for minimal
 // targets the left blocks are those of A Q_v (a two-sided projection of the enlarged spaces has
@@ -2082,8 +2083,9 @@ void Solver::lob_remove(double* Y, int rows, std::initializer_list<const double*
     }
 }
 
-// Pq (a copy of P0) projected and orthonormalised; returns whether the P block is kept
-bool Solver::lob_pcheck(const double* P0, double* Pq, int rows, std::initializer_list<const double*> bases,
+// Pq (a copy of P0, nact leading columns, zero columns after them) projected and orthonormalised;
+// returns whether the P block is kept
+bool Solver::lob_pcheck(const double* P0, double* Pq, int rows, int nact, std::initializer_list<const double*> bases,
                         double* tmp, const char* side) {
   const size_t w2 = (size_t)nb_ * nb_;
   launch_gram(rows, nb_, P0, P0, partial_, gram_, st_);
@@ -2092,7 +2094,7 @@ bool Solver::lob_pcheck(const double* P0, double* Pq, int rows, std::initializer
   launch_gram(rows, nb_, Pq, Pq, partial_, gram_, st_);
   HIPCHK(hipMemcpyAsync(lobchk_ + 256, gram_, w2 * sizeof(double), hipMemcpyDeviceToDevice, st_));
   // Cholesky-QR2; a failed factorisation only drops the block (status into lobflag_)
-  launch_chol_inv_upper_pivot(nb_, gram_, small1_, lobflag_, lobchk_ + 511, st_);
+  launch_chol_inv_upper_pivot(nb_, nact, gram_, small1_, lobflag_, lobchk_ + 511, st_);
   launch_rotate<double>(rows, nb_, nb_, Pq, small1_, tmp, st_);
   launch_gram(rows, nb_, tmp, tmp, partial_, gram_, st_);
   launch_chol_inv_upper(nb_, gram_, small1_, lobflag_, st_);
@@ -2100,7 +2102,7 @@ bool Solver::lob_pcheck(const double* P0, double* Pq, int rows, std::initializer
   std::vector<double> h;
   d2h(h, lobchk_, 512, st_);
   double ratio = 1.0;
-  for (int j = 0; j < nb_; ++j) {
+  for (int j = 0; j < nact; ++j) {
     const double g0 = h[(size_t)j * nb_ + j], g = h[256 + (size_t)j * nb_ + j];
     ratio = g > 0.0 ? std::min(ratio, std::sqrt(g / g0)) : 0.0;
     if (!(g > 0.0)) break;
@@ -2139,6 +2141,7 @@ void Solver::lobpcg_iteration() {
   lob_remove(lbu_.W, mu, {lbu_.X});
   cholqr2(lbu_.W, mu, lbu_.tmp, lbu_.W);
   bool keep = false;
+  int act[16] = {}, nact = 0;
   if (lob_have_p_) {
     // columns of P at least 1e-10 on each side (a smaller one: a Ritz vector that no longer moves)
     const size_t w2 = (size_t)nb_ * nb_;
@@ -2150,28 +2153,27 @@ void Solver::lobpcg_iteration() {
     }
     std::vector<double> h;
     d2h(h, lobchk_, 512, st_);
-    bool moving = true;
+    // the columns that still move, in column order; their blocks (P0 in T) lead, zeros after
     for (int j = 0; j < nb_; ++j) {
-      moving = moving && h[(size_t)j * nb_ + j] >= 1e-20;
-      if (svd) moving = moving && h[256 + (size_t)j * nb_ + j] >= 1e-20;
+      bool m = h[(size_t)j * nb_ + j] >= 1e-20;
+      if (svd) m = m && h[256 + (size_t)j * nb_ + j] >= 1e-20;
+      if (m) act[nact++] = j;
     }
-    bool okv = moving;
-    if (svd && moving) {
-      HIPCHK(hipMemcpyAsync(lbv_.Pq, lbv_.P, nv * sizeof(double), hipMemcpyDeviceToDevice, st_));
-      okv = lob_pcheck(lbv_.P, lbv_.Pq, mv, {lbv_.X, lbv_.W}, lbv_.tmp, "V");
+    bool okv = nact > 0;
+    if (svd && okv) {
+      launch_gather_cols(mv, nb_, act, nact, lbv_.P, lbv_.T, st_);
+      HIPCHK(hipMemcpyAsync(lbv_.Pq, lbv_.T, nv * sizeof(double), hipMemcpyDeviceToDevice, st_));
+      okv = lob_pcheck(lbv_.T, lbv_.Pq, mv, nact, {lbv_.X, lbv_.W}, lbv_.tmp, "V");
     }
-    if (okv && moving) {
-      const double* P0 = lbu_.P;
-      if (one_sided) {
-        spmm<double>(0, L.A, L.A.v, nb_, lbv_.Pq, lbu_.T, 0.0);
-        P0 = lbu_.T;
-      }
-      HIPCHK(hipMemcpyAsync(lbu_.Pq, P0, nu * sizeof(double), hipMemcpyDeviceToDevice, st_));
-      keep = lob_pcheck(P0, lbu_.Pq, mu, {lbu_.X, lbu_.W}, lbu_.tmp, svd ? "U" : "X");
+    if (okv) {
+      if (one_sided) spmm<double>(0, L.A, L.A.v, nb_, lbv_.Pq, lbu_.T, 0.0);
+      else launch_gather_cols(mu, nb_, act, nact, lbu_.P, lbu_.T, st_);
+      HIPCHK(hipMemcpyAsync(lbu_.Pq, lbu_.T, nu * sizeof(double), hipMemcpyDeviceToDevice, st_));
+      keep = lob_pcheck(lbu_.T, lbu_.Pq, mu, nact, {lbu_.X, lbu_.W}, lbu_.tmp, svd ? "U" : "X");
     }
     if (!keep) ++rep_.p_dropped;
   }
-  const int nblk = keep ? 3 : 2, k = nblk * nb_;
+  const int nblk = keep ? 3 : 2, k = 2 * nb_ + (keep ? nact : 0);
   const double* Qu[3] = {lbu_.X, lbu_.W, lbu_.Pq};
   const double* Qv[3] = {svd ? lbv_.X : lbu_.X, svd ? lbv_.W : lbu_.W, svd ? lbv_.Pq : lbu_.Pq};
   for (int c = 0; c < nblk; ++c) {
@@ -2179,11 +2181,15 @@ void Solver::lobpcg_iteration() {
     for (int a = 0; a < nblk; ++a) {
       if (!svd && a > c) continue;   // symmetric: block (c, a) is the transpose of (a, c)
       launch_gram(mu, nb_, Qu[a], lbu_.T, partial_, gram_, st_);
-      launch_place_block(nb_, gram_, lobM_, k, a * nb_, c * nb_, !svd && a != c, st_);
+      launch_place_block(nb_, a == 2 ? nact : nb_, c == 2 ? nact : nb_, gram_, lobM_, k, a * nb_, c * nb_,
+                         !svd && a != c, st_);
     }
   }
   launch_eye(k, lobB_, st_);
   if (svd) launch_eye(k, lobC_, st_);
+  // rows of the Ritz coefficients beyond k stay zero (they meet the zero columns of the P basis)
+  launch_fill(lobY_, (size_t)3 * nb_ * nb_, 0.0, st_);
+  if (svd) launch_fill(lobZ_, (size_t)3 * nb_ * nb_, 0.0, st_);
   launch_coarse_gsvd(spd_, minimal_, k, k, nb_, lobM_, lobB_, svd ? lobC_ : nullptr, lobwork_, sig_, lobY_,
                      svd ? lobZ_ : nullptr, status_, st_);
   // new Ritz vectors Q Y and search directions (the W and P block parts)
