@@ -52,8 +52,8 @@ TRAFFIC = {
         note="mean of the finest-level u-row and v-row launches"),
     # every finest-level k_kacz launch of the multiplicative phase and one additive iteration
     ("aniso3d_128_min8", 1): dict(
-        kernels_sha256="638b24dfeeba679741954e4e00386d8d35bbae2cd5665c343558d3f3fbbc7416",
-        fetch_kib=(117666.6,), write_kib=(154370.1,),
+        kernels_sha256="f910d07505489c0af19a2c36b9cd904ffbc5434d5678dffd5a5bfb7076029ec4",
+        fetch_kib=(117662.2,), write_kib=(154376.8,),
         copy_fetch_kib=524304.5, copy_write_kib=1048576.0, copy_bytes=1 << 30,
         note="mean over the 1240 finest-level Kaczmarz colour launches of the multiplicative phase and "
              "one additive iteration"),
