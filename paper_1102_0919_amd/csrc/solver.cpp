@@ -291,6 +291,7 @@ class Solver {
   void residual_collect(std::vector<double>& rho);
   void iteration_body();
   void capture_iteration();
+  bool lob_replay_ = false;   // the LOBPCG iteration replays the captured additive cycle
   std::vector<void**> block_pointers();
   void check_status();
   void dense_coarsest(double* X, double* Y);
@@ -2125,7 +2126,13 @@ void Solver::lobpcg_iteration() {
   const bool svd = !spd_, one_sided = svd && minimal_;
   HIPCHK(hipMemcpyAsync(lbu_.X, b.Ub, nu * sizeof(double), hipMemcpyDeviceToDevice, st_));
   if (svd) HIPCHK(hipMemcpyAsync(lbv_.X, b.Vb, nv * sizeof(double), hipMemcpyDeviceToDevice, st_));
-  additive_iteration();
+  if (lob_replay_) {
+    HIPCHK(hipGraphLaunch(igx_, st_));
+    if (p_.coarse_pinv == 0) pinv_calls_ += coarse_calls_per_iter();
+    ++rep_.graph_iters;
+  } else {
+    additive_iteration();
+  }
   launch_axpby(nu, 1.0, b.Ub, -1.0, lbu_.X, lbu_.W, st_);   // W = C(X) - X
   if (svd) {
     launch_axpby(nv, 1.0, b.Vb, -1.0, lbv_.X, lbv_.W, st_);
@@ -2280,7 +2287,8 @@ std::vector<void**> Solver::block_pointers() {
   return v;
 }
 
-// Capture one iteration into a graph.  The capture runs the host side of the iteration without
+// Capture one iteration into a graph (the LOBPCG phase: its additive cycle only, the rest of its
+// iteration decides on P on the host).  The capture runs the host side of the iteration without
 // executing anything; the graph is kept only if the iteration leaves every block pointer where it
 // found it (an even number of swaps per pair), so that replays chain.
 void Solver::capture_iteration() {
@@ -2294,7 +2302,8 @@ void Solver::capture_iteration() {
   try {
     HIPCHK(hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal));
     try {
-      iteration_body();
+      if (p_.solve_phase == 1) additive_iteration();
+      else iteration_body();
     } catch (...) {
       hipGraph_t g2 = nullptr;
       (void)hipStreamEndCapture(st_, &g2);
@@ -2483,7 +2492,7 @@ void Solver::run(const double* init_tests, SolveOutput& out) {
   if (mixed_) cast_transfers();
   for (auto& Lp : lv_) long_rows(*Lp);   // before any capture
   int it = 0, it0 = 0;
-  graph_off_ = !p_.graphs || p_.solve_phase == 1;   // LOBPCG decides on P on the host
+  graph_off_ = !p_.graphs;
   if (p_.solve_phase == 1) lobpcg_setup();
   // redetermined interpolation (§6.3): pairs whose sigma has settled, and the previous sigma
   std::vector<char> conv(nb_, 0);
@@ -2498,12 +2507,13 @@ void Solver::run(const double* init_tests, SolveOutput& out) {
     pinv_reortho_ = eager;
     if (!eager && !graph_off_ && !igx_) capture_iteration();
     const bool replay = !eager && igx_ != nullptr;
-    if (replay) {
+    if (p_.solve_phase == 1) {
+      lob_replay_ = replay;
+      lobpcg_iteration();
+    } else if (replay) {
       HIPCHK(hipGraphLaunch(igx_, st_));
       if (p_.coarse_pinv == 0) pinv_calls_ += coarse_calls_per_iter();
       ++rep_.graph_iters;
-    } else if (p_.solve_phase == 1) {
-      lobpcg_iteration();
     } else {
       iteration_body();
     }

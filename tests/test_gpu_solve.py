@@ -243,6 +243,8 @@ def test_request_interface_matches_solve(ctx):
     ("gradient2d_256_dom8", 32, {}),                               # Jacobi-type, rectangular SVD
     ("laplace2d_31_min4", None, {"cycle_gamma": 2}),               # W-cycle: 8 coarsest solves per iteration
     ("laplace2d_31_min4", None, {"fmg": 1}),                       # FMG: 5 coarsest solves per iteration
+    ("laplace2d_31_min4", None, {"solve_phase": 1}),               # LOBPCG: the cycle replayed, the rest eager
+    ("gradient2d_256_dom8", 32, {"solve_phase": 1}),               # LOBPCG, rectangular SVD
 ])
 def test_graph_replay_bitwise_equals_eager(ctx, name, scale, over):
     from paper_1102_0919_amd import api
@@ -709,7 +711,7 @@ def test_lobpcg_phase_vs_oracle(ctx, name, scale, precision, ref):
     assert r.converged and o.report["converged"]
     assert rep["sizes"] == [tuple(x) for x in o.report["sizes"]]
     assert rep["add_iters"] < 40 and abs(rep["add_iters"] - o.report["add_iters"]) <= 2
-    assert r.report.graph_iters == 0
+    assert r.report.graph_iters > 0            # the additive cycle of an iteration replays a graph
     orho = [float(np.max(x[: wl["n_b"]])) for x in o.report["rho"]]
     assert np.allclose(rep["rho_history"][:4], orho[:4], rtol=1e-4)
     if ref is not None:
