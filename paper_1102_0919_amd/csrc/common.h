@@ -233,6 +233,8 @@ void launch_chol_inv_upper_pivot(int w, int wpiv, const double* G, double* T, in
 // two factorisations (G0 -> T0, G1 -> T1) in one launch
 void launch_chol_inv_upper2(int w, const double* G0, double* T0, const double* G1, double* T1, int* status,
                             hipStream_t s);
+// SVD of a k x k projected matrix (k <= 32), the nb triplets in target order: Y, Z (k x nb), sig
+void launch_proj_svd(int k, int nb, int minimal, const double* M, double* Y, double* Z, double* sig, hipStream_t s);
 void launch_small_ritz(int w, int spd, int minimal, const double* M, double* Y, double* Z, double* sig,
                        double* work, int* status, hipStream_t s);
 void launch_coarse_gsvd(int spd, int minimal, int mL, int nL, int nb, double* A, double* B, double* C,

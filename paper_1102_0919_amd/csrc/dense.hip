@@ -468,6 +468,139 @@ __global__ __launch_bounds__(64) void k_small_svd(int w, int minimal, const doub
   if (lane < w) sig[lane] = ss[lane];
 }
 
+// SVD of the k x k projected matrix of the LOBPCG step (k <= 32) by one-sided (Hestenes) Jacobi, as
+// k_small_svd: columns of M and of V (from I) rotated in pairs until every pair is orthogonal to
+// 1e-15 relative; sigma_j = ||M e_j||, z_j = V e_j, y_j = M z_j / sigma_j, zero sigma (<= 1e-13
+// sigma_max) completed to an orthonormal set.  A pair slot of 8 lanes holds rows r, r + 8, r + 16,
+// r + 24 of its two columns; 16 slots rotate the 16 pairs of a round.  Output: the nb triplets in
+// target order (descending for dominant, ascending for minimal), Y, Z (k x nb row-major), sig (nb).
+constexpr int PSB = 128;
+__global__ __launch_bounds__(PSB) void k_proj_svd(int k, int nb, int minimal, const double* M, double* Y, double* Z,
+                                                  double* sig) {
+  __shared__ double Ms[32 * 32], Vs[32 * 32];   // row-major, ld 32, zero beyond k
+  __shared__ double Ys[32 * 32], Zs[32 * 32];   // sorted triplets, ld 32
+  __shared__ double sg[32], ss[32];
+  __shared__ int ord[32], tinyk[32];
+  __shared__ int rot;
+  const int t = threadIdx.x;
+  for (int q = t; q < 1024; q += PSB) {
+    const int i = q >> 5, j = q & 31;
+    Ms[q] = (i < k && j < k) ? M[i * k + j] : 0.0;
+    Vs[q] = (i == j && i < k) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int W = k + (k & 1), np = W / 2;
+  const int slot = t >> 3, r = t & 7;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    if (t == 0) rot = 0;
+    __syncthreads();
+    for (int rr = 0; rr < W - 1; ++rr) {
+      int p = 0, q = 0;
+      if (slot < np) {
+        const int a = slot, b = W - 1 - slot;
+        int pp = a - 1 + rr, qq = b - 1 + rr;
+        pp = a == 0 ? 0 : (pp >= W - 1 ? pp - (W - 1) : pp) + 1;
+        qq = b == 0 ? 0 : (qq >= W - 1 ? qq - (W - 1) : qq) + 1;
+        p = pp < qq ? pp : qq;
+        q = pp < qq ? qq : pp;
+      }
+      const bool act = slot < np && q < k;   // the padding column (odd k) pairs with nothing
+      double mp[4], mq[4], vp[4], vq[4];
+      double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int row = r + 8 * u;
+        mp[u] = act ? Ms[row * 32 + p] : 0.0;
+        mq[u] = act ? Ms[row * 32 + q] : 0.0;
+        vp[u] = act ? Vs[row * 32 + p] : 0.0;
+        vq[u] = act ? Vs[row * 32 + q] : 0.0;
+        al += mp[u] * mp[u];
+        be += mq[u] * mq[u];
+        ga += mp[u] * mq[u];
+      }
+#pragma unroll
+      for (int m = 1; m < 8; m <<= 1) {
+        al += __shfl_xor(al, m);
+        be += __shfl_xor(be, m);
+        ga += __shfl_xor(ga, m);
+      }
+      if (act && ga * ga > 1e-30 * al * be && fabs(ga) > 1e-300) {
+        const double zeta = (be - al) / (2.0 * ga);
+        const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + tt * tt), sn = tt * c;
+        if (r == 0) rot = 1;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int row = r + 8 * u;
+          Ms[row * 32 + p] = c * mp[u] - sn * mq[u];
+          Ms[row * 32 + q] = sn * mp[u] + c * mq[u];
+          Vs[row * 32 + p] = c * vp[u] - sn * vq[u];
+          Vs[row * 32 + q] = sn * vp[u] + c * vq[u];
+        }
+      }
+      __syncthreads();
+    }
+    const int any = rot;
+    __syncthreads();
+    if (any == 0) break;
+  }
+  if (t < k) {
+    double s2 = 0.0;
+    for (int i = 0; i < k; ++i) s2 += Ms[i * 32 + t] * Ms[i * 32 + t];
+    sg[t] = sqrt(s2);
+  }
+  select_extremal<PSB>(sg, k, k, true, ord);   // descending
+  const double smax = sg[ord[0]];
+  if (t < k) {
+    const int src = ord[t], dst = minimal ? (k - 1 - t) : t;
+    const double sk = sg[src];
+    const bool tiny = !(sk > 1e-13 * smax);
+    for (int i = 0; i < k; ++i) {
+      Zs[i * 32 + dst] = Vs[i * 32 + src];
+      Ys[i * 32 + dst] = tiny ? 0.0 : Ms[i * 32 + src] / sk;
+    }
+    ss[dst] = sk;
+    tinyk[dst] = tiny ? 1 : 0;
+  }
+  __syncthreads();
+  // zero sigma: y from the first unit vector that keeps norm > 1/2 after two Gram-Schmidt passes
+  // against the columns already set (column order)
+  if (t == 0) {
+    for (int c = 0; c < k; ++c) {
+      if (!tinyk[c]) continue;
+      for (int e = 0; e < k; ++e) {
+        for (int i = 0; i < k; ++i) Ys[i * 32 + c] = i == e ? 1.0 : 0.0;
+        for (int pass = 0; pass < 2; ++pass)
+          for (int c2 = 0; c2 < k; ++c2) {
+            if (c2 == c || (tinyk[c2] && c2 > c)) continue;
+            double d = 0.0;
+            for (int i = 0; i < k; ++i) d += Ys[i * 32 + c] * Ys[i * 32 + c2];
+            for (int i = 0; i < k; ++i) Ys[i * 32 + c] -= d * Ys[i * 32 + c2];
+          }
+        double nrm = 0.0;
+        for (int i = 0; i < k; ++i) nrm += Ys[i * 32 + c] * Ys[i * 32 + c];
+        nrm = sqrt(nrm);
+        if (nrm > 0.5) {
+          for (int i = 0; i < k; ++i) Ys[i * 32 + c] /= nrm;
+          break;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int q = t; q < k * nb; q += PSB) {
+    const int i = q / nb, d = q % nb;
+    Y[q] = Ys[i * 32 + d];
+    Z[q] = Zs[i * 32 + d];
+  }
+  if (t < nb) sig[t] = ss[t];
+}
+// the caller keeps 1 <= nb <= k <= 32; other sizes launch nothing
+void launch_proj_svd(int k, int nb, int minimal, const double* M, double* Y, double* Z, double* sig, hipStream_t s) {
+  if (k < 1 || k > 32 || nb < 1 || nb > k) return;
+  hipLaunchKernelGGL(k_proj_svd, dim3(1), dim3(PSB), 0, s, k, nb, minimal, M, Y, Z, sig);
+}
+
 void launch_small_ritz(int w, int spd, int minimal, const double* M, double* Y, double* Z, double* sig, double* work,
                        int* status, hipStream_t s) {
   (void)work;

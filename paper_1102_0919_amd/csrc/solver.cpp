@@ -2197,8 +2197,13 @@ void Solver::lobpcg_iteration() {
   // rows of the Ritz coefficients beyond k stay zero (they meet the zero columns of the P basis)
   launch_fill(lobY_, (size_t)3 * nb_ * nb_, 0.0, st_);
   if (svd) launch_fill(lobZ_, (size_t)3 * nb_ * nb_, 0.0, st_);
-  launch_coarse_gsvd(spd_, minimal_, k, k, nb_, lobM_, lobB_, svd ? lobC_ : nullptr, lobwork_, sig_, lobY_,
-                     svd ? lobZ_ : nullptr, status_, st_);
+  if (svd && k <= 32) {
+    // one-sided Jacobi on the projected matrix itself (orthonormal bases: identity metrics)
+    launch_proj_svd(k, nb_, minimal_, lobM_, lobY_, lobZ_, sig_, st_);
+  } else {
+    launch_coarse_gsvd(spd_, minimal_, k, k, nb_, lobM_, lobB_, svd ? lobC_ : nullptr, lobwork_, sig_, lobY_,
+                       svd ? lobZ_ : nullptr, status_, st_);
+  }
   // new Ritz vectors Q Y and search directions (the W and P block parts)
   const size_t w2 = (size_t)nb_ * nb_;
   auto update = [&](const double* const* Q, const double* Y, int rows, double* X, double* P) {
