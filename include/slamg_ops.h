@@ -141,6 +141,15 @@ slamg_status slamg_op_coarse_gsvd(int32_t spd, int32_t minimal, int32_t mL, int3
                                   const double* h_a, const double* h_b, const double* h_c, double* h_sig,
                                   double* h_u, double* h_v);
 
+/* SVD of the k x k projected matrix of the LOBPCG step (§7, the Rayleigh-Ritz step on span[X, W, P]
+ * of an SVD target with orthonormal bases): the nb singular triplets M z_j = sigma_j y_j with the
+ * largest (minimal = 0) or smallest (minimal = 1) sigma, in that order, by one-sided Jacobi on M.
+ * h_m: dense row-major k x k (host); h_sig (nb), h_y (k x nb), h_z (k x nb) row-major (host,
+ * caller-owned).  Singular values at or below 1e-13 sigma_max get y completed to an orthonormal
+ * set.  SLAMG_E_INVALID unless 1 <= nb <= k <= 32 and every pointer is non-null. */
+slamg_status slamg_op_proj_svd(int32_t minimal, int32_t k, int32_t nb, const double* h_m, double* h_sig,
+                               double* h_y, double* h_z);
+
 /* Additive coarsest solve (§4.2): per column j, variant 0 applies the pseudo-inverse of
  * X - sig_j Y from its SVD without the smallest singular component; variant 1 the pencil variant;
  * variants 2, 3 and 4 are variant 0 computed the way consecutive additive iterations compute it,

@@ -91,6 +91,7 @@ SIGNATURES = {
     "slamg_op_topsel": (_I, [_I, _P, _P, _P, _I, _P, _P, _P]),
     "slamg_op_coarse_gsvd": (_I, [_I, _I, _I, _I, _I, _P, _P, _P, _P, _P, _P]),
     "slamg_op_coarse_solve": (_I, [_I, _I, _I, _P, _P, _P, _P, _P]),
+    "slamg_op_proj_svd": (_I, [_I, _I, _I, _P, _P, _P, _P]),
     "slamg_graph_strength": (_I, [_I, _P, _P, _P, _D, _I, _I, _P, _P]),
     "slamg_graph_rs": (_I, [_I, _P, _P, _P]),
     "slamg_graph_interp": (_I, [_I, _P, _P, _P, _P, _P, _P, _I, _P, _P, _P]),

@@ -436,28 +436,36 @@ __global__ __launch_bounds__(64) void k_small_svd(int w, int minimal, const doub
     tinyk[dst] = tiny ? 1 : 0;
   }
   __syncthreads();
-  // zero sigma: y_k from the first unit vector that keeps norm > 1/2 after two Gram-Schmidt passes
-  // against the columns already set (column order)
+  // zero sigma: y_k from the unit vector e_e with the largest remainder after projection onto the
+  // columns already set (orthonormal, so the remainder is 1 - sum_k2 Y[e][k2]^2, at least 1/w while
+  // the complement is not empty; ties to the lower e), then two Gram-Schmidt passes against them
+  // (column order)
   if (lane == 0) {
     for (int k = 0; k < w; ++k) {
       if (!tinyk[k]) continue;
+      int eb = 0;
+      double best = -1.0;
       for (int e = 0; e < w; ++e) {
-        for (int i = 0; i < w; ++i) Ys[i * w + k] = i == e ? 1.0 : 0.0;
-        for (int pass = 0; pass < 2; ++pass)
-          for (int k2 = 0; k2 < w; ++k2) {
-            if (k2 == k || (tinyk[k2] && k2 > k)) continue;
-            double d = 0.0;
-            for (int i = 0; i < w; ++i) d += Ys[i * w + k] * Ys[i * w + k2];
-            for (int i = 0; i < w; ++i) Ys[i * w + k] -= d * Ys[i * w + k2];
-          }
-        double nrm = 0.0;
-        for (int i = 0; i < w; ++i) nrm += Ys[i * w + k] * Ys[i * w + k];
-        nrm = sqrt(nrm);
-        if (nrm > 0.5) {
-          for (int i = 0; i < w; ++i) Ys[i * w + k] /= nrm;
-          break;
+        double rem = 1.0;
+        for (int k2 = 0; k2 < w; ++k2)
+          if (k2 != k && !(tinyk[k2] && k2 > k)) rem -= Ys[e * w + k2] * Ys[e * w + k2];
+        if (rem > best) {
+          best = rem;
+          eb = e;
         }
       }
+      for (int i = 0; i < w; ++i) Ys[i * w + k] = i == eb ? 1.0 : 0.0;
+      for (int pass = 0; pass < 2; ++pass)
+        for (int k2 = 0; k2 < w; ++k2) {
+          if (k2 == k || (tinyk[k2] && k2 > k)) continue;
+          double d = 0.0;
+          for (int i = 0; i < w; ++i) d += Ys[i * w + k] * Ys[i * w + k2];
+          for (int i = 0; i < w; ++i) Ys[i * w + k] -= d * Ys[i * w + k2];
+        }
+      double nrm = 0.0;
+      for (int i = 0; i < w; ++i) nrm += Ys[i * w + k] * Ys[i * w + k];
+      nrm = sqrt(nrm);
+      for (int i = 0; i < w; ++i) Ys[i * w + k] /= nrm;
     }
   }
   __syncthreads();
@@ -563,28 +571,36 @@ __global__ __launch_bounds__(PSB) void k_proj_svd(int k, int nb, int minimal, co
     tinyk[dst] = tiny ? 1 : 0;
   }
   __syncthreads();
-  // zero sigma: y from the first unit vector that keeps norm > 1/2 after two Gram-Schmidt passes
-  // against the columns already set (column order)
+  // zero sigma: y from the unit vector e_e with the largest remainder after projection onto the
+  // columns already set (orthonormal, so the remainder is 1 - sum_c2 Y[e][c2]^2, at least 1/k while
+  // the complement is not empty; ties to the lower e), then two Gram-Schmidt passes against them
+  // (column order)
   if (t == 0) {
     for (int c = 0; c < k; ++c) {
       if (!tinyk[c]) continue;
+      int eb = 0;
+      double best = -1.0;
       for (int e = 0; e < k; ++e) {
-        for (int i = 0; i < k; ++i) Ys[i * 32 + c] = i == e ? 1.0 : 0.0;
-        for (int pass = 0; pass < 2; ++pass)
-          for (int c2 = 0; c2 < k; ++c2) {
-            if (c2 == c || (tinyk[c2] && c2 > c)) continue;
-            double d = 0.0;
-            for (int i = 0; i < k; ++i) d += Ys[i * 32 + c] * Ys[i * 32 + c2];
-            for (int i = 0; i < k; ++i) Ys[i * 32 + c] -= d * Ys[i * 32 + c2];
-          }
-        double nrm = 0.0;
-        for (int i = 0; i < k; ++i) nrm += Ys[i * 32 + c] * Ys[i * 32 + c];
-        nrm = sqrt(nrm);
-        if (nrm > 0.5) {
-          for (int i = 0; i < k; ++i) Ys[i * 32 + c] /= nrm;
-          break;
+        double rem = 1.0;
+        for (int c2 = 0; c2 < k; ++c2)
+          if (c2 != c && !(tinyk[c2] && c2 > c)) rem -= Ys[e * 32 + c2] * Ys[e * 32 + c2];
+        if (rem > best) {
+          best = rem;
+          eb = e;
         }
       }
+      for (int i = 0; i < k; ++i) Ys[i * 32 + c] = i == eb ? 1.0 : 0.0;
+      for (int pass = 0; pass < 2; ++pass)
+        for (int c2 = 0; c2 < k; ++c2) {
+          if (c2 == c || (tinyk[c2] && c2 > c)) continue;
+          double d = 0.0;
+          for (int i = 0; i < k; ++i) d += Ys[i * 32 + c] * Ys[i * 32 + c2];
+          for (int i = 0; i < k; ++i) Ys[i * 32 + c] -= d * Ys[i * 32 + c2];
+        }
+      double nrm = 0.0;
+      for (int i = 0; i < k; ++i) nrm += Ys[i * 32 + c] * Ys[i * 32 + c];
+      nrm = sqrt(nrm);
+      for (int i = 0; i < k; ++i) Ys[i * 32 + c] /= nrm;
     }
   }
   __syncthreads();

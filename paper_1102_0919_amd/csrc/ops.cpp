@@ -393,6 +393,24 @@ extern "C" slamg_status slamg_op_coarse_gsvd(int32_t spd, int32_t minimal, int32
   });
 }
 
+extern "C" slamg_status slamg_op_proj_svd(int32_t minimal, int32_t k, int32_t nb, const double* h_m, double* h_sig,
+                                          double* h_y, double* h_z) {
+  if (k < 1 || k > 32 || nb < 1 || nb > k || !h_m || !h_sig || !h_y || !h_z) return SLAMG_E_INVALID;
+  hipStream_t s = nullptr;
+  return guarded(s, [&] {
+    Tmp t;
+    double* M = t.get<double>((size_t)k * k);
+    double* Y = t.get<double>((size_t)k * nb);
+    double* Z = t.get<double>((size_t)k * nb);
+    double* sig = t.get<double>(nb);
+    up(M, h_m, (size_t)k * k, s);
+    launch_proj_svd(k, nb, minimal ? 1 : 0, M, Y, Z, sig, s);
+    down(h_sig, sig, nb, s);
+    down(h_y, Y, (size_t)k * nb, s);
+    down(h_z, Z, (size_t)k * nb, s);
+  });
+}
+
 extern "C" slamg_status slamg_op_coarse_solve(int32_t variant, int32_t N, int32_t nb, const double* h_x,
                                               const double* h_y, const double* h_sig, const double* h_rhs,
                                               double* h_out) {

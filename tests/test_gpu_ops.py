@@ -307,6 +307,37 @@ def test_ritz_parity(L, kind, target):
                            atol=1e-10)
 
 
+@pytest.mark.parametrize("nnull,seed", [(1, 0), (1, 2), (1, 3), (3, 1), (6, 2)])
+def test_ritz_zero_singular_values(L, nnull, seed):
+    # a block V whose span meets null(A) in nnull dimensions makes the w x w Ritz matrix rank
+    # deficient: its zero singular values come first for a minimal target with their left vectors
+    # completed to an orthonormal set, so the new U and V stay orthonormal, U^t A V is the diagonal
+    # of the Ritz values, and the nonzero Ritz values agree with the oracle's.  With 16 columns the
+    # complement of the nonzero left vectors can have no unit-vector component above 1/2 (seeds 0, 2
+    # and 3 of one null direction, seed 2 of six).
+    rng = np.random.default_rng(seed * 10 + nnull)
+    m, n, w = 60, 50, 16
+    Ad = sp.random(m, n, density=0.3, random_state=np.random.RandomState(seed * 10 + nnull), format="lil")
+    Ad[:, :10] = 0.0
+    A = sp.csr_matrix(Ad)
+    U = rng.normal(size=(m, w))
+    V = rng.normal(size=(n, w))
+    V[10:, w - nnull:] = 0.0           # the last nnull columns lie in null(A)
+    sig_o, _, _ = O.ritz(A, "svd", "minimal", U, V)
+    assert np.all(sig_o[:nnull] <= 1e-13 * sig_o[-1]) and sig_o[nnull] > 1e-3 * sig_o[-1]
+    a = csr_dev(A)
+    du, dv = dev(U), dev(V)
+    hs = np.zeros(w)
+    assert L.slamg_op_ritz(0, 1, m, n, w, *map(ptr, a), ptr(du), ptr(dv), hp(hs), None) == 0
+    Ug, Vg = host(du), host(dv)
+    smax = sig_o[-1]
+    assert np.all(hs[:nnull] <= 1e-13 * smax)
+    assert np.allclose(hs[nnull:], sig_o[nnull:], rtol=1e-11)
+    assert np.allclose(Ug.T @ Ug, np.eye(w), atol=1e-12)
+    assert np.allclose(Vg.T @ Vg, np.eye(w), atol=1e-12)
+    assert np.allclose(Ug.T @ (A @ Vg), np.diag(hs), atol=1e-12 * smax)
+
+
 @pytest.mark.parametrize("boots", [False, True])
 def test_ls_fit_parity(L, boots):
     N = W.laplace2d(30).to_scipy()
@@ -451,6 +482,74 @@ def test_coarse_gsvd_zero_singular_value(L, m, n):
         s = np.sign(hu[:, j] @ Bd @ Uo[:, j])
         assert np.allclose(hu[:, j] * s, Uo[:, j], atol=1e-7)
         assert np.allclose(hv[:, j] * s, Vo[:, j], atol=1e-7)
+
+
+def _proj_svd(L, M, nb, minimal):
+    k = M.shape[0]
+    hs, hy, hz = np.zeros(nb), np.zeros((k, nb)), np.zeros((k, nb))
+    assert L.slamg_op_proj_svd(1 if minimal else 0, k, nb, hp(np.ascontiguousarray(M)), hp(hs), hp(hy), hp(hz)) == 0
+    return hs, hy, hz
+
+
+@pytest.mark.parametrize("k,nb", [(1, 1), (2, 1), (7, 7), (16, 8), (17, 8), (24, 8), (31, 12), (32, 8), (32, 32)])
+@pytest.mark.parametrize("target", ["dominant", "minimal"])
+def test_proj_svd_parity(L, k, nb, target):
+    # the projected problem of the LOBPCG step for SVD targets (§7): the oracle takes it by a dense
+    # SVD of the k x k matrix; singular values agree to a few eps sigma_max, the triplets satisfy
+    # M z = sigma y and M^t y = sigma z with orthonormal y and z, and vectors of well separated
+    # values agree up to sign
+    rng = np.random.default_rng(k * 100 + nb)
+    M = rng.standard_normal((k, k))
+    hs, hy, hz = _proj_svd(L, M, nb, target == "minimal")
+    Yo, so, Zto = np.linalg.svd(M)
+    order = np.argsort(so) if target == "minimal" else np.argsort(-so)
+    sel = order[:nb]
+    smax = so[0]
+    assert np.all(np.abs(hs - so[sel]) <= 1e-13 * smax), np.abs(hs - so[sel]) / smax
+    assert np.linalg.norm(M @ hz - hy * hs[None, :]) <= 1e-13 * smax
+    assert np.linalg.norm(M.T @ hy - hz * hs[None, :]) <= 1e-13 * smax
+    assert np.allclose(hy.T @ hy, np.eye(nb), atol=1e-13)
+    assert np.allclose(hz.T @ hz, np.eye(nb), atol=1e-13)
+    for j, src in enumerate(sel):
+        gap = np.min(np.abs(np.delete(so, src) - so[src])) if k > 1 else smax
+        if gap < 1e-3 * smax:
+            continue
+        sgn = np.sign(hz[:, j] @ Zto[src])
+        assert np.allclose(hz[:, j] * sgn, Zto[src], atol=1e-10)
+        assert np.allclose(hy[:, j] * sgn, Yo[:, src], atol=1e-10)
+
+
+@pytest.mark.parametrize("k,nb,nzero", [(9, 4, 2), (20, 6, 3), (32, 32, 5), (16, 16, 1), (32, 8, 1), (32, 32, 31),
+                                        (5, 5, 5)])
+def test_proj_svd_zero_singular_values(L, k, nb, nzero):
+    # a projected matrix of rank k - nzero: its zero singular values come first for a minimal target,
+    # with y completed to an orthonormal set in the left null space, and the rest agree with the
+    # dense SVD
+    rng = np.random.default_rng(k + nzero)
+    Uq, _ = np.linalg.qr(rng.standard_normal((k, k)))
+    Vq, _ = np.linalg.qr(rng.standard_normal((k, k)))
+    s = np.concatenate([np.zeros(nzero), np.linspace(0.5, 3.0, k - nzero)])
+    M = (Uq * s[None, :]) @ Vq.T
+    hs, hy, hz = _proj_svd(L, M, nb, True)
+    so = np.sort(np.linalg.svd(M, compute_uv=False))[:nb]
+    smax = 3.0
+    assert np.all(np.abs(hs - so) <= 1e-13 * smax), np.abs(hs - so) / smax
+    nz = min(nzero, nb)
+    assert np.all(hs[:nz] <= 1e-13 * smax)
+    assert np.linalg.norm(M @ hz[:, :nz]) <= 1e-13 * smax
+    assert np.linalg.norm(M.T @ hy[:, :nz]) <= 1e-13 * smax
+    assert np.linalg.norm(M @ hz - hy * hs[None, :]) <= 1e-13 * smax
+    assert np.allclose(hy.T @ hy, np.eye(nb), atol=1e-13)
+    assert np.allclose(hz.T @ hz, np.eye(nb), atol=1e-13)
+
+
+def test_proj_svd_rejects_sizes(L):
+    M = np.eye(33)
+    hs, hy, hz = np.zeros(33), np.zeros((33, 33)), np.zeros((33, 33))
+    assert L.slamg_op_proj_svd(0, 33, 8, hp(M), hp(hs), hp(hy), hp(hz)) == -1
+    assert L.slamg_op_proj_svd(0, 8, 9, hp(M), hp(hs), hp(hy), hp(hz)) == -1
+    assert L.slamg_op_proj_svd(0, 8, 0, hp(M), hp(hs), hp(hy), hp(hz)) == -1
+    assert L.slamg_op_proj_svd(0, 0, 0, hp(M), hp(hs), hp(hy), hp(hz)) == -1
 
 
 @pytest.mark.parametrize("variant,m,n", [(0, 30, 20), (1, 30, 20), (2, 30, 20), (3, 30, 20), (4, 30, 20), (5, 30, 20),

@@ -595,12 +595,17 @@ def test_gradient_minimal_null_pair_and_valid_output(ctx):
     if r.converged:                      # only the true spectrum passes the residual test
         ref = W.gradient2d_singular_values(16)[:8]
         _sig_close(r.sigma, ref, anorm)
-    # the zero pair: sigma_1 = 0 and u_1 in the null space of A^t; v_1 tends to +-1/16 (unique),
-    # which after 30 iterations of a run that does not converge is an iterate: within 1e-2
+    # the zero pair: sigma_1 = 0 and u_1 in the null space of A^t; v_1 tends to +-1/16 (unique), but
+    # after 30 iterations of a run that does not converge it is an iterate whose distance from the
+    # constant vector depends on rounding (cos 0.999995 in the oracle, 0.935 on the device); what the
+    # SVD of A fixes is that its angle to that vector is bounded by its own residual,
+    # sin <= ||A v_1|| / sigma_2 with sigma_2 = 2 sin(pi / 32), and the residual is the reported one
     n = A.shape[1]
+    s2 = 2.0 * np.sin(np.pi / 32)
     for res in (r, o):
         assert res.sigma[0] <= 1e-8 * anorm
-        assert abs(res.V[:, 0].sum()) / np.sqrt(n) >= 0.99
+        cos = abs(res.V[:, 0].sum()) / np.sqrt(n)
+        assert np.sqrt(max(0.0, 1.0 - cos * cos)) <= np.linalg.norm(A @ res.V[:, 0]) / s2 + 1e-12
         assert np.linalg.norm(A.T @ res.U[:, 0]) <= 1e-8 * anorm
     # a valid output: ascending non-negative estimates, orthonormal blocks, and the reported final
     # residual is the residual of the returned triplets
