@@ -192,6 +192,13 @@ struct Level {
   DCsr S1, S2, S3;
   std::vector<Plan> plans;  // Galerkin numeric products producing level + 1
   Plan pAc, pBc, pCc;
+  // A colouring still running reads hA / hAt through pointers.  Members are destroyed in reverse
+  // declaration order, so the future's own wait would come after those patterns are freed: a level
+  // dropped while its colouring runs (a set-up that ends in an error, a level never relaxed, a level
+  // rebuilt) waits for it here, before any member goes.
+  ~Level() {
+    if (colour_job.valid()) colour_job.wait();
+  }
 };
 
 template <class T> static const T* vals(const DCsr& a);
