@@ -187,7 +187,13 @@ slamg_status slamg_params_init(slamg_params* p, slamg_kind kind, slamg_target ta
 slamg_status slamg_create(slamg_ctx** ctx, int device, void* hip_stream, size_t hbm_budget_bytes);
 void slamg_destroy(slamg_ctx* ctx);
 
-/* Solve for n_b triplets (kind SVD) or eigenpairs (kind SPD_EIG, m == n) of A.
+/* Solve for n_b triplets (kind SVD) or eigenpairs (kind SPD_EIG, m == n) of A: the problem of §1,
+ * eq. (1.2), for the dominant or minimal end of the spectrum (§5.2, §5.3), by the multiplicative
+ * set-up cycles of §3 (hierarchy, interpolation and test vectors learnt together) followed by the
+ * additive multigrid-Ritz iterations of §4 (or, solve_phase = 1, LOBPCG preconditioned by the
+ * learnt hierarchy, §7) until every pair's residual max(||A v - sigma u||, ||A^t u - sigma v||) /
+ * ||A|| (eigenpairs: ||A x - lambda x|| / ||A||; ||A|| the estimate reported as anorm) is at
+ * most tol.
  * init_tests: NULL (seeded SplitMix64 uniform[-1,1) test vectors) or a column-major
  *   (m'+n') x n_t (SVD) / n' x n_t (eigen) array for the prepared matrix (m' >= n' after the
  *   optional transposition, empty rows and columns removed).
