@@ -3,7 +3,7 @@
 
 One step = one complete solve (multiplicative set-up phase + additive phase with Ritz steps down
 to relative residual 1e-8) of the named workload, with the matrix resident in device memory when
-the timed region starts.  Prints ONE JSON line (see the design doc for the definitions):
+the timed region starts.  Prints ONE JSON line:
 
   value      triplets/s = n_b / (seconds per solve)
   roofline   the dominant kernel class, timed live with HIP events on the library's stream over the

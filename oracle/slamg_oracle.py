@@ -1205,7 +1205,7 @@ class Solver:
             if kind == SVD:
                 Vt = Vt[lev.sv.cpts]; Vb = Vb[lev.sv.cpts]
 
-    # -------------------------------------------------------------- driver (§3.3, §4)
+    # -------------------------------------------------------------- solve loop (§3.3, §4)
     def run(self):
         p, A0 = self.p, self.levels[0].A
         for c in range(1, p.n_mult + 1):
